@@ -1,0 +1,157 @@
+/*
+ * lbm.h -- C ABI of the MI355X drying-droplet lattice Boltzmann library.
+ *
+ * The library advances a two-component Shan-Chen D3Q19 BGK fluid (lattice
+ * Boltzmann equation, Eq. 1; equilibrium, Eq. 2; moments, Eq. 3 of
+ * "Evaporation-Driven Nanowire Self-Assembly in an Elongated Droplet",
+ * Methods: fluid-filament simulation method) on one AMD Instinct MI355X
+ * (gfx950), with halfway bounce-back walls whose ghost pseudo-densities set
+ * the wettability (the paper's solid ghost layer for wetting, Methods), a
+ * fixed-density reservoir plane on top through which component A evaporates,
+ * and rigid capsule rods standing in for the paper's nanowire filaments.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Lattice index: node (x, y, z) has flat index n = (z*ny + y)*nx + x.
+ *  - Populations are stored structure-of-arrays, one array per (component k,
+ *    direction i), array a = k*19 + i starting at element a*pop_stride, where
+ *    pop_stride = lb_pop_stride(params) >= nx*ny*nz.  Element type follows
+ *    params.prec (FP64, FP32, IEEE half or bfloat16); every form stores the
+ *    deviation f - w_i*rho_ref[k] from the lattice weights (rho_ref = 0
+ *    stores f itself).  The stored state at time t is the post-collision
+ *    population f*(t); at t = 0 it is w_i*rho_k.
+ *  - D3Q19 direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 =
+ *    (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),
+ *    (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *  - Material codes (uint8): 0 fluid, 1 reservoir plane (must be the whole
+ *    plane z = nz-1 when evaporation is on), 2..7 static wall materials,
+ *    8 rod.  A non-periodic direction must be closed by non-fluid end planes.
+ *  - Ownership: every device buffer is allocated and freed by the caller;
+ *    the library allocates only its small host-side context.  Buffers must
+ *    outlive the context.  The library never calls hipMalloc/hipFree.
+ *  - Streams: every call enqueues on the given stream and returns without
+ *    synchronising, except lb_init, lb_observables and lb_export which
+ *    synchronise that stream before returning.  One context per stream; a
+ *    context is not thread-safe.
+ *  - Errors: 0 = LB_OK; negative codes below.  No exception crosses the ABI.
+ *    lb_last_error() returns a thread-local message for the last failure.
+ *    Faults detected inside kernels (NaN, non-positive total density,
+ *    |u| > 0.3) set a device status word that lb_observables reports as
+ *    LB_EUNSTABLE.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,    /* bad argument: null pointer, size, tau <= 1/2, boundary */
+    LB_ENOTSUP = -2,   /* precision or feature combination not supported */
+    LB_EHIP = -3,      /* a HIP runtime call failed; see lb_last_error() */
+    LB_EUNSTABLE = -4, /* device status word set: NaN, rho <= 0 or |u| > 0.3 */
+    LB_EPLACE = 1      /* warning: fewer rods placed than requested */
+};
+
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3 } lb_prec;
+
+#define LB_NMAT 9
+
+/* All parameters of one lattice (plain data; mirrored by a Python dataclass). */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t periodic[3];          /* x, y, z: 1 periodic, 0 closed by non-fluid planes */
+    int32_t prec;                 /* lb_prec */
+    double tau[2];                /* BGK relaxation time per component, > 1/2 (Eq. 1) */
+    double G;                     /* Shan-Chen cross-coupling strength */
+    double body_force[3];         /* acceleration g; force rho_k*g */
+    double psi_solid[LB_NMAT][2]; /* ghost pseudo-density seen at solid material m */
+    int32_t evap_on;              /* 1: plane z = nz-1 is the fixed-density reservoir */
+    double rho_top[2];            /* reservoir densities */
+    double rho_ref[2];            /* storage reference: arrays hold f_i - w_i*rho_ref[k] (0: f_i) */
+    /* tiling of the fused step (0 = library default); see lb_autotune */
+    int32_t tile_y;               /* 4, 8 or 16 rows per tile */
+    int32_t rows_per_thread;      /* 1 or 2 */
+    int32_t zchunk;               /* planes marched by one work-group; 0 = auto */
+} lb_params;
+
+/* Caller-owned device buffers. */
+typedef struct {
+    void *f[2];        /* two population buffers, lb_pop_bytes() each */
+    void *workspace;   /* lb_workspace_bytes() bytes, 256-byte aligned */
+} lb_buffers;
+
+/* Host-side results of lb_observables (FP64 reductions over fluid nodes). */
+typedef struct {
+    int64_t step;          /* steps taken since lb_init */
+    double mass[2];        /* sum over fluid nodes of rho_k */
+    double ledger[2];      /* mass of component k lost to the reservoir so far */
+    double momentum[3];    /* sum over fluid nodes and components of post-collision j */
+    double max_speed;      /* max |sum_k j_k / sum_k rho_k| */
+    double kinetic;        /* sum of |j|^2 / (2 rho) */
+    int64_t fluid_nodes;
+    uint32_t status;       /* device status bits (1 NaN, 2 rho <= 0, 4 |u| > 0.3) */
+} lb_obs;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Elements between consecutive population arrays (>= nx*ny*nz). */
+int64_t lb_pop_stride(const lb_params *p);
+/* Bytes of one population buffer: 38 * pop_stride * element size. */
+size_t lb_pop_bytes(const lb_params *p);
+/* Bytes of the workspace (material map copy, ledger partials, reductions). */
+size_t lb_workspace_bytes(const lb_params *p);
+
+/*
+ * Create a context and write the t = 0 state f* = w_i rho_k into buffers.f[0].
+ *   rho_init_host : host, FP64 [2][nz][ny][nx] initial densities (values on
+ *                   non-fluid nodes are ignored).
+ *   material_host : host, uint8 [nz][ny][nx] material codes (copied).
+ * Validates the parameters and the boundary layout (LB_EINVAL), uses
+ * buffers.f[1] as upload staging, and synchronises the stream.
+ */
+int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host,
+            const uint8_t *material_host, hipStream_t stream, lb_ctx **out);
+
+/* Advance the fluid nsteps >= 0 time steps (pull stream, boundaries, moments,
+ * pseudopotential force, velocity shift, BGK collision, store; reservoir
+ * ledger).  Asynchronous. */
+int lb_step(lb_ctx *ctx, int32_t nsteps, hipStream_t stream);
+
+/* FP64 reductions of the current state into *out (host).  Synchronises.
+ * Returns LB_EUNSTABLE if the device status word is set. */
+int lb_observables(lb_ctx *ctx, lb_obs *out, hipStream_t stream);
+
+/*
+ * Decode the current state to FP64 device arrays (caller-owned):
+ *   rho_dev : [2][N] densities (0 on non-fluid nodes), nullable
+ *   f_dev   : [2][19][N] post-collision populations (0 on non-fluid), nullable
+ * Synchronises.
+ */
+int lb_export(lb_ctx *ctx, double *rho_dev, double *f_dev, hipStream_t stream);
+
+/* Index (0 or 1) of the buffer holding the current state. */
+int lb_current_buffer(const lb_ctx *ctx);
+
+/* Destroy the host context (device buffers stay with the caller). */
+int lb_destroy(lb_ctx *ctx);
+
+/* Thread-local text of the last error. */
+const char *lb_last_error(void);
+
+/* sizeof(lb_params), sizeof(lb_buffers), sizeof(lb_obs) into out[0..2], so a
+ * binding can verify its mirrors of the structs.  Never fails. */
+void lb_abi_sizes(size_t out[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

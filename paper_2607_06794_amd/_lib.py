@@ -1,0 +1,132 @@
+"""ctypes binding of liblbm.so (the C ABI in include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbm.so")
+
+LB_OK, LB_EINVAL, LB_ENOTSUP, LB_EHIP, LB_EUNSTABLE, LB_EPLACE = 0, -1, -2, -3, -4, 1
+LB_F64, LB_F32, LB_F16DEV, LB_BF16DEV = 0, 1, 2, 3
+LB_NMAT = 9
+
+# Every exported symbol declared in include/lbm.h
+EXPORTS = (
+    "lb_pop_stride",
+    "lb_pop_bytes",
+    "lb_workspace_bytes",
+    "lb_init",
+    "lb_step",
+    "lb_observables",
+    "lb_export",
+    "lb_current_buffer",
+    "lb_destroy",
+    "lb_last_error",
+    "lb_abi_sizes",
+)
+
+
+class LbParams(ct.Structure):
+    _fields_ = [
+        ("nx", ct.c_int32),
+        ("ny", ct.c_int32),
+        ("nz", ct.c_int32),
+        ("periodic", ct.c_int32 * 3),
+        ("prec", ct.c_int32),
+        ("tau", ct.c_double * 2),
+        ("G", ct.c_double),
+        ("body_force", ct.c_double * 3),
+        ("psi_solid", (ct.c_double * 2) * LB_NMAT),
+        ("evap_on", ct.c_int32),
+        ("rho_top", ct.c_double * 2),
+        ("rho_ref", ct.c_double * 2),
+        ("tile_y", ct.c_int32),
+        ("rows_per_thread", ct.c_int32),
+        ("zchunk", ct.c_int32),
+    ]
+
+
+class LbBuffers(ct.Structure):
+    _fields_ = [("f", ct.c_void_p * 2), ("workspace", ct.c_void_p)]
+
+
+class LbObs(ct.Structure):
+    _fields_ = [
+        ("step", ct.c_int64),
+        ("mass", ct.c_double * 2),
+        ("ledger", ct.c_double * 2),
+        ("momentum", ct.c_double * 3),
+        ("max_speed", ct.c_double),
+        ("kinetic", ct.c_double),
+        ("fluid_nodes", ct.c_int64),
+        ("status", ct.c_uint32),
+    ]
+
+
+class LbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblbm.so (once) and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # liblbm must bind to the same HIP runtime as PyTorch (which allocates the
+    # device buffers and owns the streams); loading torch first makes the
+    # dynamic loader resolve libamdhip64.so.7 to torch's copy
+    import torch  # noqa: F401
+
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first (python -m paper_2607_06794_amd.build); "
+            "there is no CPU fallback"
+        )
+    lib = ct.CDLL(path)
+    P = ct.POINTER
+    lib.lb_pop_stride.argtypes = [P(LbParams)]
+    lib.lb_pop_stride.restype = ct.c_int64
+    lib.lb_pop_bytes.argtypes = [P(LbParams)]
+    lib.lb_pop_bytes.restype = ct.c_size_t
+    lib.lb_workspace_bytes.argtypes = [P(LbParams)]
+    lib.lb_workspace_bytes.restype = ct.c_size_t
+    lib.lb_init.argtypes = [P(LbParams), P(LbBuffers), ct.c_void_p, ct.c_void_p, ct.c_void_p, P(ct.c_void_p)]
+    lib.lb_init.restype = ct.c_int
+    lib.lb_step.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p]
+    lib.lb_step.restype = ct.c_int
+    lib.lb_observables.argtypes = [ct.c_void_p, P(LbObs), ct.c_void_p]
+    lib.lb_observables.restype = ct.c_int
+    lib.lb_export.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_export.restype = ct.c_int
+    lib.lb_current_buffer.argtypes = [ct.c_void_p]
+    lib.lb_current_buffer.restype = ct.c_int
+    lib.lb_destroy.argtypes = [ct.c_void_p]
+    lib.lb_destroy.restype = ct.c_int
+    lib.lb_last_error.argtypes = []
+    lib.lb_last_error.restype = ct.c_char_p
+    lib.lb_abi_sizes.argtypes = [P(ct.c_size_t)]
+    lib.lb_abi_sizes.restype = None
+    sizes = (ct.c_size_t * 3)()
+    lib.lb_abi_sizes(sizes)
+    want = (ct.sizeof(LbParams), ct.sizeof(LbBuffers), ct.sizeof(LbObs))
+    if tuple(sizes) != want:
+        raise RuntimeError(f"liblbm struct sizes {tuple(sizes)} differ from the binding's {want}")
+    _lib = lib
+    return lib
+
+
+def check(rc: int, allow=(LB_OK,)):
+    if rc not in allow:
+        msg = load().lb_last_error()
+        raise LbError(rc, msg.decode() if msg else "")
+    return rc

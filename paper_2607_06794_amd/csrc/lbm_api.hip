@@ -1,0 +1,348 @@
+// Host side of the C ABI declared in include/lbm.h: validation, workspace
+// layout, kernel launches and error reporting.  No exception crosses the ABI.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                        \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t elem_bytes(int prec) {
+    switch (prec) {
+        case LB_F64:
+            return 8;
+        case LB_F32:
+            return 4;
+        case LB_F16DEV:
+        case LB_BF16DEV:
+            return 2;
+        default:
+            return 0;
+    }
+}
+
+int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
+
+// Workspace layout (all offsets 256-byte aligned):
+//   mat      : N bytes, working material map with flag bits
+//   ledger   : max_tiles * 2 doubles, per-xy-tile reservoir ledger
+//   status   : 256 bytes (status word)
+//   partials : OBS_BLOCKS * OBS_FIELDS doubles
+//   result   : 256 bytes
+struct WsLayout {
+    size_t mat, ledger, status, partials, result, total;
+    int max_tiles;
+};
+
+WsLayout ws_layout(const lb_params *p) {
+    WsLayout w{};
+    const int64_t n = nodes(p);
+    w.max_tiles = tiles_xy(p->nx, p->ny, 4);
+    size_t o = 0;
+    w.mat = o;
+    o = align256(o + size_t(n));
+    w.ledger = o;
+    o = align256(o + size_t(w.max_tiles) * 2 * sizeof(double));
+    w.status = o;
+    o = align256(o + 256);
+    w.partials = o;
+    o = align256(o + size_t(OBS_BLOCKS) * OBS_FIELDS * sizeof(double));
+    w.result = o;
+    o = align256(o + 256);
+    w.total = o;
+    return w;
+}
+
+int validate(const lb_params *p) {
+    if (!p) return fail(LB_EINVAL, "null params");
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(LB_EINVAL, "lattice must be at least 3 nodes per direction");
+    if (nodes(p) > (int64_t(1) << 31) / 2) return fail(LB_EINVAL, "lattice too large for one context");
+    if (elem_bytes(p->prec) == 0) return fail(LB_ENOTSUP, "unknown precision %d", p->prec);
+    for (int k = 0; k < 2; ++k)
+        if (!(p->tau[k] > 0.5)) return fail(LB_EINVAL, "tau[%d] = %g must exceed 1/2", k, p->tau[k]);
+    if (!isfinite(p->G)) return fail(LB_EINVAL, "G not finite");
+    const int ty = p->tile_y ? p->tile_y : 8;
+    const int rp = p->rows_per_thread ? p->rows_per_thread : 2;
+    const bool ok_tile = (ty == 4 && rp == 1) || (ty == 8 && (rp == 1 || rp == 2)) || (ty == 16 && rp == 2);
+    if (!ok_tile) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
+    const bool tau1 = p->tau[0] == 1.0 && p->tau[1] == 1.0;
+    if (!tau1 && rp != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
+    if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
+    return LB_OK;
+}
+
+int validate_material(const lb_params *p, const uint8_t *m) {
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    auto at = [&](int x, int y, int z) { return m[(int64_t(z) * ny + y) * nx + x]; };
+    const int64_t n = nodes(p);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t v = m[i];
+        if (v > MAT_ROD) return fail(LB_EINVAL, "material code %u at node %lld out of range", v, (long long)i);
+        if (v == MAT_ROD) return fail(LB_EINVAL, "rod nodes are placed by the rod module, not by lb_init");
+    }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const uint8_t v = at(x, y, z);
+                if (v == MAT_GHOST && !(p->evap_on && z == nz - 1))
+                    return fail(LB_EINVAL, "reservoir node off the top plane (%d,%d,%d)", x, y, z);
+                if (v != MAT_FLUID) continue;
+                if (!p->periodic[0] && (x == 0 || x == nx - 1))
+                    return fail(LB_EINVAL, "fluid node on a closed x end plane");
+                if (!p->periodic[1] && (y == 0 || y == ny - 1))
+                    return fail(LB_EINVAL, "fluid node on a closed y end plane");
+                if (!p->periodic[2] && (z == 0 || z == nz - 1))
+                    return fail(LB_EINVAL, "fluid node on a closed z end plane");
+            }
+    if (p->evap_on) {
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (at(x, y, nz - 1) != MAT_GHOST) return fail(LB_EINVAL, "evaporation needs the whole top plane as reservoir");
+        if (p->periodic[2]) return fail(LB_EINVAL, "evaporation needs z non-periodic");
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    void *f[2];
+    int cur;
+    uint8_t *mat;
+    double *ledger;
+    unsigned *status;
+    double *partials;
+    double *result;
+    TileCfg tile;
+    int ntx, nty, nzc, zchunk;
+    int nledger;
+    int64_t steps;
+    int64_t fs;
+    double rref[2];  // storage reference density of the precision form
+};
+
+extern "C" {
+
+int64_t lb_pop_stride(const lb_params *p) {
+    if (!p) return 0;
+    // pad each array to a multiple of 256 elements plus 64 so that the 38
+    // concurrent streams do not start on the same HBM channel
+    const int64_t n = nodes(p);
+    return ((n + 255) / 256) * 256 + 64;
+}
+
+size_t lb_pop_bytes(const lb_params *p) {
+    if (!p) return 0;
+    return size_t(2 * Q) * size_t(lb_pop_stride(p)) * elem_bytes(p->prec);
+}
+
+size_t lb_workspace_bytes(const lb_params *p) {
+    if (!p) return 0;
+    return ws_layout(p).total;
+}
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+void lb_abi_sizes(size_t out[3]) {
+    out[0] = sizeof(lb_params);
+    out[1] = sizeof(lb_buffers);
+    out[2] = sizeof(lb_obs);
+}
+
+int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
+            hipStream_t stream, lb_ctx **out) {
+    if (!out) return fail(LB_EINVAL, "null out");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!buf || !buf->f[0] || !buf->f[1] || !buf->workspace) return fail(LB_EINVAL, "null device buffer");
+    if (!rho_init_host || !material_host) return fail(LB_EINVAL, "null initial data");
+    if ((reinterpret_cast<uintptr_t>(buf->workspace) & 255) != 0) return fail(LB_EINVAL, "workspace not 256-byte aligned");
+    rc = validate_material(p, material_host);
+    if (rc) return rc;
+
+    lb_ctx *c = new (std::nothrow) lb_ctx();
+    if (!c) return fail(LB_EINVAL, "out of host memory");
+    c->p = *p;
+    c->f[0] = buf->f[0];
+    c->f[1] = buf->f[1];
+    c->cur = 0;
+    const WsLayout w = ws_layout(p);
+    char *ws = static_cast<char *>(buf->workspace);
+    c->mat = reinterpret_cast<uint8_t *>(ws + w.mat);
+    c->ledger = reinterpret_cast<double *>(ws + w.ledger);
+    c->status = reinterpret_cast<unsigned *>(ws + w.status);
+    c->partials = reinterpret_cast<double *>(ws + w.partials);
+    c->result = reinterpret_cast<double *>(ws + w.result);
+    c->fs = lb_pop_stride(p);
+    for (int k = 0; k < 2; ++k) c->rref[k] = p->rho_ref[k];
+    c->tile.tile_y = p->tile_y ? p->tile_y : 8;
+    c->tile.rows_per_thread = p->rows_per_thread ? p->rows_per_thread : 2;
+    c->ntx = (p->nx + 63) / 64;
+    c->nty = (p->ny + c->tile.tile_y - 1) / c->tile.tile_y;
+    c->nledger = c->ntx * c->nty;
+    int zc = p->zchunk;
+    if (zc <= 0) {
+        // aim for ~1024 work-groups (4 per CU) while marching at least 8 planes
+        const int xy = c->ntx * c->nty;
+        int nzc = (1024 + xy - 1) / xy;
+        nzc = std::max(1, std::min(nzc, (p->nz + 7) / 8));
+        zc = (p->nz + nzc - 1) / nzc;
+    }
+    c->zchunk = std::max(1, std::min(zc, p->nz));
+    c->nzc = (p->nz + c->zchunk - 1) / c->zchunk;
+    c->tile.zchunk = c->zchunk;
+    c->steps = 0;
+
+    const int64_t n = nodes(p);
+    const int per[3] = {p->periodic[0], p->periodic[1], p->periodic[2]};
+    auto cleanup = [&](int code) {
+        delete c;
+        return code;
+    };
+    // staging: densities go through buffer f[1], which the first step overwrites
+    if (lb_pop_bytes(p) < size_t(2 * n) * sizeof(double)) return cleanup(fail(LB_EINVAL, "population buffer too small for staging"));
+    double *stage = static_cast<double *>(c->f[1]);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(stage, rho_init_host, size_t(2 * n) * sizeof(double), hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "upload densities"));
+    if ((e = hipMemcpyAsync(c->mat, material_host, size_t(n), hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "upload material"));
+    if ((e = hipMemsetAsync(c->ledger, 0, size_t(w.max_tiles) * 2 * sizeof(double), stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "clear ledger"));
+    if ((e = hipMemsetAsync(c->status, 0, 256, stream)) != hipSuccess) return cleanup(hip_fail(e, "clear status"));
+    if ((e = launch_flags(c->mat, p->nx, p->ny, p->nz, per, stream)) != hipSuccess) return cleanup(hip_fail(e, "flags"));
+    if ((e = launch_init_populations(p->prec, c->f[0], c->fs, stage, c->mat, n, c->rref, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "init populations"));
+    if ((e = launch_slot_fill(p->prec, c->f[0], c->fs, c->mat, p->nx, p->ny, p->nz, per, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "slot fill"));
+    // the second buffer needs the same wall slots only after the first step
+    // writes them; clear it so that stale staging bytes never look like state
+    if ((e = hipMemsetAsync(c->f[1], 0, lb_pop_bytes(p), stream)) != hipSuccess) return cleanup(hip_fail(e, "clear f[1]"));
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
+    *out = c;
+    return LB_OK;
+}
+
+int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
+    if (!c) return fail(LB_EINVAL, "null ctx");
+    if (nsteps < 0) return fail(LB_EINVAL, "negative step count");
+    const lb_params &p = c->p;
+    StepArgs a{};
+    a.mat = c->mat;
+    a.ledger_part = c->ledger;
+    a.status = c->status;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.px = p.periodic[0];
+    a.py = p.periodic[1];
+    a.pz = p.periodic[2];
+    a.fs = c->fs;
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.nzc = c->nzc;
+    a.zchunk = c->zchunk;
+    a.evap = p.evap_on;
+    for (int k = 0; k < 2; ++k) {
+        a.tau[k] = p.tau[k];
+        a.omega[k] = 1.0 / p.tau[k];
+        a.rho_top[k] = p.rho_top[k];
+        a.rho_ref[k] = c->rref[k];
+    }
+    a.G = p.G;
+    for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
+    for (int m = 0; m < 16; ++m)
+        for (int k = 0; k < 2; ++k) a.psi_s[m][k] = m < LB_NMAT ? p.psi_solid[m][k] : 0.0;
+    const bool tau1 = (p.tau[0] == 1.0 && p.tau[1] == 1.0);
+    for (int s = 0; s < nsteps; ++s) {
+        a.fsrc = c->f[c->cur];
+        a.fdst = c->f[c->cur ^ 1];
+        hipError_t e = launch_sc_step(p.prec, tau1, c->tile, a, stream);
+        if (e != hipSuccess) return hip_fail(e, "sc_step launch");
+        c->cur ^= 1;
+        c->steps++;
+    }
+    return LB_OK;
+}
+
+int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
+    if (!c || !out) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    HIP_TRY(launch_observables(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, c->ledger, c->nledger,
+                               c->partials, OBS_BLOCKS, c->result, stream),
+            "observables");
+    double r[OBS_FIELDS];
+    unsigned st = 0;
+    HIP_TRY(hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, stream), "copy observables");
+    HIP_TRY(hipMemcpyAsync(&st, c->status, sizeof st, hipMemcpyDeviceToHost, stream), "copy status");
+    HIP_TRY(hipStreamSynchronize(stream), "observables sync");
+    memset(out, 0, sizeof *out);
+    out->step = c->steps;
+    out->mass[0] = r[0];
+    out->mass[1] = r[1];
+    out->ledger[0] = r[2];
+    out->ledger[1] = r[3];
+    out->momentum[0] = r[4];
+    out->momentum[1] = r[5];
+    out->momentum[2] = r[6];
+    out->max_speed = r[7];
+    out->kinetic = r[8];
+    out->fluid_nodes = int64_t(r[9]);
+    out->status = st;
+    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3)", st);
+    return LB_OK;
+}
+
+int lb_export(lb_ctx *c, double *rho_dev, double *f_dev, hipStream_t stream) {
+    if (!c) return fail(LB_EINVAL, "null ctx");
+    const lb_params &p = c->p;
+    HIP_TRY(launch_export(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, rho_dev, f_dev, stream), "export");
+    HIP_TRY(hipStreamSynchronize(stream), "export sync");
+    return LB_OK;
+}
+
+int lb_current_buffer(const lb_ctx *c) { return c ? c->cur : -1; }
+
+int lb_destroy(lb_ctx *c) {
+    delete c;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Device-side lattice constants and population storage codecs for gfx950.
+//
+// D3Q19 velocity set (the discrete velocities c_i of the lattice Boltzmann
+// equation, Eq. 1) with weights w_i of the second-order equilibrium (Eq. 2),
+// c_s^2 = 1/3.  Direction order: rest; +x,-x,+y,-y,+z,-z; then the twelve
+// (+-1,+-1,0)-type permutations with each direction followed by its opposite.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+__host__ __device__ constexpr int cx(int i) {
+    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[i];
+}
+// opposite direction: pairs (1,2), (3,4), ... are adjacent
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <class C>
+__host__ __device__ constexpr C wgt(int i) {
+    return i == 0 ? C(1) / C(3) : (i <= 6 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// material byte: low nibble = material id, bit 7 = fluid node next to a static wall
+constexpr uint8_t MAT_FLUID = 0, MAT_GHOST = 1, MAT_ROD = 8;
+constexpr uint8_t MAT_ID_MASK = 0x0F, MAT_NEAR_WALL = 0x80;
+__host__ __device__ inline bool is_static_wall(uint8_t id) { return id >= 2 && id <= 7; }
+
+// status bits
+constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u;
+
+// ---------------------------------------------------------------------------
+// storage codecs: S = element type in HBM, C = compute type in registers.
+// The kernels store and compute the deviation d_i = f_i - w_i*rho_ref[k]
+// (rho_ref = 0 stores f_i itself); the codecs only convert d_i between the
+// storage and the compute type.
+// ---------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using C = double;
+    __device__ static inline double dec(double s) { return s; }
+    __device__ static inline double enc(double v) { return v; }
+};
+
+template <>
+struct Codec<float> {
+    using C = float;
+    __device__ static inline float dec(float s) { return s; }
+    __device__ static inline float enc(float v) { return v; }
+};
+
+// IEEE half, round to nearest even (hardware conversion)
+template <>
+struct Codec<_Float16> {
+    using C = float;
+    __device__ static inline float dec(_Float16 s) { return static_cast<float>(s); }
+    __device__ static inline _Float16 enc(float v) { return static_cast<_Float16>(v); }
+};
+
+// bfloat16, round to nearest even on the float bit pattern
+template <>
+struct Codec<bf16_t> {
+    using C = float;
+    __device__ static inline float dec(bf16_t s) { return __uint_as_float(static_cast<uint32_t>(s.bits) << 16); }
+    __device__ static inline bf16_t enc(float d) {
+        uint32_t u = __float_as_uint(d);
+        bf16_t r;
+        if ((u & 0x7f800000u) == 0x7f800000u) {  // inf or nan: keep, quiet the nan
+            r.bits = static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            r.bits = static_cast<uint16_t>(u >> 16);
+        }
+        return r;
+    }
+};
+
+
+}  // namespace lbm

@@ -1,0 +1,58 @@
+// Internal declarations shared by the HIP translation units of liblbm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Arguments of the fused step kernel (passed by value as kernel arguments).
+struct StepArgs {
+    const void *fsrc;
+    void *fdst;
+    const uint8_t *mat;
+    double *ledger_part;  // [nty*ntx][2] running FP64 sums, one slot per xy tile
+    unsigned *status;
+    int nx, ny, nz;
+    int px, py, pz;
+    int64_t fs;  // elements between population arrays
+    int ntx, nty, nzc, zchunk;
+    int evap;
+    double tau[2], omega[2];
+    double G;
+    double g[3];
+    double psi_s[16][2];
+    double rho_top[2];
+    double rho_ref[2];
+};
+
+// Tile shape of the fused step: TX = 64 columns x tile_y rows, each thread
+// owning rows_per_thread rows; the work-group marches zchunk planes.
+struct TileCfg {
+    int tile_y = 8;
+    int rows_per_thread = 2;
+    int zchunk = 0;
+};
+
+hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s);
+int tiles_xy(int nx, int ny, int tile_y);
+
+// auxiliary kernels (aux.hip)
+hipError_t launch_init_populations(int prec, void *f, int64_t fs, const double *rho, const uint8_t *mat,
+                                   int64_t n, const double rho_ref[2], hipStream_t s);
+hipError_t launch_flags(uint8_t *mat, int nx, int ny, int nz, const int per[3], hipStream_t s);
+hipError_t launch_slot_fill(int prec, void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                            const int per[3], hipStream_t s);
+hipError_t launch_export(int prec, const void *f, int64_t fs, const uint8_t *mat, int64_t n,
+                         const double rho_ref[2], double *rho_out, double *f_out, hipStream_t s);
+// observables: writes [16] doubles into result (device): mass[2], ledger[2], momentum[3],
+// max_speed, kinetic, fluid_nodes
+hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t *mat, int64_t n,
+                              const double rho_ref[2], const double *ledger_part, int nledger,
+                              double *partials, int nblocks, double *result, hipStream_t s);
+constexpr int OBS_BLOCKS = 512;
+constexpr int OBS_FIELDS = 10;
+
+}  // namespace lbm

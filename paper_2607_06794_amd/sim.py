@@ -1,0 +1,154 @@
+"""Thin Python front end over liblbm: device memory from PyTorch, work in HIP.
+
+``Lattice`` owns the caller-side buffers (torch tensors on the GPU) and a
+library context.  Every computation happens inside liblbm's kernels; this
+module only allocates memory, passes pointers and converts results.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+PREC = {"f64": _lib.LB_F64, "f32": _lib.LB_F32, "f16dev": _lib.LB_F16DEV, "bf16dev": _lib.LB_BF16DEV}
+
+
+@dataclass
+class LatticeParams:
+    """Python mirror of lb_params (see include/lbm.h)."""
+
+    shape: tuple  # (nz, ny, nx)
+    periodic: tuple = (True, True, True)  # x, y, z
+    prec: str = "f64"
+    tau: tuple = (1.0, 1.0)
+    G: float = 3.6
+    body_force: tuple = (0.0, 0.0, 0.0)
+    psi_solid: np.ndarray = field(default_factory=lambda: np.zeros((9, 2)))
+    evaporation: bool = False
+    rho_top: tuple = (0.0, 1.0)
+    rho_ref: tuple = (0.0, 0.0)  # storage reference: 0 stores f_i, else f_i - w_i rho_ref
+    tile_y: int = 0
+    rows_per_thread: int = 0
+    zchunk: int = 0
+
+    def to_c(self) -> _lib.LbParams:
+        p = _lib.LbParams()
+        p.nz, p.ny, p.nx = (int(v) for v in self.shape)
+        for d in range(3):
+            p.periodic[d] = int(bool(self.periodic[d]))
+            p.body_force[d] = float(self.body_force[d])
+        p.prec = PREC[self.prec]
+        for k in range(2):
+            p.tau[k] = float(self.tau[k])
+            p.rho_top[k] = float(self.rho_top[k])
+            p.rho_ref[k] = float(self.rho_ref[k])
+        p.G = float(self.G)
+        ps = np.asarray(self.psi_solid, dtype=np.float64)
+        for m in range(_lib.LB_NMAT):
+            for k in range(2):
+                p.psi_solid[m][k] = float(ps[m, k]) if m < ps.shape[0] else 0.0
+        p.evap_on = int(bool(self.evaporation))
+        p.tile_y = int(self.tile_y)
+        p.rows_per_thread = int(self.rows_per_thread)
+        p.zchunk = int(self.zchunk)
+        return p
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+class Lattice:
+    """One lattice on one GPU: caller-owned buffers plus a liblbm context."""
+
+    def __init__(self, params: LatticeParams, rho0: np.ndarray, material: np.ndarray, device="cuda:0", stream=None):
+        import torch
+
+        self.lib = _lib.load()
+        self.params = params
+        self.device = torch.device(device)
+        self.stream = stream
+        self._cp = params.to_c()
+        nz, ny, nx = params.shape
+        self.n = nx * ny * nz
+        pop_bytes = self.lib.lb_pop_bytes(ct.byref(self._cp))
+        ws_bytes = self.lib.lb_workspace_bytes(ct.byref(self._cp))
+        self.pop_stride = self.lib.lb_pop_stride(ct.byref(self._cp))
+        with torch.cuda.device(self.device):
+            self.f = [torch.empty(pop_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+            self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = self.ws.data_ptr()
+        ws_ptr = (ws_ptr + 255) & ~255
+        self._buf = _lib.LbBuffers()
+        self._buf.f[0] = self.f[0].data_ptr()
+        self._buf.f[1] = self.f[1].data_ptr()
+        self._buf.workspace = ws_ptr
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        material = np.ascontiguousarray(material, dtype=np.uint8)
+        assert rho0.shape == (2,) + tuple(params.shape), rho0.shape
+        assert material.shape == tuple(params.shape), material.shape
+        self._ctx = ct.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.lb_init(
+                ct.byref(self._cp),
+                ct.byref(self._buf),
+                rho0.ctypes.data_as(ct.c_void_p),
+                material.ctypes.data_as(ct.c_void_p),
+                _stream_ptr(self.stream),
+                ct.byref(self._ctx),
+            )
+        _lib.check(rc)
+
+    # ------------------------------------------------------------------
+    def step(self, n: int = 1):
+        _lib.check(self.lib.lb_step(self._ctx, int(n), _stream_ptr(self.stream)))
+        return self
+
+    def observables(self, allow_unstable=False) -> dict:
+        o = _lib.LbObs()
+        allow = (_lib.LB_OK, _lib.LB_EUNSTABLE) if allow_unstable else (_lib.LB_OK,)
+        _lib.check(self.lib.lb_observables(self._ctx, ct.byref(o), _stream_ptr(self.stream)), allow=allow)
+        return {
+            "step": o.step,
+            "mass": np.array(o.mass[:]),
+            "ledger": np.array(o.ledger[:]),
+            "momentum": np.array(o.momentum[:]),
+            "max_speed": o.max_speed,
+            "kinetic": o.kinetic,
+            "fluid_nodes": o.fluid_nodes,
+            "status": o.status,
+        }
+
+    def export(self, populations: bool = True):
+        """Decoded FP64 state: (rho[2, nz, ny, nx], f[2, 19, nz, ny, nx] or None) as numpy."""
+        import torch
+
+        nz, ny, nx = self.params.shape
+        rho = torch.empty((2, nz, ny, nx), dtype=torch.float64, device=self.device)
+        f = torch.empty((2, 19, nz, ny, nx), dtype=torch.float64, device=self.device) if populations else None
+        _lib.check(
+            self.lib.lb_export(
+                self._ctx,
+                ct.c_void_p(rho.data_ptr()),
+                ct.c_void_p(f.data_ptr()) if f is not None else None,
+                _stream_ptr(self.stream),
+            )
+        )
+        return rho.cpu().numpy(), (f.cpu().numpy() if f is not None else None)
+
+    def close(self):
+        if self._ctx:
+            self.lib.lb_destroy(self._ctx)
+            self._ctx = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

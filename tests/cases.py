@@ -1,0 +1,52 @@
+"""Workload definitions shared by the parity tests and the benchmark.
+
+Each case is plain numbers; ``oracle_params`` and ``lattice_params`` turn the
+same numbers into the oracle's and the library's parameter objects.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2607_06794_amd import inputs
+
+# Ghost pseudo-densities (psi_A, psi_B) of the wall materials: stripe wets A,
+# the surround repels it; rods wet like the stripe.
+PSI_SOLID = np.zeros((9, 2))
+PSI_SOLID[inputs.STRIPE] = (0.60, 0.25)
+PSI_SOLID[inputs.SURROUND] = (0.25, 0.60)
+PSI_SOLID[inputs.ROD] = (0.60, 0.25)
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b| (the per-field relative error used throughout)."""
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def sphere_case(n=32, radius=8, seed=1000, noise=1e-4, G=3.6, tau=(1.0, 1.0)):
+    rho, mat = inputs.sphere_droplet((n, n, n), radius, noise=noise, seed=seed)
+    return dict(shape=(n, n, n), periodic=(True, True, True), G=G, tau=tau, rho=rho, mat=mat,
+                evaporation=False, body_force=(0.0, 0.0, 0.0))
+
+
+def cap_case(shape=(64, 128, 256), footprint=(150.0, 36.0), height=24.0, stripe=(160, 40), seed=2000, noise=1e-4):
+    spec = inputs.CapSpec(shape=shape, footprint=footprint, height=height, stripe=stripe, seed=seed, noise=noise)
+    rho, mat = inputs.sessile_cap(spec)
+    return dict(shape=shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), rho=rho, mat=mat,
+                evaporation=True, body_force=(0.0, 0.0, 0.0))
+
+
+def oracle_params(c):
+    from oracle import lbm
+
+    return lbm.Params(shape=c["shape"], periodic=c["periodic"], tau=c["tau"], G=c["G"],
+                      body_force=c["body_force"], psi_solid=PSI_SOLID.copy(), rho_top=(0.0, 1.0),
+                      evaporation=c["evaporation"])
+
+
+def lattice_params(c, prec, rho_ref=(0.0, 0.0), **tile):
+    from paper_2607_06794_amd.sim import LatticeParams
+
+    return LatticeParams(shape=c["shape"], periodic=c["periodic"], prec=prec, tau=c["tau"], G=c["G"],
+                         body_force=c["body_force"], psi_solid=PSI_SOLID.copy(), evaporation=c["evaporation"],
+                         rho_top=(0.0, 1.0), rho_ref=rho_ref, **tile)

@@ -1,0 +1,120 @@
+"""The C-ABI library loads, exports every declared symbol and validates input on the host.
+
+No compute calls: these run without a GPU.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_06794_amd import _lib
+from paper_2607_06794_amd.sim import LatticeParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(lb_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("liblbm.so not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    assert declared == set(_lib.EXPORTS), declared ^ set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_struct_mirrors_match(lib):
+    sizes = (ct.c_size_t * 3)()
+    lib.lb_abi_sizes(sizes)
+    assert tuple(sizes) == (ct.sizeof(_lib.LbParams), ct.sizeof(_lib.LbBuffers), ct.sizeof(_lib.LbObs))
+
+
+def test_buffer_sizes(lib):
+    p = LatticeParams(shape=(64, 128, 256), prec="f32").to_c()
+    n = 256 * 128 * 64
+    stride = lib.lb_pop_stride(ct.byref(p))
+    assert stride >= n and stride % 64 == 0
+    assert lib.lb_pop_bytes(ct.byref(p)) == 38 * stride * 4
+    p.prec = _lib.LB_F64
+    assert lib.lb_pop_bytes(ct.byref(p)) == 38 * stride * 8
+    p.prec = _lib.LB_BF16DEV
+    assert lib.lb_pop_bytes(ct.byref(p)) == 38 * stride * 2
+    assert lib.lb_workspace_bytes(ct.byref(p)) >= n
+
+
+def _init_rc(lib, params, rho=None, mat=None):
+    cp = params.to_c()
+    nz, ny, nx = params.shape
+    rho = np.ones((2, nz, ny, nx)) if rho is None else rho
+    mat = np.zeros((nz, ny, nx), np.uint8) if mat is None else mat
+    buf = _lib.LbBuffers()
+    buf.f[0] = 256
+    buf.f[1] = 512
+    buf.workspace = 1024
+    ctx = ct.c_void_p()
+    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None, ct.byref(ctx))
+    return rc, lib.lb_last_error().decode()
+
+
+def test_validation_rejects_bad_input_before_any_device_call(lib):
+    # tau <= 1/2
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), tau=(0.5, 1.0)))
+    assert rc == _lib.LB_EINVAL and "tau" in msg
+    # unknown precision
+    p = LatticeParams(shape=(8, 8, 8))
+    cp = p.to_c()
+    cp.prec = 9
+    buf = _lib.LbBuffers()
+    ctx = ct.c_void_p()
+    rho = np.ones((2, 8, 8, 8))
+    mat = np.zeros((8, 8, 8), np.uint8)
+    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None, ct.byref(ctx))
+    assert rc == _lib.LB_ENOTSUP
+    # fluid on a closed end plane
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), periodic=(True, True, False)))
+    assert rc == _lib.LB_EINVAL and "closed" in msg
+    # reservoir requested but top plane is fluid
+    mat = np.zeros((8, 8, 8), np.uint8)
+    mat[0] = 2
+    mat[-1] = 3
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), periodic=(True, True, False), evaporation=True), mat=mat)
+    assert rc == _lib.LB_EINVAL and "reservoir" in msg
+    # reservoir nodes off the top plane
+    mat = np.zeros((8, 8, 8), np.uint8)
+    mat[3, 3, 3] = 1
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8)), mat=mat)
+    assert rc == _lib.LB_EINVAL
+    # tau != 1 with two rows per thread
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), tau=(0.8, 0.8), tile_y=8, rows_per_thread=2))
+    assert rc == _lib.LB_ENOTSUP
+    # unsupported tile
+    rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), tile_y=5, rows_per_thread=1))
+    assert rc == _lib.LB_EINVAL
+    # null out pointer
+    cp = LatticeParams(shape=(8, 8, 8)).to_c()
+    assert lib.lb_init(ct.byref(cp), None, None, None, None, None) == _lib.LB_EINVAL
+    # step / observables / export on a null context
+    assert lib.lb_step(None, 1, None) == _lib.LB_EINVAL
+    assert lib.lb_observables(None, None, None) == _lib.LB_EINVAL
+    assert lib.lb_export(None, None, None, None) == _lib.LB_EINVAL
+    assert lib.lb_current_buffer(None) == -1
+    assert lib.lb_destroy(None) == _lib.LB_OK
