@@ -137,6 +137,23 @@ int lb_observables(lb_ctx *ctx, lb_obs *out, hipStream_t stream);
  */
 int lb_export(lb_ctx *ctx, double *rho_dev, double *f_dev, hipStream_t stream);
 
+/* Tile shape of the fused step: 64 x tile_y columns, rows_per_thread rows per
+ * thread, zchunk planes marched per work-group. */
+typedef struct {
+    int32_t tile_y, rows_per_thread, zchunk;
+    double us_per_step;   /* measured by lb_autotune (0 when set by hand) */
+} lb_tile;
+
+/* Switch the tile shape of later steps (same rules as lb_params).  The
+ * reservoir ledger is carried over exactly.  Asynchronous. */
+int lb_set_tiles(lb_ctx *ctx, const lb_tile *tile, hipStream_t stream);
+
+/* Time every supported tile shape for trial_steps >= 1 steps each (HIP events
+ * on the stream), keep the fastest and return it in *best.  The trial steps
+ * are real steps of the simulation (the state advances by n_shapes *
+ * trial_steps steps).  Synchronises. */
+int lb_autotune(lb_ctx *ctx, int32_t trial_steps, hipStream_t stream, lb_tile *best);
+
 /* Index (0 or 1) of the buffer holding the current state. */
 int lb_current_buffer(const lb_ctx *ctx);
 

@@ -28,6 +28,8 @@ EXPORTS = (
     "lb_destroy",
     "lb_last_error",
     "lb_abi_sizes",
+    "lb_set_tiles",
+    "lb_autotune",
 )
 
 
@@ -65,6 +67,15 @@ class LbObs(ct.Structure):
         ("kinetic", ct.c_double),
         ("fluid_nodes", ct.c_int64),
         ("status", ct.c_uint32),
+    ]
+
+
+class LbTile(ct.Structure):
+    _fields_ = [
+        ("tile_y", ct.c_int32),
+        ("rows_per_thread", ct.c_int32),
+        ("zchunk", ct.c_int32),
+        ("us_per_step", ct.c_double),
     ]
 
 
@@ -114,6 +125,10 @@ def load(path: str = LIB_PATH):
     lib.lb_destroy.restype = ct.c_int
     lib.lb_last_error.argtypes = []
     lib.lb_last_error.restype = ct.c_char_p
+    lib.lb_set_tiles.argtypes = [ct.c_void_p, P(LbTile), ct.c_void_p]
+    lib.lb_set_tiles.restype = ct.c_int
+    lib.lb_autotune.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p, P(LbTile)]
+    lib.lb_autotune.restype = ct.c_int
     lib.lb_abi_sizes.argtypes = [P(ct.c_size_t)]
     lib.lb_abi_sizes.restype = None
     sizes = (ct.c_size_t * 3)()

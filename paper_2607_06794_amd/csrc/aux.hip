@@ -158,9 +158,23 @@ __global__ void __launch_bounds__(256) obs_partial_kernel(const S *f, int64_t fs
     }
 }
 
+// fold the per-tile ledger slots into the carry (fixed order) and clear them
+__global__ void fold_ledger_kernel(double *ledger_part, int nslots, double *carry) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s0 = carry[0], s1 = carry[1];
+    for (int t = 0; t < nslots; ++t) {
+        s0 += ledger_part[2 * t];
+        s1 += ledger_part[2 * t + 1];
+        ledger_part[2 * t] = 0.0;
+        ledger_part[2 * t + 1] = 0.0;
+    }
+    carry[0] = s0;
+    carry[1] = s1;
+}
+
 // pass 2: one block sums the partials in a fixed order (deterministic)
 __global__ void obs_final_kernel(const double *partials, int nblocks, const double *ledger_part, int nledger,
-                                 double *result) {
+                                 const double *carry, double *result) {
     if (threadIdx.x != 0) return;
     double r[OBS_FIELDS];
     for (int q = 0; q < OBS_FIELDS; ++q) r[q] = 0.0;
@@ -169,6 +183,8 @@ __global__ void obs_final_kernel(const double *partials, int nblocks, const doub
             const double v = partials[b * OBS_FIELDS + q];
             r[q] = (q == 7) ? fmax(r[q], v) : r[q] + v;
         }
+    r[2] = carry[0];
+    r[3] = carry[1];
     for (int t = 0; t < nledger; ++t) {
         r[2] += ledger_part[2 * t];
         r[3] += ledger_part[2 * t + 1];
@@ -238,9 +254,15 @@ hipError_t launch_export(int prec, const void *f, int64_t fs, const uint8_t *mat
     });
 }
 
+hipError_t launch_fold_ledger(double *ledger_part, int nslots, double *carry, hipStream_t s) {
+    hipLaunchKernelGGL(fold_ledger_kernel, dim3(1), dim3(64), 0, s, ledger_part, nslots, carry);
+    return hipGetLastError();
+}
+
 hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t *mat, int64_t n,
-                              const double rho_ref[2], const double *ledger_part, int nledger, double *partials,
-                              int nblocks, double *result, hipStream_t s) {
+                              const double rho_ref[2], const double *ledger_part, int nledger,
+                              const double *ledger_carry, double *partials, int nblocks, double *result,
+                              hipStream_t s) {
     hipError_t e = by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(obs_partial_kernel<S>, dim3(nblocks), dim3(256), 0, s, static_cast<const S *>(f), fs, mat,
@@ -248,7 +270,8 @@ hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, ledger_part, nledger, result);
+    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, ledger_part, nledger,
+                       ledger_carry, result);
     return hipGetLastError();
 }
 

@@ -64,8 +64,10 @@ int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
 //   status   : 256 bytes (status word)
 //   partials : OBS_BLOCKS * OBS_FIELDS doubles
 //   result   : 256 bytes
+//   psi      : 16 x 2 doubles, ghost pseudo-densities per material id
+//   carry    : 2 doubles, ledger folded out of the tile slots on tile changes
 struct WsLayout {
-    size_t mat, ledger, status, partials, result, total;
+    size_t mat, ledger, status, partials, result, psi, carry, total;
     int max_tiles;
 };
 
@@ -84,8 +86,17 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + size_t(OBS_BLOCKS) * OBS_FIELDS * sizeof(double));
     w.result = o;
     o = align256(o + 256);
+    w.psi = o;
+    o = align256(o + 32 * sizeof(double));
+    w.carry = o;
+    o = align256(o + 2 * sizeof(double));
     w.total = o;
     return w;
+}
+
+bool tile_ok(int ty, int rp, bool tau1) {
+    const bool ok = (ty == 4 && rp == 1) || (ty == 8 && (rp == 1 || rp == 2)) || (ty == 16 && rp == 2);
+    return ok && (tau1 || rp == 1);
 }
 
 int validate(const lb_params *p) {
@@ -93,15 +104,19 @@ int validate(const lb_params *p) {
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(LB_EINVAL, "lattice must be at least 3 nodes per direction");
     if (nodes(p) > (int64_t(1) << 31) / 2) return fail(LB_EINVAL, "lattice too large for one context");
     if (elem_bytes(p->prec) == 0) return fail(LB_ENOTSUP, "unknown precision %d", p->prec);
+    // the step kernel addresses each component's 19 arrays through one buffer
+    // resource with 32-bit byte offsets
+    const uint64_t comp_bytes = uint64_t(Q) * uint64_t(((nodes(p) + 255) / 256) * 256 + 64) * elem_bytes(p->prec);
+    if (comp_bytes > 0xFFFFFFFFull) return fail(LB_EINVAL, "lattice too large: one component exceeds 4 GiB");
     for (int k = 0; k < 2; ++k)
         if (!(p->tau[k] > 0.5)) return fail(LB_EINVAL, "tau[%d] = %g must exceed 1/2", k, p->tau[k]);
     if (!isfinite(p->G)) return fail(LB_EINVAL, "G not finite");
     const int ty = p->tile_y ? p->tile_y : 8;
-    const int rp = p->rows_per_thread ? p->rows_per_thread : 2;
-    const bool ok_tile = (ty == 4 && rp == 1) || (ty == 8 && (rp == 1 || rp == 2)) || (ty == 16 && rp == 2);
-    if (!ok_tile) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
+    const int rp = p->rows_per_thread;
+    const int rp1 = p->rows_per_thread ? p->rows_per_thread : 1;
     const bool tau1 = p->tau[0] == 1.0 && p->tau[1] == 1.0;
-    if (!tau1 && rp != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
+    if (!tile_ok(ty, rp1, true)) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
+    if (!tau1 && rp1 != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
     if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
     return LB_OK;
 }
@@ -140,6 +155,9 @@ int validate_material(const lb_params *p, const uint8_t *m) {
 
 }  // namespace
 
+struct lb_ctx;
+static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk);
+
 struct lb_ctx {
     lb_params p;
     void *f[2];
@@ -149,13 +167,38 @@ struct lb_ctx {
     unsigned *status;
     double *partials;
     double *result;
+    double *psi;
+    double *carry;
+    double psi_host[32];
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
     int nledger;
+    int max_tiles;
     int64_t steps;
     int64_t fs;
     double rref[2];  // storage reference density of the precision form
 };
+
+// tile bookkeeping of a context (no device work)
+static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk) {
+    const lb_params *p = &c->p;
+    c->tile.tile_y = tile_y;
+    c->tile.rows_per_thread = rows_per_thread;
+    c->ntx = (p->nx + 63) / 64;
+    c->nty = (p->ny + tile_y - 1) / tile_y;
+    c->nledger = c->ntx * c->nty;
+    int zc = zchunk;
+    if (zc <= 0) {
+        // about two work-groups per CU while marching at least 8 planes
+        const int xy = c->ntx * c->nty;
+        int nzc = (512 + xy - 1) / xy;
+        nzc = std::max(1, std::min(nzc, (p->nz + 7) / 8));
+        zc = (p->nz + nzc - 1) / nzc;
+    }
+    c->zchunk = std::max(1, std::min(zc, p->nz));
+    c->nzc = (p->nz + c->zchunk - 1) / c->zchunk;
+    c->tile.zchunk = c->zchunk;
+}
 
 extern "C" {
 
@@ -210,24 +253,15 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->status = reinterpret_cast<unsigned *>(ws + w.status);
     c->partials = reinterpret_cast<double *>(ws + w.partials);
     c->result = reinterpret_cast<double *>(ws + w.result);
+    c->psi = reinterpret_cast<double *>(ws + w.psi);
+    c->carry = reinterpret_cast<double *>(ws + w.carry);
+    for (int m = 0; m < 16; ++m)
+        for (int k = 0; k < 2; ++k)
+            c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
     c->fs = lb_pop_stride(p);
+    c->max_tiles = w.max_tiles;
     for (int k = 0; k < 2; ++k) c->rref[k] = p->rho_ref[k];
-    c->tile.tile_y = p->tile_y ? p->tile_y : 8;
-    c->tile.rows_per_thread = p->rows_per_thread ? p->rows_per_thread : 2;
-    c->ntx = (p->nx + 63) / 64;
-    c->nty = (p->ny + c->tile.tile_y - 1) / c->tile.tile_y;
-    c->nledger = c->ntx * c->nty;
-    int zc = p->zchunk;
-    if (zc <= 0) {
-        // aim for ~1024 work-groups (4 per CU) while marching at least 8 planes
-        const int xy = c->ntx * c->nty;
-        int nzc = (1024 + xy - 1) / xy;
-        nzc = std::max(1, std::min(nzc, (p->nz + 7) / 8));
-        zc = (p->nz + nzc - 1) / nzc;
-    }
-    c->zchunk = std::max(1, std::min(zc, p->nz));
-    c->nzc = (p->nz + c->zchunk - 1) / c->zchunk;
-    c->tile.zchunk = c->zchunk;
+    apply_tiles(c, p->tile_y ? p->tile_y : 8, p->rows_per_thread ? p->rows_per_thread : 1, p->zchunk);
     c->steps = 0;
 
     const int64_t n = nodes(p);
@@ -247,6 +281,10 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     if ((e = hipMemsetAsync(c->ledger, 0, size_t(w.max_tiles) * 2 * sizeof(double), stream)) != hipSuccess)
         return cleanup(hip_fail(e, "clear ledger"));
     if ((e = hipMemsetAsync(c->status, 0, 256, stream)) != hipSuccess) return cleanup(hip_fail(e, "clear status"));
+    if ((e = hipMemsetAsync(c->carry, 0, 2 * sizeof(double), stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "clear ledger carry"));
+    if ((e = hipMemcpyAsync(c->psi, c->psi_host, sizeof c->psi_host, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "upload psi table"));
     if ((e = launch_flags(c->mat, p->nx, p->ny, p->nz, per, stream)) != hipSuccess) return cleanup(hip_fail(e, "flags"));
     if ((e = launch_init_populations(p->prec, c->f[0], c->fs, stage, c->mat, n, c->rref, stream)) != hipSuccess)
         return cleanup(hip_fail(e, "init populations"));
@@ -288,8 +326,7 @@ int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
     }
     a.G = p.G;
     for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
-    for (int m = 0; m < 16; ++m)
-        for (int k = 0; k < 2; ++k) a.psi_s[m][k] = m < LB_NMAT ? p.psi_solid[m][k] : 0.0;
+    a.psi_tab = c->psi;
     const bool tau1 = (p.tau[0] == 1.0 && p.tau[1] == 1.0);
     for (int s = 0; s < nsteps; ++s) {
         a.fsrc = c->f[c->cur];
@@ -306,7 +343,7 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     if (!c || !out) return fail(LB_EINVAL, "null argument");
     const lb_params &p = c->p;
     HIP_TRY(launch_observables(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, c->ledger, c->nledger,
-                               c->partials, OBS_BLOCKS, c->result, stream),
+                               c->carry, c->partials, OBS_BLOCKS, c->result, stream),
             "observables");
     double r[OBS_FIELDS];
     unsigned st = 0;
@@ -335,6 +372,61 @@ int lb_export(lb_ctx *c, double *rho_dev, double *f_dev, hipStream_t stream) {
     const lb_params &p = c->p;
     HIP_TRY(launch_export(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, rho_dev, f_dev, stream), "export");
     HIP_TRY(hipStreamSynchronize(stream), "export sync");
+    return LB_OK;
+}
+
+int lb_set_tiles(lb_ctx *c, const lb_tile *t, hipStream_t stream) {
+    if (!c || !t) return fail(LB_EINVAL, "null argument");
+    const bool tau1 = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
+    if (!tile_ok(t->tile_y, t->rows_per_thread, tau1))
+        return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", t->tile_y, t->rows_per_thread);
+    if (t->zchunk < 0) return fail(LB_EINVAL, "negative zchunk");
+    // the ledger slots are indexed by xy tile: fold them before the layout changes
+    HIP_TRY(launch_fold_ledger(c->ledger, c->max_tiles, c->carry, stream), "fold ledger");
+    apply_tiles(c, t->tile_y, t->rows_per_thread, t->zchunk);
+    return LB_OK;
+}
+
+int lb_autotune(lb_ctx *c, int32_t trial_steps, hipStream_t stream, lb_tile *best) {
+    if (!c || !best || trial_steps < 1) return fail(LB_EINVAL, "bad autotune arguments");
+    const bool tau1 = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
+    const int shapes[4][2] = {{4, 1}, {8, 1}, {8, 2}, {16, 2}};
+    const int nz = c->p.nz;
+    std::vector<int> chunks;
+    for (int zc : {4, 8, 12, 16, 24, 32, 48, 64})
+        if (zc <= nz) chunks.push_back(zc);
+    if (chunks.empty()) chunks.push_back(nz);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    lb_tile b{0, 0, 0, 1e30};
+    int rc = LB_OK;
+    for (const auto &sh : shapes) {
+        if (!tile_ok(sh[0], sh[1], tau1)) continue;
+        for (int zc : chunks) {
+            lb_tile t{sh[0], sh[1], zc, 0.0};
+            if ((rc = lb_set_tiles(c, &t, stream)) != LB_OK) break;
+            if ((rc = lb_step(c, 1, stream)) != LB_OK) break;  // first launch of a shape untimed
+            (void)hipEventRecord(e0, stream);
+            if ((rc = lb_step(c, trial_steps, stream)) != LB_OK) break;
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(LB_EHIP, "autotune sync");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1e3 * ms / trial_steps;
+            if (us < b.us_per_step) b = lb_tile{sh[0], sh[1], zc, us};
+        }
+        if (rc != LB_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LB_OK) return rc;
+    rc = lb_set_tiles(c, &b, stream);
+    if (rc != LB_OK) return rc;
+    *best = b;
     return LB_OK;
 }
 

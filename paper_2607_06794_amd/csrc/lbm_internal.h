@@ -23,7 +23,7 @@ struct StepArgs {
     double tau[2], omega[2];
     double G;
     double g[3];
-    double psi_s[16][2];
+    const double *psi_tab;  // [16][2] ghost pseudo-densities per material id (device)
     double rho_top[2];
     double rho_ref[2];
 };
@@ -51,7 +51,9 @@ hipError_t launch_export(int prec, const void *f, int64_t fs, const uint8_t *mat
 // max_speed, kinetic, fluid_nodes
 hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t *mat, int64_t n,
                               const double rho_ref[2], const double *ledger_part, int nledger,
-                              double *partials, int nblocks, double *result, hipStream_t s);
+                              const double *ledger_carry, double *partials, int nblocks, double *result,
+                              hipStream_t s);
+hipError_t launch_fold_ledger(double *ledger_part, int nslots, double *carry, hipStream_t s);
 constexpr int OBS_BLOCKS = 512;
 constexpr int OBS_FIELDS = 10;
 

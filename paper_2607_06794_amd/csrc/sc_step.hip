@@ -15,8 +15,14 @@
 // it pulls f_i(x) = f*_i(x - c_i) for its TY rows plus a one-node ring around
 // them, sums the densities of all (TY+2) x 66 positions into a 4-plane LDS
 // ring of pseudo-potentials, and finishes the plane below once the plane above
-// is in LDS.  Densities therefore never travel through HBM: every population
-// is read once and written once, the ring re-reads hit L2.
+// is in LDS.  Densities never travel through HBM: every population is read
+// once and written once; the ring re-reads mostly hit L2.
+//
+// Addressing: all HBM traffic goes through buffer resources (one per
+// component).  The plane being marched is the same for the whole work-group,
+// so the array index and the z offset form a wave-uniform scalar offset, and
+// each thread keeps nine fixed xy offsets (the 3 x 3 neighbourhood of its
+// node): a pull costs no vector address arithmetic.
 //
 // Boundaries inside the same pass:
 //  * static walls (halfway bounce-back): a fluid node next to a wall writes
@@ -24,8 +30,8 @@
 //    is branch-free;
 //  * the reservoir plane z = nz-1: the plane below it takes w_i rho_top_k for
 //    the directions pulled from the reservoir and books the outflow of its
-//    stored f*(t) towards the reservoir into a
-//    per-tile FP64 ledger slot (deterministic: each tile owns its slot);
+//    stored f*(t) towards the reservoir into a per-tile FP64 ledger slot
+//    (deterministic: each tile owns its slot);
 //  * rod nodes: their slots are written by the rod link kernel.
 #include "lbm_device.h"
 #include "lbm_internal.h"
@@ -34,21 +40,76 @@ namespace lbm {
 
 namespace {
 
+constexpr int RSRC_FLAGS = 0x00020000;  // raw dword buffer, gfx9 family
+
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 __device__ inline int wrapmod(int v, int n) {
     int r = v % n;
     return r < 0 ? r + n : r;
 }
 
-// Per-node source offsets: o[0] = coordinate - 1, o[1] = coordinate, o[2] = + 1
-struct NodeIdx {
-    uint32_t xo[3];
-    uint32_t yo[3];  // already multiplied by nx
+// raw buffer access of one storage element at byte offsets (voff per lane, soff uniform)
+template <class S>
+__device__ inline S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __hiloint2double(static_cast<int>(v[1]), static_cast<int>(v[0]));
+}
+template <>
+__device__ inline _Float16 buf_load<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return __builtin_bit_cast(_Float16, b);
+}
+template <>
+__device__ inline bf16_t buf_load<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    bf16_t o;
+    o.bits = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return o;
+}
+
+template <class S>
+__device__ inline void buf_store(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+template <>
+__device__ inline void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const unsigned long long u = __double_as_longlong(v);
+    __attribute__((ext_vector_type(2))) unsigned int w;
+    w[0] = static_cast<unsigned int>(u);
+    w[1] = static_cast<unsigned int>(u >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
+}
+template <>
+__device__ inline void buf_store<_Float16>(_Float16 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+}
+template <>
+__device__ inline void buf_store<bf16_t>(bf16_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(v.bits, r, voff, soff, 0);
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                             RSRC_FLAGS);
+}
+
+// A node's 3 x 3 xy neighbourhood as element offsets within a plane:
+// xy[a][b] = (y + a - 1) * nx + (x + b - 1) with periodic wrap (clamped when
+// the direction is closed, where fluid nodes never reach the end planes).
+struct NodeXY {
+    uint32_t xy[3][3];
     bool valid;
 };
 
-__device__ inline NodeIdx make_node(int x, int y, const StepArgs &a) {
-    NodeIdx n;
+__device__ inline NodeXY make_node(int x, int y, const StepArgs &a) {
+    NodeXY n;
     bool vx, vy;
     if (a.px) {
         x = wrapmod(x, a.nx);
@@ -65,34 +126,13 @@ __device__ inline NodeIdx make_node(int x, int y, const StepArgs &a) {
     n.valid = vx && vy;
     x = min(max(x, 0), a.nx - 1);
     y = min(max(y, 0), a.ny - 1);
-    const int xm = a.px ? wrap1(x - 1, a.nx) : max(x - 1, 0);
-    const int xp = a.px ? wrap1(x + 1, a.nx) : min(x + 1, a.nx - 1);
-    const int ym = a.py ? wrap1(y - 1, a.ny) : max(y - 1, 0);
-    const int yp = a.py ? wrap1(y + 1, a.ny) : min(y + 1, a.ny - 1);
-    n.xo[0] = xm;
-    n.xo[1] = x;
-    n.xo[2] = xp;
-    n.yo[0] = static_cast<uint32_t>(ym) * a.nx;
-    n.yo[1] = static_cast<uint32_t>(y) * a.nx;
-    n.yo[2] = static_cast<uint32_t>(yp) * a.nx;
-    return n;
-}
-
-// Pull the 19 population deviations d_i = f_i - w_i rho_ref of component k at
-// node n on the plane with offsets zo; directions pulled from the reservoir
-// plane take w_i (rho_top_k - rho_ref_k).
-template <class S, class C>
-__device__ inline void pull_devs(const S *__restrict__ f, int64_t fs, int k, const NodeIdx &n,
-                                 const uint32_t zo[3], bool top_rule, C top_dev_k, C v[Q]) {
+    const int xs[3] = {a.px ? wrap1(x - 1, a.nx) : max(x - 1, 0), x, a.px ? wrap1(x + 1, a.nx) : min(x + 1, a.nx - 1)};
+    const int ys[3] = {a.py ? wrap1(y - 1, a.ny) : max(y - 1, 0), y, a.py ? wrap1(y + 1, a.ny) : min(y + 1, a.ny - 1)};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const uint32_t src = zo[1 - cz(i)] + n.yo[1 - cy(i)] + n.xo[1 - cx(i)];
-        if (cz(i) == -1 && top_rule) {
-            v[i] = wgt<C>(i) * top_dev_k;
-        } else {
-            v[i] = Codec<S>::dec(f[static_cast<int64_t>(k * Q + i) * fs + src]);
-        }
-    }
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) n.xy[p][q] = static_cast<uint32_t>(ys[p]) * a.nx + xs[q];
+    return n;
 }
 
 template <class C>
@@ -114,41 +154,65 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
     constexpr int NH = 2 * HX + 2 * TY;
     constexpr int NHPT = (NH + NT - 1) / NT;
     constexpr int NW = NT / 64;
+    constexpr uint32_t E = sizeof(S);
+    // software-pipelined plane loads need a second set of raw registers; that
+    // fits for tau = 1 with 4- or 2-byte storage, the other forms load and
+    // consume a plane in turn
+    constexpr bool PIPE = TAU1 && sizeof(S) <= 4;
 
     __shared__ C ring[4][2][PL];
+    __shared__ C psi_tab[16][2];
     __shared__ double red[NW][2];
 
-    // ---- tile of this work-group; consecutive tiles stay on one XCD
+    // ---- tile of this work-group.  Work-groups are dealt to the eight XCDs
+    // round-robin; the remap gives each XCD a contiguous range of logical
+    // tiles, ordered z-chunk fastest, so an XCD owns whole xy columns and
+    // neighbouring columns (their shared ring reads then hit its L2).
     const int nblk = gridDim.x;
     int b = blockIdx.x;
     if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-    const int tx = b % a.ntx;
-    const int ty = (b / a.ntx) % a.nty;
-    const int tz = b / (a.ntx * a.nty);
+    const int tz = b % a.nzc;
+    const int tx = (b / a.nzc) % a.ntx;
+    const int ty = b / (a.nzc * a.ntx);
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = tz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, a.nz);
     if (z0 >= a.nz) return;  // uniform per block
+    // even chunks march up, odd chunks march down: two chunks meet at their
+    // shared boundary plane at the same time (both at the start or both at
+    // the end of their marches), so the boundary pulls are shared in cache
+    const int dir = (tz & 1) ? -1 : 1;
+    const int zfirst = dir > 0 ? z0 : z1 - 1;
+    const int nplanes = z1 - z0;
 
     const int tid = threadIdx.x;
     const int lx = tid & 63;
     const int ly = tid >> 6;
-    const S *__restrict__ fsrc = static_cast<const S *>(a.fsrc);
-    S *__restrict__ fdst = static_cast<S *>(a.fdst);
     const uint32_t nxy = static_cast<uint32_t>(a.nx) * a.ny;
+    const uint32_t fsE = static_cast<uint32_t>(a.fs) * E;  // bytes between population arrays
+
+    // one buffer resource per component over its 19 arrays
+    __amdgpu_buffer_rsrc_t src[2], dst[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        src[k] = make_rsrc(static_cast<const char *>(a.fsrc) + size_t(k) * Q * fsE, Q * fsE);
+        dst[k] = make_rsrc(static_cast<const char *>(a.fdst) + size_t(k) * Q * fsE, Q * fsE);
+    }
+    const __amdgpu_buffer_rsrc_t matr = make_rsrc(a.mat, nxy * a.nz);
+
+    if (tid < 32) psi_tab[tid >> 1][tid & 1] = C(a.psi_tab[tid]);
 
     // constants in compute precision; rref is the storage reference density
-    // (0 for the FP64 form), populations travel as d_i = f_i - w_i rref
+    // (populations travel as d_i = f_i - w_i rref)
     const C G = C(a.G);
     const C rref[2] = {C(a.rho_ref[0]), C(a.rho_ref[1])};
-    const C rtop[2] = {C(a.rho_top[0]), C(a.rho_top[1])};
     const C tdev[2] = {C(a.rho_top[0] - a.rho_ref[0]), C(a.rho_top[1] - a.rho_ref[1])};
     const C om[2] = {C(a.omega[0]), C(a.omega[1])};
     const C ta[2] = {C(a.tau[0]), C(a.tau[1])};
     const C gb[3] = {C(a.g[0]), C(a.g[1]), C(a.g[2])};
 
     // ---- owned interior nodes and ring (halo) nodes of this thread
-    NodeIdx own[NPT];
+    NodeXY own[NPT];
     bool own_fin[NPT];
     int own_ring[NPT];
 #pragma unroll
@@ -158,7 +222,7 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
         own_fin[r] = (x0 + lx < a.nx) && (y0 + yy < a.ny);
         own_ring[r] = (yy + 1) * HX + (lx + 1);
     }
-    NodeIdx hal[NHPT];
+    NodeXY hal[NHPT];
     int hal_ring[NHPT];
     bool hal_on[NHPT];
 #pragma unroll
@@ -183,6 +247,7 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
         hal[m] = make_node(x0 + hx - 1, y0 + hy - 1, a);
         hal_ring[m] = hy * HX + hx;
     }
+    __syncthreads();  // psi_tab
 
     // moments of the owned nodes: current plane and next plane
     C cur_rho[NPT][2], cur_drho[NPT][2], cur_j[NPT][2][3];
@@ -191,68 +256,106 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
     C nxt_f[TAU1 ? 1 : NPT][TAU1 ? 1 : 2][TAU1 ? 1 : Q];
     uint8_t cur_m[NPT], nxt_m[NPT];
 
+    // raw pulled values of one plane, in flight between issue() and process()
+    S raw_own[NPT][2][Q];
+    S raw_hal[NHPT][2][Q];
+    uint8_t mat_own[NPT], mat_hal[NHPT];
+    bool plane_valid = false, plane_top = false;
+
     // psi of a node given its material byte and densities
     auto psi_of = [&](uint8_t m, int k, C rho) -> C {
         const uint8_t id = m & MAT_ID_MASK;
-        if (id == MAT_FLUID) return rho;
-        if (id == MAT_GHOST) return rtop[k];
-        return C(a.psi_s[id][k]);
+        return id == MAT_FLUID ? rho : psi_tab[id][k];
     };
 
-    // fill the ring slot of plane z (and the owned moments when own_out)
-    auto fill_plane = [&](int z, bool keep) {
-        const int slot = z & 3;
-        bool zvalid;
+    // Issue the pulls f*_i(x - c_i) of plane z for the owned and ring nodes.
+    // Loads are unconditional (every offset is wrapped or clamped into the
+    // lattice); values pulled for non-fluid nodes are discarded by process().
+    // Directions pulled from the reservoir plane are not loaded.
+    auto issue = [&](int z) {
         int zz = z;
         if (a.pz) {
             zz = wrap1(z, a.nz);
-            zvalid = true;
+            plane_valid = true;
         } else {
-            zvalid = (z >= 0 && z < a.nz);
+            plane_valid = (z >= 0 && z < a.nz);
         }
         zz = min(max(zz, 0), a.nz - 1);
         const int zm = a.pz ? wrap1(zz - 1, a.nz) : max(zz - 1, 0);
         const int zp = a.pz ? wrap1(zz + 1, a.nz) : min(zz + 1, a.nz - 1);
-        const uint32_t zo[3] = {zm * nxy, zz * nxy, zp * nxy};
-        const bool top_rule = a.evap && (zz == a.nz - 2);
+        const uint32_t zoE[3] = {zm * nxy * E, zz * nxy * E, zp * nxy * E};
+        plane_top = a.evap && (zz == a.nz - 2);
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            const NodeIdx &n = own[r];
-            const bool v = zvalid && n.valid;
-            const uint8_t m = v ? a.mat[zo[1] + n.yo[1] + n.xo[1]] : uint8_t(MAT_ID_MASK);
+            mat_own[r] = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, own[r].xy[1][1], zz * nxy, 0));
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (!(cz(i) == -1 && plane_top))
+                        raw_own[r][k][i] =
+                            buf_load<S>(src[k], own[r].xy[1 - cy(i)][1 - cx(i)] * E, i * fsE + zoE[1 - cz(i)]);
+        }
+#pragma unroll
+        for (int mm = 0; mm < NHPT; ++mm) {
+            if (!hal_on[mm]) continue;
+            mat_hal[mm] = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, hal[mm].xy[1][1], zz * nxy, 0));
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (!(cz(i) == -1 && plane_top))
+                        raw_hal[mm][k][i] =
+                            buf_load<S>(src[k], hal[mm].xy[1 - cy(i)][1 - cx(i)] * E, i * fsE + zoE[1 - cz(i)]);
+        }
+    };
+
+    // decoded deviation d_i of a raw pulled value (reservoir sources: w_i (rho_top - rref))
+    auto devof = [&](const S (&raw)[2][Q], int k, int i) -> C {
+        return (cz(i) == -1 && plane_top) ? wgt<C>(i) * tdev[k] : Codec<S>::dec(raw[k][i]);
+    };
+
+    // Turn the issued plane into psi values in ring slot z & 3 and, when
+    // keep, into the owned nodes' moments for the next finish.
+    auto process = [&](int z, bool keep) {
+        const int slot = z & 3;
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const bool v = plane_valid && own[r].valid;
+            const uint8_t m = v ? mat_own[r] : uint8_t(MAT_ID_MASK);
             C rho[2] = {C(0), C(0)}, drho[2] = {C(0), C(0)};
             C j[2][3] = {{C(0), C(0), C(0)}, {C(0), C(0), C(0)}};
-            if (v && (m & MAT_ID_MASK) == MAT_FLUID) {
+            const bool fl = v && (m & MAT_ID_MASK) == MAT_FLUID;
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    C fv[Q];
-                    pull_devs<S, C>(fsrc, a.fs, k, n, zo, top_rule, tdev[k], fv);
-                    C s = C(0), jx = C(0), jy = C(0), jz = C(0);
+            for (int k = 0; k < 2; ++k) {
+                C fv[Q];
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) s += fv[i];
-                    // momentum over opposite pairs: f_i - f_opp(i) is nearly exact
-                    // (the two are close), which avoids cancellation in j
+                for (int i = 0; i < Q; ++i) fv[i] = devof(raw_own[r], k, i);
+                C s = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
-                    for (int i = 1; i < Q; i += 2) {
-                        const C d = fv[i] - fv[i + 1];
-                        if (cx(i) == 1) jx += d;
-                        if (cx(i) == -1) jx -= d;
-                        if (cy(i) == 1) jy += d;
-                        if (cy(i) == -1) jy -= d;
-                        if (cz(i) == 1) jz += d;
-                        if (cz(i) == -1) jz -= d;
-                    }
-                    // Eq. 3: rho_k = sum_i f_i = rref_k + sum_i d_i (sum_i w_i = 1)
-                    drho[k] = s;
-                    rho[k] = rref[k] + s;
-                    j[k][0] = jx;
-                    j[k][1] = jy;
-                    j[k][2] = jz;
-                    if constexpr (!TAU1) {
-                        if (keep) {
+                for (int i = 0; i < Q; ++i) s += fv[i];
+                // momentum over opposite pairs: f_i - f_opp(i) is nearly exact
+                // (the two are close), which avoids cancellation in j
 #pragma unroll
-                            for (int i = 0; i < Q; ++i) nxt_f[r][k][i] = fv[i];
-                        }
+                for (int i = 1; i < Q; i += 2) {
+                    const C d = fv[i] - fv[i + 1];
+                    if (cx(i) == 1) jx += d;
+                    if (cx(i) == -1) jx -= d;
+                    if (cy(i) == 1) jy += d;
+                    if (cy(i) == -1) jy -= d;
+                    if (cz(i) == 1) jz += d;
+                    if (cz(i) == -1) jz -= d;
+                }
+                // Eq. 3: rho_k = sum_i f_i = rref_k + sum_i d_i (sum_i w_i = 1)
+                drho[k] = fl ? s : C(0);
+                rho[k] = fl ? rref[k] + s : C(0);
+                j[k][0] = fl ? jx : C(0);
+                j[k][1] = fl ? jy : C(0);
+                j[k][2] = fl ? jz : C(0);
+                if constexpr (!TAU1) {
+                    if (keep) {
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) nxt_f[r][k][i] = fv[i];
                     }
                 }
             }
@@ -272,20 +375,16 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
 #pragma unroll
         for (int mm = 0; mm < NHPT; ++mm) {
             if (!hal_on[mm]) continue;
-            const NodeIdx &n = hal[mm];
-            const bool v = zvalid && n.valid;
-            const uint8_t m = v ? a.mat[zo[1] + n.yo[1] + n.xo[1]] : uint8_t(MAT_ID_MASK);
+            const bool v = plane_valid && hal[mm].valid;
+            const uint8_t m = v ? mat_hal[mm] : uint8_t(MAT_ID_MASK);
+            const bool fl = v && (m & MAT_ID_MASK) == MAT_FLUID;
             C rho[2] = {C(0), C(0)};
-            if (v && (m & MAT_ID_MASK) == MAT_FLUID) {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    C fv[Q];
-                    pull_devs<S, C>(fsrc, a.fs, k, n, zo, top_rule, tdev[k], fv);
-                    C s = C(0);
+            for (int k = 0; k < 2; ++k) {
+                C s = C(0);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) s += fv[i];
-                    rho[k] = rref[k] + s;
-                }
+                for (int i = 0; i < Q; ++i) s += devof(raw_hal[mm], k, i);
+                rho[k] = fl ? rref[k] + s : C(0);
             }
             ring[slot][0][hal_ring[mm]] = v ? psi_of(m, 0, rho[0]) : C(0);
             ring[slot][1][hal_ring[mm]] = v ? psi_of(m, 1, rho[1]) : C(0);
@@ -310,17 +409,33 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
         }
     };
 
-    // prologue: planes z0-1 (psi only) and z0 (psi + moments)
-    fill_plane(z0 - 1, false);
-    fill_plane(z0, true);
+    // prologue: the plane behind the first one (psi only), the first plane
+    // (psi + moments), then the loads of the plane after it
+    issue(zfirst - dir);
+    process(zfirst - dir, false);
+    issue(zfirst);
+    process(zfirst, true);
     shift_next();
+    if constexpr (PIPE) issue(zfirst + dir);
 
-    for (int z = z0; z < z1; ++z) {
-        fill_plane(z + 1, true);
+    for (int it = 0; it < nplanes; ++it) {
+        const int z = zfirst + it * dir;
+        // the ring holds 4 planes: this iteration writes plane z + dir and
+        // reads z - 1, z, z + 1; the next one writes z + 2 dir, which no
+        // thread of this iteration reads, so one barrier per plane suffices
+        if constexpr (PIPE) {
+            process(z + dir, true);
+            // software pipeline: the pulls of plane z + 2 dir stay in flight
+            // across the barrier (which waits on LDS only) and the finish below
+            if (it + 1 < nplanes) issue(z + 2 * dir);
+        } else {
+            issue(z + dir);
+            process(z + dir, true);
+        }
         __syncthreads();
 
         const int sm = (z - 1) & 3, s0 = z & 3, sp = (z + 1) & 3;
-        const uint32_t zoff = static_cast<uint32_t>(z) * nxy;
+        const uint32_t zE = static_cast<uint32_t>(z) * nxy * E;
         const bool ledger_plane = a.evap && (z == a.nz - 2);
         double led[2] = {0.0, 0.0};
         unsigned st = 0;
@@ -366,7 +481,7 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
             if (!(rho[0] + rho[1] > C(0))) st |= ST_RHO;
             if (!(usq_chk <= C(0.09))) st |= (usq_chk != usq_chk) ? ST_NAN : ST_SPEED;
 
-            const uint32_t idx = zoff + own[r].yo[1] + own[r].xo[1];
+            const uint32_t voE = own[r].xy[1][1] * E;
             const bool near_wall = (cur_m[r] & MAT_NEAR_WALL) != 0;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -379,29 +494,35 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
                 const C dr = cur_drho[r][k];
                 C fstar[Q];
                 C deq_sum = C(0);
+                // Eq. 2 as a deviation, built per opposite pair (i, opp(i)):
+                //   f^eq - w rref = w (rho - rref) + w rho [9/2 (c.u)^2 - 3/2 u^2]  +-  w rho 3 c.u
+                // The rest population is the remainder so that sum_i f_i^eq = rho holds up to
+                // one rounding: the rounded weights do not sum to one, and using them for all
+                // 19 directions would drift the mass by a fixed factor every step.
+                C deq[Q];
+                const C base = C(-1.5) * usq;
 #pragma unroll
-                for (int ii = 1; ii <= Q; ++ii) {
-                    const int i = ii % Q;  // directions 1..18 first, the rest direction last
-                    // Eq. 2 as a deviation: f_i^eq - w_i rref = w_i (rho - rref) + w_i rho [3 c.u + 9/2 (c.u)^2 - 3/2 u^2].
-                    // The rest population is the remainder so that sum_i f_i^eq = rho holds up to one
-                    // rounding: the rounded weights do not sum to one, and using them for all 19
-                    // directions would drift the mass by a fixed factor every step.
+                for (int i = 1; i < Q; i += 2) {
                     const C cu = C(cx(i)) * ue[0] + C(cy(i)) * ue[1] + C(cz(i)) * ue[2];
-                    C deq;
-                    if (i != 0) {
-                        deq = wgt<C>(i) * dr + wgt<C>(i) * rho[k] * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq);
-                        deq_sum += deq;
-                    } else {
-                        deq = dr - deq_sum;
-                    }
+                    const C wr = wgt<C>(i) * rho[k];
+                    const C sym = wgt<C>(i) * dr + wr * (base + C(4.5) * cu * cu);
+                    const C asym = wr * (C(3) * cu);
+                    deq[i] = sym + asym;
+                    deq[i + 1] = sym - asym;
+                    deq_sum += deq[i];
+                    deq_sum += deq[i + 1];
+                }
+                deq[0] = dr - deq_sum;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
                     C ds;
                     if constexpr (TAU1) {
-                        ds = deq;  // Eq. 1 with tau = 1: f* = f^eq
+                        ds = deq[i];  // Eq. 1 with tau = 1: f* = f^eq
                     } else {
-                        ds = cur_f[r][k][i] - (cur_f[r][k][i] - deq) * om[k];
+                        ds = cur_f[r][k][i] - (cur_f[r][k][i] - deq[i]) * om[k];
                     }
                     fstar[i] = ds;
-                    fdst[static_cast<int64_t>(k * Q + i) * a.fs + idx] = Codec<S>::enc(ds);
+                    buf_store<S>(Codec<S>::enc(ds), dst[k], voE, i * fsE + zE);
                 }
                 if (ledger_plane) {
                     // this step's streaming moves the node's stored f*_i(t) with c_iz = +1
@@ -410,7 +531,7 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         if (cz(i) == 1)
-                            outflow += double(Codec<S>::dec(fsrc[static_cast<int64_t>(k * Q + i) * a.fs + idx])) +
+                            outflow += double(Codec<S>::dec(buf_load<S>(src[k], voE, i * fsE + zE))) +
                                        wgt<double>(i) * a.rho_ref[k];
                         if (cz(i) == -1) inflow += wgt<double>(i) * a.rho_top[k];
                     }
@@ -419,14 +540,16 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
                 if (near_wall) {
                     // halfway bounce-back: hand f*_j(x) to the wall node x + c_j as
                     // direction opp(j) (w_j = w_opp(j), so the deviation carries over)
-                    const uint32_t zo3[3] = {
-                        static_cast<uint32_t>(a.pz ? wrap1(z - 1, a.nz) : max(z - 1, 0)) * nxy, zoff,
+                    const uint32_t zl[3] = {
+                        static_cast<uint32_t>(a.pz ? wrap1(z - 1, a.nz) : max(z - 1, 0)) * nxy,
+                        static_cast<uint32_t>(z) * nxy,
                         static_cast<uint32_t>(a.pz ? wrap1(z + 1, a.nz) : min(z + 1, a.nz - 1)) * nxy};
 #pragma unroll
                     for (int jd = 1; jd < Q; ++jd) {
-                        const uint32_t nb = zo3[1 + cz(jd)] + own[r].yo[1 + cy(jd)] + own[r].xo[1 + cx(jd)];
-                        if (is_static_wall(a.mat[nb] & MAT_ID_MASK))
-                            fdst[static_cast<int64_t>(k * Q + opp(jd)) * a.fs + nb] = Codec<S>::enc(fstar[jd]);
+                        const uint32_t nxyo = own[r].xy[1 + cy(jd)][1 + cx(jd)];
+                        const uint8_t nm = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, nxyo, zl[1 + cz(jd)], 0));
+                        if (is_static_wall(nm & MAT_ID_MASK))
+                            buf_store<S>(Codec<S>::enc(fstar[jd]), dst[k], nxyo * E, opp(jd) * fsE + zl[1 + cz(jd)] * E);
                     }
                 }
             }

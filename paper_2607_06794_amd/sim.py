@@ -7,6 +7,8 @@ module only allocates memory, passes pointers and converts results.
 from __future__ import annotations
 
 import ctypes as ct
+import json
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -141,6 +143,51 @@ class Lattice:
             )
         )
         return rho.cpu().numpy(), (f.cpu().numpy() if f is not None else None)
+
+    def set_tiles(self, tile_y: int, rows_per_thread: int, zchunk: int = 0):
+        t = _lib.LbTile(int(tile_y), int(rows_per_thread), int(zchunk), 0.0)
+        _lib.check(self.lib.lb_set_tiles(self._ctx, ct.byref(t), _stream_ptr(self.stream)))
+        return self
+
+    def _tile_key(self):
+        import torch
+
+        p = self.params
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        return f"{arch}|{p.prec}|{'x'.join(str(v) for v in p.shape)}|tau1={p.tau == (1.0, 1.0)}"
+
+    def autotune(self, trial_steps: int = 20, cache: str | None = None) -> dict:
+        """Pick the fastest tile shape with lb_autotune (real steps), caching by lattice class.
+
+        The cache is a JSON file keyed by (gfx arch, precision, lattice shape,
+        tau = 1); a hit applies the stored shape without running trials.
+        """
+        path = cache or os.path.join(
+            os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "paper_2607_06794_amd", "tiles.json")
+        key = self._tile_key()
+        table = {}
+        try:
+            with open(path) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+        if key in table:
+            t = table[key]
+            self.set_tiles(t["tile_y"], t["rows_per_thread"], t["zchunk"])
+            return dict(t, cached=True)
+        best = _lib.LbTile()
+        _lib.check(self.lib.lb_autotune(self._ctx, int(trial_steps), _stream_ptr(self.stream), ct.byref(best)))
+        t = {"tile_y": best.tile_y, "rows_per_thread": best.rows_per_thread, "zchunk": best.zchunk,
+             "us_per_step": best.us_per_step}
+        table[key] = t
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path + ".tmp", "w") as fh:
+                json.dump(table, fh, indent=1)
+            os.replace(path + ".tmp", path)
+        except OSError:
+            pass
+        return dict(t, cached=False)
 
     def close(self):
         if self._ctx:

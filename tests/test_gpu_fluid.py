@@ -199,3 +199,43 @@ def test_deviation_storage_fp64_parity():
     fo, ro, _, _ = oracle_run("cfg1", 1000)
     fg, rg, _ = gpu_run("cfg1", "f64", 1000, rho_ref=(1.0, 1.0))
     assert cases.rel_err(fg, fo) <= 1e-12 and cases.rel_err(rg, ro) <= 1e-12
+
+
+def test_tile_switching_mid_run_and_autotune(tmp_path):
+    """Changing tiles between steps (and the autotuner's trial steps) keeps the
+    populations bitwise identical to a fixed-tile run; the ledger agrees to
+    FP64 rounding (its per-tile slots are folded in a fixed order)."""
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = small_cap()
+    ref = Lattice(cases.lattice_params(c, "f64", tile_y=8, rows_per_thread=1, zchunk=5), c["rho"], c["mat"])
+    ref.step(40)
+    o_ref = ref.observables()
+    _, f_ref = ref.export()
+    ref.close()
+    lat = Lattice(cases.lattice_params(c, "f64", tile_y=4, rows_per_thread=1), c["rho"], c["mat"])
+    for i, (ty, rp, zc) in enumerate([(8, 2, 0), (16, 2, 7), (4, 1, 20), (8, 1, 3)]):
+        lat.step(5)
+        lat.set_tiles(ty, rp, zc)
+    lat.step(20)
+    o = lat.observables()
+    _, f = lat.export()
+    lat.close()
+    assert np.array_equal(f, f_ref)
+    assert np.allclose(o["ledger"], o_ref["ledger"], rtol=1e-14, atol=1e-12)
+    # autotune: returns a supported shape, caches it, and the run stays on the oracle trajectory
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    t = lat.autotune(trial_steps=2, cache=str(tmp_path / "tiles.json"))
+    assert (t["tile_y"], t["rows_per_thread"]) in {(4, 1), (8, 1), (8, 2), (16, 2)} and t["us_per_step"] > 0
+    steps_done = lat.observables()["step"]
+    lat.close()
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    t2 = lat.autotune(trial_steps=2, cache=str(tmp_path / "tiles.json"))
+    assert t2["cached"] and t2["tile_y"] == t["tile_y"] and t2["zchunk"] == t["zchunk"]
+    lat.close()
+    fo, _, _, _ = oracle_run("cap_small", steps_done)
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    lat.autotune(trial_steps=2, cache=str(tmp_path / "other.json"))
+    _, fg = lat.export()
+    lat.close()
+    assert cases.rel_err(fg, fo) <= 1e-5
