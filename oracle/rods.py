@@ -30,7 +30,9 @@ bounce-back on every boundary link:
 * Re-mask after the move: a node the rod now covers gives its fluid mass to
   the solid-exchange ledger and its momentum to the rod; a node it uncovers
   gets f^eq(rho_bar, u_b) with rho_bar the mean density of its fluid
-  neighbours, paid for by the rod and the ledger.
+  neighbours, paid for by the rod and the ledger.  All transfers of one
+  re-mask use the rod state right after the substeps and are applied to the
+  rod together.
 
 Readings of the paper and the task that these choices take are listed in the
 design notes (rod shape, d0 = 2R + 1, r_c = 1.5 d0, shifted cohesion, wall
@@ -428,6 +430,10 @@ class CoupledRun:
         uncovered = (old_rid >= 0) & (new_rid < 0)
         stay_fluid = (old_rid < 0) & (new_rid < 0) & (self.static == lbm.FLUID)
         f = self.f
+        # all transfers of one re-mask act on the rod state right after the
+        # substeps: they are summed per rod and applied together at the end
+        dV = np.zeros((n, 3))
+        dL = np.zeros((n, 3))
         for z, y, x in zip(*np.nonzero(covered)):
             r = new_rid[z, y, x]
             pos = np.array([x, y, z], dtype=np.float64)
@@ -436,8 +442,8 @@ class CoupledRun:
                 rk, jk = lbm.moments(f[k, :, z, y, x][:, None])
                 self.solid[k] += rk[0]
                 mom += jk[:, 0]
-            rods.V[r] += mom / rods.p.mass
-            rods.L[r] += np.cross(min_image(pos - rods.X[r], rods.box, rods.periodic), mom)
+            dV[r] += mom
+            dL[r] += np.cross(min_image(pos - rods.X[r], rods.box, rods.periodic), mom)
             f[:, :, z, y, x] = 0.0
         rho_now = np.array([f[k].sum(axis=0) for k in range(2)])
         for z, y, x in zip(*np.nonzero(uncovered)):
@@ -458,8 +464,10 @@ class CoupledRun:
                 f[k, :, z, y, x] = lbm.equilibrium(np.array([rbar[k]]), ub[:, None])[:, 0]
                 self.solid[k] -= rbar[k]
                 mom += rbar[k] * ub
-            rods.V[r] -= mom / rods.p.mass
-            rods.L[r] -= np.cross(min_image(pos - rods.X[r], rods.box, rods.periodic), mom)
+            dV[r] -= mom
+            dL[r] -= np.cross(min_image(pos - rods.X[r], rods.box, rods.periodic), mom)
+        rods.V = rods.V + dV / rods.p.mass
+        rods.L = rods.L + dL
         self.rid = new_rid
         self.material = np.where(new_rid >= 0, lbm.ROD, self.static).astype(np.uint8)
         self.f = f
