@@ -76,6 +76,20 @@ typedef struct {
     int32_t evap_on;              /* 1: plane z = nz-1 is the fixed-density reservoir */
     double rho_top[2];            /* reservoir densities */
     double rho_ref[2];            /* storage reference: arrays hold f_i - w_i*rho_ref[k] (0: f_i) */
+    /* rigid rods (capsules): count, shape and interactions */
+    int32_t n_rods;               /* rods given to lb_init (0: none) */
+    int32_t n_sub;                /* rigid-body substeps per lattice step (5) */
+    double rod_length;            /* tip-to-tip length L */
+    double rod_radius;            /* capsule radius R */
+    double rod_rho;               /* rod density (mass = rho pi R^2 L) */
+    double eps_att;               /* rod-rod cohesion well depth (Eq. 12 form) */
+    double eps_rep;               /* rod-rod excluded-volume strength (Eq. 10 form) */
+    double rod_d0;                /* contact distance of the segment-segment potentials */
+    double rod_rcut;              /* cohesion cutoff (energy shifted to 0 there) */
+    double eps_wall;              /* rod-wall excluded volume strength */
+    double rod_d0_wall;           /* rod-wall contact distance */
+    int32_t wall_on;              /* 1: wall plane at z = wall_z repels rods */
+    double wall_z;
     /* tiling of the fused step (0 = library default); see lb_autotune */
     int32_t tile_y;               /* 4, 8 or 16 rows per tile */
     int32_t rows_per_thread;      /* 1 or 2 */
@@ -97,7 +111,10 @@ typedef struct {
     double max_speed;      /* max |sum_k j_k / sum_k rho_k| */
     double kinetic;        /* sum of |j|^2 / (2 rho) */
     int64_t fluid_nodes;
-    uint32_t status;       /* device status bits (1 NaN, 2 rho <= 0, 4 |u| > 0.3) */
+    uint32_t status;       /* device status bits (1 NaN, 2 rho <= 0, 4 |u| > 0.3,
+                              8 rod moved >= 1 node in a step or hit a wall) */
+    double solid[2];       /* mass of component k moved from the fluid into rods */
+    double rod_momentum[3];/* sum over rods of M V */
 } lb_obs;
 
 typedef struct lb_ctx lb_ctx;
@@ -114,11 +131,25 @@ size_t lb_workspace_bytes(const lb_params *p);
  *   rho_init_host : host, FP64 [2][nz][ny][nx] initial densities (values on
  *                   non-fluid nodes are ignored).
  *   material_host : host, uint8 [nz][ny][nx] material codes (copied).
+ *   rods_host     : host, FP64 [n_rods][13] = centre X (x, y, z), unit
+ *                   quaternion q (w, x, y, z) of the rotation taking e_z to the
+ *                   axis, velocity V, angular momentum L; nullable when
+ *                   n_rods = 0.  Rod nodes are cut out of the fluid.
  * Validates the parameters and the boundary layout (LB_EINVAL), uses
  * buffers.f[1] as upload staging, and synchronises the stream.
  */
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host,
-            const uint8_t *material_host, hipStream_t stream, lb_ctx **out);
+            const uint8_t *material_host, const double *rods_host, hipStream_t stream, lb_ctx **out);
+
+/* One rod update after lb_step(1): reaction of the adhesion force, n_sub
+ * rigid-body substeps with the momentum exchanged at the links, rod-rod and
+ * rod-wall forces, re-mask with cover/uncover, and the moving bounce-back of
+ * the next step.  A no-op without rods.  Asynchronous. */
+int lb_rods_step(lb_ctx *ctx, hipStream_t stream);
+
+/* Copy the rod states to out_host [n_rods][13] (layout as in lb_init).
+ * Synchronises. */
+int lb_rods_get(lb_ctx *ctx, double *out_host, hipStream_t stream);
 
 /* Advance the fluid nsteps >= 0 time steps (pull stream, boundaries, moments,
  * pseudopotential force, velocity shift, BGK collision, store; reservoir

@@ -30,6 +30,8 @@ EXPORTS = (
     "lb_abi_sizes",
     "lb_set_tiles",
     "lb_autotune",
+    "lb_rods_step",
+    "lb_rods_get",
 )
 
 
@@ -47,6 +49,19 @@ class LbParams(ct.Structure):
         ("evap_on", ct.c_int32),
         ("rho_top", ct.c_double * 2),
         ("rho_ref", ct.c_double * 2),
+        ("n_rods", ct.c_int32),
+        ("n_sub", ct.c_int32),
+        ("rod_length", ct.c_double),
+        ("rod_radius", ct.c_double),
+        ("rod_rho", ct.c_double),
+        ("eps_att", ct.c_double),
+        ("eps_rep", ct.c_double),
+        ("rod_d0", ct.c_double),
+        ("rod_rcut", ct.c_double),
+        ("eps_wall", ct.c_double),
+        ("rod_d0_wall", ct.c_double),
+        ("wall_on", ct.c_int32),
+        ("wall_z", ct.c_double),
         ("tile_y", ct.c_int32),
         ("rows_per_thread", ct.c_int32),
         ("zchunk", ct.c_int32),
@@ -67,6 +82,8 @@ class LbObs(ct.Structure):
         ("kinetic", ct.c_double),
         ("fluid_nodes", ct.c_int64),
         ("status", ct.c_uint32),
+        ("solid", ct.c_double * 2),
+        ("rod_momentum", ct.c_double * 3),
     ]
 
 
@@ -111,7 +128,8 @@ def load(path: str = LIB_PATH):
     lib.lb_pop_bytes.restype = ct.c_size_t
     lib.lb_workspace_bytes.argtypes = [P(LbParams)]
     lib.lb_workspace_bytes.restype = ct.c_size_t
-    lib.lb_init.argtypes = [P(LbParams), P(LbBuffers), ct.c_void_p, ct.c_void_p, ct.c_void_p, P(ct.c_void_p)]
+    lib.lb_init.argtypes = [P(LbParams), P(LbBuffers), ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                            P(ct.c_void_p)]
     lib.lb_init.restype = ct.c_int
     lib.lb_step.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p]
     lib.lb_step.restype = ct.c_int
@@ -125,6 +143,10 @@ def load(path: str = LIB_PATH):
     lib.lb_destroy.restype = ct.c_int
     lib.lb_last_error.argtypes = []
     lib.lb_last_error.restype = ct.c_char_p
+    lib.lb_rods_step.argtypes = [ct.c_void_p, ct.c_void_p]
+    lib.lb_rods_step.restype = ct.c_int
+    lib.lb_rods_get.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_rods_get.restype = ct.c_int
     lib.lb_set_tiles.argtypes = [ct.c_void_p, P(LbTile), ct.c_void_p]
     lib.lb_set_tiles.restype = ct.c_int
     lib.lb_autotune.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p, P(LbTile)]

@@ -66,8 +66,11 @@ int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
 //   result   : 256 bytes
 //   psi      : 16 x 2 doubles, ghost pseudo-densities per material id
 //   carry    : 2 doubles, ledger folded out of the tile slots on tile changes
+//   rods     : n_rods x ROD_STRIDE doubles
+//   rodid    : N int16, rod id per node (-1 none); newid: N int16
+//   rodsum   : 8 doubles (solid ledger, rod momentum)
 struct WsLayout {
-    size_t mat, ledger, status, partials, result, psi, carry, total;
+    size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, total;
     int max_tiles;
 };
 
@@ -90,6 +93,15 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + 32 * sizeof(double));
     w.carry = o;
     o = align256(o + 2 * sizeof(double));
+    w.rods = o;
+    o = align256(o + size_t(std::max(p->n_rods, 0)) * ROD_STRIDE * sizeof(double));
+    const size_t idb = p->n_rods > 0 ? size_t(n) * sizeof(int16_t) : 0;
+    w.rodid = o;
+    o = align256(o + idb);
+    w.newid = o;
+    o = align256(o + idb);
+    w.rodsum = o;
+    o = align256(o + 8 * sizeof(double));
     w.total = o;
     return w;
 }
@@ -118,6 +130,15 @@ int validate(const lb_params *p) {
     if (!tile_ok(ty, rp1, true)) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
     if (!tau1 && rp1 != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
     if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
+    if (p->n_rods < 0 || p->n_rods > 4096) return fail(LB_EINVAL, "n_rods = %d outside [0, 4096]", p->n_rods);
+    if (p->n_rods > 0) {
+        if (!(p->rod_radius > 0.0) || !(p->rod_length >= 2.0 * p->rod_radius) || !(p->rod_rho > 0.0))
+            return fail(LB_EINVAL, "bad rod shape or density");
+        if (p->n_sub < 1) return fail(LB_EINVAL, "n_sub must be >= 1");
+        if (!(p->rod_d0 > 0.0) || (p->eps_att > 0.0 && !(p->rod_rcut > p->rod_d0)))
+            return fail(LB_EINVAL, "bad rod contact distance or cutoff");
+        if (p->wall_on && !(p->rod_d0_wall > 0.0)) return fail(LB_EINVAL, "bad rod-wall contact distance");
+    }
     return LB_OK;
 }
 
@@ -169,6 +190,9 @@ struct lb_ctx {
     double *result;
     double *psi;
     double *carry;
+    double *rods;
+    int16_t *rodid, *newid;
+    double *rodsum;
     double psi_host[32];
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
@@ -178,6 +202,8 @@ struct lb_ctx {
     int64_t fs;
     double rref[2];  // storage reference density of the precision form
 };
+
+static RodArgs rod_args(lb_ctx *c);
 
 // tile bookkeeping of a context (no device work)
 static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk) {
@@ -198,6 +224,45 @@ static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk) 
     c->zchunk = std::max(1, std::min(zc, p->nz));
     c->nzc = (p->nz + c->zchunk - 1) / c->zchunk;
     c->tile.zchunk = c->zchunk;
+}
+
+static RodArgs rod_args(lb_ctx *c) {
+    const lb_params &p = c->p;
+    RodArgs a{};
+    a.rods = c->rods;
+    a.rodid = c->rodid;
+    a.newid = c->newid;
+    a.mat = c->mat;
+    a.status = c->status;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.px = p.periodic[0];
+    a.py = p.periodic[1];
+    a.pz = p.periodic[2];
+    a.fs = c->fs;
+    a.n_rods = p.n_rods;
+    a.n_sub = p.n_sub;
+    a.radius = p.rod_radius;
+    a.half = 0.5 * (p.rod_length - 2.0 * p.rod_radius);
+    // solid cylinder of length L and radius R
+    a.mass = p.rod_rho * M_PI * p.rod_radius * p.rod_radius * p.rod_length;
+    a.Ipar = 0.5 * a.mass * p.rod_radius * p.rod_radius;
+    a.Iperp = a.mass * (3.0 * p.rod_radius * p.rod_radius + p.rod_length * p.rod_length) / 12.0;
+    a.eps_att = p.eps_att;
+    a.eps_rep = p.eps_rep;
+    a.d0 = p.rod_d0;
+    a.r_cut = p.rod_rcut;
+    a.eps_wall = p.eps_wall;
+    a.d0_wall = p.rod_d0_wall;
+    a.wall_z = p.wall_z;
+    a.wall_on = p.wall_on;
+    a.G = p.G;
+    a.psi_rod[0] = p.psi_solid[MAT_ROD][0];
+    a.psi_rod[1] = p.psi_solid[MAT_ROD][1];
+    a.rho_ref[0] = c->rref[0];
+    a.rho_ref[1] = c->rref[1];
+    return a;
 }
 
 extern "C" {
@@ -229,7 +294,7 @@ void lb_abi_sizes(size_t out[3]) {
 }
 
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
-            hipStream_t stream, lb_ctx **out) {
+            const double *rods_host, hipStream_t stream, lb_ctx **out) {
     if (!out) return fail(LB_EINVAL, "null out");
     *out = nullptr;
     int rc = validate(p);
@@ -239,6 +304,20 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     if ((reinterpret_cast<uintptr_t>(buf->workspace) & 255) != 0) return fail(LB_EINVAL, "workspace not 256-byte aligned");
     rc = validate_material(p, material_host);
     if (rc) return rc;
+    if (p->n_rods > 0 && !rods_host) return fail(LB_EINVAL, "n_rods > 0 needs the rod states");
+    std::vector<double> rod_stage(size_t(std::max(p->n_rods, 0)) * ROD_STRIDE, 0.0);
+    for (int r = 0; r < p->n_rods; ++r) {
+        const double *in = rods_host + 13 * r;
+        double qn = 0.0;
+        for (int q = 0; q < 4; ++q) qn += in[3 + q] * in[3 + q];
+        if (!(qn > 0.5 && qn < 2.0)) return fail(LB_EINVAL, "rod %d: quaternion not normalised", r);
+        qn = sqrt(qn);
+        double *o = rod_stage.data() + size_t(r) * ROD_STRIDE;
+        for (int q = 0; q < 3; ++q) o[ROD_X + q] = in[q];
+        for (int q = 0; q < 4; ++q) o[ROD_Q + q] = in[3 + q] / qn;
+        for (int q = 0; q < 3; ++q) o[ROD_V + q] = in[7 + q];
+        for (int q = 0; q < 3; ++q) o[ROD_L + q] = in[10 + q];
+    }
 
     lb_ctx *c = new (std::nothrow) lb_ctx();
     if (!c) return fail(LB_EINVAL, "out of host memory");
@@ -255,6 +334,10 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->result = reinterpret_cast<double *>(ws + w.result);
     c->psi = reinterpret_cast<double *>(ws + w.psi);
     c->carry = reinterpret_cast<double *>(ws + w.carry);
+    c->rods = reinterpret_cast<double *>(ws + w.rods);
+    c->rodid = reinterpret_cast<int16_t *>(ws + w.rodid);
+    c->newid = reinterpret_cast<int16_t *>(ws + w.newid);
+    c->rodsum = reinterpret_cast<double *>(ws + w.rodsum);
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
             c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
@@ -290,10 +373,25 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
         return cleanup(hip_fail(e, "init populations"));
     if ((e = launch_slot_fill(p->prec, c->f[0], c->fs, c->mat, p->nx, p->ny, p->nz, per, stream)) != hipSuccess)
         return cleanup(hip_fail(e, "slot fill"));
+    if (p->n_rods > 0) {
+        if ((e = hipMemcpyAsync(c->rods, rod_stage.data(), rod_stage.size() * sizeof(double), hipMemcpyHostToDevice,
+                                stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "upload rods"));
+        if ((e = hipMemsetAsync(c->rodid, 0xFF, size_t(n) * sizeof(int16_t), stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "clear rod ids"));
+        if ((e = launch_rods_place(p->prec, rod_args(c), c->f[0], stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "place rods"));
+    }
     // the second buffer needs the same wall slots only after the first step
     // writes them; clear it so that stale staging bytes never look like state
     if ((e = hipMemsetAsync(c->f[1], 0, lb_pop_bytes(p), stream)) != hipSuccess) return cleanup(hip_fail(e, "clear f[1]"));
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
+    if (p->n_rods > 0) {
+        unsigned st = 0;
+        if ((e = hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost)) != hipSuccess)
+            return cleanup(hip_fail(e, "read status"));
+        if (st & ST_ROD) return cleanup(fail(LB_EINVAL, "a rod overlaps a wall, the reservoir or a closed end plane"));
+    }
     *out = c;
     return LB_OK;
 }
@@ -346,7 +444,12 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
                                c->carry, c->partials, OBS_BLOCKS, c->result, stream),
             "observables");
     double r[OBS_FIELDS];
+    double rs[5] = {0, 0, 0, 0, 0};
     unsigned st = 0;
+    if (p.n_rods > 0) {
+        HIP_TRY(launch_rods_sums(rod_args(c), c->rodsum, stream), "rod sums");
+        HIP_TRY(hipMemcpyAsync(rs, c->rodsum, sizeof rs, hipMemcpyDeviceToHost, stream), "copy rod sums");
+    }
     HIP_TRY(hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, stream), "copy observables");
     HIP_TRY(hipMemcpyAsync(&st, c->status, sizeof st, hipMemcpyDeviceToHost, stream), "copy status");
     HIP_TRY(hipStreamSynchronize(stream), "observables sync");
@@ -363,7 +466,10 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     out->kinetic = r[8];
     out->fluid_nodes = int64_t(r[9]);
     out->status = st;
-    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3)", st);
+    out->solid[0] = rs[0];
+    out->solid[1] = rs[1];
+    for (int q = 0; q < 3; ++q) out->rod_momentum[q] = rs[2 + q];
+    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3, 8 rod)", st);
     return LB_OK;
 }
 
@@ -372,6 +478,24 @@ int lb_export(lb_ctx *c, double *rho_dev, double *f_dev, hipStream_t stream) {
     const lb_params &p = c->p;
     HIP_TRY(launch_export(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, rho_dev, f_dev, stream), "export");
     HIP_TRY(hipStreamSynchronize(stream), "export sync");
+    return LB_OK;
+}
+
+int lb_rods_step(lb_ctx *c, hipStream_t stream) {
+    if (!c) return fail(LB_EINVAL, "null ctx");
+    if (c->p.n_rods == 0) return LB_OK;
+    HIP_TRY(launch_rods_step(c->p.prec, rod_args(c), c->f[c->cur], stream), "rods step");
+    return LB_OK;
+}
+
+int lb_rods_get(lb_ctx *c, double *out_host, hipStream_t stream) {
+    if (!c || (!out_host && c->p.n_rods > 0)) return fail(LB_EINVAL, "null argument");
+    if (c->p.n_rods == 0) return LB_OK;
+    std::vector<double> tmp(size_t(c->p.n_rods) * ROD_STRIDE);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), c->rods, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, stream), "copy rods");
+    HIP_TRY(hipStreamSynchronize(stream), "rods sync");
+    for (int r = 0; r < c->p.n_rods; ++r)
+        for (int q = 0; q < 13; ++q) out_host[13 * r + q] = tmp[size_t(r) * ROD_STRIDE + q];
     return LB_OK;
 }
 

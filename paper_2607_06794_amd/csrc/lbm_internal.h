@@ -36,6 +36,35 @@ struct TileCfg {
     int zchunk = 0;
 };
 
+// Rod record: ROD_STRIDE doubles per rod in the workspace
+constexpr int ROD_STRIDE = 48;
+constexpr int ROD_X = 0, ROD_Q = 3, ROD_V = 7, ROD_L = 10;  // centre, quaternion (w,x,y,z), velocity, ang. momentum
+constexpr int ROD_FS = 13, ROD_TS = 16;                      // momentum exchanged by the streamed links
+constexpr int ROD_FA = 19, ROD_TA = 22;                      // adhesion reaction
+constexpr int ROD_FC = 25, ROD_TC = 28;                      // contact force of the current substep
+constexpr int ROD_XOLD = 31, ROD_QOLD = 34;                  // pose before the last move
+constexpr int ROD_SOLID = 38;                                // mass exchanged with the fluid [2]
+constexpr int ROD_PEND = 40;                                 // moving bounce-back mass of the filled slots [2]
+
+struct RodArgs {
+    double *rods;
+    int16_t *rodid;  // rod id per node before the move (-1: none)
+    int16_t *newid;  // rod id per node after the move
+    uint8_t *mat;
+    unsigned *status;
+    int nx, ny, nz, px, py, pz;
+    int64_t fs;
+    int n_rods, n_sub;
+    double half, radius, mass, Ipar, Iperp;
+    double eps_att, eps_rep, d0, r_cut, eps_wall, d0_wall, wall_z;
+    int wall_on;
+    double G, psi_rod[2], rho_ref[2];
+};
+
+hipError_t launch_rods_place(int prec, const RodArgs &a, void *f, hipStream_t s);
+hipError_t launch_rods_step(int prec, const RodArgs &a, void *f, hipStream_t s);
+hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s);
+
 hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s);
 int tiles_xy(int nx, int ny, int tile_y);
 

@@ -105,3 +105,105 @@ def channel(shape, rho=1.0):
     r[0] = rho
     r[:, mat != FLUID] = 0.0
     return r, mat
+
+
+# ---------------------------------------------------------------------------
+# rods: random sequential placement of capsules
+# ---------------------------------------------------------------------------
+
+
+def _quat_from_axis(e):
+    """Unit quaternion (w, x, y, z) of the shortest rotation taking e_z to e."""
+    e = np.asarray(e, dtype=np.float64)
+    e = e / np.linalg.norm(e)
+    if e[2] < -1.0 + 1e-12:
+        return np.array([0.0, 1.0, 0.0, 0.0])
+    q = np.array([1.0 + e[2], -e[1], e[0], 0.0])
+    return q / np.linalg.norm(q)
+
+
+def _seg_dists(p1, q1, P2, Q2, samples=41):
+    """Distances from segment [p1, q1] to segments [P2[m], Q2[m]]: dense
+    sampling of the first, exact projection onto each of the others."""
+    s = np.linspace(0.0, 1.0, samples)[:, None, None]
+    pts = p1[None, None, :] + s * (q1 - p1)[None, None, :]  # (S, 1, 3)
+    d2 = (Q2 - P2)[None]  # (1, M, 3)
+    L2 = np.maximum((d2 * d2).sum(-1), 1e-300)
+    t = np.clip(((pts - P2[None]) * d2).sum(-1) / L2, 0.0, 1.0)
+    c = P2[None] + t[..., None] * d2
+    return np.sqrt(((pts - c) ** 2).sum(-1)).min(axis=0)
+
+
+def place_rods(n_req, length, radius, box, inside=None, seed=3000, gap=1.0, margin=3.0, zmin=None,
+               max_trials=200000):
+    """Random sequential placement of capsule rods.
+
+    box: (nx, ny, nz).  Each trial draws a centre uniform in the box (3
+    uniforms) and an axis from a normalised Gaussian triplet (3 normals), in
+    that order, from PCG64(seed).  A trial is accepted when
+      * ``inside`` is None (stress placement), or every point within
+        ``radius + margin`` of the axis (sampled) satisfies ``inside(x, y, z)``
+        (physical placement: fully immersed);
+      * the lowest axis point is at least ``zmin`` (default radius + 2.5 above
+        the wall plane z = 1/2);
+      * the axis segment is at least 2 radius + gap from every placed rod.
+    Stops after n_req rods or max_trials trials.  Returns an [n][13] array:
+    centre, quaternion (w, x, y, z), zero velocity, zero angular momentum.
+    """
+    rng = _rng(seed)
+    nx, ny, nz = box
+    half = 0.5 * (length - 2.0 * radius)
+    zmin = 0.5 + radius + 2.5 if zmin is None else zmin
+    placed = []
+    ends = []
+    ring = [np.array([np.cos(a), np.sin(a)]) for a in np.linspace(0, 2 * np.pi, 8, endpoint=False)]
+    for _ in range(max_trials):
+        if len(placed) >= n_req:
+            break
+        c = rng.uniform(0.0, 1.0, 3) * np.array([nx, ny, nz], dtype=np.float64)
+        e = rng.normal(size=3)
+        e /= np.linalg.norm(e)
+        a, b = c - half * e, c + half * e
+        if min(a[2], b[2]) < zmin or max(a[2], b[2]) > nz - 1.5 - radius - 2.5:
+            continue
+        if inside is not None:
+            u = np.cross(e, [1.0, 0, 0] if abs(e[0]) < 0.9 else [0, 1.0, 0])
+            u /= np.linalg.norm(u)
+            v = np.cross(e, u)
+            ok = True
+            for s in np.linspace(-half - radius - margin, half + radius + margin, 13):
+                base = c + np.clip(s, -half, half) * e
+                reach = radius + margin
+                pts = [base + s_e * e for s_e in (0.0,)] + [base + reach * (r[0] * u + r[1] * v) for r in ring]
+                if abs(s) > half:
+                    pts.append(c + np.sign(s) * (half + reach) * e)
+                if not all(inside(*p) for p in pts):
+                    ok = False
+                    break
+            if not ok:
+                continue
+        if ends:
+            PA = np.array([pa for pa, _ in ends])
+            PB = np.array([pb for _, pb in ends])
+            # minimum image in x and y (periodic); rods stay clear of the z ends
+            mid = 0.5 * (PA + PB)
+            shift = np.zeros_like(mid)
+            shift[:, 0] = nx * np.round((c[0] - mid[:, 0]) / nx)
+            shift[:, 1] = ny * np.round((c[1] - mid[:, 1]) / ny)
+            if np.any(_seg_dists(a, b, PA + shift, PB + shift) < 2.0 * radius + gap):
+                continue
+        placed.append(np.concatenate([c, _quat_from_axis(e), np.zeros(6)]))
+        ends.append((a, b))
+    return np.array(placed).reshape(-1, 13)
+
+
+def cap_inside(spec: CapSpec):
+    """Membership test of the sessile cap of ``sessile_cap`` (continuous coordinates)."""
+    nz, ny, nx = spec.shape
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    a, b = spec.footprint[0] / 2.0, spec.footprint[1] / 2.0
+
+    def inside(x, y, z):
+        return z >= 1.0 and ((x - cx) / a) ** 2 + ((y - cy) / b) ** 2 + ((z - 0.5) / spec.height) ** 2 <= 1.0
+
+    return inside

@@ -32,6 +32,18 @@ class LatticeParams:
     evaporation: bool = False
     rho_top: tuple = (0.0, 1.0)
     rho_ref: tuple = (0.0, 0.0)  # storage reference: 0 stores f_i, else f_i - w_i rho_ref
+    # rigid rods
+    n_sub: int = 5
+    rod_length: float = 24.0
+    rod_radius: float = 2.0
+    rod_rho: float = 1.0
+    eps_att: float = 1e-4
+    eps_rep: float = 0.03
+    rod_d0: float = 5.0
+    rod_rcut: float = 7.5
+    eps_wall: float = 0.03
+    rod_d0_wall: float = 3.0
+    wall_z: float | None = None  # wall plane repelling rods (None: no wall force)
     tile_y: int = 0
     rows_per_thread: int = 0
     zchunk: int = 0
@@ -53,6 +65,18 @@ class LatticeParams:
             for k in range(2):
                 p.psi_solid[m][k] = float(ps[m, k]) if m < ps.shape[0] else 0.0
         p.evap_on = int(bool(self.evaporation))
+        p.n_sub = int(self.n_sub)
+        p.rod_length = float(self.rod_length)
+        p.rod_radius = float(self.rod_radius)
+        p.rod_rho = float(self.rod_rho)
+        p.eps_att = float(self.eps_att)
+        p.eps_rep = float(self.eps_rep)
+        p.rod_d0 = float(self.rod_d0)
+        p.rod_rcut = float(self.rod_rcut)
+        p.eps_wall = float(self.eps_wall)
+        p.rod_d0_wall = float(self.rod_d0_wall)
+        p.wall_on = int(self.wall_z is not None)
+        p.wall_z = float(self.wall_z) if self.wall_z is not None else 0.0
         p.tile_y = int(self.tile_y)
         p.rows_per_thread = int(self.rows_per_thread)
         p.zchunk = int(self.zchunk)
@@ -69,7 +93,9 @@ def _stream_ptr(stream):
 class Lattice:
     """One lattice on one GPU: caller-owned buffers plus a liblbm context."""
 
-    def __init__(self, params: LatticeParams, rho0: np.ndarray, material: np.ndarray, device="cuda:0", stream=None):
+    def __init__(self, params: LatticeParams, rho0: np.ndarray, material: np.ndarray, device="cuda:0", stream=None,
+                 rods: np.ndarray | None = None):
+        """rods: optional FP64 [n][13] array (X, q (w,x,y,z), V, L) per rod."""
         import torch
 
         self.lib = _lib.load()
@@ -77,6 +103,8 @@ class Lattice:
         self.device = torch.device(device)
         self.stream = stream
         self._cp = params.to_c()
+        self.rods_in = None if rods is None else np.ascontiguousarray(rods, dtype=np.float64).reshape(-1, 13)
+        self._cp.n_rods = 0 if self.rods_in is None else self.rods_in.shape[0]
         nz, ny, nx = params.shape
         self.n = nx * ny * nz
         pop_bytes = self.lib.lb_pop_bytes(ct.byref(self._cp))
@@ -102,6 +130,7 @@ class Lattice:
                 ct.byref(self._buf),
                 rho0.ctypes.data_as(ct.c_void_p),
                 material.ctypes.data_as(ct.c_void_p),
+                self.rods_in.ctypes.data_as(ct.c_void_p) if self.rods_in is not None and len(self.rods_in) else None,
                 _stream_ptr(self.stream),
                 ct.byref(self._ctx),
             )
@@ -111,6 +140,26 @@ class Lattice:
     def step(self, n: int = 1):
         _lib.check(self.lib.lb_step(self._ctx, int(n), _stream_ptr(self.stream)))
         return self
+
+    @property
+    def n_rods(self) -> int:
+        return int(self._cp.n_rods)
+
+    def rods_step(self):
+        _lib.check(self.lib.lb_rods_step(self._ctx, _stream_ptr(self.stream)))
+        return self
+
+    def coupled_step(self, n: int = 1):
+        """n coupled steps: one fluid step then one rod update each."""
+        for _ in range(int(n)):
+            self.step(1)
+            self.rods_step()
+        return self
+
+    def rods(self) -> np.ndarray:
+        out = np.zeros((self.n_rods, 13))
+        _lib.check(self.lib.lb_rods_get(self._ctx, out.ctypes.data_as(ct.c_void_p), _stream_ptr(self.stream)))
+        return out
 
     def observables(self, allow_unstable=False) -> dict:
         o = _lib.LbObs()
@@ -125,6 +174,8 @@ class Lattice:
             "kinetic": o.kinetic,
             "fluid_nodes": o.fluid_nodes,
             "status": o.status,
+            "solid": np.array(o.solid[:]),
+            "rod_momentum": np.array(o.rod_momentum[:]),
         }
 
     def export(self, populations: bool = True):

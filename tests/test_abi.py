@@ -71,7 +71,8 @@ def _init_rc(lib, params, rho=None, mat=None):
     buf.f[1] = 512
     buf.workspace = 1024
     ctx = ct.c_void_p()
-    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None, ct.byref(ctx))
+    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
+                     None, ct.byref(ctx))
     return rc, lib.lb_last_error().decode()
 
 
@@ -87,7 +88,8 @@ def test_validation_rejects_bad_input_before_any_device_call(lib):
     ctx = ct.c_void_p()
     rho = np.ones((2, 8, 8, 8))
     mat = np.zeros((8, 8, 8), np.uint8)
-    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None, ct.byref(ctx))
+    rc = lib.lb_init(ct.byref(cp), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
+                     None, ct.byref(ctx))
     assert rc == _lib.LB_ENOTSUP
     # fluid on a closed end plane
     rc, msg = _init_rc(lib, LatticeParams(shape=(8, 8, 8), periodic=(True, True, False)))
@@ -111,7 +113,18 @@ def test_validation_rejects_bad_input_before_any_device_call(lib):
     assert rc == _lib.LB_EINVAL
     # null out pointer
     cp = LatticeParams(shape=(8, 8, 8)).to_c()
-    assert lib.lb_init(ct.byref(cp), None, None, None, None, None) == _lib.LB_EINVAL
+    assert lib.lb_init(ct.byref(cp), None, None, None, None, None, None) == _lib.LB_EINVAL
+    # rods requested without rod states; bad rod shape
+    p = LatticeParams(shape=(8, 8, 8)).to_c()
+    p.n_rods = 2
+    rc = lib.lb_init(ct.byref(p), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
+                     None, ct.byref(ctx))
+    assert rc == _lib.LB_EINVAL
+    p.rod_radius = -1.0
+    rc = lib.lb_init(ct.byref(p), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
+                     None, ct.byref(ctx))
+    assert rc == _lib.LB_EINVAL and "rod" in lib.lb_last_error().decode()
+    assert lib.lb_rods_step(None, None) == _lib.LB_EINVAL
     # step / observables / export on a null context
     assert lib.lb_step(None, 1, None) == _lib.LB_EINVAL
     assert lib.lb_observables(None, None, None) == _lib.LB_EINVAL
