@@ -63,6 +63,7 @@ enum {
 typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3 } lb_prec;
 
 #define LB_NMAT 9
+#define LB_MAX_RODS 512 /* rods per lattice */
 
 /* All parameters of one lattice (plain data; mirrored by a Python dataclass). */
 typedef struct {
@@ -77,7 +78,7 @@ typedef struct {
     double rho_top[2];            /* reservoir densities */
     double rho_ref[2];            /* storage reference: arrays hold f_i - w_i*rho_ref[k] (0: f_i) */
     /* rigid rods (capsules): count, shape and interactions */
-    int32_t n_rods;               /* rods given to lb_init (0: none) */
+    int32_t n_rods;               /* rods given to lb_init (0: none, at most LB_MAX_RODS) */
     int32_t n_sub;                /* rigid-body substeps per lattice step (5) */
     double rod_length;            /* tip-to-tip length L */
     double rod_radius;            /* capsule radius R */

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "liblbm.so")
 LB_OK, LB_EINVAL, LB_ENOTSUP, LB_EHIP, LB_EUNSTABLE, LB_EPLACE = 0, -1, -2, -3, -4, 1
 LB_F64, LB_F32, LB_F16DEV, LB_BF16DEV = 0, 1, 2, 3
 LB_NMAT = 9
+LB_MAX_RODS = 512
 
 # Every exported symbol declared in include/lbm.h
 EXPORTS = (

@@ -69,8 +69,26 @@ int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
 //   rods     : n_rods x ROD_STRIDE doubles
 //   rodid    : N int16, rod id per node (-1 none); newid: N int16
 //   rodsum   : 8 doubles (solid ledger, rod momentum)
+//   rodpart  : 3 x n_rods x rod_nblk x ROD_PART doubles, per-block partial sums
+//   shell    : n_rods x rod_shell_cap int32 surface lists; shell_cnt: n_rods int32
+//   nbr      : n_rods x ROD_NBR int16 neighbour lists; nbr_cnt: n_rods int32
+//
+// Capacity of a rod's surface list (nodes within R + 3/2 of the axis): the
+// unit cells centred on those nodes are disjoint and lie within
+// R + 3/2 + sqrt(3)/2 of the axis segment, so their number is at most that
+// capsule's volume.  Rounded up to whole 256-thread work-groups.
+static int rod_shell_cap(const lb_params &p) {
+    const double pi = 3.14159265358979323846;
+    const double half = 0.5 * p.rod_length - p.rod_radius;
+    const double rr = p.rod_radius + 1.5 + 0.5 * std::sqrt(3.0);
+    const double vol = pi * rr * rr * 2.0 * half + 4.0 / 3.0 * pi * rr * rr * rr;
+    return int((std::ceil(vol) + 255.0) / 256.0) * 256;
+}
+static int rod_nblk(const lb_params &p) { return rod_shell_cap(p) / 256; }
+
 struct WsLayout {
-    size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, total;
+    size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
+        nbr, nbr_cnt, total;
     int max_tiles;
 };
 
@@ -102,6 +120,18 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + idb);
     w.rodsum = o;
     o = align256(o + 8 * sizeof(double));
+    w.rodpart = o;
+    const size_t nr = size_t(std::max(p->n_rods, 0));
+    const bool rods = nr > 0;
+    o = align256(o + (rods ? 3 * nr * rod_nblk(*p) * ROD_PART * sizeof(double) : 0));
+    w.shell = o;
+    o = align256(o + (rods ? nr * rod_shell_cap(*p) * sizeof(int) : 0));
+    w.shell_cnt = o;
+    o = align256(o + nr * sizeof(int));
+    w.nbr = o;
+    o = align256(o + nr * ROD_NBR * sizeof(int16_t));
+    w.nbr_cnt = o;
+    o = align256(o + nr * sizeof(int));
     w.total = o;
     return w;
 }
@@ -130,7 +160,9 @@ int validate(const lb_params *p) {
     if (!tile_ok(ty, rp1, true)) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
     if (!tau1 && rp1 != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
     if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
-    if (p->n_rods < 0 || p->n_rods > 4096) return fail(LB_EINVAL, "n_rods = %d outside [0, 4096]", p->n_rods);
+    // the integrator keeps 13 doubles per rod in one work-group's shared memory
+    if (p->n_rods < 0 || p->n_rods > LB_MAX_RODS)
+        return fail(LB_EINVAL, "n_rods = %d outside [0, %d]", p->n_rods, LB_MAX_RODS);
     if (p->n_rods > 0) {
         if (!(p->rod_radius > 0.0) || !(p->rod_length >= 2.0 * p->rod_radius) || !(p->rod_rho > 0.0))
             return fail(LB_EINVAL, "bad rod shape or density");
@@ -193,6 +225,9 @@ struct lb_ctx {
     double *rods;
     int16_t *rodid, *newid;
     double *rodsum;
+    double *rodpart;
+    int *shell, *shell_cnt, *nbr_cnt;
+    int16_t *nbr;
     double psi_host[32];
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
@@ -230,6 +265,16 @@ static RodArgs rod_args(lb_ctx *c) {
     const lb_params &p = c->p;
     RodArgs a{};
     a.rods = c->rods;
+    a.shell_cap = p.n_rods > 0 ? rod_shell_cap(p) : 0;
+    a.nblk = p.n_rods > 0 ? rod_nblk(p) : 0;
+    a.shell = c->shell;
+    a.shell_cnt = c->shell_cnt;
+    a.nbr = c->nbr;
+    a.nbr_cnt = c->nbr_cnt;
+    const size_t np = size_t(std::max(p.n_rods, 0)) * a.nblk * ROD_PART;
+    a.part_adh = c->rodpart;
+    a.part_upd = c->rodpart + np;
+    a.part_link = c->rodpart + 2 * np;
     a.rodid = c->rodid;
     a.newid = c->newid;
     a.mat = c->mat;
@@ -338,6 +383,11 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->rodid = reinterpret_cast<int16_t *>(ws + w.rodid);
     c->newid = reinterpret_cast<int16_t *>(ws + w.newid);
     c->rodsum = reinterpret_cast<double *>(ws + w.rodsum);
+    c->rodpart = reinterpret_cast<double *>(ws + w.rodpart);
+    c->shell = reinterpret_cast<int *>(ws + w.shell);
+    c->shell_cnt = reinterpret_cast<int *>(ws + w.shell_cnt);
+    c->nbr = reinterpret_cast<int16_t *>(ws + w.nbr);
+    c->nbr_cnt = reinterpret_cast<int *>(ws + w.nbr_cnt);
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
             c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
@@ -379,6 +429,9 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
             return cleanup(hip_fail(e, "upload rods"));
         if ((e = hipMemsetAsync(c->rodid, 0xFF, size_t(n) * sizeof(int16_t), stream)) != hipSuccess)
             return cleanup(hip_fail(e, "clear rod ids"));
+        if ((e = hipMemsetAsync(c->rodpart, 0, 3 * size_t(p->n_rods) * rod_nblk(*p) * ROD_PART * sizeof(double), stream)) !=
+            hipSuccess)
+            return cleanup(hip_fail(e, "clear rod partials"));
         if ((e = launch_rods_place(p->prec, rod_args(c), c->f[0], stream)) != hipSuccess)
             return cleanup(hip_fail(e, "place rods"));
     }

@@ -44,10 +44,17 @@ constexpr int ROD_FA = 19, ROD_TA = 22;                      // adhesion reactio
 constexpr int ROD_FC = 25, ROD_TC = 28;                      // contact force of the current substep
 constexpr int ROD_XOLD = 31, ROD_QOLD = 34;                  // pose before the last move
 constexpr int ROD_SOLID = 38;                                // mass exchanged with the fluid [2]
-constexpr int ROD_PEND = 40;                                 // moving bounce-back mass of the filled slots [2]
+constexpr int ROD_PART = 8;                                  // doubles per (rod, block) partial-sum slot
+constexpr int ROD_NBR = 64;                                  // neighbour-list entries per rod
 
 struct RodArgs {
     double *rods;
+    double *part_adh, *part_upd, *part_link;  // [n_rods][nblk][ROD_PART] partial sums
+    int *shell;                               // [n_rods][shell_cap] surface-list node indices
+    int *shell_cnt;                           // [n_rods]
+    int shell_cap, nblk;                      // list capacity; work-groups per rod (shell_cap / 256)
+    int16_t *nbr;                             // [n_rods][ROD_NBR] neighbour lists
+    int *nbr_cnt;                             // [n_rods]
     int16_t *rodid;  // rod id per node before the move (-1: none)
     int16_t *newid;  // rod id per node after the move
     uint8_t *mat;

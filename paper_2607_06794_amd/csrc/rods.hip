@@ -12,10 +12,11 @@
 // closest points of the axis segments; a WCA wall keeps rods off the
 // substrate.  All rod arithmetic is FP64.
 //
-// Work decomposition: every per-rod pass runs one work-group per rod over the
-// rod's bounding box, and every per-rod sum is a fixed-order block reduction,
-// so results do not depend on scheduling.  The integrator is one work-group
-// with one thread per rod; each thread sums the pair forces on its own rod.
+// Work decomposition: the re-mask builds, per rod, the list of lattice nodes
+// near its surface; every per-node pass runs one thread per listed node, and
+// every sum is a fixed-order block or wavefront reduction, so results do not
+// depend on scheduling.  Pair forces use a per-step neighbour list; the
+// integrator is one work-group with one thread per rod.
 #include <type_traits>
 
 #include "lbm_device.h"
@@ -151,12 +152,13 @@ __device__ inline bool wrap_coord(int &v, int n, int per) {
     return v >= 0 && v < n;
 }
 
-__device__ inline bool inside_capsule(const double *rod, d3 p, const RodArgs &a) {
+// squared distance from lattice point p (unwrapped, near the rod) to the axis segment
+__device__ inline double axis_dist2(const double *rod, d3 p, const RodArgs &a) {
     const d3 d = min_image(p - ld3(rod + ROD_X), a);
     const d3 e = quat_axis(rod + ROD_Q);
     const double t = fmin(fmax(dot(d, e), -a.half), a.half);
     const d3 c = d - t * e;
-    return dot(c, c) <= a.radius * a.radius;
+    return dot(c, c);
 }
 
 __device__ inline double block_sum_d(double v, double *sh) {
@@ -177,6 +179,41 @@ constexpr int RB = 256;  // threads per per-rod work-group
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Per-rod surface lists.  The re-mask (one work-group per rod) scans the
+// rod's bounding box once and writes, in box order, every lattice node within
+// R + 3/2 of the axis: all of the rod's nodes before and after a move of less
+// than one node, and every fluid node that shares a link with them.  The
+// passes that follow run one thread per listed node, work-group (b, r) on
+// entries [b RB, (b + 1) RB) of rod r's list, and write their partial sums to
+// slot [r][b]; consumers add the slots with a fixed wavefront butterfly.
+// ---------------------------------------------------------------------------
+constexpr int MB = 1024;  // threads of the re-mask work-group
+
+__device__ inline double wave_sum_d(double v) {
+    // xor butterfly: every lane ends with the same, order-fixed sum
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double *part_slot(double *base, const RodArgs &a, int r, int b) {
+    return base + (size_t(r) * a.nblk + b) * ROD_PART;
+}
+
+__device__ inline double shell_r2(const RodArgs &a) { return (a.radius + 1.5) * (a.radius + 1.5); }
+
+// listed node of this thread: false if the entry is past the end of the list
+__device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, int &y, int &z) {
+    const int idx = blockIdx.x * RB + threadIdx.x;
+    if (idx >= a.shell_cnt[r]) return false;
+    n = a.shell[size_t(r) * a.shell_cap + idx];
+    x = int(n % a.nx);
+    y = int((n / a.nx) % a.ny);
+    z = int(n / (int64_t(a.nx) * a.ny));
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // 1. reaction to the adhesion force: for fluid x next to rod node y = x + c_i,
 //    F_rod += G psi_k(x) w_i psi^s_kbar c_i (psi_k(x) = rho_k(x), the collision
 //    invariant of the current post-collision state), torque about X at y
@@ -184,89 +221,165 @@ constexpr int RB = 256;  // threads per per-rod work-group
 template <class S>
 __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodArgs a, const S *f) {
     __shared__ double sh[RB / 64];
-    double *rod = a.rods + blockIdx.x * ROD_STRIDE;
-    const Box b = rod_box(rod, a, 1);
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = int64_t(ex) * ey * ez;
-    const int r = blockIdx.x;
+    const int r = blockIdx.y;
+    const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t m = threadIdx.x; m < nbox; m += RB) {
-        int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
-        const double px = x, py = y, pz = z;  // unwrapped position near the rod
-        if (!wrap_coord(x, a.nx, a.px) || !wrap_coord(y, a.ny, a.py) || !wrap_coord(z, a.nz, a.pz)) continue;
-        const int64_t n = (int64_t(z) * a.ny + y) * a.nx + x;
-        if ((a.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
-        bool any = false;
+    int64_t n;
+    int x, y, z;
+    if (shell_node(a, r, n, x, y, z) && (a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
+        unsigned links = 0;
+#pragma unroll
         for (int i = 1; i < Q; ++i) {
             int xx = x + cx(i), yy = y + cy(i), zz = z + cz(i);
             if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-            any |= a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx] == r;
+            if (a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx] == r) links |= 1u << i;
         }
-        if (!any) continue;
-        double rho[2];
-        for (int k = 0; k < 2; ++k) {
-            double s = 0.0;
-            for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
-            rho[k] = s;
-        }
-        for (int i = 1; i < Q; ++i) {
-            int xx = x + cx(i), yy = y + cy(i), zz = z + cz(i);
-            if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-            if (a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx] != r) continue;
-            const double g = a.G * wgt<double>(i) * (rho[0] * a.psi_rod[1] + rho[1] * a.psi_rod[0]);
-            const d3 fr = mk(g * cx(i), g * cy(i), g * cz(i));
-            const d3 arm = min_image(mk(px + cx(i), py + cy(i), pz + cz(i)) - X, a);
-            const d3 tq = cross(arm, fr);
-            acc[0] += fr.x;
-            acc[1] += fr.y;
-            acc[2] += fr.z;
-            acc[3] += tq.x;
-            acc[4] += tq.y;
-            acc[5] += tq.z;
+        if (links) {
+            double rho[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
+                rho[k] = s;
+            }
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                if (!(links & (1u << i))) continue;
+                const double g = a.G * wgt<double>(i) * (rho[0] * a.psi_rod[1] + rho[1] * a.psi_rod[0]);
+                const d3 fr = mk(g * cx(i), g * cy(i), g * cz(i));
+                const d3 arm = min_image(mk(x + cx(i), y + cy(i), z + cz(i)) - X, a);
+                const d3 tq = cross(arm, fr);
+                acc[0] += fr.x;
+                acc[1] += fr.y;
+                acc[2] += fr.z;
+                acc[3] += tq.x;
+                acc[4] += tq.y;
+                acc[5] += tq.z;
+            }
         }
     }
+    double *part = part_slot(a.part_adh, a, r, blockIdx.x);
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
         const double v = block_sum_d(acc[q], sh);
-        if (threadIdx.x == 0) rod[ROD_FA + q] = v;
-    }
-    if (threadIdx.x == 0) {
-        // the slots filled by the last link pass have now been streamed: book their mass
-        rod[ROD_SOLID] += rod[ROD_PEND];
-        rod[ROD_SOLID + 1] += rod[ROD_PEND + 1];
-        rod[ROD_PEND] = 0.0;
-        rod[ROD_PEND + 1] = 0.0;
+        if (threadIdx.x == 0) part[q] = v;
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2. rigid-body substeps (one work-group, one thread per rod)
+// 2a. per rod (one wavefront each): the fluid load of the step that just ran
+//     (momentum of the streamed links, adhesion reaction; the mass carried by
+//     the streamed moving bounce-back is booked now), and the list of rods
+//     that can come within interaction range during this step (each point of
+//     a rod moves less than 0.9 per step, so a pair farther apart than
+//     r_int + 2 at the start stays out of range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) rod_integrate_kernel(RodArgs a) {
-    const int nr = a.n_rods;
-    const double dt = 1.0 / a.n_sub;
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-        double *rod = a.rods + r * ROD_STRIDE;
-        for (int q = 0; q < 3; ++q) rod[ROD_XOLD + q] = rod[ROD_X + q];
-        for (int q = 0; q < 4; ++q) rod[ROD_QOLD + q] = rod[ROD_Q + q];
+__global__ void __launch_bounds__(64) rod_pairs_kernel(RodArgs a) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    double *rod = a.rods + r * ROD_STRIDE;
+    {
+        double ls[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ad[6] = {0, 0, 0, 0, 0, 0};
+        for (int b = lane; b < a.nblk; b += 64) {
+            const double *pl = part_slot(a.part_link, a, r, b);
+            const double *pa = part_slot(a.part_adh, a, r, b);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ls[q] += pl[q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) ad[q] += pa[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ls[q] = wave_sum_d(ls[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ad[q] = wave_sum_d(ad[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rod[ROD_XOLD + q] = rod[ROD_X + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rod[ROD_QOLD + q] = rod[ROD_Q + q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) rod[ROD_FS + q] = ls[q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) rod[ROD_FA + q] = ad[q];
+            rod[ROD_SOLID] += ls[6];
+            rod[ROD_SOLID + 1] += ls[7];
+        }
     }
-    for (int sub = 0; sub < a.n_sub; ++sub) {
-        __syncthreads();
-        // contact forces at the positions of this substep
-        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-            const double *ra = a.rods + r * ROD_STRIDE;
-            const d3 Xa = ld3(ra + ROD_X), ea = quat_axis(ra + ROD_Q);
-            const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
-            d3 F = mk(0, 0, 0), T = mk(0, 0, 0);
-            const double reach = 2.0 * a.half + fmax(a.d0, a.eps_att > 0.0 ? a.r_cut : a.d0);
-            for (int s = 0; s < nr; ++s) {
-                if (s == r) continue;
-                const double *rb = a.rods + s * ROD_STRIDE;
-                const d3 Xb = ld3(rb + ROD_X);
-                const d3 dx = min_image(Xb - Xa, a);
-                if (dot(dx, dx) >= reach * reach) continue;
+    const double r_int = fmax(a.d0, a.eps_att > 0.0 ? a.r_cut : a.d0);
+    const double keep = r_int + 2.0, reach = 2.0 * a.half + keep;
+    const d3 Xa = ld3(rod + ROD_X), ea = quat_axis(rod + ROD_Q);
+    const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
+    int base = 0;
+    for (int s0 = 0; s0 < a.n_rods; s0 += 64) {
+        const int s = s0 + lane;
+        bool near = false;
+        if (s < a.n_rods && s != r) {
+            const double *rb = a.rods + s * ROD_STRIDE;
+            const d3 Xb = ld3(rb + ROD_X);
+            const d3 dx = min_image(Xb - Xa, a);
+            if (dot(dx, dx) < reach * reach) {
                 const d3 shift = dx - (Xb - Xa);
                 const d3 eb = quat_axis(rb + ROD_Q);
+                d3 ca, cb;
+                near = seg_seg(pa, qa, Xb - a.half * eb + shift, Xb + a.half * eb + shift, ca, cb) < keep;
+            }
+        }
+        const uint64_t bal = __ballot(near);
+        const int slot = base + __popcll(bal & ((uint64_t(1) << lane) - 1));
+        if (near) {
+            if (slot < ROD_NBR) a.nbr[r * ROD_NBR + slot] = static_cast<int16_t>(s);
+            else atomicOr(a.status, ST_ROD);  // more neighbours than the list holds
+        }
+        base += __popcll(bal);
+    }
+    if (lane == 0) a.nbr_cnt[r] = min(base, ROD_NBR);
+}
+
+// ---------------------------------------------------------------------------
+// 2b. rigid-body substeps: one work-group of LB_MAX_RODS threads.  Centres
+//     and axes of all rods live in shared memory for the whole step; thread r
+//     keeps rod r's velocity, angular momentum and fluid load in registers,
+//     sums its pair forces over its neighbour list (in list order) and
+//     advances the rod.
+// ---------------------------------------------------------------------------
+constexpr int RS_X = 0, RS_Q = 3, RS_N = 7;  // shared-memory record per rod
+
+__global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodArgs a) {
+    extern __shared__ double rs[];  // [n_rods][RS_N]
+    const int nr = a.n_rods, me = threadIdx.x;
+    const bool mine = me < nr;
+    const double dt = 1.0 / a.n_sub;
+    d3 V = mk(0, 0, 0), Lm = mk(0, 0, 0), Fx = mk(0, 0, 0), Tx = mk(0, 0, 0), F = mk(0, 0, 0), T = mk(0, 0, 0);
+    int nn = 0;
+    double *rm = rs + (mine ? me : 0) * RS_N;
+    const double *rod = a.rods + (mine ? me : 0) * ROD_STRIDE;
+    if (mine) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) rm[RS_X + q] = rod[ROD_X + q];  // X then q
+        V = ld3(rod + ROD_V);
+        Lm = ld3(rod + ROD_L);
+        Fx = ld3(rod + ROD_FS) + ld3(rod + ROD_FA);
+        Tx = ld3(rod + ROD_TS) + ld3(rod + ROD_TA);
+        nn = a.nbr_cnt[me];
+    }
+    const d3 X0 = mine ? ld3(rod + ROD_XOLD) : mk(0, 0, 0);
+    const d3 e0 = mine ? quat_axis(rod + ROD_QOLD) : mk(0, 0, 1);
+    bool moved_far = false;
+    __syncthreads();
+    for (int sub = 0; sub < a.n_sub; ++sub) {
+        if (mine) {
+            // contact forces at the positions of this substep
+            const d3 Xa = ld3(rm + RS_X), ea = quat_axis(rm + RS_Q);
+            const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
+            F = mk(0, 0, 0);
+            T = mk(0, 0, 0);
+            for (int l = 0; l < nn; ++l) {
+                const double *rb = rs + a.nbr[me * ROD_NBR + l] * RS_N;
+                const d3 Xb = ld3(rb + RS_X);
+                const d3 dx = min_image(Xb - Xa, a);
+                const d3 shift = dx - (Xb - Xa);
+                const d3 eb = quat_axis(rb + RS_Q);
                 const d3 pb = Xb - a.half * eb + shift, qb = Xb + a.half * eb + shift;
                 d3 ca, cb;
                 const double d = seg_seg(pa, qa, pb, qb, ca, cb);
@@ -286,74 +399,103 @@ __global__ void __launch_bounds__(1024) rod_integrate_kernel(RodArgs a) {
                     T = T + cross(low - Xa, fw);
                 }
             }
-            double *rw = a.rods + r * ROD_STRIDE;
-            st3(rw + ROD_FC, F);
-            st3(rw + ROD_TC, T);
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-            double *rod = a.rods + r * ROD_STRIDE;
-            const d3 F = ld3(rod + ROD_FS) + ld3(rod + ROD_FA) + ld3(rod + ROD_FC);
-            const d3 T = ld3(rod + ROD_TS) + ld3(rod + ROD_TA) + ld3(rod + ROD_TC);
-            d3 V = ld3(rod + ROD_V) + (dt / a.mass) * F;
-            d3 X = ld3(rod + ROD_X) + dt * V;
-            const d3 L = ld3(rod + ROD_L) + dt * T;
-            st3(rod + ROD_V, V);
-            st3(rod + ROD_L, L);
-            const d3 w = omega_of(rod, a);  // uses the new L and the current q
+        if (mine) {
+            V = V + (dt / a.mass) * (Fx + F);
+            d3 X = ld3(rm + RS_X) + dt * V;
+            Lm = Lm + dt * (Tx + T);
+            // omega = I^-1 L with the current axis, then q <- exp(omega dt / 2) q
+            const d3 e = quat_axis(rm + RS_Q);
+            const d3 w = (1.0 / a.Iperp) * Lm + ((1.0 / a.Ipar - 1.0 / a.Iperp) * dot(Lm, e)) * e;
             const double wn = sqrt(dot(w, w));
             if (wn > 0.0) {
                 const double h = 0.5 * wn * dt;
                 const double sh = sin(h) / wn;
                 const double dq[4] = {cos(h), sh * w.x, sh * w.y, sh * w.z};
-                const double *q = rod + ROD_Q;
+                const double q[4] = {rm[RS_Q], rm[RS_Q + 1], rm[RS_Q + 2], rm[RS_Q + 3]};
                 double qn[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
                                 dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
                                 dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1],
                                 dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0]};
-                const double nn = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-                for (int c = 0; c < 4; ++c) rod[ROD_Q + c] = qn[c] / nn;
+                const double nq = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rm[RS_Q + c] = qn[c] / nq;
             }
             if (a.px) X.x = X.x - a.nx * floor(X.x / a.nx);
             if (a.py) X.y = X.y - a.ny * floor(X.y / a.ny);
             if (a.pz) X.z = X.z - a.nz * floor(X.z / a.nz);
-            st3(rod + ROD_X, X);
+            st3(rm + RS_X, X);
+            // every point of the rod stays within 0.9 of where it started the
+            // step (the re-mask and the neighbour list rely on it)
+            const d3 dX = min_image(X - X0, a);
+            const d3 de = quat_axis(rm + RS_Q) - e0;
+            moved_far |= !(sqrt(dot(dX, dX)) + (a.half + a.radius) * sqrt(dot(de, de)) < 0.9);
         }
+        __syncthreads();
     }
-    __syncthreads();
-    // a rod may move less than one node per step (the re-mask relies on it)
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-        double *rod = a.rods + r * ROD_STRIDE;
-        const d3 dX = min_image(ld3(rod + ROD_X) - ld3(rod + ROD_XOLD), a);
-        const d3 e0 = quat_axis(rod + ROD_QOLD), e1 = quat_axis(rod + ROD_Q);
-        const d3 de = e1 - e0;
-        const double tip = sqrt(dot(dX, dX)) + (a.half + a.radius) * sqrt(dot(de, de));
-        if (!(tip < 0.9)) atomicOr(a.status, ST_ROD);
+    if (mine) {
+        double *rw = a.rods + me * ROD_STRIDE;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) rw[ROD_X + q] = rm[RS_X + q];
+        st3(rw + ROD_V, V);
+        st3(rw + ROD_L, Lm);
+        st3(rw + ROD_FC, F);
+        st3(rw + ROD_TC, T);
+        if (moved_far) atomicOr(a.status, ST_ROD);
     }
 }
 
 // ---------------------------------------------------------------------------
-// 3. new occupancy of every rod (newid has been filled with -1)
+// 3. re-mask: new occupancy of every rod (newid is -1 everywhere on entry) and
+//    the rod's surface list; one work-group per rod
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(RB) rod_mask_kernel(RodArgs a) {
-    const double *rod = a.rods + blockIdx.x * ROD_STRIDE;
-    const Box b = rod_box(rod, a, 0);
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = int64_t(ex) * ey * ez;
-    for (int64_t m = threadIdx.x; m < nbox; m += RB) {
-        int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
-        if (!inside_capsule(rod, mk(x, y, z), a)) continue;
-        if (!wrap_coord(x, a.nx, a.px) || !wrap_coord(y, a.ny, a.py) || !wrap_coord(z, a.nz, a.pz)) {
-            atomicOr(a.status, ST_ROD);
-            continue;
+__global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
+    __shared__ int wcount[MB / 64];
+    const int r = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double *rod = a.rods + r * ROD_STRIDE;
+    const Box b = rod_box(rod, a, 2);
+    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1;
+    const int64_t nbox = int64_t(ex) * ey * (b.hi[2] - b.lo[2] + 1);
+    const double r2in = a.radius * a.radius, r2sh = shell_r2(a);
+    int base = 0;  // same in every thread
+    for (int64_t m0 = 0; m0 < nbox; m0 += MB) {
+        const int64_t m = m0 + threadIdx.x;
+        bool listed = false;
+        int64_t n = 0;
+        if (m < nbox) {
+            int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
+            const double d2 = axis_dist2(rod, mk(x, y, z), a);
+            const bool in_box = wrap_coord(x, a.nx, a.px) && wrap_coord(y, a.ny, a.py) && wrap_coord(z, a.nz, a.pz);
+            if (d2 <= r2in && !in_box) atomicOr(a.status, ST_ROD);  // a rod left the lattice
+            if (d2 <= r2sh && in_box) {
+                n = (int64_t(z) * a.ny + y) * a.nx + x;
+                listed = true;
+                if (d2 <= r2in) {
+                    const uint8_t mt = a.mat[n] & MAT_ID_MASK;
+                    if (mt == MAT_FLUID || mt == MAT_ROD) a.newid[n] = static_cast<int16_t>(r);
+                    else atomicOr(a.status, ST_ROD);  // a rod ran into a wall or the reservoir
+                }
+            }
         }
-        const int64_t n = (int64_t(z) * a.ny + y) * a.nx + x;
-        if ((a.mat[n] & MAT_ID_MASK) != MAT_FLUID && (a.mat[n] & MAT_ID_MASK) != MAT_ROD) {
-            atomicOr(a.status, ST_ROD);  // a rod ran into a wall or the reservoir
-            continue;
+        // append the listed nodes in box order
+        const uint64_t bal = __ballot(listed);
+        if (lane == 0) wcount[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int q = 0; q < MB / 64; ++q) {
+            off += q < wv ? wcount[q] : 0;
+            tot += wcount[q];
         }
-        a.newid[n] = static_cast<int16_t>(blockIdx.x);
+        if (listed) {
+            const int idx = base + off + __popcll(bal & ((uint64_t(1) << lane) - 1));
+            if (idx < a.shell_cap) a.shell[size_t(r) * a.shell_cap + idx] = static_cast<int>(n);
+            else atomicOr(a.status, ST_ROD);  // cannot happen for a capsule of the stated size
+        }
+        base += tot;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) a.shell_cnt[r] = min(base, a.shell_cap);
 }
 
 __global__ void fill_i16_kernel(int16_t *p, int64_t n, int16_t v) {
@@ -362,33 +504,37 @@ __global__ void fill_i16_kernel(int16_t *p, int64_t n, int16_t v) {
 
 // ---------------------------------------------------------------------------
 // 4. cover / uncover (init = 1: place the rods without bookkeeping)
+//    A covered node is handled by the thread that finds it.  Uncovered nodes
+//    are compacted in thread order into shared memory and refilled by a whole
+//    wavefront each (two lanes per neighbour gather the neighbour densities);
+//    the finding thread then adds the transfer to its own sums.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_update_kernel(RodArgs a, S *f, int init) {
     __shared__ double sh[RB / 64];
-    double *rod = a.rods + blockIdx.x * ROD_STRIDE;
-    const int r = blockIdx.x;
-    const Box b = rod_box(rod, a, 1);  // covers the old position too (moves < 1 node)
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = int64_t(ex) * ey * ez;
+    __shared__ int wcount[RB / 64];
+    __shared__ int64_t un_node[RB];
+    __shared__ double un_out[RB][8];
+    const int r = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // momentum[3], torque[3], mass[2]
-    for (int64_t m = threadIdx.x; m < nbox; m += RB) {
-        int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
-        const double px = x, py = y, pz = z;
-        if (!wrap_coord(x, a.nx, a.px) || !wrap_coord(y, a.ny, a.py) || !wrap_coord(z, a.nz, a.pz)) continue;
-        const int64_t n = (int64_t(z) * a.ny + y) * a.nx + x;
+    int64_t n = 0;
+    int x = 0, y = 0, z = 0;
+    bool unc = false;
+    if (shell_node(a, r, n, x, y, z)) {
         const int16_t oldid = a.rodid[n], newid = a.newid[n];
-        const bool cover = newid == r && oldid != r;
-        const bool uncover = oldid == r && newid != r;
-        if (!cover && !uncover) continue;
-        const d3 arm = min_image(mk(px, py, pz) - X, a);
-        if (cover) {
+        unc = oldid == r && newid != r;
+        if (newid == r && oldid != r) {  // covered
             if (!init) {
+                const d3 arm = min_image(mk(x, y, z) - X, a);
                 d3 mom = mk(0, 0, 0);
+#pragma unroll
                 for (int k = 0; k < 2; ++k) {
                     double s = 0.0;
                     d3 jk = mk(0, 0, 0);
+#pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         const double v = decf(f, (k * Q + i) * a.fs + n) + wgt<double>(i) * a.rho_ref[k];
                         s += v;
@@ -406,76 +552,112 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodArgs a, S *f, int ini
                 acc[5] += tq.z;
             }
             a.mat[n] = MAT_ROD;
-        } else {
-            // uncovered: f = f^eq(rho_bar, u_b), rho_bar = mean over neighbours
-            // that are fluid before and after the move
-            double rb[2] = {0.0, 0.0};
-            int cnt = 0;
-            bool near_wall = false;
-            for (int i = 1; i < Q; ++i) {
-                int xx = x + cx(i), yy = y + cy(i), zz = z + cz(i);
-                if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-                const int64_t q = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-                const uint8_t mq = a.mat[q] & MAT_ID_MASK;
-                near_wall |= is_static_wall(mq);
-                if (mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0) {
-                    for (int k = 0; k < 2; ++k) {
-                        double s = 0.0;
-                        for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * a.rho_ref[k];
-                        rb[k] += s;
-                    }
-                    ++cnt;
-                }
-            }
-            if (cnt) {
-                rb[0] /= cnt;
-                rb[1] /= cnt;
-            }
-            const d3 ub = velocity_at(rod, mk(px, py, pz), a);
-            const double usq = dot(ub, ub);
-            d3 mom = mk(0, 0, 0);
-            for (int k = 0; k < 2; ++k) {
-                for (int i = 0; i < Q; ++i) {
-                    const double cu = cx(i) * ub.x + cy(i) * ub.y + cz(i) * ub.z;
-                    const double feq = wgt<double>(i) * rb[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-                    f[(k * Q + i) * a.fs + n] = Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(i) * a.rho_ref[k]));
-                }
-                acc[6 + k] -= rb[k];
-                mom = mom + rb[k] * ub;
-            }
-            const d3 tq = cross(arm, mom);
-            acc[0] -= mom.x;
-            acc[1] -= mom.y;
-            acc[2] -= mom.z;
-            acc[3] -= tq.x;
-            acc[4] -= tq.y;
-            acc[5] -= tq.z;
-            a.mat[n] = MAT_FLUID | (near_wall ? MAT_NEAR_WALL : 0);
         }
     }
-    double tot[8];
-    for (int q = 0; q < 8; ++q) tot[q] = block_sum_d(acc[q], sh);
-    if (threadIdx.x == 0 && !init) {
-        for (int q = 0; q < 3; ++q) rod[ROD_V + q] += tot[q] / a.mass;
-        for (int q = 0; q < 3; ++q) rod[ROD_L + q] += tot[3 + q];
-        rod[ROD_SOLID] += tot[6];
-        rod[ROD_SOLID + 1] += tot[7];
+    // compact the uncovered nodes in thread order
+    const uint64_t bal = __ballot(unc);
+    if (lane == 0) wcount[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int q = 0; q < RB / 64; ++q) {
+        off += q < wv ? wcount[q] : 0;
+        tot += wcount[q];
+    }
+    const int slot = off + __popcll(bal & ((uint64_t(1) << lane) - 1));
+    if (unc) un_node[slot] = n;
+    __syncthreads();
+    // refill: f = f^eq(rho_bar, u_b), rho_bar = mean over the neighbours that
+    // are fluid before and after the move
+    for (int e = wv; e < tot; e += RB / 64) {
+        const int64_t un = un_node[e];
+        const int ux = int(un % a.nx), uy = int((un / a.nx) % a.ny), uz = int(un / (int64_t(a.nx) * a.ny));
+        const int i = 1 + (lane >> 1), k = lane & 1;
+        double val = 0.0;
+        bool ok = false, wall = false;
+        if (lane < 2 * (Q - 1)) {
+            int xx = ux + cx(i), yy = uy + cy(i), zz = uz + cz(i);
+            if (wrap_coord(xx, a.nx, a.px) && wrap_coord(yy, a.ny, a.py) && wrap_coord(zz, a.nz, a.pz)) {
+                const int64_t q = (int64_t(zz) * a.ny + yy) * a.nx + xx;
+                const uint8_t mq = a.mat[q] & MAT_ID_MASK;
+                wall = is_static_wall(mq);
+                ok = mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0;
+                if (ok) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * a.rho_ref[k];
+                    val = s;
+                }
+            }
+        }
+        const int cnt = __popcll(__ballot(ok && k == 0));
+        const bool near_wall = __ballot(wall) != 0;
+        double rb[2] = {wave_sum_d(k == 0 ? val : 0.0), wave_sum_d(k == 1 ? val : 0.0)};
+        if (cnt) {
+            rb[0] /= cnt;
+            rb[1] /= cnt;
+        }
+        const d3 pu = mk(ux, uy, uz);
+        const d3 ub = velocity_at(rod, pu, a);
+        const double usq = dot(ub, ub);
+        if (lane < 2 * Q) {
+            const int kk = lane / Q, ii = lane % Q;
+            const double cu = cx(ii) * ub.x + cy(ii) * ub.y + cz(ii) * ub.z;
+            const double feq = wgt<double>(ii) * rb[kk] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            f[(kk * Q + ii) * a.fs + un] = Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(ii) * a.rho_ref[kk]));
+        }
+        if (lane == 0) {
+            const d3 mom = (rb[0] + rb[1]) * ub;
+            const d3 tq = cross(min_image(pu - X, a), mom);
+            un_out[e][0] = -mom.x;
+            un_out[e][1] = -mom.y;
+            un_out[e][2] = -mom.z;
+            un_out[e][3] = -tq.x;
+            un_out[e][4] = -tq.y;
+            un_out[e][5] = -tq.z;
+            un_out[e][6] = -rb[0];
+            un_out[e][7] = -rb[1];
+            a.mat[un] = MAT_FLUID | (near_wall ? MAT_NEAR_WALL : 0);
+        }
+    }
+    __syncthreads();
+    if (unc) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += un_out[slot][q];
+    }
+    double *part = part_slot(a.part_upd, a, r, blockIdx.x);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double v = block_sum_d(acc[q], sh);
+        if (threadIdx.x == 0) part[q] = init ? 0.0 : v;
     }
 }
 
-// commit the new occupancy of rod r (after every block has read the old one)
+// commit the new occupancy of rod r (after every work-group has read the old
+// one); work-group (0, r) also applies rod r's cover/uncover transfers
 __global__ void __launch_bounds__(RB) rod_commit_kernel(RodArgs a) {
-    const double *rod = a.rods + blockIdx.x * ROD_STRIDE;
-    const int r = blockIdx.x;
-    const Box b = rod_box(rod, a, 1);
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = int64_t(ex) * ey * ez;
-    for (int64_t m = threadIdx.x; m < nbox; m += RB) {
-        int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
-        if (!wrap_coord(x, a.nx, a.px) || !wrap_coord(y, a.ny, a.py) || !wrap_coord(z, a.nz, a.pz)) continue;
-        const int64_t n = (int64_t(z) * a.ny + y) * a.nx + x;
-        if (a.rodid[n] == r || a.newid[n] == r) a.rodid[n] = a.newid[n];
+    const int r = blockIdx.y;
+    double *rod = a.rods + r * ROD_STRIDE;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = threadIdx.x; b < a.nblk; b += 64) {
+            const double *p = part_slot(a.part_upd, a, r, b);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] += p[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = wave_sum_d(t[q]);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rod[ROD_V + q] += t[q] / a.mass;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rod[ROD_L + q] += t[3 + q];
+            rod[ROD_SOLID] += t[6];
+            rod[ROD_SOLID + 1] += t[7];
+        }
     }
+    int64_t n;
+    int x, y, z;
+    if (shell_node(a, r, n, x, y, z) && (a.rodid[n] == r || a.newid[n] == r)) a.rodid[n] = a.newid[n];
 }
 
 // totals over rods in a fixed order: solid ledger [2], rod momentum M V [3]
@@ -492,71 +674,80 @@ __global__ void rod_sums_kernel(RodArgs a, double *out) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. moving bounce-back slots for the next pull, and the momentum they carry
+// 5. moving bounce-back slots for the next pull, and the momentum they carry;
+//    also returns rod r's entries of newid to -1 for the next re-mask
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_link_kernel(RodArgs a, S *f) {
     __shared__ double sh[RB / 64];
-    double *rod = a.rods + blockIdx.x * ROD_STRIDE;
-    const int r = blockIdx.x;
-    const Box b = rod_box(rod, a, 1);
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = int64_t(ex) * ey * ez;
+    const int r = blockIdx.y;
+    const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // dP[3], dT[3], mass[2]
-    for (int64_t m = threadIdx.x; m < nbox; m += RB) {
-        int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
-        const double px = x, py = y, pz = z;
-        if (!wrap_coord(x, a.nx, a.px) || !wrap_coord(y, a.ny, a.py) || !wrap_coord(z, a.nz, a.pz)) continue;
-        const int64_t n = (int64_t(z) * a.ny + y) * a.nx + x;
-        if ((a.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
-        bool any = false;
-        for (int i = 1; i < Q; ++i) {
-            int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
-            if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-            any |= a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx] == r;
-        }
-        if (!any) continue;
-        double rho[2];
-        for (int k = 0; k < 2; ++k) {
-            double s = 0.0;
-            for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
-            rho[k] = s;
-        }
-        for (int i = 1; i < Q; ++i) {
-            int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
-            if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-            const int64_t s = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-            if (a.rodid[s] != r) continue;
-            const d3 ci = mk(cx(i), cy(i), cz(i));
-            const d3 xb = mk(px - 0.5 * cx(i), py - 0.5 * cy(i), pz - 0.5 * cz(i));
-            const d3 ub = velocity_at(rod, xb, a);
-            const d3 arm = min_image(xb - X, a);
-            d3 dp = mk(0, 0, 0);
-            for (int k = 0; k < 2; ++k) {
-                const double fo = decf(f, (k * Q + opp(i)) * a.fs + n) + wgt<double>(opp(i)) * a.rho_ref[k];
-                const double add = 2.0 * wgt<double>(i) * rho[k] * dot(ci, ub) * 3.0;
-                const double fin = fo + add;
-                f[(k * Q + i) * a.fs + s] = Codec<S>::enc(typename Codec<S>::C(fin - wgt<double>(i) * a.rho_ref[k]));
-                dp = dp - (fo + fin) * ci;
-                acc[6 + k] -= add;
+    int64_t n;
+    int x, y, z;
+    if (shell_node(a, r, n, x, y, z)) {
+        if (a.newid[n] == r) a.newid[n] = -1;
+        unsigned links = 0;
+        int64_t src[Q];
+        if ((a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
+                src[i] = -1;
+                if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
+                src[i] = (int64_t(zz) * a.ny + yy) * a.nx + xx;
+                if (a.rodid[src[i]] == r) links |= 1u << i;
             }
-            const d3 tq = cross(arm, dp);
-            acc[0] += dp.x;
-            acc[1] += dp.y;
-            acc[2] += dp.z;
-            acc[3] += tq.x;
-            acc[4] += tq.y;
-            acc[5] += tq.z;
+        }
+        if (links) {
+            // all populations of x at once (the slot stores below cannot alias
+            // them, but the compiler would have to assume they might)
+            double fx[2][Q], rho[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) {
+                    fx[k][j] = decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
+                    s += fx[k][j];
+                }
+                rho[k] = s;
+            }
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                if (!(links & (1u << i))) continue;
+                const int64_t s = src[i];
+                const d3 ci = mk(cx(i), cy(i), cz(i));
+                const d3 xb = mk(x - 0.5 * cx(i), y - 0.5 * cy(i), z - 0.5 * cz(i));
+                const d3 ub = velocity_at(rod, xb, a);
+                const d3 arm = min_image(xb - X, a);
+                d3 dp = mk(0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const double fo = fx[k][opp(i)];
+                    const double add = 2.0 * wgt<double>(i) * rho[k] * dot(ci, ub) * 3.0;
+                    const double fin = fo + add;
+                    f[(k * Q + i) * a.fs + s] = Codec<S>::enc(typename Codec<S>::C(fin - wgt<double>(i) * a.rho_ref[k]));
+                    dp = dp - (fo + fin) * ci;
+                    acc[6 + k] -= add;
+                }
+                const d3 tq = cross(arm, dp);
+                acc[0] += dp.x;
+                acc[1] += dp.y;
+                acc[2] += dp.z;
+                acc[3] += tq.x;
+                acc[4] += tq.y;
+                acc[5] += tq.z;
+            }
         }
     }
-    double tot[8];
-    for (int q = 0; q < 8; ++q) tot[q] = block_sum_d(acc[q], sh);
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 6; ++q) rod[ROD_FS + q] = tot[q];
-        // booked once the next fluid step has streamed these slots
-        rod[ROD_PEND] = tot[6];
-        rod[ROD_PEND + 1] = tot[7];
+    // read by the next rod update, after the fluid step has streamed these slots
+    double *part = part_slot(a.part_link, a, r, blockIdx.x);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double v = block_sum_d(acc[q], sh);
+        if (threadIdx.x == 0) part[q] = v;
     }
 }
 
@@ -587,16 +778,16 @@ static int fill_grid(int64_t n) {
 hipError_t launch_rods_place(int prec, const RodArgs &a, void *f, hipStream_t s) {
     if (a.n_rods == 0) return hipSuccess;
     const int64_t n = int64_t(a.nx) * a.ny * a.nz;
+    const dim3 grid(a.nblk, a.n_rods);
     hipLaunchKernelGGL(fill_i16_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, int16_t(-1));
-    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(RB), 0, s, a);
-    hipError_t e = rods_by_prec(prec, [&](auto *tag) {
+    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, a);
+    return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_update_kernel<S>, dim3(a.n_rods), dim3(RB), 0, s, a, static_cast<S *>(f), 1);
-        hipLaunchKernelGGL(rod_commit_kernel, dim3(a.n_rods), dim3(RB), 0, s, a);
-        hipLaunchKernelGGL(rod_link_kernel<S>, dim3(a.n_rods), dim3(RB), 0, s, a, static_cast<S *>(f));
+        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f), 1);
+        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, a);
+        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f));
         return hipGetLastError();
     });
-    return e;
 }
 
 hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s) {
@@ -606,21 +797,17 @@ hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s) {
 
 hipError_t launch_rods_step(int prec, const RodArgs &a, void *f, hipStream_t s) {
     if (a.n_rods == 0) return hipSuccess;
-    const int64_t n = int64_t(a.nx) * a.ny * a.nz;
-    hipError_t e = rods_by_prec(prec, [&](auto *tag) {
-        using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_adhesion_kernel<S>, dim3(a.n_rods), dim3(RB), 0, s, a, static_cast<const S *>(f));
-        return hipGetLastError();
-    });
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rod_integrate_kernel, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(fill_i16_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, int16_t(-1));
-    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(RB), 0, s, a);
+    const dim3 grid(a.nblk, a.n_rods);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_update_kernel<S>, dim3(a.n_rods), dim3(RB), 0, s, a, static_cast<S *>(f), 0);
-        hipLaunchKernelGGL(rod_commit_kernel, dim3(a.n_rods), dim3(RB), 0, s, a);
-        hipLaunchKernelGGL(rod_link_kernel<S>, dim3(a.n_rods), dim3(RB), 0, s, a, static_cast<S *>(f));
+        hipLaunchKernelGGL(rod_adhesion_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<const S *>(f));
+        hipLaunchKernelGGL(rod_pairs_kernel, dim3(a.n_rods), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(rod_integrate_kernel, dim3(1), dim3(LB_MAX_RODS), size_t(a.n_rods) * RS_N * sizeof(double), s,
+                           a);
+        hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, a);
+        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f), 0);
+        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, a);
+        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f));
         return hipGetLastError();
     });
 }

@@ -477,9 +477,19 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
             C up[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) up[d] = (cur_j[r][0][d] * om[0] + cur_j[r][1][d] * om[1]) * rden;
-            const C usq_chk = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
-            if (!(rho[0] + rho[1] > C(0))) st |= ST_RHO;
-            if (!(usq_chk <= C(0.09))) st |= (usq_chk != usq_chk) ? ST_NAN : ST_SPEED;
+            // health check on the physical velocity (sum_k j_k + F/2) / rho
+            {
+                const C rt = rho[0] + rho[1];
+                const C ir = rt > C(0) ? C(1) / rt : C(0);
+                C usq_chk = C(0);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const C ud = (cur_j[r][0][d] + cur_j[r][1][d] + C(0.5) * (F[0][d] + F[1][d])) * ir;
+                    usq_chk += ud * ud;
+                }
+                if (!(rt > C(0))) st |= ST_RHO;
+                if (!(usq_chk <= C(0.09))) st |= (usq_chk != usq_chk) ? ST_NAN : ST_SPEED;
+            }
 
             const uint32_t voE = own[r].xy[1][1] * E;
             const bool near_wall = (cur_m[r] & MAT_NEAR_WALL) != 0;

@@ -124,6 +124,11 @@ def test_validation_rejects_bad_input_before_any_device_call(lib):
     rc = lib.lb_init(ct.byref(p), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
                      None, ct.byref(ctx))
     assert rc == _lib.LB_EINVAL and "rod" in lib.lb_last_error().decode()
+    p.rod_radius = 2.0
+    p.n_rods = _lib.LB_MAX_RODS + 1
+    rc = lib.lb_init(ct.byref(p), ct.byref(buf), rho.ctypes.data_as(ct.c_void_p), mat.ctypes.data_as(ct.c_void_p), None,
+                     None, ct.byref(ctx))
+    assert rc == _lib.LB_EINVAL and "n_rods" in lib.lb_last_error().decode()
     assert lib.lb_rods_step(None, None) == _lib.LB_EINVAL
     # step / observables / export on a null context
     assert lib.lb_step(None, 1, None) == _lib.LB_EINVAL
