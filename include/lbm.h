@@ -169,6 +169,62 @@ int lb_observables(lb_ctx *ctx, lb_obs *out, hipStream_t stream);
  */
 int lb_export(lb_ctx *ctx, double *rho_dev, double *f_dev, hipStream_t stream);
 
+/*
+ * Droplet shape of the current state (Results, drying dynamics: height,
+ * footprint radii and contact angles along x and y; the extraction is this
+ * library's reading, the paper gives none).  Colour C = (rho_A - rho_B) /
+ * (rho_A + rho_B) on fluid nodes, liquid C > 0:
+ *   height    : largest column height above the wall surface z = 1/2 (topmost
+ *               wet node of the column plus the interpolated C = 0 crossing)
+ *   r_x, r_y  : half-lengths of the run of C > 0 on plane z = 1 along the row
+ *               y = yc and the column x = xc through the centre node (xc, yc
+ *               rounded half to even), ends interpolated at C = 0
+ *   theta_x/y : spherical-cap contact angles 2 atan(height / r) [rad]
+ *   wet_nodes : fluid nodes with C > 0
+ * The centre node must lie in the lattice (LB_EINVAL otherwise).  Synchronises.
+ */
+typedef struct {
+    double height, r_x, r_y, theta_x, theta_y;
+    int64_t wet_nodes;
+} lb_droplet;
+int lb_droplet_shape(lb_ctx *ctx, double xc, double yc, lb_droplet *out, hipStream_t stream);
+
+/*
+ * Deposit statistics of the rods (Methods, structural characterisation,
+ * Eqs. 13 and 14).  Each rod is represented by nb = max(2, floor(2 h /
+ * bead_spacing + 1/2) + 1) beads evenly spaced along its axis segment
+ * (half-length h = L/2 - R; nb <= 64) and the nb - 1 segments between them.
+ * Axial profiles bin x into n_bins_x equal bins over [0, nx) for beads and
+ * segment midpoints with |y - yc| <= strip_y / 2; transverse profiles bin y
+ * into n_bins_y bins over [0, ny) with |x - xc| <= strip_x / 2 (minimum image
+ * in periodic directions; 1 <= bins <= 256).  Outputs (host, caller-owned):
+ *   g_x[n_bins_x], g_y[n_bins_y] : Eq. 14, bead count over the mean count per
+ *                                  bin (all 0 if no bead is binned)
+ *   s_x[n_bins_x], s_y[n_bins_y] : Eq. 13, mean of 2 cos^2(zeta_x) - 1 over
+ *                                  the segments of the bin (0 if none)
+ *   n_x, n_y                     : segments per bin
+ *   labels[n_rods] (nullable)    : contact-graph cluster of each rod (its
+ *                                  smallest rod index)
+ *   graph                        : rods, edges (segment distance < r_contact),
+ *                                  largest cluster size, spanning = 1 if one
+ *                                  cluster reaches x < x_src and x > x_snk
+ * Synchronises.
+ */
+typedef struct {
+    int32_t n_bins_x, n_bins_y;
+    double xc, yc, strip_x, strip_y;
+    double bead_spacing, r_contact, x_src, x_snk;
+} lb_deposit_spec;
+typedef struct {
+    int32_t n_rods, edges, largest, spanning;
+} lb_graph;
+int lb_deposit(lb_ctx *ctx, const lb_deposit_spec *spec, double *g_x, double *s_x, int32_t *n_x, double *g_y,
+               double *s_y, int32_t *n_y, int32_t *labels, lb_graph *graph, hipStream_t stream);
+
+/* z-projected rod occupancy: rod nodes per (y, x) column into map_host
+ * [ny][nx] (host, caller-owned).  Synchronises. */
+int lb_rod_map(lb_ctx *ctx, int32_t *map_host, hipStream_t stream);
+
 /* Tile shape of the fused step: 64 x tile_y columns, rows_per_thread rows per
  * thread, zchunk planes marched per work-group. */
 typedef struct {
@@ -195,9 +251,10 @@ int lb_destroy(lb_ctx *ctx);
 /* Thread-local text of the last error. */
 const char *lb_last_error(void);
 
-/* sizeof(lb_params), sizeof(lb_buffers), sizeof(lb_obs) into out[0..2], so a
- * binding can verify its mirrors of the structs.  Never fails. */
-void lb_abi_sizes(size_t out[3]);
+/* sizeof of lb_params, lb_buffers, lb_obs, lb_droplet, lb_deposit_spec and
+ * lb_graph into out[0..5], so a binding can verify its mirrors of the
+ * structs.  Never fails. */
+void lb_abi_sizes(size_t out[6]);
 
 #ifdef __cplusplus
 }

@@ -33,6 +33,9 @@ EXPORTS = (
     "lb_autotune",
     "lb_rods_step",
     "lb_rods_get",
+    "lb_droplet_shape",
+    "lb_deposit",
+    "lb_rod_map",
 )
 
 
@@ -97,6 +100,44 @@ class LbTile(ct.Structure):
     ]
 
 
+class LbDroplet(ct.Structure):
+    _fields_ = [
+        ("height", ct.c_double),
+        ("r_x", ct.c_double),
+        ("r_y", ct.c_double),
+        ("theta_x", ct.c_double),
+        ("theta_y", ct.c_double),
+        ("wet_nodes", ct.c_int64),
+    ]
+
+
+class LbDepositSpec(ct.Structure):
+    _fields_ = [
+        ("n_bins_x", ct.c_int32),
+        ("n_bins_y", ct.c_int32),
+        ("xc", ct.c_double),
+        ("yc", ct.c_double),
+        ("strip_x", ct.c_double),
+        ("strip_y", ct.c_double),
+        ("bead_spacing", ct.c_double),
+        ("r_contact", ct.c_double),
+        ("x_src", ct.c_double),
+        ("x_snk", ct.c_double),
+    ]
+
+
+class LbGraph(ct.Structure):
+    _fields_ = [
+        ("n_rods", ct.c_int32),
+        ("edges", ct.c_int32),
+        ("largest", ct.c_int32),
+        ("spanning", ct.c_int32),
+    ]
+
+
+STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph")
+
+
 class LbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"liblbm error {code}: {msg}")
@@ -152,11 +193,17 @@ def load(path: str = LIB_PATH):
     lib.lb_set_tiles.restype = ct.c_int
     lib.lb_autotune.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p, P(LbTile)]
     lib.lb_autotune.restype = ct.c_int
+    lib.lb_droplet_shape.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, P(LbDroplet), ct.c_void_p]
+    lib.lb_droplet_shape.restype = ct.c_int
+    lib.lb_deposit.argtypes = [ct.c_void_p, P(LbDepositSpec)] + [ct.c_void_p] * 7 + [P(LbGraph), ct.c_void_p]
+    lib.lb_deposit.restype = ct.c_int
+    lib.lb_rod_map.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_rod_map.restype = ct.c_int
     lib.lb_abi_sizes.argtypes = [P(ct.c_size_t)]
     lib.lb_abi_sizes.restype = None
-    sizes = (ct.c_size_t * 3)()
+    sizes = (ct.c_size_t * len(STRUCTS))()
     lib.lb_abi_sizes(sizes)
-    want = (ct.sizeof(LbParams), ct.sizeof(LbBuffers), ct.sizeof(LbObs))
+    want = tuple(ct.sizeof(globals()[n]) for n in STRUCTS)
     if tuple(sizes) != want:
         raise RuntimeError(f"liblbm struct sizes {tuple(sizes)} differ from the binding's {want}")
     _lib = lib

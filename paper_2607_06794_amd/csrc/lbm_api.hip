@@ -67,7 +67,7 @@ int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
 //   psi      : 16 x 2 doubles, ghost pseudo-densities per material id
 //   carry    : 2 doubles, ledger folded out of the tile slots on tile changes
 //   rods     : n_rods x ROD_STRIDE doubles
-//   rodid    : N int16, rod id per node (-1 none); newid: N int16
+//   rodid    : N int16, rod id per node (-1 none); newid: N int32
 //   rodsum   : 8 doubles (solid ledger, rod momentum)
 //   rodpart  : 3 x n_rods x rod_nblk x ROD_PART doubles, per-block partial sums
 //   shell    : n_rods x rod_shell_cap int32 surface lists; shell_cnt: n_rods int32
@@ -86,9 +86,44 @@ static int rod_shell_cap(const lb_params &p) {
 }
 static int rod_nblk(const lb_params &p) { return rod_shell_cap(p) / 256; }
 
+// Observable scratch: droplet column scan, then deposit binning and graph.
+struct ObsLayout {
+    size_t col_h, col_wet, line_x, line_y, out, bins, sval, dep_out, labels, graph, map, total;
+};
+static ObsLayout obs_layout(const lb_params *p) {
+    ObsLayout l{};
+    const size_t ncol = size_t(p->nx) * p->ny, nr = size_t(std::max(p->n_rods, 0));
+    size_t o = 0;
+    l.col_h = o;
+    o = align256(o + ncol * sizeof(double));
+    l.col_wet = o;
+    o = align256(o + ncol * sizeof(int));
+    l.line_x = o;
+    o = align256(o + size_t(p->nx) * sizeof(double));
+    l.line_y = o;
+    o = align256(o + size_t(p->ny) * sizeof(double));
+    l.out = o;
+    o = align256(o + 16 * sizeof(double));
+    l.bins = o;
+    o = align256(o + nr * 4 * DEP_NB * sizeof(int16_t));
+    l.sval = o;
+    o = align256(o + nr * sizeof(double));
+    l.dep_out = o;
+    o = align256(o + 6 * DEP_MAXBIN * sizeof(double));
+    l.labels = o;
+    o = align256(o + nr * sizeof(int32_t));
+    l.graph = o;
+    o = align256(o + 4 * sizeof(int32_t));
+    l.map = o;
+    o = align256(o + ncol * sizeof(int32_t));
+    l.total = o;
+    return l;
+}
+static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
+
 struct WsLayout {
     size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
-        nbr, nbr_cnt, total;
+        nbr, nbr_cnt, obs, total;
     int max_tiles;
 };
 
@@ -117,7 +152,7 @@ WsLayout ws_layout(const lb_params *p) {
     w.rodid = o;
     o = align256(o + idb);
     w.newid = o;
-    o = align256(o + idb);
+    o = align256(o + 2 * idb);  // int32
     w.rodsum = o;
     o = align256(o + 8 * sizeof(double));
     w.rodpart = o;
@@ -132,6 +167,8 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + nr * ROD_NBR * sizeof(int16_t));
     w.nbr_cnt = o;
     o = align256(o + nr * sizeof(int));
+    w.obs = o;
+    o = align256(o + obs_bytes(p));
     w.total = o;
     return w;
 }
@@ -223,11 +260,13 @@ struct lb_ctx {
     double *psi;
     double *carry;
     double *rods;
-    int16_t *rodid, *newid;
+    int16_t *rodid;
+    int *newid;
     double *rodsum;
     double *rodpart;
     int *shell, *shell_cnt, *nbr_cnt;
     int16_t *nbr;
+    char *obs;
     double psi_host[32];
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
@@ -332,10 +371,13 @@ size_t lb_workspace_bytes(const lb_params *p) {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
-void lb_abi_sizes(size_t out[3]) {
+void lb_abi_sizes(size_t out[6]) {
     out[0] = sizeof(lb_params);
     out[1] = sizeof(lb_buffers);
     out[2] = sizeof(lb_obs);
+    out[3] = sizeof(lb_droplet);
+    out[4] = sizeof(lb_deposit_spec);
+    out[5] = sizeof(lb_graph);
 }
 
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
@@ -381,13 +423,14 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->carry = reinterpret_cast<double *>(ws + w.carry);
     c->rods = reinterpret_cast<double *>(ws + w.rods);
     c->rodid = reinterpret_cast<int16_t *>(ws + w.rodid);
-    c->newid = reinterpret_cast<int16_t *>(ws + w.newid);
+    c->newid = reinterpret_cast<int *>(ws + w.newid);
     c->rodsum = reinterpret_cast<double *>(ws + w.rodsum);
     c->rodpart = reinterpret_cast<double *>(ws + w.rodpart);
     c->shell = reinterpret_cast<int *>(ws + w.shell);
     c->shell_cnt = reinterpret_cast<int *>(ws + w.shell_cnt);
     c->nbr = reinterpret_cast<int16_t *>(ws + w.nbr);
     c->nbr_cnt = reinterpret_cast<int *>(ws + w.nbr_cnt);
+    c->obs = ws + w.obs;
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
             c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
@@ -531,6 +574,122 @@ int lb_export(lb_ctx *c, double *rho_dev, double *f_dev, hipStream_t stream) {
     const lb_params &p = c->p;
     HIP_TRY(launch_export(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, rho_dev, f_dev, stream), "export");
     HIP_TRY(hipStreamSynchronize(stream), "export sync");
+    return LB_OK;
+}
+
+int lb_droplet_shape(lb_ctx *c, double xc, double yc, lb_droplet *out, hipStream_t stream) {
+    if (!c || !out) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    const double rx = nearbyint(xc), ry = nearbyint(yc);  // half to even
+    if (!(rx >= 0 && rx < p.nx && ry >= 0 && ry < p.ny)) return fail(LB_EINVAL, "centre (%g, %g) off the lattice", xc, yc);
+    const ObsLayout l = obs_layout(&p);
+    ObsArgs o{};
+    o.mat = c->mat;
+    o.fs = c->fs;
+    o.nx = p.nx;
+    o.ny = p.ny;
+    o.nz = p.nz;
+    o.ix = int(rx);
+    o.iy = int(ry);
+    o.rho_ref[0] = c->rref[0];
+    o.rho_ref[1] = c->rref[1];
+    o.col_h = reinterpret_cast<double *>(c->obs + l.col_h);
+    o.col_wet = reinterpret_cast<int *>(c->obs + l.col_wet);
+    o.line_x = reinterpret_cast<double *>(c->obs + l.line_x);
+    o.line_y = reinterpret_cast<double *>(c->obs + l.line_y);
+    o.out = reinterpret_cast<double *>(c->obs + l.out);
+    HIP_TRY(launch_droplet(p.prec, c->f[c->cur], o, stream), "droplet shape");
+    double r[6];
+    HIP_TRY(hipMemcpyAsync(r, o.out, sizeof(r), hipMemcpyDeviceToHost, stream), "copy droplet");
+    HIP_TRY(hipStreamSynchronize(stream), "droplet sync");
+    out->height = r[0];
+    out->r_x = r[1];
+    out->r_y = r[2];
+    out->theta_x = r[3];
+    out->theta_y = r[4];
+    out->wet_nodes = int64_t(r[5]);
+    return LB_OK;
+}
+
+int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, int32_t *n_x, double *g_y, double *s_y,
+               int32_t *n_y, int32_t *labels, lb_graph *graph, hipStream_t stream) {
+    if (!c || !s || !g_x || !s_x || !n_x || !g_y || !s_y || !n_y || !graph) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    if (s->n_bins_x < 1 || s->n_bins_x > DEP_MAXBIN || s->n_bins_y < 1 || s->n_bins_y > DEP_MAXBIN)
+        return fail(LB_EINVAL, "bins per profile must be in [1, %d]", DEP_MAXBIN);
+    if (!(s->bead_spacing > 0) || !(s->r_contact >= 0) || !(s->strip_x >= 0) || !(s->strip_y >= 0))
+        return fail(LB_EINVAL, "bad deposit spec");
+    const double half = 0.5 * p.rod_length - p.rod_radius;
+    const double nbd = floor(2.0 * half / s->bead_spacing + 0.5) + 1.0;
+    const int nb = nbd < 2.0 ? 2 : (nbd > DEP_NB ? DEP_NB + 1 : int(nbd));
+    if (nb > DEP_NB) return fail(LB_EINVAL, "more than %d beads per rod", DEP_NB);
+    const ObsLayout l = obs_layout(&p);
+    DepArgs d{};
+    d.rods = c->rods;
+    d.n_rods = p.n_rods;
+    d.nb = nb;
+    d.nbx = s->n_bins_x;
+    d.nby = s->n_bins_y;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nz = p.nz;
+    d.px = p.periodic[0];
+    d.py = p.periodic[1];
+    d.pz = p.periodic[2];
+    d.half = half;
+    d.xc = s->xc;
+    d.yc = s->yc;
+    d.strip_x = s->strip_x;
+    d.strip_y = s->strip_y;
+    d.r_contact = s->r_contact;
+    d.x_src = s->x_src;
+    d.x_snk = s->x_snk;
+    d.bins = reinterpret_cast<int16_t *>(c->obs + l.bins);
+    d.sval = reinterpret_cast<double *>(c->obs + l.sval);
+    d.out = reinterpret_cast<double *>(c->obs + l.dep_out);
+    d.labels = reinterpret_cast<int32_t *>(c->obs + l.labels);
+    d.graph = reinterpret_cast<int32_t *>(c->obs + l.graph);
+    HIP_TRY(launch_deposit(d, stream), "deposit");
+    std::vector<double> res(6 * DEP_MAXBIN);
+    int32_t gr[4];
+    std::vector<int32_t> lab(size_t(std::max(p.n_rods, 0)));
+    HIP_TRY(hipMemcpyAsync(res.data(), d.out, res.size() * sizeof(double), hipMemcpyDeviceToHost, stream), "copy deposit");
+    HIP_TRY(hipMemcpyAsync(gr, d.graph, sizeof(gr), hipMemcpyDeviceToHost, stream), "copy graph");
+    if (!lab.empty())
+        HIP_TRY(hipMemcpyAsync(lab.data(), d.labels, lab.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream),
+                "copy labels");
+    HIP_TRY(hipStreamSynchronize(stream), "deposit sync");
+    // Eq. 14 with equal bins: counts over the mean count per bin
+    auto finish = [&](const double *r, int nbins, double *g, double *sv, int32_t *ns) {
+        double tot = 0.0;
+        for (int b = 0; b < nbins; ++b) tot += r[b];
+        const double mean = tot / nbins;
+        for (int b = 0; b < nbins; ++b) {
+            g[b] = mean > 0.0 ? r[b] / mean : 0.0;
+            sv[b] = r[DEP_MAXBIN + b];
+            ns[b] = int32_t(r[2 * DEP_MAXBIN + b]);
+        }
+    };
+    finish(res.data(), s->n_bins_x, g_x, s_x, n_x);
+    finish(res.data() + 3 * DEP_MAXBIN, s->n_bins_y, g_y, s_y, n_y);
+    graph->n_rods = gr[0];
+    graph->edges = gr[1];
+    graph->largest = gr[2];
+    graph->spanning = gr[3];
+    if (labels)
+        for (size_t r = 0; r < lab.size(); ++r) labels[r] = lab[r];
+    return LB_OK;
+}
+
+int lb_rod_map(lb_ctx *c, int32_t *map_host, hipStream_t stream) {
+    if (!c || !map_host) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    const ObsLayout l = obs_layout(&p);
+    int32_t *map = reinterpret_cast<int32_t *>(c->obs + l.map);
+    HIP_TRY(launch_rod_map(c->mat, p.nx, p.ny, p.nz, map, stream), "rod map");
+    HIP_TRY(hipMemcpyAsync(map_host, map, size_t(p.nx) * p.ny * sizeof(int32_t), hipMemcpyDeviceToHost, stream),
+            "copy rod map");
+    HIP_TRY(hipStreamSynchronize(stream), "rod map sync");
     return LB_OK;
 }
 

@@ -56,7 +56,7 @@ struct RodArgs {
     int16_t *nbr;                             // [n_rods][ROD_NBR] neighbour lists
     int *nbr_cnt;                             // [n_rods]
     int16_t *rodid;  // rod id per node before the move (-1: none)
-    int16_t *newid;  // rod id per node after the move
+    int *newid;      // rod id per node after the move
     uint8_t *mat;
     unsigned *status;
     int nx, ny, nz, px, py, pz;
@@ -90,6 +90,35 @@ hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t
                               const double *ledger_carry, double *partials, int nblocks, double *result,
                               hipStream_t s);
 hipError_t launch_fold_ledger(double *ledger_part, int nslots, double *carry, hipStream_t s);
+// droplet shape (column scan) and deposit statistics
+struct ObsArgs {
+    const uint8_t *mat;
+    int64_t fs;
+    int nx, ny, nz, ix, iy;
+    double rho_ref[2];
+    double *col_h;   // [ny][nx] column heights
+    int *col_wet;    // [ny][nx] wet nodes per column
+    double *line_x;  // [nx] colour on plane z = 1 along row iy
+    double *line_y;  // [ny] colour on plane z = 1 along column ix
+    double *out;     // h, r_x, r_y, theta_x, theta_y, wet nodes
+};
+constexpr int DEP_NB = 64;       // beads per rod at most
+constexpr int DEP_MAXBIN = 256;  // bins per profile at most
+struct DepArgs {
+    const double *rods;
+    int n_rods, nb, nbx, nby;
+    int nx, ny, nz, px, py, pz;
+    double half, xc, yc, strip_x, strip_y, r_contact, x_src, x_snk;
+    int16_t *bins;   // [n_rods][4][DEP_NB]: bead bin x, bead bin y, segment bin x, segment bin y (-1 outside)
+    double *sval;    // [n_rods] 2 e_x^2 - 1
+    double *out;     // axial: count, S, segments [3][DEP_MAXBIN]; then transverse, same
+    int32_t *labels; // [n_rods] cluster label (smallest rod index of the cluster)
+    int32_t *graph;  // n_rods, edges, largest cluster, spanning
+};
+hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t s);
+hipError_t launch_deposit(const DepArgs &d, hipStream_t s);
+hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s);
+
 constexpr int OBS_BLOCKS = 512;
 constexpr int OBS_FIELDS = 10;
 

@@ -134,10 +134,19 @@ __device__ inline Box rod_box(const double *rod, const RodArgs &a, int margin) {
     const int n[3] = {a.nx, a.ny, a.nz}, per[3] = {a.px, a.py, a.pz};
     Box b;
     for (int d = 0; d < 3; ++d) {
-        b.lo[d] = static_cast<int>(floor(c[d] - ext[d])) - margin;
-        b.hi[d] = static_cast<int>(ceil(c[d] + ext[d])) + margin;
-        // never visit a node twice through the periodic wrap
-        if (per[d] && b.hi[d] - b.lo[d] + 1 > n[d]) b.hi[d] = b.lo[d] + n[d] - 1;
+        // clamp in floating point first: a rod state gone bad (huge or NaN
+        // coordinates) must still give a small, bounded box
+        const double lo = fmin(fmax(floor(c[d] - ext[d]), -4.0 * n[d]), 4.0 * n[d]);
+        const double hi = fmin(fmax(ceil(c[d] + ext[d]), -4.0 * n[d]), 4.0 * n[d]);
+        b.lo[d] = static_cast<int>(lo) - margin;
+        b.hi[d] = static_cast<int>(hi) + margin;
+        if (per[d]) {
+            // never visit a node twice through the periodic wrap
+            if (b.hi[d] - b.lo[d] + 1 > n[d]) b.hi[d] = b.lo[d] + n[d] - 1;
+        } else {
+            b.lo[d] = max(b.lo[d], -margin);
+            b.hi[d] = min(b.hi[d], n[d] - 1 + margin);
+        }
     }
     return b;
 }
@@ -455,8 +464,8 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
     const int r = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double *rod = a.rods + r * ROD_STRIDE;
     const Box b = rod_box(rod, a, 2);
-    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1;
-    const int64_t nbox = int64_t(ex) * ey * (b.hi[2] - b.lo[2] + 1);
+    const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
+    const int64_t nbox = (ex > 0 && ey > 0 && ez > 0) ? int64_t(ex) * ey * ez : 0;
     const double r2in = a.radius * a.radius, r2sh = shell_r2(a);
     int base = 0;  // same in every thread
     for (int64_t m0 = 0; m0 < nbox; m0 += MB) {
@@ -473,7 +482,8 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
                 listed = true;
                 if (d2 <= r2in) {
                     const uint8_t mt = a.mat[n] & MAT_ID_MASK;
-                    if (mt == MAT_FLUID || mt == MAT_ROD) a.newid[n] = static_cast<int16_t>(r);
+                    // overlapping rods: the highest index keeps the node
+                    if (mt == MAT_FLUID || mt == MAT_ROD) atomicMax(&a.newid[n], r);
                     else atomicOr(a.status, ST_ROD);  // a rod ran into a wall or the reservoir
                 }
             }
@@ -498,7 +508,7 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
     if (threadIdx.x == 0) a.shell_cnt[r] = min(base, a.shell_cap);
 }
 
-__global__ void fill_i16_kernel(int16_t *p, int64_t n, int16_t v) {
+__global__ void fill_i32_kernel(int *p, int64_t n, int v) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
 
@@ -524,9 +534,10 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodArgs a, S *f, int ini
     int x = 0, y = 0, z = 0;
     bool unc = false;
     if (shell_node(a, r, n, x, y, z)) {
-        const int16_t oldid = a.rodid[n], newid = a.newid[n];
-        unc = oldid == r && newid != r;
-        if (newid == r && oldid != r) {  // covered
+        // a node passing from one rod to another stays solid and is neither
+        const int oldid = a.rodid[n], newid = a.newid[n];
+        unc = oldid == r && newid < 0;
+        if (newid == r && oldid < 0) {  // covered
             if (!init) {
                 const d3 arm = min_image(mk(x, y, z) - X, a);
                 d3 mom = mk(0, 0, 0);
@@ -657,7 +668,7 @@ __global__ void __launch_bounds__(RB) rod_commit_kernel(RodArgs a) {
     }
     int64_t n;
     int x, y, z;
-    if (shell_node(a, r, n, x, y, z) && (a.rodid[n] == r || a.newid[n] == r)) a.rodid[n] = a.newid[n];
+    if (shell_node(a, r, n, x, y, z) && (a.rodid[n] == r || a.newid[n] == r)) a.rodid[n] = int16_t(a.newid[n]);
 }
 
 // totals over rods in a fixed order: solid ledger [2], rod momentum M V [3]
@@ -779,7 +790,7 @@ hipError_t launch_rods_place(int prec, const RodArgs &a, void *f, hipStream_t s)
     if (a.n_rods == 0) return hipSuccess;
     const int64_t n = int64_t(a.nx) * a.ny * a.nz;
     const dim3 grid(a.nblk, a.n_rods);
-    hipLaunchKernelGGL(fill_i16_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, int16_t(-1));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, -1);
     hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, a);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;

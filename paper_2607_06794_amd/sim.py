@@ -195,6 +195,37 @@ class Lattice:
         )
         return rho.cpu().numpy(), (f.cpu().numpy() if f is not None else None)
 
+    def droplet_shape(self, xc: float, yc: float) -> dict:
+        """Height, footprint half-lengths and contact angles (radians) of the droplet."""
+        d = _lib.LbDroplet()
+        _lib.check(self.lib.lb_droplet_shape(self._ctx, float(xc), float(yc), ct.byref(d), _stream_ptr(self.stream)))
+        return {"height": d.height, "r_x": d.r_x, "r_y": d.r_y, "theta_x": d.theta_x, "theta_y": d.theta_y,
+                "wet_nodes": d.wet_nodes}
+
+    def deposit(self, n_bins_x: int, n_bins_y: int, xc: float, yc: float, strip_x: float, strip_y: float,
+                bead_spacing: float = 2.0, r_contact: float = 5.25, x_src: float = 0.0, x_snk: float = 0.0) -> dict:
+        """Deposit profiles g^b (Eq. 14) and S_x^b (Eq. 13) and the rod contact graph."""
+        spec = _lib.LbDepositSpec(int(n_bins_x), int(n_bins_y), xc, yc, strip_x, strip_y, bead_spacing, r_contact,
+                                  x_src, x_snk)
+        gx, sx = np.zeros(n_bins_x), np.zeros(n_bins_x)
+        gy, sy = np.zeros(n_bins_y), np.zeros(n_bins_y)
+        nx_, ny_ = np.zeros(n_bins_x, np.int32), np.zeros(n_bins_y, np.int32)
+        labels = np.zeros(max(self.n_rods, 1), np.int32)
+        g = _lib.LbGraph()
+        ptr = lambda a: a.ctypes.data_as(ct.c_void_p)
+        _lib.check(self.lib.lb_deposit(self._ctx, ct.byref(spec), ptr(gx), ptr(sx), ptr(nx_), ptr(gy), ptr(sy),
+                                       ptr(ny_), ptr(labels), ct.byref(g), _stream_ptr(self.stream)))
+        return {"g_x": gx, "s_x": sx, "n_x": nx_, "g_y": gy, "s_y": sy, "n_y": ny_,
+                "labels": labels[: self.n_rods], "edges": g.edges, "largest": g.largest,
+                "spanning": bool(g.spanning)}
+
+    def rod_map(self) -> np.ndarray:
+        """Rod nodes per (y, x) column (z-projected occupancy)."""
+        nz, ny, nx = self.params.shape
+        m = np.zeros((ny, nx), np.int32)
+        _lib.check(self.lib.lb_rod_map(self._ctx, m.ctypes.data_as(ct.c_void_p), _stream_ptr(self.stream)))
+        return m
+
     def set_tiles(self, tile_y: int, rows_per_thread: int, zchunk: int = 0):
         t = _lib.LbTile(int(tile_y), int(rows_per_thread), int(zchunk), 0.0)
         _lib.check(self.lib.lb_set_tiles(self._ctx, ct.byref(t), _stream_ptr(self.stream)))

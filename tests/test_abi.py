@@ -43,9 +43,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_mirrors_match(lib):
-    sizes = (ct.c_size_t * 3)()
+    sizes = (ct.c_size_t * len(_lib.STRUCTS))()
     lib.lb_abi_sizes(sizes)
-    assert tuple(sizes) == (ct.sizeof(_lib.LbParams), ct.sizeof(_lib.LbBuffers), ct.sizeof(_lib.LbObs))
+    assert tuple(sizes) == tuple(ct.sizeof(getattr(_lib, n)) for n in _lib.STRUCTS)
+    # field layout of the observable structs (plain C rules, no padding surprises)
+    assert ct.sizeof(_lib.LbDroplet) == 48 and ct.sizeof(_lib.LbDepositSpec) == 72 and ct.sizeof(_lib.LbGraph) == 16
 
 
 def test_buffer_sizes(lib):
@@ -135,4 +137,7 @@ def test_validation_rejects_bad_input_before_any_device_call(lib):
     assert lib.lb_observables(None, None, None) == _lib.LB_EINVAL
     assert lib.lb_export(None, None, None, None) == _lib.LB_EINVAL
     assert lib.lb_current_buffer(None) == -1
+    assert lib.lb_droplet_shape(None, 0.0, 0.0, None, None) == _lib.LB_EINVAL
+    assert lib.lb_deposit(None, None, None, None, None, None, None, None, None, None, None) == _lib.LB_EINVAL
+    assert lib.lb_rod_map(None, None, None) == _lib.LB_EINVAL
     assert lib.lb_destroy(None) == _lib.LB_OK

@@ -63,7 +63,33 @@ def cap_rods_case():
                 wall=0.5)
 
 
-CASES = {"periodic": periodic_case, "cap": cap_rods_case}
+def overlap_case():
+    """Two crossing rods whose capsules share nodes (axis distance 3 < 2R), one
+    moving along the other's axis: nodes pass from one rod to the other, which
+    must leave them solid (no cover, no uncover); overlaps go to the higher
+    index.  Heavy rods, a negligible repulsion."""
+    shape = (16, 24, 32)
+    rho = np.zeros((2,) + shape)
+    rho[0] = 1.0
+    rho[1] = 0.03
+    mat = np.zeros(shape, np.uint8)
+    rods = np.zeros((2, 13))
+    q = lambda ang, ax: np.concatenate([[np.cos(ang / 2)], np.sin(ang / 2) * np.asarray(ax) / np.linalg.norm(ax)])
+    rods[0, :3] = (16.2, 12.1, 8.0)
+    rods[0, 3:7] = q(np.pi / 2, (0, 1, 0))  # along x
+    rods[0, 7:10] = (0.0, 0.06, 0.0)
+    rods[1, :3] = (16.0, 12.3, 11.0)
+    rods[1, 3:7] = q(np.pi / 2, (1, 0, 0))  # along y, 3 above rod 0
+    rods[1, 7:10] = (0.05, 0.0, 0.0)
+    return dict(shape=shape, periodic=(True, True, True), rho=rho, mat=mat, rods=rods, evaporation=False, wall=None,
+                rod=dict(eps_rep=1e-6, eps_att=0.0, rho_rod=100.0))
+
+
+CASES = {"periodic": periodic_case, "cap": cap_rods_case, "overlap": overlap_case}
+
+
+def rod_params(c):
+    return dict(ROD, **c.get("rod", {}))
 
 
 def oracle_params(c):
@@ -76,7 +102,7 @@ def oracle_params(c):
 def oracle_run(name, steps):
     c = CASES[name]()
     nz, ny, nx = c["shape"]
-    rp = R.RodParams(wall_z=c["wall"], **ROD)
+    rp = R.RodParams(wall_z=c["wall"], **rod_params(c))
     rods = R.Rods(c["rods"][:, :3], c["rods"][:, 3:7], c["rods"][:, 7:10], c["rods"][:, 10:13], rp, (nx, ny, nz),
                   c["periodic"])
     run = R.CoupledRun(c["rho"], c["mat"], oracle_params(c), rods)
@@ -92,9 +118,10 @@ def gpu_run(name, prec, steps, **tile):
     c = CASES[name]()
     say(f"[gpu] rods case={name} prec={prec} steps={steps} n_rods={len(c['rods'])} tile={tile}")
     lp = cases.lattice_params(dict(c, G=3.6, tau=(1.0, 1.0), body_force=(0, 0, 0)), prec, **tile)
-    lp.rod_length, lp.rod_radius, lp.rod_rho = ROD["length"], ROD["radius"], ROD["rho_rod"]
-    lp.eps_att, lp.eps_rep, lp.rod_d0, lp.rod_rcut = ROD["eps_att"], ROD["eps_rep"], ROD["d0"], ROD["r_cut"]
-    lp.eps_wall, lp.rod_d0_wall, lp.n_sub, lp.wall_z = ROD["eps_wall"], ROD["d0_wall"], ROD["n_sub"], c["wall"]
+    rp = rod_params(c)
+    lp.rod_length, lp.rod_radius, lp.rod_rho = rp["length"], rp["radius"], rp["rho_rod"]
+    lp.eps_att, lp.eps_rep, lp.rod_d0, lp.rod_rcut = rp["eps_att"], rp["eps_rep"], rp["d0"], rp["r_cut"]
+    lp.eps_wall, lp.rod_d0_wall, lp.n_sub, lp.wall_z = rp["eps_wall"], rp["d0_wall"], rp["n_sub"], c["wall"]
     lat = Lattice(lp, c["rho"], c["mat"], rods=c["rods"])
     o0 = lat.observables()
     lat.coupled_step(steps)
@@ -113,7 +140,7 @@ def _rod_err(g, o, L):
     return dx, dq, dv, dl
 
 
-@pytest.mark.parametrize("name,steps", [("periodic", 25), ("cap", 15)])
+@pytest.mark.parametrize("name,steps", [("periodic", 25), ("cap", 15), ("overlap", 20)])
 def test_coupled_rods_fp64_parity(name, steps):
     fo, mo, so, solid_o, led_o, P0, P1 = oracle_run(name, steps)
     fg, sg, obs, o0 = gpu_run(name, "f64", steps)
@@ -126,7 +153,10 @@ def test_coupled_rods_fp64_parity(name, steps):
     assert dx <= 1e-12 and dq <= 1e-12 and dv <= 1e-10 and dl <= 1e-10
     assert np.allclose(obs["solid"], solid_o, rtol=1e-10, atol=1e-12)
     assert obs["status"] == 0
-    if name == "periodic":
+    if name == "overlap":
+        # the sliding rod really carried nodes across the shared region
+        assert abs(sg[0, 1] - 12.1) > 0.8
+    if name in ("periodic", "overlap"):
         # momentum of fluid + rods conserved on the GPU
         Pg0 = o0["momentum"] + o0["rod_momentum"]
         Pg1 = obs["momentum"] + obs["rod_momentum"]
