@@ -36,8 +36,8 @@
  *  - Errors: 0 = LB_OK; negative codes below.  No exception crosses the ABI.
  *    lb_last_error() returns a thread-local message for the last failure.
  *    Faults detected inside kernels (NaN, non-positive total density,
- *    |u| > 0.3) set a device status word that lb_observables reports as
- *    LB_EUNSTABLE.
+ *    |u| > 0.3, rod limits) set a device status word that lb_observables
+ *    reports as LB_EUNSTABLE.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -113,7 +113,9 @@ typedef struct {
     double kinetic;        /* sum of |j|^2 / (2 rho) */
     int64_t fluid_nodes;
     uint32_t status;       /* device status bits (1 NaN, 2 rho <= 0, 4 |u| > 0.3,
-                              8 rod moved >= 1 node in a step or hit a wall) */
+                              8 a rod point moved >= 0.9 in one step, 16 a rod
+                              reached a wall, the reservoir or a closed end,
+                              32 a rod's surface or neighbour list overflowed) */
     double solid[2];       /* mass of component k moved from the fluid into rods */
     double rod_momentum[3];/* sum over rods of M V */
 } lb_obs;

@@ -486,7 +486,9 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
         unsigned st = 0;
         if ((e = hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost)) != hipSuccess)
             return cleanup(hip_fail(e, "read status"));
-        if (st & ST_ROD) return cleanup(fail(LB_EINVAL, "a rod overlaps a wall, the reservoir or a closed end plane"));
+        if (st & ST_ROD_WALL)
+            return cleanup(fail(LB_EINVAL, "a rod overlaps a wall, the reservoir or a closed end plane"));
+        if (st & ST_ROD_LIST) return cleanup(fail(LB_EINVAL, "a rod's surface or neighbour list overflowed"));
     }
     *out = c;
     return LB_OK;

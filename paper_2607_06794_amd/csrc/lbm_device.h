@@ -39,7 +39,7 @@ constexpr uint8_t MAT_ID_MASK = 0x0F, MAT_NEAR_WALL = 0x80;
 __host__ __device__ inline bool is_static_wall(uint8_t id) { return id >= 2 && id <= 7; }
 
 // status bits
-constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u, ST_ROD = 8u;
+constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u, ST_ROD = 8u, ST_ROD_WALL = 16u, ST_ROD_LIST = 32u;
 
 // ---------------------------------------------------------------------------
 // storage codecs: S = element type in HBM, C = compute type in registers.

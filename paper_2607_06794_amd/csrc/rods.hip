@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(64) rod_pairs_kernel(RodArgs a) {
         const int slot = base + __popcll(bal & ((uint64_t(1) << lane) - 1));
         if (near) {
             if (slot < ROD_NBR) a.nbr[r * ROD_NBR + slot] = static_cast<int16_t>(s);
-            else atomicOr(a.status, ST_ROD);  // more neighbours than the list holds
+            else atomicOr(a.status, ST_ROD_LIST);  // more neighbours than the list holds
         }
         base += __popcll(bal);
     }
@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
             int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
             const double d2 = axis_dist2(rod, mk(x, y, z), a);
             const bool in_box = wrap_coord(x, a.nx, a.px) && wrap_coord(y, a.ny, a.py) && wrap_coord(z, a.nz, a.pz);
-            if (d2 <= r2in && !in_box) atomicOr(a.status, ST_ROD);  // a rod left the lattice
+            if (d2 <= r2in && !in_box) atomicOr(a.status, ST_ROD_WALL);  // a rod left the lattice
             if (d2 <= r2sh && in_box) {
                 n = (int64_t(z) * a.ny + y) * a.nx + x;
                 listed = true;
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
                     const uint8_t mt = a.mat[n] & MAT_ID_MASK;
                     // overlapping rods: the highest index keeps the node
                     if (mt == MAT_FLUID || mt == MAT_ROD) atomicMax(&a.newid[n], r);
-                    else atomicOr(a.status, ST_ROD);  // a rod ran into a wall or the reservoir
+                    else atomicOr(a.status, ST_ROD_WALL);  // a rod ran into a wall or the reservoir
                 }
             }
         }
@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
         if (listed) {
             const int idx = base + off + __popcll(bal & ((uint64_t(1) << lane) - 1));
             if (idx < a.shell_cap) a.shell[size_t(r) * a.shell_cap + idx] = static_cast<int>(n);
-            else atomicOr(a.status, ST_ROD);  // cannot happen for a capsule of the stated size
+            else atomicOr(a.status, ST_ROD_LIST);  // cannot happen for a capsule of the stated size
         }
         base += tot;
         __syncthreads();
