@@ -244,6 +244,30 @@ int lb_set_tiles(lb_ctx *ctx, const lb_tile *tile, hipStream_t stream);
  * trial_steps steps).  Synchronises. */
 int lb_autotune(lb_ctx *ctx, int32_t trial_steps, hipStream_t stream, lb_tile *best);
 
+/*
+ * Batches (many lattices per launch).  A batch advances n >= 1 lattices that
+ * were each set up with lb_init (any sizes, parameters, rod counts and tile
+ * shapes; one precision) with shared launches: one fused-step launch per
+ * tile class walks a device work list of (lattice, tile) entries with a
+ * parameter record per lattice, and each rod pass covers the rods of every
+ * lattice.  Results are identical to stepping each lattice alone with
+ * lb_step and lb_rods_step.  While a batch exists its lattices must be
+ * stepped only through it (lb_batch_step fails with LB_EINVAL otherwise);
+ * observables, export and rod reads work as usual.  The batch keeps its
+ * records in a caller-owned device workspace of lb_batch_workspace_bytes()
+ * bytes, which must outlive it.
+ */
+typedef struct lb_batch lb_batch;
+size_t lb_batch_workspace_bytes(lb_ctx *const *ctxs, int32_t n); /* 0 on bad input */
+/* Synchronises (uploads the work lists and records). */
+int lb_batch_create(lb_ctx *const *ctxs, int32_t n, void *workspace_dev, hipStream_t stream, lb_batch **out);
+/* nsteps steps of every lattice: the fused fluid step, then (with_rods != 0)
+ * the rod update.  use_graph != 0: pairs of steps run as one HIP graph,
+ * captured on first use on a stream of the batch's own and replayed on
+ * `stream` (the graph holds no memset or memcpy nodes).  Asynchronous. */
+int lb_batch_step(lb_batch *b, int32_t nsteps, int32_t with_rods, int32_t use_graph, hipStream_t stream);
+int lb_batch_destroy(lb_batch *b);
+
 /* Index (0 or 1) of the buffer holding the current state. */
 int lb_current_buffer(const lb_ctx *ctx);
 

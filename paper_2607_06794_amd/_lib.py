@@ -36,6 +36,10 @@ EXPORTS = (
     "lb_droplet_shape",
     "lb_deposit",
     "lb_rod_map",
+    "lb_batch_workspace_bytes",
+    "lb_batch_create",
+    "lb_batch_step",
+    "lb_batch_destroy",
 )
 
 
@@ -199,6 +203,14 @@ def load(path: str = LIB_PATH):
     lib.lb_deposit.restype = ct.c_int
     lib.lb_rod_map.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.lb_rod_map.restype = ct.c_int
+    lib.lb_batch_workspace_bytes.argtypes = [P(ct.c_void_p), ct.c_int32]
+    lib.lb_batch_workspace_bytes.restype = ct.c_size_t
+    lib.lb_batch_create.argtypes = [P(ct.c_void_p), ct.c_int32, ct.c_void_p, ct.c_void_p, P(ct.c_void_p)]
+    lib.lb_batch_create.restype = ct.c_int
+    lib.lb_batch_step.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]
+    lib.lb_batch_step.restype = ct.c_int
+    lib.lb_batch_destroy.argtypes = [ct.c_void_p]
+    lib.lb_batch_destroy.restype = ct.c_int
     lib.lb_abi_sizes.argtypes = [P(ct.c_size_t)]
     lib.lb_abi_sizes.restype = None
     sizes = (ct.c_size_t * len(STRUCTS))()

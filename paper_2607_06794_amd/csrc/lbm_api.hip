@@ -123,7 +123,7 @@ static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
 
 struct WsLayout {
     size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
-        nbr, nbr_cnt, obs, total;
+        nbr, nbr_cnt, rodargs, obs, total;
     int max_tiles;
 };
 
@@ -167,6 +167,8 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + nr * ROD_NBR * sizeof(int16_t));
     w.nbr_cnt = o;
     o = align256(o + nr * sizeof(int));
+    w.rodargs = o;
+    o = align256(o + (rods ? 2 * sizeof(RodArgs) : 0));
     w.obs = o;
     o = align256(o + obs_bytes(p));
     w.total = o;
@@ -267,6 +269,8 @@ struct lb_ctx {
     int *shell, *shell_cnt, *nbr_cnt;
     int16_t *nbr;
     char *obs;
+    RodArgs *rodargs_dev;      // rod records with f = f[0] and f = f[1]
+    RodArgs rodargs_host[2];
     double psi_host[32];
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
@@ -303,6 +307,7 @@ static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk) 
 static RodArgs rod_args(lb_ctx *c) {
     const lb_params &p = c->p;
     RodArgs a{};
+    a.f = c->f[c->cur];
     a.rods = c->rods;
     a.shell_cap = p.n_rods > 0 ? rod_shell_cap(p) : 0;
     a.nblk = p.n_rods > 0 ? rod_nblk(p) : 0;
@@ -431,6 +436,7 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->nbr = reinterpret_cast<int16_t *>(ws + w.nbr);
     c->nbr_cnt = reinterpret_cast<int *>(ws + w.nbr_cnt);
     c->obs = ws + w.obs;
+    c->rodargs_dev = reinterpret_cast<RodArgs *>(ws + w.rodargs);
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
             c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
@@ -475,7 +481,15 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
         if ((e = hipMemsetAsync(c->rodpart, 0, 3 * size_t(p->n_rods) * rod_nblk(*p) * ROD_PART * sizeof(double), stream)) !=
             hipSuccess)
             return cleanup(hip_fail(e, "clear rod partials"));
-        if ((e = launch_rods_place(p->prec, rod_args(c), c->f[0], stream)) != hipSuccess)
+        for (int q = 0; q < 2; ++q) {
+            c->rodargs_host[q] = rod_args(c);
+            c->rodargs_host[q].f = c->f[q];
+        }
+        if ((e = hipMemcpyAsync(c->rodargs_dev, c->rodargs_host, sizeof(c->rodargs_host), hipMemcpyHostToDevice,
+                                stream)) != hipSuccess)
+            return cleanup(hip_fail(e, "upload rod records"));
+        if ((e = launch_rods_place(p->prec, c->rodargs_host[0], RodBatch{c->rodargs_dev, nullptr}, stream)) !=
+            hipSuccess)
             return cleanup(hip_fail(e, "place rods"));
     }
     // the second buffer needs the same wall slots only after the first step
@@ -494,11 +508,14 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     return LB_OK;
 }
 
-int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
-    if (!c) return fail(LB_EINVAL, "null ctx");
-    if (nsteps < 0) return fail(LB_EINVAL, "negative step count");
+}  // extern "C"
+
+// step record of a context whose current state is in buffer cur
+static StepArgs step_args(const lb_ctx *c, int cur) {
     const lb_params &p = c->p;
     StepArgs a{};
+    a.fsrc = c->f[cur];
+    a.fdst = c->f[cur ^ 1];
     a.mat = c->mat;
     a.ledger_part = c->ledger;
     a.status = c->status;
@@ -523,17 +540,27 @@ int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
     a.G = p.G;
     for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
     a.psi_tab = c->psi;
-    const bool tau1 = (p.tau[0] == 1.0 && p.tau[1] == 1.0);
+    return a;
+}
+
+static bool is_tau1(const lb_params &p) { return p.tau[0] == 1.0 && p.tau[1] == 1.0; }
+
+extern "C" {
+
+int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
+    if (!c) return fail(LB_EINVAL, "null ctx");
+    if (nsteps < 0) return fail(LB_EINVAL, "negative step count");
+    const lb_params &p = c->p;
+    const bool tau1 = is_tau1(p);
     for (int s = 0; s < nsteps; ++s) {
-        a.fsrc = c->f[c->cur];
-        a.fdst = c->f[c->cur ^ 1];
-        hipError_t e = launch_sc_step(p.prec, tau1, c->tile, a, stream);
+        hipError_t e = launch_sc_step(p.prec, tau1, c->tile, step_args(c, c->cur), stream);
         if (e != hipSuccess) return hip_fail(e, "sc_step launch");
         c->cur ^= 1;
         c->steps++;
     }
     return LB_OK;
 }
+
 
 int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     if (!c || !out) return fail(LB_EINVAL, "null argument");
@@ -567,7 +594,7 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     out->solid[0] = rs[0];
     out->solid[1] = rs[1];
     for (int q = 0; q < 3; ++q) out->rod_momentum[q] = rs[2 + q];
-    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3, 8 rod)", st);
+    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3, 8 rod motion, 16 rod at a wall, 32 rod list)", st);
     return LB_OK;
 }
 
@@ -698,7 +725,9 @@ int lb_rod_map(lb_ctx *c, int32_t *map_host, hipStream_t stream) {
 int lb_rods_step(lb_ctx *c, hipStream_t stream) {
     if (!c) return fail(LB_EINVAL, "null ctx");
     if (c->p.n_rods == 0) return LB_OK;
-    HIP_TRY(launch_rods_step(c->p.prec, rod_args(c), c->f[c->cur], stream), "rods step");
+    HIP_TRY(launch_rods_step(c->p.prec, RodBatch{c->rodargs_dev + c->cur, nullptr}, 1, c->p.n_rods, rod_nblk(c->p),
+                             c->p.n_rods, stream),
+            "rods step");
     return LB_OK;
 }
 
@@ -772,6 +801,238 @@ int lb_current_buffer(const lb_ctx *c) { return c ? c->cur : -1; }
 
 int lb_destroy(lb_ctx *c) {
     delete c;
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches: many lattices advanced by shared launches
+// ---------------------------------------------------------------------------
+struct lb_batch {
+    struct Class {
+        TileCfg tile;
+        bool tau1;
+        int nwork;
+        int2 *work;  // device
+    };
+    std::vector<lb_ctx *> ctx;
+    std::vector<int> cur0;  // each lattice's current buffer when the batch was made
+    std::vector<Class> classes;
+    int prec = 0;
+    StepArgs *steps = nullptr;  // device [2][n]: records for batch parity 0 and 1
+    RodArgs *rods = nullptr;    // device [2][n]
+    int2 *rodmap = nullptr;     // device [total_rods]
+    int total_rods = 0, nblk_max = 0, max_rods = 0;
+    int par = 0;  // steps taken since creation, mod 2
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps from parity 0, without / with rods
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t steps, rods, rodmap, work, total;
+    std::vector<size_t> work_off;
+};
+
+bool same_tile(const TileCfg &a, const TileCfg &b) { return a.tile_y == b.tile_y && a.rows_per_thread == b.rows_per_thread; }
+
+// class of each lattice (tile shape and tau = 1 select the kernel instance)
+std::vector<int> batch_classes(lb_ctx *const *ctxs, int n, std::vector<lb_batch::Class> &cls,
+                               std::vector<int> &counts) {
+    std::vector<int> of(n);
+    for (int i = 0; i < n; ++i) {
+        const bool t1 = is_tau1(ctxs[i]->p);
+        int k = 0;
+        while (k < int(cls.size()) && !(same_tile(cls[k].tile, ctxs[i]->tile) && cls[k].tau1 == t1)) ++k;
+        if (k == int(cls.size())) {
+            cls.push_back(lb_batch::Class{ctxs[i]->tile, t1, 0, nullptr});
+            counts.push_back(0);
+        }
+        of[i] = k;
+        counts[k] += ctxs[i]->ntx * ctxs[i]->nty * ctxs[i]->nzc;
+    }
+    for (int &c : counts) c = (c + 7) / 8 * 8;  // padded to whole rounds of the eight XCDs
+    return of;
+}
+
+BatchLayout batch_layout(lb_ctx *const *ctxs, int n) {
+    BatchLayout l{};
+    std::vector<lb_batch::Class> cls;
+    std::vector<int> counts;
+    batch_classes(ctxs, n, cls, counts);
+    int total_rods = 0;
+    for (int i = 0; i < n; ++i) total_rods += ctxs[i]->p.n_rods;
+    size_t o = 0;
+    l.steps = o;
+    o = align256(o + 2 * size_t(n) * sizeof(StepArgs));
+    l.rods = o;
+    o = align256(o + 2 * size_t(n) * sizeof(RodArgs));
+    l.rodmap = o;
+    o = align256(o + size_t(total_rods) * sizeof(int2));
+    l.work = o;
+    for (int c : counts) {
+        l.work_off.push_back(o);
+        o = align256(o + size_t(c) * sizeof(int2));
+    }
+    l.total = o;
+    return l;
+}
+
+int batch_check(lb_ctx *const *ctxs, int n) {
+    if (!ctxs || n < 1) return fail(LB_EINVAL, "a batch needs at least one lattice");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(LB_EINVAL, "null lattice %d", i);
+        if (ctxs[i]->p.prec != ctxs[0]->p.prec) return fail(LB_EINVAL, "lattices of a batch share one precision");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(LB_EINVAL, "lattice %d appears twice", i);
+    }
+    return LB_OK;
+}
+
+hipError_t batch_enqueue(lb_batch *b, int par, bool rods, hipStream_t s) {
+    const int n = int(b->ctx.size());
+    for (const auto &c : b->classes) {
+        hipError_t e = launch_sc_step_batch(b->prec, c.tau1, c.tile, b->steps + size_t(par) * n, c.work, c.nwork, s);
+        if (e != hipSuccess) return e;
+    }
+    // the rod update acts on the state the fluid step just wrote: the records
+    // of the next parity
+    if (rods && b->total_rods > 0)
+        return launch_rods_step(b->prec, RodBatch{b->rods + size_t(par ^ 1) * n, b->rodmap}, n, b->total_rods,
+                                b->nblk_max, b->max_rods, s);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_batch_workspace_bytes(lb_ctx *const *ctxs, int32_t n) {
+    if (batch_check(ctxs, n) != LB_OK) return 0;
+    return batch_layout(ctxs, n).total;
+}
+
+int lb_batch_create(lb_ctx *const *ctxs, int32_t n, void *workspace, hipStream_t stream, lb_batch **out) {
+    if (!out) return fail(LB_EINVAL, "null out");
+    *out = nullptr;
+    int rc = batch_check(ctxs, n);
+    if (rc) return rc;
+    if (!workspace) return fail(LB_EINVAL, "null workspace");
+    const BatchLayout l = batch_layout(ctxs, n);
+    char *ws = static_cast<char *>(workspace);
+    auto *b = new (std::nothrow) lb_batch();
+    if (!b) return fail(LB_EINVAL, "out of host memory");
+    b->ctx.assign(ctxs, ctxs + n);
+    b->prec = ctxs[0]->p.prec;
+    std::vector<int> counts;
+    const std::vector<int> of = batch_classes(ctxs, n, b->classes, counts);
+    b->steps = reinterpret_cast<StepArgs *>(ws + l.steps);
+    b->rods = reinterpret_cast<RodArgs *>(ws + l.rods);
+    b->rodmap = reinterpret_cast<int2 *>(ws + l.rodmap);
+    // per-parity records
+    std::vector<StepArgs> sa(2 * size_t(n));
+    std::vector<RodArgs> ra(2 * size_t(n));
+    std::vector<int2> rmap;
+    for (int i = 0; i < n; ++i) {
+        lb_ctx *c = ctxs[i];
+        b->cur0.push_back(c->cur);
+        for (int q = 0; q < 2; ++q) {
+            sa[size_t(q) * n + i] = step_args(c, c->cur ^ q);
+            ra[size_t(q) * n + i] = rod_args(c);
+            ra[size_t(q) * n + i].f = c->f[c->cur ^ q];
+        }
+        for (int r = 0; r < c->p.n_rods; ++r) rmap.push_back(make_int2(i, r));
+        if (c->p.n_rods > 0) {
+            b->nblk_max = std::max(b->nblk_max, rod_nblk(c->p));
+            b->max_rods = std::max(b->max_rods, c->p.n_rods);
+        }
+    }
+    b->total_rods = int(rmap.size());
+    // work lists: each lattice's tiles in its own logical order, the lists of
+    // a class concatenated, padded to a multiple of 8 and permuted so that
+    // the round-robin dealing of work-groups gives XCD j the j-th eighth
+    std::vector<std::vector<int2>> logical(b->classes.size());
+    for (int i = 0; i < n; ++i) {
+        const int nb = ctxs[i]->ntx * ctxs[i]->nty * ctxs[i]->nzc;
+        for (int t = 0; t < nb; ++t) logical[of[i]].push_back(make_int2(i, t));
+    }
+    hipError_t e = hipSuccess;
+    std::vector<std::vector<int2>> hw(b->classes.size());
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        const int np = counts[k];
+        logical[k].resize(np, make_int2(-1, -1));
+        hw[k].resize(np);
+        for (int pidx = 0; pidx < np; ++pidx) hw[k][pidx] = logical[k][(pidx & 7) * (np >> 3) + (pidx >> 3)];
+        b->classes[k].nwork = np;
+        b->classes[k].work = reinterpret_cast<int2 *>(ws + l.work_off[k]);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->classes[k].work, hw[k].data(), np * sizeof(int2), hipMemcpyHostToDevice, stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->steps, sa.data(), sa.size() * sizeof(StepArgs), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->rods, ra.data(), ra.size() * sizeof(RodArgs), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !rmap.empty())
+        e = hipMemcpyAsync(b->rodmap, rmap.data(), rmap.size() * sizeof(int2), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host staging vectors end here
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch set-up");
+    }
+    *out = b;
+    return LB_OK;
+}
+
+int lb_batch_step(lb_batch *b, int32_t nsteps, int32_t with_rods, int32_t use_graph, hipStream_t stream) {
+    if (!b || nsteps < 0) return fail(LB_EINVAL, "bad batch step arguments");
+    const int n = int(b->ctx.size());
+    for (int i = 0; i < n; ++i)
+        if (b->ctx[i]->cur != (b->cur0[i] ^ b->par))
+            return fail(LB_EINVAL, "lattice %d was stepped outside its batch", i);
+    const bool rods = with_rods != 0;
+    int left = nsteps;
+    while (left > 0) {
+        if (use_graph && left >= 2 && b->par == 0) {
+            hipGraphExec_t &g = b->graph[rods ? 1 : 0];
+            if (!g) {
+                // capture two steps (parity 0 then 1) once; replays leave every
+                // lattice's buffer parity unchanged
+                hipGraph_t gr = nullptr;
+                HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+                hipError_t e1 = batch_enqueue(b, 0, rods, b->cap);
+                hipError_t e2 = e1 == hipSuccess ? batch_enqueue(b, 1, rods, b->cap) : e1;
+                hipError_t e3 = hipStreamEndCapture(b->cap, &gr);
+                if (e2 != hipSuccess) return hip_fail(e2, "capture batch step");
+                if (e3 != hipSuccess) return hip_fail(e3, "end capture");
+                hipError_t e4 = hipGraphInstantiate(&g, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e4 != hipSuccess) {
+                    g = nullptr;
+                    return hip_fail(e4, "instantiate batch graph");
+                }
+            }
+            HIP_TRY(hipGraphLaunch(g, stream), "launch batch graph");
+            left -= 2;
+        } else {
+            HIP_TRY(batch_enqueue(b, b->par, rods, stream), "batch step");
+            b->par ^= 1;
+            left -= 1;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        b->ctx[i]->cur ^= (nsteps & 1);
+        b->ctx[i]->steps += nsteps;
+    }
+    return LB_OK;
+}
+
+int lb_batch_destroy(lb_batch *b) {
+    if (!b) return LB_OK;
+    for (auto &g : b->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
     return LB_OK;
 }
 

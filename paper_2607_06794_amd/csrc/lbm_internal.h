@@ -48,6 +48,7 @@ constexpr int ROD_PART = 8;                                  // doubles per (rod
 constexpr int ROD_NBR = 64;                                  // neighbour-list entries per rod
 
 struct RodArgs {
+    void *f;  // current populations (post-collision state)
     double *rods;
     double *part_adh, *part_upd, *part_link;  // [n_rods][nblk][ROD_PART] partial sums
     int *shell;                               // [n_rods][shell_cap] surface-list node indices
@@ -68,11 +69,25 @@ struct RodArgs {
     double G, psi_rod[2], rho_ref[2];
 };
 
-hipError_t launch_rods_place(int prec, const RodArgs &a, void *f, hipStream_t s);
-hipError_t launch_rods_step(int prec, const RodArgs &a, void *f, hipStream_t s);
+// per-lattice rod records on the device; map: global rod -> (lattice, rod),
+// null for a single lattice (rod = global index)
+struct RodBatch {
+    const RodArgs *all;
+    const int2 *map;
+};
+// a: host copy of the single lattice's record (sizes, newid), bt its device copy
+hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s);
+// one rod update for every lattice of bt: n_lat lattices, total_rods rods,
+// nblk_max surface-list work-groups per rod and max_rods rods per lattice at most
+hipError_t launch_rods_step(int prec, const RodBatch &bt, int n_lat, int total_rods, int nblk_max, int max_rods,
+                            hipStream_t s);
 hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s);
 
 hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s);
+// all: device array of per-lattice step records; work: device list of
+// (lattice, logical tile) entries, (-1, -1) for padding
+hipError_t launch_sc_step_batch(int prec, bool tau1, const TileCfg &t, const StepArgs *all, const int2 *work, int nwork,
+                                hipStream_t s);
 int tiles_xy(int nx, int ny, int tile_y);
 
 // auxiliary kernels (aux.hip)

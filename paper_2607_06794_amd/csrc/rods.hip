@@ -209,6 +209,18 @@ __device__ inline double *part_slot(double *base, const RodArgs &a, int r, int b
     return base + (size_t(r) * a.nblk + b) * ROD_PART;
 }
 
+// record and local index of global rod g (one lattice when bt.map is null)
+__device__ inline RodArgs rod_of(const RodBatch &bt, int g, int &r) {
+    int lat = 0;
+    r = g;
+    if (bt.map) {
+        const int2 m = bt.map[g];
+        lat = m.x;
+        r = m.y;
+    }
+    return bt.all[lat];
+}
+
 __device__ inline double shell_r2(const RodArgs &a) { return (a.radius + 1.5) * (a.radius + 1.5); }
 
 // listed node of this thread: false if the entry is past the end of the list
@@ -228,9 +240,12 @@ __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, i
 //    invariant of the current post-collision state), torque about X at y
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodArgs a, const S *f) {
+__global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     __shared__ double sh[RB / 64];
-    const int r = blockIdx.y;
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.y, r);
+    if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    const S *f = static_cast<const S *>(a.f);
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -285,8 +300,10 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodArgs a, const S *f)
 //     a rod moves less than 0.9 per step, so a pair farther apart than
 //     r_int + 2 at the start stays out of range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) rod_pairs_kernel(RodArgs a) {
-    const int r = blockIdx.x, lane = threadIdx.x;
+__global__ void __launch_bounds__(64) rod_pairs_kernel(RodBatch bt) {
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.x, r);
+    const int lane = threadIdx.x;
     double *rod = a.rods + r * ROD_STRIDE;
     {
         double ls[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ad[6] = {0, 0, 0, 0, 0, 0};
@@ -354,8 +371,9 @@ __global__ void __launch_bounds__(64) rod_pairs_kernel(RodArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int RS_X = 0, RS_Q = 3, RS_N = 7;  // shared-memory record per rod
 
-__global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodArgs a) {
+__global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt) {
     extern __shared__ double rs[];  // [n_rods][RS_N]
+    const RodArgs a = bt.all[blockIdx.x];  // one work-group per lattice
     const int nr = a.n_rods, me = threadIdx.x;
     const bool mine = me < nr;
     const double dt = 1.0 / a.n_sub;
@@ -459,9 +477,11 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodArgs a) {
 // 3. re-mask: new occupancy of every rod (newid is -1 everywhere on entry) and
 //    the rod's surface list; one work-group per rod
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(MB) rod_mask_kernel(RodArgs a) {
+__global__ void __launch_bounds__(MB) rod_mask_kernel(RodBatch bt) {
     __shared__ int wcount[MB / 64];
-    const int r = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.x, r);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double *rod = a.rods + r * ROD_STRIDE;
     const Box b = rod_box(rod, a, 2);
     const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
@@ -520,12 +540,15 @@ __global__ void fill_i32_kernel(int *p, int64_t n, int v) {
 //    the finding thread then adds the transfer to its own sums.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void __launch_bounds__(RB) rod_update_kernel(RodArgs a, S *f, int init) {
+__global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     __shared__ double sh[RB / 64];
     __shared__ int wcount[RB / 64];
     __shared__ int64_t un_node[RB];
     __shared__ double un_out[RB][8];
-    const int r = blockIdx.y;
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.y, r);
+    if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    S *f = static_cast<S *>(a.f);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
@@ -645,8 +668,10 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodArgs a, S *f, int ini
 
 // commit the new occupancy of rod r (after every work-group has read the old
 // one); work-group (0, r) also applies rod r's cover/uncover transfers
-__global__ void __launch_bounds__(RB) rod_commit_kernel(RodArgs a) {
-    const int r = blockIdx.y;
+__global__ void __launch_bounds__(RB) rod_commit_kernel(RodBatch bt) {
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.y, r);
+    if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
     double *rod = a.rods + r * ROD_STRIDE;
     if (blockIdx.x == 0 && threadIdx.x < 64) {
         double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -689,9 +714,12 @@ __global__ void rod_sums_kernel(RodArgs a, double *out) {
 //    also returns rod r's entries of newid to -1 for the next re-mask
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void __launch_bounds__(RB) rod_link_kernel(RodArgs a, S *f) {
+__global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
     __shared__ double sh[RB / 64];
-    const int r = blockIdx.y;
+    int r;
+    const RodArgs a = rod_of(bt, blockIdx.y, r);
+    if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    S *f = static_cast<S *>(a.f);
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // dP[3], dT[3], mass[2]
@@ -786,17 +814,17 @@ static int fill_grid(int64_t n) {
     return int(g > 8192 ? 8192 : (g < 1 ? 1 : g));
 }
 
-hipError_t launch_rods_place(int prec, const RodArgs &a, void *f, hipStream_t s) {
+hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s) {
     if (a.n_rods == 0) return hipSuccess;
     const int64_t n = int64_t(a.nx) * a.ny * a.nz;
     const dim3 grid(a.nblk, a.n_rods);
     hipLaunchKernelGGL(fill_i32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, -1);
-    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, a);
+    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, bt);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f), 1);
-        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, a);
-        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f));
+        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 1);
+        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
         return hipGetLastError();
     });
 }
@@ -806,19 +834,20 @@ hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rods_step(int prec, const RodArgs &a, void *f, hipStream_t s) {
-    if (a.n_rods == 0) return hipSuccess;
-    const dim3 grid(a.nblk, a.n_rods);
+hipError_t launch_rods_step(int prec, const RodBatch &bt, int n_lat, int total_rods, int nblk_max, int max_rods,
+                            hipStream_t s) {
+    if (total_rods == 0) return hipSuccess;
+    const dim3 grid(nblk_max, total_rods);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_adhesion_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<const S *>(f));
-        hipLaunchKernelGGL(rod_pairs_kernel, dim3(a.n_rods), dim3(64), 0, s, a);
-        hipLaunchKernelGGL(rod_integrate_kernel, dim3(1), dim3(LB_MAX_RODS), size_t(a.n_rods) * RS_N * sizeof(double), s,
-                           a);
-        hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, a);
-        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f), 0);
-        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, a);
-        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, a, static_cast<S *>(f));
+        hipLaunchKernelGGL(rod_adhesion_kernel<S>, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL(rod_pairs_kernel, dim3(total_rods), dim3(64), 0, s, bt);
+        hipLaunchKernelGGL(rod_integrate_kernel, dim3(n_lat), dim3(LB_MAX_RODS), size_t(max_rods) * RS_N * sizeof(double),
+                           s, bt);
+        hipLaunchKernelGGL(rod_mask_kernel, dim3(total_rods), dim3(MB), 0, s, bt);
+        hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 0);
+        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
         return hipGetLastError();
     });
 }

@@ -144,8 +144,11 @@ __device__ inline C wave_sum(C v) {
 
 }  // namespace
 
+// One work-group's tile: logical tile b of a lattice whose step runs as nblk
+// work-groups.  remap: b is a hardware dispatch index to be spread over the
+// XCDs (else b is already the logical tile).
 template <class S, int TY, int NPT, bool TAU1>
-__global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
+__device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk, bool remap) {
     using C = typename Codec<S>::C;
     constexpr int TX = 64;
     constexpr int RY = TY / NPT;
@@ -168,9 +171,7 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
     // round-robin; the remap gives each XCD a contiguous range of logical
     // tiles, ordered z-chunk fastest, so an XCD owns whole xy columns and
     // neighbouring columns (their shared ring reads then hit its L2).
-    const int nblk = gridDim.x;
-    int b = blockIdx.x;
-    if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    if (remap && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
     const int tz = b % a.nzc;
     const int tx = (b / a.nzc) % a.ntx;
     const int ty = b / (a.nzc * a.ntx);
@@ -589,6 +590,24 @@ __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
     }
 }
 
+template <class S, int TY, int NPT, bool TAU1>
+__global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
+    sc_step_tile<S, TY, NPT, TAU1>(a, blockIdx.x, gridDim.x, true);
+}
+
+// Batched step: one launch walks a device work list of (lattice, logical
+// tile) entries over many lattices of one tile class, each with its own
+// parameter record.  The list is ordered so that the hardware's round-robin
+// dealing of work-groups to XCDs gives each XCD a contiguous range of it.
+template <class S, int TY, int NPT, bool TAU1>
+__global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_batch_kernel(const StepArgs *__restrict__ all,
+                                                                         const int2 *__restrict__ work) {
+    const int2 w = work[blockIdx.x];
+    if (w.x < 0) return;  // padding entry, uniform per block
+    const StepArgs a = all[w.x];
+    sc_step_tile<S, TY, NPT, TAU1>(a, w.y, a.ntx * a.nty * a.nzc, false);
+}
+
 int tiles_xy(int nx, int ny, int tile_y) { return ((nx + 63) / 64) * ((ny + tile_y - 1) / tile_y); }
 
 template <class S, int TY, int NPT, bool TAU1>
@@ -608,6 +627,43 @@ static hipError_t launch_prec(const TileCfg &t, const StepArgs &a, hipStream_t s
         if (t.tile_y == 16 && t.rows_per_thread == 2) return launch_one<S, 16, 2, TAU1>(a, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <class S, int TY, int NPT, bool TAU1>
+static hipError_t launch_batch_one(const StepArgs *all, const int2 *work, int nwork, hipStream_t s) {
+    hipLaunchKernelGGL((sc_step_batch_kernel<S, TY, NPT, TAU1>), dim3(nwork), dim3(64 * (TY / NPT)), 0, s, all, work);
+    return hipGetLastError();
+}
+
+template <class S, bool TAU1>
+static hipError_t launch_batch_prec(const TileCfg &t, const StepArgs *all, const int2 *work, int nwork, hipStream_t s) {
+    if (t.tile_y == 4 && t.rows_per_thread == 1) return launch_batch_one<S, 4, 1, TAU1>(all, work, nwork, s);
+    if (t.tile_y == 8 && t.rows_per_thread == 1) return launch_batch_one<S, 8, 1, TAU1>(all, work, nwork, s);
+    if constexpr (TAU1) {
+        if (t.tile_y == 8 && t.rows_per_thread == 2) return launch_batch_one<S, 8, 2, TAU1>(all, work, nwork, s);
+        if (t.tile_y == 16 && t.rows_per_thread == 2) return launch_batch_one<S, 16, 2, TAU1>(all, work, nwork, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sc_step_batch(int prec, bool tau1, const TileCfg &t, const StepArgs *all, const int2 *work, int nwork,
+                                hipStream_t s) {
+    switch (prec) {
+        case LB_F64:
+            return tau1 ? launch_batch_prec<double, true>(t, all, work, nwork, s)
+                        : launch_batch_prec<double, false>(t, all, work, nwork, s);
+        case LB_F32:
+            return tau1 ? launch_batch_prec<float, true>(t, all, work, nwork, s)
+                        : launch_batch_prec<float, false>(t, all, work, nwork, s);
+        case LB_F16DEV:
+            return tau1 ? launch_batch_prec<_Float16, true>(t, all, work, nwork, s)
+                        : launch_batch_prec<_Float16, false>(t, all, work, nwork, s);
+        case LB_BF16DEV:
+            return tau1 ? launch_batch_prec<bf16_t, true>(t, all, work, nwork, s)
+                        : launch_batch_prec<bf16_t, false>(t, all, work, nwork, s);
+        default:
+            return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s) {

@@ -281,3 +281,43 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many lattices advanced by shared launches (the library's lb_batch).
+
+    The lattices keep their own state; while the batch exists, step them only
+    through it.  Results equal stepping each lattice alone.
+    """
+
+    def __init__(self, lattices, stream=None):
+        import torch
+
+        self.lattices = list(lattices)
+        self.lib = _lib.load()
+        self.device = self.lattices[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = len(self.lattices)
+        arr = (ct.c_void_p * n)(*[lat._ctx for lat in self.lattices])
+        nbytes = self.lib.lb_batch_workspace_bytes(arr, n)
+        if nbytes == 0:
+            _lib.check(_lib.LB_EINVAL)
+        self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._b = ct.c_void_p()
+        _lib.check(self.lib.lb_batch_create(arr, n, ct.c_void_p(self._ws.data_ptr()), _stream_ptr(self.stream),
+                                            ct.byref(self._b)))
+
+    def step(self, n: int = 1, rods: bool = True, graph: bool = True):
+        _lib.check(self.lib.lb_batch_step(self._b, int(n), int(bool(rods)), int(bool(graph)), _stream_ptr(self.stream)))
+        return self
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self.lib.lb_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
