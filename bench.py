@@ -113,6 +113,92 @@ def time_step(case, prec, steps, warmup, tile, autotune, rods=None, segment=0):
     return total_ms / steps, fused_ms / steps, n_fluid, obs, chosen, nseg
 
 
+def batched_form(steps, warmup, n_lattices=64):
+    """Many-droplet sweep: every lattice stepped alone, one after another, against
+    the batched step (one launch per tile class and per rod pass) with and
+    without the HIP graph, fluid-only and coupled (with rods).  Each coupled
+    variant starts from freshly initialised lattices (rods placed anywhere in
+    the fluid degrade the state within a few hundred steps)."""
+    import torch
+
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd.sim import Batch, Lattice
+    from tests import cases
+
+    specs = list(inputs.sweep_droplets(n_lattices))
+    tuned = {}
+
+    def make():
+        lats = []
+        for d in specs:
+            c = dict(shape=d["shape"], periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+                     body_force=(0.0, 0.0, 0.0))
+            lp = rod_params(cases.lattice_params(c, "f32"), length=d["rod_length"])
+            lp.eps_att = d["eps_att"]
+            lat = Lattice(lp, d["rho"], d["mat"], rods=d["rods"])
+            key = d["shape"]
+            if key not in tuned:
+                # tile shape per grid class from the autotuner (its trial steps
+                # are fluid steps of the first lattice of the class)
+                t = lat.autotune(trial_steps=5, cache=os.path.join(ROOT, "gpurun_out", "tiles.json"))
+                tuned[key] = (t["tile_y"], t["rows_per_thread"], t["zchunk"])
+                lat.close()
+                lat = Lattice(lp, d["rho"], d["mat"], rods=d["rods"])
+            lat.set_tiles(*tuned[key])
+            lats.append(lat)
+        torch.cuda.synchronize()
+        return lats
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(n)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def solo(lats, rods):
+        def run(n):
+            for _ in range(n):
+                for lat in lats:
+                    lat.step(1)
+                    if rods:
+                        lat.rods_step()
+        return run
+
+    n_fluid = sum(int((d["mat"] == 0).sum()) for d in specs)
+    out = {"lattices": len(specs), "fluid_nodes": n_fluid,
+           "rods": int(sum(0 if d["rods"] is None else len(d["rods"]) for d in specs))}
+    for rods in (False, True):
+        res = {}
+        for variant in ("solo", "batched", "graph"):
+            lats = make()
+            if variant == "solo":
+                ms = timed(solo(lats, rods), steps)
+            else:
+                batch = Batch(lats, stream=stream)
+                ms = timed(lambda n: batch.step(n, rods=rods, graph=(variant == "graph")), steps)
+                batch.close()
+            st = 0
+            for lat in lats:
+                st |= int(lat.observables(allow_unstable=True)["status"])
+                lat.close()
+            res[variant] = (ms, st)
+        key = "coupled" if rods else "fluid"
+        out[key] = {f"ms_per_step_{v}": res[v][0] for v in res}
+        out[key].update({f"mlups_{v}": n_fluid / (res[v][0] * 1e-3) / 1e6 for v in res})
+        out[key]["speedup_vs_solo"] = res["solo"][0] / min(res["batched"][0], res["graph"][0])
+        out[key]["status"] = {v: res[v][1] for v in res}
+        log(f"[bench] batched {key}: solo {res['solo'][0]:.2f} ms, batched {res['batched'][0]:.2f} ms, "
+            f"graph {res['graph'][0]:.2f} ms per step")
+    out["grid_classes"] = {f"{k[2]}x{k[1]}x{k[0]}": v for k, v in tuned.items()}
+    return out
+
+
 def cpu_baseline(case, sample_steps):
     from oracle import lbm
     from tests import cases
@@ -138,6 +224,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU baseline sample (0: skip)")
     ap.add_argument("--rods", type=int, default=200, help="rods requested (stress placement)")
     ap.add_argument("--forms", type=int, default=1, help="also time the FP16/BF16 storage forms")
+    ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
+    ap.add_argument("--batched-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -187,6 +275,11 @@ def main():
             log(f"[bench] form {prec}: {msk * 1e3:.1f} us, {forms[prec]['mlups']:.0f} MLUPS, "
                 f"x{forms[prec]['speedup_vs_f32']:.2f} vs f32")
 
+    batched = None
+    if args.batched > 0:
+        log(f"[bench] batched form: {args.batched} droplets of the sweep")
+        batched = batched_form(args.batched_steps, 2, args.batched)
+
     cpu = None
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps of the same lattice")
@@ -224,6 +317,7 @@ def main():
             "rod_time_share": max(0.0, 1.0 - ms_fused / ms),
         },
         "forms": forms,
+        "batched": batched,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

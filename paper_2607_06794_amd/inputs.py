@@ -207,3 +207,36 @@ def cap_inside(spec: CapSpec):
         return z >= 1.0 and ((x - cx) / a) ** 2 + ((y - cy) / b) ** 2 + ((z - 0.5) / spec.height) ** 2 <= 1.0
 
     return inside
+
+
+def sweep_droplets(n=64, seed0=4000, rods=True):
+    """Parameter sweep of sessile caps of uneven size (many-droplet batches).
+
+    Droplet i (seed seed0 + i): NX from (128, 160, 192, 224, 256) in turn,
+    NY = NX / 2, NZ = 48 + 16 (NX - 128) / 128; from PCG64(seed0 + i), in
+    this order: footprint aspect ratio U[1, 4], rod length from (12, 24, 48),
+    cohesion depth from (0, 5e-5, 1e-4, 2e-4), rod count U{50..400}.  The cap
+    spans 0.6 NX along x and 0.6 NX / aspect (at most 0.8 NY) along y with
+    height 0.375 NZ, on a stripe of 0.625 NX x 0.3125 NY (the proportions of
+    the 256 x 128 x 64 case).  Rods: the drawn count placed anywhere in the
+    fluid (stress placement, place_rods with inside=None, seed seed0 + 500 + i,
+    3 trials per requested rod).  Yields dicts with shape, rho, mat, rods,
+    rod_length, eps_att.
+    """
+    for i in range(n):
+        nx = (128, 160, 192, 224, 256)[i % 5]
+        ny, nz = nx // 2, 48 + 16 * (nx - 128) // 128
+        rng = _rng(seed0 + i)
+        ar = rng.uniform(1.0, 4.0)
+        length = (12.0, 24.0, 48.0)[int(rng.integers(3))]
+        eps = (0.0, 5e-5, 1e-4, 2e-4)[int(rng.integers(4))]
+        n_rods = int(rng.integers(50, 401))
+        fx = 0.6 * nx
+        spec = CapSpec(shape=(nz, ny, nx), footprint=(fx, min(fx / ar, 0.8 * ny)), height=0.375 * nz,
+                       stripe=(0.625 * nx, 0.3125 * ny), seed=seed0 + i)
+        rho, mat = sessile_cap(spec)
+        r = None
+        if rods:
+            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=None, seed=seed0 + 500 + i,
+                           max_trials=3 * n_rods)
+        yield dict(shape=(nz, ny, nx), rho=rho, mat=mat, rods=r, rod_length=length, eps_att=eps, aspect=ar)
