@@ -216,12 +216,12 @@ def sweep_droplets(n=64, seed0=4000, rods=True):
     NY = NX / 2, NZ = 48 + 16 (NX - 128) / 128; from PCG64(seed0 + i), in
     this order: footprint aspect ratio U[1, 4], rod length from (12, 24, 48),
     cohesion depth from (0, 5e-5, 1e-4, 2e-4), rod count U{50..400}.  The cap
-    spans 0.6 NX along x and 0.6 NX / aspect (at most 0.8 NY) along y with
-    height 0.375 NZ, on a stripe of 0.625 NX x 0.3125 NY (the proportions of
-    the 256 x 128 x 64 case).  Rods: the drawn count placed anywhere in the
-    fluid (stress placement, place_rods with inside=None, seed seed0 + 500 + i,
-    3 trials per requested rod).  Yields dicts with shape, rho, mat, rods,
-    rod_length, eps_att.
+    footprint is 0.6 NX long (x) and 0.6 NX / aspect wide (y), its height
+    min(0.4 NZ, 0.66 width); the stripe is the footprint plus 10 nodes on
+    every side (clipped to the lattice).  Rods: the drawn count placed
+    anywhere in the fluid (stress placement, place_rods with inside=None,
+    seed seed0 + 500 + i, 3 trials per requested rod).  Yields dicts with
+    shape, rho, mat, rods, rod_length, eps_att, aspect.
     """
     for i in range(n):
         nx = (128, 160, 192, 224, 256)[i % 5]
@@ -232,8 +232,9 @@ def sweep_droplets(n=64, seed0=4000, rods=True):
         eps = (0.0, 5e-5, 1e-4, 2e-4)[int(rng.integers(4))]
         n_rods = int(rng.integers(50, 401))
         fx = 0.6 * nx
-        spec = CapSpec(shape=(nz, ny, nx), footprint=(fx, min(fx / ar, 0.8 * ny)), height=0.375 * nz,
-                       stripe=(0.625 * nx, 0.3125 * ny), seed=seed0 + i)
+        fy = fx / ar
+        spec = CapSpec(shape=(nz, ny, nx), footprint=(fx, fy), height=min(0.4 * nz, 0.66 * fy),
+                       stripe=(min(fx + 20.0, nx), min(fy + 20.0, ny)), seed=seed0 + i)
         rho, mat = sessile_cap(spec)
         r = None
         if rods:
