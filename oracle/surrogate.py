@@ -1,0 +1,311 @@
+"""FP64 oracle of the learned surrogate: restriction, prolongation, 3-D
+convolutions with their gradients, the U-Net and Adam.
+
+TEST INFRASTRUCTURE ONLY -- never imported by the product path.
+
+What it follows (the benchmark spec form (4): a small 3-D convolutional encoder-decoder
+advancing coarse-grained fields of the lattice Boltzmann state; the paper
+itself has no surrogate):
+* restriction: 2 x 2 x 2 block means onto a coarse canvas of the channels
+  rho_A, rho_B, u_x, u_y, u_z (means over the block's fluid nodes, with
+  u = sum_k sum_i f*_i c_i / sum_k rho_k of the stored state), the rod volume
+  fraction (rod nodes / 8) and a domain mask (1 inside the lattice); canvas
+  cells outside a smaller lattice hold gas (rho_A 0.03, rho_B 1), zero
+  velocity and mask 0;
+* prolongation: trilinear interpolation of rho_A, rho_B, u at fine node x from
+  coarse coordinate x / 2 - 1/4 (clamped to the lattice's own coarse extent),
+  then f_i^k = f_i^eq(rho_k, u) (Eq. 2) at fluid nodes;
+* convolution: y[p, o] = b[o] + sum_{t, c} x[p + o_t, c] w[t, c, o] over the
+  27 taps o_t in {-1, 0, 1}^3 with zero padding, channels-last tensors;
+  input gradient dx[q, c] = sum_{t, o} g[q - o_t, o] w[t, c, o]; weight
+  gradient dw[t, c, o] = sum_p x[p + o_t, c] g[p, o]; bias gradient sum_p g;
+* U-Net with four levels (32, 64, 128, 128 channels), two ReLU convolutions
+  per level, 2 x 2 x 2 average pooling down, nearest-neighbour upsampling and
+  channel concatenation of the skip on the way up, a final linear
+  convolution to the six predicted channels added to the input (residual);
+* loss: masked mean squared error over the six channels plus lambda times the
+  squared relative mass error of rho_A;
+* Adam (Kingma and Ba) with bias correction.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lbm
+
+GAS = (0.03, 1.0)
+TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+# ---------------------------------------------------------------------------
+# restriction / prolongation
+# ---------------------------------------------------------------------------
+def restrict(f, material, canvas):
+    """Coarse canvas [D, H, W, 7] (FP64) of a lattice state f[2, 19, nz, ny, nx]."""
+    D, H, W = canvas
+    nz, ny, nx = material.shape
+    fluid = material == lbm.FLUID
+    rho = np.where(fluid, f.sum(axis=1), 0.0)  # [2, nz, ny, nx]
+    C = lbm.C.astype(np.float64)
+    mom = np.einsum("kizyx,id->dzyx", f, C)
+    mom = np.where(fluid[None], mom, 0.0)
+    out = np.zeros((D, H, W, 7))
+    out[..., 0], out[..., 1] = GAS
+    for cz in range(D):
+        for cy in range(H):
+            for cx in range(W):
+                z0, y0, x0 = 2 * cz, 2 * cy, 2 * cx
+                if z0 + 1 >= nz or y0 + 1 >= ny or x0 + 1 >= nx:
+                    continue  # outside the lattice: gas, mask 0
+                blk = (slice(z0, z0 + 2), slice(y0, y0 + 2), slice(x0, x0 + 2))
+                nf = int(fluid[blk].sum())
+                cell = np.zeros(7)
+                if nf:
+                    r = rho[(slice(None),) + blk].reshape(2, -1).sum(axis=1)
+                    m = mom[(slice(None),) + blk].reshape(3, -1).sum(axis=1)
+                    cell[0:2] = r / nf
+                    tot = r.sum()
+                    cell[2:5] = m / tot if tot > 0 else 0.0
+                cell[5] = float((material[blk] == lbm.ROD).sum()) / 8.0
+                cell[6] = 1.0
+                out[cz, cy, cx] = cell
+    return out
+
+
+def _lerp_axis(n_fine, n_coarse):
+    """Per fine index x: (lower coarse index, upper, weight of upper) for x/2 - 1/4."""
+    lo, hi, wt = [], [], []
+    for x in range(n_fine):
+        c = x / 2.0 - 0.25
+        c = min(max(c, 0.0), n_coarse - 1.0)
+        i0 = int(np.floor(c))
+        i1 = min(i0 + 1, n_coarse - 1)
+        lo.append(i0)
+        hi.append(i1)
+        wt.append(c - i0)
+    return np.array(lo), np.array(hi), np.array(wt)
+
+
+def prolong(coarse, material):
+    """Fine (rho[2], u[3]) on the lattice from coarse [D, H, W, >=5] fields; the
+    lattice occupies coarse cells [0, n/2) per axis."""
+    nz, ny, nx = material.shape
+    cz, cy, cx = nz // 2, ny // 2, nx // 2
+    a = coarse[:cz, :cy, :cx, :5]
+    lz, hz, wz = _lerp_axis(nz, cz)
+    ly, hy, wy = _lerp_axis(ny, cy)
+    lx, hx, wx = _lerp_axis(nx, cx)
+    out = np.zeros((nz, ny, nx, 5))
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                acc = np.zeros(5)
+                for iz, fz in ((lz[z], 1 - wz[z]), (hz[z], wz[z])):
+                    for iy, fy in ((ly[y], 1 - wy[y]), (hy[y], wy[y])):
+                        for ix, fx in ((lx[x], 1 - wx[x]), (hx[x], wx[x])):
+                            acc += fz * fy * fx * a[iz, iy, ix]
+                out[z, y, x] = acc
+    rho = np.moveaxis(out[..., 0:2], -1, 0)
+    u = np.moveaxis(out[..., 2:5], -1, 0)
+    return rho, u
+
+
+def lift(coarse, material):
+    """Post-collision state f = f^eq(rho_k, u) (Eq. 2) at fluid nodes, 0 elsewhere."""
+    rho, u = prolong(coarse, material)
+    fluid = material == lbm.FLUID
+    f = np.stack([lbm.equilibrium(rho[k], u) for k in range(2)])
+    return np.where(fluid[None, None], f, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# convolution and its gradients (channels last: x[D, H, W, C])
+# ---------------------------------------------------------------------------
+def _shifted(x, off):
+    """x[p + off] with zero padding."""
+    D, H, W = x.shape[:3]
+    out = np.zeros_like(x)
+    dz, dy, dx = off
+    zs = slice(max(0, -dz), min(D, D - dz))
+    ys = slice(max(0, -dy), min(H, H - dy))
+    xs = slice(max(0, -dx), min(W, W - dx))
+    zt = slice(max(0, dz), min(D, D + dz))
+    yt = slice(max(0, dy), min(H, H + dy))
+    xt = slice(max(0, dx), min(W, W + dx))
+    out[zs, ys, xs] = x[zt, yt, xt]
+    return out
+
+
+def conv3d(x, w, b=None):
+    """x [D, H, W, Cin], w [27, Cin, Cout] (tap index (dz+1)*9 + (dy+1)*3 + dx+1)."""
+    y = np.zeros(x.shape[:3] + (w.shape[2],))
+    for t, off in enumerate(TAPS):
+        y += _shifted(x, off) @ w[t]
+    if b is not None:
+        y += b
+    return y
+
+
+def conv3d_dgrad(g, w):
+    dx = np.zeros(g.shape[:3] + (w.shape[1],))
+    for t, off in enumerate(TAPS):
+        dx += _shifted(g, tuple(-o for o in off)) @ w[t].T
+    return dx
+
+
+def conv3d_wgrad(x, g):
+    cin, cout = x.shape[3], g.shape[3]
+    dw = np.zeros((27, cin, cout))
+    gm = g.reshape(-1, cout)
+    for t, off in enumerate(TAPS):
+        dw[t] = _shifted(x, off).reshape(-1, cin).T @ gm
+    return dw, gm.sum(axis=0)
+
+
+def conv3d_direct(x, w, b):
+    """Seven nested loops, for tiny shapes (pins the tap convention)."""
+    D, H, W, cin = x.shape
+    cout = w.shape[2]
+    y = np.zeros((D, H, W, cout))
+    for z in range(D):
+        for yy in range(H):
+            for xx in range(W):
+                for o in range(cout):
+                    s = b[o]
+                    for t, (dz, dy, dx) in enumerate(TAPS):
+                        qz, qy, qx = z + dz, yy + dy, xx + dx
+                        if 0 <= qz < D and 0 <= qy < H and 0 <= qx < W:
+                            for c in range(cin):
+                                s += x[qz, qy, qx, c] * w[t, c, o]
+                    y[z, yy, xx, o] = s
+    return y
+
+
+def pool2(x):
+    D, H, W, C = x.shape
+    return x.reshape(D // 2, 2, H // 2, 2, W // 2, 2, C).mean(axis=(1, 3, 5))
+
+
+def pool2_back(g):
+    return np.repeat(np.repeat(np.repeat(g, 2, 0), 2, 1), 2, 2) / 8.0
+
+
+def up2(x):
+    return np.repeat(np.repeat(np.repeat(x, 2, 0), 2, 1), 2, 2)
+
+
+def up2_back(g):
+    D, H, W, C = g.shape
+    return g.reshape(D // 2, 2, H // 2, 2, W // 2, 2, C).sum(axis=(1, 3, 5))
+
+
+# ---------------------------------------------------------------------------
+# U-Net
+# ---------------------------------------------------------------------------
+CH = (32, 64, 128, 128)
+IN_CH, OUT_CH = 7, 6
+
+
+def layer_shapes(cin=IN_CH, ch=CH, cout=OUT_CH):
+    """(name, Cin, Cout) of every convolution, in forward order."""
+    L = []
+    c = cin
+    for lvl, co in enumerate(ch):
+        L.append((f"enc{lvl}a", c, co))
+        L.append((f"enc{lvl}b", co, co))
+        c = co
+    for lvl in range(len(ch) - 2, -1, -1):
+        L.append((f"dec{lvl}a", c + ch[lvl], ch[lvl]))
+        L.append((f"dec{lvl}b", ch[lvl], ch[lvl]))
+        c = ch[lvl]
+    L.append(("out", c, cout))
+    return L
+
+
+def init_params(seed, cin=IN_CH, ch=CH, cout=OUT_CH):
+    """He-normal weights (std sqrt(2 / (27 Cin))), zero biases; the output layer
+    starts at zero so the untrained network is the persistence baseline."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = {}
+    for name, ci, co in layer_shapes(cin, ch, cout):
+        std = 0.0 if name == "out" else np.sqrt(2.0 / (27 * ci))
+        P[name] = (rng.normal(0.0, 1.0, (27, ci, co)) * std, np.zeros(co))
+    return P
+
+
+def unet_forward(x, P, ch=CH):
+    """x [D, H, W, 7] -> (prediction [D, H, W, 6], cache)."""
+    cache = {"x": x}
+    h = x
+    skips = []
+    nlev = len(ch)
+    for lvl in range(nlev):
+        for s in "ab":
+            name = f"enc{lvl}{s}"
+            cache[name + ":in"] = h
+            h = np.maximum(conv3d(h, *P[name]), 0.0)
+            cache[name + ":out"] = h
+        if lvl < nlev - 1:
+            skips.append(h)
+            h = pool2(h)
+    for lvl in range(nlev - 2, -1, -1):
+        h = np.concatenate([up2(h), skips[lvl]], axis=-1)
+        for s in "ab":
+            name = f"dec{lvl}{s}"
+            cache[name + ":in"] = h
+            h = np.maximum(conv3d(h, *P[name]), 0.0)
+            cache[name + ":out"] = h
+    cache["out:in"] = h
+    y = conv3d(h, *P["out"])
+    return x[..., :OUT_CH] + y, cache
+
+
+def unet_backward(gy, P, cache, ch=CH):
+    """Gradients of every parameter for dL/dprediction = gy."""
+    G = {}
+    dw, db = conv3d_wgrad(cache["out:in"], gy)
+    G["out"] = (dw, db)
+    gh = conv3d_dgrad(gy, P["out"][0])
+    nlev = len(ch)
+    gskip = [None] * (nlev - 1)
+    for lvl in range(0, nlev - 1):
+        for s in "ba":
+            name = f"dec{lvl}{s}"
+            g = gh * (cache[name + ":out"] > 0)
+            G[name] = conv3d_wgrad(cache[name + ":in"], g)
+            gh = conv3d_dgrad(g, P[name][0])
+        cu = gh.shape[-1] - ch[lvl]
+        gskip[lvl] = gh[..., cu:]
+        gh = up2_back(gh[..., :cu])
+    for lvl in range(nlev - 1, -1, -1):
+        if lvl < nlev - 1:
+            gh = pool2_back(gh) + gskip[lvl]
+        for s in "ba":
+            name = f"enc{lvl}{s}"
+            g = gh * (cache[name + ":out"] > 0)
+            G[name] = conv3d_wgrad(cache[name + ":in"], g)
+            gh = conv3d_dgrad(g, P[name][0])
+    return G
+
+
+def loss(pred, target, mask, lam):
+    """Masked MSE over the six channels + lam * (relative rho_A mass error)^2,
+    and its gradient with respect to pred."""
+    m = mask[..., None]
+    n = mask.sum()
+    diff = (pred - target) * m
+    mse = float((diff * diff).sum() / (OUT_CH * n))
+    mt = float((mask * target[..., 0]).sum())
+    me = float((mask * (pred[..., 0] - target[..., 0])).sum()) / mt
+    g = 2.0 * diff / (OUT_CH * n)
+    g[..., 0] += 2.0 * lam * me * mask / mt
+    return mse + lam * me * me, g
+
+
+def adam(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (step counts from 1); returns (p, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -1,0 +1,187 @@
+"""Pins of the surrogate oracle: brute force, library convolution and autograd
+(PyTorch CPU, FP64), finite differences, adjoint identities, closed forms."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbm
+from oracle import surrogate as S
+
+RNG = np.random.default_rng(7007)
+
+
+def _torch_conv(x, w, b):
+    """Independent library check: torch.nn.functional.conv3d in FP64 on the CPU."""
+    xt = torch.from_numpy(np.ascontiguousarray(np.moveaxis(x, -1, 0)[None]))
+    wt = torch.from_numpy(np.ascontiguousarray(w.reshape(3, 3, 3, w.shape[1], w.shape[2]).transpose(4, 3, 0, 1, 2)))
+    y = torch.nn.functional.conv3d(xt, wt, torch.from_numpy(b), padding=1)
+    return np.moveaxis(y[0].numpy(), 0, -1)
+
+
+def test_conv_matches_direct_loops_and_torch():
+    x = RNG.normal(size=(3, 4, 5, 2))
+    w = RNG.normal(size=(27, 2, 3))
+    b = RNG.normal(size=3)
+    y = S.conv3d(x, w, b)
+    assert np.allclose(y, S.conv3d_direct(x, w, b), rtol=0, atol=1e-12)
+    x2 = RNG.normal(size=(6, 5, 7, 4))
+    w2 = RNG.normal(size=(27, 4, 5))
+    b2 = RNG.normal(size=5)
+    assert np.allclose(S.conv3d(x2, w2, b2), _torch_conv(x2, w2, b2), rtol=0, atol=1e-12)
+
+
+def test_centre_tap_is_a_matmul():
+    x = RNG.normal(size=(4, 3, 5, 6))
+    w = np.zeros((27, 6, 4))
+    w[13] = RNG.normal(size=(6, 4))  # tap (0, 0, 0)
+    assert np.allclose(S.conv3d(x, w), x @ w[13], rtol=0, atol=1e-13)
+
+
+def test_conv_gradients_finite_differences():
+    x = RNG.normal(size=(3, 3, 4, 2))
+    w = RNG.normal(size=(27, 2, 3))
+    r = RNG.normal(size=(3, 3, 4, 3))
+    f = lambda xx, ww: float((S.conv3d(xx, ww) * r).sum())
+    dx = S.conv3d_dgrad(r, w)
+    dw, db = S.conv3d_wgrad(x, r)
+    h = 1e-6
+    for _ in range(12):
+        i = tuple(RNG.integers(0, n) for n in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[i] += h
+        xm[i] -= h
+        assert (f(xp, w) - f(xm, w)) / (2 * h) == pytest.approx(dx[i], rel=1e-6, abs=1e-8)
+        j = tuple(RNG.integers(0, n) for n in w.shape)
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        assert (f(x, wp) - f(x, wm)) / (2 * h) == pytest.approx(dw[j], rel=1e-6, abs=1e-8)
+    assert np.allclose(db, r.reshape(-1, 3).sum(axis=0))
+
+
+def test_pool_and_upsample_adjoints():
+    x = RNG.normal(size=(4, 6, 8, 3))
+    y = RNG.normal(size=(2, 3, 4, 3))
+    assert (S.pool2(x) * y).sum() == pytest.approx((x * S.pool2_back(y)).sum(), rel=1e-13)
+    assert (S.up2(y) * x).sum() == pytest.approx((y * S.up2_back(x)).sum(), rel=1e-13)
+    assert np.allclose(S.pool2(S.up2(y)), y)
+
+
+def _torch_unet(P, ch):
+    """The same U-Net written with torch modules (FP64, CPU) for autograd."""
+    import torch.nn.functional as F
+
+    params = {k: (torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for k, (w, b) in P.items()}
+
+    def conv(h, name):
+        w, b = params[name]
+        wt = w.reshape(3, 3, 3, w.shape[1], w.shape[2]).permute(4, 3, 0, 1, 2)
+        return F.conv3d(h, wt, b, padding=1)
+
+    def run(x):
+        h = x
+        skips = []
+        for lvl in range(len(ch)):
+            h = F.relu(conv(h, f"enc{lvl}a"))
+            h = F.relu(conv(h, f"enc{lvl}b"))
+            if lvl < len(ch) - 1:
+                skips.append(h)
+                h = F.avg_pool3d(h, 2)
+        for lvl in range(len(ch) - 2, -1, -1):
+            h = torch.cat([F.interpolate(h, scale_factor=2, mode="nearest"), skips[lvl]], dim=1)
+            h = F.relu(conv(h, f"dec{lvl}a"))
+            h = F.relu(conv(h, f"dec{lvl}b"))
+        return x[:, : S.OUT_CH] + conv(h, "out")
+
+    return params, run
+
+
+def test_unet_gradients_match_torch_autograd():
+    ch = (4, 6, 8, 8)
+    P = S.init_params(11, ch=ch)
+    P["out"] = (RNG.normal(size=P["out"][0].shape) * 0.1, RNG.normal(size=6) * 0.1)
+    x = RNG.normal(size=(8, 8, 16, S.IN_CH))
+    pred, cache = S.unet_forward(x, P, ch=ch)
+    gy = RNG.normal(size=pred.shape)
+    G = S.unet_backward(gy, P, cache, ch=ch)
+    params, run = _torch_unet(P, ch)
+    xt = torch.from_numpy(np.ascontiguousarray(np.moveaxis(x, -1, 0)[None]))
+    yt = run(xt)
+    assert np.allclose(np.moveaxis(yt[0].detach().numpy(), 0, -1), pred, rtol=0, atol=1e-11)
+    (yt * torch.from_numpy(np.ascontiguousarray(np.moveaxis(gy, -1, 0)[None]))).sum().backward()
+    for name, (gw, gb) in G.items():
+        assert np.allclose(gw, params[name][0].grad.numpy(), rtol=1e-9, atol=1e-11), name
+        assert np.allclose(gb, params[name][1].grad.numpy(), rtol=1e-9, atol=1e-11), name
+
+
+def test_untrained_network_is_persistence_and_param_count():
+    P = S.init_params(3)
+    x = RNG.normal(size=(8, 8, 8, S.IN_CH))
+    small = S.init_params(3, ch=(4, 6, 8, 8))
+    pred, _ = S.unet_forward(x, small, ch=(4, 6, 8, 8))
+    assert np.array_equal(pred, x[..., :6])
+    n = sum(w.size + b.size for w, b in P.values())
+    assert 3.0e6 < n < 4.0e6  # the 32-64-128-128 network: about 3.5 M parameters
+
+
+def test_loss_gradient_finite_differences():
+    pred = RNG.normal(size=(2, 3, 4, 6)) + 1.0
+    tgt = RNG.normal(size=(2, 3, 4, 6)) + 1.0
+    mask = (RNG.uniform(size=(2, 3, 4)) > 0.3).astype(float)
+    L, g = S.loss(pred, tgt, mask, 0.7)
+    h = 1e-6
+    for _ in range(10):
+        i = tuple(RNG.integers(0, n) for n in pred.shape)
+        p1, p2 = pred.copy(), pred.copy()
+        p1[i] += h
+        p2[i] -= h
+        assert (S.loss(p1, tgt, mask, 0.7)[0] - S.loss(p2, tgt, mask, 0.7)[0]) / (2 * h) == pytest.approx(g[i],
+                                                                                                       rel=1e-6,
+                                                                                                       abs=1e-9)
+
+
+def test_adam_first_step_is_signed_lr():
+    p = RNG.normal(size=10)
+    g = RNG.normal(size=10)
+    p1, m, v = S.adam(p, g, np.zeros(10), np.zeros(10), 1, lr=0.01)
+    assert np.allclose(p1, p - 0.01 * np.sign(g), rtol=0, atol=1e-9)
+
+
+def test_restrict_uniform_state_and_rod_fraction():
+    shape = (6, 8, 10)
+    rho = np.zeros((2,) + shape)
+    rho[0], rho[1] = 0.7, 0.2
+    f = lbm.initial_state(rho)
+    mat = np.zeros(shape, np.uint8)
+    mat[0:2, 0:2, 0:2] = lbm.ROD  # one whole block of rod nodes
+    mat[2, 2, 2] = lbm.ROD  # one node of another block
+    f[:, :, mat != 0] = 0.0
+    c = S.restrict(f, mat, (4, 6, 8))
+    inside = c[:3, :4, :5]
+    assert np.allclose(inside[..., 6], 1.0) and np.allclose(c[3:, ..., 6], 0.0) and np.allclose(c[:, 4:, :, 6], 0)
+    assert np.allclose(c[3:, ..., 0], S.GAS[0]) and np.allclose(c[3:, ..., 1], S.GAS[1])
+    assert c[0, 0, 0, 5] == 1.0 and c[1, 1, 1, 5] == 1.0 / 8.0
+    assert c[0, 0, 0, 0] == 0.0  # no fluid node in the block
+    assert np.allclose(inside[1:, 1:, 1:, 0], 0.7) and np.allclose(inside[..., 2:5], 0.0, atol=1e-15)
+
+
+def test_prolong_reproduces_linear_fields_and_lift_moments():
+    shape = (8, 10, 12)
+    cz, cy, cx = 4, 5, 6
+    zz, yy, xx = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    coarse = np.zeros((cz, cy, cx, 7))
+    for ch, (a, b, c, d) in enumerate([(0.5, 0.01, 0.02, 0.03), (0.3, -0.01, 0.0, 0.02), (0.0, 0.001, 0.0, 0.0),
+                                       (0.01, 0.0, 0.002, 0.0), (0.0, 0.0, 0.0, 0.001)]):
+        coarse[..., ch] = a + b * xx + c * yy + d * zz
+    mat = np.zeros(shape, np.uint8)
+    rho, u = S.prolong(coarse, mat)
+    # interior fine nodes (not clamped): the coarse linear function at x/2 - 1/4
+    z, y, x = 3, 4, 5
+    X, Y, Z = x / 2 - 0.25, y / 2 - 0.25, z / 2 - 0.25
+    assert rho[0, z, y, x] == pytest.approx(0.5 + 0.01 * X + 0.02 * Y + 0.03 * Z, rel=1e-13)
+    assert u[1, z, y, x] == pytest.approx(0.01 + 0.002 * Y, rel=1e-13)
+    f = S.lift(coarse, mat)
+    r0 = f[0].sum(axis=0)
+    assert np.allclose(r0, rho[0], rtol=1e-13)
+    j = np.einsum("izyx,id->dzyx", f[0], lbm.C.astype(float))
+    assert np.allclose(j, rho[0][None] * u, rtol=1e-12, atol=1e-15)
