@@ -268,6 +268,85 @@ int lb_batch_create(lb_ctx *const *ctxs, int32_t n, void *workspace_dev, hipStre
 int lb_batch_step(lb_batch *b, int32_t nsteps, int32_t with_rods, int32_t use_graph, hipStream_t stream);
 int lb_batch_destroy(lb_batch *b);
 
+/*
+ * Learned surrogate (the benchmark spec form (4); the paper has none).  A coarse
+ * canvas is [D][H][W][8] channels-last: rho_A, rho_B, u_x, u_y, u_z (means over
+ * the fluid nodes of each 2 x 2 x 2 block, u = sum_k sum_i f*_i c_i / sum_k
+ * rho_k), rod volume fraction, domain mask (1 inside the lattice), 0.  The
+ * lattice occupies cells [0, n/2) per axis (n even, n/2 <= canvas size);
+ * cells outside hold gas (0.03, 1), zero velocity and mask 0.
+ *
+ * lb_sur_restrict : canvas of the current state into coarse_f32 and/or
+ *                   coarse_bf16 (device, caller-owned, nullable one of them).
+ * lb_sur_lift     : trilinear prolongation of channels 0..4 of coarse (device
+ *                   FP32 canvas) to the lattice, then f = f^eq(rho_k, u) (Eq. 2)
+ *                   at every fluid node as the new current state; wall
+ *                   bounce-back slots are refreshed, rods stay where they are.
+ * Both asynchronous; LB_EINVAL on null pointers or a lattice that does not fit.
+ */
+int lb_sur_restrict(lb_ctx *ctx, int32_t D, int32_t H, int32_t W, float *coarse_f32, void *coarse_bf16,
+                    hipStream_t stream);
+int lb_sur_lift(lb_ctx *ctx, const float *coarse_f32, int32_t D, int32_t H, int32_t W, hipStream_t stream);
+
+/*
+ * 3-D convolution, 3 x 3 x 3 taps, zero padding, channels-last BF16 tensors
+ * [D][H][W][C] on the device, FP32 accumulation on the matrix cores:
+ *   y[p, o] = b[o] + sum_{t, c} x[p + o_t, c] w[t, c, o], then ReLU if relu.
+ * The input is the concatenation of x1 (channels [0, c1); at half resolution
+ * and read through nearest-neighbour upsampling when up1 != 0) and x2
+ * (channels [c1, c1 + c2), full resolution; c2 = 0 for none).  w: BF16
+ * [27][c1 + c2][cout], tap t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1); b: FP32
+ * [cout] or null; outputs y (BF16) and/or yf (FP32) [D][H][W][cout].  c1, c2,
+ * cout: multiples of 8; D, H, W even when up1.  Asynchronous.
+ */
+typedef struct {
+    const void *x1;
+    int32_t c1, up1;
+    const void *x2;
+    int32_t c2;
+    const void *w;
+    const float *b;
+    void *y;
+    float *yf;
+    int32_t D, H, W, cout, relu;
+} lb_conv;
+int lb_conv3d_forward(const lb_conv *conv, hipStream_t stream);
+/* dx [D][H][W][c1 + c2] FP32 (overwritten) = the input gradient for the
+ * output gradient dy [D][H][W][cout] FP32; with relu, dy is masked by y > 0
+ * (conv->y must then hold the forward output). */
+int lb_conv3d_backward_data(const lb_conv *conv, const float *dy, float *dx, hipStream_t stream);
+/* dw [27][c1 + c2][cout] and db [cout] (nullable) FP32 += the parameter
+ * gradients (accumulated with atomics, so the summation order varies). */
+int lb_conv3d_backward_weights(const lb_conv *conv, const float *dy, float *dw, float *db, hipStream_t stream);
+/* 2 x 2 x 2 average pooling of BF16 x [D][H][W][C] into y [D/2][H/2][W/2][C]. */
+int lb_pool2(const void *x, int32_t D, int32_t H, int32_t W, int32_t C, void *y, hipStream_t stream);
+/* g[p, c] = gc[parent(p), c] / 8 (+ skip[p * skip_stride + skip_off + c] when
+ * skip is not null): the gradient through pooling plus a skip connection. */
+int lb_pool2_backward(const float *gc, const float *skip, int32_t skip_stride, int32_t skip_off, int32_t D, int32_t H,
+                      int32_t W, int32_t C, float *g, hipStream_t stream);
+/* gc[q, c] = sum of g[p * stride + c] over the 8 children p of q: the gradient
+ * through nearest-neighbour upsampling. */
+int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_t H, int32_t W, float *gc,
+                    hipStream_t stream);
+int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream);        /* graph-safe clear */
+int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream);       /* round to nearest even */
+/* Network prediction on P canvas cells: pred[:, 0:6] = xin[:, 0:6] + out[:, 0:6]
+ * (residual), channels 6, 7 copied from xin; into pred (FP32) and/or pred_bf16. */
+int lb_sur_residual(const float *out, const float *xin, int64_t P, float *pred, void *pred_bf16, hipStream_t stream);
+/* Surrogate loss over P cells of [P][8] FP32 tensors: pred = xin[0:6] +
+ * out[0:6], mask = xin[6]; loss = masked mean of (pred - tgt)^2 over the six
+ * channels + lam * (relative rho_A mass error)^2.  grad (nullable) [P][8]
+ * receives dloss/dout.  scratch: device, lb_sur_loss_scratch_bytes() bytes.
+ * result_host (nullable; the call then synchronises): sum mask, sum mask tgt_A,
+ * relative mass error, loss. */
+size_t lb_sur_loss_scratch_bytes(void);
+int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, float *grad, void *scratch,
+                double *result_host, hipStream_t stream);
+/* Adam (Kingma and Ba) with bias correction on n FP32 master parameters p
+ * with moments m, v; p_bf16 (nullable) receives the rounded copy.  step >= 1. */
+int lb_adam(float *p, const float *g, float *m, float *v, void *p_bf16, int64_t n, int32_t step, double lr, double b1,
+            double b2, double eps, hipStream_t stream);
+
 /* Index (0 or 1) of the buffer holding the current state. */
 int lb_current_buffer(const lb_ctx *ctx);
 
@@ -277,10 +356,10 @@ int lb_destroy(lb_ctx *ctx);
 /* Thread-local text of the last error. */
 const char *lb_last_error(void);
 
-/* sizeof of lb_params, lb_buffers, lb_obs, lb_droplet, lb_deposit_spec and
- * lb_graph into out[0..5], so a binding can verify its mirrors of the
- * structs.  Never fails. */
-void lb_abi_sizes(size_t out[6]);
+/* sizeof of lb_params, lb_buffers, lb_obs, lb_droplet, lb_deposit_spec,
+ * lb_graph and lb_conv into out[0..6], so a binding can verify its mirrors of
+ * the structs.  Never fails. */
+void lb_abi_sizes(size_t out[7]);
 
 #ifdef __cplusplus
 }

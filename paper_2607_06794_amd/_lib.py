@@ -40,6 +40,20 @@ EXPORTS = (
     "lb_batch_create",
     "lb_batch_step",
     "lb_batch_destroy",
+    "lb_sur_restrict",
+    "lb_sur_lift",
+    "lb_conv3d_forward",
+    "lb_conv3d_backward_data",
+    "lb_conv3d_backward_weights",
+    "lb_pool2",
+    "lb_pool2_backward",
+    "lb_up2_backward",
+    "lb_fill_f32",
+    "lb_to_bf16",
+    "lb_sur_residual",
+    "lb_sur_loss_scratch_bytes",
+    "lb_sur_loss",
+    "lb_adam",
 )
 
 
@@ -139,7 +153,26 @@ class LbGraph(ct.Structure):
     ]
 
 
-STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph")
+class LbConv(ct.Structure):
+    _fields_ = [
+        ("x1", ct.c_void_p),
+        ("c1", ct.c_int32),
+        ("up1", ct.c_int32),
+        ("x2", ct.c_void_p),
+        ("c2", ct.c_int32),
+        ("w", ct.c_void_p),
+        ("b", ct.c_void_p),
+        ("y", ct.c_void_p),
+        ("yf", ct.c_void_p),
+        ("D", ct.c_int32),
+        ("H", ct.c_int32),
+        ("W", ct.c_int32),
+        ("cout", ct.c_int32),
+        ("relu", ct.c_int32),
+    ]
+
+
+STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph", "LbConv")
 
 
 class LbError(RuntimeError):
@@ -211,6 +244,27 @@ def load(path: str = LIB_PATH):
     lib.lb_batch_step.restype = ct.c_int
     lib.lb_batch_destroy.argtypes = [ct.c_void_p]
     lib.lb_batch_destroy.restype = ct.c_int
+    V, I32, I64, D_ = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double
+    sigs = {
+        "lb_sur_restrict": [V, I32, I32, I32, V, V, V],
+        "lb_sur_lift": [V, V, I32, I32, I32, V],
+        "lb_conv3d_forward": [P(LbConv), V],
+        "lb_conv3d_backward_data": [P(LbConv), V, V, V],
+        "lb_conv3d_backward_weights": [P(LbConv), V, V, V, V],
+        "lb_pool2": [V, I32, I32, I32, I32, V, V],
+        "lb_pool2_backward": [V, V, I32, I32, I32, I32, I32, I32, V, V],
+        "lb_up2_backward": [V, I32, I32, I32, I32, I32, V, V],
+        "lb_fill_f32": [V, I64, ct.c_float, V],
+        "lb_to_bf16": [V, I64, V, V],
+        "lb_sur_loss": [V, V, V, I64, D_, V, V, V, V],
+        "lb_sur_residual": [V, V, I64, V, V, V],
+        "lb_adam": [V, V, V, V, V, I64, I32, D_, D_, D_, D_, V],
+    }
+    for name, args in sigs.items():
+        getattr(lib, name).argtypes = args
+        getattr(lib, name).restype = ct.c_int
+    lib.lb_sur_loss_scratch_bytes.argtypes = []
+    lib.lb_sur_loss_scratch_bytes.restype = ct.c_size_t
     lib.lb_abi_sizes.argtypes = [P(ct.c_size_t)]
     lib.lb_abi_sizes.restype = None
     sizes = (ct.c_size_t * len(STRUCTS))()

@@ -376,13 +376,14 @@ size_t lb_workspace_bytes(const lb_params *p) {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
-void lb_abi_sizes(size_t out[6]) {
+void lb_abi_sizes(size_t out[7]) {
     out[0] = sizeof(lb_params);
     out[1] = sizeof(lb_buffers);
     out[2] = sizeof(lb_obs);
     out[3] = sizeof(lb_droplet);
     out[4] = sizeof(lb_deposit_spec);
     out[5] = sizeof(lb_graph);
+    out[6] = sizeof(lb_conv);
 }
 
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
@@ -719,6 +720,153 @@ int lb_rod_map(lb_ctx *c, int32_t *map_host, hipStream_t stream) {
     HIP_TRY(hipMemcpyAsync(map_host, map, size_t(p.nx) * p.ny * sizeof(int32_t), hipMemcpyDeviceToHost, stream),
             "copy rod map");
     HIP_TRY(hipStreamSynchronize(stream), "rod map sync");
+    return LB_OK;
+}
+
+static bool canvas_fits(const lb_params &p, int D, int H, int W) {
+    return D > 0 && H > 0 && W > 0 && p.nx % 2 == 0 && p.ny % 2 == 0 && p.nz % 2 == 0 && p.nx / 2 <= W &&
+           p.ny / 2 <= H && p.nz / 2 <= D;
+}
+
+int lb_sur_restrict(lb_ctx *c, int32_t D, int32_t H, int32_t W, float *coarse_f32, void *coarse_bf16,
+                    hipStream_t stream) {
+    if (!c || (!coarse_f32 && !coarse_bf16)) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
+    HIP_TRY(launch_restrict(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, c->rref, D, H, W, coarse_f32,
+                            static_cast<uint16_t *>(coarse_bf16), stream),
+            "restrict");
+    return LB_OK;
+}
+
+int lb_sur_lift(lb_ctx *c, const float *coarse_f32, int32_t D, int32_t H, int32_t W, hipStream_t stream) {
+    if (!c || !coarse_f32) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
+    HIP_TRY(launch_lift(p.prec, coarse_f32, D, H, W, c->mat, p.nx, p.ny, p.nz, c->f[c->cur], c->fs, c->rref, stream),
+            "lift");
+    const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
+    HIP_TRY(launch_slot_fill(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, per, stream), "lift slots");
+    return LB_OK;
+}
+
+static int conv_check(const lb_conv *a, bool fwd) {
+    if (!a || !a->x1 || !a->w) return fail(LB_EINVAL, "null convolution argument");
+    if (a->c1 <= 0 || a->c1 % 8 || a->c2 < 0 || a->c2 % 8 || a->cout <= 0 || a->cout % 8)
+        return fail(LB_EINVAL, "channel counts must be positive multiples of 8 (c2 may be 0)");
+    if (a->c2 > 0 && !a->x2) return fail(LB_EINVAL, "null x2 with c2 > 0");
+    if (a->D < 1 || a->H < 1 || a->W < 1) return fail(LB_EINVAL, "empty volume");
+    if (a->up1 && (a->D % 2 || a->H % 2 || a->W % 2)) return fail(LB_EINVAL, "upsampled input needs even sizes");
+    if (fwd && !a->y && !a->yf) return fail(LB_EINVAL, "no output");
+    if (!fwd && a->relu && !a->y) return fail(LB_EINVAL, "the ReLU mask needs the forward output y");
+    return LB_OK;
+}
+
+static ConvArgs conv_args(const lb_conv *a) {
+    ConvArgs c{};
+    c.x1 = static_cast<const uint16_t *>(a->x1);
+    c.c1 = a->c1;
+    c.up1 = a->up1 != 0;
+    c.x2 = static_cast<const uint16_t *>(a->x2);
+    c.c2 = a->c2;
+    c.w = static_cast<const uint16_t *>(a->w);
+    c.b = a->b;
+    c.y = static_cast<uint16_t *>(a->y);
+    c.yf = a->yf;
+    c.D = a->D;
+    c.H = a->H;
+    c.W = a->W;
+    c.cout = a->cout;
+    c.relu = a->relu != 0;
+    return c;
+}
+
+int lb_conv3d_forward(const lb_conv *a, hipStream_t stream) {
+    int rc = conv_check(a, true);
+    if (rc) return rc;
+    HIP_TRY(launch_conv_fwd(conv_args(a), stream), "conv forward");
+    return LB_OK;
+}
+
+int lb_conv3d_backward_data(const lb_conv *a, const float *dy, float *dx, hipStream_t stream) {
+    int rc = conv_check(a, false);
+    if (rc) return rc;
+    if (!dy || !dx) return fail(LB_EINVAL, "null gradient");
+    HIP_TRY(launch_conv_dgrad(conv_args(a), dy, dx, stream), "conv backward data");
+    return LB_OK;
+}
+
+int lb_conv3d_backward_weights(const lb_conv *a, const float *dy, float *dw, float *db, hipStream_t stream) {
+    int rc = conv_check(a, false);
+    if (rc) return rc;
+    if (!dy || !dw) return fail(LB_EINVAL, "null gradient");
+    HIP_TRY(launch_conv_wgrad(conv_args(a), dy, dw, db, stream), "conv backward weights");
+    return LB_OK;
+}
+
+int lb_pool2(const void *x, int32_t D, int32_t H, int32_t W, int32_t C, void *y, hipStream_t stream) {
+    if (!x || !y || D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2 || C < 1) return fail(LB_EINVAL, "bad pooling");
+    HIP_TRY(launch_pool2(static_cast<const uint16_t *>(x), D, H, W, C, static_cast<uint16_t *>(y), stream), "pool");
+    return LB_OK;
+}
+
+int lb_pool2_backward(const float *gc, const float *skip, int32_t skip_stride, int32_t skip_off, int32_t D, int32_t H,
+                      int32_t W, int32_t C, float *g, hipStream_t stream) {
+    if (!gc || !g || D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2 || C < 1 ||
+        (skip && (skip_off < 0 || skip_stride < skip_off + C)))
+        return fail(LB_EINVAL, "bad pooling gradient");
+    HIP_TRY(launch_pool2_back(gc, skip, skip_stride, skip_off, D, H, W, C, g, stream), "pool backward");
+    return LB_OK;
+}
+
+int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_t H, int32_t W, float *gc,
+                    hipStream_t stream) {
+    if (!g || !gc || C < 1 || stride < C || D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2)
+        return fail(LB_EINVAL, "bad upsampling gradient");
+    HIP_TRY(launch_up2_back(g, stride, C, D, H, W, gc, stream), "upsample backward");
+    return LB_OK;
+}
+
+int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream) {
+    if (!p || n < 0) return fail(LB_EINVAL, "bad fill");
+    if (n) HIP_TRY(launch_fill_f32(p, n, value, stream), "fill");
+    return LB_OK;
+}
+
+int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream) {
+    if (!x || !y || n < 0) return fail(LB_EINVAL, "bad conversion");
+    if (n) HIP_TRY(launch_to_bf16(x, n, static_cast<uint16_t *>(y), stream), "to bf16");
+    return LB_OK;
+}
+
+int lb_sur_residual(const float *out, const float *xin, int64_t P, float *pred, void *pred_bf16, hipStream_t stream) {
+    if (!out || !xin || (!pred && !pred_bf16) || P < 1) return fail(LB_EINVAL, "bad residual arguments");
+    HIP_TRY(launch_residual(out, xin, P, pred, static_cast<uint16_t *>(pred_bf16), stream), "residual");
+    return LB_OK;
+}
+
+size_t lb_sur_loss_scratch_bytes(void) { return SUR_LOSS_SCRATCH * sizeof(double); }
+
+int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, float *grad, void *scratch,
+                double *result_host, hipStream_t stream) {
+    if (!out || !xin || !tgt || !scratch || P < 1) return fail(LB_EINVAL, "bad loss arguments");
+    double *part = static_cast<double *>(scratch);
+    double *res = part + 256 * 4;
+    HIP_TRY(launch_loss(out, xin, tgt, P, lam, part, res, grad, stream), "loss");
+    if (result_host) {
+        HIP_TRY(hipMemcpyAsync(result_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy loss");
+        HIP_TRY(hipStreamSynchronize(stream), "loss sync");
+    }
+    return LB_OK;
+}
+
+int lb_adam(float *p, const float *g, float *m, float *v, void *p_bf16, int64_t n, int32_t step, double lr, double b1,
+            double b2, double eps, hipStream_t stream) {
+    if (!p || !g || !m || !v || n < 0 || step < 1) return fail(LB_EINVAL, "bad Adam arguments");
+    if (n)
+        HIP_TRY(launch_adam(p, g, m, v, static_cast<uint16_t *>(p_bf16), n, step, float(lr), float(b1), float(b2),
+                            float(eps), stream),
+                "adam");
     return LB_OK;
 }
 

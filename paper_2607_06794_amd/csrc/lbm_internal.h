@@ -134,6 +134,38 @@ hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t
 hipError_t launch_deposit(const DepArgs &d, hipStream_t s);
 hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s);
 
+// surrogate (surrogate.hip): channels-last BF16 convolutions and helpers
+struct ConvArgs {
+    const uint16_t *x1;  // channels [0, c1), half resolution when up1
+    int c1, up1;
+    const uint16_t *x2;  // channels [c1, c1 + c2), full resolution (c2 may be 0)
+    int c2;
+    const uint16_t *w;   // [27][c1 + c2][cout]
+    const float *b;      // [cout] or null
+    uint16_t *y;         // [P][cout] BF16 output (or null)
+    float *yf;           // [P][cout] FP32 output (or null)
+    int D, H, W, cout, relu;
+};
+hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t s);
+hipError_t launch_conv_dgrad(const ConvArgs &a, const float *dy, float *dx, hipStream_t s);
+hipError_t launch_conv_wgrad(const ConvArgs &a, const float *dy, float *dw, float *db, hipStream_t s);
+hipError_t launch_pool2(const uint16_t *x, int D, int H, int W, int C, uint16_t *y, hipStream_t s);
+hipError_t launch_pool2_back(const float *gc, const float *skip, int skip_stride, int skip_off, int D, int H, int W,
+                             int C, float *g, hipStream_t s);
+hipError_t launch_up2_back(const float *g, int stride, int C, int D, int H, int W, float *gc, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s);
+hipError_t launch_residual(const float *out, const float *xin, int64_t P, float *pred, uint16_t *predb, hipStream_t s);
+constexpr int SUR_LOSS_SCRATCH = 256 * 4 + 8;  // doubles
+hipError_t launch_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, double *part,
+                       double *res, float *grad, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t s);
+hipError_t launch_restrict(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                           const double rref[2], int D, int H, int W, float *outf, uint16_t *outb, hipStream_t s);
+hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const uint8_t *mat, int nx, int ny, int nz,
+                       void *f, int64_t fs, const double rref[2], hipStream_t s);
+
 constexpr int OBS_BLOCKS = 512;
 constexpr int OBS_FIELDS = 10;
 

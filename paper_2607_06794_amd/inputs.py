@@ -209,7 +209,7 @@ def cap_inside(spec: CapSpec):
     return inside
 
 
-def sweep_droplets(n=64, seed0=4000, rods=True):
+def sweep_droplets(n=64, seed0=4000, rods=True, placement="stress"):
     """Parameter sweep of sessile caps of uneven size (many-droplet batches).
 
     Droplet i (seed seed0 + i): NX from (128, 160, 192, 224, 256) in turn,
@@ -220,8 +220,10 @@ def sweep_droplets(n=64, seed0=4000, rods=True):
     min(0.4 NZ, 0.66 width); the stripe is the footprint plus 10 nodes on
     every side (clipped to the lattice).  Rods: the drawn count placed
     anywhere in the fluid (stress placement, place_rods with inside=None,
-    seed seed0 + 500 + i, 3 trials per requested rod).  Yields dicts with
-    shape, rho, mat, rods, rod_length, eps_att, aspect.
+    seed seed0 + 500 + i, 3 trials per requested rod), or with
+    placement="physical" as many of them as fit fully inside the cap with a
+    one-node margin (seed seed0 + 500 + i, 20 trials per requested rod).
+    Yields dicts with shape, rho, mat, rods, rod_length, eps_att, aspect.
     """
     for i in range(n):
         nx = (128, 160, 192, 224, 256)[i % 5]
@@ -237,7 +239,10 @@ def sweep_droplets(n=64, seed0=4000, rods=True):
                        stripe=(min(fx + 20.0, nx), min(fy + 20.0, ny)), seed=seed0 + i)
         rho, mat = sessile_cap(spec)
         r = None
-        if rods:
+        if rods and placement == "physical":
+            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=cap_inside(spec), seed=seed0 + 500 + i,
+                           margin=1.0, max_trials=20 * n_rods)
+        elif rods:
             r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=None, seed=seed0 + 500 + i,
                            max_trials=3 * n_rods)
         yield dict(shape=(nz, ny, nx), rho=rho, mat=mat, rods=r, rod_length=length, eps_att=eps, aspect=ar)

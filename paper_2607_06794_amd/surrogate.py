@@ -1,0 +1,365 @@
+"""Learned surrogate: a 3-D convolutional U-Net on the coarse canvas, trained
+and run with the library's own kernels (BF16 matrix-core convolutions with
+FP32 accumulation, pooling and gradient plumbing, the loss and Adam).
+
+This module only allocates device buffers (PyTorch tensors) and sequences the
+C-ABI calls; every arithmetic step runs in liblbm.so.
+
+Network (four levels, 32-64-128-128 channels): per level two 3x3x3 ReLU
+convolutions; 2x2x2 average pooling down; on the way up nearest-neighbour
+upsampling concatenated with the skip (read in place by the convolution),
+two ReLU convolutions; a final linear 3x3x3 convolution to the six predicted
+channels, added to the input channels (residual).  Canvas tensors are
+[D][H][W][8] channels-last; the input's 7 channels are rho_A, rho_B, u_x, u_y,
+u_z, rod fraction, mask (+1 zero channel), the output's 6 the same minus the
+mask (+2 zero channels).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+
+from . import _lib
+
+CH = (32, 64, 128, 128)
+CIN, COUT = 8, 8  # padded input / output channel counts (7 and 6 used)
+
+
+def layer_shapes(ch=CH):
+    """(name, c1, c2, cout, up1, level) of every convolution in forward order."""
+    L = []
+    c = CIN
+    for lvl, co in enumerate(ch):
+        L.append((f"enc{lvl}a", c, 0, co, 0, lvl))
+        L.append((f"enc{lvl}b", co, 0, co, 0, lvl))
+        c = co
+    for lvl in range(len(ch) - 2, -1, -1):
+        L.append((f"dec{lvl}a", c, ch[lvl], ch[lvl], 1, lvl))
+        L.append((f"dec{lvl}b", ch[lvl], 0, ch[lvl], 0, lvl))
+        c = ch[lvl]
+    L.append(("out", c, 0, COUT, 0, 0))
+    return L
+
+
+def _p(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class UNet:
+    def __init__(self, D=32, H=64, W=128, ch=CH, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = _lib.load()
+        self.D, self.H, self.W, self.ch = D, H, W, tuple(ch)
+        nlev = len(self.ch)
+        if any(n % (1 << (nlev - 1)) for n in (D, H, W)):
+            raise ValueError(f"canvas {D}x{H}x{W} must be divisible by {1 << (nlev - 1)}")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.layers = layer_shapes(self.ch)
+        # flat FP32 master parameters (w then b per layer), BF16 copy, grads, moments
+        self.off = {}
+        n = 0
+        for name, c1, c2, co, _, _ in self.layers:
+            nw = 27 * (c1 + c2) * co
+            self.off[name] = (n, nw, n + nw, co)
+            n += nw + co
+            n = (n + 7) // 8 * 8  # keep every block 16-byte aligned
+        self.nparam = n
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.p = torch.zeros(n, **f32)
+        self.g = torch.zeros(n, **f32)
+        self.m = torch.zeros(n, **f32)
+        self.v = torch.zeros(n, **f32)
+        self.pb = torch.zeros(n, dtype=torch.int16, device=self.device)
+        self.step_count = 0
+        # activations (BF16) and gradients (FP32) per level
+        self.P = [(D >> l) * (H >> l) * (W >> l) for l in range(nlev)]
+        bf = dict(dtype=torch.int16, device=self.device)
+        self.act = {}
+        for name, c1, c2, co, _, lvl in self.layers[:-1]:
+            self.act[name] = torch.zeros(self.P[lvl] * co, **bf)
+        self.pooled = [torch.zeros(self.P[l + 1] * self.ch[l], **bf) for l in range(nlev - 1)]
+        self.out = torch.zeros(self.P[0] * COUT, **f32)
+        cmax = [max(self.ch[l] + (self.ch[l + 1] if l + 1 < nlev else 0), self.ch[l]) for l in range(nlev)]
+        self.gA = [torch.zeros(self.P[l] * max(cmax[l], CIN, self.ch[-1] * 2), **f32) for l in range(nlev)]
+        self.gB = [torch.zeros(self.P[l] * max(self.ch), **f32) for l in range(nlev)]
+        self.gcat = [torch.zeros(self.P[l] * (self.ch[l] + (self.ch[l + 1] if l + 1 < nlev - 1 else self.ch[-1])), **f32)
+                     for l in range(nlev - 1)]
+        self.loss_scratch = torch.zeros(self.lib.lb_sur_loss_scratch_bytes() // 4 + 64, **f32)
+
+    # ------------------------------------------------------------------ params
+    def _s(self):
+        return ct.c_void_p(self.stream.cuda_stream)
+
+    def init(self, seed=0):
+        """He-normal weights (std sqrt(2 / (27 Cin))) from a seeded generator, zero
+        biases, a zero output layer (the untrained network is persistence)."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        host = np.zeros(self.nparam, np.float32)
+        for name, c1, c2, co, _, _ in self.layers:
+            o, nw, ob, _ = self.off[name]
+            if name != "out":
+                host[o:o + nw] = rng.normal(0.0, np.sqrt(2.0 / (27 * (c1 + c2))), nw)
+        self.set_flat(host)
+        return self
+
+    def set_flat(self, host):
+        self.p.copy_(self.torch.from_numpy(np.asarray(host, np.float32)))
+        self.m.zero_()
+        self.v.zero_()
+        self.step_count = 0
+        _lib.check(self.lib.lb_to_bf16(_p(self.p), self.nparam, _p(self.pb), self._s()))
+
+    def set_layer(self, name, w, b):
+        """w [27][cin_used][cout_used] and b [cout_used] (host arrays), zero padded."""
+        o, nw, ob, co = self.off[name]
+        c = next(l for l in self.layers if l[0] == name)
+        cin = c[1] + c[2]
+        full = np.zeros((27, cin, co), np.float32)
+        full[:, : w.shape[1], : w.shape[2]] = w
+        host = self.p.cpu().numpy()
+        host[o:o + nw] = full.ravel()
+        host[ob:ob + co] = 0.0
+        host[ob:ob + len(b)] = b
+        self.set_flat(host)
+
+    def get_layer_grad(self, name):
+        o, nw, ob, co = self.off[name]
+        c = next(l for l in self.layers if l[0] == name)
+        g = self.g.cpu().numpy()
+        return g[o:o + nw].reshape(27, c[1] + c[2], co), g[ob:ob + co]
+
+    def _conv(self, name, x1, x2, y=None, yf=None, relu=1):
+        o, nw, ob, co = self.off[name]
+        c = next(l for l in self.layers if l[0] == name)
+        lvl = c[5]
+        cv = _lib.LbConv()
+        cv.x1, cv.c1, cv.up1 = x1.data_ptr(), c[1], c[4]
+        cv.x2, cv.c2 = (x2.data_ptr() if x2 is not None else None), c[2]
+        cv.w = self.pb.data_ptr() + 2 * o
+        cv.b = self.p.data_ptr() + 4 * ob
+        cv.y = y.data_ptr() if y is not None else None
+        cv.yf = yf.data_ptr() if yf is not None else None
+        cv.D, cv.H, cv.W = self.D >> lvl, self.H >> lvl, self.W >> lvl
+        cv.cout, cv.relu = co, relu
+        return cv, o, ob
+
+    # ---------------------------------------------------------------- forward
+    def forward(self, x_bf16):
+        """x_bf16: int16 tensor [P0 * 8] (BF16 canvas).  Returns self.out, the FP32
+        [P0][8] network output before the residual."""
+        s = self._s()
+        nlev = len(self.ch)
+        self._x = x_bf16
+        h = x_bf16
+        for lvl in range(nlev):
+            for part in "ab":
+                name = f"enc{lvl}{part}"
+                cv, _, _ = self._conv(name, h, None, y=self.act[name])
+                _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
+                h = self.act[name]
+            if lvl < nlev - 1:
+                _lib.check(self.lib.lb_pool2(_p(h), self.D >> lvl, self.H >> lvl, self.W >> lvl, self.ch[lvl],
+                                             _p(self.pooled[lvl]), s))
+                h = self.pooled[lvl]
+        for lvl in range(nlev - 2, -1, -1):
+            name = f"dec{lvl}a"
+            cv, _, _ = self._conv(name, h, self.act[f"enc{lvl}b"], y=self.act[name])
+            _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
+            name = f"dec{lvl}b"
+            cv, _, _ = self._conv(name, self.act[f"dec{lvl}a"], None, y=self.act[name])
+            _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
+            h = self.act[name]
+        cv, _, _ = self._conv("out", h, None, yf=self.out, relu=0)
+        _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
+        return self.out
+
+    # --------------------------------------------------------------- backward
+    def zero_grad(self):
+        _lib.check(self.lib.lb_fill_f32(_p(self.g), self.nparam, 0.0, self._s()))
+
+    def _wgrad_dgrad(self, name, x1, x2, y, dy, dx):
+        cv, o, ob = self._conv(name, x1, x2, y=y, relu=0 if name == "out" else 1)
+        s = self._s()
+        _lib.check(self.lib.lb_conv3d_backward_weights(ct.byref(cv), _p(dy), ct.c_void_p(self.g.data_ptr() + 4 * o),
+                                                       ct.c_void_p(self.g.data_ptr() + 4 * ob), s))
+        if dx is not None:
+            _lib.check(self.lib.lb_conv3d_backward_data(ct.byref(cv), _p(dy), _p(dx), s))
+
+    def backward(self, gout):
+        """Accumulate the parameter gradients for dloss/dout = gout [P0][8] FP32
+        (uses the activations of the last forward call)."""
+        s = self._s()
+        nlev = len(self.ch)
+        g = self.gB[0]
+        self._wgrad_dgrad("out", self.act["dec0b"], None, None, gout, g)
+        gl = {}
+        for lvl in range(0, nlev - 1):
+            # dec{lvl}b, then dec{lvl}a whose input is (up(h), skip)
+            ga = self.gA[lvl]
+            self._wgrad_dgrad(f"dec{lvl}b", self.act[f"dec{lvl}a"], None, self.act[f"dec{lvl}b"], g, ga)
+            coarse = self.act[f"dec{lvl + 1}b"] if lvl + 1 < nlev - 1 else self.act[f"enc{nlev - 1}b"]
+            cup = self.ch[lvl + 1] if lvl + 1 < nlev - 1 else self.ch[-1]
+            gcat = self.gcat[lvl]
+            self._wgrad_dgrad(f"dec{lvl}a", coarse, self.act[f"enc{lvl}b"], self.act[f"dec{lvl}a"], ga, gcat)
+            gl[lvl] = (gcat, cup + self.ch[lvl], cup)
+            # gradient of the coarse input: sum over the upsampled children
+            g = self.gB[lvl + 1]
+            _lib.check(self.lib.lb_up2_backward(_p(gcat), cup + self.ch[lvl], cup, self.D >> lvl, self.H >> lvl,
+                                                self.W >> lvl, _p(g), s))
+        for lvl in range(nlev - 1, -1, -1):
+            if lvl < nlev - 1:
+                # gradient of enc{lvl}b's output: through the pooling plus the skip
+                gcat, stride, off = gl[lvl]
+                gn = self.gA[lvl]
+                _lib.check(self.lib.lb_pool2_backward(_p(g), _p(gcat), stride, off, self.D >> lvl, self.H >> lvl,
+                                                      self.W >> lvl, self.ch[lvl], _p(gn), s))
+                g = gn
+            ga = self.gB[lvl] if g is not self.gB[lvl] else self.gA[lvl]
+            self._wgrad_dgrad(f"enc{lvl}b", self.act[f"enc{lvl}a"], None, self.act[f"enc{lvl}b"], g, ga)
+            xin = self._x if lvl == 0 else self.pooled[lvl - 1]
+            gb = None
+            if lvl > 0:
+                gb = self.gB[lvl] if ga is not self.gB[lvl] else self.gA[lvl]
+            self._wgrad_dgrad(f"enc{lvl}a", xin, None, self.act[f"enc{lvl}a"], ga, gb)
+            if lvl > 0:
+                g = gb
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        _lib.check(self.lib.lb_adam(_p(self.p), _p(self.g), _p(self.m), _p(self.v), _p(self.pb), self.nparam,
+                                    self.step_count, lr, b1, b2, eps, self._s()))
+
+    def loss(self, xin_f32, tgt_f32, lam=1.0, grad=None, sync=True):
+        """(loss, relative mass error) of pred = xin + out against tgt; grad
+        (FP32 [P0][8]) receives dloss/dout when given."""
+        res = (ct.c_double * 4)()
+        _lib.check(self.lib.lb_sur_loss(_p(self.out), _p(xin_f32), _p(tgt_f32), self.P[0], float(lam), _p(grad),
+                                        _p(self.loss_scratch), res if sync else None, self._s()))
+        return (res[3], res[2]) if sync else None
+
+    def train_step(self, x_bf16, xin_f32, tgt_f32, lam=1.0, lr=1e-3):
+        if not hasattr(self, "_gout"):
+            self._gout = self.torch.zeros(self.P[0] * COUT, dtype=self.torch.float32, device=self.device)
+        self.zero_grad()
+        self.forward(x_bf16)
+        out = self.loss(xin_f32, tgt_f32, lam, grad=self._gout)
+        self.backward(self._gout)
+        self.adam(lr)
+        return out
+
+
+# ---------------------------------------------------------------------------
+# canvas I/O, rollouts, training and evaluation (sequencing only)
+# ---------------------------------------------------------------------------
+def restrict(lat, D, H, W, out_f32=None, out_bf16=None):
+    """Coarse canvas of a lattice's current state (library kernel)."""
+    import torch
+
+    lib = _lib.load()
+    P = D * H * W
+    if out_f32 is None:
+        out_f32 = torch.empty(P * 8, dtype=torch.float32, device=lat.device)
+    if out_bf16 is None:
+        out_bf16 = torch.empty(P * 8, dtype=torch.int16, device=lat.device)
+    _lib.check(lib.lb_sur_restrict(lat._ctx, D, H, W, _p(out_f32), _p(out_bf16), _stream(lat)))
+    return out_f32, out_bf16
+
+
+def lift(lat, pred_f32, D, H, W):
+    """Replace a lattice's state by the prolonged equilibrium of a predicted canvas."""
+    lib = _lib.load()
+    _lib.check(lib.lb_sur_lift(lat._ctx, _p(pred_f32), D, H, W, _stream(lat)))
+
+
+def _stream(lat):
+    import torch
+
+    s = lat.stream if lat.stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def predict(net, x_f32, x_bf16, pred_f32=None, pred_bf16=None):
+    """pred = x + network(x) on the first six channels (library kernels)."""
+    net.forward(x_bf16)
+    _lib.check(net.lib.lb_sur_residual(_p(net.out), _p(x_f32), net.P[0], _p(pred_f32), _p(pred_bf16), net._s()))
+    return pred_f32, pred_bf16
+
+
+def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True):
+    """Canvases of every lattice every `interval` steps (after `warm` steps):
+    tensors [n_lat, n_snap, P * 8] in FP32 and BF16."""
+    import torch
+
+    P = D * H * W
+    dev = lats[0].device
+    xf = torch.empty((len(lats), n_snap, P * 8), dtype=torch.float32, device=dev)
+    xb = torch.empty((len(lats), n_snap, P * 8), dtype=torch.int16, device=dev)
+    if warm:
+        batch.step(warm, rods=rods)
+    for s in range(n_snap):
+        if s:
+            batch.step(interval, rods=rods)
+        for i, lat in enumerate(lats):
+            restrict(lat, D, H, W, xf[i, s], xb[i, s])
+    torch.cuda.synchronize()
+    return xf, xb
+
+
+def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None):
+    """Adam on (x_f32, x_bf16, y_f32) pairs, `batch` samples per update
+    (gradients summed).  Returns the mean training loss of every epoch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    import torch
+
+    gout = torch.zeros(net.P[0] * COUT, dtype=torch.float32, device=net.device)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(pairs))
+        tot = 0.0
+        for k in range(0, len(order), batch):
+            net.zero_grad()
+            for j in order[k:k + batch]:
+                xf, xb, yf = pairs[j]
+                net.forward(xb)
+                loss, _ = net.loss(xf, yf, lam, grad=gout)
+                net.backward(gout)
+                tot += loss
+            net.adam(lr)
+        hist.append(tot / max(1, len(pairs)))
+        if log:
+            log(f"[surrogate] epoch {ep}: loss {hist[-1]:.4e}")
+    return hist
+
+
+def evaluate(net, pairs, lam=1.0, prev=None):
+    """Mean loss of the network, of persistence (y = x) and, when the previous
+    snapshots are given, of linear extrapolation (y = 2 x - x_prev), using the
+    library's loss kernel for all three."""
+    import torch
+
+    zeros = torch.zeros(net.P[0] * COUT, dtype=torch.float32, device=net.device)
+    res = {"net": 0.0, "persistence": 0.0, "mass_err_net": 0.0, "mass_err_persistence": 0.0}
+    if prev is not None:
+        res["linear"] = 0.0
+    for k, (xf, xb, yf) in enumerate(pairs):
+        net.forward(xb)
+        l, me = net.loss(xf, yf, lam)
+        res["net"] += l
+        res["mass_err_net"] += abs(me)
+        saved = net.out.clone()
+        net.out.copy_(zeros)
+        l0, me0 = net.loss(xf, yf, lam)
+        res["persistence"] += l0
+        res["mass_err_persistence"] += abs(me0)
+        if prev is not None:
+            net.out.copy_(xf - prev[k])  # x + (x - x_prev) on the six channels
+            l1, _ = net.loss(xf, yf, lam)
+            res["linear"] += l1
+        net.out.copy_(saved)
+    for key in res:
+        res[key] /= max(1, len(pairs))
+    return res
