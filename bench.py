@@ -26,6 +26,7 @@ import time  # noqa: E402
 import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+TILE_CACHE = None  # JSON file of the autotuner's choices (--tile-cache; None: the per-user default)
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
@@ -82,7 +83,7 @@ def time_step(case, prec, steps, warmup, tile, autotune, rods=None, segment=0):
             if autotune:
                 # tile shape picked by the library's autotuner (its trial steps
                 # are ordinary fluid steps, run before the timed region)
-                t = lat.autotune(trial_steps=10, cache=os.path.join(ROOT, "gpurun_out", "tiles.json"))
+                t = lat.autotune(trial_steps=10, cache=TILE_CACHE)
                 chosen = {k: t[k] for k in ("tile_y", "rows_per_thread", "zchunk")}
                 lat.close()
                 lp = rod_params(cases.lattice_params(case, prec, **chosen))
@@ -140,7 +141,7 @@ def batched_form(steps, warmup, n_lattices=64):
             if key not in tuned:
                 # tile shape per grid class from the autotuner (its trial steps
                 # are fluid steps of the first lattice of the class)
-                t = lat.autotune(trial_steps=5, cache=os.path.join(ROOT, "gpurun_out", "tiles.json"))
+                t = lat.autotune(trial_steps=5, cache=TILE_CACHE)
                 tuned[key] = (t["tile_y"], t["rows_per_thread"], t["zchunk"])
                 lat.close()
                 lat = Lattice(lp, d["rho"], d["mat"], rods=d["rods"])
@@ -199,6 +200,113 @@ def batched_form(steps, warmup, n_lattices=64):
     return out
 
 
+def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=50, log_fn=None):
+    """Learned surrogate: LBM trajectories of the droplet sweep (physically
+    placed rods) restricted to the 128 x 64 x 32 canvas every `interval` steps;
+    the U-Net is trained with the library's kernels on the first 7/8 of the
+    droplets and evaluated on the rest against persistence and linear
+    extrapolation; then one interval of one 256 x 128 x 64 test droplet is
+    timed both ways: `interval` LBM steps against restrict + network + lift +
+    K re-equilibration steps."""
+    import torch
+
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Batch, Lattice
+    from tests import cases
+
+    D, H, W = 32, 64, 128
+    specs = list(inputs.sweep_droplets(n_droplets, placement="physical"))
+
+    def make(d):
+        c = dict(shape=d["shape"], periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+                 body_force=(0.0, 0.0, 0.0))
+        lp = rod_params(cases.lattice_params(c, "f32"), length=d["rod_length"])
+        lp.eps_att = d["eps_att"]
+        return Lattice(lp, d["rho"], d["mat"], rods=d["rods"] if d["rods"] is not None and len(d["rods"]) else None)
+
+    lats = [make(d) for d in specs]
+    batch = Batch(lats)
+    t0 = time.perf_counter()
+    xf, xb = SU.rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=warm)
+    t_gen = time.perf_counter() - t0
+    batch.close()
+    status = 0
+    for lat in lats:
+        status |= int(lat.observables(allow_unstable=True)["status"])
+        lat.close()
+    finite = torch.isfinite(xf.view(len(specs), n_snap, -1)).all(dim=2).cpu().numpy()
+    ntrain = len(specs) * 7 // 8
+    train = [(xf[i, s], xb[i, s], xf[i, s + 1]) for i in range(ntrain) for s in range(n_snap - 1)
+             if finite[i, s] and finite[i, s + 1]]
+    test = [(xf[i, s], xb[i, s], xf[i, s + 1]) for i in range(ntrain, len(specs)) for s in range(1, n_snap - 1)
+            if finite[i, s] and finite[i, s + 1] and finite[i, s - 1]]
+    prev = [xf[i, s - 1] for i in range(ntrain, len(specs)) for s in range(1, n_snap - 1)
+            if finite[i, s] and finite[i, s + 1] and finite[i, s - 1]]
+    net = SU.UNet(D, H, W).init(0)
+    t0 = time.perf_counter()
+    hist = SU.fit(net, train, epochs=epochs, batch=4, lr=1e-3, lam=100.0, log=log_fn)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = SU.evaluate(net, test, lam=100.0, prev=prev)
+    # forward throughput of the network (matrix-core work)
+    flops = sum(2.0 * 27 * (c1 + c2) * co * net.P[lvl] for _, c1, c2, co, _, lvl in net.layers)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.forward(test[0][1])
+    e0.record(stream)
+    for _ in range(10):
+        net.forward(test[0][1])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / 10
+    # one interval of a 256 x 128 x 64 test droplet, both ways
+    idx = max(range(ntrain, len(specs)), key=lambda i: np.prod(specs[i]["shape"]))
+    lat_a, lat_b = make(specs[idx]), make(specs[idx])
+    for lat in (lat_a, lat_b):
+        lat.coupled_step(warm)
+    xa_f, xa_b = SU.restrict(lat_a, D, H, W)
+    m0 = lat_a.observables(allow_unstable=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat_a.coupled_step(interval)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_lbm = e0.elapsed_time(e1)
+    pf = torch.empty_like(xa_f)
+    e0.record(stream)
+    xs_f, xs_b = SU.restrict(lat_b, D, H, W)
+    SU.predict(net, xs_f, xs_b, pred_f32=pf)
+    SU.jump_rods(lat_b, xs_f, pf, D, H, W, interval)
+    SU.lift(lat_b, pf, D, H, W)
+    lat_b.coupled_step(K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sur = e0.elapsed_time(e1)
+    ma = lat_a.observables(allow_unstable=True)
+    mb = lat_b.observables(allow_unstable=True)
+    mass_err = float(abs(mb["mass"][0] - ma["mass"][0]) / ma["mass"][0])
+    # deposit density: z-projected rod occupancy maps, L1 over the total
+    ra, rb = lat_a.rod_map(), lat_b.rod_map()
+    dep_err = float(np.abs(ra - rb).sum() / max(1, ra.sum())) if ra.sum() else 0.0
+    lat_a.close()
+    lat_b.close()
+    out = {
+        "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
+        "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),
+        "data_generation_s": t_gen, "train_s": t_train, "epochs": epochs, "train_loss": hist,
+        "test_loss": ev, "gain_over_persistence": ev["persistence"] / max(ev["net"], 1e-30),
+        "fwd_ms": ms_fwd, "fwd_tflops": flops / (ms_fwd * 1e-3) / 1e12, "fwd_gflop_per_sample": flops / 1e9,
+        "ms_lbm_interval": ms_lbm, "ms_surrogate_interval": ms_sur, "speedup": ms_lbm / ms_sur,
+        "mass_error_vs_lbm": mass_err, "deposit_error_vs_lbm": dep_err,
+        "fallback_threshold": 0.005, "would_fall_back": mass_err > 0.005, "status": status,
+    }
+    if log_fn:
+        log_fn(f"[surrogate] gain over persistence x{out['gain_over_persistence']:.2f}, speedup x{out['speedup']:.2f}, "
+               f"mass error {mass_err:.2e}, forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s)")
+    return out
+
+
 def cpu_baseline(case, sample_steps):
     from oracle import lbm
     from tests import cases
@@ -226,7 +334,12 @@ def main():
     ap.add_argument("--forms", type=int, default=1, help="also time the FP16/BF16 storage forms")
     ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
+    ap.add_argument("--surrogate-epochs", type=int, default=6)
+    ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
     args = ap.parse_args()
+    global TILE_CACHE
+    TILE_CACHE = args.tile_cache
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -280,6 +393,11 @@ def main():
         log(f"[bench] batched form: {args.batched} droplets of the sweep")
         batched = batched_form(args.batched_steps, 2, args.batched)
 
+    sur = None
+    if args.surrogate > 0:
+        log(f"[bench] surrogate form: {args.surrogate} droplets")
+        sur = surrogate_form(args.surrogate, epochs=args.surrogate_epochs, log_fn=log)
+
     cpu = None
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps of the same lattice")
@@ -318,6 +436,7 @@ def main():
         },
         "forms": forms,
         "batched": batched,
+        "surrogate": sur,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

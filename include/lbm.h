@@ -269,24 +269,48 @@ int lb_batch_step(lb_batch *b, int32_t nsteps, int32_t with_rods, int32_t use_gr
 int lb_batch_destroy(lb_batch *b);
 
 /*
- * Learned surrogate (the benchmark spec form (4); the paper has none).  A coarse
- * canvas is [D][H][W][8] channels-last: rho_A, rho_B, u_x, u_y, u_z (means over
- * the fluid nodes of each 2 x 2 x 2 block, u = sum_k sum_i f*_i c_i / sum_k
- * rho_k), rod volume fraction, domain mask (1 inside the lattice), 0.  The
- * lattice occupies cells [0, n/2) per axis (n even, n/2 <= canvas size);
- * cells outside hold gas (0.03, 1), zero velocity and mask 0.
+ * Learned surrogate (a 3-D convolutional U-Net advancing coarse-grained
+ * fields; the paper has none).  A coarse canvas is [D][H][W][8]
+ * channels-last: rho_A, rho_B, u_x, u_y, u_z, rod volume fraction, domain
+ * mask (1 inside the lattice), fluid fraction (fluid nodes / 8).  Densities
+ * are means over the fluid nodes of each 2 x 2 x 2 block; u is the block's
+ * physical velocity sum (j + F/2) / sum rho over those nodes (Eq. 5 force F,
+ * the velocity the method reports), read off the stored post-collision state
+ * as j* - F/2.  The lattice occupies cells [0, n/2) per axis (n even, n/2 <=
+ * canvas size); cells outside hold gas (0.03, 1), zero velocity, mask 0 and
+ * fluid fraction 0.
  *
  * lb_sur_restrict : canvas of the current state into coarse_f32 and/or
  *                   coarse_bf16 (device, caller-owned, nullable one of them).
- * lb_sur_lift     : trilinear prolongation of channels 0..4 of coarse (device
- *                   FP32 canvas) to the lattice, then f = f^eq(rho_k, u) (Eq. 2)
- *                   at every fluid node as the new current state; wall
- *                   bounce-back slots are refreshed, rods stay where they are.
- * Both asynchronous; LB_EINVAL on null pointers or a lattice that does not fit.
+ * lb_sur_lift     : prolongation of channels 0..4 of coarse (device FP32
+ *                   canvas) to every fluid node: trilinear from coarse
+ *                   coordinate x/2 - 1/4 over the corner cells holding fluid,
+ *                   renormalised (else the mean of the fluid-holding cells of
+ *                   the 4 x 4 x 4 block around them, else gas at rest); then
+ *                   the collision output of those fields becomes the current
+ *                   state: f_k = f^eq(rho_k, u - F/(2 rho) + tau_k F_k / rho_k)
+ *                   (Eq. 2) with F the force of the lifted densities; wall and
+ *                   rod bounce-back slots are refreshed.
+ * Both asynchronous; LB_EINVAL on null pointers or a lattice that does not
+ * fit.  Both use the context's other population buffer as scratch (it holds
+ * no state between steps).
  */
 int lb_sur_restrict(lb_ctx *ctx, int32_t D, int32_t H, int32_t W, float *coarse_f32, void *coarse_bf16,
                     hipStream_t stream);
 int lb_sur_lift(lb_ctx *ctx, const float *coarse_f32, int32_t D, int32_t H, int32_t W, hipStream_t stream);
+/* Rods over a surrogate jump of `steps` lattice steps: each centre moves by
+ * steps x the mean of the coarse velocities of coarse_now and coarse_next
+ * (trilinear at the centre, from coarse coordinate x/2 - 1/4; kept one node
+ * off closed end planes), V takes that mean, orientation and angular momentum
+ * are kept.  A rods-only relaxation then removes the overlaps the move made:
+ * Jacobi sweeps move both rods of a pair whose axis segments are closer than
+ * rod_d0 apart by half the deficit along the closest-point direction (and a
+ * rod whose axis end is closer than rod_d0_wall to the wall up), until no
+ * deficit exceeds 1e-6 or 200 sweeps are done.  The rods are then re-placed
+ * (rod nodes recomputed, no mass booked).  Call before lb_sur_lift, which
+ * fills the vacated nodes.  Asynchronous. */
+int lb_sur_jump_rods(lb_ctx *ctx, const float *coarse_now, const float *coarse_next, int32_t D, int32_t H, int32_t W,
+                     double steps, hipStream_t stream);
 
 /*
  * 3-D convolution, 3 x 3 x 3 taps, zero padding, channels-last BF16 tensors
@@ -330,18 +354,24 @@ int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_
                     hipStream_t stream);
 int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream);        /* graph-safe clear */
 int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream);       /* round to nearest even */
-/* Network prediction on P canvas cells: pred[:, 0:6] = xin[:, 0:6] + out[:, 0:6]
- * (residual), channels 6, 7 copied from xin; into pred (FP32) and/or pred_bf16. */
-int lb_sur_residual(const float *out, const float *xin, int64_t P, float *pred, void *pred_bf16, hipStream_t stream);
-/* Surrogate loss over P cells of [P][8] FP32 tensors: pred = xin[0:6] +
- * out[0:6], mask = xin[6]; loss = masked mean of (pred - tgt)^2 over the six
- * channels + lam * (relative rho_A mass error)^2.  grad (nullable) [P][8]
- * receives dloss/dout.  scratch: device, lb_sur_loss_scratch_bytes() bytes.
- * result_host (nullable; the call then synchronises): sum mask, sum mask tgt_A,
- * relative mass error, loss. */
+/* Network prediction on P canvas cells: pred[:, c] = xin[:, c] + scale[c] *
+ * out[:, c] for c < 6 (residual; scale: host, 6 positive values, null = 1),
+ * channels 6, 7 copied from xin; into pred (FP32) and/or pred_bf16. */
+int lb_sur_residual(const float *out, const float *xin, int64_t P, const float *scale, float *pred, void *pred_bf16,
+                    hipStream_t stream);
+/* Surrogate loss over P cells of [P][8] FP32 tensors in channel-normalised
+ * units: pred = xin[0:6] + scale * out[0:6], e = (pred - tgt) / scale, mask =
+ * xin[6]; loss = masked mean of e^2 over the six channels + lam * (relative
+ * rho_A mass error)^2.  grad (nullable) [P][8] receives dloss/dout.  scratch:
+ * device, lb_sur_loss_scratch_bytes() bytes.  result_host (nullable; the call
+ * then synchronises): sum mask, sum mask tgt_A, relative mass error, loss. */
 size_t lb_sur_loss_scratch_bytes(void);
-int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, float *grad, void *scratch,
-                double *result_host, hipStream_t stream);
+int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, const float *scale, double lam,
+                float *grad, void *scratch, double *result_host, hipStream_t stream);
+/* Per-channel sums over P cells of mask * (y - x)^2 (channels 0..5) and of the
+ * mask (xin channel 6) into result_host[7]; the scratch of lb_sur_loss.
+ * Synchronises. */
+int lb_sur_moments(const float *x, const float *y, int64_t P, void *scratch, double *result_host, hipStream_t stream);
 /* Adam (Kingma and Ba) with bias correction on n FP32 master parameters p
  * with moments m, v; p_bf16 (nullable) receives the rounded copy.  step >= 1. */
 int lb_adam(float *p, const float *g, float *m, float *v, void *p_bf16, int64_t n, int32_t step, double lr, double b1,

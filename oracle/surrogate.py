@@ -3,18 +3,31 @@ convolutions with their gradients, the U-Net and Adam.
 
 TEST INFRASTRUCTURE ONLY -- never imported by the product path.
 
-What it follows (the benchmark spec form (4): a small 3-D convolutional encoder-decoder
+What it follows (a learned surrogate: a small 3-D convolutional encoder-decoder
 advancing coarse-grained fields of the lattice Boltzmann state; the paper
 itself has no surrogate):
 * restriction: 2 x 2 x 2 block means onto a coarse canvas of the channels
-  rho_A, rho_B, u_x, u_y, u_z (means over the block's fluid nodes, with
-  u = sum_k sum_i f*_i c_i / sum_k rho_k of the stored state), the rod volume
-  fraction (rod nodes / 8) and a domain mask (1 inside the lattice); canvas
-  cells outside a smaller lattice hold gas (rho_A 0.03, rho_B 1), zero
-  velocity and mask 0;
+  rho_A, rho_B, u_x, u_y, u_z (densities are means over the block's fluid
+  nodes; u is the block's physical velocity, sum of (j* - F/2) over its fluid
+  nodes divided by their summed density, where j* = sum_k sum_i f*_i c_i is
+  the momentum of the stored post-collision state and F = F_A + F_B the
+  Shan-Chen plus body force of its densities (Eq. 5), so that with equal tau
+  the momentum before collision is j* - F and the velocity u = (j + F/2) / rho
+  the one the method reports), the rod volume
+  fraction (rod nodes / 8), a domain mask (1 inside the lattice) and the
+  fluid fraction (fluid nodes / 8); canvas cells outside a smaller lattice
+  hold gas (rho_A 0.03, rho_B 1), zero velocity, mask 0 and fluid fraction 0;
 * prolongation: trilinear interpolation of rho_A, rho_B, u at fine node x from
-  coarse coordinate x / 2 - 1/4 (clamped to the lattice's own coarse extent),
-  then f_i^k = f_i^eq(rho_k, u) (Eq. 2) at fluid nodes;
+  coarse coordinate x / 2 - 1/4 (clamped to the lattice's own coarse extent)
+  over the corner cells that hold fluid (fluid fraction > 0), the weights
+  renormalised; when none of the 8 corners holds fluid, the plain mean of the
+  fluid-holding cells of the 4 x 4 x 4 block around them, and gas at rest
+  when there is none either; then the post-collision state of those fields:
+  with F_k the force of the prolonged densities (Eq. 5), u' = u - F / (2 rho)
+  and u_k^eq = u' + tau_k F_k / rho_k (the velocity shift of the collision),
+  (u' alone where rho_k < 1e-12), f_i^k = f_i^eq(rho_k, u_k^eq) (Eq. 2) at
+  fluid nodes, so that restricting
+  the lifted state node by node gives back rho_k and u;
 * convolution: y[p, o] = b[o] + sum_{t, c} x[p + o_t, c] w[t, c, o] over the
   27 taps o_t in {-1, 0, 1}^3 with zero padding, channels-last tensors;
   input gradient dx[q, c] = sum_{t, o} g[q - o_t, o] w[t, c, o]; weight
@@ -23,8 +36,9 @@ itself has no surrogate):
   per level, 2 x 2 x 2 average pooling down, nearest-neighbour upsampling and
   channel concatenation of the skip on the way up, a final linear
   convolution to the six predicted channels added to the input (residual);
-* loss: masked mean squared error over the six channels plus lambda times the
-  squared relative mass error of rho_A;
+* loss: masked mean squared error over the six channels, each channel in
+  units of its own scale (the RMS change of that channel over the training
+  interval), plus lambda times the squared relative mass error of rho_A;
 * Adam (Kingma and Ba) with bias correction.
 """
 from __future__ import annotations
@@ -40,16 +54,19 @@ TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0,
 # ---------------------------------------------------------------------------
 # restriction / prolongation
 # ---------------------------------------------------------------------------
-def restrict(f, material, canvas):
-    """Coarse canvas [D, H, W, 7] (FP64) of a lattice state f[2, 19, nz, ny, nx]."""
+def restrict(f, material, canvas, p):
+    """Coarse canvas [D, H, W, 8] (FP64) of a stored post-collision state
+    f[2, 19, nz, ny, nx] with the lattice parameters p (lbm.Params)."""
     D, H, W = canvas
     nz, ny, nx = material.shape
     fluid = material == lbm.FLUID
-    rho = np.where(fluid, f.sum(axis=1), 0.0)  # [2, nz, ny, nx]
+    rho_all = f.sum(axis=1)
+    F = lbm.sc_force(lbm.pseudopotential(rho_all, material, p), rho_all, p)
+    rho = np.where(fluid, rho_all, 0.0)  # [2, nz, ny, nx]
     C = lbm.C.astype(np.float64)
-    mom = np.einsum("kizyx,id->dzyx", f, C)
+    mom = np.einsum("kizyx,id->dzyx", f, C) - 0.5 * (F[0] + F[1])
     mom = np.where(fluid[None], mom, 0.0)
-    out = np.zeros((D, H, W, 7))
+    out = np.zeros((D, H, W, 8))
     out[..., 0], out[..., 1] = GAS
     for cz in range(D):
         for cy in range(H):
@@ -59,7 +76,7 @@ def restrict(f, material, canvas):
                     continue  # outside the lattice: gas, mask 0
                 blk = (slice(z0, z0 + 2), slice(y0, y0 + 2), slice(x0, x0 + 2))
                 nf = int(fluid[blk].sum())
-                cell = np.zeros(7)
+                cell = np.zeros(8)
                 if nf:
                     r = rho[(slice(None),) + blk].reshape(2, -1).sum(axis=1)
                     m = mom[(slice(None),) + blk].reshape(3, -1).sum(axis=1)
@@ -68,6 +85,7 @@ def restrict(f, material, canvas):
                     cell[2:5] = m / tot if tot > 0 else 0.0
                 cell[5] = float((material[blk] == lbm.ROD).sum()) / 8.0
                 cell[6] = 1.0
+                cell[7] = nf / 8.0
                 out[cz, cy, cx] = cell
     return out
 
@@ -87,35 +105,61 @@ def _lerp_axis(n_fine, n_coarse):
 
 
 def prolong(coarse, material):
-    """Fine (rho[2], u[3]) on the lattice from coarse [D, H, W, >=5] fields; the
+    """Fine (rho[2], u[3]) on the lattice from coarse [D, H, W, 8] fields; the
     lattice occupies coarse cells [0, n/2) per axis."""
     nz, ny, nx = material.shape
     cz, cy, cx = nz // 2, ny // 2, nx // 2
     a = coarse[:cz, :cy, :cx, :5]
+    ok = coarse[:cz, :cy, :cx, 7] > 0
     lz, hz, wz = _lerp_axis(nz, cz)
     ly, hy, wy = _lerp_axis(ny, cy)
     lx, hx, wx = _lerp_axis(nx, cx)
+    gas = np.array([GAS[0], GAS[1], 0.0, 0.0, 0.0])
     out = np.zeros((nz, ny, nx, 5))
     for z in range(nz):
         for y in range(ny):
             for x in range(nx):
                 acc = np.zeros(5)
+                wsum = 0.0
                 for iz, fz in ((lz[z], 1 - wz[z]), (hz[z], wz[z])):
                     for iy, fy in ((ly[y], 1 - wy[y]), (hy[y], wy[y])):
                         for ix, fx in ((lx[x], 1 - wx[x]), (hx[x], wx[x])):
-                            acc += fz * fy * fx * a[iz, iy, ix]
-                out[z, y, x] = acc
+                            if ok[iz, iy, ix]:
+                                wt = fz * fy * fx
+                                acc += wt * a[iz, iy, ix]
+                                wsum += wt
+                if wsum > 0:
+                    out[z, y, x] = acc / wsum
+                    continue
+                acc[:] = 0.0
+                cnt = 0
+                for iz in range(lz[z] - 1, lz[z] + 3):
+                    for iy in range(ly[y] - 1, ly[y] + 3):
+                        for ix in range(lx[x] - 1, lx[x] + 3):
+                            if 0 <= iz < cz and 0 <= iy < cy and 0 <= ix < cx and ok[iz, iy, ix]:
+                                acc += a[iz, iy, ix]
+                                cnt += 1
+                out[z, y, x] = acc / cnt if cnt else gas
     rho = np.moveaxis(out[..., 0:2], -1, 0)
     u = np.moveaxis(out[..., 2:5], -1, 0)
     return rho, u
 
 
-def lift(coarse, material):
-    """Post-collision state f = f^eq(rho_k, u) (Eq. 2) at fluid nodes, 0 elsewhere."""
+def lift(coarse, material, p):
+    """Post-collision state f^k = f^eq(rho_k, u_k^eq) (Eq. 2) of the prolonged
+    fields at fluid nodes, 0 elsewhere; u_k^eq = u - F / (2 rho) + tau_k F_k /
+    rho_k with F_k the force (Eq. 5) of the prolonged densities."""
     rho, u = prolong(coarse, material)
     fluid = material == lbm.FLUID
-    f = np.stack([lbm.equilibrium(rho[k], u) for k in range(2)])
-    return np.where(fluid[None, None], f, 0.0)
+    F = lbm.sc_force(lbm.pseudopotential(rho, material, p), rho, p)
+    tot = np.where(fluid, rho[0] + rho[1], 1.0)
+    up = u - 0.5 * (F[0] + F[1]) / tot
+    f = []
+    for k in range(2):
+        ok = fluid & (rho[k] >= 1e-12)  # the shift is skipped for a vanishing component
+        ueq = np.where(ok, up + p.tau[k] * F[k] / np.where(ok, rho[k], 1.0), up)
+        f.append(lbm.equilibrium(rho[k], ueq))
+    return np.where(fluid[None, None], np.stack(f), 0.0)
 
 
 # ---------------------------------------------------------------------------
@@ -288,16 +332,18 @@ def unet_backward(gy, P, cache, ch=CH):
     return G
 
 
-def loss(pred, target, mask, lam):
-    """Masked MSE over the six channels + lam * (relative rho_A mass error)^2,
-    and its gradient with respect to pred."""
+def loss(pred, target, mask, lam, scale=None):
+    """Masked MSE over the six channels in channel-normalised units
+    e_c = (pred_c - target_c) / scale_c, plus lam * (relative rho_A mass
+    error)^2, and its gradient with respect to pred."""
+    s = np.ones(OUT_CH) if scale is None else np.asarray(scale, dtype=np.float64)
     m = mask[..., None]
     n = mask.sum()
-    diff = (pred - target) * m
+    diff = (pred - target) / s * m
     mse = float((diff * diff).sum() / (OUT_CH * n))
     mt = float((mask * target[..., 0]).sum())
     me = float((mask * (pred[..., 0] - target[..., 0])).sum()) / mt
-    g = 2.0 * diff / (OUT_CH * n)
+    g = 2.0 * diff / s / (OUT_CH * n)
     g[..., 0] += 2.0 * lam * me * mask / mt
     return mse + lam * me * me, g
 

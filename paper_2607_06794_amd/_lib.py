@@ -42,6 +42,7 @@ EXPORTS = (
     "lb_batch_destroy",
     "lb_sur_restrict",
     "lb_sur_lift",
+    "lb_sur_jump_rods",
     "lb_conv3d_forward",
     "lb_conv3d_backward_data",
     "lb_conv3d_backward_weights",
@@ -51,6 +52,7 @@ EXPORTS = (
     "lb_fill_f32",
     "lb_to_bf16",
     "lb_sur_residual",
+    "lb_sur_moments",
     "lb_sur_loss_scratch_bytes",
     "lb_sur_loss",
     "lb_adam",
@@ -248,6 +250,7 @@ def load(path: str = LIB_PATH):
     sigs = {
         "lb_sur_restrict": [V, I32, I32, I32, V, V, V],
         "lb_sur_lift": [V, V, I32, I32, I32, V],
+        "lb_sur_jump_rods": [V, V, V, I32, I32, I32, D_, V],
         "lb_conv3d_forward": [P(LbConv), V],
         "lb_conv3d_backward_data": [P(LbConv), V, V, V],
         "lb_conv3d_backward_weights": [P(LbConv), V, V, V, V],
@@ -256,8 +259,9 @@ def load(path: str = LIB_PATH):
         "lb_up2_backward": [V, I32, I32, I32, I32, I32, V, V],
         "lb_fill_f32": [V, I64, ct.c_float, V],
         "lb_to_bf16": [V, I64, V, V],
-        "lb_sur_loss": [V, V, V, I64, D_, V, V, V, V],
-        "lb_sur_residual": [V, V, I64, V, V, V],
+        "lb_sur_loss": [V, V, V, I64, V, D_, V, V, V, V],
+        "lb_sur_residual": [V, V, I64, V, V, V, V],
+        "lb_sur_moments": [V, V, I64, V, V, V],
         "lb_adam": [V, V, V, V, V, I64, I32, D_, D_, D_, D_, V],
     }
     for name, args in sigs.items():

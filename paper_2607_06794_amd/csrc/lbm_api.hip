@@ -728,12 +728,43 @@ static bool canvas_fits(const lb_params &p, int D, int H, int W) {
            p.ny / 2 <= H && p.nz / 2 <= D;
 }
 
+}  // extern "C"
+
+// Restriction and lift read the Shan-Chen force of the state they read or
+// write.  Its psi field goes to the context's other population buffer: between
+// steps that buffer holds nothing the next step reads before writing it (the
+// step rewrites every fluid node and every wall and rod slot), and it holds at
+// least 38 x 2 bytes per node, more than the 16 the field takes.
+static SurLattice sur_lattice(lb_ctx *c) {
+    const lb_params &p = c->p;
+    SurLattice L{};
+    L.mat = c->mat;
+    L.nx = p.nx;
+    L.ny = p.ny;
+    L.nz = p.nz;
+    L.px = p.periodic[0];
+    L.py = p.periodic[1];
+    L.pz = p.periodic[2];
+    L.fs = c->fs;
+    for (int k = 0; k < 2; ++k) {
+        L.rref[k] = c->rref[k];
+        L.tau[k] = p.tau[k];
+    }
+    L.G = p.G;
+    for (int d = 0; d < 3; ++d) L.g[d] = p.body_force[d];
+    L.psi_tab = c->psi;
+    L.psi = static_cast<double *>(c->f[c->cur ^ 1]);
+    return L;
+}
+
+extern "C" {
+
 int lb_sur_restrict(lb_ctx *c, int32_t D, int32_t H, int32_t W, float *coarse_f32, void *coarse_bf16,
                     hipStream_t stream) {
     if (!c || (!coarse_f32 && !coarse_bf16)) return fail(LB_EINVAL, "null argument");
     const lb_params &p = c->p;
     if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
-    HIP_TRY(launch_restrict(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, c->rref, D, H, W, coarse_f32,
+    HIP_TRY(launch_restrict(p.prec, c->f[c->cur], sur_lattice(c), D, H, W, coarse_f32,
                             static_cast<uint16_t *>(coarse_bf16), stream),
             "restrict");
     return LB_OK;
@@ -743,10 +774,29 @@ int lb_sur_lift(lb_ctx *c, const float *coarse_f32, int32_t D, int32_t H, int32_
     if (!c || !coarse_f32) return fail(LB_EINVAL, "null argument");
     const lb_params &p = c->p;
     if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
-    HIP_TRY(launch_lift(p.prec, coarse_f32, D, H, W, c->mat, p.nx, p.ny, p.nz, c->f[c->cur], c->fs, c->rref, stream),
-            "lift");
+    HIP_TRY(launch_lift(p.prec, coarse_f32, D, H, W, sur_lattice(c), c->f[c->cur], stream), "lift");
     const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
     HIP_TRY(launch_slot_fill(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, per, stream), "lift slots");
+    // moving bounce-back slots of the rods for the lifted state
+    if (p.n_rods > 0)
+        HIP_TRY(launch_rods_link(p.prec, c->rodargs_host[c->cur], RodBatch{c->rodargs_dev + c->cur, nullptr}, stream),
+                "lift rod links");
+    return LB_OK;
+}
+
+int lb_sur_jump_rods(lb_ctx *c, const float *coarse_now, const float *coarse_next, int32_t D, int32_t H, int32_t W,
+                     double steps, hipStream_t stream) {
+    if (!c || !coarse_now || !coarse_next) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
+    if (!(steps >= 0)) return fail(LB_EINVAL, "negative jump length");
+    if (p.n_rods == 0) return LB_OK;
+    const RodArgs &a = c->rodargs_host[c->cur];
+    const RodBatch bt{c->rodargs_dev + c->cur, nullptr};
+    HIP_TRY(launch_rods_jump(a, bt, coarse_now, coarse_next, D, H, W, steps, stream), "rod jump");
+    HIP_TRY(launch_rods_place(p.prec, a, bt, stream), "re-place rods");
+    const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
+    HIP_TRY(launch_flags(c->mat, p.nx, p.ny, p.nz, per, stream), "flags after the jump");
     return LB_OK;
 }
 
@@ -839,24 +889,51 @@ int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream) {
     return LB_OK;
 }
 
-int lb_sur_residual(const float *out, const float *xin, int64_t P, float *pred, void *pred_bf16, hipStream_t stream) {
+static int chan_scale(const float *scale, ChanScale &sc) {
+    for (int c = 0; c < 8; ++c) sc.s[c] = 1.0f;
+    if (scale)
+        for (int c = 0; c < 6; ++c) {
+            if (!(scale[c] > 0.0f)) return fail(LB_EINVAL, "channel scale %d must be positive", c);
+            sc.s[c] = scale[c];
+        }
+    return LB_OK;
+}
+
+int lb_sur_residual(const float *out, const float *xin, int64_t P, const float *scale, float *pred, void *pred_bf16,
+                    hipStream_t stream) {
     if (!out || !xin || (!pred && !pred_bf16) || P < 1) return fail(LB_EINVAL, "bad residual arguments");
-    HIP_TRY(launch_residual(out, xin, P, pred, static_cast<uint16_t *>(pred_bf16), stream), "residual");
+    ChanScale sc;
+    int rc = chan_scale(scale, sc);
+    if (rc) return rc;
+    HIP_TRY(launch_residual(out, xin, P, sc, pred, static_cast<uint16_t *>(pred_bf16), stream), "residual");
     return LB_OK;
 }
 
 size_t lb_sur_loss_scratch_bytes(void) { return SUR_LOSS_SCRATCH * sizeof(double); }
 
-int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, float *grad, void *scratch,
-                double *result_host, hipStream_t stream) {
+int lb_sur_loss(const float *out, const float *xin, const float *tgt, int64_t P, const float *scale, double lam,
+                float *grad, void *scratch, double *result_host, hipStream_t stream) {
     if (!out || !xin || !tgt || !scratch || P < 1) return fail(LB_EINVAL, "bad loss arguments");
+    ChanScale sc;
+    int rc = chan_scale(scale, sc);
+    if (rc) return rc;
     double *part = static_cast<double *>(scratch);
-    double *res = part + 256 * 4;
-    HIP_TRY(launch_loss(out, xin, tgt, P, lam, part, res, grad, stream), "loss");
+    double *res = part + 256 * 7;
+    HIP_TRY(launch_loss(out, xin, tgt, P, sc, lam, part, res, grad, stream), "loss");
     if (result_host) {
         HIP_TRY(hipMemcpyAsync(result_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy loss");
         HIP_TRY(hipStreamSynchronize(stream), "loss sync");
     }
+    return LB_OK;
+}
+
+int lb_sur_moments(const float *x, const float *y, int64_t P, void *scratch, double *result_host, hipStream_t stream) {
+    if (!x || !y || !scratch || !result_host || P < 1) return fail(LB_EINVAL, "bad moments arguments");
+    double *part = static_cast<double *>(scratch);
+    double *res = part + 256 * 7;
+    HIP_TRY(launch_moments(x, y, P, part, res, stream), "moments");
+    HIP_TRY(hipMemcpyAsync(result_host, res, 7 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy moments");
+    HIP_TRY(hipStreamSynchronize(stream), "moments sync");
     return LB_OK;
 }
 

@@ -82,6 +82,12 @@ hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hip
 hipError_t launch_rods_step(int prec, const RodBatch &bt, int n_lat, int total_rods, int nblk_max, int max_rods,
                             hipStream_t s);
 hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s);
+// surrogate jump of one lattice's rods: centres advected by `steps` times the
+// mean of the coarse velocities of canvases c0 and c1 ([D][H][W][8]); then all
+// rod nodes are returned to fluid (re-place with launch_rods_place)
+hipError_t launch_rods_jump(const RodArgs &a, const RodBatch &bt, const float *c0, const float *c1, int D, int H, int W,
+                            double steps, hipStream_t s);
+hipError_t launch_rods_link(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s);
 
 hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s);
 // all: device array of per-lattice step records; work: device list of
@@ -155,16 +161,30 @@ hipError_t launch_pool2_back(const float *gc, const float *skip, int skip_stride
 hipError_t launch_up2_back(const float *g, int stride, int C, int D, int H, int W, float *gc, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s);
-hipError_t launch_residual(const float *out, const float *xin, int64_t P, float *pred, uint16_t *predb, hipStream_t s);
-constexpr int SUR_LOSS_SCRATCH = 256 * 4 + 8;  // doubles
-hipError_t launch_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, double *part,
-                       double *res, float *grad, hipStream_t s);
+struct ChanScale {
+    float s[8];  // per-channel output scale of the network (channels 0..5)
+};
+hipError_t launch_residual(const float *out, const float *xin, int64_t P, const ChanScale &sc, float *pred,
+                           uint16_t *predb, hipStream_t s);
+constexpr int SUR_LOSS_SCRATCH = 256 * 7 + 8;  // doubles
+hipError_t launch_loss(const float *out, const float *xin, const float *tgt, int64_t P, const ChanScale &sc, double lam,
+                       double *part, double *res, float *grad, hipStream_t s);
+hipError_t launch_moments(const float *x, const float *y, int64_t P, double *part, double *res, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, int step, float lr, float b1,
                        float b2, float eps, hipStream_t s);
-hipError_t launch_restrict(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
-                           const double rref[2], int D, int H, int W, float *outf, uint16_t *outb, hipStream_t s);
-hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const uint8_t *mat, int nx, int ny, int nz,
-                       void *f, int64_t fs, const double rref[2], hipStream_t s);
+// What restriction and lift need of a lattice: geometry, storage and the
+// Shan-Chen force parameters; psi is scratch of 2 x nx ny nz doubles
+struct SurLattice {
+    const uint8_t *mat;
+    int nx, ny, nz, px, py, pz;
+    int64_t fs;
+    double rref[2], tau[2], G, g[3];
+    const double *psi_tab;  // [16][2] ghost pseudo-densities per material id (device)
+    double *psi;            // [2][nx ny nz] scratch
+};
+hipError_t launch_restrict(int prec, const void *f, const SurLattice &L, int D, int H, int W, float *outf,
+                           uint16_t *outb, hipStream_t s);
+hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const SurLattice &L, void *f, hipStream_t s);
 
 constexpr int OBS_BLOCKS = 512;
 constexpr int OBS_FIELDS = 10;

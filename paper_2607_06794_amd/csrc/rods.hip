@@ -791,6 +791,139 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
 }
 
 // ---------------------------------------------------------------------------
+// 6. surrogate jumps: advect the rods with the time-averaged coarse velocity
+//    of the canvases before and after the jump, then re-place them
+// ---------------------------------------------------------------------------
+// centre height that keeps a capsule of axis e off the closed end planes: one
+// fluid node between its surface and each plane
+__device__ inline double clamp_ends(const RodArgs &a, d3 e, double z) {
+    const double ez = fabs(e.z) * a.half + a.radius;
+    return fmin(fmax(z, 1.5 + ez), a.nz - 2.5 - ez);
+}
+
+__device__ inline void coarse_velocity(const float *c, int D, int H, int W, int ncz, int ncy, int ncx, d3 p, double u[3]) {
+    const double q[3] = {p.z / 2.0 - 0.25, p.y / 2.0 - 0.25, p.x / 2.0 - 0.25};
+    const int n[3] = {ncz, ncy, ncx};
+    int i0[3], i1[3];
+    double w[3];
+    for (int d = 0; d < 3; ++d) {
+        const double v = fmin(fmax(q[d], 0.0), n[d] - 1.0);
+        i0[d] = int(floor(v));
+        i1[d] = min(i0[d] + 1, n[d] - 1);
+        w[d] = v - i0[d];
+    }
+    u[0] = u[1] = u[2] = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const int iz = (j >> 2) ? i1[0] : i0[0], iy = ((j >> 1) & 1) ? i1[1] : i0[1], ix = (j & 1) ? i1[2] : i0[2];
+        const double wt = ((j >> 2) ? w[0] : 1.0 - w[0]) * (((j >> 1) & 1) ? w[1] : 1.0 - w[1]) * ((j & 1) ? w[2] : 1.0 - w[2]);
+        const float *cc = c + ((int64_t(iz) * H + iy) * W + ix) * 8;
+        for (int d = 0; d < 3; ++d) u[d] += wt * double(cc[2 + d]);
+    }
+}
+
+__global__ void rod_jump_kernel(RodBatch bt, const float *c0, const float *c1, int D, int H, int W, double steps) {
+    const RodArgs a = bt.all[0];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_rods) return;
+    double *rod = a.rods + r * ROD_STRIDE;
+    d3 X = ld3(rod + ROD_X);
+    double ua[3], ub[3];
+    coarse_velocity(c0, D, H, W, a.nz / 2, a.ny / 2, a.nx / 2, X, ua);
+    coarse_velocity(c1, D, H, W, a.nz / 2, a.ny / 2, a.nx / 2, X, ub);
+    const d3 V = mk(0.5 * (ua[0] + ub[0]), 0.5 * (ua[1] + ub[1]), 0.5 * (ua[2] + ub[2]));
+    X = X + steps * V;
+    if (a.px) X.x = X.x - a.nx * floor(X.x / a.nx);
+    if (a.py) X.y = X.y - a.ny * floor(X.y / a.ny);
+    if (a.pz) X.z = X.z - a.nz * floor(X.z / a.nz);
+    if (!a.pz) X.z = clamp_ends(a, quat_axis(rod + ROD_Q), X.z);
+    st3(rod + ROD_X, X);
+    st3(rod + ROD_V, V);
+}
+
+// Rods-only relaxation after the advection of a jump: overlaps the jump made
+// (axis segments closer than the contact distance d0 of the excluded-volume
+// potential, or an axis end closer than d0_wall to the wall) are removed by
+// Jacobi projection, each rod of an overlapping pair moved half the deficit
+// along the closest-point direction, orientation kept, until no deficit
+// exceeds 1e-6 lattice units or RELAX_IT sweeps are done.  One work-group,
+// thread r owns rod r; centres live in LDS.
+constexpr int RELAX_IT = 200;
+
+__global__ void __launch_bounds__(LB_MAX_RODS) rod_relax_kernel(RodBatch bt) {
+    const RodArgs a = bt.all[0];
+    extern __shared__ double rl[];  // [max_rods][6]: centre, axis
+    __shared__ int busy;
+    const int r = threadIdx.x, n = a.n_rods;
+    const bool mine = r < n;
+    d3 X = mk(0, 0, 0), e = mk(0, 0, 0);
+    if (mine) {
+        X = ld3(a.rods + r * ROD_STRIDE + ROD_X);
+        e = quat_axis(a.rods + r * ROD_STRIDE + ROD_Q);
+        st3(rl + 6 * r, X);
+        st3(rl + 6 * r + 3, e);
+    }
+    const double reach = 2.0 * a.half + a.d0;  // centres farther apart never overlap
+    for (int it = 0; it < RELAX_IT; ++it) {
+        if (r == 0) busy = 0;
+        __syncthreads();
+        d3 push = mk(0, 0, 0);
+        bool deficit = false;
+        if (mine) {
+            const d3 pa = X - a.half * e, qa = X + a.half * e;
+            for (int s2 = 0; s2 < n; ++s2) {
+                if (s2 == r) continue;
+                const d3 Xs = ld3(rl + 6 * s2);
+                const d3 dx = min_image(Xs - X, a);
+                if (dot(dx, dx) >= reach * reach) continue;
+                const d3 es = ld3(rl + 6 * s2 + 3);
+                const d3 c = X + dx;  // image of s next to r
+                d3 ca, cb;
+                const double d = seg_seg(pa, qa, c - a.half * es, c + a.half * es, ca, cb);
+                if (d >= a.d0 - 1e-6) continue;
+                deficit = true;
+                d3 nrm;
+                if (d > 1e-9) {
+                    nrm = (1.0 / d) * (ca - cb);
+                } else {
+                    const double l = sqrt(dot(dx, dx));
+                    nrm = l > 1e-9 ? (-1.0 / l) * dx : mk(0, 0, r > s2 ? 1.0 : -1.0);
+                }
+                push = push + (0.5 * (a.d0 - d)) * nrm;
+            }
+            if (a.wall_on) {
+                const double h = fmin(pa.z, qa.z) - a.wall_z;
+                if (h < a.d0_wall - 1e-6) {
+                    deficit = true;
+                    push.z += a.d0_wall - h;
+                }
+            }
+        }
+        if (deficit) busy = 1;
+        __syncthreads();
+        const bool again = busy != 0;
+        if (mine && again) {
+            X = X + push;
+            if (a.px) X.x = X.x - a.nx * floor(X.x / a.nx);
+            if (a.py) X.y = X.y - a.ny * floor(X.y / a.ny);
+            if (a.pz) X.z = X.z - a.nz * floor(X.z / a.nz);
+            if (!a.pz) X.z = clamp_ends(a, e, X.z);
+            st3(rl + 6 * r, X);
+        }
+        __syncthreads();
+        if (!again) break;
+    }
+    if (mine) st3(a.rods + r * ROD_STRIDE + ROD_X, X);
+}
+
+// every rod node back to fluid, no rod ids (before a re-placement)
+__global__ void unrod_kernel(uint8_t *mat, int16_t *rodid, int64_t n) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < n; p += int64_t(gridDim.x) * blockDim.x) {
+        if ((mat[p] & MAT_ID_MASK) == MAT_ROD) mat[p] = MAT_FLUID;
+        rodid[p] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <class F>
@@ -824,6 +957,26 @@ hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hip
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 1);
         hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_rods_jump(const RodArgs &a, const RodBatch &bt, const float *c0, const float *c1, int D, int H, int W,
+                            double steps, hipStream_t s) {
+    if (a.n_rods == 0) return hipSuccess;
+    const int64_t n = int64_t(a.nx) * a.ny * a.nz;
+    hipLaunchKernelGGL(rod_jump_kernel, dim3((a.n_rods + 63) / 64), dim3(64), 0, s, bt, c0, c1, D, H, W, steps);
+    hipLaunchKernelGGL(rod_relax_kernel, dim3(1), dim3(LB_MAX_RODS), size_t(a.n_rods) * 6 * sizeof(double), s, bt);
+    hipLaunchKernelGGL(unrod_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.mat, a.rodid, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rods_link(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s) {
+    if (a.n_rods == 0) return hipSuccess;
+    const dim3 grid(a.nblk, a.n_rods);
+    return rods_by_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
         return hipGetLastError();
     });

@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -339,26 +341,29 @@ __global__ void fill_f32_kernel(float *p, int64_t n, float v) {
 }
 
 // ---------------------------------------------------------------------------
-// loss: masked MSE over 6 channels + lam (relative rho_A mass error)^2.
-// pred = xin[:, 0:6] + out[:, 0:6]; tensors [P][8] FP32, mask = xin[:, 6]
+// loss in channel-normalised units: pred = xin[:, 0:6] + s * out[:, 0:6],
+// e_c = (pred_c - tgt_c) / s_c, loss = masked mean of e^2 over the six
+// channels + lam (relative rho_A mass error)^2; tensors [P][8] FP32, mask =
+// xin[:, 6]
 // ---------------------------------------------------------------------------
 constexpr int LOSS_BLOCKS = 256;
 
 __global__ void __launch_bounds__(256) loss_partial_kernel(const float *out, const float *xin, const float *tgt, int64_t P,
-                                                           double *part) {
+                                                           ChanScale sc, double *part) {
     __shared__ double sh[4][4];
-    double s[4] = {0, 0, 0, 0};  // sum mask, sum mask tgt_A, sum mask (pred_A - tgt_A), sum mask sq
+    double s[4] = {0, 0, 0, 0};  // sum mask, sum mask tgt_A, sum mask (pred_A - tgt_A), sum mask e^2
     for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < P; p += int64_t(gridDim.x) * blockDim.x) {
         const float m = xin[p * 8 + 6];
         if (m == 0.0f) continue;
         double sq = 0.0;
         for (int c = 0; c < 6; ++c) {
-            const double d = double(xin[p * 8 + c]) + double(out[p * 8 + c]) - double(tgt[p * 8 + c]);
+            const double d = (double(xin[p * 8 + c]) + double(sc.s[c]) * double(out[p * 8 + c]) - double(tgt[p * 8 + c])) /
+                             double(sc.s[c]);
             sq += d * d;
         }
         s[0] += m;
         s[1] += m * double(tgt[p * 8]);
-        s[2] += m * (double(xin[p * 8]) + double(out[p * 8]) - double(tgt[p * 8]));
+        s[2] += m * (double(xin[p * 8]) + double(sc.s[0]) * double(out[p * 8]) - double(tgt[p * 8]));
         s[3] += m * sq;
     }
     for (int q = 0; q < 4; ++q) {
@@ -384,8 +389,8 @@ __global__ void loss_total_kernel(const double *part, int nb, double lam, double
     res[3] = (s[0] > 0.0 ? s[3] / (6.0 * s[0]) : 0.0) + lam * me * me;
 }
 
-__global__ void loss_grad_kernel(const float *out, const float *xin, const float *tgt, int64_t P, double lam,
-                                 const double *res, float *grad) {
+__global__ void loss_grad_kernel(const float *out, const float *xin, const float *tgt, int64_t P, ChanScale sc,
+                                 double lam, const double *res, float *grad) {
     const double n = res[0], mt = res[1], me = res[2];
     for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < P * 8; e += int64_t(gridDim.x) * blockDim.x) {
         const int64_t p = e >> 3;
@@ -393,12 +398,44 @@ __global__ void loss_grad_kernel(const float *out, const float *xin, const float
         const float m = xin[p * 8 + 6];
         double g = 0.0;
         if (c < 6 && m != 0.0f && n > 0.0) {
-            const double d = double(xin[e]) + double(out[e]) - double(tgt[e]);
+            const double sc_c = sc.s[c];
+            const double d = (double(xin[e]) + sc_c * double(out[e]) - double(tgt[e])) / sc_c;
             g = 2.0 * m * d / (6.0 * n);
-            if (c == 0 && mt != 0.0) g += 2.0 * lam * me * m / mt;
+            if (c == 0 && mt != 0.0) g += 2.0 * lam * me * m * sc_c / mt;
         }
         grad[e] = float(g);
     }
+}
+
+// per-channel sums of mask (y - x)^2 and of the mask over one pair of canvases
+__global__ void __launch_bounds__(256) moments_kernel(const float *x, const float *y, int64_t P, double *part) {
+    __shared__ double sh[4][7];
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < P; p += int64_t(gridDim.x) * blockDim.x) {
+        const double m = x[p * 8 + 6];
+        if (m == 0.0) continue;
+        for (int c = 0; c < 6; ++c) {
+            const double d = double(y[p * 8 + c]) - double(x[p * 8 + c]);
+            s[c] += m * d * d;
+        }
+        s[6] += m;
+    }
+    for (int q = 0; q < 7; ++q) {
+        double v = s[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) part[blockIdx.x * 7 + threadIdx.x] = sh[0][threadIdx.x] + sh[1][threadIdx.x] +
+                                                            sh[2][threadIdx.x] + sh[3][threadIdx.x];
+}
+
+__global__ void moments_total_kernel(const double *part, int nb, double *res) {
+    if (threadIdx.x != 0) return;
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 7; ++q) s[q] += part[b * 7 + q];
+    for (int q = 0; q < 7; ++q) res[q] = s[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -418,12 +455,13 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16
     }
 }
 
-// prediction of the network: pred[:, 0:6] = xin[:, 0:6] + out[:, 0:6], the rest
+// prediction of the network: pred[:, 0:6] = xin[:, 0:6] + s * out[:, 0:6], the rest
 // copied from the input; also the BF16 copy (next input of a rollout)
-__global__ void residual_kernel(const float *out, const float *xin, int64_t P, float *pred, uint16_t *predb) {
+__global__ void residual_kernel(const float *out, const float *xin, int64_t P, ChanScale sc, float *pred,
+                                uint16_t *predb) {
     for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < P * 8; e += int64_t(gridDim.x) * blockDim.x) {
         const int c = int(e & 7);
-        const float v = c < 6 ? xin[e] + out[e] : xin[e];
+        const float v = c < 6 ? xin[e] + sc.s[c] * out[e] : xin[e];
         if (pred) pred[e] = v;
         if (predb) predb[e] = f2bf(v);
     }
@@ -436,12 +474,66 @@ __global__ void to_bf16_kernel(const float *x, int64_t n, uint16_t *y) {
 
 // ---------------------------------------------------------------------------
 // restriction and lift
+//
+// Both work with the physical velocity u = (j + F/2) / rho of the method
+// (Eq. 5 force F, velocity shift of the collision).  The stored state is the
+// collision output f*, whose momentum is j* = j + F for equal relaxation
+// times, so a restriction reads u = (j* - F/2) / rho with F from the stored
+// densities, and a lift writes f*_k = f^eq(rho_k, u - F/(2 rho) + tau_k F_k /
+// rho_k) with F from the lifted densities.  The force needs psi of the
+// neighbours: a first pass writes psi_k of every node to scratch.
 // ---------------------------------------------------------------------------
+__device__ inline double psi_solid(const SurLattice &L, uint8_t m, int k) {
+    return L.psi_tab[2 * (m & MAT_ID_MASK) + k];
+}
+
+// F_k = -G psi_k(x) sum_i w_i psi_kbar(x + c_i) c_i + rho_k g at fluid node
+// (x, y, z) with densities rho (= psi on fluid); neighbours beyond a closed
+// end plane count as 0 (fluid nodes never reach them: the end planes are solid)
+__device__ inline void force_at(const SurLattice &L, int x, int y, int z, const double rho[2], double F[2][3]) {
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    double s[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int i = 1; i < Q; ++i) {
+        int xx = x + cx(i), yy = y + cy(i), zz = z + cz(i);
+        if (L.px) xx = (xx + L.nx) % L.nx;
+        if (L.py) yy = (yy + L.ny) % L.ny;
+        if (L.pz) zz = (zz + L.nz) % L.nz;
+        if (xx < 0 || xx >= L.nx || yy < 0 || yy >= L.ny || zz < 0 || zz >= L.nz) continue;
+        const int64_t m = (int64_t(zz) * L.ny + yy) * L.nx + xx;
+        for (int k = 0; k < 2; ++k) {
+            const double v = wgt<double>(i) * L.psi[(1 - k) * n_all + m];
+            s[k][0] += v * cx(i);
+            s[k][1] += v * cy(i);
+            s[k][2] += v * cz(i);
+        }
+    }
+    for (int k = 0; k < 2; ++k)
+        for (int d = 0; d < 3; ++d) F[k][d] = -L.G * rho[k] * s[k][d] + rho[k] * L.g[d];
+}
+
+// psi_k of the stored state: rho_k on fluid nodes, the material's value elsewhere
 template <class S>
-__global__ void restrict_kernel(const S *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz, double r0, double r1,
-                                int D, int H, int W, float *outf, uint16_t *outb) {
+__global__ void psi_state_kernel(const S *f, SurLattice L) {
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
+        const uint8_t m = L.mat[n];
+        for (int k = 0; k < 2; ++k) {
+            double v;
+            if ((m & MAT_ID_MASK) == MAT_FLUID) {
+                v = 0.0;
+                for (int i = 0; i < Q; ++i) v += double(Codec<S>::dec(f[(k * Q + i) * L.fs + n])) + wgt<double>(i) * L.rref[k];
+            } else {
+                v = psi_solid(L, m, k);
+            }
+            L.psi[k * n_all + n] = v;
+        }
+    }
+}
+
+template <class S>
+__global__ void restrict_kernel(const S *f, SurLattice L, int D, int H, int W, float *outf, uint16_t *outb) {
     const int64_t P = int64_t(D) * H * W;
-    const double rr[2] = {r0, r1};
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
     for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < P; c += int64_t(gridDim.x) * blockDim.x) {
         const int qx = int(c % W), qy = int((c / W) % H), qz = int(c / (int64_t(W) * H));
         float cell[8] = {0.03f, 1.0f, 0, 0, 0, 0, 0, 0};
@@ -449,22 +541,28 @@ __global__ void restrict_kernel(const S *f, int64_t fs, const uint8_t *mat, int 
             double rho[2] = {0, 0}, mom[3] = {0, 0, 0};
             int nf = 0, nrod = 0;
             for (int j = 0; j < 8; ++j) {
-                const int64_t n =
-                    (int64_t(2 * qz + (j >> 2)) * ny + 2 * qy + ((j >> 1) & 1)) * nx + 2 * qx + (j & 1);
-                const uint8_t m = mat[n] & MAT_ID_MASK;
+                const int z = 2 * qz + (j >> 2), y = 2 * qy + ((j >> 1) & 1), x = 2 * qx + (j & 1);
+                const int64_t n = (int64_t(z) * ny + y) * nx + x;
+                const uint8_t m = L.mat[n] & MAT_ID_MASK;
                 nrod += m == MAT_ROD;
                 if (m != MAT_FLUID) continue;
                 ++nf;
+                double r[2] = {0, 0};
                 for (int k = 0; k < 2; ++k)
                     for (int i = 0; i < Q; ++i) {
-                        const double v = double(Codec<S>::dec(f[(k * Q + i) * fs + n])) + wgt<double>(i) * rr[k];
-                        rho[k] += v;
+                        const double v = double(Codec<S>::dec(f[(k * Q + i) * L.fs + n])) + wgt<double>(i) * L.rref[k];
+                        r[k] += v;
                         mom[0] += v * cx(i);
                         mom[1] += v * cy(i);
                         mom[2] += v * cz(i);
                     }
+                double F[2][3];
+                force_at(L, x, y, z, r, F);
+                for (int d = 0; d < 3; ++d) mom[d] -= 0.5 * (F[0][d] + F[1][d]);
+                rho[0] += r[0];
+                rho[1] += r[1];
             }
-            double out[7] = {0, 0, 0, 0, 0, nrod / 8.0, 1.0};
+            double out[8] = {0, 0, 0, 0, 0, nrod / 8.0, 1.0, nf / 8.0};
             if (nf) {
                 out[0] = rho[0] / nf;
                 out[1] = rho[1] / nf;
@@ -472,8 +570,7 @@ __global__ void restrict_kernel(const S *f, int64_t fs, const uint8_t *mat, int 
                 if (tot > 0.0)
                     for (int d = 0; d < 3; ++d) out[2 + d] = mom[d] / tot;
             }
-            for (int q = 0; q < 7; ++q) cell[q] = float(out[q]);
-            cell[7] = 0.0f;
+            for (int q = 0; q < 8; ++q) cell[q] = float(out[q]);
         }
         for (int q = 0; q < 8; ++q) {
             if (outf) outf[c * 8 + q] = cell[q];
@@ -490,35 +587,96 @@ __device__ inline void lerp_index(int x, int nc, int &i0, int &i1, double &w) {
     w = c - i0;
 }
 
-template <class S>
-__global__ void lift_kernel(const float *coarse, int D, int H, int W, const uint8_t *mat, int nx, int ny, int nz, S *f,
-                            int64_t fs, double r0, double r1) {
-    const int64_t n_all = int64_t(nx) * ny * nz;
-    const int ncz = nz / 2, ncy = ny / 2, ncx = nx / 2;
-    const double rr[2] = {r0, r1};
-    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
-        if ((mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
-        const int x = int(n % nx), y = int((n / nx) % ny), z = int(n / (int64_t(nx) * ny));
-        int z0, z1, y0, y1, x0, x1;
-        double wz, wy, wx;
-        lerp_index(z, ncz, z0, z1, wz);
-        lerp_index(y, ncy, y0, y1, wy);
-        lerp_index(x, ncx, x0, x1, wx);
-        double a[5] = {0, 0, 0, 0, 0};
-        for (int j = 0; j < 8; ++j) {
-            const int iz = (j >> 2) ? z1 : z0, iy = ((j >> 1) & 1) ? y1 : y0, ix = (j & 1) ? x1 : x0;
-            const double fz = (j >> 2) ? wz : 1.0 - wz, fy = ((j >> 1) & 1) ? wy : 1.0 - wy, fx = (j & 1) ? wx : 1.0 - wx;
-            const float *cc = coarse + ((int64_t(iz) * H + iy) * W + ix) * 8;
-            const double wt = fz * fy * fx;
-            for (int q = 0; q < 5; ++q) a[q] += wt * double(cc[q]);
-        }
-        const double usq = a[2] * a[2] + a[3] * a[3] + a[4] * a[4];
-        for (int k = 0; k < 2; ++k)
-            for (int i = 0; i < Q; ++i) {
-                const double cu = cx(i) * a[2] + cy(i) * a[3] + cz(i) * a[4];
-                const double feq = wgt<double>(i) * a[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-                f[(k * Q + i) * fs + n] = Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(i) * rr[k]));
+// prolonged (rho_A, rho_B, u) at fine node (x, y, z): trilinear over the
+// corner cells that hold fluid (channel 7 > 0), renormalised; else the plain
+// mean of the fluid-holding cells of the 4 x 4 x 4 block around them; else
+// gas at rest
+__device__ inline void prolong_at(const float *coarse, int H, int W, int ncz, int ncy, int ncx, int x, int y, int z,
+                                  double a[5]) {
+    int z0, z1, y0, y1, x0, x1;
+    double wz, wy, wx;
+    lerp_index(z, ncz, z0, z1, wz);
+    lerp_index(y, ncy, y0, y1, wy);
+    lerp_index(x, ncx, x0, x1, wx);
+    for (int q = 0; q < 5; ++q) a[q] = 0.0;
+    double wsum = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const int iz = (j >> 2) ? z1 : z0, iy = ((j >> 1) & 1) ? y1 : y0, ix = (j & 1) ? x1 : x0;
+        const double fz = (j >> 2) ? wz : 1.0 - wz, fy = ((j >> 1) & 1) ? wy : 1.0 - wy, fx = (j & 1) ? wx : 1.0 - wx;
+        const float *cc = coarse + ((int64_t(iz) * H + iy) * W + ix) * 8;
+        if (!(cc[7] > 0.0f)) continue;
+        const double wt = fz * fy * fx;
+        for (int q = 0; q < 5; ++q) a[q] += wt * double(cc[q]);
+        wsum += wt;
+    }
+    if (wsum > 0.0) {
+        for (int q = 0; q < 5; ++q) a[q] /= wsum;
+        return;
+    }
+    int cnt = 0;
+    for (int iz = z0 - 1; iz <= z0 + 2; ++iz)
+        for (int iy = y0 - 1; iy <= y0 + 2; ++iy)
+            for (int ix = x0 - 1; ix <= x0 + 2; ++ix) {
+                if (iz < 0 || iz >= ncz || iy < 0 || iy >= ncy || ix < 0 || ix >= ncx) continue;
+                const float *cc = coarse + ((int64_t(iz) * H + iy) * W + ix) * 8;
+                if (!(cc[7] > 0.0f)) continue;
+                for (int q = 0; q < 5; ++q) a[q] += double(cc[q]);
+                ++cnt;
             }
+    if (cnt) {
+        for (int q = 0; q < 5; ++q) a[q] /= cnt;
+    } else {
+        a[0] = 0.03;
+        a[1] = 1.0;
+    }
+}
+
+// psi_k of the lifted state: prolonged rho_k on fluid nodes, the material's value elsewhere
+__global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L) {
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
+        const uint8_t m = L.mat[n];
+        double v[2];
+        if ((m & MAT_ID_MASK) == MAT_FLUID) {
+            const int x = int(n % L.nx), y = int((n / L.nx) % L.ny), z = int(n / (int64_t(L.nx) * L.ny));
+            double a[5];
+            prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
+            v[0] = a[0];
+            v[1] = a[1];
+        } else {
+            v[0] = psi_solid(L, m, 0);
+            v[1] = psi_solid(L, m, 1);
+        }
+        L.psi[n] = v[0];
+        L.psi[n_all + n] = v[1];
+    }
+}
+
+template <class S>
+__global__ void lift_kernel(const float *coarse, int H, int W, SurLattice L, S *f) {
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
+        if ((L.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
+        const int x = int(n % L.nx), y = int((n / L.nx) % L.ny), z = int(n / (int64_t(L.nx) * L.ny));
+        double a[5];
+        prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
+        const double rho[2] = {a[0], a[1]};
+        double F[2][3];
+        force_at(L, x, y, z, rho, F);
+        const double tot = rho[0] + rho[1];
+        double up[3];
+        for (int d = 0; d < 3; ++d) up[d] = a[2 + d] - 0.5 * (F[0][d] + F[1][d]) / tot;
+        for (int k = 0; k < 2; ++k) {
+            double u[3];
+            const bool ok = rho[k] >= 1e-12;  // no shift for a vanishing component
+            for (int d = 0; d < 3; ++d) u[d] = ok ? up[d] + L.tau[k] * F[k][d] / rho[k] : up[d];
+            const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            for (int i = 0; i < Q; ++i) {
+                const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+                const double feq = wgt<double>(i) * rho[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+                f[(k * Q + i) * L.fs + n] = Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(i) * L.rref[k]));
+            }
+        }
     }
 }
 
@@ -582,16 +740,24 @@ hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const float *out, const float *xin, int64_t P, float *pred, uint16_t *predb, hipStream_t s) {
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(P * 8)), dim3(256), 0, s, out, xin, P, pred, predb);
+hipError_t launch_residual(const float *out, const float *xin, int64_t P, const ChanScale &sc, float *pred,
+                           uint16_t *predb, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(P * 8)), dim3(256), 0, s, out, xin, P, sc, pred, predb);
     return hipGetLastError();
 }
 
-hipError_t launch_loss(const float *out, const float *xin, const float *tgt, int64_t P, double lam, double *part,
-                       double *res, float *grad, hipStream_t s) {
-    hipLaunchKernelGGL(loss_partial_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, out, xin, tgt, P, part);
+hipError_t launch_loss(const float *out, const float *xin, const float *tgt, int64_t P, const ChanScale &sc, double lam,
+                       double *part, double *res, float *grad, hipStream_t s) {
+    hipLaunchKernelGGL(loss_partial_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, out, xin, tgt, P, sc, part);
     hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, s, part, LOSS_BLOCKS, lam, res);
-    if (grad) hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_for(P * 8)), dim3(256), 0, s, out, xin, tgt, P, lam, res, grad);
+    if (grad)
+        hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_for(P * 8)), dim3(256), 0, s, out, xin, tgt, P, sc, lam, res, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const float *x, const float *y, int64_t P, double *part, double *res, hipStream_t s) {
+    hipLaunchKernelGGL(moments_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, x, y, P, part);
+    hipLaunchKernelGGL(moments_total_kernel, dim3(1), dim3(64), 0, s, part, LOSS_BLOCKS, res);
     return hipGetLastError();
 }
 
@@ -602,56 +768,43 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *p
     return hipGetLastError();
 }
 
-hipError_t launch_restrict(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
-                           const double rref[2], int D, int H, int W, float *outf, uint16_t *outb, hipStream_t s) {
-    const int g = grid_for(int64_t(D) * H * W);
+template <class F>
+static hipError_t by_prec(int prec, F &&fn) {
     switch (prec) {
         case LB_F64:
-            hipLaunchKernelGGL(restrict_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<const double *>(f), fs, mat,
-                               nx, ny, nz, rref[0], rref[1], D, H, W, outf, outb);
-            break;
+            return fn(static_cast<double *>(nullptr));
         case LB_F32:
-            hipLaunchKernelGGL(restrict_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<const float *>(f), fs, mat, nx,
-                               ny, nz, rref[0], rref[1], D, H, W, outf, outb);
-            break;
+            return fn(static_cast<float *>(nullptr));
         case LB_F16DEV:
-            hipLaunchKernelGGL(restrict_kernel<_Float16>, dim3(g), dim3(256), 0, s, static_cast<const _Float16 *>(f), fs,
-                               mat, nx, ny, nz, rref[0], rref[1], D, H, W, outf, outb);
-            break;
+            return fn(static_cast<_Float16 *>(nullptr));
         case LB_BF16DEV:
-            hipLaunchKernelGGL(restrict_kernel<bf16_t>, dim3(g), dim3(256), 0, s, static_cast<const bf16_t *>(f), fs, mat,
-                               nx, ny, nz, rref[0], rref[1], D, H, W, outf, outb);
-            break;
+            return fn(static_cast<bf16_t *>(nullptr));
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const uint8_t *mat, int nx, int ny, int nz,
-                       void *f, int64_t fs, const double rref[2], hipStream_t s) {
-    const int g = grid_for(int64_t(nx) * ny * nz);
-    switch (prec) {
-        case LB_F64:
-            hipLaunchKernelGGL(lift_kernel<double>, dim3(g), dim3(256), 0, s, coarse, D, H, W, mat, nx, ny, nz,
-                               static_cast<double *>(f), fs, rref[0], rref[1]);
-            break;
-        case LB_F32:
-            hipLaunchKernelGGL(lift_kernel<float>, dim3(g), dim3(256), 0, s, coarse, D, H, W, mat, nx, ny, nz,
-                               static_cast<float *>(f), fs, rref[0], rref[1]);
-            break;
-        case LB_F16DEV:
-            hipLaunchKernelGGL(lift_kernel<_Float16>, dim3(g), dim3(256), 0, s, coarse, D, H, W, mat, nx, ny, nz,
-                               static_cast<_Float16 *>(f), fs, rref[0], rref[1]);
-            break;
-        case LB_BF16DEV:
-            hipLaunchKernelGGL(lift_kernel<bf16_t>, dim3(g), dim3(256), 0, s, coarse, D, H, W, mat, nx, ny, nz,
-                               static_cast<bf16_t *>(f), fs, rref[0], rref[1]);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+hipError_t launch_restrict(int prec, const void *f, const SurLattice &L, int D, int H, int W, float *outf,
+                           uint16_t *outb, hipStream_t s) {
+    const int gn = grid_for(int64_t(L.nx) * L.ny * L.nz), gc = grid_for(int64_t(D) * H * W);
+    return by_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        const S *fs = static_cast<const S *>(f);
+        hipLaunchKernelGGL(psi_state_kernel<S>, dim3(gn), dim3(256), 0, s, fs, L);
+        hipLaunchKernelGGL(restrict_kernel<S>, dim3(gc), dim3(256), 0, s, fs, L, D, H, W, outf, outb);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const SurLattice &L, void *f, hipStream_t s) {
+    (void)D;
+    const int gn = grid_for(int64_t(L.nx) * L.ny * L.nz);
+    return by_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(psi_lift_kernel, dim3(gn), dim3(256), 0, s, coarse, H, W, L);
+        hipLaunchKernelGGL(lift_kernel<S>, dim3(gn), dim3(256), 0, s, coarse, H, W, L, static_cast<S *>(f));
+        return hipGetLastError();
+    });
 }
 
 }  // namespace lbm

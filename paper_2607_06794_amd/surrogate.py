@@ -89,6 +89,11 @@ class UNet:
         self.gcat = [torch.zeros(self.P[l] * (self.ch[l] + (self.ch[l + 1] if l + 1 < nlev - 1 else self.ch[-1])), **f32)
                      for l in range(nlev - 1)]
         self.loss_scratch = torch.zeros(self.lib.lb_sur_loss_scratch_bytes() // 4 + 64, **f32)
+        # output scale per channel (the network predicts changes in these units)
+        self.scale = np.ones(6, np.float32)
+
+    def set_scale(self, scale):
+        self.scale = np.ascontiguousarray(scale, dtype=np.float32).reshape(6)
 
     # ------------------------------------------------------------------ params
     def _s(self):
@@ -237,7 +242,8 @@ class UNet:
         """(loss, relative mass error) of pred = xin + out against tgt; grad
         (FP32 [P0][8]) receives dloss/dout when given."""
         res = (ct.c_double * 4)()
-        _lib.check(self.lib.lb_sur_loss(_p(self.out), _p(xin_f32), _p(tgt_f32), self.P[0], float(lam), _p(grad),
+        _lib.check(self.lib.lb_sur_loss(_p(self.out), _p(xin_f32), _p(tgt_f32), self.P[0],
+                                        self.scale.ctypes.data_as(ct.c_void_p), float(lam), _p(grad),
                                         _p(self.loss_scratch), res if sync else None, self._s()))
         return (res[3], res[2]) if sync else None
 
@@ -275,6 +281,12 @@ def lift(lat, pred_f32, D, H, W):
     _lib.check(lib.lb_sur_lift(lat._ctx, _p(pred_f32), D, H, W, _stream(lat)))
 
 
+def jump_rods(lat, now_f32, next_f32, D, H, W, steps):
+    """Advect and re-place a lattice's rods over a jump (before lift)."""
+    lib = _lib.load()
+    _lib.check(lib.lb_sur_jump_rods(lat._ctx, _p(now_f32), _p(next_f32), D, H, W, float(steps), _stream(lat)))
+
+
 def _stream(lat):
     import torch
 
@@ -285,8 +297,20 @@ def _stream(lat):
 def predict(net, x_f32, x_bf16, pred_f32=None, pred_bf16=None):
     """pred = x + network(x) on the first six channels (library kernels)."""
     net.forward(x_bf16)
-    _lib.check(net.lib.lb_sur_residual(_p(net.out), _p(x_f32), net.P[0], _p(pred_f32), _p(pred_bf16), net._s()))
+    _lib.check(net.lib.lb_sur_residual(_p(net.out), _p(x_f32), net.P[0], net.scale.ctypes.data_as(ct.c_void_p),
+                                       _p(pred_f32), _p(pred_bf16), net._s()))
     return pred_f32, pred_bf16
+
+
+def channel_scales(net, pairs, floor=1e-6):
+    """RMS change of each of the six channels over the training pairs (masked),
+    from the library's moments kernel."""
+    acc = np.zeros(7)
+    res = (ct.c_double * 7)()
+    for xf, _, yf in pairs:
+        _lib.check(net.lib.lb_sur_moments(_p(xf), _p(yf), net.P[0], _p(net.loss_scratch), res, net._s()))
+        acc += np.array(res[:])
+    return np.maximum(np.sqrt(acc[:6] / max(acc[6], 1.0)), floor).astype(np.float32)
 
 
 def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True):
@@ -311,10 +335,12 @@ def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True)
 
 def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None):
     """Adam on (x_f32, x_bf16, y_f32) pairs, `batch` samples per update
-    (gradients summed).  Returns the mean training loss of every epoch."""
+    (gradients summed), in channel-normalised units (scales from the pairs).
+    Returns the mean training loss of every epoch."""
     rng = np.random.Generator(np.random.PCG64(seed))
     import torch
 
+    net.set_scale(channel_scales(net, pairs))
     gout = torch.zeros(net.P[0] * COUT, dtype=torch.float32, device=net.device)
     hist = []
     for ep in range(epochs):
@@ -356,7 +382,10 @@ def evaluate(net, pairs, lam=1.0, prev=None):
         res["persistence"] += l0
         res["mass_err_persistence"] += abs(me0)
         if prev is not None:
-            net.out.copy_(xf - prev[k])  # x + (x - x_prev) on the six channels
+            # x + (x - x_prev): the network output that gives it, in scaled units
+            sc = torch.ones(8, dtype=torch.float32, device=net.device)
+            sc[:6] = torch.from_numpy(net.scale)
+            net.out.copy_(((xf - prev[k]).view(-1, 8) / sc).view(-1))
             l1, _ = net.loss(xf, yf, lam)
             res["linear"] += l1
         net.out.copy_(saved)

@@ -3,9 +3,11 @@
 Inputs that enter the BF16 matrix cores are made BF16-representable on the
 host, so the oracle sees exactly what the kernels see; the remaining
 difference is FP32 accumulation (tolerance 2e-5 relative to the output scale).
-The whole U-Net, with BF16 activations between layers, is compared by the
-relative error of each parameter gradient (bound 3e-2) and its cosine
-similarity.
+The whole U-Net's parameter gradients are compared with the oracle's
+backward pass run on the activations the GPU computed (BF16 values and the
+same ReLU masks); the remaining difference is the rounding of each layer's
+incoming gradient to BF16 (bound 2e-2 relative, cosine > 0.9998).  Each
+single layer is checked at 2e-5 above.
 """
 import ctypes as ct
 import sys
@@ -123,17 +125,19 @@ def test_pooling_and_plumbing():
     D, H, W, C = 4, 6, 10, 16
     x, xb = bf16_round(RNG.normal(size=(D, H, W, C)))
     y = torch.zeros(D * H * W * C // 8, dtype=torch.int16, device="cuda:0")
-    L.check(lib.lb_pool2(dev(xb).data_ptr(), D, H, W, C, y.data_ptr(), _stream()))
+    tx = dev(xb)  # device tensors stay referenced until the kernels have run
+    L.check(lib.lb_pool2(tx.data_ptr(), D, H, W, C, y.data_ptr(), _stream()))
     yv = (host(y).astype(np.uint16).astype(np.uint32) << 16).view(np.float32).reshape(D // 2, H // 2, W // 2, C)
     ref = OS.pool2(x)
     assert np.abs(yv - ref).max() <= np.abs(ref).max() * 2 ** -8
     gc = RNG.normal(size=(D // 2, H // 2, W // 2, C)).astype(np.float32)
     skip = RNG.normal(size=(D, H, W, 24)).astype(np.float32)
     g = torch.zeros(D * H * W * C, dtype=torch.float32, device="cuda:0")
-    L.check(lib.lb_pool2_backward(dev(gc).data_ptr(), dev(skip).data_ptr(), 24, 8, D, H, W, C, g.data_ptr(), _stream()))
+    tgc, tskip = dev(gc), dev(skip)
+    L.check(lib.lb_pool2_backward(tgc.data_ptr(), tskip.data_ptr(), 24, 8, D, H, W, C, g.data_ptr(), _stream()))
     assert np.allclose(host(g).reshape(D, H, W, C), OS.pool2_back(gc) + skip[..., 8:24], rtol=1e-6, atol=1e-7)
     gc2 = torch.zeros(D * H * W * C // 8, dtype=torch.float32, device="cuda:0")
-    L.check(lib.lb_up2_backward(dev(skip).data_ptr(), 24, C, D, H, W, gc2.data_ptr(), _stream()))
+    L.check(lib.lb_up2_backward(tskip.data_ptr(), 24, C, D, H, W, gc2.data_ptr(), _stream()))
     assert np.allclose(host(gc2).reshape(D // 2, H // 2, W // 2, C), OS.up2_back(skip[..., :C]), rtol=1e-5, atol=1e-6)
 
 
@@ -149,13 +153,21 @@ def test_loss_and_adam():
     scratch = torch.zeros(lib.lb_sur_loss_scratch_bytes() // 4 + 16, dtype=torch.float32, device="cuda:0")
     grad = torch.zeros(P * 8, dtype=torch.float32, device="cuda:0")
     res = (ct.c_double * 4)()
-    L.check(lib.lb_sur_loss(dev(out).data_ptr(), dev(xin).data_ptr(), dev(tgt).data_ptr(), P, 0.5, grad.data_ptr(),
-                            scratch.data_ptr(), res, _stream()))
-    pred = xin[:, :6].astype(np.float64) + out[:, :6]
-    Lr, gr = OS.loss(pred, tgt[:, :6].astype(np.float64), xin[:, 6].astype(np.float64), 0.5)
+    tout, txin, ttgt = dev(out), dev(xin), dev(tgt)
+    scale = np.array([0.5, 2.0, 0.01, 0.02, 0.03, 1.0], np.float32)
+    L.check(lib.lb_sur_loss(tout.data_ptr(), txin.data_ptr(), ttgt.data_ptr(), P, scale.ctypes.data_as(ct.c_void_p),
+                            0.5, grad.data_ptr(), scratch.data_ptr(), res, _stream()))
+    s64 = scale.astype(np.float64)
+    pred = xin[:, :6].astype(np.float64) + s64 * out[:, :6]
+    Lr, gr = OS.loss(pred, tgt[:, :6].astype(np.float64), xin[:, 6].astype(np.float64), 0.5, s64)
     assert res[3] == pytest.approx(Lr, rel=1e-10)
-    assert np.allclose(host(grad).reshape(P, 8)[:, :6], gr, rtol=1e-5, atol=1e-9)
+    # dloss/dout = scale * dloss/dpred
+    assert np.allclose(host(grad).reshape(P, 8)[:, :6], gr * s64, rtol=1e-5, atol=1e-9)
     assert np.all(host(grad).reshape(P, 8)[:, 6:] == 0)
+    mom = (ct.c_double * 7)()
+    L.check(lib.lb_sur_moments(txin.data_ptr(), ttgt.data_ptr(), P, scratch.data_ptr(), mom, _stream()))
+    d = (tgt[:, :6].astype(np.float64) - xin[:, :6]) ** 2 * xin[:, 6:7]
+    assert np.allclose(np.array(mom[:6]), d.sum(axis=0), rtol=1e-10) and mom[6] == pytest.approx(xin[:, 6].sum())
     p = RNG.normal(size=500).astype(np.float32)
     gg = RNG.normal(size=500).astype(np.float32)
     tp, tg = dev(p), dev(gg)
@@ -176,24 +188,26 @@ def test_restrict_and_lift_match_oracle():
 
     L, lib = _lib()
     c = cases.cap_case(shape=(16, 24, 40), footprint=(26.0, 10.0), height=8.0, stripe=(30, 14))
+    c["body_force"] = (2e-6, -1e-6, -3e-6)
+    p = cases.oracle_params(c)
     lat = Lattice(cases.lattice_params(c, "f64"), c["rho"], c["mat"])
     lat.step(20)
     D, H, W = 10, 14, 24  # larger than the lattice's 8 x 12 x 20 coarse extent
     cf = torch.zeros(D * H * W * 8, dtype=torch.float32, device="cuda:0")
     L.check(lib.lb_sur_restrict(lat._ctx, D, H, W, cf.data_ptr(), None, _stream()))
     _, f = lat.export()
-    ref = OS.restrict(f, c["mat"], (D, H, W))
+    ref = OS.restrict(f, c["mat"], (D, H, W), p)
     got = host(cf).reshape(D, H, W, 8)
-    assert np.abs(got[..., :7] - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
-    assert np.all(got[..., 7] == 0)
+    assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
     # lift a perturbed canvas and compare the populations (FP64 storage)
     coarse = ref.copy()
     coarse[..., 0] *= 1.0 + 0.01 * RNG.normal(size=coarse.shape[:3])
-    cc = np.zeros((D, H, W, 8), np.float32)
-    cc[..., :7] = coarse
-    L.check(lib.lb_sur_lift(lat._ctx, dev(cc).data_ptr(), D, H, W, _stream()))
+    coarse[2:4, 3:5, 4:7, 7] = 0.0  # cells without fluid: renormalised stencil and the block fallback
+    cc = coarse.astype(np.float32)
+    tcc = dev(cc)
+    L.check(lib.lb_sur_lift(lat._ctx, tcc.data_ptr(), D, H, W, _stream()))
     _, f2 = lat.export()
-    want = OS.lift(cc[..., :7].astype(np.float64), c["mat"])
+    want = OS.lift(cc.astype(np.float64), c["mat"], p)
     fl = (c["mat"] == lbm.FLUID)[None, None]
     assert np.abs(np.where(fl, f2 - want, 0)).max() <= 1e-12
     lat.close()
@@ -225,15 +239,190 @@ def test_unet_gradients_match_oracle():
     gy = RNG.normal(size=(D, H, W, 6))
     g8 = np.zeros((D, H, W, 8), np.float32)
     g8[..., :6] = gy
+    tg8 = dev(g8.reshape(-1))
     net.zero_grad()
-    net.backward(dev(g8.reshape(-1)))
-    G = OS.unet_backward(gy, P, cache, ch=ch)
+    net.backward(tg8)
+    # the oracle's backward pass on the activations the GPU computed (BF16
+    # values, same ReLU masks): what remains is the rounding of the gradients
+    # to BF16 on their way into each layer's matrix products
+    def act(name, lvl, c):
+        bits = host(net.act[name]).astype(np.uint16).astype(np.uint32) << 16
+        return bits.view(np.float32).astype(np.float64).reshape(D >> lvl, H >> lvl, W >> lvl, c)
+
+    def pooled(lvl, c):
+        bits = host(net.pooled[lvl]).astype(np.uint16).astype(np.uint32) << 16
+        return bits.view(np.float32).astype(np.float64).reshape(D >> (lvl + 1), H >> (lvl + 1), W >> (lvl + 1), c)
+
+    gcache = {"x": xv[..., :7]}
+    nlev = len(ch)
+    for lvl in range(nlev):
+        gcache[f"enc{lvl}a:in"] = xv[..., :7] if lvl == 0 else pooled(lvl - 1, ch[lvl - 1])
+        gcache[f"enc{lvl}a:out"] = act(f"enc{lvl}a", lvl, ch[lvl])
+        gcache[f"enc{lvl}b:in"] = gcache[f"enc{lvl}a:out"]
+        gcache[f"enc{lvl}b:out"] = act(f"enc{lvl}b", lvl, ch[lvl])
+    for lvl in range(nlev - 2, -1, -1):
+        coarse = gcache[f"enc{nlev - 1}b:out"] if lvl == nlev - 2 else gcache[f"dec{lvl + 1}b:out"]
+        gcache[f"dec{lvl}a:in"] = np.concatenate([OS.up2(coarse), gcache[f"enc{lvl}b:out"]], axis=-1)
+        gcache[f"dec{lvl}a:out"] = act(f"dec{lvl}a", lvl, ch[lvl])
+        gcache[f"dec{lvl}b:in"] = gcache[f"dec{lvl}a:out"]
+        gcache[f"dec{lvl}b:out"] = act(f"dec{lvl}b", lvl, ch[lvl])
+    gcache["out:in"] = gcache["dec0b:out"]
+    G = OS.unet_backward(gy, P, gcache, ch=ch)
+    G_own = OS.unet_backward(gy, P, cache, ch=ch)
     for name, (gw, gb) in G.items():
         ww, bb = net.get_layer_grad(name)
         ww = ww[:, : gw.shape[1], : gw.shape[2]]
         bb = bb[: gb.shape[0]]
         rel = np.linalg.norm(ww - gw) / np.linalg.norm(gw)
         cos = float((ww * gw).sum() / (np.linalg.norm(ww) * np.linalg.norm(gw)))
-        say(f"[gpu] grad {name}: rel {rel:.2e} cos {cos:.6f}")
-        assert rel < 3e-2 and cos > 0.999, name
-        assert np.linalg.norm(bb - gb) <= 3e-2 * np.linalg.norm(gb) + 1e-6, name
+        own = G_own[name][0]
+        rel_own = np.linalg.norm(ww - own) / np.linalg.norm(own)
+        say(f"[gpu] grad {name}: rel {rel:.2e} cos {cos:.6f} (vs the oracle's own forward: {rel_own:.2e})")
+        assert rel < 2e-2 and cos > 0.9998, name
+        assert np.linalg.norm(bb - gb) <= 2e-2 * np.linalg.norm(gb) + 1e-6, name
+
+
+def test_training_beats_persistence_on_lbm_trajectories():
+    """The network trained on LBM trajectories with the library's kernels
+    predicts a held-out droplet's next snapshot better than persistence."""
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Batch, Lattice
+
+    shape = (32, 32, 64)
+    D, H, W = 16, 16, 32
+    lats = []
+    for seed in (5101, 5102, 5103, 5104):
+        spec = inputs.CapSpec(shape=shape, footprint=(40.0, 14.0), height=10.0, stripe=(46, 20), seed=seed, noise=1e-2)
+        rho, mat = inputs.sessile_cap(spec)
+        c = dict(shape=shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+                 body_force=(0.0, 0.0, 0.0))
+        lats.append(Lattice(cases.lattice_params(c, "f32"), rho, mat))
+    batch = Batch(lats)
+    xf, xb = SU.rollout_snapshots(batch, lats, 7, 40, D, H, W, warm=20, rods=False)
+    batch.close()
+    for lat in lats:
+        lat.close()
+    train = [(xf[i, s], xb[i, s], xf[i, s + 1]) for i in range(3) for s in range(6)]
+    test = [(xf[3, s], xb[3, s], xf[3, s + 1]) for s in range(6)]
+    net = SU.UNet(D, H, W, ch=(16, 16, 32, 32)).init(1)
+    before = SU.evaluate(net, test)
+    assert before["net"] == pytest.approx(before["persistence"], rel=1e-6)  # zero output layer
+    hist = SU.fit(net, train, epochs=40, batch=2, lr=2e-3, lam=1.0, seed=3)
+    after = SU.evaluate(net, test)
+    say(f"[gpu] surrogate train loss {hist[0]:.3e} -> {hist[-1]:.3e}; test net {after['net']:.3e} "
+        f"persistence {after['persistence']:.3e}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert after["net"] < 0.9 * after["persistence"]
+
+
+def _min_gap(orods):
+    """Smallest axis-segment distance over all rod pairs (minimum image)."""
+    from oracle import rods as R
+
+    best = np.inf
+    for a in range(orods.n):
+        pa, qa = orods.ends(a)
+        for b in range(a + 1, orods.n):
+            pb, qb = orods.ends(b)
+            sh = R.min_image(orods.X[b] - orods.X[a], orods.box, orods.periodic) - (orods.X[b] - orods.X[a])
+            best = min(best, R.segment_segment(pa, qa, pb + sh, qb + sh)[0])
+    return best
+
+
+def test_rod_jump_relaxes_overlaps():
+    """Three rods placed crossing each other and one touching the wall; a jump
+    of zero steps leaves only the relaxation: every axis pair ends at least
+    d0 apart, the axis ends d0_wall above the wall, the pair moves are
+    symmetric (the mean centre of the crossing pair stays put in x, y), and
+    the re-placed lattice steps on healthily."""
+    from oracle import rods as R
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Lattice
+
+    spec = inputs.CapSpec(shape=(32, 48, 96), footprint=(70.0, 28.0), height=14.0, stripe=(80, 34), seed=5301)
+    rho, mat = inputs.sessile_cap(spec)
+    s2 = np.sqrt(0.5)
+    rods = np.zeros((3, 13))
+    rods[0, :3], rods[0, 3:7] = (46.0, 24.0, 8.0), (s2, 0.0, s2, 0.0)  # along x
+    rods[1, :3], rods[1, 3:7] = (48.0, 24.5, 9.5), (s2, -s2, 0.0, 0.0)  # along y, 1.5 above rod 0
+    rods[2, :3], rods[2, 3:7] = (30.0, 20.0, 4.2), (s2, 0.0, s2, 0.0)  # flat, axis 3.7 above the wall
+    c = dict(shape=spec.shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+             body_force=(0.0, 0.0, 0.0))
+    lp = cases.lattice_params(c, "f32")
+    lp.rod_length, lp.rod_radius, lp.wall_z = 12.0, 2.0, 0.5
+    lp.rod_d0, lp.rod_d0_wall = 5.0, 4.0
+    say("[gpu] rod relaxation: 3 rods, shape", spec.shape)
+    lat = Lattice(lp, rho, mat, rods=rods)
+    D, H, W = 16, 24, 48
+    now_f, _ = SU.restrict(lat, D, H, W)
+    before = lat.rods()
+    SU.jump_rods(lat, now_f, now_f, D, H, W, 0)
+    SU.lift(lat, now_f, D, H, W)
+    after = lat.rods()
+    assert np.abs(after[:, 3:7] - before[:, 3:7]).max() == 0.0
+    rp = R.RodParams(length=12.0, radius=2.0)
+    orods = R.Rods(after[:, :3], after[:, 3:7], after[:, 7:10], after[:, 10:13], rp, (96, 48, 32), (True, True, False))
+    assert _min_gap(orods) >= 5.0 - 1e-5
+    assert _min_gap(orods) <= 5.0 + 1e-3  # moved no further than needed
+    low = min(orods.ends(2)[0][2], orods.ends(2)[1][2])
+    assert low - 0.5 >= 4.0 - 1e-5
+    assert np.allclose(after[0, :2] + after[1, :2], before[0, :2] + before[1, :2], atol=1e-9)
+    assert after[0, 2] < before[0, 2] and after[1, 2] > before[1, 2]  # pushed apart along z
+    want = (orods.mask(spec.shape) >= 0).sum(axis=0)
+    assert np.array_equal(lat.rod_map(), want)
+    lat.coupled_step(20)
+    assert lat.observables(allow_unstable=True)["status"] == 0
+    lat.close()
+
+
+def test_rod_jump_moves_and_replaces_rods():
+    """A jump moves every rod centre by steps x the mean coarse velocity and
+    re-places the rods: the rod nodes afterwards are exactly the capsules at
+    the new poses (oracle mask), and the lattice stays healthy."""
+    import torch
+
+    from oracle import rods as R
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Lattice
+
+    spec = inputs.CapSpec(shape=(32, 48, 96), footprint=(70.0, 28.0), height=14.0, stripe=(80, 34), seed=5201)
+    rho, mat = inputs.sessile_cap(spec)
+    rods = inputs.place_rods(4, 12.0, 2.0, (96, 48, 32), inside=inputs.cap_inside(spec), seed=5202, margin=1.0,
+                             max_trials=20000)
+    assert len(rods) >= 2
+    c = dict(shape=spec.shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+             body_force=(0.0, 0.0, 0.0))
+    lp = cases.lattice_params(c, "f32")
+    lp.rod_length, lp.rod_radius, lp.wall_z = 12.0, 2.0, 0.5
+    lat = Lattice(lp, rho, mat, rods=rods)
+    lat.coupled_step(10)
+    D, H, W = 16, 24, 48
+    now_f, _ = SU.restrict(lat, D, H, W)
+    nxt = now_f.clone()
+    v = torch.zeros(8, device="cuda:0")
+    v[2], v[3], v[4] = 0.004, -0.002, 0.0005
+    nxt.view(-1, 8).add_(v)  # a uniform velocity change of the predicted canvas
+    before = lat.rods()
+    SU.jump_rods(lat, now_f, nxt, D, H, W, 500)
+    SU.lift(lat, nxt, D, H, W)
+    after = lat.rods()
+    # each centre moved by 500 x its new velocity (the mean of the two
+    # canvases), up to the relaxation of overlaps the move made
+    rp = R.RodParams(length=12.0, radius=2.0)
+    for r in range(len(before)):
+        d = after[r, :3] - before[r, :3]
+        d[0] -= 96 * np.round(d[0] / 96)
+        d[1] -= 48 * np.round(d[1] / 48)
+        assert np.abs(d[:2] - 500 * after[r, 7:9]).max() < 0.5
+    assert np.abs(after[:, 3:7] - before[:, 3:7]).max() == 0.0  # orientation kept
+    orods = R.Rods(after[:, :3], after[:, 3:7], after[:, 7:10], after[:, 10:13], rp, (96, 48, 32), (True, True, False))
+    assert _min_gap(orods) >= lp.rod_d0 - 1e-5
+    want = (orods.mask(spec.shape) >= 0).sum(axis=0)
+    assert np.array_equal(lat.rod_map(), want)
+    lat.coupled_step(20)
+    o = lat.observables(allow_unstable=True)
+    assert o["status"] == 0
+    lat.close()
