@@ -228,14 +228,16 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     lats = [make(d) for d in specs]
     batch = Batch(lats)
     t0 = time.perf_counter()
-    xf, xb = SU.rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=warm)
+    xf, xb, healthy = SU.rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=warm)
     t_gen = time.perf_counter() - t0
     batch.close()
-    status = 0
+    lat_status = []
     for lat in lats:
-        status |= int(lat.observables(allow_unstable=True)["status"])
+        lat_status.append(int(lat.observables(allow_unstable=True)["status"]))
         lat.close()
-    finite = torch.isfinite(xf.view(len(specs), n_snap, -1)).all(dim=2).cpu().numpy()
+    # pairs only from lattices whose status word is still clear at the later
+    # snapshot: states on the way to an instability are not training data
+    finite = torch.isfinite(xf.view(len(specs), n_snap, -1)).all(dim=2).cpu().numpy() & healthy
     ntrain = len(specs) * 7 // 8
     train = [(xf[i, s], xb[i, s], xf[i, s + 1]) for i in range(ntrain) for s in range(n_snap - 1)
              if finite[i, s] and finite[i, s + 1]]
@@ -286,11 +288,27 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     ma = lat_a.observables(allow_unstable=True)
     mb = lat_b.observables(allow_unstable=True)
     mass_err = float(abs(mb["mass"][0] - ma["mass"][0]) / ma["mass"][0])
-    # deposit density: z-projected rod occupancy maps, L1 over the total
-    ra, rb = lat_a.rod_map(), lat_b.rod_map()
-    dep_err = float(np.abs(ra - rb).sum() / max(1, ra.sum())) if ra.sum() else 0.0
+    # deposit: L1 distance of the z-projected rod-fraction maps of the two
+    # end states on the canvas, over the LBM map's total
+    ca, _ = SU.restrict(lat_a, D, H, W)
+    cb, _ = SU.restrict(lat_b, D, H, W)
+    rmap_a = ca.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
+    rmap_b = cb.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
+    dep_err = float(np.abs(rmap_a - rmap_b).sum() / max(rmap_a.sum(), 1e-30)) if rmap_a.sum() > 0 else 0.0
+    # deposit density profile g^b along x (Eq. 14) and the contact graph
+    nzl, nyl, nxl = specs[idx]["shape"]
+    dspec = (16, 4, (nxl - 1) / 2, (nyl - 1) / 2, float(nxl), nyl / 2.0)
+    da, db = lat_a.deposit(*dspec), lat_b.deposit(*dspec)
+    g_err = float(np.abs(da["g_x"] - db["g_x"]).mean())
+    ra, rb = lat_a.rods(), lat_b.rods()
+    dx_r = rb[:, :3] - ra[:, :3]
+    for ax, n in ((0, nxl), (1, nyl)):
+        dx_r[:, ax] -= n * np.round(dx_r[:, ax] / n)
+    rod_err = float(np.sqrt((dx_r ** 2).sum(axis=1)).mean()) if len(ra) else 0.0
+    status_b = int(mb["status"])
     lat_a.close()
     lat_b.close()
+    n_unstable = int(sum(1 for st in lat_status if st))
     out = {
         "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
         "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),
@@ -298,12 +316,17 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         "test_loss": ev, "gain_over_persistence": ev["persistence"] / max(ev["net"], 1e-30),
         "fwd_ms": ms_fwd, "fwd_tflops": flops / (ms_fwd * 1e-3) / 1e12, "fwd_gflop_per_sample": flops / 1e9,
         "ms_lbm_interval": ms_lbm, "ms_surrogate_interval": ms_sur, "speedup": ms_lbm / ms_sur,
-        "mass_error_vs_lbm": mass_err, "deposit_error_vs_lbm": dep_err,
-        "fallback_threshold": 0.005, "would_fall_back": mass_err > 0.005, "status": status,
+        "mass_error_vs_lbm": mass_err, "deposit_error_vs_lbm": dep_err, "g_x_error_vs_lbm": g_err,
+        "rod_position_error": rod_err, "rods": int(len(ra)),
+        "contacts": {"lbm": [int(da["edges"]), int(da["largest"])], "surrogate": [int(db["edges"]), int(db["largest"])]},
+        "fallback_threshold": 0.005, "would_fall_back": mass_err > 0.005, "status_after_jump": status_b,
+        "rollout_unstable_droplets": n_unstable, "pairs_dropped_unhealthy": int(
+            (len(specs) * 7 // 8) * (n_snap - 1) - len(train) + (len(specs) - len(specs) * 7 // 8) * (n_snap - 2) - len(test)),
     }
     if log_fn:
         log_fn(f"[surrogate] gain over persistence x{out['gain_over_persistence']:.2f}, speedup x{out['speedup']:.2f}, "
-               f"mass error {mass_err:.2e}, forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s)")
+               f"mass error {mass_err:.2e}, deposit error {dep_err:.3f}, g_x error {g_err:.3f}, rod error {rod_err:.2f}, "
+               f"forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s), {n_unstable} unstable rollouts")
     return out
 
 
@@ -335,7 +358,7 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
-    ap.add_argument("--surrogate-epochs", type=int, default=6)
+    ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
     args = ap.parse_args()
     global TILE_CACHE

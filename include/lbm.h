@@ -319,9 +319,15 @@ int lb_sur_jump_rods(lb_ctx *ctx, const float *coarse_now, const float *coarse_n
  * The input is the concatenation of x1 (channels [0, c1); at half resolution
  * and read through nearest-neighbour upsampling when up1 != 0) and x2
  * (channels [c1, c1 + c2), full resolution; c2 = 0 for none).  w: BF16
- * [27][c1 + c2][cout], tap t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1); b: FP32
- * [cout] or null; outputs y (BF16) and/or yf (FP32) [D][H][W][cout].  c1, c2,
- * cout: multiples of 8; D, H, W even when up1.  Asynchronous.
+ * [27][c1 + c2][cout], tap t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1); wt: the
+ * same weights packed [cout][27][c1 + c2] (lb_conv_pack_weights), read by the
+ * forward only; b: FP32 [cout] or null; outputs y (BF16) and/or yf (FP32)
+ * [D][H][W][cout]; acc: nullable FP32 scratch [D][H][W][cout] (forward
+ * only; with it a layer of few output tiles splits its K range over more
+ * work-groups, adding partial sums with atomics, so the summation order
+ * varies).  c1, c2, cout: multiples of 8; D, H, W even when up1;
+ * D H W max(c1 + c2, cout) < 2^31.  Asynchronous; LB_EINVAL on bad shapes or
+ * null pointers.
  */
 typedef struct {
     const void *x1;
@@ -329,19 +335,27 @@ typedef struct {
     const void *x2;
     int32_t c2;
     const void *w;
+    const void *wt;
     const float *b;
     void *y;
     float *yf;
+    float *acc;
     int32_t D, H, W, cout, relu;
 } lb_conv;
 int lb_conv3d_forward(const lb_conv *conv, hipStream_t stream);
+/* wt [cout][27][cin] = w [27][cin][cout] (BF16, device). */
+int lb_conv_pack_weights(const void *w, int32_t cin, int32_t cout, void *wt, hipStream_t stream);
+/* g = BF16(dy) masked by y > 0 when relu (dy FP32, y BF16, n elements): the
+ * gradient at a convolution's pre-activation, the operand of both backward
+ * passes below. */
+int lb_relu_grad(const float *dy, const void *y, int64_t n, int32_t relu, void *g, hipStream_t stream);
 /* dx [D][H][W][c1 + c2] FP32 (overwritten) = the input gradient for the
- * output gradient dy [D][H][W][cout] FP32; with relu, dy is masked by y > 0
- * (conv->y must then hold the forward output). */
-int lb_conv3d_backward_data(const lb_conv *conv, const float *dy, float *dx, hipStream_t stream);
+ * pre-activation gradient g [D][H][W][cout] BF16 (lb_relu_grad).  Layers of
+ * few output tiles split K and add into dx with atomics (order varies). */
+int lb_conv3d_backward_data(const lb_conv *conv, const void *g, float *dx, hipStream_t stream);
 /* dw [27][c1 + c2][cout] and db [cout] (nullable) FP32 += the parameter
- * gradients (accumulated with atomics, so the summation order varies). */
-int lb_conv3d_backward_weights(const lb_conv *conv, const float *dy, float *dw, float *db, hipStream_t stream);
+ * gradients for g (accumulated with atomics, so the summation order varies). */
+int lb_conv3d_backward_weights(const lb_conv *conv, const void *g, float *dw, float *db, hipStream_t stream);
 /* 2 x 2 x 2 average pooling of BF16 x [D][H][W][C] into y [D/2][H/2][W/2][C]. */
 int lb_pool2(const void *x, int32_t D, int32_t H, int32_t W, int32_t C, void *y, hipStream_t stream);
 /* g[p, c] = gc[parent(p), c] / 8 (+ skip[p * skip_stride + skip_off + c] when
@@ -354,6 +368,9 @@ int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_
                     hipStream_t stream);
 int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream);        /* graph-safe clear */
 int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream);       /* round to nearest even */
+/* Network input from an FP32 canvas of P cells: y[:, c] = BF16((x[:, c] -
+ * shift[c]) * gain[c]) (shift, gain: host, 8 finite values each). */
+int lb_sur_normalize(const float *x, int64_t P, const float *shift, const float *gain, void *y, hipStream_t stream);
 /* Network prediction on P canvas cells: pred[:, c] = xin[:, c] + scale[c] *
  * out[:, c] for c < 6 (residual; scale: host, 6 positive values, null = 1),
  * channels 6, 7 copied from xin; into pred (FP32) and/or pred_bf16. */

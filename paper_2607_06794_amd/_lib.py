@@ -46,6 +46,9 @@ EXPORTS = (
     "lb_conv3d_forward",
     "lb_conv3d_backward_data",
     "lb_conv3d_backward_weights",
+    "lb_conv_pack_weights",
+    "lb_relu_grad",
+    "lb_sur_normalize",
     "lb_pool2",
     "lb_pool2_backward",
     "lb_up2_backward",
@@ -163,9 +166,11 @@ class LbConv(ct.Structure):
         ("x2", ct.c_void_p),
         ("c2", ct.c_int32),
         ("w", ct.c_void_p),
+        ("wt", ct.c_void_p),
         ("b", ct.c_void_p),
         ("y", ct.c_void_p),
         ("yf", ct.c_void_p),
+        ("acc", ct.c_void_p),
         ("D", ct.c_int32),
         ("H", ct.c_int32),
         ("W", ct.c_int32),
@@ -255,6 +260,9 @@ def load(path: str = LIB_PATH):
         "lb_conv3d_backward_data": [P(LbConv), V, V, V],
         "lb_conv3d_backward_weights": [P(LbConv), V, V, V, V],
         "lb_pool2": [V, I32, I32, I32, I32, V, V],
+        "lb_conv_pack_weights": [V, I32, I32, V, V],
+        "lb_relu_grad": [V, V, I64, I32, V, V],
+        "lb_sur_normalize": [V, I64, V, V, V, V],
         "lb_pool2_backward": [V, V, I32, I32, I32, I32, I32, I32, V, V],
         "lb_up2_backward": [V, I32, I32, I32, I32, I32, V, V],
         "lb_fill_f32": [V, I64, ct.c_float, V],

@@ -802,13 +802,16 @@ int lb_sur_jump_rods(lb_ctx *c, const float *coarse_now, const float *coarse_nex
 
 static int conv_check(const lb_conv *a, bool fwd) {
     if (!a || !a->x1 || !a->w) return fail(LB_EINVAL, "null convolution argument");
+    if (fwd && !a->wt) return fail(LB_EINVAL, "the forward needs the packed weights wt");
     if (a->c1 <= 0 || a->c1 % 8 || a->c2 < 0 || a->c2 % 8 || a->cout <= 0 || a->cout % 8)
         return fail(LB_EINVAL, "channel counts must be positive multiples of 8 (c2 may be 0)");
     if (a->c2 > 0 && !a->x2) return fail(LB_EINVAL, "null x2 with c2 > 0");
     if (a->D < 1 || a->H < 1 || a->W < 1) return fail(LB_EINVAL, "empty volume");
     if (a->up1 && (a->D % 2 || a->H % 2 || a->W % 2)) return fail(LB_EINVAL, "upsampled input needs even sizes");
+    const int64_t P = int64_t(a->D) * a->H * a->W;
+    if (P * std::max(a->c1 + a->c2, a->cout) >= (int64_t(1) << 31) || int64_t(27) * (a->c1 + a->c2) * a->cout >= (1 << 30))
+        return fail(LB_EINVAL, "tensor too large (element offsets are 32-bit)");
     if (fwd && !a->y && !a->yf) return fail(LB_EINVAL, "no output");
-    if (!fwd && a->relu && !a->y) return fail(LB_EINVAL, "the ReLU mask needs the forward output y");
     return LB_OK;
 }
 
@@ -820,6 +823,7 @@ static ConvArgs conv_args(const lb_conv *a) {
     c.x2 = static_cast<const uint16_t *>(a->x2);
     c.c2 = a->c2;
     c.w = static_cast<const uint16_t *>(a->w);
+    c.wt = static_cast<const uint16_t *>(a->wt);
     c.b = a->b;
     c.y = static_cast<uint16_t *>(a->y);
     c.yf = a->yf;
@@ -834,23 +838,39 @@ static ConvArgs conv_args(const lb_conv *a) {
 int lb_conv3d_forward(const lb_conv *a, hipStream_t stream) {
     int rc = conv_check(a, true);
     if (rc) return rc;
-    HIP_TRY(launch_conv_fwd(conv_args(a), stream), "conv forward");
+    HIP_TRY(launch_conv_fwd(conv_args(a), a->acc, stream), "conv forward");
     return LB_OK;
 }
 
-int lb_conv3d_backward_data(const lb_conv *a, const float *dy, float *dx, hipStream_t stream) {
+int lb_conv3d_backward_data(const lb_conv *a, const void *g, float *dx, hipStream_t stream) {
     int rc = conv_check(a, false);
     if (rc) return rc;
-    if (!dy || !dx) return fail(LB_EINVAL, "null gradient");
-    HIP_TRY(launch_conv_dgrad(conv_args(a), dy, dx, stream), "conv backward data");
+    if (!g || !dx) return fail(LB_EINVAL, "null gradient");
+    HIP_TRY(launch_conv_dgrad(conv_args(a), static_cast<const uint16_t *>(g), dx, stream), "conv backward data");
     return LB_OK;
 }
 
-int lb_conv3d_backward_weights(const lb_conv *a, const float *dy, float *dw, float *db, hipStream_t stream) {
+int lb_conv3d_backward_weights(const lb_conv *a, const void *g, float *dw, float *db, hipStream_t stream) {
     int rc = conv_check(a, false);
     if (rc) return rc;
-    if (!dy || !dw) return fail(LB_EINVAL, "null gradient");
-    HIP_TRY(launch_conv_wgrad(conv_args(a), dy, dw, db, stream), "conv backward weights");
+    if (!g || !dw) return fail(LB_EINVAL, "null gradient");
+    HIP_TRY(launch_conv_wgrad(conv_args(a), static_cast<const uint16_t *>(g), dw, db, stream), "conv backward weights");
+    return LB_OK;
+}
+
+int lb_conv_pack_weights(const void *w, int32_t cin, int32_t cout, void *wt, hipStream_t stream) {
+    if (!w || !wt || cin <= 0 || cout <= 0 || int64_t(27) * cin * cout >= (1 << 30))
+        return fail(LB_EINVAL, "bad weight packing");
+    HIP_TRY(launch_pack_weights(static_cast<const uint16_t *>(w), cin, cout, static_cast<uint16_t *>(wt), stream),
+            "pack weights");
+    return LB_OK;
+}
+
+int lb_relu_grad(const float *dy, const void *y, int64_t n, int32_t relu, void *g, hipStream_t stream) {
+    if (!dy || !g || n < 0 || (relu && !y)) return fail(LB_EINVAL, "bad ReLU gradient");
+    if (n == 0) return LB_OK;
+    HIP_TRY(launch_relu_grad(dy, static_cast<const uint16_t *>(y), n, relu != 0, static_cast<uint16_t *>(g), stream),
+            "relu grad");
     return LB_OK;
 }
 
@@ -896,6 +916,18 @@ static int chan_scale(const float *scale, ChanScale &sc) {
             if (!(scale[c] > 0.0f)) return fail(LB_EINVAL, "channel scale %d must be positive", c);
             sc.s[c] = scale[c];
         }
+    return LB_OK;
+}
+
+int lb_sur_normalize(const float *x, int64_t P, const float *shift, const float *gain, void *y, hipStream_t stream) {
+    if (!x || !y || !shift || !gain || P < 1) return fail(LB_EINVAL, "bad normalisation arguments");
+    ChanScale sh, gn;
+    for (int c = 0; c < 8; ++c) {
+        if (!isfinite(shift[c]) || !isfinite(gain[c])) return fail(LB_EINVAL, "non-finite normalisation");
+        sh.s[c] = shift[c];
+        gn.s[c] = gain[c];
+    }
+    HIP_TRY(launch_normalize(x, P, sh, gn, static_cast<uint16_t *>(y), stream), "normalise");
     return LB_OK;
 }
 

@@ -147,14 +147,17 @@ struct ConvArgs {
     const uint16_t *x2;  // channels [c1, c1 + c2), full resolution (c2 may be 0)
     int c2;
     const uint16_t *w;   // [27][c1 + c2][cout]
+    const uint16_t *wt;  // the same weights packed [cout][27][c1 + c2] (forward)
     const float *b;      // [cout] or null
     uint16_t *y;         // [P][cout] BF16 output (or null)
     float *yf;           // [P][cout] FP32 output (or null)
     int D, H, W, cout, relu;
 };
-hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t s);
-hipError_t launch_conv_dgrad(const ConvArgs &a, const float *dy, float *dx, hipStream_t s);
-hipError_t launch_conv_wgrad(const ConvArgs &a, const float *dy, float *dw, float *db, hipStream_t s);
+hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s);
+hipError_t launch_conv_dgrad(const ConvArgs &a, const uint16_t *g, float *dx, hipStream_t s);
+hipError_t launch_conv_wgrad(const ConvArgs &a, const uint16_t *g, float *dw, float *db, hipStream_t s);
+hipError_t launch_pack_weights(const uint16_t *w, int cin, int cout, uint16_t *wt, hipStream_t s);
+hipError_t launch_relu_grad(const float *dy, const uint16_t *y, int64_t n, int relu, uint16_t *g, hipStream_t s);
 hipError_t launch_pool2(const uint16_t *x, int D, int H, int W, int C, uint16_t *y, hipStream_t s);
 hipError_t launch_pool2_back(const float *gc, const float *skip, int skip_stride, int skip_off, int D, int H, int W,
                              int C, float *g, hipStream_t s);
@@ -164,6 +167,8 @@ hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s)
 struct ChanScale {
     float s[8];  // per-channel output scale of the network (channels 0..5)
 };
+hipError_t launch_normalize(const float *x, int64_t P, const ChanScale &shift, const ChanScale &gain, uint16_t *y,
+                            hipStream_t s);
 hipError_t launch_residual(const float *out, const float *xin, int64_t P, const ChanScale &sc, float *pred,
                            uint16_t *predb, hipStream_t s);
 constexpr int SUR_LOSS_SCRATCH = 256 * 7 + 8;  // doubles

@@ -2,21 +2,23 @@
 // canvas, prolongation and lift back to populations, and the training and
 // inference kernels of a 3-D convolutional U-Net.
 //
-// Convolutions are implicit GEMMs on BF16 MFMA (32 x 32 x 8, FP32
+// Convolutions are implicit GEMMs on BF16 MFMA (32 x 32 x 16, FP32
 // accumulation).  Tensors are channels-last, [D][H][W][C], C a multiple of 8.
 //   forward  y[p, o]  = b[o] + sum_{t, c} x[p + o_t, c] w[t, c, o]
 //            M = positions, N = output channels, K = 27 x input channels
 //   dgrad    dx[q, c] = sum_{t, o} g[q - o_t, o] w[t, c, o],  g = dy (y > 0)
 //            M = positions, N = input channels, K = 27 x output channels
 //   wgrad    dw[t, c, o] += sum_p x[p + o_t, c] g[p, o]
-//            per tap: M = input channels, N = output channels, K = positions
-// A work-group of four wavefronts computes a 64 x 64 output tile, each
-// wavefront a 32 x 32 block; K advances in steps of 32 staged through LDS.
+//            M = 27 x input channels, N = output channels, K = positions
+// A work-group of four wavefronts computes a 256 x 32, 128 x 64 or 128 x 128
+// tile (chosen by N), each wavefront 64 x 32 or 64 x 64; K advances in steps
+// of 32 through two LDS buffers.
 // The decoder's inputs are read in place: channels [0, c1) from the coarser
 // level through nearest-neighbour upsampling, [c1, c1 + c2) from the skip.
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lbm_device.h"
@@ -26,7 +28,6 @@ namespace lbm {
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ inline uint16_t f2bf(float x) {
@@ -36,254 +37,429 @@ __device__ inline uint16_t f2bf(float x) {
 }
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
-constexpr int TM = 64, TN = 64, TK = 32;
-constexpr int LDA = TK + 8;   // A tile row stride (elements)
-constexpr int LDB = TN + 8;   // B tile row stride
-constexpr int NTH = 256;
-
-__device__ inline void tap_offset(int t, int &dz, int &dy, int &dx) {
-    dz = t / 9 - 1;
-    dy = (t / 3) % 3 - 1;
-    dx = t % 3 - 1;
-}
-
-// 8 consecutive channels [c, c + 8) of the (virtual) input at full-resolution
-// position (qd, qh, qw); zeros outside the volume or past cin
-__device__ inline void load_in8(const ConvArgs &a, int qd, int qh, int qw, int c, uint16_t out[8]) {
-    const int cin = a.c1 + a.c2;
-    bool ok = qd >= 0 && qd < a.D && qh >= 0 && qh < a.H && qw >= 0 && qw < a.W && c < cin;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (ok) {
-        if (c < a.c1) {
-            int64_t idx;
-            if (a.up1)
-                idx = (int64_t(qd >> 1) * (a.H >> 1) + (qh >> 1)) * (a.W >> 1) + (qw >> 1);
-            else
-                idx = (int64_t(qd) * a.H + qh) * a.W + qw;
-            v = *reinterpret_cast<const uint4 *>(a.x1 + idx * a.c1 + c);
-        } else {
-            const int64_t idx = (int64_t(qd) * a.H + qh) * a.W + qw;
-            v = *reinterpret_cast<const uint4 *>(a.x2 + idx * a.c2 + (c - a.c1));
-        }
-    }
-    const uint16_t *s = reinterpret_cast<const uint16_t *>(&v);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) out[j] = s[j];
-}
-
-// 8 consecutive channels of g = dy (y > 0) (or dy without the ReLU) at p
-__device__ inline void load_g8(const ConvArgs &a, const float *dy, int64_t p, int o, bool valid, uint16_t out[8]) {
-    if (!valid || o >= a.cout) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) out[j] = 0;
-        return;
-    }
-    const float4 g0 = *reinterpret_cast<const float4 *>(dy + p * a.cout + o);
-    const float4 g1 = *reinterpret_cast<const float4 *>(dy + p * a.cout + o + 4);
-    float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-    if (a.relu) {
-        const uint4 yv = *reinterpret_cast<const uint4 *>(a.y + p * a.cout + o);
-        const uint16_t *ys = reinterpret_cast<const uint16_t *>(&yv);
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (!(bf2f(ys[j]) > 0.0f)) g[j] = 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) out[j] = f2bf(g[j]);
-}
-
-// one 32 x 32 x 32 step of a wavefront from LDS: A[m][k] at sa + m * lda + k
-// (or transposed: sa + k * lda + m), B[k][n] at sb + k * ldb + n
-template <bool AT>
-__device__ inline void mma_step(const uint16_t *sa, int lda, const uint16_t *sb, int ldb, v16f &acc) {
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 8) {
-        v4s av, bv;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = kk + 4 * (l >> 5) + i;
-            av[i] = AT ? short(sa[k * lda + (l & 31)]) : short(sa[(l & 31) * lda + k]);
-            bv[i] = short(sb[k * ldb + (l & 31)]);
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
-    }
-}
 
 // ---------------------------------------------------------------------------
-// forward
+// forward and input gradient: one implicit GEMM, C[M][N] = sum_k A[M][k] B[k][N]
+//   forward: M = positions p, N = output channels o, k = (tap t, input channel c),
+//            A[p][k] = x[p + o_t][c], B[k][o] = wt[o][t][c] (packed weights)
+//   dgrad:   M = positions q, N = input channels c, k = (tap t, output channel o),
+//            A[q][k] = g[q - o_t][o], B[k][c] = w[t][c][o]
+// Both operands sit in LDS K-contiguous per row ([row][BK + 8], 80-byte rows,
+// conflict-free 16-byte reads), so every MFMA operand is one 128-bit LDS
+// read: lane l takes row l % 32, k = 8 (l / 32) .. + 7 of a 32 x 32 x 16
+// block.  K advances by BK = 32 per stage through two LDS buffers; the global
+// loads of stage s + 1 are in flight while stage s computes, one barrier per
+// stage.  TPR threads share an A row (4 / TPR k-groups of 8 channels each);
+// the row's coordinates and its 27-bit mask of in-volume taps are computed
+// once, so a stage costs each thread a few integer operations per load.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTH) conv_fwd_kernel(ConvArgs a) {
-    __shared__ uint16_t As[TM * LDA];
-    __shared__ uint16_t Bs[TK * LDB];
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int BK = 32, LDK = BK + 8;
+
+// bit t set when tap t of (d, h, w) lies inside the volume
+__device__ inline unsigned tap_mask(int d, int h, int w, int D, int H, int W) {
+    const unsigned mz = 2u | (d > 0 ? 1u : 0u) | (d < D - 1 ? 4u : 0u);
+    const unsigned my = 2u | (h > 0 ? 1u : 0u) | (h < H - 1 ? 4u : 0u);
+    const unsigned mx = 2u | (w > 0 ? 1u : 0u) | (w < W - 1 ? 4u : 0u);
+    unsigned m = 0;
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+        if ((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) m |= 1u << t;
+    return m;
+}
+
+template <int BM, int BN, int WM, int WN, bool DGRAD>
+__global__ void __launch_bounds__(256) conv_gemm_kernel(ConvArgs a, const uint16_t *g, float *dx, float *acc_out) {
+    static_assert(WM * WN == 4, "four wavefronts");
+    constexpr int MB = BM / WM / 32, NB = BN / WN / 32;
+    static_assert(MB >= 1 && NB >= 1 && MB * WM * 32 == BM && NB * WN * 32 == BN, "tile shape");
+    constexpr int TPR = 256 / BM, GPT = 4 / TPR;  // threads per A row, k-groups per thread
+    constexpr int BLD = BN * 4;                    // B loads (16 bytes) per stage
+    constexpr int BLT = BLD >= 256 ? BLD / 256 : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];
+
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int64_t p0 = int64_t(blockIdx.x) * TM;
-    const int o0 = blockIdx.y * TN;
+    const int P = a.D * a.H * a.W;
+    const int HW = a.H * a.W;
     const int cin = a.c1 + a.c2;
-    const int m0 = (wv >> 1) * 32, n0 = (wv & 1) * 32;
-    v16f acc;
+    const int N = DGRAD ? cin : a.cout;   // columns of C
+    const int kc = DGRAD ? a.cout : cin;  // channels per tap along k
+    const int Kd = 27 * kc;
+    const int m0 = blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int wm = (wv / WN) * MB * 32, wn = (wv % WN) * NB * 32;
+
+    // ---- this thread's A row and its k-groups
+    // rows tid % BM; the k-groups (tid / BM) * GPT .. are the same for a whole
+    // wavefront, so its tap and channel bookkeeping is scalar
+    const int ar = tid % BM, ag0 = __builtin_amdgcn_readfirstlane((tid / BM) * GPT);
+    const int p = m0 + ar;
+    const bool prow = p < P;
+    const int pw = p % a.W, ph = (p / a.W) % a.H, pd = p / HW;
+    unsigned tmask = prow ? tap_mask(pd, ph, pw, a.D, a.H, a.W) : 0u;
+    // split-K: work-group z of gridDim.z takes stages [s0, s1) and adds its
+    // partial sums (no bias or ReLU) into acc_out (forward) or dx (dgrad)
+    const int nst_all = (Kd + BK - 1) / BK;
+    const int s0 = int(int64_t(nst_all) * blockIdx.z / gridDim.z);
+    const int s1 = int(int64_t(nst_all) * (blockIdx.z + 1) / gridDim.z);
+    const bool split = gridDim.z > 1;
+    int gt[GPT], gc[GPT];  // tap and channel of each k-group at the current stage
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    // this thread's A row and B row
-    const int ar = tid >> 2, ac = (tid & 3) * 8;
-    const int64_t pa = p0 + ar;
-    const bool arow = pa < P;
-    const int aw = int(pa % a.W), ah = int((pa / a.W) % a.H), ad = int(pa / (int64_t(a.W) * a.H));
-    const int br = tid >> 3, bc = (tid & 7) * 8;
-    for (int t = 0; t < 27; ++t) {
-        int dz, dy, dx;
-        tap_offset(t, dz, dy, dx);
-        for (int c0 = 0; c0 < cin; c0 += TK) {
-            uint16_t va[8];
-            if (arow)
-                load_in8(a, ad + dz, ah + dy, aw + dx, c0 + ac, va);
-            else
-#pragma unroll
-                for (int j = 0; j < 8; ++j) va[j] = 0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) As[ar * LDA + ac + j] = va[j];
-            uint4 wb = make_uint4(0, 0, 0, 0);
-            if (c0 + br < cin && o0 + bc < a.cout)
-                wb = *reinterpret_cast<const uint4 *>(a.w + (int64_t(t) * cin + c0 + br) * a.cout + o0 + bc);
-            const uint16_t *wbs = reinterpret_cast<const uint16_t *>(&wb);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) Bs[br * LDB + bc + j] = wbs[j];
-            __syncthreads();
-            mma_step<false>(As + m0 * LDA, LDA, Bs + n0, LDB, acc);
-            __syncthreads();
-        }
+    for (int j = 0; j < GPT; ++j) {
+        gt[j] = (s0 * BK + 8 * (ag0 + j)) / kc;
+        gc[j] = (s0 * BK + 8 * (ag0 + j)) % kc;
     }
-    // D element i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
+    const int H2 = a.H >> 1, W2 = a.W >> 1;
+
+    // ---- B: BN rows x 4 k-groups per stage
+    int bn[BLT], bgi[BLT], bt[BLT], bc[BLT];
+    bool bon[BLT];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t p = p0 + m0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-        const int o = o0 + n0 + (l & 31);
-        if (p >= P || o >= a.cout) continue;
-        float v = acc[i] + (a.b ? a.b[o] : 0.0f);
+    for (int j = 0; j < BLT; ++j) {
+        const int idx = tid + 256 * j;
+        bn[j] = idx >> 2;
+        bgi[j] = idx & 3;
+        bon[j] = idx < BLD && n0 + bn[j] < N;
+        bt[j] = (s0 * BK + 8 * bgi[j]) / kc;
+        bc[j] = (s0 * BK + 8 * bgi[j]) % kc;
+    }
+
+    // Loads are unconditional (an invalid one reads a safe address) and the
+    // zero fill happens at the LDS store, so no load waits on another.
+    uint4 ra[GPT], rb[BLT];
+    bool aok[GPT], bok[BLT];
+    const uint16_t *asafe = DGRAD ? g : a.x1;
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < GPT; ++j) {
+            const int t = gt[j], c = gc[j];
+            const bool ok = prow && (k0 + 8 * (ag0 + j) < Kd) && ((tmask >> (DGRAD ? 26 - t : t)) & 1u);
+            const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dxx = t % 3 - 1;
+            const uint16_t *src;
+            if (DGRAD) {
+                src = g + (p - (dz * HW + dyy * a.W + dxx)) * a.cout + c;
+            } else if (c < a.c1) {
+                if (a.up1) {
+                    const int q = (((pd + dz) >> 1) * H2 + ((ph + dyy) >> 1)) * W2 + ((pw + dxx) >> 1);
+                    src = a.x1 + q * a.c1 + c;
+                } else {
+                    src = a.x1 + (p + dz * HW + dyy * a.W + dxx) * a.c1 + c;
+                }
+            } else {
+                src = a.x2 + (p + dz * HW + dyy * a.W + dxx) * a.c2 + (c - a.c1);
+            }
+            ra[j] = *reinterpret_cast<const uint4 *>(ok ? src : asafe);
+            aok[j] = ok;
+        }
+#pragma unroll
+        for (int j = 0; j < BLT; ++j) {
+            const bool ok = bon[j] && k0 + 8 * bgi[j] < Kd;
+            const uint16_t *src = DGRAD ? a.w + (bt[j] * cin + n0 + bn[j]) * a.cout + bc[j]
+                                        : a.wt + (n0 + bn[j]) * Kd + k0 + 8 * bgi[j];
+            rb[j] = *reinterpret_cast<const uint4 *>(ok ? src : (DGRAD ? a.w : a.wt));
+            bok[j] = ok;
+        }
+    };
+    auto advance = [&]() {
+#pragma unroll
+        for (int j = 0; j < GPT; ++j) {
+            gc[j] += BK;
+            while (gc[j] >= kc) {
+                gc[j] -= kc;
+                ++gt[j];
+            }
+        }
+        if (DGRAD) {
+#pragma unroll
+            for (int j = 0; j < BLT; ++j) {
+                bc[j] += BK;
+                while (bc[j] >= kc) {
+                    bc[j] -= kc;
+                    ++bt[j];
+                }
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < GPT; ++j)
+            *reinterpret_cast<uint4 *>(&As[buf][ar * LDK + 8 * (ag0 + j)]) = aok[j] ? ra[j] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < BLT; ++j)
+            if (tid + 256 * j < BLD)
+                *reinterpret_cast<uint4 *>(&Bs[buf][bn[j] * LDK + 8 * bgi[j]]) = bok[j] ? rb[j] : make_uint4(0, 0, 0, 0);
+    };
+
+    v16f acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    const int nst = s1 - s0;
+    load(s0 * BK);
+    store(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < nst) {
+            advance();
+            load((s0 + st + 1) * BK);
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            v8bf fa[MB], fb[NB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                fa[i] = *reinterpret_cast<const v8bf *>(&As[cur][(wm + 32 * i + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                fb[j] = *reinterpret_cast<const v8bf *>(&Bs[cur][(wn + 32 * j + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < nst) store(cur ^ 1);
+        __syncthreads();
+    }
+
+    // D element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int col = n0 + wn + 32 * j + (l & 31);
+            if (col >= N) continue;
+            const float bias = (!DGRAD && a.b) ? a.b[col] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+                if (row >= P) continue;
+                if (split) {
+                    atomicAdd((DGRAD ? dx + row * cin : acc_out + row * a.cout) + col, acc[i][j][e]);
+                } else if (DGRAD) {
+                    dx[row * cin + col] = acc[i][j][e];
+                } else {
+                    float v = acc[i][j][e] + bias;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    if (a.y) a.y[row * a.cout + col] = f2bf(v);
+                    if (a.yf) a.yf[row * a.cout + col] = v;
+                }
+            }
+        }
+}
+
+// packed forward weights: wt[o][t][c] = w[t][c][o]
+__global__ void pack_weights_kernel(const uint16_t *w, int cin, int cout, uint16_t *wt) {
+    const int n = 27 * cin * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int o = e / (27 * cin), k = e % (27 * cin);
+        wt[e] = w[k * cout + o];
+    }
+}
+
+// g = BF16(dy (y > 0)) (or BF16(dy) without the ReLU)
+__global__ void relu_grad_kernel(const float *dy, const uint16_t *y, int64_t n, int relu, uint16_t *g) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const float v = (relu && !(bf2f(y[i]) > 0.0f)) ? 0.0f : dy[i];
+        g[i] = f2bf(v);
+    }
+}
+
+
+// Weight gradient as one GEMM over all taps: C[(t, c)][o] = sum_p x[p + o_t][c]
+// g[p][o], M = 27 cin rows in dw's own (tap-major) order, N = cout, K = the
+// positions of one chunk; chunks add their partial sums with FP32 atomics.
+// Operands are staged K-contiguous ([row][position]): each thread loads 8
+// channels of one position (16 bytes) and scatters them down a column.  A
+// g tile serves every tap of the row tile.
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(ConvArgs a, const uint16_t *g, float *dw, int chunk) {
+    constexpr int MB = BM / WM / 32, NB = BN / WN / 32;
+    static_assert(WM * WN == 4 && MB * WM * 32 == BM && NB * WN * 32 == BN, "tile shape");
+    constexpr int XL = BM / 64, GL = BN / 64;  // loads per thread (0: the first 4 BM or 4 BN threads)
+    constexpr int XLT = XL > 0 ? XL : 1, GLT = GL > 0 ? GL : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Gs[2][BN * LDK];
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int P = a.D * a.H * a.W, HW = a.H * a.W;
+    const int cin = a.c1 + a.c2;
+    const int M = 27 * cin;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.z * BN;
+    const int wm = (wv / WN) * MB * 32, wn = (wv % WN) * NB * 32;
+    const int pbeg = blockIdx.x * chunk, pend = min(P, pbeg + chunk);
+    const int pl = tid & 31;
+    const int H2 = a.H >> 1, W2 = a.W >> 1;
+
+    // x loads: rows m0 + 8 rg .. + 7 (tap t, channels c .. c + 7), position pl
+    int xc[XLT], xr[XLT], xdz[XLT], xdy[XLT], xdx[XLT];
+    bool xon[XLT];
+#pragma unroll
+    for (int j = 0; j < XLT; ++j) {
+        const int rg = (tid >> 5) + 8 * j;
+        xr[j] = 8 * rg;
+        const int r = m0 + xr[j];
+        xon[j] = (XL > 0 || tid < 4 * BM) && r < M;
+        const int t = xon[j] ? r / cin : 13;
+        xc[j] = r % cin;
+        xdz[j] = t / 9 - 1;
+        xdy[j] = (t / 3) % 3 - 1;
+        xdx[j] = t % 3 - 1;
+    }
+    int go[GLT];
+    bool gon[GLT];
+#pragma unroll
+    for (int j = 0; j < GLT; ++j) {
+        go[j] = 8 * ((tid >> 5) + 8 * j);
+        gon[j] = (GL > 0 || tid < 4 * BN) && n0 + go[j] < a.cout;
+    }
+    // this thread's position, advanced by BK per stage
+    int cp = pbeg + pl, cw = cp % a.W, chh = (cp / a.W) % a.H, cd = cp / HW;
+
+    uint4 rx[XLT], rg[GLT];
+    bool xok[XLT], gok[GLT];
+    auto load = [&]() {
+        const bool valid = cp < pend;
+#pragma unroll
+        for (int j = 0; j < XLT; ++j) {
+            const int qd = cd + xdz[j], qh = chh + xdy[j], qw = cw + xdx[j];
+            const bool ok = valid && xon[j] && unsigned(qd) < unsigned(a.D) && unsigned(qh) < unsigned(a.H) &&
+                            unsigned(qw) < unsigned(a.W);
+            const int c = xc[j];
+            const uint16_t *src;
+            if (c < a.c1)
+                src = a.up1 ? a.x1 + (((qd >> 1) * H2 + (qh >> 1)) * W2 + (qw >> 1)) * a.c1 + c
+                            : a.x1 + ((qd * a.H + qh) * a.W + qw) * a.c1 + c;
+            else
+                src = a.x2 + ((qd * a.H + qh) * a.W + qw) * a.c2 + (c - a.c1);
+            rx[j] = *reinterpret_cast<const uint4 *>(ok ? src : a.x1);
+            xok[j] = ok;
+        }
+#pragma unroll
+        for (int j = 0; j < GLT; ++j) {
+            const bool ok = valid && gon[j];
+            rg[j] = *reinterpret_cast<const uint4 *>(ok ? g + cp * a.cout + n0 + go[j] : g);
+            gok[j] = ok;
+        }
+    };
+    auto advance = [&]() {
+        cp += BK;
+        cw += BK;
+        while (cw >= a.W) {
+            cw -= a.W;
+            if (++chh >= a.H) {
+                chh = 0;
+                ++cd;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < XLT; ++j) {
+            if (!(XL > 0 || tid < 4 * BM)) continue;
+            const uint4 w = xok[j] ? rx[j] : make_uint4(0, 0, 0, 0);
+            const uint16_t *v = reinterpret_cast<const uint16_t *>(&w);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Xs[buf][(xr[j] + e) * LDK + pl] = v[e];
+        }
+#pragma unroll
+        for (int j = 0; j < GLT; ++j) {
+            if (!(GL > 0 || tid < 4 * BN)) continue;
+            const uint4 w = gok[j] ? rg[j] : make_uint4(0, 0, 0, 0);
+            const uint16_t *v = reinterpret_cast<const uint16_t *>(&w);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Gs[buf][(go[j] + e) * LDK + pl] = v[e];
+        }
+    };
+
+    v16f acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    const int nst = (pend - pbeg + BK - 1) / BK;
+    load();
+    store(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < nst) {
+            advance();
+            load();
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            v8bf fa[MB], fb[NB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                fa[i] = *reinterpret_cast<const v8bf *>(&Xs[cur][(wm + 32 * i + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                fb[j] = *reinterpret_cast<const v8bf *>(&Gs[cur][(wn + 32 * j + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < nst) store(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int col = n0 + wn + 32 * j + (l & 31);
+            if (col >= a.cout) continue;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+                if (row < M) atomicAdd(dw + int64_t(row) * a.cout + col, acc[i][j][e]);
+            }
+        }
+}
+
+// bias gradient: db[o] += sum_p g[p, o] over a chunk of positions; 256 / cout
+// position lanes per channel (each summing about 16 positions), combined in
+// LDS, one atomic per channel and chunk
+__global__ void conv_bgrad_kernel(int P, int cout, int chunk, const uint16_t *g, float *db) {
+    __shared__ float part[256];
+    const int pbeg = blockIdx.x * chunk, pend = min(P, pbeg + chunk);
+    const int cw = min(cout, 256), G = 256 / cw;
+    const int t = threadIdx.x, oc = t % cw, r = t / cw;
+    for (int o0 = 0; o0 < cout; o0 += cw) {
+        const int o = o0 + oc;
+        float s = 0.0f;
+        if (r < G && o < cout)
+            for (int p = pbeg + r; p < pend; p += G) s += bf2f(g[p * cout + o]);
+        part[t] = s;
+        __syncthreads();
+        if (t < cw && o0 + t < cout) {
+            float tot = 0.0f;
+            for (int q = 0; q < G; ++q) tot += part[q * cw + t];
+            atomicAdd(db + o0 + t, tot);
+        }
+        __syncthreads();
+    }
+}
+
+// split-K forward epilogue: y = ReLU(acc + b) in BF16 and/or FP32
+__global__ void conv_finalize_kernel(ConvArgs a, const float *acc) {
+    const int64_t n = int64_t(a.D) * a.H * a.W * a.cout;
+    for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+        float v = acc[e] + (a.b ? a.b[e % a.cout] : 0.0f);
         if (a.relu) v = fmaxf(v, 0.0f);
-        if (a.y) a.y[p * a.cout + o] = f2bf(v);
-        if (a.yf) a.yf[p * a.cout + o] = v;
+        if (a.y) a.y[e] = f2bf(v);
+        if (a.yf) a.yf[e] = v;
     }
-}
-
-// ---------------------------------------------------------------------------
-// input gradient
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTH) conv_dgrad_kernel(ConvArgs a, const float *dy, float *dx) {
-    __shared__ uint16_t As[TM * LDA];
-    __shared__ uint16_t Bs[TK * LDB];
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int64_t q0 = int64_t(blockIdx.x) * TM;
-    const int c0n = blockIdx.y * TN;  // input-channel tile
-    const int cin = a.c1 + a.c2;
-    const int m0 = (wv >> 1) * 32, n0 = (wv & 1) * 32;
-    v16f acc;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    const int ar = tid >> 2, ac = (tid & 3) * 8;
-    const int64_t qa = q0 + ar;
-    const bool arow = qa < P;
-    const int aw = int(qa % a.W), ah = int((qa / a.W) % a.H), ad = int(qa / (int64_t(a.W) * a.H));
-    // B tile rows are output channels k, columns input channels n: thread loads
-    // 8 output channels of one input channel and scatters them down a column
-    const int bn = tid >> 2, bk = (tid & 3) * 8;
-    for (int t = 0; t < 27; ++t) {
-        int dz, dyy, dxx;
-        tap_offset(t, dz, dyy, dxx);
-        const int sd = ad - dz, sh = ah - dyy, sw = aw - dxx;
-        const bool in = arow && sd >= 0 && sd < a.D && sh >= 0 && sh < a.H && sw >= 0 && sw < a.W;
-        const int64_t ps = (int64_t(sd) * a.H + sh) * a.W + sw;
-        for (int o0 = 0; o0 < a.cout; o0 += TK) {
-            uint16_t va[8];
-            load_g8(a, dy, ps, o0 + ac, in, va);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) As[ar * LDA + ac + j] = va[j];
-            uint4 wb = make_uint4(0, 0, 0, 0);
-            if (c0n + bn < cin && o0 + bk < a.cout)
-                wb = *reinterpret_cast<const uint4 *>(a.w + (int64_t(t) * cin + c0n + bn) * a.cout + o0 + bk);
-            const uint16_t *wbs = reinterpret_cast<const uint16_t *>(&wb);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) Bs[(bk + j) * LDB + bn] = wbs[j];
-            __syncthreads();
-            mma_step<false>(As + m0 * LDA, LDA, Bs + n0, LDB, acc);
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t q = q0 + m0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-        const int c = c0n + n0 + (l & 31);
-        if (q < P && c < cin) dx[q * cin + c] = acc[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// weight gradient (accumulated with FP32 atomics over position chunks)
-// ---------------------------------------------------------------------------
-constexpr int WG_CHUNK = 2048;  // positions per work-group
-
-__global__ void __launch_bounds__(NTH) conv_wgrad_kernel(ConvArgs a, const float *dy, float *dw) {
-    __shared__ uint16_t Xs[TK * LDB];  // [position][input channel]
-    __shared__ uint16_t Gs[TK * LDB];  // [position][output channel]
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int cin = a.c1 + a.c2;
-    const int ntile_o = (a.cout + TN - 1) / TN;
-    const int ci0 = (blockIdx.y / ntile_o) * TM, o0 = (blockIdx.y % ntile_o) * TN;
-    const int t = blockIdx.z;
-    int dz, dyy, dxx;
-    tap_offset(t, dz, dyy, dxx);
-    const int m0 = (wv >> 1) * 32, n0 = (wv & 1) * 32;
-    v16f acc;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    const int r = tid >> 3, cc = (tid & 7) * 8;
-    const int64_t pbeg = int64_t(blockIdx.x) * WG_CHUNK;
-    const int64_t pend = min(P, pbeg + WG_CHUNK);
-    for (int64_t pk = pbeg; pk < pend; pk += TK) {
-        const int64_t p = pk + r;
-        const bool valid = p < pend;
-        const int pw = int(p % a.W), ph = int((p / a.W) % a.H), pd = int(p / (int64_t(a.W) * a.H));
-        uint16_t vx[8], vg[8];
-        if (valid)
-            load_in8(a, pd + dz, ph + dyy, pw + dxx, ci0 + cc, vx);
-        else
-#pragma unroll
-            for (int j = 0; j < 8; ++j) vx[j] = 0;
-        load_g8(a, dy, p, o0 + cc, valid, vg);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            Xs[r * LDB + cc + j] = vx[j];
-            Gs[r * LDB + cc + j] = vg[j];
-        }
-        __syncthreads();
-        // A[m = input channel][k = position] is Xs transposed
-        mma_step<true>(Xs + m0, LDB, Gs + n0, LDB, acc);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int c = ci0 + m0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-        const int o = o0 + n0 + (l & 31);
-        if (c < cin && o < a.cout) atomicAdd(dw + (int64_t(t) * cin + c) * a.cout + o, acc[i]);
-    }
-}
-
-// bias gradient: db[o] += sum_p g[p, o]; thread per (chunk, channel)
-__global__ void conv_bgrad_kernel(ConvArgs a, const float *dy, float *db) {
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int o = threadIdx.x;
-    if (o >= a.cout) return;
-    const int64_t pbeg = int64_t(blockIdx.x) * WG_CHUNK, pend = min(P, pbeg + WG_CHUNK);
-    float s = 0.0f;
-    for (int64_t p = pbeg; p < pend; ++p) {
-        float g = dy[p * a.cout + o];
-        if (a.relu && !(bf2f(a.y[p * a.cout + o]) > 0.0f)) g = 0.0f;
-        s += g;
-    }
-    atomicAdd(db + o, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -464,6 +640,14 @@ __global__ void residual_kernel(const float *out, const float *xin, int64_t P, C
         const float v = c < 6 ? xin[e] + sc.s[c] * out[e] : xin[e];
         if (pred) pred[e] = v;
         if (predb) predb[e] = f2bf(v);
+    }
+}
+
+// network input: y[:, c] = BF16((x[:, c] - shift[c]) * gain[c]) on [P][8] cells
+__global__ void normalize_kernel(const float *x, int64_t P, ChanScale shift, ChanScale gain, uint16_t *y) {
+    for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < P * 8; e += int64_t(gridDim.x) * blockDim.x) {
+        const int c = int(e & 7);
+        y[e] = f2bf((x[e] - shift.s[c]) * gain.s[c]);
     }
 }
 
@@ -687,27 +871,87 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t s) {
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    hipLaunchKernelGGL(conv_fwd_kernel, dim3(unsigned((P + TM - 1) / TM), (a.cout + TN - 1) / TN), dim3(NTH), 0, s, a);
+template <bool DGRAD>
+static hipError_t launch_gemm(const ConvArgs &a, const uint16_t *g, float *dx, float *acc, hipStream_t s) {
+    const int P = a.D * a.H * a.W;
+    const int N = DGRAD ? a.c1 + a.c2 : a.cout;
+    const int kc = DGRAD ? a.cout : a.c1 + a.c2;
+    const int nst = (27 * kc + BK - 1) / BK;
+    // 256-row tiles while they give at least ~2 work-groups per CU, else 128;
+    // layers with fewer tiles than that split K over up to 512 work-groups
+    // (at least 8 stages each) when there is somewhere to add the partials
+    const int bn = N <= 32 ? 32 : (N <= 64 ? 64 : 128);
+    const unsigned ny = unsigned((N + bn - 1) / bn);
+    const bool big = int64_t((P + 255) / 256) * ny >= 512;
+    const unsigned gx = unsigned(big ? (P + 255) / 256 : (P + 127) / 128);
+    unsigned gz = 1;
+    if ((DGRAD || acc) && gx * ny < 256) gz = unsigned(std::max(1, std::min(nst / 8, int(512 / (gx * ny)))));
+    if (gz > 1) {
+        float *dst = DGRAD ? dx : acc;
+        const int64_t n = int64_t(P) * N;
+        hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, n, 0.0f);
+    }
+    const dim3 grid(gx, ny, gz);
+    if (N <= 32) {
+        if (big)
+            hipLaunchKernelGGL((conv_gemm_kernel<256, 32, 4, 1, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+        else
+            hipLaunchKernelGGL((conv_gemm_kernel<128, 32, 4, 1, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+    } else if (N <= 64) {
+        if (big)
+            hipLaunchKernelGGL((conv_gemm_kernel<256, 64, 4, 1, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+        else
+            hipLaunchKernelGGL((conv_gemm_kernel<128, 64, 2, 2, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+    } else {
+        if (big)
+            hipLaunchKernelGGL((conv_gemm_kernel<256, 128, 2, 2, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+        else
+            hipLaunchKernelGGL((conv_gemm_kernel<128, 128, 2, 2, DGRAD>), grid, dim3(256), 0, s, a, g, dx, acc);
+    }
+    if (!DGRAD && gz > 1)
+        hipLaunchKernelGGL(conv_finalize_kernel, dim3(grid_for(int64_t(P) * N)), dim3(256), 0, s, a, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_conv_dgrad(const ConvArgs &a, const float *dy, float *dx, hipStream_t s) {
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int cin = a.c1 + a.c2;
-    hipLaunchKernelGGL(conv_dgrad_kernel, dim3(unsigned((P + TM - 1) / TM), (cin + TN - 1) / TN), dim3(NTH), 0, s, a, dy,
-                       dx);
+hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s) {
+    return launch_gemm<false>(a, nullptr, nullptr, acc, s);
+}
+
+hipError_t launch_conv_dgrad(const ConvArgs &a, const uint16_t *g, float *dx, hipStream_t s) {
+    return launch_gemm<true>(a, g, dx, nullptr, s);
+}
+
+hipError_t launch_conv_wgrad(const ConvArgs &a, const uint16_t *g, float *dw, float *db, hipStream_t s) {
+    const int P = a.D * a.H * a.W;
+    const int M = 27 * (a.c1 + a.c2);
+    // position chunks: about 1024 work-groups, 256 to 4096 positions each
+    auto launch = [&](auto kern, int BM, int BN) {
+        const unsigned tm = unsigned((M + BM - 1) / BM), tn = unsigned((a.cout + BN - 1) / BN);
+        int chunk = 4096;
+        while (chunk > 256 && int64_t((P + chunk - 1) / chunk) * tm * tn < 1024) chunk /= 2;
+        hipLaunchKernelGGL(kern, dim3(unsigned((P + chunk - 1) / chunk), tm, tn), dim3(256), 0, s, a, g, dw, chunk);
+    };
+    if (a.cout <= 32)
+        launch(conv_wgrad_kernel<256, 32, 4, 1>, 256, 32);
+    else if (a.cout <= 64)
+        launch(conv_wgrad_kernel<128, 64, 2, 2>, 128, 64);
+    else
+        launch(conv_wgrad_kernel<128, 128, 2, 2>, 128, 128);
+    if (db) {
+        const int chunk = 16 * (256 / std::min(a.cout, 256));
+        hipLaunchKernelGGL(conv_bgrad_kernel, dim3(unsigned((P + chunk - 1) / chunk)), dim3(256), 0, s, P, a.cout, chunk,
+                           g, db);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_conv_wgrad(const ConvArgs &a, const float *dy, float *dw, float *db, hipStream_t s) {
-    const int64_t P = int64_t(a.D) * a.H * a.W;
-    const int cin = a.c1 + a.c2;
-    const unsigned nchunk = unsigned((P + WG_CHUNK - 1) / WG_CHUNK);
-    const int tiles = ((cin + TM - 1) / TM) * ((a.cout + TN - 1) / TN);
-    hipLaunchKernelGGL(conv_wgrad_kernel, dim3(nchunk, tiles, 27), dim3(NTH), 0, s, a, dy, dw);
-    if (db) hipLaunchKernelGGL(conv_bgrad_kernel, dim3(nchunk), dim3(256), 0, s, a, dy, db);
+hipError_t launch_pack_weights(const uint16_t *w, int cin, int cout, uint16_t *wt, hipStream_t s) {
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(grid_for(int64_t(27) * cin * cout)), dim3(256), 0, s, w, cin, cout, wt);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_grad(const float *dy, const uint16_t *y, int64_t n, int relu, uint16_t *g, hipStream_t s) {
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(grid_for(n)), dim3(256), 0, s, dy, y, n, relu, g);
     return hipGetLastError();
 }
 
@@ -737,6 +981,12 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s) {
 
 hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const float *x, int64_t P, const ChanScale &shift, const ChanScale &gain, uint16_t *y,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(normalize_kernel, dim3(grid_for(P * 8)), dim3(256), 0, s, x, P, shift, gain, y);
     return hipGetLastError();
 }
 

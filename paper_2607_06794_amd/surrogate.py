@@ -74,6 +74,7 @@ class UNet:
         self.m = torch.zeros(n, **f32)
         self.v = torch.zeros(n, **f32)
         self.pb = torch.zeros(n, dtype=torch.int16, device=self.device)
+        self.pt = torch.zeros(n, dtype=torch.int16, device=self.device)  # weights packed for the forward
         self.step_count = 0
         # activations (BF16) and gradients (FP32) per level
         self.P = [(D >> l) * (H >> l) * (W >> l) for l in range(nlev)]
@@ -89,11 +90,26 @@ class UNet:
         self.gcat = [torch.zeros(self.P[l] * (self.ch[l] + (self.ch[l + 1] if l + 1 < nlev - 1 else self.ch[-1])), **f32)
                      for l in range(nlev - 1)]
         self.loss_scratch = torch.zeros(self.lib.lb_sur_loss_scratch_bytes() // 4 + 64, **f32)
+        # BF16 pre-activation gradient of the layer being differentiated
+        self.gm = torch.zeros(max(self.P[lvl] * co for _, _, _, co, _, lvl in self.layers), **bf)
+        # FP32 scratch for the split-K forward of the coarse levels
+        self.acc = torch.zeros(max(self.P[lvl] * co for _, _, _, co, _, lvl in self.layers if lvl >= 1), **f32)
         # output scale per channel (the network predicts changes in these units)
         self.scale = np.ones(6, np.float32)
+        # input normalisation: lattice velocities are O(1e-3 .. 1e-2) next to
+        # O(1) densities and fractions, so they enter the network scaled by 100
+        self.in_shift = np.zeros(8, np.float32)
+        self.in_gain = np.array([1, 1, 100, 100, 100, 1, 1, 1], np.float32)
+        self.xin = torch.zeros(self.P[0] * CIN, **bf)
 
     def set_scale(self, scale):
         self.scale = np.ascontiguousarray(scale, dtype=np.float32).reshape(6)
+
+    def prepare(self, x_f32):
+        """The normalised BF16 network input of an FP32 canvas (kept in self.xin)."""
+        _lib.check(self.lib.lb_sur_normalize(_p(x_f32), self.P[0], self.in_shift.ctypes.data_as(ct.c_void_p),
+                                             self.in_gain.ctypes.data_as(ct.c_void_p), _p(self.xin), self._s()))
+        return self.xin
 
     # ------------------------------------------------------------------ params
     def _s(self):
@@ -117,6 +133,14 @@ class UNet:
         self.v.zero_()
         self.step_count = 0
         _lib.check(self.lib.lb_to_bf16(_p(self.p), self.nparam, _p(self.pb), self._s()))
+        self._pack()
+
+    def _pack(self):
+        """Forward copies of the BF16 weights, [cout][27][cin] per layer."""
+        for name, c1, c2, co, _, _ in self.layers:
+            o = self.off[name][0]
+            _lib.check(self.lib.lb_conv_pack_weights(ct.c_void_p(self.pb.data_ptr() + 2 * o), c1 + c2, co,
+                                                     ct.c_void_p(self.pt.data_ptr() + 2 * o), self._s()))
 
     def set_layer(self, name, w, b):
         """w [27][cin_used][cout_used] and b [cout_used] (host arrays), zero padded."""
@@ -145,9 +169,11 @@ class UNet:
         cv.x1, cv.c1, cv.up1 = x1.data_ptr(), c[1], c[4]
         cv.x2, cv.c2 = (x2.data_ptr() if x2 is not None else None), c[2]
         cv.w = self.pb.data_ptr() + 2 * o
+        cv.wt = self.pt.data_ptr() + 2 * o
         cv.b = self.p.data_ptr() + 4 * ob
         cv.y = y.data_ptr() if y is not None else None
         cv.yf = yf.data_ptr() if yf is not None else None
+        cv.acc = self.acc.data_ptr() if lvl >= 1 else None
         cv.D, cv.H, cv.W = self.D >> lvl, self.H >> lvl, self.W >> lvl
         cv.cout, cv.relu = co, relu
         return cv, o, ob
@@ -189,10 +215,12 @@ class UNet:
     def _wgrad_dgrad(self, name, x1, x2, y, dy, dx):
         cv, o, ob = self._conv(name, x1, x2, y=y, relu=0 if name == "out" else 1)
         s = self._s()
-        _lib.check(self.lib.lb_conv3d_backward_weights(ct.byref(cv), _p(dy), ct.c_void_p(self.g.data_ptr() + 4 * o),
+        n = cv.D * cv.H * cv.W * cv.cout
+        _lib.check(self.lib.lb_relu_grad(_p(dy), _p(y) if y is not None else None, n, cv.relu, _p(self.gm), s))
+        _lib.check(self.lib.lb_conv3d_backward_weights(ct.byref(cv), _p(self.gm), ct.c_void_p(self.g.data_ptr() + 4 * o),
                                                        ct.c_void_p(self.g.data_ptr() + 4 * ob), s))
         if dx is not None:
-            _lib.check(self.lib.lb_conv3d_backward_data(ct.byref(cv), _p(dy), _p(dx), s))
+            _lib.check(self.lib.lb_conv3d_backward_data(ct.byref(cv), _p(self.gm), _p(dx), s))
 
     def backward(self, gout):
         """Accumulate the parameter gradients for dloss/dout = gout [P0][8] FP32
@@ -237,6 +265,7 @@ class UNet:
         self.step_count += 1
         _lib.check(self.lib.lb_adam(_p(self.p), _p(self.g), _p(self.m), _p(self.v), _p(self.pb), self.nparam,
                                     self.step_count, lr, b1, b2, eps, self._s()))
+        self._pack()
 
     def loss(self, xin_f32, tgt_f32, lam=1.0, grad=None, sync=True):
         """(loss, relative mass error) of pred = xin + out against tgt; grad
@@ -248,10 +277,12 @@ class UNet:
         return (res[3], res[2]) if sync else None
 
     def train_step(self, x_bf16, xin_f32, tgt_f32, lam=1.0, lr=1e-3):
+        """One Adam step on one pair; x_bf16 is the network input (None: the
+        normalised input of xin_f32)."""
         if not hasattr(self, "_gout"):
             self._gout = self.torch.zeros(self.P[0] * COUT, dtype=self.torch.float32, device=self.device)
         self.zero_grad()
-        self.forward(x_bf16)
+        self.forward(x_bf16 if x_bf16 is not None else self.prepare(xin_f32))
         out = self.loss(xin_f32, tgt_f32, lam, grad=self._gout)
         self.backward(self._gout)
         self.adam(lr)
@@ -294,9 +325,10 @@ def _stream(lat):
     return ct.c_void_p(s.cuda_stream)
 
 
-def predict(net, x_f32, x_bf16, pred_f32=None, pred_bf16=None):
-    """pred = x + network(x) on the first six channels (library kernels)."""
-    net.forward(x_bf16)
+def predict(net, x_f32, x_bf16=None, pred_f32=None, pred_bf16=None):
+    """pred = x + network(x) on the first six channels (library kernels); the
+    network reads the normalised input of x_f32 (x_bf16 is not used)."""
+    net.forward(net.prepare(x_f32))
     _lib.check(net.lib.lb_sur_residual(_p(net.out), _p(x_f32), net.P[0], net.scale.ctypes.data_as(ct.c_void_p),
                                        _p(pred_f32), _p(pred_bf16), net._s()))
     return pred_f32, pred_bf16
@@ -315,13 +347,18 @@ def channel_scales(net, pairs, floor=1e-6):
 
 def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True):
     """Canvases of every lattice every `interval` steps (after `warm` steps):
-    tensors [n_lat, n_snap, P * 8] in FP32 and BF16."""
+    tensors [n_lat, n_snap, P * 8] in FP32 and BF16, and a host array
+    healthy[n_lat, n_snap]: so far no NaN, no non-positive density, no rod
+    limit (status bits 1, 2, 8, 16, 32; the velocity bit 4 alone also trips
+    on the start-up transient of a fresh cap) and no canvas speed above
+    0.15."""
     import torch
 
     P = D * H * W
     dev = lats[0].device
     xf = torch.empty((len(lats), n_snap, P * 8), dtype=torch.float32, device=dev)
     xb = torch.empty((len(lats), n_snap, P * 8), dtype=torch.int16, device=dev)
+    healthy = np.zeros((len(lats), n_snap), bool)
     if warm:
         batch.step(warm, rods=rods)
     for s in range(n_snap):
@@ -329,13 +366,17 @@ def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True)
             batch.step(interval, rods=rods)
         for i, lat in enumerate(lats):
             restrict(lat, D, H, W, xf[i, s], xb[i, s])
+            st = int(lat.observables(allow_unstable=True)["status"])
+            u = xf[i, s].view(P, 8)[:, 2:5]
+            healthy[i, s] = (st & ~4) == 0 and bool(torch.isfinite(u).all()) and float(u.abs().max()) <= 0.15
     torch.cuda.synchronize()
-    return xf, xb
+    return xf, xb, healthy
 
 
-def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None):
+def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None, warmup=100):
     """Adam on (x_f32, x_bf16, y_f32) pairs, `batch` samples per update
-    (gradients summed), in channel-normalised units (scales from the pairs).
+    (gradients summed), in channel-normalised units (scales from the pairs);
+    the learning rate ramps up linearly over the first `warmup` updates.
     Returns the mean training loss of every epoch."""
     rng = np.random.Generator(np.random.PCG64(seed))
     import torch
@@ -350,11 +391,12 @@ def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None):
             net.zero_grad()
             for j in order[k:k + batch]:
                 xf, xb, yf = pairs[j]
-                net.forward(xb)
+                net.forward(net.prepare(xf))
                 loss, _ = net.loss(xf, yf, lam, grad=gout)
                 net.backward(gout)
                 tot += loss
-            net.adam(lr)
+            upd = net.step_count + 1
+            net.adam(lr * min(1.0, upd / max(1, warmup)))
         hist.append(tot / max(1, len(pairs)))
         if log:
             log(f"[surrogate] epoch {ep}: loss {hist[-1]:.4e}")
@@ -372,7 +414,7 @@ def evaluate(net, pairs, lam=1.0, prev=None):
     if prev is not None:
         res["linear"] = 0.0
     for k, (xf, xb, yf) in enumerate(pairs):
-        net.forward(xb)
+        net.forward(net.prepare(xf))
         l, me = net.loss(xf, yf, lam)
         res["net"] += l
         res["mass_err_net"] += abs(me)

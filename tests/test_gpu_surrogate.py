@@ -62,12 +62,13 @@ def _stream():
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _conv(x1, c1, up1, x2, c2, w, b, D, H, W, cout, relu, y=None, yf=None):
+def _conv(x1, c1, up1, x2, c2, w, b, D, H, W, cout, relu, y=None, yf=None, wt=None):
     L, _ = _lib()
     cv = L.LbConv()
     cv.x1, cv.c1, cv.up1 = x1.data_ptr(), c1, up1
     cv.x2, cv.c2 = (x2.data_ptr() if x2 is not None else None), c2
     cv.w = w.data_ptr()
+    cv.wt = wt.data_ptr() if wt is not None else None
     cv.b = b.data_ptr() if b is not None else None
     cv.y = y.data_ptr() if y is not None else None
     cv.yf = yf.data_ptr() if yf is not None else None
@@ -75,8 +76,16 @@ def _conv(x1, c1, up1, x2, c2, w, b, D, H, W, cout, relu, y=None, yf=None):
     return cv
 
 
+# Tile shapes follow N (output channels forward, input channels for the input
+# gradient): <= 32, <= 64, > 64 (and > 128: two column tiles).  The larger
+# cases span several work-groups with ragged last tiles and several
+# weight-gradient position chunks; layers of few tiles split K (the forward
+# when given FP32 scratch, checked both ways), the last case has enough tiles
+# not to.
 @pytest.mark.parametrize("D,H,W,c1,c2,cout,up", [(3, 5, 7, 8, 0, 8, 0), (4, 6, 10, 16, 0, 72, 0),
-                                                   (4, 6, 8, 32, 16, 40, 1), (6, 10, 22, 64, 32, 128, 1)])
+                                                   (4, 6, 8, 32, 16, 40, 1), (6, 10, 22, 64, 32, 128, 1),
+                                                   (8, 16, 40, 32, 0, 32, 0), (6, 12, 34, 128, 64, 64, 1),
+                                                   (8, 16, 42, 64, 32, 136, 1), (16, 32, 64, 32, 0, 32, 0)])
 def test_conv_forward_and_gradients(D, H, W, c1, c2, cout, up):
     import torch
 
@@ -94,25 +103,40 @@ def test_conv_forward_and_gradients(D, H, W, c1, c2, cout, up):
     y = torch.zeros(D * H * W * cout, dtype=torch.int16, device="cuda:0")
     tx1, tw, tb = dev(x1b), dev(wb), dev(b)
     tx2 = dev(x2b) if c2 else None
-    cv = _conv(tx1, c1, up, tx2, c2, tw, tb, D, H, W, cout, 1, y=y, yf=yf)
+    twt = torch.zeros(27 * cin * cout, dtype=torch.int16, device="cuda:0")
+    L.check(lib.lb_conv_pack_weights(tw.data_ptr(), cin, cout, twt.data_ptr(), _stream()))
+    assert int((host(twt).reshape(cout, 27, cin) != wb.reshape(27, cin, cout).transpose(2, 0, 1)).sum()) == 0
+    cv = _conv(tx1, c1, up, tx2, c2, tw, tb, D, H, W, cout, 1, y=y, yf=yf, wt=twt)
     L.check(lib.lb_conv3d_forward(ct.byref(cv), _stream()))
     ref = np.maximum(OS.conv3d(xin, w, b.astype(np.float64)), 0.0)
     got = host(yf).reshape(D, H, W, cout)
     scale = np.abs(ref).max()
     assert np.abs(got - ref).max() <= 2e-5 * scale
+    # again with FP32 scratch: split K where the layer has few tiles
+    acc = torch.zeros(D * H * W * cout, dtype=torch.float32, device="cuda:0")
+    yf2 = torch.zeros_like(yf)
+    y2 = torch.zeros_like(y)
+    cv2 = _conv(tx1, c1, up, tx2, c2, tw, tb, D, H, W, cout, 1, y=y2, yf=yf2, wt=twt)
+    cv2.acc = acc.data_ptr()
+    L.check(lib.lb_conv3d_forward(ct.byref(cv2), _stream()))
+    assert np.abs(host(yf2).reshape(D, H, W, cout) - ref).max() <= 2e-5 * scale
     # gradients with the ReLU mask of this output; dy BF16-representable
     dyv, _ = bf16_round(RNG.normal(size=(D, H, W, cout)))
     tdy = dev(dyv.astype(np.float32))
     ybits = host(y).reshape(D, H, W, cout)
     yv = (ybits.astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
     g = dyv * (yv > 0)
+    tg = torch.zeros(D * H * W * cout, dtype=torch.int16, device="cuda:0")
+    L.check(lib.lb_relu_grad(tdy.data_ptr(), y.data_ptr(), D * H * W * cout, 1, tg.data_ptr(), _stream()))
+    gbits = bf16_round(np.where(yv > 0, dyv, 0.0))[1]  # +0 where masked, as the kernel writes
+    assert int((host(tg).reshape(D, H, W, cout) != gbits).sum()) == 0
     dx = torch.zeros(D * H * W * cin, dtype=torch.float32, device="cuda:0")
-    L.check(lib.lb_conv3d_backward_data(ct.byref(cv), tdy.data_ptr(), dx.data_ptr(), _stream()))
+    L.check(lib.lb_conv3d_backward_data(ct.byref(cv), tg.data_ptr(), dx.data_ptr(), _stream()))
     dref = OS.conv3d_dgrad(g, w)
     assert np.abs(host(dx).reshape(D, H, W, cin) - dref).max() <= 2e-5 * np.abs(dref).max()
     dw = torch.zeros(27 * cin * cout, dtype=torch.float32, device="cuda:0")
     db = torch.zeros(cout, dtype=torch.float32, device="cuda:0")
-    L.check(lib.lb_conv3d_backward_weights(ct.byref(cv), tdy.data_ptr(), dw.data_ptr(), db.data_ptr(), _stream()))
+    L.check(lib.lb_conv3d_backward_weights(ct.byref(cv), tg.data_ptr(), dw.data_ptr(), db.data_ptr(), _stream()))
     wref, bref = OS.conv3d_wgrad(xin, g)
     assert np.abs(host(dw).reshape(27, cin, cout) - wref).max() <= 2e-5 * np.abs(wref).max()
     assert np.abs(host(db) - bref).max() <= 2e-5 * np.abs(bref).max()
@@ -299,7 +323,8 @@ def test_training_beats_persistence_on_lbm_trajectories():
                  body_force=(0.0, 0.0, 0.0))
         lats.append(Lattice(cases.lattice_params(c, "f32"), rho, mat))
     batch = Batch(lats)
-    xf, xb = SU.rollout_snapshots(batch, lats, 7, 40, D, H, W, warm=20, rods=False)
+    xf, xb, healthy = SU.rollout_snapshots(batch, lats, 7, 40, D, H, W, warm=20, rods=False)
+    assert healthy.all()
     batch.close()
     for lat in lats:
         lat.close()
