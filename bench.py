@@ -330,6 +330,91 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     return out
 
 
+def unet_form(reps=20):
+    """U-Net alone on the 128 x 64 x 32 canvas of the 256 x 128 x 64 cap at
+    t = 0: forward and forward + backward, timed with events on the
+    network's stream.  One JSON line; used to profile the convolutions."""
+    import torch
+
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Lattice
+    from tests import cases
+
+    D, H, W = 32, 64, 128
+    c = cases.cap_case()
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    lat.step(50)
+    xf, _ = SU.restrict(lat, D, H, W)
+    lat.close()
+    net = SU.UNet(D, H, W).init(0)
+    tgt = xf.clone()
+    gout = torch.zeros(net.P[0] * SU.COUT, dtype=torch.float32, device=xf.device)
+    flops = sum(2.0 * 27 * (c1 + c2) * co * net.P[lvl] for _, c1, c2, co, _, lvl in net.layers)
+    stream = net.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        net.forward(net.prepare(xf))
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(net.prepare(xf))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / reps
+    net.forward(net.prepare(xf))
+    net.loss(xf, tgt, 1.0, grad=gout)
+    e0.record(stream)
+    for _ in range(reps):
+        net.zero_grad()
+        net.backward(gout)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / reps
+    return {"metric": "U-Net forward and backward", "canvas": [W, H, D], "params": int(net.nparam),
+            "gflop_forward": flops / 1e9, "ms_forward": ms_f, "ms_backward": ms_b,
+            "tflops_forward": flops / (ms_f * 1e-3) / 1e12, "tflops_backward": 2 * flops / (ms_b * 1e-3) / 1e12,
+            "peak_tflops_bf16": 2500.0, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic"}
+
+
+def copy_probe(mib, reps=5):
+    """A plain device copy of `mib` MiB (torch copy_, source written first):
+    the known byte count against which the FETCH_SIZE and WRITE_SIZE
+    counters are scaled."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"metric": "copy probe", "bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}
+
+
+def traffic_record(prec, tile, n_fluid, ms_fused):
+    """Measured HBM traffic of the fused step from the committed counter
+    record (FETCH_SIZE and WRITE_SIZE per launch, each scaled by what the
+    counter reads for a plain copy of known size), or None when the record
+    does not describe this kernel source, precision, tile and lattice."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "sc_step_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(os.path.join(ROOT, "paper_2607_06794_amd", "csrc", "sc_step.hip"), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("sc_step_sha256") != sha or rec.get("prec") != prec or rec.get("tile") != tile \
+            or rec.get("fluid_nodes") != n_fluid:
+        return None
+    kib = 1024.0
+    b = rec["fetch_kib"] * kib * rec["fetch_scale"] + rec["write_kib"] * kib * rec["write_scale"]
+    return {"bytes_per_launch": b, "gbs": b / (ms_fused * 1e-3) / 1e9,
+            "vs_algorithmic": b / (algorithmic_bytes_per_lu(prec) * n_fluid)}
+
+
 def cpu_baseline(case, sample_steps):
     from oracle import lbm
     from tests import cases
@@ -360,6 +445,8 @@ def main():
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
+    ap.add_argument("--unet-only", action="store_true", help="time the U-Net alone (one JSON line)")
+    ap.add_argument("--copy-probe", type=int, default=0, help="MiB of a plain copy for counter calibration, then exit")
     args = ap.parse_args()
     global TILE_CACHE
     TILE_CACHE = args.tile_cache
@@ -373,6 +460,12 @@ def main():
     from tests import cases
 
     torch.cuda.init()
+    if args.copy_probe:
+        print(json.dumps(copy_probe(args.copy_probe)), flush=True)
+        return
+    if args.unet_only:
+        print(json.dumps(unet_form()), flush=True)
+        return
     from paper_2607_06794_amd import inputs
 
     case = cases.cap_case()
@@ -429,6 +522,7 @@ def main():
                "sample": f"{args.cpu_steps} FP64 NumPy oracle steps of the full 256x128x64 cap from t=0 "
                          f"({dt:.1f} s, 1 of {os.cpu_count()} host cores)"}
 
+    tr = traffic_record(args.prec, chosen, n_fluid, ms_fused)
     out = {
         "metric": METRIC,
         "value": mlups,
@@ -466,7 +560,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (tr["gbs"] if tr else None),
+            "traffic_bytes_per_launch": (tr["bytes_per_launch"] if tr else None),
+            "traffic_vs_algorithmic": (tr["vs_algorithmic"] if tr else None),
             "kernel": "sc_step_kernel",
             "bytes_per_lu": bpl,
             "units_per_launch": n_fluid,
