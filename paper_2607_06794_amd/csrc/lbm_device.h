@@ -13,20 +13,28 @@ namespace lbm {
 
 constexpr int Q = 19;
 
-__host__ __device__ constexpr int cx(int i) {
-    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-    return v[i];
-}
-__host__ __device__ constexpr int cy(int i) {
-    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-    return v[i];
-}
-__host__ __device__ constexpr int cz(int i) {
-    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-    return v[i];
-}
+// Components of c_i, two bits per direction (value + 1) in one constant, so
+// that a run-time index costs a shift and a mask instead of a table in
+// private memory.
+__host__ __device__ constexpr int cx(int i) { return int((0x1548889549ull >> (2 * i)) & 3ull) - 1; }
+__host__ __device__ constexpr int cy(int i) { return int((0x895609495ull >> (2 * i)) & 3ull) - 1; }
+__host__ __device__ constexpr int cz(int i) { return int((0x20A0954955ull >> (2 * i)) & 3ull) - 1; }
 // opposite direction: pairs (1,2), (3,4), ... are adjacent
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// compile-time check of the encoded velocity set: c_0 = 0, opposite pairs,
+// six axis and twelve edge directions
+constexpr bool d3q19_ok() {
+    int axis = 0, edge = 0;
+    for (int i = 1; i < Q; ++i) {
+        if (cx(opp(i)) != -cx(i) || cy(opp(i)) != -cy(i) || cz(opp(i)) != -cz(i)) return false;
+        const int n2 = cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i);
+        axis += n2 == 1;
+        edge += n2 == 2;
+    }
+    return cx(0) == 0 && cy(0) == 0 && cz(0) == 0 && axis == 6 && edge == 12;
+}
+static_assert(d3q19_ok(), "D3Q19 velocity set");
 
 template <class C>
 __host__ __device__ constexpr C wgt(int i) {

@@ -170,17 +170,25 @@ __device__ inline double axis_dist2(const double *rod, d3 p, const RodArgs &a) {
     return dot(c, c);
 }
 
-__device__ inline double block_sum_d(double v, double *sh) {
+// out[q] = work-group sum of v[q], q < N: a fixed xor butterfly per wavefront,
+// then the wavefront sums in order (sh: N x wavefronts doubles; out written by
+// threads 0 .. N-1, zeros instead when `zero`)
+template <int N>
+__device__ inline void block_sums(double (&v)[N], double *sh, double *out, bool zero = false) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) sh[w * N + q] = v[q];
     __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int q = 0; q < int(blockDim.x >> 6); ++q) s += sh[q];
-    __syncthreads();
-    return s;
+    if (int(threadIdx.x) < N) {
+        double s = 0.0;
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) s += sh[k * N + threadIdx.x];
+        out[threadIdx.x] = zero ? 0.0 : s;
+    }
 }
 
 constexpr int RB = 256;  // threads per per-rod work-group
@@ -241,7 +249,7 @@ __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, i
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
-    __shared__ double sh[RB / 64];
+    __shared__ double sh[RB / 64 * 8];
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
@@ -284,12 +292,7 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
             }
         }
     }
-    double *part = part_slot(a.part_adh, a, r, blockIdx.x);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double v = block_sum_d(acc[q], sh);
-        if (threadIdx.x == 0) part[q] = v;
-    }
+    block_sums(acc, sh, part_slot(a.part_adh, a, r, blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -364,21 +367,29 @@ __global__ void __launch_bounds__(64) rod_pairs_kernel(RodBatch bt) {
 
 // ---------------------------------------------------------------------------
 // 2b. rigid-body substeps: one work-group of LB_MAX_RODS threads.  Centres
-//     and axes of all rods live in shared memory for the whole step; thread r
-//     keeps rod r's velocity, angular momentum and fluid load in registers,
-//     sums its pair forces over its neighbour list (in list order) and
-//     advances the rod.
+//     and axes of all rods live in shared memory for the whole step.  Pair
+//     forces: TPR = 2 (1 above 256 rods) adjacent lanes per rod split its
+//     neighbour list (lane j takes entries j, j + TPR, ...) and add their sums
+//     with a fixed xor butterfly into shared memory.  Rod update: thread r
+//     keeps rod r's velocity, angular momentum and fluid load in registers
+//     and advances it (threads 0 .. n - 1, so the FP64 update runs on as few
+//     wavefronts as possible).
 // ---------------------------------------------------------------------------
-constexpr int RS_X = 0, RS_Q = 3, RS_N = 7;  // shared-memory record per rod
+constexpr int RS_X = 0, RS_Q = 3, RS_F = 7, RS_N = 13;  // shared-memory record per rod: X, q, F, T
 
 __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt) {
     extern __shared__ double rs[];  // [n_rods][RS_N]
     const RodArgs a = bt.all[blockIdx.x];  // one work-group per lattice
-    const int nr = a.n_rods, me = threadIdx.x;
+    const int nr = a.n_rods;
+    const int TPR = nr <= LB_MAX_RODS / 2 ? 2 : 1;
+    // pair role
+    const int pr = threadIdx.x / TPR, sub_lane = threadIdx.x % TPR;
+    const bool pmine = pr < nr;
+    // update role
+    const int me = threadIdx.x;
     const bool mine = me < nr;
     const double dt = 1.0 / a.n_sub;
     d3 V = mk(0, 0, 0), Lm = mk(0, 0, 0), Fx = mk(0, 0, 0), Tx = mk(0, 0, 0), F = mk(0, 0, 0), T = mk(0, 0, 0);
-    int nn = 0;
     double *rm = rs + (mine ? me : 0) * RS_N;
     const double *rod = a.rods + (mine ? me : 0) * ROD_STRIDE;
     if (mine) {
@@ -388,21 +399,21 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
         Lm = ld3(rod + ROD_L);
         Fx = ld3(rod + ROD_FS) + ld3(rod + ROD_FA);
         Tx = ld3(rod + ROD_TS) + ld3(rod + ROD_TA);
-        nn = a.nbr_cnt[me];
     }
+    const int nn = pmine ? a.nbr_cnt[pr] : 0;
     const d3 X0 = mine ? ld3(rod + ROD_XOLD) : mk(0, 0, 0);
     const d3 e0 = mine ? quat_axis(rod + ROD_QOLD) : mk(0, 0, 1);
     bool moved_far = false;
     __syncthreads();
     for (int sub = 0; sub < a.n_sub; ++sub) {
-        if (mine) {
-            // contact forces at the positions of this substep
-            const d3 Xa = ld3(rm + RS_X), ea = quat_axis(rm + RS_Q);
+        // contact forces between rods at the positions of this substep
+        d3 Fp = mk(0, 0, 0), Tp = mk(0, 0, 0);
+        if (pmine) {
+            const double *ra = rs + pr * RS_N;
+            const d3 Xa = ld3(ra + RS_X), ea = quat_axis(ra + RS_Q);
             const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
-            F = mk(0, 0, 0);
-            T = mk(0, 0, 0);
-            for (int l = 0; l < nn; ++l) {
-                const double *rb = rs + a.nbr[me * ROD_NBR + l] * RS_N;
+            for (int l = sub_lane; l < nn; l += TPR) {
+                const double *rb = rs + a.nbr[pr * ROD_NBR + l] * RS_N;
                 const d3 Xb = ld3(rb + RS_X);
                 const d3 dx = min_image(Xb - Xa, a);
                 const d3 shift = dx - (Xb - Xa);
@@ -414,10 +425,27 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
                 const double fm = pair_force(d, a);
                 if (fm == 0.0) continue;
                 const d3 fv = (fm / d) * (ca - cb);
-                F = F + fv;
-                T = T + cross(ca - Xa, fv);
+                Fp = Fp + fv;
+                Tp = Tp + cross(ca - Xa, fv);
             }
+        }
+        // the rod's lanes are adjacent within one wavefront: fixed butterfly
+        for (int o = 1; o < TPR; o <<= 1) {
+            Fp = mk(Fp.x + __shfl_xor(Fp.x, o, 64), Fp.y + __shfl_xor(Fp.y, o, 64), Fp.z + __shfl_xor(Fp.z, o, 64));
+            Tp = mk(Tp.x + __shfl_xor(Tp.x, o, 64), Tp.y + __shfl_xor(Tp.y, o, 64), Tp.z + __shfl_xor(Tp.z, o, 64));
+        }
+        if (pmine && sub_lane == 0) {
+            double *rf = rs + pr * RS_N + RS_F;
+            st3(rf, Fp);
+            st3(rf + 3, Tp);
+        }
+        __syncthreads();
+        if (mine) {
+            F = ld3(rm + RS_F);
+            T = ld3(rm + RS_F + 3);
             if (a.wall_on) {
+                const d3 Xa = ld3(rm + RS_X), ea = quat_axis(rm + RS_Q);
+                const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
                 const d3 low = pa.z <= qa.z ? pa : qa;
                 const double h = low.z - a.wall_z;
                 if (h > 0.0 && h <= a.d0_wall) {
@@ -426,9 +454,6 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
                     T = T + cross(low - Xa, fw);
                 }
             }
-        }
-        __syncthreads();
-        if (mine) {
             V = V + (dt / a.mass) * (Fx + F);
             d3 X = ld3(rm + RS_X) + dt * V;
             Lm = Lm + dt * (Tx + T);
@@ -541,7 +566,7 @@ __global__ void fill_i32_kernel(int *p, int64_t n, int v) {
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
-    __shared__ double sh[RB / 64];
+    __shared__ double sh[RB / 64 * 8];
     __shared__ int wcount[RB / 64];
     __shared__ int64_t un_node[RB];
     __shared__ double un_out[RB][8];
@@ -606,6 +631,9 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
         const int64_t un = un_node[e];
         const int ux = int(un % a.nx), uy = int((un / a.nx) % a.ny), uz = int(un / (int64_t(a.nx) * a.ny));
         const int i = 1 + (lane >> 1), k = lane & 1;
+        // select, not index: a run-time index into the argument record would
+        // put the whole record in private memory
+        const double rref_k = k ? a.rho_ref[1] : a.rho_ref[0];
         double val = 0.0;
         bool ok = false, wall = false;
         if (lane < 2 * (Q - 1)) {
@@ -618,7 +646,7 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
                 if (ok) {
                     double s = 0.0;
 #pragma unroll
-                    for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * a.rho_ref[k];
+                    for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
                     val = s;
                 }
             }
@@ -636,8 +664,9 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
         if (lane < 2 * Q) {
             const int kk = lane / Q, ii = lane % Q;
             const double cu = cx(ii) * ub.x + cy(ii) * ub.y + cz(ii) * ub.z;
-            const double feq = wgt<double>(ii) * rb[kk] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-            f[(kk * Q + ii) * a.fs + un] = Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(ii) * a.rho_ref[kk]));
+            const double feq = wgt<double>(ii) * (kk ? rb[1] : rb[0]) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            f[(kk * Q + ii) * a.fs + un] =
+                Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(ii) * (kk ? a.rho_ref[1] : a.rho_ref[0])));
         }
         if (lane == 0) {
             const d3 mom = (rb[0] + rb[1]) * ub;
@@ -658,12 +687,7 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] += un_out[slot][q];
     }
-    double *part = part_slot(a.part_upd, a, r, blockIdx.x);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const double v = block_sum_d(acc[q], sh);
-        if (threadIdx.x == 0) part[q] = init ? 0.0 : v;
-    }
+    block_sums(acc, sh, part_slot(a.part_upd, a, r, blockIdx.x), init != 0);
 }
 
 // commit the new occupancy of rod r (after every work-group has read the old
@@ -715,7 +739,7 @@ __global__ void rod_sums_kernel(RodArgs a, double *out) {
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
-    __shared__ double sh[RB / 64];
+    __shared__ double sh[RB / 64 * 8];
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
@@ -728,44 +752,43 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
     if (shell_node(a, r, n, x, y, z)) {
         if (a.newid[n] == r) a.newid[n] = -1;
         unsigned links = 0;
-        int64_t src[Q];
         if ((a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
-                src[i] = -1;
                 if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-                src[i] = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-                if (a.rodid[src[i]] == r) links |= 1u << i;
+                if (a.rodid[(zz * a.ny + yy) * a.nx + xx] == r) links |= 1u << i;
             }
         }
         if (links) {
-            // all populations of x at once (the slot stores below cannot alias
-            // them, but the compiler would have to assume they might)
-            double fx[2][Q], rho[2];
+            double rho[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < Q; ++j) {
-                    fx[k][j] = decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
-                    s += fx[k][j];
-                }
+                for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
                 rho[k] = s;
             }
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                if (!(links & (1u << i))) continue;
-                const int64_t s = src[i];
+            // one linked direction at a time (rolled: an unrolled body per
+            // direction costs occupancy); f*_opp(i)(x) is read again from
+            // cache, which is what the slot stores to other nodes require anyway
+            for (unsigned m = links; m; m &= m - 1) {
+                const int i = __builtin_ctz(m);
+                int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
+                wrap_coord(xx, a.nx, a.px);
+                wrap_coord(yy, a.ny, a.py);
+                wrap_coord(zz, a.nz, a.pz);
+                const int64_t s = (int64_t(zz) * a.ny + yy) * a.nx + xx;
                 const d3 ci = mk(cx(i), cy(i), cz(i));
                 const d3 xb = mk(x - 0.5 * cx(i), y - 0.5 * cy(i), z - 0.5 * cz(i));
                 const d3 ub = velocity_at(rod, xb, a);
                 const d3 arm = min_image(xb - X, a);
+                const double cu = dot(ci, ub);
                 d3 dp = mk(0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const double fo = fx[k][opp(i)];
-                    const double add = 2.0 * wgt<double>(i) * rho[k] * dot(ci, ub) * 3.0;
+                    const double fo = decf(f, (k * Q + opp(i)) * a.fs + n) + wgt<double>(opp(i)) * a.rho_ref[k];
+                    const double add = 2.0 * wgt<double>(i) * rho[k] * cu * 3.0;
                     const double fin = fo + add;
                     f[(k * Q + i) * a.fs + s] = Codec<S>::enc(typename Codec<S>::C(fin - wgt<double>(i) * a.rho_ref[k]));
                     dp = dp - (fo + fin) * ci;
@@ -782,12 +805,7 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
         }
     }
     // read by the next rod update, after the fluid step has streamed these slots
-    double *part = part_slot(a.part_link, a, r, blockIdx.x);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const double v = block_sum_d(acc[q], sh);
-        if (threadIdx.x == 0) part[q] = v;
-    }
+    block_sums(acc, sh, part_slot(a.part_link, a, r, blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------
