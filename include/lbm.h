@@ -192,6 +192,15 @@ typedef struct {
 int lb_droplet_shape(lb_ctx *ctx, double xc, double yc, lb_droplet *out, hipStream_t stream);
 
 /*
+ * Pressure at probe nodes (Shan-Chen equation of state of the current state,
+ * the quantity of the Laplace check): p = c_s^2 (rho_A + rho_B) + G c_s^2
+ * psi_A psi_B with psi_k = rho_k, c_s^2 = 1/3.  xyz: host, n x (x, y, z) node
+ * coordinates, 0 <= n <= 256; p_out: host, n doubles, NaN at probes that are
+ * not fluid nodes.  LB_EINVAL for probes off the lattice.  Synchronises.
+ */
+int lb_pressure(lb_ctx *ctx, const int32_t *xyz, int32_t n, double *p_out, hipStream_t stream);
+
+/*
  * Deposit statistics of the rods (Methods, structural characterisation,
  * Eqs. 13 and 14).  Each rod is represented by nb = max(2, floor(2 h /
  * bead_spacing + 1/2) + 1) beads evenly spaced along its axis segment

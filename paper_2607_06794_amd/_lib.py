@@ -48,6 +48,7 @@ EXPORTS = (
     "lb_conv3d_backward_weights",
     "lb_conv_pack_weights",
     "lb_relu_grad",
+    "lb_pressure",
     "lb_sur_normalize",
     "lb_pool2",
     "lb_pool2_backward",
@@ -262,6 +263,7 @@ def load(path: str = LIB_PATH):
         "lb_pool2": [V, I32, I32, I32, I32, V, V],
         "lb_conv_pack_weights": [V, I32, I32, V, V],
         "lb_relu_grad": [V, V, I64, I32, V, V],
+        "lb_pressure": [V, V, I32, V, V],
         "lb_sur_normalize": [V, I64, V, V, V, V],
         "lb_pool2_backward": [V, V, I32, I32, I32, I32, I32, I32, V, V],
         "lb_up2_backward": [V, I32, I32, I32, I32, I32, V, V],

@@ -88,7 +88,7 @@ static int rod_nblk(const lb_params &p) { return rod_shell_cap(p) / 256; }
 
 // Observable scratch: droplet column scan, then deposit binning and graph.
 struct ObsLayout {
-    size_t col_h, col_wet, line_x, line_y, out, bins, sval, dep_out, labels, graph, map, total;
+    size_t col_h, col_wet, line_x, line_y, out, bins, sval, dep_out, labels, graph, map, probe_xyz, probe_p, total;
 };
 static ObsLayout obs_layout(const lb_params *p) {
     ObsLayout l{};
@@ -116,6 +116,10 @@ static ObsLayout obs_layout(const lb_params *p) {
     o = align256(o + 4 * sizeof(int32_t));
     l.map = o;
     o = align256(o + ncol * sizeof(int32_t));
+    l.probe_xyz = o;
+    o = align256(o + 3 * PROBE_MAX * sizeof(int32_t));
+    l.probe_p = o;
+    o = align256(o + PROBE_MAX * sizeof(double));
     l.total = o;
     return l;
 }
@@ -638,6 +642,26 @@ int lb_droplet_shape(lb_ctx *c, double xc, double yc, lb_droplet *out, hipStream
     out->theta_x = r[3];
     out->theta_y = r[4];
     out->wet_nodes = int64_t(r[5]);
+    return LB_OK;
+}
+
+int lb_pressure(lb_ctx *c, const int32_t *xyz, int32_t n, double *p_out, hipStream_t stream) {
+    if (!c || !xyz || !p_out || n < 0) return fail(LB_EINVAL, "null argument or negative count");
+    if (n > PROBE_MAX) return fail(LB_EINVAL, "at most %d probes per call", PROBE_MAX);
+    if (n == 0) return LB_OK;
+    const lb_params &p = c->p;
+    for (int q = 0; q < n; ++q)
+        if (xyz[3 * q] < 0 || xyz[3 * q] >= p.nx || xyz[3 * q + 1] < 0 || xyz[3 * q + 1] >= p.ny || xyz[3 * q + 2] < 0 ||
+            xyz[3 * q + 2] >= p.nz)
+            return fail(LB_EINVAL, "probe %d off the lattice", q);
+    const ObsLayout l = obs_layout(&p);
+    int *dxyz = reinterpret_cast<int *>(c->obs + l.probe_xyz);
+    double *dp = reinterpret_cast<double *>(c->obs + l.probe_p);
+    HIP_TRY(hipMemcpyAsync(dxyz, xyz, size_t(3) * n * sizeof(int32_t), hipMemcpyHostToDevice, stream), "copy probes");
+    HIP_TRY(launch_pressure(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, c->rref, p.G, dxyz, n, dp, stream),
+            "pressure");
+    HIP_TRY(hipMemcpyAsync(p_out, dp, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, stream), "copy pressure");
+    HIP_TRY(hipStreamSynchronize(stream), "pressure sync");
     return LB_OK;
 }
 

@@ -137,6 +137,9 @@ struct DepArgs {
     int32_t *graph;  // n_rods, edges, largest cluster, spanning
 };
 hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t s);
+constexpr int PROBE_MAX = 256;  // pressure probes per call
+hipError_t launch_pressure(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                           const double rref[2], double G, const int *xyz, int n, double *out, hipStream_t s);
 hipError_t launch_deposit(const DepArgs &d, hipStream_t s);
 hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s);
 

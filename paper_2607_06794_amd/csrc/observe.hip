@@ -333,6 +333,29 @@ int grid_cols(int64_t ncol) {
 
 }  // namespace
 
+// Shan-Chen equation of state at probe nodes: p = c_s^2 (rho_A + rho_B) +
+// G c_s^2 psi_A psi_B with psi = rho on fluid nodes; NaN at non-fluid probes
+template <class S>
+__global__ void pressure_probe_kernel(const S *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz, double r0,
+                                      double r1, double G, const int *xyz, int n, double *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int x = xyz[3 * q], y = xyz[3 * q + 1], z = xyz[3 * q + 2];
+    const int64_t node = (int64_t(z) * ny + y) * nx + x;
+    if ((mat[node] & MAT_ID_MASK) != MAT_FLUID) {
+        out[q] = __builtin_nan("");
+        return;
+    }
+    const double rr[2] = {r0, r1};
+    double rho[2];
+    for (int k = 0; k < 2; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += double(Codec<S>::dec(f[(k * Q + i) * fs + node])) + wgt<double>(i) * rr[k];
+        rho[k] = s;
+    }
+    out[q] = (rho[0] + rho[1]) / 3.0 + G / 3.0 * rho[0] * rho[1];
+}
+
 hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t s) {
     const int64_t ncol = int64_t(o.nx) * o.ny;
     hipError_t e;
@@ -369,6 +392,32 @@ hipError_t launch_deposit(const DepArgs &d, hipStream_t s) {
 
 hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s) {
     hipLaunchKernelGGL(rod_map_kernel, dim3(grid_cols(int64_t(nx) * ny)), dim3(256), 0, s, mat, nx, ny, nz, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                           const double rref[2], double G, const int *xyz, int n, double *out, hipStream_t s) {
+    const dim3 grid((n + 255) / 256);
+    switch (prec) {
+        case LB_F64:
+            hipLaunchKernelGGL(pressure_probe_kernel<double>, grid, dim3(256), 0, s, static_cast<const double *>(f), fs,
+                               mat, nx, ny, nz, rref[0], rref[1], G, xyz, n, out);
+            break;
+        case LB_F32:
+            hipLaunchKernelGGL(pressure_probe_kernel<float>, grid, dim3(256), 0, s, static_cast<const float *>(f), fs, mat,
+                               nx, ny, nz, rref[0], rref[1], G, xyz, n, out);
+            break;
+        case LB_F16DEV:
+            hipLaunchKernelGGL(pressure_probe_kernel<_Float16>, grid, dim3(256), 0, s, static_cast<const _Float16 *>(f),
+                               fs, mat, nx, ny, nz, rref[0], rref[1], G, xyz, n, out);
+            break;
+        case LB_BF16DEV:
+            hipLaunchKernelGGL(pressure_probe_kernel<bf16_t>, grid, dim3(256), 0, s, static_cast<const bf16_t *>(f), fs,
+                               mat, nx, ny, nz, rref[0], rref[1], G, xyz, n, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

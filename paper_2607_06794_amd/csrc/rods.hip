@@ -510,15 +510,21 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodBatch bt) {
     const double *rod = a.rods + r * ROD_STRIDE;
     const Box b = rod_box(rod, a, 2);
     const int ex = b.hi[0] - b.lo[0] + 1, ey = b.hi[1] - b.lo[1] + 1, ez = b.hi[2] - b.lo[2] + 1;
-    const int64_t nbox = (ex > 0 && ey > 0 && ez > 0) ? int64_t(ex) * ey * ez : 0;
+    // a box is a few thousand nodes: 32-bit index arithmetic; a box beyond
+    // 2^30 nodes can only come from a rod state gone bad, which is flagged
+    const int64_t nbox64 = (ex > 0 && ey > 0 && ez > 0) ? int64_t(ex) * ey * ez : 0;
+    if (nbox64 > (int64_t(1) << 30) && threadIdx.x == 0) atomicOr(a.status, ST_ROD_WALL);
+    const int nbox = nbox64 > (int64_t(1) << 30) ? 0 : int(nbox64);
+    const int exy = ex * ey;
     const double r2in = a.radius * a.radius, r2sh = shell_r2(a);
     int base = 0;  // same in every thread
-    for (int64_t m0 = 0; m0 < nbox; m0 += MB) {
-        const int64_t m = m0 + threadIdx.x;
+    for (int m0 = 0; m0 < nbox; m0 += MB) {
+        const int m = m0 + int(threadIdx.x);
         bool listed = false;
         int64_t n = 0;
         if (m < nbox) {
-            int x = b.lo[0] + int(m % ex), y = b.lo[1] + int((m / ex) % ey), z = b.lo[2] + int(m / (int64_t(ex) * ey));
+            const int mz = m / exy, rem = m - mz * exy, my = rem / ex;
+            int x = b.lo[0] + (rem - my * ex), y = b.lo[1] + my, z = b.lo[2] + mz;
             const double d2 = axis_dist2(rod, mk(x, y, z), a);
             const bool in_box = wrap_coord(x, a.nx, a.px) && wrap_coord(y, a.ny, a.py) && wrap_coord(z, a.nz, a.pz);
             if (d2 <= r2in && !in_box) atomicOr(a.status, ST_ROD_WALL);  // a rod left the lattice

@@ -219,6 +219,14 @@ class Lattice:
                 "labels": labels[: self.n_rods], "edges": g.edges, "largest": g.largest,
                 "spanning": bool(g.spanning)}
 
+    def pressure(self, probes) -> np.ndarray:
+        """Shan-Chen pressure at probe nodes [(x, y, z), ...] (NaN off the fluid)."""
+        xyz = np.ascontiguousarray(np.asarray(probes, np.int32).reshape(-1, 3))
+        out = np.zeros(len(xyz))
+        _lib.check(self.lib.lb_pressure(self._ctx, xyz.ctypes.data_as(ct.c_void_p), len(xyz),
+                                        out.ctypes.data_as(ct.c_void_p), _stream_ptr(self.stream)))
+        return out
+
     def rod_map(self) -> np.ndarray:
         """Rod nodes per (y, x) column (z-projected occupancy)."""
         nz, ny, nx = self.params.shape

@@ -117,3 +117,30 @@ def test_contact_graph_designed_chain():
         g = lat.deposit(8, 8, 99.5, 31.5, 100.0, 40.0, 2.0, 5.25, 10.0, 160.0)
         lat.close()
         assert (g["edges"], g["largest"], g["spanning"]) == want
+
+
+def test_pressure_probes_match_oracle_and_laplace():
+    """Pressure at probes after 200 steps of the periodic sphere, FP64, against
+    the oracle's equation of state on the oracle's own state; the droplet's
+    inside is at higher pressure (Laplace); a wall probe of the cap reads NaN."""
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = cases.sphere_case()
+    p = cases.oracle_params(c)
+    say("[gpu] pressure probes: 32^3 sphere, 200 steps, f64")
+    lat = Lattice(cases.lattice_params(c, "f64"), c["rho"], c["mat"])
+    lat.step(200)
+    probes = [(16, 16, 16), (16, 16, 9), (16, 16, 8), (16, 16, 7), (2, 3, 4), (31, 0, 16)]
+    got = lat.pressure(probes)
+    lat.close()
+    run = lbm.Run(c["rho"], c["mat"], p).step(200)
+    rho = run.f.sum(axis=1)
+    want = lbm.pressure(rho, p.G)
+    for (x, y, z), g in zip(probes, got):
+        assert _close(g, want[z, y, x]), (x, y, z, g, want[z, y, x])
+    assert got[0] > got[4]  # inside above outside
+    cap = cases.cap_case(shape=(16, 24, 40), footprint=(26.0, 10.0), height=8.0, stripe=(30, 14))
+    lat = Lattice(cases.lattice_params(cap, "f32"), cap["rho"], cap["mat"])
+    pw = lat.pressure([(5, 5, 0), (5, 5, 3)])
+    lat.close()
+    assert np.isnan(pw[0]) and np.isfinite(pw[1])
