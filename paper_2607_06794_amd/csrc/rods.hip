@@ -276,12 +276,13 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
                 for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
                 rho[k] = s;
             }
+            const d3 dx0 = min_image(mk(x, y, z) - X, a);
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 if (!(links & (1u << i))) continue;
                 const double g = a.G * wgt<double>(i) * (rho[0] * a.psi_rod[1] + rho[1] * a.psi_rod[0]);
                 const d3 fr = mk(g * cx(i), g * cy(i), g * cz(i));
-                const d3 arm = min_image(mk(x + cx(i), y + cy(i), z + cz(i)) - X, a);
+                const d3 arm = dx0 + mk(cx(i), cy(i), cz(i));  // the rod node x + c_i
                 const d3 tq = cross(arm, fr);
                 acc[0] += fr.x;
                 acc[1] += fr.y;
@@ -752,6 +753,8 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
     S *f = static_cast<S *>(a.f);
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
+    // the rod's velocity and angular velocity, once per work-group
+    const d3 Vr = ld3(rod + ROD_V), Om = omega_of(rod, a);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // dP[3], dT[3], mass[2]
     int64_t n;
     int x, y, z;
@@ -775,6 +778,7 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
                 for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
                 rho[k] = s;
             }
+            const d3 dx0 = min_image(mk(x, y, z) - X, a);
             // one linked direction at a time (rolled: an unrolled body per
             // direction costs occupancy); f*_opp(i)(x) is read again from
             // cache, which is what the slot stores to other nodes require anyway
@@ -786,9 +790,11 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
                 wrap_coord(zz, a.nz, a.pz);
                 const int64_t s = (int64_t(zz) * a.ny + yy) * a.nx + xx;
                 const d3 ci = mk(cx(i), cy(i), cz(i));
-                const d3 xb = mk(x - 0.5 * cx(i), y - 0.5 * cy(i), z - 0.5 * cz(i));
-                const d3 ub = velocity_at(rod, xb, a);
-                const d3 arm = min_image(xb - X, a);
+                // link midpoint relative to the centre: the node's minimum
+                // image shifted by -c_i / 2 (a surface node is far from the
+                // half-box, so the shift never needs a second wrap)
+                const d3 arm = dx0 - 0.5 * ci;
+                const d3 ub = Vr + cross(Om, arm);
                 const double cu = dot(ci, ub);
                 d3 dp = mk(0, 0, 0);
 #pragma unroll
