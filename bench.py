@@ -247,7 +247,7 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
             if finite[i, s] and finite[i, s + 1] and finite[i, s - 1]]
     net = SU.UNet(D, H, W).init(0)
     t0 = time.perf_counter()
-    hist = SU.fit(net, train, epochs=epochs, batch=4, lr=1e-3, lam=100.0, log=log_fn)
+    hist = SU.fit(net, train, epochs=epochs, batch=4, lr=3e-4, lam=100.0, log=log_fn)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ev = SU.evaluate(net, test, lam=100.0, prev=prev)
