@@ -180,3 +180,45 @@ def test_coupled_rods_deterministic_and_tile_invariant():
     f2, s2, o2, _ = gpu_run("periodic", "f64", 10, tile_y=4, rows_per_thread=1, zchunk=5)
     assert np.array_equal(f1, f2) and np.array_equal(s1, s2)
     assert np.array_equal(o1["solid"], o2["solid"])
+
+
+def _bench_lattice(tile):
+    """The benchmark's workload: 256 x 128 x 64 cap, FP32, 200 stress-placed rods (L = 24)."""
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = cases.cap_case()
+    rods = inputs.place_rods(200, 24.0, 2.0, (256, 128, 64), inside=None, seed=2000, max_trials=20000)
+    lp = cases.lattice_params(c, "f32", **tile)
+    lp.rod_length, lp.rod_radius, lp.rod_rho = 24.0, 2.0, 1.0
+    lp.eps_att, lp.eps_rep, lp.rod_d0, lp.rod_rcut = 1e-4, 0.03, 5.0, 7.5
+    lp.eps_wall, lp.rod_d0_wall, lp.n_sub, lp.wall_z = 0.03, 3.0, 5, 0.5
+    return c, Lattice(lp, c["rho"], c["mat"], rods=rods)
+
+
+def test_full_size_coupled_step_properties():
+    """The benchmark's coupled step at full size (an oracle step with 200 rods
+    on this lattice takes minutes on the host, so the oracle parity of the
+    coupled step is the small cases above): over 20 steps no NaN or
+    non-positive density appears, mass closes with the reservoir and rod ledgers
+    to the FP32 bar, and two runs with different tile shapes give
+    bit-identical populations, rod states and rod ledger (the reservoir ledger,
+    summed per tile, to rounding)."""
+    out = []
+    for tile in (dict(tile_y=8, rows_per_thread=1, zchunk=16), dict(tile_y=4, rows_per_thread=1, zchunk=32)):
+        say(f"[gpu] full-size coupled step, 200 rods, 20 steps, tile {tile}")
+        c, lat = _bench_lattice(tile)
+        o0 = lat.observables()
+        lat.coupled_step(20)
+        o = lat.observables(allow_unstable=True)
+        out.append((lat.export()[1], lat.rods(), o))
+        lat.close()
+        assert (o["status"] & 3) == 0, o["status"]  # no NaN, no rho <= 0
+        say(f"[gpu] status {o['status']}, mass {o['mass']}, ledger {o['ledger']}, solid {o['solid']}")
+        m0 = o0["mass"] + o0["ledger"] + o0["solid"]
+        m = o["mass"] + o["ledger"] + o["solid"]
+        assert np.all(np.abs(m - m0) / m0 < 1e-5), (m, m0)
+    (f1, r1, o1), (f2, r2, o2) = out
+    assert np.array_equal(f1, f2) and np.array_equal(r1, r2)
+    assert np.array_equal(o1["solid"], o2["solid"])
+    # the reservoir ledger is summed per xy tile: another tiling adds in another order
+    assert np.allclose(o1["ledger"], o2["ledger"], rtol=1e-12, atol=0)
