@@ -219,6 +219,31 @@ class Lattice:
                 "labels": labels[: self.n_rods], "edges": g.edges, "largest": g.largest,
                 "spanning": bool(g.spanning)}
 
+    def snapshot(self):
+        """Device copy of the lattice's state for restore(): the current
+        populations and the workspace (material map, rods, ledgers, status)."""
+        import torch
+
+        torch.cuda.synchronize(self.device)
+        cur = self.lib.lb_current_buffer(self._ctx)
+        snap = (self.f[cur].clone(), self.ws.clone())
+        torch.cuda.synchronize(self.device)
+        return snap
+
+    def restore(self, snap):
+        """Return to a snapshot() of this lattice.  Between steps the other
+        population buffer carries no state (a step writes everything the next
+        one reads from it), so the saved populations go to whichever buffer is
+        current now."""
+        import torch
+
+        f, ws = snap
+        torch.cuda.synchronize(self.device)
+        cur = self.lib.lb_current_buffer(self._ctx)
+        self.f[cur].copy_(f)
+        self.ws.copy_(ws)
+        torch.cuda.synchronize(self.device)
+
     def pressure(self, probes) -> np.ndarray:
         """Shan-Chen pressure at probe nodes [(x, y, z), ...] (NaN off the fluid)."""
         xyz = np.ascontiguousarray(np.asarray(probes, np.int32).reshape(-1, 3))

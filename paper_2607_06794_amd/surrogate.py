@@ -334,6 +334,37 @@ def predict(net, x_f32, x_bf16=None, pred_f32=None, pred_bf16=None):
     return pred_f32, pred_bf16
 
 
+def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005):
+    """One interval of a lattice by the surrogate, with the fallback rule.
+
+    The network's prediction is lifted onto the lattice (rods advected and
+    re-placed first); if its rho_A mass differs from M_t - rate * interval
+    (rate: the measured rho_A loss to the reservoir per step) by more than
+    `threshold` of M_t, the lattice returns to its state before the jump and
+    runs the `interval` steps of the method instead; otherwise K coupled
+    re-equilibration steps follow.  A jump books nothing in the reservoir
+    ledger.  Returns {"surrogate": bool, "mass_error": float}.
+    """
+    import torch
+
+    m_t = float(lat.observables(allow_unstable=True)["mass"][0])
+    snap = lat.snapshot()
+    xf, _ = restrict(lat, D, H, W)
+    pf = torch.empty_like(xf)
+    predict(net, xf, pred_f32=pf)
+    if lat.n_rods:
+        jump_rods(lat, xf, pf, D, H, W, interval)
+    lift(lat, pf, D, H, W)
+    m_pred = float(lat.observables(allow_unstable=True)["mass"][0])
+    err = abs(m_pred - (m_t - rate * interval)) / m_t
+    if err > threshold:
+        lat.restore(snap)
+        lat.coupled_step(interval)
+        return {"surrogate": False, "mass_error": err}
+    lat.coupled_step(K)
+    return {"surrogate": True, "mass_error": err}
+
+
 def channel_scales(net, pairs, floor=1e-6):
     """RMS change of each of the six channels over the training pairs (masked),
     from the library's moments kernel."""

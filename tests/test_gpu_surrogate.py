@@ -451,3 +451,51 @@ def test_rod_jump_moves_and_replaces_rods():
     o = lat.observables(allow_unstable=True)
     assert o["status"] == 0
     lat.close()
+
+
+def test_surrogate_advance_and_fallback():
+    """A network that keeps the state (zero output) passes a loose mass check:
+    the surrogate path runs (jump, lift, K steps).  A network whose output adds
+    0.2 to rho_A everywhere fails the 0.5 % check: the lattice goes back to its
+    state before the jump and runs the plain interval, bit-identical to a twin
+    lattice that never tried the jump."""
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Lattice
+
+    spec = inputs.CapSpec(shape=(32, 48, 96), footprint=(70.0, 28.0), height=14.0, stripe=(80, 34), seed=5401)
+    rho, mat = inputs.sessile_cap(spec)
+    rods = inputs.place_rods(4, 12.0, 2.0, (96, 48, 32), inside=inputs.cap_inside(spec), seed=5402, margin=1.0,
+                             max_trials=20000)
+    c = dict(shape=spec.shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+             body_force=(0.0, 0.0, 0.0))
+
+    def make():
+        lp = cases.lattice_params(c, "f32")
+        lp.rod_length, lp.rod_radius, lp.wall_z = 12.0, 2.0, 0.5
+        lat = Lattice(lp, rho, mat, rods=rods)
+        lat.coupled_step(10)
+        return lat
+
+    D, H, W = 16, 24, 48
+    say(f"[gpu] surrogate advance: shape {spec.shape}, {len(rods)} rods")
+    keep = SU.UNet(D, H, W, ch=(8, 16, 16, 16)).init(0)
+    lat = make()
+    r = SU.advance(lat, keep, D, H, W, interval=40, K=10, rate=0.0, threshold=1.0)
+    say(f"[gpu] persistence jump: mass error {r['mass_error']:.3e}")
+    assert r["surrogate"] and r["mass_error"] < 0.05
+    assert lat.observables(allow_unstable=True)["status"] == 0
+    lat.close()
+    bad = SU.UNet(D, H, W, ch=(8, 16, 16, 16)).init(0)
+    bad.set_layer("out", np.zeros((27, 8, 6)), np.array([0.2, 0, 0, 0, 0, 0]))
+    lat, twin = make(), make()
+    r = SU.advance(lat, bad, D, H, W, interval=40, K=10, rate=0.0, threshold=0.005)
+    assert not r["surrogate"] and r["mass_error"] > 0.005
+    twin.coupled_step(40)
+    _, fa = lat.export()
+    _, fb = twin.export()
+    assert np.array_equal(fa, fb) and np.array_equal(lat.rods(), twin.rods())
+    oa, ob = lat.observables(), twin.observables()
+    assert np.array_equal(oa["ledger"], ob["ledger"]) and np.array_equal(oa["solid"], ob["solid"])
+    lat.close()
+    twin.close()
