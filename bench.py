@@ -321,8 +321,9 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         "mass_error_vs_lbm": mass_err, "deposit_error_vs_lbm": dep_err, "g_x_error_vs_lbm": g_err,
         "rod_position_error": rod_err, "rods": int(len(ra)),
         "contacts": {"lbm": [int(da["edges"]), int(da["largest"])], "surrogate": [int(db["edges"]), int(db["largest"])]},
-        "fallback_threshold": 0.005, "jump_mass_error": adv["mass_error"],
-        "would_fall_back": adv["mass_error"] > 0.005, "reservoir_rate_per_step": rate, "status_after_jump": status_b,
+        "fallback_threshold": 0.005, "jump_mass_error": float(adv["mass_error"]),
+        "would_fall_back": bool(adv["mass_error"] > 0.005), "reservoir_rate_per_step": float(rate),
+        "status_after_jump": status_b,
         "rollout_unstable_droplets": n_unstable, "pairs_dropped_unhealthy": int(
             (len(specs) * 7 // 8) * (n_snap - 1) - len(train) + (len(specs) - len(specs) * 7 // 8) * (n_snap - 2) - len(test)),
     }
@@ -331,6 +332,21 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
                f"mass error {mass_err:.2e}, deposit error {dep_err:.3f}, g_x error {g_err:.3f}, rod error {rod_err:.2f}, "
                f"forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s), {n_unstable} unstable rollouts")
     return out
+
+
+def _finite(v):
+    """The record with every non-finite float as null (strict JSON)."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, (float, np.floating)):
+        return float(v) if np.isfinite(v) else None
+    if isinstance(v, np.integer):
+        return int(v)
+    if isinstance(v, np.bool_):
+        return bool(v)
+    return v
 
 
 def unet_form(reps=20):
@@ -573,7 +589,7 @@ def main():
         "cpu_baseline": cpu,
         "status": int(obs["status"]),
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

@@ -295,10 +295,14 @@ int lb_batch_destroy(lb_batch *b);
  *                   canvas) to every fluid node: trilinear from coarse
  *                   coordinate x/2 - 1/4 over the corner cells holding fluid,
  *                   renormalised (else the mean of the fluid-holding cells of
- *                   the 4 x 4 x 4 block around them, else gas at rest); then
+ *                   the 4 x 4 x 4 block around them, else gas at rest),
+ *                   each rho_k clamped at 0 and a speed above 0.15 scaled
+ *                   down to 0.15 (a prediction can leave the states the
+ *                   lattice takes); then
  *                   the collision output of those fields becomes the current
  *                   state: f_k = f^eq(rho_k, u - F/(2 rho) + tau_k F_k / rho_k)
- *                   (Eq. 2) with F the force of the lifted densities; wall and
+ *                   (Eq. 2) with F the force of the lifted densities (no
+ *                   F/(2 rho) shift where rho vanishes); wall and
  *                   rod bounce-back slots are refreshed.
  * Both asynchronous; LB_EINVAL on null pointers or a lattice that does not
  * fit.  Both use the context's other population buffer as scratch (it holds

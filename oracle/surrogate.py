@@ -145,15 +145,33 @@ def prolong(coarse, material):
     return rho, u
 
 
+# largest lifted speed: half the lattice's stability flag |u| > 0.3, the
+# speed above which a canvas is no longer taken as training data
+LIFT_SPEED_MAX = 0.15
+
+
+def admissible(rho, u):
+    """The prolonged fields mapped onto states the lattice can take: each
+    rho_k clamped at 0, and a speed above LIFT_SPEED_MAX scaled down to it
+    (direction kept).  A predicted canvas can leave both sets; the method's
+    own states never do."""
+    rho = np.maximum(rho, 0.0)
+    speed = np.sqrt((u * u).sum(axis=0))
+    scale = np.where(speed > LIFT_SPEED_MAX, LIFT_SPEED_MAX / np.where(speed > 0, speed, 1.0), 1.0)
+    return rho, u * scale
+
+
 def lift(coarse, material, p):
     """Post-collision state f^k = f^eq(rho_k, u_k^eq) (Eq. 2) of the prolonged
-    fields at fluid nodes, 0 elsewhere; u_k^eq = u - F / (2 rho) + tau_k F_k /
-    rho_k with F_k the force (Eq. 5) of the prolonged densities."""
-    rho, u = prolong(coarse, material)
+    fields, made admissible, at fluid nodes, 0 elsewhere; u_k^eq = u - F /
+    (2 rho) + tau_k F_k / rho_k with F_k the force (Eq. 5) of the prolonged
+    densities (no half-force shift where rho vanishes)."""
+    rho, u = admissible(*prolong(coarse, material))
     fluid = material == lbm.FLUID
     F = lbm.sc_force(lbm.pseudopotential(rho, material, p), rho, p)
-    tot = np.where(fluid, rho[0] + rho[1], 1.0)
-    up = u - 0.5 * (F[0] + F[1]) / tot
+    tot = rho[0] + rho[1]
+    has = fluid & (tot > 1e-12)
+    up = u - np.where(has, 0.5 * (F[0] + F[1]) / np.where(has, tot, 1.0), 0.0)
     f = []
     for k in range(2):
         ok = fluid & (rho[k] >= 1e-12)  # the shift is skipped for a vanishing component

@@ -815,6 +815,22 @@ __device__ inline void prolong_at(const float *coarse, int H, int W, int ncz, in
     }
 }
 
+// Largest lifted speed: half the lattice's |u| > 0.3 stability flag.  A
+// predicted canvas can hold negative densities or such speeds, which the
+// method's own states never do; the lift maps each prolonged node back: rho_k
+// clamped at 0, u scaled down to this speed with its direction kept.
+constexpr double kLiftSpeedMax = 0.15;
+
+__device__ inline void make_admissible(double a[5]) {
+    a[0] = fmax(a[0], 0.0);
+    a[1] = fmax(a[1], 0.0);
+    const double sp = sqrt(a[2] * a[2] + a[3] * a[3] + a[4] * a[4]);
+    if (sp > kLiftSpeedMax) {
+        const double sc = kLiftSpeedMax / sp;
+        for (int d = 2; d < 5; ++d) a[d] *= sc;
+    }
+}
+
 // psi_k of the lifted state: prolonged rho_k on fluid nodes, the material's value elsewhere
 __global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L) {
     const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
@@ -825,6 +841,7 @@ __global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L)
             const int x = int(n % L.nx), y = int((n / L.nx) % L.ny), z = int(n / (int64_t(L.nx) * L.ny));
             double a[5];
             prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
+            make_admissible(a);
             v[0] = a[0];
             v[1] = a[1];
         } else {
@@ -844,12 +861,14 @@ __global__ void lift_kernel(const float *coarse, int H, int W, SurLattice L, S *
         const int x = int(n % L.nx), y = int((n / L.nx) % L.ny), z = int(n / (int64_t(L.nx) * L.ny));
         double a[5];
         prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
+        make_admissible(a);
         const double rho[2] = {a[0], a[1]};
         double F[2][3];
         force_at(L, x, y, z, rho, F);
         const double tot = rho[0] + rho[1];
+        const double ih = tot > 1e-12 ? 0.5 / tot : 0.0;  // no shift where the density vanishes
         double up[3];
-        for (int d = 0; d < 3; ++d) up[d] = a[2 + d] - 0.5 * (F[0][d] + F[1][d]) / tot;
+        for (int d = 0; d < 3; ++d) up[d] = a[2 + d] - (F[0][d] + F[1][d]) * ih;
         for (int k = 0; k < 2; ++k) {
             double u[3];
             const bool ok = rho[k] >= 1e-12;  // no shift for a vanishing component

@@ -356,7 +356,7 @@ def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005):
         jump_rods(lat, xf, pf, D, H, W, interval)
     lift(lat, pf, D, H, W)
     m_pred = float(lat.observables(allow_unstable=True)["mass"][0])
-    err = abs(m_pred - (m_t - rate * interval)) / m_t
+    err = float(abs(m_pred - (m_t - float(rate) * interval)) / m_t)
     if err > threshold:
         lat.restore(snap)
         lat.coupled_step(interval)

@@ -234,6 +234,20 @@ def test_restrict_and_lift_match_oracle():
     want = OS.lift(cc.astype(np.float64), c["mat"], p)
     fl = (c["mat"] == lbm.FLUID)[None, None]
     assert np.abs(np.where(fl, f2 - want, 0)).max() <= 1e-12
+    # a canvas outside the admissible states: negative densities of either
+    # component and speeds past the lift's limit in some cells
+    bad = ref.copy()
+    bad[1:3, 2:5, 3:9, 0] = -0.05
+    bad[4:6, 1:3, 10:14, 1] = -0.2
+    bad[2:5, 6:9, 2:12, 2] = 0.4
+    bad[0:3, 0:4, 12:18, 3:5] = -0.12
+    cc = bad.astype(np.float32)
+    L.check(lib.lb_sur_lift(lat._ctx, dev(cc).data_ptr(), D, H, W, _stream()))
+    _, f3 = lat.export()
+    want = OS.lift(cc.astype(np.float64), c["mat"], p)
+    assert np.abs(np.where(fl, f3 - want, 0)).max() <= 1e-12
+    r = np.where(fl[0, 0], f3.sum(axis=1), 1.0)
+    assert np.all(r >= -1e-12) and np.isfinite(f3).all()
     lat.close()
 
 

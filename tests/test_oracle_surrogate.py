@@ -221,6 +221,33 @@ def test_prolong_reproduces_linear_fields_and_lift_moments():
     assert np.allclose(j, rho[0][None] * u, rtol=1e-12, atol=1e-15)
 
 
+def test_lift_maps_a_canvas_onto_admissible_states():
+    # a uniform canvas with a negative rho_A and a speed of sqrt(0.1) on a
+    # periodic fluid box: prolongation keeps it uniform and a uniform psi
+    # exerts no force, so the lifted state is the plain equilibrium of
+    # rho = (0, 1) moving at 0.15 in the canvas's direction (3, 1, 0)
+    shape = (6, 8, 10)
+    coarse = np.zeros((3, 4, 5, 8))
+    coarse[..., 0], coarse[..., 1] = -0.1, 1.0
+    coarse[..., 2], coarse[..., 3] = 0.3, 0.1
+    coarse[..., 6], coarse[..., 7] = 1.0, 1.0
+    mat = np.zeros(shape, np.uint8)
+    f = S.lift(coarse, mat, lbm.Params(shape=shape, G=3.6))
+    assert np.all(f[0] == 0.0)
+    assert np.allclose(f[1].sum(axis=0), 1.0, rtol=0, atol=1e-15)
+    j = np.einsum("izyx,id->dzyx", f[1], lbm.C.astype(float))
+    want = 0.15 * np.array([3.0, 1.0, 0.0]) / np.sqrt(10.0)
+    assert np.allclose(j, want[:, None, None, None], rtol=0, atol=1e-15)
+    pxx = np.einsum("izyx,i->zyx", f[1], lbm.C[:, 0].astype(float) ** 2)
+    assert np.allclose(pxx, 1.0 / 3.0 + want[0] ** 2, rtol=0, atol=1e-15)
+    # below the limits the map leaves a canvas alone
+    coarse[..., 0], coarse[..., 2] = 0.05, 0.1
+    f = S.lift(coarse, mat, lbm.Params(shape=shape, G=3.6))
+    assert np.allclose(f[0].sum(axis=0), 0.05, rtol=1e-14)
+    j = np.einsum("izyx,id->dzyx", f[0] + f[1], lbm.C.astype(float))
+    assert np.allclose(j[0], 1.05 * 0.1, rtol=1e-13) and np.allclose(j[1], 1.05 * 0.1, rtol=1e-13)
+
+
 def _two_phase(shape, seed):
     """A sessile cap of A in B on a patterned wall under a reservoir, with a body force."""
     from tests import cases
