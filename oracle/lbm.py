@@ -78,6 +78,12 @@ class Params:
     psi_solid: np.ndarray = field(default_factory=lambda: np.zeros((9, 2)))
     rho_top: tuple = (0.0, 1.0)
     evaporation: bool = False
+    # the paper's evaporation law (Eq. 8): an interfacial sink with flux
+    # J = J0 / (K + h / h0) per interface node and step
+    sink: bool = False
+    sink_J0: float = 0.0
+    sink_K: float = 0.01
+    sink_h0: float = 1.0
 
 
 def _shift(a, c):
@@ -226,12 +232,56 @@ def collide(f, rho, ueq, p: Params):
     return out
 
 
+# --------------------------------------------------------------------------
+# Evaporation as an interfacial sink (Methods, evaporation paragraph; Eq. 8)
+#
+# Readings where the paper is silent: a node is liquid where rho_A > rho_B and
+# gas where rho_A < rho_B; the interface node of a column is a liquid fluid
+# node whose upper neighbour (z + 1) is a gas fluid node; the local height h
+# of a column (x, y) is its number of liquid fluid nodes in the stored state
+# the step starts from, h0 the initial apex height; the sink moves
+# delta = min(J0 / (K + h / h0), f*_0^A) of the liquid's post-collision rest
+# population into the rest population of the gas (component B), so the total
+# mass is kept and both ledgers book the transfer.
+# --------------------------------------------------------------------------
+def column_heights(rho, material):
+    """h[y, x]: liquid fluid nodes (rho_A > rho_B) in each column."""
+    liquid = (material == FLUID) & (rho[0] > rho[1])
+    return liquid.sum(axis=0)
+
+
+def interface_nodes(rho, material, p: Params):
+    """Liquid fluid nodes whose upper neighbour is a gas fluid node."""
+    fluid = material == FLUID
+    liquid = fluid & (rho[0] > rho[1])
+    gas = fluid & (rho[0] < rho[1])
+    above = np.roll(gas, -1, axis=0)  # gas at z + 1
+    if not p.periodic[2]:
+        above[-1] = False
+    return liquid & above
+
+
+def evaporation_sink(fpost, rho, material, h, p: Params):
+    """Eq. 8 applied to the post-collision state: at each interface node,
+    delta = min(J0 / (K + h / h0), f*_0^A), at least 0, leaves the rest
+    population of A for that of B.  Returns (f*, total delta)."""
+    iface = interface_nodes(rho, material, p)
+    J = p.sink_J0 / (p.sink_K + h / p.sink_h0)
+    delta = np.where(iface, np.maximum(np.minimum(J[None], fpost[0, 0]), 0.0), 0.0)
+    out = fpost.copy()
+    out[0, 0] = fpost[0, 0] - delta
+    out[1, 0] = fpost[1, 0] + delta
+    return out, float(delta.sum())
+
+
 def fluid_step(fpost, material, p: Params, rod_link=None):
     """One full step t -> t+1 on the post-collision state.
 
     Returns (f*(t+1), ledger_delta[2], diagnostics dict).
     """
     fluid = material == FLUID
+    if p.sink:
+        h = column_heights(fields(fpost, material)[0], material)
     f, dledger = pull_stream(fpost, material, p, rod_link)
     rho = np.empty((2,) + material.shape)
     j = np.empty((2, 3) + material.shape)
@@ -245,6 +295,9 @@ def fluid_step(fpost, material, p: Params, rod_link=None):
     up, ueq = eq_velocities(rho, j, F, p)
     out = collide(f, rho, ueq, p)
     out = np.where(fluid, out, 0.0)
+    if p.sink:
+        out, moved = evaporation_sink(out, rho, material, h, p)
+        dledger = dledger + np.array([moved, -moved])
     return out, dledger, {"rho": rho, "j": j, "F": F, "psi": psi}
 
 

@@ -36,12 +36,28 @@ def cap_case(shape=(64, 128, 256), footprint=(150.0, 36.0), height=24.0, stripe=
                 evaporation=True, body_force=(0.0, 0.0, 0.0))
 
 
+def sink_case(shape=(16, 24, 40), footprint=(26.0, 10.0), height=8.0, stripe=(30, 14), seed=2100, J0=2e-4, K=0.01):
+    """The sessile cap under a closed lid (top plane a wall) evaporating by the
+    interfacial sink of Eq. 8 instead of the reservoir plane; h0 = the cap
+    height."""
+    c = cap_case(shape=shape, footprint=footprint, height=height, stripe=stripe, seed=seed)
+    mat = c["mat"].copy()
+    mat[-1] = inputs.SURROUND
+    rho = c["rho"].copy()
+    rho[:, -1] = 0.0
+    c.update(mat=mat, rho=rho, evaporation=False, sink=(J0, K, height))
+    return c
+
+
 def oracle_params(c):
     from oracle import lbm
 
+    sink = c.get("sink")
     return lbm.Params(shape=c["shape"], periodic=c["periodic"], tau=c["tau"], G=c["G"],
                       body_force=c["body_force"], psi_solid=PSI_SOLID.copy(), rho_top=(0.0, 1.0),
-                      evaporation=c["evaporation"])
+                      evaporation=c["evaporation"], sink=sink is not None,
+                      sink_J0=sink[0] if sink else 0.0, sink_K=sink[1] if sink else 0.01,
+                      sink_h0=sink[2] if sink else 1.0)
 
 
 def lattice_params(c, prec, rho_ref=(0.0, 0.0), **tile):
