@@ -75,12 +75,11 @@ __device__ inline double ljf_d(double d, double d0) {
     return (-12.0 * x6 * x6 + 12.0 * x6) / d;
 }
 
-// -dU/dd of the rod-rod potential (excluded volume + shifted cohesion)
+// -dU/dd of the rod-rod potential (excluded volume + shifted cohesion); one
+// potential shape, its strength chosen by the range d falls in
 __device__ inline double pair_force(double d, const RodArgs &a) {
-    double f = 0.0;
-    if (d <= a.d0) f -= a.eps_rep * ljf_d(d, a.d0);
-    if (a.eps_att > 0.0 && d > a.d0 && d < a.r_cut) f -= a.eps_att * ljf_d(d, a.d0);
-    return f;
+    const double eps = d <= a.d0 ? a.eps_rep : ((a.eps_att > 0.0 && d < a.r_cut) ? a.eps_att : 0.0);
+    return eps != 0.0 ? -(eps * ljf_d(d, a.d0)) : 0.0;
 }
 
 // closest points of segments [p1, q1], [p2, q2]: stationary point of the
@@ -88,11 +87,11 @@ __device__ inline double pair_force(double d, const RodArgs &a) {
 __device__ inline double seg_seg(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2) {
     const d3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
     const double aa = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r), c = dot(d1, r), b = dot(d1, d2);
-    double best = 1e300;
+    double best = 1e300;  // squared distance of the best candidate so far
     auto tryst = [&](double s, double t) {
         const d3 x1 = p1 + s * d1, x2 = p2 + t * d2;
         const d3 dd = x1 - x2;
-        const double v = sqrt(dot(dd, dd));
+        const double v = dot(dd, dd);
         if (v < best) {
             best = v;
             c1 = x1;
@@ -114,7 +113,7 @@ __device__ inline double seg_seg(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2) {
         const double s = aa == 0.0 ? 0.0 : fmin(fmax((b * t - c) / aa, 0.0), 1.0);
         tryst(s, t);
     }
-    return best;
+    return sqrt(best);
 }
 
 template <class S>
@@ -369,9 +368,10 @@ __global__ void __launch_bounds__(64) rod_pairs_kernel(RodBatch bt) {
 // ---------------------------------------------------------------------------
 // 2b. rigid-body substeps: one work-group of LB_MAX_RODS threads.  Centres
 //     and axes of all rods live in shared memory for the whole step.  Pair
-//     forces: TPR = 2 (1 above 256 rods) adjacent lanes per rod split its
-//     neighbour list (lane j takes entries j, j + TPR, ...) and add their sums
-//     with a fixed xor butterfly into shared memory.  Rod update: thread r
+//     forces: TPR adjacent lanes per rod (the largest power of two that fits
+//     the work-group: 2 for 200 rods, 16 for 20) split its neighbour list
+//     (lane j takes entries j, j + TPR, ...) and add their sums with a fixed
+//     xor butterfly into shared memory.  Rod update: thread r
 //     keeps rod r's velocity, angular momentum and fluid load in registers
 //     and advances it (threads 0 .. n - 1, so the FP64 update runs on as few
 //     wavefronts as possible).
@@ -382,7 +382,10 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
     extern __shared__ double rs[];  // [n_rods][RS_N]
     const RodArgs a = bt.all[blockIdx.x];  // one work-group per lattice
     const int nr = a.n_rods;
-    const int TPR = nr <= LB_MAX_RODS / 2 ? 2 : 1;
+    // as many lanes per rod as the work-group holds (a power of two, so the
+    // lanes of one rod stay adjacent within a wavefront)
+    int TPR = 1;
+    while (TPR < 64 && 2 * TPR * nr <= LB_MAX_RODS) TPR *= 2;
     // pair role
     const int pr = threadIdx.x / TPR, sub_lane = threadIdx.x % TPR;
     const bool pmine = pr < nr;
@@ -413,7 +416,9 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
             const double *ra = rs + pr * RS_N;
             const d3 Xa = ld3(ra + RS_X), ea = quat_axis(ra + RS_Q);
             const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
-            for (int l = sub_lane; l < nn; l += TPR) {
+            // force and torque on rod pr from one neighbour; exactly zero
+            // for touching axes (d = 0) and beyond the potential's range
+            auto term = [&](int l, d3 &fv, d3 &tv) {
                 const double *rb = rs + a.nbr[pr * ROD_NBR + l] * RS_N;
                 const d3 Xb = ld3(rb + RS_X);
                 const d3 dx = min_image(Xb - Xa, a);
@@ -422,12 +427,27 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
                 const d3 pb = Xb - a.half * eb + shift, qb = Xb + a.half * eb + shift;
                 d3 ca, cb;
                 const double d = seg_seg(pa, qa, pb, qb, ca, cb);
-                if (d <= 0.0) continue;
-                const double fm = pair_force(d, a);
-                if (fm == 0.0) continue;
-                const d3 fv = (fm / d) * (ca - cb);
-                Fp = Fp + fv;
-                Tp = Tp + cross(ca - Xa, fv);
+                const double fmd = d > 0.0 ? pair_force(d, a) / d : 0.0;
+                fv = fmd * (ca - cb);
+                tv = cross(ca - Xa, fv);
+            };
+            // two neighbours per iteration without branches, so that their
+            // dependent FP64 chains interleave; added in list order
+            int l = sub_lane;
+            for (; l + TPR < nn; l += 2 * TPR) {
+                d3 f0, t0, f1, t1;
+                term(l, f0, t0);
+                term(l + TPR, f1, t1);
+                Fp = Fp + f0;
+                Tp = Tp + t0;
+                Fp = Fp + f1;
+                Tp = Tp + t1;
+            }
+            if (l < nn) {
+                d3 f0, t0;
+                term(l, f0, t0);
+                Fp = Fp + f0;
+                Tp = Tp + t0;
             }
         }
         // the rod's lanes are adjacent within one wavefront: fixed butterfly
