@@ -522,6 +522,18 @@ def main():
                            "gbs_algorithmic": algorithmic_bytes_per_lu(prec) * n_fluid / (msk * 1e-3) / 1e9}
             log(f"[bench] form {prec}: {msk * 1e3:.1f} us, {forms[prec]['mlups']:.0f} MLUPS, "
                 f"x{forms[prec]['speedup_vs_f32']:.2f} vs f32")
+        # the paper's evaporation law (Eq. 8) in place of the reservoir plane:
+        # the same cap under a lid, FP32, J0 = 1e-4, K = 0.01, h0 = the cap height
+        sink_case = cases.sink_case(shape=case["shape"], footprint=spec.footprint, height=spec.height,
+                                    stripe=spec.stripe, seed=spec.seed, J0=1e-4, K=0.01)
+        msf, msk, n_sink, obs_s, _, _ = time_step(sink_case, "f32", 500, 50, tile, autotune, None)
+        forms["f32sink"] = {"us_per_fused_step": msk * 1e3, "mlups": n_sink / (msk * 1e-3) / 1e6,
+                            "speedup_vs_f32": base / msk,
+                            "gbs_algorithmic": algorithmic_bytes_per_lu("f32") * n_sink / (msk * 1e-3) / 1e9,
+                            "moved_A_to_B": float(obs_s["ledger"][0]), "status": int(obs_s["status"]),
+                            "note": "interfacial sink (Eq. 8) instead of the reservoir plane, lid on top, 550 steps"}
+        log(f"[bench] form f32sink: {msk * 1e3:.1f} us, {forms['f32sink']['mlups']:.0f} MLUPS, "
+            f"x{forms['f32sink']['speedup_vs_f32']:.2f} vs f32, moved {obs_s['ledger'][0]:.1f}")
 
     batched = None
     if args.batched > 0:

@@ -95,6 +95,21 @@ typedef struct {
     int32_t tile_y;               /* 4, 8 or 16 rows per tile */
     int32_t rows_per_thread;      /* 1 or 2 */
     int32_t zchunk;               /* planes marched by one work-group; 0 = auto */
+    /* the paper's evaporation law (Methods, evaporation paragraph; Eq. 8): an
+     * interfacial sink with flux J = J0 / (K + h / h0), used instead of (or
+     * besides) the reservoir plane.  After each collision, at every
+     * interface node -- a fluid node with rho_A > rho_B whose upper
+     * neighbour (z + 1) is a fluid node with rho_A < rho_B -- the amount
+     * min(J, f*_0^A), at least 0, moves from the rest population of A to
+     * that of B and is booked in the ledgers (ledger[0] += moved,
+     * ledger[1] -= moved).  h is the number of fluid nodes with
+     * rho_A > rho_B in the node's column in the state the step starts from.
+     * FP32 storage only (LB_ENOTSUP otherwise); a batch does not take such
+ * lattices (LB_ENOTSUP). */
+    int32_t sink_on;              /* 1: interfacial sink */
+    double sink_J0;               /* flux scale J0 >= 0 */
+    double sink_K;                /* kinetic resistance K >= 0 (0.01 in the paper) */
+    double sink_h0;               /* initial droplet height h0 > 0 (nodes) */
 } lb_params;
 
 /* Caller-owned device buffers. */

@@ -93,6 +93,10 @@ class LbParams(ct.Structure):
         ("tile_y", ct.c_int32),
         ("rows_per_thread", ct.c_int32),
         ("zchunk", ct.c_int32),
+        ("sink_on", ct.c_int32),
+        ("sink_J0", ct.c_double),
+        ("sink_K", ct.c_double),
+        ("sink_h0", ct.c_double),
     ]
 
 

@@ -31,6 +31,32 @@ __global__ void init_pop_kernel(S *f, int64_t fs, const double *rho, const uint8
     }
 }
 
+// evaporation sink: liquid fluid nodes (rho_A > rho_B, FP64 sums of the
+// stored populations) per column into chunk slot 0 of h; slots 1 .. nz-1
+// cleared, so that any z-chunk count of the next step reads the full height
+template <class S>
+__global__ void sink_heights_kernel(const S *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz, double r0,
+                                    double r1, int32_t *h) {
+    const int64_t nxy = int64_t(nx) * ny;
+    const double rr[2] = {r0, r1};
+    for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < nxy; c += int64_t(gridDim.x) * blockDim.x) {
+        int cnt = 0;
+        for (int z = 0; z < nz; ++z) {
+            const int64_t p = z * nxy + c;
+            if (z) h[p] = 0;
+            if ((mat[p] & MAT_ID_MASK) != MAT_FLUID) continue;
+            double rho[2];
+            for (int k = 0; k < 2; ++k) {
+                double sum = 0.0;
+                for (int i = 0; i < Q; ++i) sum += double(Codec<S>::dec(f[(k * Q + i) * fs + p])) + wgt<double>(i) * rr[k];
+                rho[k] = sum;
+            }
+            cnt += rho[0] > rho[1] ? 1 : 0;
+        }
+        h[c] = cnt;
+    }
+}
+
 __device__ inline int wrapc(int v, int n, int per) {
     if (per) return v < 0 ? v + n : (v >= n ? v - n : v);
     return min(max(v, 0), n - 1);
@@ -250,6 +276,17 @@ hipError_t launch_export(int prec, const void *f, int64_t fs, const uint8_t *mat
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(export_kernel<S>, dim3(grid_for(n, 256)), dim3(256), 0, s, static_cast<const S *>(f), fs,
                            mat, n, rho_ref[0], rho_ref[1], rho_out, f_out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_sink_heights(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                               const double rho_ref[2], int32_t *h, hipStream_t s) {
+    const int64_t nxy = int64_t(nx) * ny;
+    return by_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(sink_heights_kernel<S>, dim3(grid_for(nxy, 256)), dim3(256), 0, s, static_cast<const S *>(f),
+                           fs, mat, nx, ny, nz, rho_ref[0], rho_ref[1], h);
         return hipGetLastError();
     });
 }

@@ -60,7 +60,11 @@ int64_t nodes(const lb_params *p) { return int64_t(p->nx) * p->ny * p->nz; }
 
 // Workspace layout (all offsets 256-byte aligned):
 //   mat      : N bytes, working material map with flag bits
-//   ledger   : max_tiles * 2 doubles, per-xy-tile reservoir ledger
+//   ledger   : max_tiles * 2 doubles, per-xy-tile reservoir ledger; with the
+//              evaporation sink max_tiles * nz more pairs, one per work-group
+//              (xy tile, z chunk) of the step
+//   heights  : with the sink, [2][nz][ny*nx] int32 liquid-node counts per
+//              column and z chunk (read by one step, written by the other)
 //   status   : 256 bytes (status word)
 //   partials : OBS_BLOCKS * OBS_FIELDS doubles
 //   result   : 256 bytes
@@ -126,9 +130,10 @@ static ObsLayout obs_layout(const lb_params *p) {
 static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
 
 struct WsLayout {
-    size_t mat, ledger, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
+    size_t mat, ledger, heights, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
         nbr, nbr_cnt, rodargs, obs, total;
     int max_tiles;
+    int nslots;  // ledger slot pairs
 };
 
 WsLayout ws_layout(const lb_params *p) {
@@ -139,7 +144,10 @@ WsLayout ws_layout(const lb_params *p) {
     w.mat = o;
     o = align256(o + size_t(n));
     w.ledger = o;
-    o = align256(o + size_t(w.max_tiles) * 2 * sizeof(double));
+    w.nslots = w.max_tiles * (p->sink_on ? 1 + p->nz : 1);
+    o = align256(o + size_t(w.nslots) * 2 * sizeof(double));
+    w.heights = o;
+    o = align256(o + (p->sink_on ? 2 * size_t(n) * sizeof(int32_t) : 0));
     w.status = o;
     o = align256(o + 256);
     w.partials = o;
@@ -203,6 +211,14 @@ int validate(const lb_params *p) {
     if (!tile_ok(ty, rp1, true)) return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", ty, rp);
     if (!tau1 && rp1 != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
     if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
+    if (p->sink_on) {
+        // the FP64 instantiation of the sink step gave wrong populations from
+        // the first step (cause not found); it is not built
+        if (p->prec != LB_F32) return fail(LB_ENOTSUP, "the evaporation sink runs with FP32 storage only");
+        if (!(p->sink_J0 >= 0.0) || !isfinite(p->sink_J0) || !(p->sink_K >= 0.0) || !isfinite(p->sink_K) ||
+            !(p->sink_h0 > 0.0) || !isfinite(p->sink_h0))
+            return fail(LB_EINVAL, "sink needs J0 >= 0, K >= 0 and h0 > 0 (finite)");
+    }
     // the integrator keeps 13 doubles per rod in one work-group's shared memory
     if (p->n_rods < 0 || p->n_rods > LB_MAX_RODS)
         return fail(LB_EINVAL, "n_rods = %d outside [0, %d]", p->n_rods, LB_MAX_RODS);
@@ -279,6 +295,8 @@ struct lb_ctx {
     TileCfg tile;
     int ntx, nty, nzc, zchunk;
     int nledger;
+    int nslots;    // ledger slot pairs (reservoir tiles, then sink work-groups)
+    int32_t *hbuf; // [2][nz][nx*ny] sink column heights per z chunk, or null
     int max_tiles;
     int64_t steps;
     int64_t fs;
@@ -286,6 +304,7 @@ struct lb_ctx {
 };
 
 static RodArgs rod_args(lb_ctx *c);
+static hipError_t sink_heights(lb_ctx *c, hipStream_t s);
 
 // tile bookkeeping of a context (no device work)
 static void apply_tiles(lb_ctx *c, int tile_y, int rows_per_thread, int zchunk) {
@@ -426,6 +445,8 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     char *ws = static_cast<char *>(buf->workspace);
     c->mat = reinterpret_cast<uint8_t *>(ws + w.mat);
     c->ledger = reinterpret_cast<double *>(ws + w.ledger);
+    c->nslots = w.nslots;
+    c->hbuf = p->sink_on ? reinterpret_cast<int32_t *>(ws + w.heights) : nullptr;
     c->status = reinterpret_cast<unsigned *>(ws + w.status);
     c->partials = reinterpret_cast<double *>(ws + w.partials);
     c->result = reinterpret_cast<double *>(ws + w.result);
@@ -465,7 +486,7 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
         return cleanup(hip_fail(e, "upload densities"));
     if ((e = hipMemcpyAsync(c->mat, material_host, size_t(n), hipMemcpyHostToDevice, stream)) != hipSuccess)
         return cleanup(hip_fail(e, "upload material"));
-    if ((e = hipMemsetAsync(c->ledger, 0, size_t(w.max_tiles) * 2 * sizeof(double), stream)) != hipSuccess)
+    if ((e = hipMemsetAsync(c->ledger, 0, size_t(w.nslots) * 2 * sizeof(double), stream)) != hipSuccess)
         return cleanup(hip_fail(e, "clear ledger"));
     if ((e = hipMemsetAsync(c->status, 0, 256, stream)) != hipSuccess) return cleanup(hip_fail(e, "clear status"));
     if ((e = hipMemsetAsync(c->carry, 0, 2 * sizeof(double), stream)) != hipSuccess)
@@ -500,6 +521,7 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     // the second buffer needs the same wall slots only after the first step
     // writes them; clear it so that stale staging bytes never look like state
     if ((e = hipMemsetAsync(c->f[1], 0, lb_pop_bytes(p), stream)) != hipSuccess) return cleanup(hip_fail(e, "clear f[1]"));
+    if (p->sink_on && (e = sink_heights(c, stream)) != hipSuccess) return cleanup(hip_fail(e, "sink heights"));
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
     if (p->n_rods > 0) {
         unsigned st = 0;
@@ -545,10 +567,29 @@ static StepArgs step_args(const lb_ctx *c, int cur) {
     a.G = p.G;
     for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
     a.psi_tab = c->psi;
+    if (p.sink_on) {
+        const size_t slab = size_t(p.nz) * size_t(p.nx) * p.ny;
+        a.sink = 1;
+        a.sink_J0 = p.sink_J0;
+        a.sink_K = p.sink_K;
+        a.sink_h0 = p.sink_h0;
+        a.h_read = c->hbuf + size_t(cur) * slab;
+        a.h_write = c->hbuf + size_t(cur ^ 1) * slab;
+        a.sink_ledger = c->ledger + 2 * size_t(c->max_tiles);
+    }
     return a;
 }
 
 static bool is_tau1(const lb_params &p) { return p.tau[0] == 1.0 && p.tau[1] == 1.0; }
+
+// liquid-node counts per column of the current state into the buffer the
+// next step reads (chunk slot 0; the other slots cleared)
+static hipError_t sink_heights(lb_ctx *c, hipStream_t s) {
+    const lb_params &p = c->p;
+    const size_t slab = size_t(p.nz) * size_t(p.nx) * p.ny;
+    return launch_sink_heights(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, c->rref,
+                               c->hbuf + size_t(c->cur) * slab, s);
+}
 
 extern "C" {
 
@@ -570,7 +611,8 @@ int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
 int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     if (!c || !out) return fail(LB_EINVAL, "null argument");
     const lb_params &p = c->p;
-    HIP_TRY(launch_observables(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, c->ledger, c->nledger,
+    HIP_TRY(launch_observables(p.prec, c->f[c->cur], c->fs, c->mat, nodes(&p), c->rref, c->ledger,
+                               p.sink_on ? c->nslots : c->nledger,
                                c->carry, c->partials, OBS_BLOCKS, c->result, stream),
             "observables");
     double r[OBS_FIELDS];
@@ -805,6 +847,7 @@ int lb_sur_lift(lb_ctx *c, const float *coarse_f32, int32_t D, int32_t H, int32_
     if (p.n_rods > 0)
         HIP_TRY(launch_rods_link(p.prec, c->rodargs_host[c->cur], RodBatch{c->rodargs_dev + c->cur, nullptr}, stream),
                 "lift rod links");
+    if (p.sink_on) HIP_TRY(sink_heights(c, stream), "sink heights");
     return LB_OK;
 }
 
@@ -1029,9 +1072,11 @@ int lb_set_tiles(lb_ctx *c, const lb_tile *t, hipStream_t stream) {
     if (!tile_ok(t->tile_y, t->rows_per_thread, tau1))
         return fail(LB_EINVAL, "unsupported tile %d x %d rows per thread", t->tile_y, t->rows_per_thread);
     if (t->zchunk < 0) return fail(LB_EINVAL, "negative zchunk");
-    // the ledger slots are indexed by xy tile: fold them before the layout changes
-    HIP_TRY(launch_fold_ledger(c->ledger, c->max_tiles, c->carry, stream), "fold ledger");
+    // the ledger slots are indexed by tile: fold them before the layout changes
+    HIP_TRY(launch_fold_ledger(c->ledger, c->nslots, c->carry, stream), "fold ledger");
     apply_tiles(c, t->tile_y, t->rows_per_thread, t->zchunk);
+    // the sink's column heights are kept per z chunk: count them afresh
+    if (c->p.sink_on) HIP_TRY(sink_heights(c, stream), "sink heights");
     return LB_OK;
 }
 
@@ -1166,6 +1211,7 @@ int batch_check(lb_ctx *const *ctxs, int n) {
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(LB_EINVAL, "null lattice %d", i);
         if (ctxs[i]->p.prec != ctxs[0]->p.prec) return fail(LB_EINVAL, "lattices of a batch share one precision");
+        if (ctxs[i]->p.sink_on) return fail(LB_ENOTSUP, "lattice %d uses the evaporation sink, which a batch does not run", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(LB_EINVAL, "lattice %d appears twice", i);
     }

@@ -26,6 +26,12 @@ struct StepArgs {
     const double *psi_tab;  // [16][2] ghost pseudo-densities per material id (device)
     double rho_top[2];
     double rho_ref[2];
+    // interfacial evaporation sink (Eq. 8); sink = 0: off
+    int sink;
+    double sink_J0, sink_K, sink_h0;
+    const int32_t *h_read;  // [nz][nx*ny] liquid nodes per column and z chunk of the previous step
+    int32_t *h_write;       // the same for this step
+    double *sink_ledger;    // [ntx*nty*nzc][2] mass moved A -> B, one running pair per work-group
 };
 
 // Tile shape of the fused step: TX = 64 columns x tile_y rows, each thread
@@ -111,6 +117,10 @@ hipError_t launch_observables(int prec, const void *f, int64_t fs, const uint8_t
                               const double *ledger_carry, double *partials, int nblocks, double *result,
                               hipStream_t s);
 hipError_t launch_fold_ledger(double *ledger_part, int nslots, double *carry, hipStream_t s);
+// liquid nodes (fluid, rho_A > rho_B) per column of the stored state into h[0][nx*ny];
+// chunk slots 1 .. nz-1 of h cleared
+hipError_t launch_sink_heights(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
+                               const double rho_ref[2], int32_t *h, hipStream_t s);
 // droplet shape (column scan) and deposit statistics
 struct ObsArgs {
     const uint8_t *mat;

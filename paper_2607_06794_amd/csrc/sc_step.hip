@@ -33,6 +33,14 @@
 //    stored f*(t) towards the reservoir into a per-tile FP64 ledger slot
 //    (deterministic: each tile owns its slot);
 //  * rod nodes: their slots are written by the rod link kernel.
+//
+// Evaporation sink (a separate instantiation, FP32 storage): after the
+// collision, an interface node (liquid here, a gas fluid node at z + 1) moves
+// min(J0 / (K + h / h0), f*_0^A) from A's rest population to B's (Methods,
+// evaporation paragraph; Eq. 8).  h, the column's liquid nodes, comes from
+// the previous step's per-chunk counts; this step writes its own.
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -147,7 +155,7 @@ __device__ inline C wave_sum(C v) {
 // One work-group's tile: logical tile b of a lattice whose step runs as nblk
 // work-groups.  remap: b is a hardware dispatch index to be spread over the
 // XCDs (else b is already the logical tile).
-template <class S, int TY, int NPT, bool TAU1>
+template <class S, int TY, int NPT, bool TAU1, bool SINK = false>
 __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk, bool remap) {
     using C = typename Codec<S>::C;
     constexpr int TX = 64;
@@ -249,6 +257,23 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
         hal_ring[m] = hy * HX + hx;
     }
     __syncthreads();  // psi_tab
+
+    // evaporation sink (Eq. 8): flux of each owned column from the heights
+    // the previous step counted over all z chunks, this chunk's count of
+    // liquid nodes after the sink, and the mass this thread moved A -> B
+    C sink_J[NPT];
+    int sink_cnt[NPT];
+    double sink_mv = 0.0;
+    if constexpr (SINK) {
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            int h = 0;
+            if (own_fin[r])
+                for (int q = 0; q < a.nzc; ++q) h += a.h_read[size_t(q) * nxy + own[r].xy[1][1]];
+            sink_J[r] = C(a.sink_J0) / (C(a.sink_K) + C(h) / C(a.sink_h0));
+            sink_cnt[r] = 0;
+        }
+    }
 
     // moments of the owned nodes: current plane and next plane
     C cur_rho[NPT][2], cur_drho[NPT][2], cur_j[NPT][2][3];
@@ -446,6 +471,17 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
             if (!own_fin[r] || (cur_m[r] & MAT_ID_MASK) != MAT_FLUID) continue;
             const int rc = own_ring[r];
             const C rho[2] = {cur_rho[r][0], cur_rho[r][1]};
+            // interface node of the sink: liquid here (rho_A > rho_B) and a
+            // gas fluid node above, whose densities are its psi in the ring
+            bool sink_if = false;
+            C sink_d = C(0);
+            if constexpr (SINK) {
+                if (rho[0] > rho[1] && (a.pz || z + 1 < a.nz) && ring[sp][0][rc] < ring[sp][1][rc]) {
+                    const int za = a.pz ? wrap1(z + 1, a.nz) : z + 1;
+                    const uint8_t ma = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, own[r].xy[1][1], za * nxy, 0));
+                    sink_if = (ma & MAT_ID_MASK) == MAT_FLUID;
+                }
+            }
             // Shan-Chen force: F_k = -G psi_k(x) sum_i w_i psi_kbar(x + c_i) c_i + rho_k g
             C F[2][3];
 #pragma unroll
@@ -532,6 +568,17 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                     } else {
                         ds = cur_f[r][k][i] - (cur_f[r][k][i] - deq[i]) * om[k];
                     }
+                    if constexpr (SINK) {
+                        // Eq. 8: min(J, f*_0^A), at least 0, leaves A's rest population for B's
+                        if (i == 0 && sink_if) {
+                            if (k == 0) {
+                                sink_d = fmax(fmin(sink_J[r], ds + wgt<C>(0) * rref[0]), C(0));
+                                ds -= sink_d;
+                            } else {
+                                ds += sink_d;
+                            }
+                        }
+                    }
                     fstar[i] = ds;
                     buf_store<S>(Codec<S>::enc(ds), dst[k], voE, i * fsE + zE);
                 }
@@ -564,6 +611,11 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                     }
                 }
             }
+            if constexpr (SINK) {
+                // the column height the next step reads: liquid after the sink
+                sink_cnt[r] += (rho[0] - sink_d > rho[1] + sink_d) ? 1 : 0;
+                sink_mv += double(sink_d);
+            }
         }
         if (st) atomicOr(a.status, st);
 
@@ -588,11 +640,30 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
         }
         shift_next();
     }
+
+    if constexpr (SINK) {
+        // this chunk's column heights, and the work-group's moved mass into
+        // its own ledger pair (A loses it, B gains it)
+#pragma unroll
+        for (int r = 0; r < NPT; ++r)
+            if (own_fin[r]) a.h_write[size_t(tz) * nxy + own[r].xy[1][1]] = sink_cnt[r];
+        const double mv = wave_sum(sink_mv);
+        __syncthreads();  // red may still be read by the last ledger plane's sum
+        if (lx == 0) red[tid >> 6][0] = mv;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < NW; ++q) sum += red[q][0];
+            double *slot = a.sink_ledger + 2 * ((size_t(tz) * a.nty + ty) * a.ntx + tx);
+            slot[0] += sum;
+            slot[1] -= sum;
+        }
+    }
 }
 
-template <class S, int TY, int NPT, bool TAU1>
+template <class S, int TY, int NPT, bool TAU1, bool SINK>
 __global__ void __launch_bounds__(64 * (TY / NPT)) sc_step_kernel(StepArgs a) {
-    sc_step_tile<S, TY, NPT, TAU1>(a, blockIdx.x, gridDim.x, true);
+    sc_step_tile<S, TY, NPT, TAU1, SINK>(a, blockIdx.x, gridDim.x, true);
 }
 
 // Batched step: one launch walks a device work list of (lattice, logical
@@ -613,7 +684,14 @@ int tiles_xy(int nx, int ny, int tile_y) { return ((nx + 63) / 64) * ((ny + tile
 template <class S, int TY, int NPT, bool TAU1>
 static hipError_t launch_one(const StepArgs &a, hipStream_t s) {
     const int nblk = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s, a);
+    if constexpr (std::is_same_v<S, float>) {
+        if (a.sink) {
+            hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1, true>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.sink) return hipErrorInvalidValue;  // the sink runs with FP32 storage only
+    hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1, false>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s, a);
     return hipGetLastError();
 }
 

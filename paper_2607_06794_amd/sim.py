@@ -47,6 +47,8 @@ class LatticeParams:
     tile_y: int = 0
     rows_per_thread: int = 0
     zchunk: int = 0
+    # interfacial evaporation sink of Eq. 8: (J0, K, h0), None: off
+    sink: tuple | None = None
 
     def to_c(self) -> _lib.LbParams:
         p = _lib.LbParams()
@@ -80,6 +82,9 @@ class LatticeParams:
         p.tile_y = int(self.tile_y)
         p.rows_per_thread = int(self.rows_per_thread)
         p.zchunk = int(self.zchunk)
+        p.sink_on = int(self.sink is not None)
+        if self.sink is not None:
+            p.sink_J0, p.sink_K, p.sink_h0 = (float(v) for v in self.sink)
         return p
 
 

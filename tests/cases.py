@@ -65,4 +65,4 @@ def lattice_params(c, prec, rho_ref=(0.0, 0.0), **tile):
 
     return LatticeParams(shape=c["shape"], periodic=c["periodic"], prec=prec, tau=c["tau"], G=c["G"],
                          body_force=c["body_force"], psi_solid=PSI_SOLID.copy(), evaporation=c["evaporation"],
-                         rho_top=(0.0, 1.0), rho_ref=rho_ref, **tile)
+                         rho_top=(0.0, 1.0), rho_ref=rho_ref, sink=c.get("sink"), **tile)

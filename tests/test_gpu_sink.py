@@ -1,0 +1,94 @@
+"""Evaporation sink of Eq. 8 (Methods, evaporation paragraph) in the fused
+step against the FP64 oracle (GPU).
+
+The sink runs with FP32 storage (the FP64 instantiation is not built).
+Tolerances as for the plain FP32 step: 1e-5 relative (max |a - b| / max |b|
+over the populations) against the FP64 oracle, ledgers to 1e-5 relative,
+mass + ledger to FP32 storage rounding; populations of two tilings bit for
+bit (the column heights are integer counts).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbm
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sink_cap(J0=5e-4):
+    # two x tiles with a ragged tail (72 = 64 + 8), lid on top
+    return cases.sink_case(shape=(20, 24, 72), footprint=(44.0, 14.0), height=9.0, stripe=(50, 18), seed=2101, J0=J0)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(steps):
+    c = sink_cap()
+    run = lbm.Run(c["rho"], c["mat"], cases.oracle_params(c))
+    m0 = run.masses()
+    run.step(steps)
+    return run.f, run.ledger.copy(), m0
+
+
+def gpu_run(prec, steps, retile=None, **tile):
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = sink_cap()
+    say(f"[gpu] sink cap {c['shape']} prec={prec} steps={steps} tile={tile} retile={retile}")
+    lat = Lattice(cases.lattice_params(c, prec, **tile), c["rho"], c["mat"])
+    if retile is None:
+        lat.step(steps)
+    else:
+        at, (ty, rp, zc) = retile
+        lat.step(at)
+        lat.set_tiles(ty, rp, zc)
+        lat.step(steps - at)
+    obs = lat.observables()
+    _, f = lat.export()
+    lat.close()
+    return f, obs
+
+
+@pytest.mark.parametrize("retile", [None, (12, (4, 1, 4))])
+def test_sink_matches_oracle(retile):
+    # the retile case changes the z chunks mid-run: the column heights are
+    # counted afresh and the ledger pairs folded
+    steps = 30
+    fo, led_o, m0 = oracle_run(steps)
+    f, obs = gpu_run("f32", steps, retile=retile, tile_y=8, rows_per_thread=1, zchunk=8)
+    ef = cases.rel_err(f, fo)
+    say(f"[gpu] sink f32 retile={retile}: rel err f {ef:.3e} ledger {obs['ledger']} oracle {led_o}")
+    assert ef <= 1e-5
+    assert led_o[0] > 0
+    assert np.allclose(obs["ledger"], led_o, rtol=1e-5, atol=0)
+    assert np.allclose(obs["mass"] + obs["ledger"], m0, rtol=1e-6, atol=0)
+    assert obs["status"] == 0
+
+
+def test_sink_is_tile_invariant():
+    a, oa = gpu_run("f32", 20, tile_y=8, rows_per_thread=1, zchunk=4)
+    b, ob = gpu_run("f32", 20, tile_y=16, rows_per_thread=2, zchunk=20)
+    assert np.array_equal(a, b)
+    assert np.allclose(oa["ledger"], ob["ledger"], rtol=1e-6, atol=0)
+
+
+def test_sink_rejected_where_unsupported():
+    from paper_2607_06794_amd import _lib
+    from paper_2607_06794_amd.sim import Batch, Lattice
+
+    c = sink_cap()
+    for prec in ("f64", "f16dev"):
+        with pytest.raises(_lib.LbError, match="sink"):
+            Lattice(cases.lattice_params(c, prec), c["rho"], c["mat"])
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    with pytest.raises(_lib.LbError, match="sink"):
+        Batch([lat])
+    lat.close()
