@@ -92,3 +92,23 @@ def test_sink_rejected_where_unsupported():
     with pytest.raises(_lib.LbError, match="sink"):
         Batch([lat])
     lat.close()
+
+
+def test_sink_with_unequal_relaxation_times():
+    # tau != 1 keeps the populations in registers and marches without the
+    # software pipeline: the same sink on that path
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = dict(sink_cap(), tau=(1.0, 0.8))
+    run = lbm.Run(c["rho"], c["mat"], cases.oracle_params(c))
+    run.step(12)
+    say(f"[gpu] sink cap tau={c['tau']} f32 12 steps")
+    lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
+    lat.step(12)
+    obs = lat.observables()
+    _, f = lat.export()
+    lat.close()
+    ef = cases.rel_err(f, run.f)
+    say(f"[gpu] sink tau != 1: rel err f {ef:.3e} ledger {obs['ledger']} oracle {run.ledger}")
+    assert ef <= 1e-5
+    assert np.allclose(obs["ledger"], run.ledger, rtol=1e-5, atol=0)
