@@ -254,6 +254,133 @@ __global__ void __launch_bounds__(256) conv_gemm_kernel(ConvArgs a, const uint16
         }
 }
 
+// Forward convolution of a 4 x 8 x 8 brick of positions (M = 256 rows, up to
+// 32 output channels) for volumes made of whole bricks.  Per chunk of 32
+// input channels the brick's 6 x 10 x 10 input halo and the weights of all
+// 27 taps are staged in LDS once; every tap's A operand is then the halo
+// read at the tap's offset, so each input element leaves L2 about 2.3 times
+// instead of 27.  Each wavefront owns 64 rows (two 32-row MFMA blocks)
+// against the one 32-column block.  Summation order: chunk, tap, channel.
+constexpr int BRZ = 4, BRY = 8, BRX = 8;
+constexpr int HLZ = BRZ + 2, HLY = BRY + 2, HLX = BRX + 2, NHALO = HLZ * HLY * HLX;
+
+constexpr int BR_HL = (NHALO * 4 + 255) / 256, BR_WL = (27 * 32 * 4 + 255) / 256;
+
+// loads of one chunk (channels c0 .. c0 + 31) of a brick's halo and weights
+// into registers; an invalid element loads a safe address and becomes zero
+__device__ __forceinline__ void brick_fetch(const ConvArgs &a, int tid, int x0, int y0, int z0, int c0,
+                                            uint4 (&hv)[BR_HL], uint4 (&wr)[BR_WL]) {
+    const int cin = a.c1 + a.c2, Kd = 27 * cin;
+    const int H2 = a.H >> 1, W2 = a.W >> 1;
+    // per-component selects: a select between two uint4 values is turned
+    // into a load through a selected address, with the zero in scratch
+    auto keep = [](bool ok, uint4 v) {
+        return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
+    };
+#pragma unroll
+    for (int j = 0; j < BR_HL; ++j) {
+        const int e = tid + 256 * j;
+        const int hp = e >> 2, gi = e & 3;
+        const int hz = hp / (HLY * HLX), hy = (hp / HLX) % HLY, hx = hp % HLX;
+        const int z = z0 + hz - 1, y = y0 + hy - 1, x = x0 + hx - 1;
+        const int c = c0 + 8 * gi;
+        const bool ok = e < NHALO * 4 && z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W && c < cin;
+        const uint16_t *src = a.x1;
+        if (ok) {
+            if (c < a.c1)
+                src = a.up1 ? a.x1 + (int64_t((z >> 1) * H2 + (y >> 1)) * W2 + (x >> 1)) * a.c1 + c
+                            : a.x1 + (int64_t(z * a.H + y) * a.W + x) * a.c1 + c;
+            else
+                src = a.x2 + (int64_t(z * a.H + y) * a.W + x) * a.c2 + (c - a.c1);
+        }
+        hv[j] = keep(ok, *reinterpret_cast<const uint4 *>(src));
+    }
+#pragma unroll
+    for (int j = 0; j < BR_WL; ++j) {
+        const int e = tid + 256 * j;
+        const int t = e >> 7, n = (e >> 2) & 31, gi = e & 3;
+        const int c = c0 + 8 * gi;
+        const bool ok = e < 27 * 32 * 4 && n < a.cout && c < cin;
+        wr[j] = keep(ok, *reinterpret_cast<const uint4 *>(ok ? a.wt + int64_t(n) * Kd + t * cin + c : a.wt));
+    }
+}
+
+__device__ __forceinline__ void brick_put(int tid, uint16_t *Hs, uint16_t *Ws, const uint4 (&hv)[BR_HL],
+                                          const uint4 (&wr)[BR_WL]) {
+#pragma unroll
+    for (int j = 0; j < BR_HL; ++j) {
+        const int e = tid + 256 * j;
+        if (e < NHALO * 4) *reinterpret_cast<uint4 *>(&Hs[(e >> 2) * LDK + 8 * (e & 3)]) = hv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < BR_WL; ++j) {
+        const int e = tid + 256 * j;
+        if (e < 27 * 32 * 4) *reinterpret_cast<uint4 *>(&Ws[(e >> 2) * LDK + 8 * (e & 3)]) = wr[j];
+    }
+}
+
+__global__ void __launch_bounds__(256) conv_brick_kernel(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[NHALO * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[27 * 32 * LDK];
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int cin = a.c1 + a.c2, Kd = 27 * cin;
+    const int nbx = a.W / BRX, nby = a.H / BRY;
+    const int b = blockIdx.x;
+    const int x0 = (b % nbx) * BRX, y0 = ((b / nbx) % nby) * BRY, z0 = (b / (nbx * nby)) * BRZ;
+    const int H2 = a.H >> 1, W2 = a.W >> 1;
+    const int wm = wv * 64;
+    v16f acc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+    // halo rows read by this lane's two A blocks (tap offset added per tap)
+    int hrow[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int m = wm + 32 * i + (l & 31);
+        hrow[i] = ((m >> 6) * HLY + ((m >> 3) & 7)) * HLX + (m & 7);
+    }
+    // Staging of a chunk: every thread issues all of its loads (halo and
+    // weights) into registers first and stores them to LDS afterwards; the
+    // next chunk's loads are issued before this chunk's MFMAs.
+    uint4 hv[BR_HL], wr[BR_WL];
+    brick_fetch(a, tid, x0, y0, z0, 0, hv, wr);
+    for (int c0 = 0; c0 < cin; c0 += BK) {
+        brick_put(tid, Hs, Ws, hv, wr);
+        __syncthreads();
+        if (c0 + BK < cin) brick_fetch(a, tid, x0, y0, z0, c0 + BK, hv, wr);
+        const int kn = min(BK, cin - c0);
+        for (int t = 0; t < 27; ++t) {
+            const int toff = ((t / 9) * HLY + (t / 3) % 3) * HLX + t % 3;
+            for (int kk = 0; kk < kn; kk += 16) {
+                const int ko = kk + 8 * (l >> 5);
+                const v8bf fb = *reinterpret_cast<const v8bf *>(&Ws[(t * 32 + (l & 31)) * LDK + ko]);
+                const v8bf fa0 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[0] + toff) * LDK + ko]);
+                const v8bf fa1 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[1] + toff) * LDK + ko]);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb, acc[1], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the halo and the weights
+    }
+    // D element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
+    const int col = l & 31;
+    if (col >= a.cout) return;
+    const float bias = a.b ? a.b[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m = wm + 32 * i + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+            const int64_t p = (int64_t(z0 + (m >> 6)) * a.H + (y0 + ((m >> 3) & 7))) * a.W + (x0 + (m & 7));
+            float v = acc[i][e] + bias;
+            if (a.relu) v = fmaxf(v, 0.0f);
+            if (a.y) a.y[p * a.cout + col] = f2bf(v);
+            if (a.yf) a.yf[p * a.cout + col] = v;
+        }
+}
+
 // packed forward weights: wt[o][t][c] = w[t][c][o]
 __global__ void pack_weights_kernel(const uint16_t *w, int cin, int cout, uint16_t *wt) {
     const int n = 27 * cin * cout;
@@ -933,6 +1060,12 @@ static hipError_t launch_gemm(const ConvArgs &a, const uint16_t *g, float *dx, f
 }
 
 hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s) {
+    // up to 32 output channels on a volume of whole bricks: the halo-staged kernel
+    if (a.cout <= 32 && a.D % BRZ == 0 && a.H % BRY == 0 && a.W % BRX == 0) {
+        const int nb = (a.D / BRZ) * (a.H / BRY) * (a.W / BRX);
+        hipLaunchKernelGGL(conv_brick_kernel, dim3(unsigned(nb)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     return launch_gemm<false>(a, nullptr, nullptr, acc, s);
 }
 
