@@ -256,27 +256,29 @@ __global__ void __launch_bounds__(256) conv_gemm_kernel(ConvArgs a, const uint16
 
 // Forward convolution of a 4 x 8 x 8 brick of positions (M = 256 rows, up to
 // 32 output channels) for volumes made of whole bricks.  Per chunk of 32
-// input channels the brick's 6 x 10 x 10 input halo and the weights of all
-// 27 taps are staged in LDS once; every tap's A operand is then the halo
+// input channels the brick's 6 x 10 x 10 input halo is staged in LDS once,
+// the weights nine taps at a time; every tap's A operand is then the halo
 // read at the tap's offset, so each input element leaves L2 about 2.3 times
 // instead of 27.  Each wavefront owns 64 rows (two 32-row MFMA blocks)
 // against the one 32-column block.  Summation order: chunk, tap, channel.
 constexpr int BRZ = 4, BRY = 8, BRX = 8;
 constexpr int HLZ = BRZ + 2, HLY = BRY + 2, HLX = BRX + 2, NHALO = HLZ * HLY * HLX;
 
-constexpr int BR_HL = (NHALO * 4 + 255) / 256, BR_WL = (27 * 32 * 4 + 255) / 256;
+constexpr int BR_TG = 9;  // taps per weight stage (one dz plane of taps)
+constexpr int BR_HL = (NHALO * 4 + 255) / 256, BR_WL = (BR_TG * 32 * 4 + 255) / 256;
 
-// loads of one chunk (channels c0 .. c0 + 31) of a brick's halo and weights
-// into registers; an invalid element loads a safe address and becomes zero
-__device__ __forceinline__ void brick_fetch(const ConvArgs &a, int tid, int x0, int y0, int z0, int c0,
-                                            uint4 (&hv)[BR_HL], uint4 (&wr)[BR_WL]) {
-    const int cin = a.c1 + a.c2, Kd = 27 * cin;
+// per-component select (a select between two uint4 values is lowered to a
+// load through a selected address with the zero kept in scratch)
+__device__ __forceinline__ uint4 keep4(bool ok, uint4 v) {
+    return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
+}
+
+// loads of a brick's input halo for channels c0 .. c0 + 31 into registers;
+// an invalid element loads a safe address and becomes zero
+__device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int x0, int y0, int z0, int c0,
+                                                 uint4 (&hv)[BR_HL]) {
+    const int cin = a.c1 + a.c2;
     const int H2 = a.H >> 1, W2 = a.W >> 1;
-    // per-component selects: a select between two uint4 values is turned
-    // into a load through a selected address, with the zero in scratch
-    auto keep = [](bool ok, uint4 v) {
-        return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
-    };
 #pragma unroll
     for (int j = 0; j < BR_HL; ++j) {
         const int e = tid + 256 * j;
@@ -293,41 +295,49 @@ __device__ __forceinline__ void brick_fetch(const ConvArgs &a, int tid, int x0, 
             else
                 src = a.x2 + (int64_t(z * a.H + y) * a.W + x) * a.c2 + (c - a.c1);
         }
-        hv[j] = keep(ok, *reinterpret_cast<const uint4 *>(src));
-    }
-#pragma unroll
-    for (int j = 0; j < BR_WL; ++j) {
-        const int e = tid + 256 * j;
-        const int t = e >> 7, n = (e >> 2) & 31, gi = e & 3;
-        const int c = c0 + 8 * gi;
-        const bool ok = e < 27 * 32 * 4 && n < a.cout && c < cin;
-        wr[j] = keep(ok, *reinterpret_cast<const uint4 *>(ok ? a.wt + int64_t(n) * Kd + t * cin + c : a.wt));
+        hv[j] = keep4(ok, *reinterpret_cast<const uint4 *>(src));
     }
 }
 
-__device__ __forceinline__ void brick_put(int tid, uint16_t *Hs, uint16_t *Ws, const uint4 (&hv)[BR_HL],
-                                          const uint4 (&wr)[BR_WL]) {
+// loads of the weights of taps t0 .. t0 + 8 for channels c0 .. c0 + 31
+__device__ __forceinline__ void brick_fetch_w(const ConvArgs &a, int tid, int c0, int t0, uint4 (&wr)[BR_WL]) {
+    const int cin = a.c1 + a.c2, Kd = 27 * cin;
+#pragma unroll
+    for (int j = 0; j < BR_WL; ++j) {
+        const int e = tid + 256 * j;
+        const int t = t0 + (e >> 7), n = (e >> 2) & 31, gi = e & 3;
+        const int c = c0 + 8 * gi;
+        const bool ok = e < BR_TG * 32 * 4 && n < a.cout && c < cin;
+        wr[j] = keep4(ok, *reinterpret_cast<const uint4 *>(ok ? a.wt + int64_t(n) * Kd + t * cin + c : a.wt));
+    }
+}
+
+__device__ __forceinline__ void brick_put_halo(int tid, uint16_t *Hs, const uint4 (&hv)[BR_HL]) {
 #pragma unroll
     for (int j = 0; j < BR_HL; ++j) {
         const int e = tid + 256 * j;
         if (e < NHALO * 4) *reinterpret_cast<uint4 *>(&Hs[(e >> 2) * LDK + 8 * (e & 3)]) = hv[j];
     }
+}
+
+__device__ __forceinline__ void brick_put_w(int tid, uint16_t *Ws, const uint4 (&wr)[BR_WL]) {
 #pragma unroll
     for (int j = 0; j < BR_WL; ++j) {
         const int e = tid + 256 * j;
-        if (e < 27 * 32 * 4) *reinterpret_cast<uint4 *>(&Ws[(e >> 2) * LDK + 8 * (e & 3)]) = wr[j];
+        if (e < BR_TG * 32 * 4) *reinterpret_cast<uint4 *>(&Ws[(e >> 2) * LDK + 8 * (e & 3)]) = wr[j];
     }
 }
 
-__global__ void __launch_bounds__(256) conv_brick_kernel(ConvArgs a) {
+// two work-groups per CU (71 KB of LDS each), so one's staging overlaps the
+// other's MFMAs
+__global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t Hs[NHALO * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Ws[27 * 32 * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[BR_TG * 32 * LDK];
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int cin = a.c1 + a.c2, Kd = 27 * cin;
+    const int cin = a.c1 + a.c2;
     const int nbx = a.W / BRX, nby = a.H / BRY;
     const int b = blockIdx.x;
     const int x0 = (b % nbx) * BRX, y0 = ((b / nbx) % nby) * BRY, z0 = (b / (nbx * nby)) * BRZ;
-    const int H2 = a.H >> 1, W2 = a.W >> 1;
     const int wm = wv * 64;
     v16f acc[2];
 #pragma unroll
@@ -341,28 +351,44 @@ __global__ void __launch_bounds__(256) conv_brick_kernel(ConvArgs a) {
         const int m = wm + 32 * i + (l & 31);
         hrow[i] = ((m >> 6) * HLY + ((m >> 3) & 7)) * HLX + (m & 7);
     }
-    // Staging of a chunk: every thread issues all of its loads (halo and
-    // weights) into registers first and stores them to LDS afterwards; the
-    // next chunk's loads are issued before this chunk's MFMAs.
+    // Staging: each thread issues all of a stage's loads into registers and
+    // stores them after the barrier that ends the previous stage; the next
+    // stage's loads are issued before this stage's MFMAs.
     uint4 hv[BR_HL], wr[BR_WL];
-    brick_fetch(a, tid, x0, y0, z0, 0, hv, wr);
+    brick_fetch_halo(a, tid, x0, y0, z0, 0, hv);
+    brick_fetch_w(a, tid, 0, 0, wr);
     for (int c0 = 0; c0 < cin; c0 += BK) {
-        brick_put(tid, Hs, Ws, hv, wr);
-        __syncthreads();
-        if (c0 + BK < cin) brick_fetch(a, tid, x0, y0, z0, c0 + BK, hv, wr);
+        brick_put_halo(tid, Hs, hv);
         const int kn = min(BK, cin - c0);
-        for (int t = 0; t < 27; ++t) {
-            const int toff = ((t / 9) * HLY + (t / 3) % 3) * HLX + t % 3;
-            for (int kk = 0; kk < kn; kk += 16) {
-                const int ko = kk + 8 * (l >> 5);
-                const v8bf fb = *reinterpret_cast<const v8bf *>(&Ws[(t * 32 + (l & 31)) * LDK + ko]);
-                const v8bf fa0 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[0] + toff) * LDK + ko]);
-                const v8bf fa1 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[1] + toff) * LDK + ko]);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb, acc[1], 0, 0, 0);
+        for (int t0 = 0; t0 < 27; t0 += BR_TG) {
+            brick_put_w(tid, Ws, wr);
+            __syncthreads();
+            if (t0 + BR_TG < 27) {
+                brick_fetch_w(a, tid, c0, t0 + BR_TG, wr);
+            } else if (c0 + BK < cin) {
+                brick_fetch_halo(a, tid, x0, y0, z0, c0 + BK, hv);
+                brick_fetch_w(a, tid, c0 + BK, 0, wr);
             }
+            // the stage's nine taps share dz = t0 / 9; unrolled so that the
+            // LDS reads of the next taps go out ahead of the MFMAs
+            const int zoff = (t0 / BR_TG) * HLY * HLX;
+#pragma unroll
+            for (int tt = 0; tt < BR_TG; ++tt) {
+                const int toff = zoff + (tt / 3) * HLX + tt % 3;
+#pragma unroll
+                for (int kq = 0; kq < 2; ++kq) {
+                    if (16 * kq < kn) {  // uniform: the chunk's last channels may end at 8 or 24
+                        const int ko = 16 * kq + 8 * (l >> 5);
+                        const v8bf fb = *reinterpret_cast<const v8bf *>(&Ws[(tt * 32 + (l & 31)) * LDK + ko]);
+                        const v8bf fa0 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[0] + toff) * LDK + ko]);
+                        const v8bf fa1 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[1] + toff) * LDK + ko]);
+                        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb, acc[0], 0, 0, 0);
+                        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb, acc[1], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();  // the next stage overwrites the weights (and the halo)
         }
-        __syncthreads();  // the next chunk overwrites the halo and the weights
     }
     // D element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
     const int col = l & 31;
