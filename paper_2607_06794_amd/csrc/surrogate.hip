@@ -254,18 +254,27 @@ __global__ void __launch_bounds__(256) conv_gemm_kernel(ConvArgs a, const uint16
         }
 }
 
-// Forward convolution of a 4 x 8 x 8 brick of positions (M = 256 rows, up to
-// 32 output channels) for volumes made of whole bricks.  Per chunk of 32
-// input channels the brick's 6 x 10 x 10 input halo is staged in LDS once,
-// the weights nine taps at a time; every tap's A operand is then the halo
-// read at the tap's offset, so each input element leaves L2 about 2.3 times
-// instead of 27.  Each wavefront owns 64 rows (two 32-row MFMA blocks)
-// against the one 32-column block.  Summation order: chunk, tap, channel.
-constexpr int BRZ = 4, BRY = 8, BRX = 8;
-constexpr int HLZ = BRZ + 2, HLY = BRY + 2, HLX = BRX + 2, NHALO = HLZ * HLY * HLX;
-
+// Forward convolution of a brick of ZB x 8 x 8 positions (M = 64 ZB rows)
+// against up to 32 WN output channels, for volumes made of whole bricks:
+// ZB = 4, WN = 1 for layers of up to 32 output channels, ZB = 2, WN = 2 for
+// up to 64.  Per chunk of 32 input channels the brick's (ZB + 2) x 10 x 10
+// input halo is staged in LDS once, the weights nine taps at a time; every
+// tap's A operand is then the halo read at the tap's offset, so each input
+// element leaves L2 a few times instead of 27.  Each wavefront owns 64 rows
+// (two 32-row MFMA blocks) of one 32-column block.  Summation order: chunk,
+// tap, channel.
+constexpr int BRY = 8, BRX = 8, HLY = BRY + 2, HLX = BRX + 2;
 constexpr int BR_TG = 9;  // taps per weight stage (one dz plane of taps)
-constexpr int BR_HL = (NHALO * 4 + 255) / 256, BR_WL = (BR_TG * 32 * 4 + 255) / 256;
+
+template <int ZB, int WN>
+struct Brick {
+    static constexpr int BN = 32 * WN;
+    static constexpr int NHALO = (ZB + 2) * HLY * HLX;
+    static constexpr int HL = (NHALO * 4 + 255) / 256;          // halo loads per thread
+    static constexpr int WE = BR_TG * BN * 4;                   // 16-byte weight elements per stage
+    static constexpr int WL = (WE + 255) / 256;                 // weight loads per thread
+    static_assert(64 * ZB * WN == 256, "four wavefronts of 64 rows x 32 columns");
+};
 
 // per-component select (a select between two uint4 values is lowered to a
 // load through a selected address with the zero kept in scratch)
@@ -275,18 +284,20 @@ __device__ __forceinline__ uint4 keep4(bool ok, uint4 v) {
 
 // loads of a brick's input halo for channels c0 .. c0 + 31 into registers;
 // an invalid element loads a safe address and becomes zero
+template <int ZB, int WN>
 __device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int x0, int y0, int z0, int c0,
-                                                 uint4 (&hv)[BR_HL]) {
+                                                 uint4 (&hv)[Brick<ZB, WN>::HL]) {
+    using B = Brick<ZB, WN>;
     const int cin = a.c1 + a.c2;
     const int H2 = a.H >> 1, W2 = a.W >> 1;
 #pragma unroll
-    for (int j = 0; j < BR_HL; ++j) {
+    for (int j = 0; j < B::HL; ++j) {
         const int e = tid + 256 * j;
         const int hp = e >> 2, gi = e & 3;
         const int hz = hp / (HLY * HLX), hy = (hp / HLX) % HLY, hx = hp % HLX;
         const int z = z0 + hz - 1, y = y0 + hy - 1, x = x0 + hx - 1;
         const int c = c0 + 8 * gi;
-        const bool ok = e < NHALO * 4 && z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W && c < cin;
+        const bool ok = e < B::NHALO * 4 && z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W && c < cin;
         const uint16_t *src = a.x1;
         if (ok) {
             if (c < a.c1)
@@ -300,45 +311,32 @@ __device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int
 }
 
 // loads of the weights of taps t0 .. t0 + 8 for channels c0 .. c0 + 31
-__device__ __forceinline__ void brick_fetch_w(const ConvArgs &a, int tid, int c0, int t0, uint4 (&wr)[BR_WL]) {
+template <int ZB, int WN>
+__device__ __forceinline__ void brick_fetch_w(const ConvArgs &a, int tid, int c0, int t0,
+                                              uint4 (&wr)[Brick<ZB, WN>::WL]) {
+    using B = Brick<ZB, WN>;
     const int cin = a.c1 + a.c2, Kd = 27 * cin;
 #pragma unroll
-    for (int j = 0; j < BR_WL; ++j) {
+    for (int j = 0; j < B::WL; ++j) {
         const int e = tid + 256 * j;
-        const int t = t0 + (e >> 7), n = (e >> 2) & 31, gi = e & 3;
+        const int t = t0 + e / (B::BN * 4), n = (e >> 2) % B::BN, gi = e & 3;
         const int c = c0 + 8 * gi;
-        const bool ok = e < BR_TG * 32 * 4 && n < a.cout && c < cin;
+        const bool ok = e < B::WE && n < a.cout && c < cin;
         wr[j] = keep4(ok, *reinterpret_cast<const uint4 *>(ok ? a.wt + int64_t(n) * Kd + t * cin + c : a.wt));
     }
 }
 
-__device__ __forceinline__ void brick_put_halo(int tid, uint16_t *Hs, const uint4 (&hv)[BR_HL]) {
-#pragma unroll
-    for (int j = 0; j < BR_HL; ++j) {
-        const int e = tid + 256 * j;
-        if (e < NHALO * 4) *reinterpret_cast<uint4 *>(&Hs[(e >> 2) * LDK + 8 * (e & 3)]) = hv[j];
-    }
-}
-
-__device__ __forceinline__ void brick_put_w(int tid, uint16_t *Ws, const uint4 (&wr)[BR_WL]) {
-#pragma unroll
-    for (int j = 0; j < BR_WL; ++j) {
-        const int e = tid + 256 * j;
-        if (e < BR_TG * 32 * 4) *reinterpret_cast<uint4 *>(&Ws[(e >> 2) * LDK + 8 * (e & 3)]) = wr[j];
-    }
-}
-
-// two work-groups per CU (71 KB of LDS each), so one's staging overlaps the
-// other's MFMAs
+template <int ZB, int WN>
 __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t Hs[NHALO * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Ws[BR_TG * 32 * LDK];
+    using B = Brick<ZB, WN>;
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[B::NHALO * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[BR_TG * B::BN * LDK];
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
     const int cin = a.c1 + a.c2;
     const int nbx = a.W / BRX, nby = a.H / BRY;
     const int b = blockIdx.x;
-    const int x0 = (b % nbx) * BRX, y0 = ((b / nbx) % nby) * BRY, z0 = (b / (nbx * nby)) * BRZ;
-    const int wm = wv * 64;
+    const int x0 = (b % nbx) * BRX, y0 = ((b / nbx) % nby) * BRY, z0 = (b / (nbx * nby)) * ZB;
+    const int wm = (wv / WN) * 64, wn = (wv % WN) * 32;
     v16f acc[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -354,20 +352,28 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
     // Staging: each thread issues all of a stage's loads into registers and
     // stores them after the barrier that ends the previous stage; the next
     // stage's loads are issued before this stage's MFMAs.
-    uint4 hv[BR_HL], wr[BR_WL];
-    brick_fetch_halo(a, tid, x0, y0, z0, 0, hv);
-    brick_fetch_w(a, tid, 0, 0, wr);
+    uint4 hv[B::HL], wr[B::WL];
+    brick_fetch_halo<ZB, WN>(a, tid, x0, y0, z0, 0, hv);
+    brick_fetch_w<ZB, WN>(a, tid, 0, 0, wr);
     for (int c0 = 0; c0 < cin; c0 += BK) {
-        brick_put_halo(tid, Hs, hv);
+#pragma unroll
+        for (int j = 0; j < B::HL; ++j) {
+            const int e = tid + 256 * j;
+            if (e < B::NHALO * 4) *reinterpret_cast<uint4 *>(&Hs[(e >> 2) * LDK + 8 * (e & 3)]) = hv[j];
+        }
         const int kn = min(BK, cin - c0);
         for (int t0 = 0; t0 < 27; t0 += BR_TG) {
-            brick_put_w(tid, Ws, wr);
+#pragma unroll
+            for (int j = 0; j < B::WL; ++j) {
+                const int e = tid + 256 * j;
+                if (e < B::WE) *reinterpret_cast<uint4 *>(&Ws[(e >> 2) * LDK + 8 * (e & 3)]) = wr[j];
+            }
             __syncthreads();
             if (t0 + BR_TG < 27) {
-                brick_fetch_w(a, tid, c0, t0 + BR_TG, wr);
+                brick_fetch_w<ZB, WN>(a, tid, c0, t0 + BR_TG, wr);
             } else if (c0 + BK < cin) {
-                brick_fetch_halo(a, tid, x0, y0, z0, c0 + BK, hv);
-                brick_fetch_w(a, tid, c0 + BK, 0, wr);
+                brick_fetch_halo<ZB, WN>(a, tid, x0, y0, z0, c0 + BK, hv);
+                brick_fetch_w<ZB, WN>(a, tid, c0 + BK, 0, wr);
             }
             // the stage's nine taps share dz = t0 / 9; unrolled so that the
             // LDS reads of the next taps go out ahead of the MFMAs
@@ -379,7 +385,8 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
                 for (int kq = 0; kq < 2; ++kq) {
                     if (16 * kq < kn) {  // uniform: the chunk's last channels may end at 8 or 24
                         const int ko = 16 * kq + 8 * (l >> 5);
-                        const v8bf fb = *reinterpret_cast<const v8bf *>(&Ws[(tt * 32 + (l & 31)) * LDK + ko]);
+                        const v8bf fb =
+                            *reinterpret_cast<const v8bf *>(&Ws[(tt * B::BN + wn + (l & 31)) * LDK + ko]);
                         const v8bf fa0 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[0] + toff) * LDK + ko]);
                         const v8bf fa1 = *reinterpret_cast<const v8bf *>(&Hs[(hrow[1] + toff) * LDK + ko]);
                         acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb, acc[0], 0, 0, 0);
@@ -391,7 +398,7 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
         }
     }
     // D element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
-    const int col = l & 31;
+    const int col = wn + (l & 31);
     if (col >= a.cout) return;
     const float bias = a.b ? a.b[col] : 0.0f;
 #pragma unroll
@@ -1086,11 +1093,18 @@ static hipError_t launch_gemm(const ConvArgs &a, const uint16_t *g, float *dx, f
 }
 
 hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s) {
-    // up to 32 output channels on a volume of whole bricks: the halo-staged kernel
-    if (a.cout <= 32 && a.D % BRZ == 0 && a.H % BRY == 0 && a.W % BRX == 0) {
-        const int nb = (a.D / BRZ) * (a.H / BRY) * (a.W / BRX);
-        hipLaunchKernelGGL(conv_brick_kernel, dim3(unsigned(nb)), dim3(256), 0, s, a);
-        return hipGetLastError();
+    // volumes of whole bricks: the halo-staged kernel (4 x 8 x 8 bricks for up
+    // to 32 output channels, 2 x 8 x 8 for up to 64)
+    if (a.H % BRY == 0 && a.W % BRX == 0) {
+        const int nxy = (a.H / BRY) * (a.W / BRX);
+        if (a.cout <= 32 && a.D % 4 == 0) {
+            hipLaunchKernelGGL((conv_brick_kernel<4, 1>), dim3(unsigned(nxy * (a.D / 4))), dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+        if (a.cout <= 64 && a.D % 2 == 0) {
+            hipLaunchKernelGGL((conv_brick_kernel<2, 2>), dim3(unsigned(nxy * (a.D / 2))), dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
     }
     return launch_gemm<false>(a, nullptr, nullptr, acc, s);
 }

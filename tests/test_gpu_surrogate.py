@@ -87,7 +87,8 @@ def _conv(x1, c1, up1, x2, c2, w, b, D, H, W, cout, relu, y=None, yf=None, wt=No
                                                    (8, 16, 40, 32, 0, 32, 0), (6, 12, 34, 128, 64, 64, 1),
                                                    (8, 16, 42, 64, 32, 136, 1), (16, 32, 64, 32, 0, 32, 0),
                                                    (8, 8, 16, 16, 24, 32, 1), (4, 8, 8, 8, 0, 8, 0),
-                                                   (8, 16, 24, 64, 32, 24, 1)])
+                                                   (8, 16, 24, 64, 32, 24, 1), (6, 8, 16, 32, 32, 64, 1),
+                                                   (2, 8, 8, 24, 0, 48, 0)])
 def test_conv_forward_and_gradients(D, H, W, c1, c2, cout, up):
     import torch
 
