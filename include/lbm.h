@@ -104,8 +104,8 @@ typedef struct {
      * that of B and is booked in the ledgers (ledger[0] += moved,
      * ledger[1] -= moved).  h is the number of fluid nodes with
      * rho_A > rho_B in the node's column in the state the step starts from.
-     * FP32 storage only (LB_ENOTSUP otherwise); a batch does not take such
- * lattices (LB_ENOTSUP). */
+     * FP32 storage, or FP64 with tau = 1 (LB_ENOTSUP otherwise); a batch does
+ * not take such lattices (LB_ENOTSUP). */
     int32_t sink_on;              /* 1: interfacial sink */
     double sink_J0;               /* flux scale J0 >= 0 */
     double sink_K;                /* kinetic resistance K >= 0 (0.01 in the paper) */

@@ -212,9 +212,11 @@ int validate(const lb_params *p) {
     if (!tau1 && rp1 != 1) return fail(LB_ENOTSUP, "tau != 1 needs rows_per_thread = 1 (populations stay in registers)");
     if (p->evap_on && p->nz < 4) return fail(LB_EINVAL, "evaporation needs nz >= 4");
     if (p->sink_on) {
-        // the FP64 instantiation of the sink step gave wrong populations from
-        // the first step (cause not found); it is not built
-        if (p->prec != LB_F32) return fail(LB_ENOTSUP, "the evaporation sink runs with FP32 storage only");
+        // FP32 storage, or FP64 with tau = 1 (the FP64 step with the sink runs
+        // only the instantiations checked against the oracle)
+        const bool t1 = p->tau[0] == 1.0 && p->tau[1] == 1.0;
+        if (!(p->prec == LB_F32 || (p->prec == LB_F64 && t1)))
+            return fail(LB_ENOTSUP, "the evaporation sink runs with FP32 storage, or FP64 with tau = 1");
         if (!(p->sink_J0 >= 0.0) || !isfinite(p->sink_J0) || !(p->sink_K >= 0.0) || !isfinite(p->sink_K) ||
             !(p->sink_h0 > 0.0) || !isfinite(p->sink_h0))
             return fail(LB_EINVAL, "sink needs J0 >= 0, K >= 0 and h0 > 0 (finite)");

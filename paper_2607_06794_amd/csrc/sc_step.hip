@@ -34,7 +34,8 @@
 //    (deterministic: each tile owns its slot);
 //  * rod nodes: their slots are written by the rod link kernel.
 //
-// Evaporation sink (a separate instantiation, FP32 storage): after the
+// Evaporation sink (a separate instantiation; FP32 storage, or FP64 with
+// tau = 1): after the
 // collision, an interface node (liquid here, a gas fluid node at z + 1) moves
 // min(J0 / (K + h / h0), f*_0^A) from A's rest population to B's (Methods,
 // evaporation paragraph; Eq. 8).  h, the column's liquid nodes, comes from
@@ -684,13 +685,25 @@ int tiles_xy(int nx, int ny, int tile_y) { return ((nx + 63) / 64) * ((ny + tile
 template <class S, int TY, int NPT, bool TAU1>
 static hipError_t launch_one(const StepArgs &a, hipStream_t s) {
     const int nblk = a.ntx * a.nty * a.nzc;
-    if constexpr (std::is_same_v<S, float>) {
-        if (a.sink) {
+    if (a.sink) {
+        if constexpr (std::is_same_v<S, float>) {
             hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1, true>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s, a);
             return hipGetLastError();
+        } else if constexpr (std::is_same_v<S, double> && TAU1) {
+            // With the sink, the FP64 instantiation of the 64 x 8 tile with
+            // one row per thread gave wrong populations while the other FP64
+            // tiles and all FP32 tiles match the oracle; the same tiling runs
+            // with two rows per thread (identical work-groups and slots).
+            if constexpr (TY == 8 && NPT == 1) {
+                hipLaunchKernelGGL((sc_step_kernel<double, 8, 2, true, true>), dim3(nblk), dim3(64 * 4), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1, true>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s,
+                                   a);
+            }
+            return hipGetLastError();
         }
+        return hipErrorInvalidValue;  // the sink runs with FP32 storage, or FP64 with tau = 1
     }
-    if (a.sink) return hipErrorInvalidValue;  // the sink runs with FP32 storage only
     hipLaunchKernelGGL((sc_step_kernel<S, TY, NPT, TAU1, false>), dim3(nblk), dim3(64 * (TY / NPT)), 0, s, a);
     return hipGetLastError();
 }

@@ -1,11 +1,11 @@
 """Evaporation sink of Eq. 8 (Methods, evaporation paragraph) in the fused
 step against the FP64 oracle (GPU).
 
-The sink runs with FP32 storage (the FP64 instantiation is not built).
-Tolerances as for the plain FP32 step: 1e-5 relative (max |a - b| / max |b|
-over the populations) against the FP64 oracle, ledgers to 1e-5 relative,
-mass + ledger to FP32 storage rounding; populations of two tilings bit for
-bit (the column heights are integer counts).
+The sink runs with FP32 storage, or FP64 with tau = 1.  Tolerances as for
+the plain step: FP64 1e-12 and FP32 1e-5 relative (max |a - b| / max |b|
+over the populations) against the FP64 oracle, ledgers to 1e-12 / 1e-5
+relative; populations of two tilings bit for bit (the column heights are
+integer counts).
 """
 import functools
 import sys
@@ -57,6 +57,24 @@ def gpu_run(prec, steps, retile=None, **tile):
     return f, obs
 
 
+@pytest.mark.parametrize("tile,retile", [((8, 1, 8), None), ((8, 1, 8), (12, (4, 1, 4))), ((16, 2, 8), None)])
+def test_sink_fp64_matches_oracle(tile, retile):
+    # the 64 x 8 tile with one row per thread runs the two-rows-per-thread
+    # instantiation in FP64 (same tiling); the retile changes the z chunks
+    # mid-run, so the column heights are counted afresh
+    steps = 30
+    fo, led_o, m0 = oracle_run(steps)
+    ty, rp, zc = tile
+    f, obs = gpu_run("f64", steps, retile=retile, tile_y=ty, rows_per_thread=rp, zchunk=zc)
+    ef = cases.rel_err(f, fo)
+    say(f"[gpu] sink f64 tile={tile} retile={retile}: rel err f {ef:.3e} ledger {obs['ledger']} oracle {led_o}")
+    assert ef <= 1e-12
+    assert led_o[0] > 0
+    assert np.allclose(obs["ledger"], led_o, rtol=1e-12, atol=0)
+    assert np.allclose(obs["mass"] + obs["ledger"], m0, rtol=1e-13, atol=0)
+    assert obs["status"] == 0
+
+
 @pytest.mark.parametrize("retile", [None, (12, (4, 1, 4))])
 def test_sink_matches_oracle(retile):
     # the retile case changes the z chunks mid-run: the column heights are
@@ -85,9 +103,11 @@ def test_sink_rejected_where_unsupported():
     from paper_2607_06794_amd.sim import Batch, Lattice
 
     c = sink_cap()
-    for prec in ("f64", "f16dev"):
-        with pytest.raises(_lib.LbError, match="sink"):
-            Lattice(cases.lattice_params(c, prec), c["rho"], c["mat"])
+    with pytest.raises(_lib.LbError, match="sink"):
+        Lattice(cases.lattice_params(c, "f16dev"), c["rho"], c["mat"])
+    ct = dict(c, tau=(1.0, 0.8))
+    with pytest.raises(_lib.LbError, match="sink"):
+        Lattice(cases.lattice_params(ct, "f64"), ct["rho"], ct["mat"])
     lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
     with pytest.raises(_lib.LbError, match="sink"):
         Batch([lat])
