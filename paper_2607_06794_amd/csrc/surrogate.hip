@@ -284,11 +284,11 @@ __device__ __forceinline__ uint4 keep4(bool ok, uint4 v) {
 
 // loads of a brick's input halo for channels c0 .. c0 + 31 into registers;
 // an invalid element loads a safe address and becomes zero
-template <int ZB, int WN>
-__device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int x0, int y0, int z0, int c0,
-                                                 uint4 (&hv)[Brick<ZB, WN>::HL]) {
+template <int ZB, int WN, bool DG>
+__device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, const uint16_t *g, int tid, int x0, int y0,
+                                                 int z0, int c0, uint4 (&hv)[Brick<ZB, WN>::HL]) {
     using B = Brick<ZB, WN>;
-    const int cin = a.c1 + a.c2;
+    const int cin = DG ? a.cout : a.c1 + a.c2;  // channels of the staged input
     const int H2 = a.H >> 1, W2 = a.W >> 1;
 #pragma unroll
     for (int j = 0; j < B::HL; ++j) {
@@ -298,8 +298,10 @@ __device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int
         const int z = z0 + hz - 1, y = y0 + hy - 1, x = x0 + hx - 1;
         const int c = c0 + 8 * gi;
         const bool ok = e < B::NHALO * 4 && z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W && c < cin;
-        const uint16_t *src = a.x1;
-        if (ok) {
+        const uint16_t *src = DG ? g : a.x1;
+        if (ok && DG) {
+            src = g + int64_t(z * a.H + y) * a.W * a.cout + int64_t(x) * a.cout + c;
+        } else if (ok) {
             if (c < a.c1)
                 src = a.up1 ? a.x1 + (int64_t((z >> 1) * H2 + (y >> 1)) * W2 + (x >> 1)) * a.c1 + c
                             : a.x1 + (int64_t(z * a.H + y) * a.W + x) * a.c1 + c;
@@ -311,28 +313,35 @@ __device__ __forceinline__ void brick_fetch_halo(const ConvArgs &a, int tid, int
 }
 
 // loads of the weights of taps t0 .. t0 + 8 for channels c0 .. c0 + 31
-template <int ZB, int WN>
+// forward: B[n = output channel][k = input channel] = wt[n][t][c]
+// input gradient: B[n = input channel][k = output channel] = w[t][n][k]
+template <int ZB, int WN, bool DG>
 __device__ __forceinline__ void brick_fetch_w(const ConvArgs &a, int tid, int c0, int t0,
                                               uint4 (&wr)[Brick<ZB, WN>::WL]) {
     using B = Brick<ZB, WN>;
     const int cin = a.c1 + a.c2, Kd = 27 * cin;
+    const int kc = DG ? a.cout : cin, nn = DG ? cin : a.cout;
 #pragma unroll
     for (int j = 0; j < B::WL; ++j) {
         const int e = tid + 256 * j;
         const int t = t0 + e / (B::BN * 4), n = (e >> 2) % B::BN, gi = e & 3;
         const int c = c0 + 8 * gi;
-        const bool ok = e < B::WE && n < a.cout && c < cin;
-        wr[j] = keep4(ok, *reinterpret_cast<const uint4 *>(ok ? a.wt + int64_t(n) * Kd + t * cin + c : a.wt));
+        const bool ok = e < B::WE && n < nn && c < kc;
+        const uint16_t *src = DG ? a.w + (int64_t(t) * cin + n) * a.cout + c : a.wt + int64_t(n) * Kd + t * cin + c;
+        wr[j] = keep4(ok, *reinterpret_cast<const uint4 *>(ok ? src : (DG ? a.w : a.wt)));
     }
 }
 
-template <int ZB, int WN>
-__global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
+// DG: the input gradient dx[q][c] = sum_{t, o} g[q - o_t][o] w[t][c][o], the
+// same computation over g with the taps mirrored, dx stored in FP32
+template <int ZB, int WN, bool DG>
+__global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a, const uint16_t *g, float *dx) {
     using B = Brick<ZB, WN>;
     __shared__ __attribute__((aligned(16))) uint16_t Hs[B::NHALO * LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Ws[BR_TG * B::BN * LDK];
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int cin = a.c1 + a.c2;
+    const int cin = DG ? a.cout : a.c1 + a.c2;  // channels summed over (k)
+    const int ncol = DG ? a.c1 + a.c2 : a.cout;  // columns of the result
     const int nbx = a.W / BRX, nby = a.H / BRY;
     const int b = blockIdx.x;
     const int x0 = (b % nbx) * BRX, y0 = ((b / nbx) % nby) * BRY, z0 = (b / (nbx * nby)) * ZB;
@@ -353,8 +362,8 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
     // stores them after the barrier that ends the previous stage; the next
     // stage's loads are issued before this stage's MFMAs.
     uint4 hv[B::HL], wr[B::WL];
-    brick_fetch_halo<ZB, WN>(a, tid, x0, y0, z0, 0, hv);
-    brick_fetch_w<ZB, WN>(a, tid, 0, 0, wr);
+    brick_fetch_halo<ZB, WN, DG>(a, g, tid, x0, y0, z0, 0, hv);
+    brick_fetch_w<ZB, WN, DG>(a, tid, 0, 0, wr);
     for (int c0 = 0; c0 < cin; c0 += BK) {
 #pragma unroll
         for (int j = 0; j < B::HL; ++j) {
@@ -370,17 +379,18 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
             }
             __syncthreads();
             if (t0 + BR_TG < 27) {
-                brick_fetch_w<ZB, WN>(a, tid, c0, t0 + BR_TG, wr);
+                brick_fetch_w<ZB, WN, DG>(a, tid, c0, t0 + BR_TG, wr);
             } else if (c0 + BK < cin) {
-                brick_fetch_halo<ZB, WN>(a, tid, x0, y0, z0, c0 + BK, hv);
-                brick_fetch_w<ZB, WN>(a, tid, c0 + BK, 0, wr);
+                brick_fetch_halo<ZB, WN, DG>(a, g, tid, x0, y0, z0, c0 + BK, hv);
+                brick_fetch_w<ZB, WN, DG>(a, tid, c0 + BK, 0, wr);
             }
             // the stage's nine taps share dz = t0 / 9; unrolled so that the
-            // LDS reads of the next taps go out ahead of the MFMAs
-            const int zoff = (t0 / BR_TG) * HLY * HLX;
+            // LDS reads of the next taps go out ahead of the MFMAs.  The input
+            // gradient reads the halo at the mirrored offset -o_t.
+            const int zoff = (DG ? 2 - t0 / BR_TG : t0 / BR_TG) * HLY * HLX;
 #pragma unroll
             for (int tt = 0; tt < BR_TG; ++tt) {
-                const int toff = zoff + (tt / 3) * HLX + tt % 3;
+                const int toff = DG ? zoff + (2 - tt / 3) * HLX + (2 - tt % 3) : zoff + (tt / 3) * HLX + tt % 3;
 #pragma unroll
                 for (int kq = 0; kq < 2; ++kq) {
                     if (16 * kq < kn) {  // uniform: the chunk's last channels may end at 8 or 24
@@ -399,14 +409,18 @@ __global__ void __launch_bounds__(256, 2) conv_brick_kernel(ConvArgs a) {
     }
     // D element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
     const int col = wn + (l & 31);
-    if (col >= a.cout) return;
-    const float bias = a.b ? a.b[col] : 0.0f;
+    if (col >= ncol) return;
+    const float bias = (!DG && a.b) ? a.b[col] : 0.0f;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int m = wm + 32 * i + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
             const int64_t p = (int64_t(z0 + (m >> 6)) * a.H + (y0 + ((m >> 3) & 7))) * a.W + (x0 + (m & 7));
+            if (DG) {
+                dx[p * ncol + col] = acc[i][e];
+                continue;
+            }
             float v = acc[i][e] + bias;
             if (a.relu) v = fmaxf(v, 0.0f);
             if (a.y) a.y[p * a.cout + col] = f2bf(v);
@@ -1098,11 +1112,13 @@ hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s) {
     if (a.H % BRY == 0 && a.W % BRX == 0) {
         const int nxy = (a.H / BRY) * (a.W / BRX);
         if (a.cout <= 32 && a.D % 4 == 0) {
-            hipLaunchKernelGGL((conv_brick_kernel<4, 1>), dim3(unsigned(nxy * (a.D / 4))), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((conv_brick_kernel<4, 1, false>), dim3(unsigned(nxy * (a.D / 4))), dim3(256), 0, s, a,
+                               nullptr, nullptr);
             return hipGetLastError();
         }
         if (a.cout <= 64 && a.D % 2 == 0) {
-            hipLaunchKernelGGL((conv_brick_kernel<2, 2>), dim3(unsigned(nxy * (a.D / 2))), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((conv_brick_kernel<2, 2, false>), dim3(unsigned(nxy * (a.D / 2))), dim3(256), 0, s, a,
+                               nullptr, nullptr);
             return hipGetLastError();
         }
     }
@@ -1110,6 +1126,21 @@ hipError_t launch_conv_fwd(const ConvArgs &a, float *acc, hipStream_t s) {
 }
 
 hipError_t launch_conv_dgrad(const ConvArgs &a, const uint16_t *g, float *dx, hipStream_t s) {
+    // volumes of whole bricks: the halo-staged kernel over g with mirrored taps
+    const int cin = a.c1 + a.c2;
+    if (a.H % BRY == 0 && a.W % BRX == 0) {
+        const int nxy = (a.H / BRY) * (a.W / BRX);
+        if (cin <= 32 && a.D % 4 == 0) {
+            hipLaunchKernelGGL((conv_brick_kernel<4, 1, true>), dim3(unsigned(nxy * (a.D / 4))), dim3(256), 0, s, a, g,
+                               dx);
+            return hipGetLastError();
+        }
+        if (cin <= 64 && a.D % 2 == 0) {
+            hipLaunchKernelGGL((conv_brick_kernel<2, 2, true>), dim3(unsigned(nxy * (a.D / 2))), dim3(256), 0, s, a, g,
+                               dx);
+            return hipGetLastError();
+        }
+    }
     return launch_gemm<true>(a, g, dx, nullptr, s);
 }
 
