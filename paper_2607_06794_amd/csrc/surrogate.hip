@@ -601,25 +601,39 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(ConvArgs a, const uint1
         }
 }
 
-// bias gradient: db[o] += sum_p g[p, o] over a chunk of positions; 256 / cout
-// position lanes per channel (each summing about 16 positions), combined in
-// LDS, one atomic per channel and chunk
+// bias gradient: db[o] += sum_p g[p, o] over a chunk of positions.  Each
+// thread reads 8 channels (16 bytes) of one position per iteration, 256 /
+// (channel groups) positions side by side; the sums are combined in LDS and
+// added with one FP32 atomic per channel and chunk (one thread per channel).
 __global__ void conv_bgrad_kernel(int P, int cout, int chunk, const uint16_t *g, float *db) {
-    __shared__ float part[256];
+    __shared__ float part[256][9];
+    const int ng = cout >> 3;  // groups of 8 channels (cout is a multiple of 8)
     const int pbeg = blockIdx.x * chunk, pend = min(P, pbeg + chunk);
-    const int cw = min(cout, 256), G = 256 / cw;
-    const int t = threadIdx.x, oc = t % cw, r = t / cw;
-    for (int o0 = 0; o0 < cout; o0 += cw) {
-        const int o = o0 + oc;
-        float s = 0.0f;
-        if (r < G && o < cout)
-            for (int p = pbeg + r; p < pend; p += G) s += bf2f(g[p * cout + o]);
-        part[t] = s;
+    const int t = threadIdx.x;
+    for (int g0 = 0; g0 < ng; g0 += 256) {
+        const int gw = min(ng - g0, 256), rows = 256 / gw;
+        const int gi = g0 + t % gw, r = t / gw;
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (r < rows)
+#pragma unroll 8
+            for (int p = pbeg + r; p < pend; p += rows) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(g + int64_t(p) * cout + 8 * gi);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc[2 * q] += __uint_as_float(w[q] << 16);
+                    acc[2 * q + 1] += __uint_as_float(w[q] & 0xFFFF0000u);
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) part[t][q] = acc[q];
         __syncthreads();
-        if (t < cw && o0 + t < cout) {
+        // one channel per thread, so one atomic instruction covers the block's channels
+        if (t < 8 * gw) {
+            const int gt = t >> 3, q = t & 7;
             float tot = 0.0f;
-            for (int q = 0; q < G; ++q) tot += part[q * cw + t];
-            atomicAdd(db + o0 + t, tot);
+            for (int rr = 0; rr < rows; ++rr) tot += part[rr * gw + gt][q];
+            atomicAdd(db + 8 * g0 + t, tot);
         }
         __syncthreads();
     }
@@ -1161,7 +1175,8 @@ hipError_t launch_conv_wgrad(const ConvArgs &a, const uint16_t *g, float *dw, fl
     else
         launch(conv_wgrad_kernel<128, 128, 2, 2>, 128, 128);
     if (db) {
-        const int chunk = 16 * (256 / std::min(a.cout, 256));
+        // about 512 chunks (at least 128 positions each)
+        const int chunk = std::max(128, (P + 511) / 512);
         hipLaunchKernelGGL(conv_bgrad_kernel, dim3(unsigned((P + chunk - 1) / chunk)), dim3(256), 0, s, P, a.cout, chunk,
                            g, db);
     }
