@@ -1161,11 +1161,15 @@ hipError_t launch_conv_dgrad(const ConvArgs &a, const uint16_t *g, float *dx, hi
 hipError_t launch_conv_wgrad(const ConvArgs &a, const uint16_t *g, float *dw, float *db, hipStream_t s) {
     const int P = a.D * a.H * a.W;
     const int M = 27 * (a.c1 + a.c2);
-    // position chunks: about 1024 work-groups, 256 to 4096 positions each
+    // position chunks: the longest (256 to 16384 positions) that still give
+    // about 1024 work-groups for the 256-row tiles (the full-resolution
+    // layers need the occupancy) and about 256 for the others (there the
+    // FP32 atomics of each work-group's tile into dw weigh more)
     auto launch = [&](auto kern, int BM, int BN) {
         const unsigned tm = unsigned((M + BM - 1) / BM), tn = unsigned((a.cout + BN - 1) / BN);
-        int chunk = 4096;
-        while (chunk > 256 && int64_t((P + chunk - 1) / chunk) * tm * tn < 1024) chunk /= 2;
+        const int64_t target = BM == 256 ? 1024 : 256;
+        int chunk = 16384;
+        while (chunk > 256 && int64_t((P + chunk - 1) / chunk) * tm * tn < target) chunk /= 2;
         hipLaunchKernelGGL(kern, dim3(unsigned((P + chunk - 1) / chunk), tm, tn), dim3(256), 0, s, a, g, dw, chunk);
     };
     if (a.cout <= 32)
