@@ -230,6 +230,15 @@ __device__ inline RodArgs rod_of(const RodBatch &bt, int g, int &r) {
 
 __device__ inline double shell_r2(const RodArgs &a) { return (a.radius + 1.5) * (a.radius + 1.5); }
 
+// A work-group wholly past the end of rod r's surface list (the list holds
+// far fewer nodes than its capacity) does no work: it writes the n zeros its
+// block sums would have produced into its partial-sum slot (if any) and ends.
+__device__ inline bool idle_block(const RodArgs &a, int r, double *slot, int n) {
+    if (int(blockIdx.x) * RB < a.shell_cnt[r]) return false;
+    if (slot && int(threadIdx.x) < n) slot[threadIdx.x] = 0.0;
+    return true;
+}
+
 // listed node of this thread: false if the entry is past the end of the list
 __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, int &y, int &z) {
     const int idx = blockIdx.x * RB + threadIdx.x;
@@ -252,6 +261,7 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    if (idle_block(a, r, part_slot(a.part_adh, a, r, blockIdx.x), 6)) return;
     const S *f = static_cast<const S *>(a.f);
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
@@ -600,6 +610,7 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    if (idle_block(a, r, part_slot(a.part_upd, a, r, blockIdx.x), 8)) return;
     S *f = static_cast<S *>(a.f);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double *rod = a.rods + r * ROD_STRIDE;
@@ -723,6 +734,7 @@ __global__ void __launch_bounds__(RB) rod_commit_kernel(RodBatch bt) {
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    if (blockIdx.x > 0 && idle_block(a, r, nullptr, 0)) return;  // block 0 also sums the rod's partials
     double *rod = a.rods + r * ROD_STRIDE;
     if (blockIdx.x == 0 && threadIdx.x < 64) {
         double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -770,6 +782,7 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    if (idle_block(a, r, part_slot(a.part_link, a, r, blockIdx.x), 8)) return;
     S *f = static_cast<S *>(a.f);
     const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
