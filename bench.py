@@ -462,7 +462,7 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
-    ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--surrogate-epochs", type=int, default=40)
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
     ap.add_argument("--unet-only", action="store_true", help="time the U-Net alone (one JSON line)")
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB of a plain copy for counter calibration, then exit")
