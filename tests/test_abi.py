@@ -141,3 +141,29 @@ def test_validation_rejects_bad_input_before_any_device_call(lib):
     assert lib.lb_deposit(None, None, None, None, None, None, None, None, None, None, None) == _lib.LB_EINVAL
     assert lib.lb_rod_map(None, None, None) == _lib.LB_EINVAL
     assert lib.lb_destroy(None) == _lib.LB_OK
+
+
+def test_sink_parameters_and_workspace_on_host(lib):
+    # the evaporation sink adds two height buffers [nz][ny][nx] int32 and one
+    # ledger pair per (smallest xy tile, z plane); its parameters are checked
+    # before any device buffer is looked at
+    shape = (16, 24, 40)
+    n = 16 * 24 * 40
+    base = LatticeParams(shape=shape, prec="f32").to_c()
+    p = LatticeParams(shape=shape, prec="f32", sink=(1e-4, 0.01, 8.0)).to_c()
+    pairs = 1 * 6 * 16  # ceil(40 / 64) x ceil(24 / 4) tiles x nz planes
+    extra = lib.lb_workspace_bytes(ct.byref(p)) - lib.lb_workspace_bytes(ct.byref(base))
+    assert 2 * n * 4 + pairs * 16 <= extra < 2 * n * 4 + pairs * 16 + 3 * 256
+    ctx = ct.c_void_p()
+
+    def init_rc(q):
+        return lib.lb_init(ct.byref(q), None, None, None, None, None, ct.byref(ctx))
+
+    assert init_rc(p) == _lib.LB_EINVAL and "buffer" in lib.lb_last_error().decode()
+    assert init_rc(LatticeParams(shape=shape, prec="f64", sink=(1e-4, 0.01, 8.0)).to_c()) == _lib.LB_EINVAL
+    for q in (LatticeParams(shape=shape, prec="f16dev", sink=(1e-4, 0.01, 8.0)),
+              LatticeParams(shape=shape, prec="bf16dev", sink=(1e-4, 0.01, 8.0)),
+              LatticeParams(shape=shape, prec="f64", tau=(1.0, 0.8), sink=(1e-4, 0.01, 8.0))):
+        assert init_rc(q.to_c()) == _lib.LB_ENOTSUP, q
+    for bad in ((-1e-4, 0.01, 8.0), (1e-4, -0.01, 8.0), (1e-4, 0.01, 0.0), (float("nan"), 0.01, 8.0)):
+        assert init_rc(LatticeParams(shape=shape, prec="f32", sink=bad).to_c()) == _lib.LB_EINVAL, bad
