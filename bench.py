@@ -38,9 +38,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_lu(prec):
-    # every population of both components read once and written once
-    return 2 * 19 * 2 * BYTES_PER_ELEM[prec]
+def algorithmic_bytes_per_lu(prec, rods=False):
+    # every population of both components read once and written once; with
+    # rods the step also writes both densities in compute precision (FP64 for
+    # FP64 storage, else FP32) for the rod passes
+    return 2 * 19 * 2 * BYTES_PER_ELEM[prec] + (2 * (8 if prec == "f64" else 4) if rods else 0)
 
 
 def rod_params(lp, length=24.0):
@@ -410,7 +412,7 @@ def copy_probe(mib, reps=5):
     return {"metric": "copy probe", "bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}
 
 
-def traffic_record(prec, tile, n_fluid, ms_fused):
+def traffic_record(prec, tile, n_fluid, ms_fused, rods=False):
     """Measured HBM traffic of the fused step from the committed counter
     record (FETCH_SIZE and WRITE_SIZE per launch, each scaled by what the
     counter reads for a plain copy of known size), or None when the record
@@ -426,12 +428,12 @@ def traffic_record(prec, tile, n_fluid, ms_fused):
     except (OSError, ValueError):
         return None
     if rec.get("sc_step_sha256") != sha or rec.get("prec") != prec or rec.get("tile") != tile \
-            or rec.get("fluid_nodes") != n_fluid:
+            or rec.get("fluid_nodes") != n_fluid or bool(rec.get("rods", False)) != bool(rods):
         return None
     kib = 1024.0
     b = rec["fetch_kib"] * kib * rec["fetch_scale"] + rec["write_kib"] * kib * rec["write_scale"]
     return {"bytes_per_launch": b, "gbs": b / (ms_fused * 1e-3) / 1e9,
-            "vs_algorithmic": b / (algorithmic_bytes_per_lu(prec) * n_fluid)}
+            "vs_algorithmic": b / (algorithmic_bytes_per_lu(prec, rods) * n_fluid)}
 
 
 def cpu_baseline(case, sample_steps):
@@ -504,7 +506,7 @@ def main():
     ms, ms_fused, n_fluid, obs, chosen, nseg = time_step(case, args.prec, args.steps, args.warmup, tile, autotune,
                                                          rods, args.segment)
     mlups = n_fluid / (ms * 1e-3) / 1e6
-    bpl = algorithmic_bytes_per_lu(args.prec)
+    bpl = algorithmic_bytes_per_lu(args.prec, rods=n_rods > 0)
     achieved = bpl * n_fluid / (ms_fused * 1e-3) / 1e9
     log(f"[bench] {ms * 1e3:.1f} us/step ({ms_fused * 1e3:.1f} us fused fluid step), {mlups:.0f} MLUPS, "
         f"{achieved:.0f} GB/s algorithmic in the fused step")
@@ -553,7 +555,7 @@ def main():
                "sample": f"{args.cpu_steps} FP64 NumPy oracle steps of the full 256x128x64 cap from t=0 "
                          f"({dt:.1f} s, 1 of {os.cpu_count()} host cores)"}
 
-    tr = traffic_record(args.prec, chosen, n_fluid, ms_fused)
+    tr = traffic_record(args.prec, chosen, n_fluid, ms_fused, rods=n_rods > 0)
     out = {
         "metric": METRIC,
         "value": mlups,

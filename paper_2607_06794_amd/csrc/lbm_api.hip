@@ -131,7 +131,7 @@ static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
 
 struct WsLayout {
     size_t mat, ledger, heights, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
-        nbr, nbr_cnt, rodargs, obs, total;
+        nbr, nbr_cnt, rodargs, rho, obs, total;
     int max_tiles;
     int nslots;  // ledger slot pairs
 };
@@ -181,6 +181,10 @@ WsLayout ws_layout(const lb_params *p) {
     o = align256(o + nr * sizeof(int));
     w.rodargs = o;
     o = align256(o + (rods ? 2 * sizeof(RodArgs) : 0));
+    // fluid densities of the current state in compute precision, written by
+    // the fluid step for the rod passes
+    w.rho = o;
+    o = align256(o + (rods ? 2 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
     w.obs = o;
     o = align256(o + obs_bytes(p));
     w.total = o;
@@ -292,6 +296,8 @@ struct lb_ctx {
     int16_t *nbr;
     char *obs;
     RodArgs *rodargs_dev;      // rod records with f = f[0] and f = f[1]
+    void *rho;                 // [2][fs] fluid densities for the rod passes (lattices with rods)
+    int rho_fresh;             // rho holds the densities of the current state
     RodArgs rodargs_host[2];
     double psi_host[32];
     TileCfg tile;
@@ -333,6 +339,7 @@ static RodArgs rod_args(lb_ctx *c) {
     const lb_params &p = c->p;
     RodArgs a{};
     a.f = c->f[c->cur];
+    a.rho = c->rho;
     a.rods = c->rods;
     a.shell_cap = p.n_rods > 0 ? rod_shell_cap(p) : 0;
     a.nblk = p.n_rods > 0 ? rod_nblk(p) : 0;
@@ -465,6 +472,8 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->nbr_cnt = reinterpret_cast<int *>(ws + w.nbr_cnt);
     c->obs = ws + w.obs;
     c->rodargs_dev = reinterpret_cast<RodArgs *>(ws + w.rodargs);
+    c->rho = p->n_rods > 0 ? static_cast<void *>(ws + w.rho) : nullptr;
+    c->rho_fresh = 0;
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
             c->psi_host[2 * m + k] = m == MAT_GHOST ? p->rho_top[k] : (m < LB_NMAT ? p->psi_solid[m][k] : 0.0);
@@ -579,6 +588,7 @@ static StepArgs step_args(const lb_ctx *c, int cur) {
         a.h_write = c->hbuf + size_t(cur ^ 1) * slab;
         a.sink_ledger = c->ledger + 2 * size_t(c->max_tiles);
     }
+    a.rho_out = c->rho;
     return a;
 }
 
@@ -606,6 +616,7 @@ int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
         c->cur ^= 1;
         c->steps++;
     }
+    if (nsteps > 0) c->rho_fresh = c->rho != nullptr;
     return LB_OK;
 }
 
@@ -842,6 +853,7 @@ int lb_sur_lift(lb_ctx *c, const float *coarse_f32, int32_t D, int32_t H, int32_
     if (!c || !coarse_f32) return fail(LB_EINVAL, "null argument");
     const lb_params &p = c->p;
     if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
+    c->rho_fresh = 0;
     HIP_TRY(launch_lift(p.prec, coarse_f32, D, H, W, sur_lattice(c), c->f[c->cur], stream), "lift");
     const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
     HIP_TRY(launch_slot_fill(p.prec, c->f[c->cur], c->fs, c->mat, p.nx, p.ny, p.nz, per, stream), "lift slots");
@@ -860,8 +872,9 @@ int lb_sur_jump_rods(lb_ctx *c, const float *coarse_now, const float *coarse_nex
     if (!canvas_fits(p, D, H, W)) return fail(LB_EINVAL, "lattice %dx%dx%d does not fit the canvas", p.nx, p.ny, p.nz);
     if (!(steps >= 0)) return fail(LB_EINVAL, "negative jump length");
     if (p.n_rods == 0) return LB_OK;
+    c->rho_fresh = 0;
     const RodArgs &a = c->rodargs_host[c->cur];
-    const RodBatch bt{c->rodargs_dev + c->cur, nullptr};
+    const RodBatch bt{c->rodargs_dev + c->cur, nullptr, 0};
     HIP_TRY(launch_rods_jump(a, bt, coarse_now, coarse_next, D, H, W, steps, stream), "rod jump");
     HIP_TRY(launch_rods_place(p.prec, a, bt, stream), "re-place rods");
     const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
@@ -1051,8 +1064,11 @@ int lb_adam(float *p, const float *g, float *m, float *v, void *p_bf16, int64_t 
 int lb_rods_step(lb_ctx *c, hipStream_t stream) {
     if (!c) return fail(LB_EINVAL, "null ctx");
     if (c->p.n_rods == 0) return LB_OK;
-    HIP_TRY(launch_rods_step(c->p.prec, RodBatch{c->rodargs_dev + c->cur, nullptr}, 1, c->p.n_rods, rod_nblk(c->p),
-                             c->p.n_rods, stream),
+    // the rod passes read the fluid step's densities while they describe the
+    // current state (the update keeps them so for the nodes it refills), else
+    // they sum the populations themselves
+    HIP_TRY(launch_rods_step(c->p.prec, RodBatch{c->rodargs_dev + c->cur, nullptr, c->rho_fresh}, 1, c->p.n_rods,
+                             rod_nblk(c->p), c->p.n_rods, stream),
             "rods step");
     return LB_OK;
 }
@@ -1229,7 +1245,7 @@ hipError_t batch_enqueue(lb_batch *b, int par, bool rods, hipStream_t s) {
     // the rod update acts on the state the fluid step just wrote: the records
     // of the next parity
     if (rods && b->total_rods > 0)
-        return launch_rods_step(b->prec, RodBatch{b->rods + size_t(par ^ 1) * n, b->rodmap}, n, b->total_rods,
+        return launch_rods_step(b->prec, RodBatch{b->rods + size_t(par ^ 1) * n, b->rodmap, 1}, n, b->total_rods,
                                 b->nblk_max, b->max_rods, s);
     return hipSuccess;
 }
@@ -1352,6 +1368,8 @@ int lb_batch_step(lb_batch *b, int32_t nsteps, int32_t with_rods, int32_t use_gr
     for (int i = 0; i < n; ++i) {
         b->ctx[i]->cur ^= (nsteps & 1);
         b->ctx[i]->steps += nsteps;
+        // every batch step runs the fluid step, which writes the densities
+        if (nsteps > 0) b->ctx[i]->rho_fresh = b->ctx[i]->rho != nullptr;
     }
     return LB_OK;
 }

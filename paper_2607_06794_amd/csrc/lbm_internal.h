@@ -32,6 +32,7 @@ struct StepArgs {
     const int32_t *h_read;  // [nz][nx*ny] liquid nodes per column and z chunk of the previous step
     int32_t *h_write;       // the same for this step
     double *sink_ledger;    // [ntx*nty*nzc][2] mass moved A -> B, one running pair per work-group
+    void *rho_out;          // [2][fs] fluid densities in compute precision for the rod passes, or null
 };
 
 // Tile shape of the fused step: TX = 64 columns x tile_y rows, each thread
@@ -54,7 +55,8 @@ constexpr int ROD_PART = 8;                                  // doubles per (rod
 constexpr int ROD_NBR = 64;                                  // neighbour-list entries per rod
 
 struct RodArgs {
-    void *f;  // current populations (post-collision state)
+    void *f;    // current populations (post-collision state)
+    void *rho;  // [2][fs] fluid densities of the current state (compute precision)
     double *rods;
     double *part_adh, *part_upd, *part_link;  // [n_rods][nblk][ROD_PART] partial sums
     int *shell;                               // [n_rods][shell_cap] surface-list node indices
@@ -80,6 +82,7 @@ struct RodArgs {
 struct RodBatch {
     const RodArgs *all;
     const int2 *map;
+    int rho_fresh;  // 1: each record's rho holds the densities of its current state
 };
 // a: host copy of the single lattice's record (sizes, newid), bt its device copy
 hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s);

@@ -239,6 +239,25 @@ __device__ inline bool idle_block(const RodArgs &a, int r, double *slot, int n) 
     return true;
 }
 
+// densities rho_k of fluid node n: from the density array while it holds the
+// current state, else the FP64 sum of the node's populations
+template <class S>
+__device__ inline void node_densities(const RodArgs &a, int fresh, const S *f, int64_t n, double rho[2]) {
+    if (fresh) {
+        const typename Codec<S>::C *ro = static_cast<const typename Codec<S>::C *>(a.rho);
+        rho[0] = double(ro[n]);
+        rho[1] = double(ro[a.fs + n]);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
+        rho[k] = s;
+    }
+}
+
 // listed node of this thread: false if the entry is past the end of the list
 __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, int &y, int &z) {
     const int idx = blockIdx.x * RB + threadIdx.x;
@@ -278,13 +297,7 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
         }
         if (links) {
             double rho[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
-                rho[k] = s;
-            }
+            node_densities<S>(a, bt.rho_fresh, f, n, rho);
             const d3 dx0 = min_image(mk(x, y, z) - X, a);
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
@@ -681,7 +694,9 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
                 const uint8_t mq = a.mat[q] & MAT_ID_MASK;
                 wall = is_static_wall(mq);
                 ok = mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0;
-                if (ok) {
+                if (ok && bt.rho_fresh) {
+                    val = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
+                } else if (ok) {
                     double s = 0.0;
 #pragma unroll
                     for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
@@ -706,6 +721,10 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
             f[(kk * Q + ii) * a.fs + un] =
                 Codec<S>::enc(typename Codec<S>::C(feq - wgt<double>(ii) * (kk ? a.rho_ref[1] : a.rho_ref[0])));
         }
+        // the refilled node's densities (those of f^eq) keep the density
+        // array valid for the passes after this one
+        if (bt.rho_fresh && lane < 2)
+            static_cast<typename Codec<S>::C *>(a.rho)[lane * a.fs + un] = typename Codec<S>::C(rb[lane]);
         if (lane == 0) {
             const d3 mom = (rb[0] + rb[1]) * ub;
             const d3 tq = cross(min_image(pu - X, a), mom);
@@ -804,13 +823,7 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
         }
         if (links) {
             double rho[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + n) + wgt<double>(j) * a.rho_ref[k];
-                rho[k] = s;
-            }
+            node_densities<S>(a, bt.rho_fresh, f, n, rho);
             const d3 dx0 = min_image(mk(x, y, z) - X, a);
             // one linked direction at a time (rolled: an unrolled body per
             // direction costs occupancy); f*_opp(i)(x) is read again from

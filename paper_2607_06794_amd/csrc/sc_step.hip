@@ -32,7 +32,10 @@
 //    the directions pulled from the reservoir and books the outflow of its
 //    stored f*(t) towards the reservoir into a per-tile FP64 ledger slot
 //    (deterministic: each tile owns its slot);
-//  * rod nodes: their slots are written by the rod link kernel.
+//  * rod nodes: their slots are written by the rod link kernel; on lattices
+//    with rods the step also stores every fluid node's densities (compute
+//    precision), which the rod passes read instead of summing 19 populations
+//    per surface node in the order of their lists.
 //
 // Evaporation sink (a separate instantiation; FP32 storage, or FP64 with
 // tau = 1): after the
@@ -478,6 +481,12 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
             if (!own_fin[r] || (cur_m[r] & MAT_ID_MASK) != MAT_FLUID) continue;
             const int rc = own_ring[r];
             const C rho[2] = {cur_rho[r][0], cur_rho[r][1]};
+            if (a.rho_out) {  // lattices with rods: the densities for the rod passes
+                C *ro = static_cast<C *>(a.rho_out);
+                const int64_t nn = int64_t(z) * nxy + own[r].xy[1][1];
+                ro[nn] = rho[0];
+                ro[a.fs + nn] = rho[1];
+            }
             // interface node of the sink: liquid here (rho_A > rho_B) and a
             // gas fluid node above, whose densities are its psi in the ring
             bool sink_if = false;
