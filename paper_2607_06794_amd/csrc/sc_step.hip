@@ -15,8 +15,8 @@
 // it pulls f_i(x) = f*_i(x - c_i) for its TY rows plus a one-node ring around
 // them, sums the densities of all (TY+2) x 66 positions into a 4-plane LDS
 // ring of pseudo-potentials, and finishes the plane below once the plane above
-// is in LDS.  Densities never travel through HBM: every population is read
-// once and written once; the ring re-reads mostly hit L2.
+// is in LDS.  The force needs no density array in HBM: every population is
+// read once and written once; the ring re-reads mostly hit L2.
 //
 // Addressing: all HBM traffic goes through buffer resources (one per
 // component).  The plane being marched is the same for the whole work-group,
