@@ -239,3 +239,59 @@ def test_tile_switching_mid_run_and_autotune(tmp_path):
     _, fg = lat.export()
     lat.close()
     assert cases.rel_err(fg, fo) <= 1e-5
+
+
+def test_largest_lattice_sampled_nodes_f32():
+    # A periodic lattice at the library's size limit: one component's 19
+    # arrays span just under 4 GiB, the reach of the 32-bit byte offsets of
+    # the step's buffer accesses.  Two FP32 steps; populations at sampled
+    # nodes (the first and last node among them) against the oracle run on
+    # a 13^3 periodic sub-box of the initial state around each node (after
+    # two steps the sub-box's wrap error has moved 4 nodes in from its faces,
+    # so the centre is exact).
+    import ctypes as ct
+
+    import torch
+
+    from paper_2607_06794_amd import _lib
+    from paper_2607_06794_amd.sim import Lattice, LatticeParams, _stream_ptr
+
+    nz, ny, nx = 215, 512, 512
+    n = nz * ny * nx
+    say(f"[gpu] largest lattice {nx}x{ny}x{nz} ({n} nodes) f32, 2 steps")
+    z = np.arange(nz)[:, None, None]
+    y = np.arange(ny)[None, :, None]
+    x = np.arange(nx)[None, None, :]
+    rho = np.empty((2, nz, ny, nx))
+    rho[0] = 0.515 + 0.485 * np.tanh(3.0 * (np.sin(2 * np.pi * x / 37) + np.sin(2 * np.pi * y / 29)
+                                             + np.sin(2 * np.pi * z / 23)))
+    rho[0] += np.random.default_rng(4242).uniform(-1e-4, 1e-4, size=(nz, ny, nx))
+    rho[1] = 1.03 - rho[0]
+    mat = np.zeros((nz, ny, nx), np.uint8)
+    lp = LatticeParams(shape=(nz, ny, nx), periodic=(True, True, True), prec="f32", G=3.6, psi_solid=cases.PSI_SOLID,
+                       tile_y=8, rows_per_thread=1)
+    c = lp.to_c()
+    assert 19 * _lib.load().lb_pop_stride(ct.byref(c)) * 4 > 0xFFFFFFFF - 16 * 2 ** 20  # within 16 MiB of the limit
+    lat = Lattice(lp, rho, mat)
+    lat.step(2)
+    obs = lat.observables()
+    f = torch.empty((2, 19, n), dtype=torch.float64, device=lat.device)
+    _lib.check(lat.lib.lb_export(lat._ctx, None, ct.c_void_p(f.data_ptr()), _stream_ptr(lat.stream)))
+    rng = np.random.default_rng(77)
+    pts = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz - 1, 0, nx - 1)]
+    pts += [tuple(int(v) for v in (rng.integers(nz), rng.integers(ny), rng.integers(nx))) for _ in range(5)]
+    idx = torch.tensor([(pz * ny + py) * nx + px for pz, py, px in pts], device=lat.device)
+    got = f[:, :, idx].cpu().numpy()
+    lat.close()
+    del f
+    assert obs["status"] == 0
+    p = lbm.Params(shape=(13, 13, 13), periodic=(True, True, True), G=3.6, psi_solid=cases.PSI_SOLID)
+    worst = 0.0
+    for s, (pz, py, px) in enumerate(pts):
+        sub = rho[:, np.arange(pz - 6, pz + 7) % nz][:, :, np.arange(py - 6, py + 7) % ny][:, :, :, np.arange(px - 6, px + 7) % nx]
+        run = lbm.Run(sub, np.zeros((13, 13, 13), np.uint8), p).step(2)
+        want = run.f[:, :, 6, 6, 6]
+        err = float(np.abs(got[:, :, s] - want).max() / np.abs(want).max())
+        worst = max(worst, err)
+    say(f"[gpu] largest lattice: worst sampled rel err {worst:.3e} over {len(pts)} nodes")
+    assert worst <= 1e-5
