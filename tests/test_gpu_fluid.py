@@ -295,3 +295,38 @@ def test_largest_lattice_sampled_nodes_f32():
         worst = max(worst, err)
     say(f"[gpu] largest lattice: worst sampled rel err {worst:.3e} over {len(pts)} nodes")
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["no_fluid", "one_fluid_node", "smallest_periodic"])
+def test_degenerate_lattices(kind):
+    # a lattice without fluid, a single fluid node boxed in by walls, and the
+    # smallest lattice the library takes (3 x 3 x 3, periodic): 4 FP64 steps
+    # against the oracle, mass kept, status clear
+    from paper_2607_06794_amd.sim import Lattice, LatticeParams
+
+    say(f"[gpu] degenerate lattice {kind}")
+    if kind == "smallest_periodic":
+        shape, per = (3, 3, 3), (True, True, True)
+        mat = np.zeros(shape, np.uint8)
+        rho = np.empty((2,) + shape)
+        rho[0] = 0.5 + 0.1 * np.random.default_rng(3).uniform(-1, 1, size=shape)
+        rho[1] = 0.5 + 0.1 * np.random.default_rng(4).uniform(-1, 1, size=shape)
+    else:
+        shape, per = (5, 6, 7), (False, False, False)
+        mat = np.full(shape, 2, np.uint8)
+        rho = np.zeros((2,) + shape)
+        if kind == "one_fluid_node":
+            mat[2, 3, 3] = 0
+            rho[:, 2, 3, 3] = (0.8, 0.2)
+    lp = LatticeParams(shape=shape, periodic=per, prec="f64", G=3.6, psi_solid=cases.PSI_SOLID)
+    lat = Lattice(lp, rho, mat)
+    m0 = lat.observables()["mass"].copy()
+    lat.step(4)
+    obs = lat.observables()
+    _, f = lat.export()
+    lat.close()
+    run = lbm.Run(rho, mat, lbm.Params(shape=shape, periodic=per, G=3.6, psi_solid=cases.PSI_SOLID)).step(4)
+    fl = (mat == 0)[None, None]
+    assert np.abs(np.where(fl, f - run.f, 0)).max() <= 1e-13 * max(1.0, np.abs(run.f).max())
+    assert np.allclose(obs["mass"], m0, rtol=1e-13, atol=1e-300) and obs["status"] == 0
+    assert obs["fluid_nodes"] == int((mat == 0).sum())
