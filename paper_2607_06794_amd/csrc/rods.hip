@@ -75,11 +75,13 @@ __device__ inline double ljf_d(double d, double d0) {
     return (-12.0 * x6 * x6 + 12.0 * x6) / d;
 }
 
-// -dU/dd of the rod-rod potential (excluded volume + shifted cohesion); one
-// potential shape, its strength chosen by the range d falls in
-__device__ inline double pair_force(double d, const RodArgs &a) {
+// -dU/dd of the rod-rod potential (excluded volume + shifted cohesion)
+// divided by d, for d > 0; one potential shape, its strength chosen by the
+// range d falls in, one reciprocal of d
+__device__ inline double pair_force_over_d(double d, const RodArgs &a) {
     const double eps = d <= a.d0 ? a.eps_rep : ((a.eps_att > 0.0 && d < a.r_cut) ? a.eps_att : 0.0);
-    return eps != 0.0 ? -(eps * ljf_d(d, a.d0)) : 0.0;
+    const double id = 1.0 / d, x = a.d0 * id, x6 = x * x * x * x * x * x;
+    return eps != 0.0 ? -(eps * ((-12.0 * x6 * x6 + 12.0 * x6) * id)) * id : 0.0;
 }
 
 // closest points of segments [p1, q1], [p2, q2]: stationary point of the
@@ -98,19 +100,22 @@ __device__ inline double seg_seg(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2) {
             c2 = x2;
         }
     };
+    // one reciprocal per denominator (FP64 division is a long sequence)
     const double den = aa * e - b * b;
     if (den > 1e-14 * fmax(aa * e, 1e-300)) {
-        const double s = (b * f - c * e) / den, t = (aa * f - b * c) / den;
+        const double iden = 1.0 / den;
+        const double s = (b * f - c * e) * iden, t = (aa * f - b * c) * iden;
         if (s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0) tryst(s, t);
     }
+    const double ie = e == 0.0 ? 0.0 : 1.0 / e, ia = aa == 0.0 ? 0.0 : 1.0 / aa;
     for (int k = 0; k < 2; ++k) {
         const double s = k;
-        const double t = e == 0.0 ? 0.0 : fmin(fmax((b * s + f) / e, 0.0), 1.0);
+        const double t = e == 0.0 ? 0.0 : fmin(fmax((b * s + f) * ie, 0.0), 1.0);
         tryst(s, t);
     }
     for (int k = 0; k < 2; ++k) {
         const double t = k;
-        const double s = aa == 0.0 ? 0.0 : fmin(fmax((b * t - c) / aa, 0.0), 1.0);
+        const double s = aa == 0.0 ? 0.0 : fmin(fmax((b * t - c) * ia, 0.0), 1.0);
         tryst(s, t);
     }
     return sqrt(best);
@@ -450,7 +455,7 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
                 const d3 pb = Xb - a.half * eb + shift, qb = Xb + a.half * eb + shift;
                 d3 ca, cb;
                 const double d = seg_seg(pa, qa, pb, qb, ca, cb);
-                const double fmd = d > 0.0 ? pair_force(d, a) / d : 0.0;
+                const double fmd = d > 0.0 ? pair_force_over_d(d, a) : 0.0;
                 fv = fmd * (ca - cb);
                 tv = cross(ca - Xa, fv);
             };
