@@ -831,10 +831,20 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
             node_densities<S>(a, bt.rho_fresh, f, n, rho);
             const d3 dx0 = min_image(mk(x, y, z) - X, a);
             // one linked direction at a time (rolled: an unrolled body per
-            // direction costs occupancy); f*_opp(i)(x) is read again from
-            // cache, which is what the slot stores to other nodes require anyway
-            for (unsigned m = links; m; m &= m - 1) {
-                const int i = __builtin_ctz(m);
+            // direction costs occupancy). The two f*_opp(i)(x) of the next
+            // link are loaded before this link's stores, so one load latency
+            // overlaps the previous link's arithmetic instead of two
+            // serialised ones per link; the stores go to rod nodes and never
+            // alias these reads of the fluid node x
+            int i = __builtin_ctz(links);
+            double fo[2], fn[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) fo[k] = decf(f, (k * Q + opp(i)) * a.fs + n);
+            for (unsigned m = links; m;) {
+                m &= m - 1;
+                const int inext = m ? __builtin_ctz(m) : i;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) fn[k] = decf(f, (k * Q + opp(inext)) * a.fs + n);
                 int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
                 wrap_coord(xx, a.nx, a.px);
                 wrap_coord(yy, a.ny, a.py);
@@ -850,13 +860,15 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
                 d3 dp = mk(0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const double fo = decf(f, (k * Q + opp(i)) * a.fs + n) + wgt<double>(opp(i)) * a.rho_ref[k];
+                    const double f_o = fo[k] + wgt<double>(opp(i)) * a.rho_ref[k];
                     const double add = 2.0 * wgt<double>(i) * rho[k] * cu * 3.0;
-                    const double fin = fo + add;
+                    const double fin = f_o + add;
                     f[(k * Q + i) * a.fs + s] = Codec<S>::enc(typename Codec<S>::C(fin - wgt<double>(i) * a.rho_ref[k]));
-                    dp = dp - (fo + fin) * ci;
+                    dp = dp - (f_o + fin) * ci;
                     acc[6 + k] -= add;
+                    fo[k] = fn[k];
                 }
+                i = inext;
                 const d3 tq = cross(arm, dp);
                 acc[0] += dp.x;
                 acc[1] += dp.y;
