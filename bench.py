@@ -312,7 +312,18 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     status_b = int(mb["status"])
     lat_a.close()
     lat_b.close()
-    n_unstable = int(sum(1 for st in lat_status if st))
+    # end-of-rollout status words by what they flag: NaN (bit 1), a
+    # non-positive density without NaN (bit 2), a rod limit only (bits 8, 16,
+    # 32), the speed bit alone (4: also set by the near-empty layer under the
+    # reservoir), or nothing
+    status_kinds = {
+        "clear": sum(1 for st in lat_status if st == 0),
+        "speed_only": sum(1 for st in lat_status if st == 4),
+        "rod_limit": sum(1 for st in lat_status if st & 56 and not st & 3),
+        "nonpositive_density": sum(1 for st in lat_status if st & 2 and not st & 1),
+        "nan": sum(1 for st in lat_status if st & 1),
+    }
+    n_unstable = int(sum(1 for st in lat_status if st & ~4))
     out = {
         "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
         "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),
@@ -326,13 +337,13 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         "fallback_threshold": 0.005, "jump_mass_error": float(adv["mass_error"]),
         "would_fall_back": bool(adv["mass_error"] > 0.005), "reservoir_rate_per_step": float(rate),
         "status_after_jump": status_b,
-        "rollout_unstable_droplets": n_unstable, "pairs_dropped_unhealthy": int(
+        "rollout_unstable_droplets": n_unstable, "rollout_status": status_kinds, "pairs_dropped_unhealthy": int(
             (len(specs) * 7 // 8) * (n_snap - 1) - len(train) + (len(specs) - len(specs) * 7 // 8) * (n_snap - 2) - len(test)),
     }
     if log_fn:
         log_fn(f"[surrogate] gain over persistence x{out['gain_over_persistence']:.2f}, speedup x{out['speedup']:.2f}, "
                f"mass error {mass_err:.2e}, deposit error {dep_err:.3f}, g_x error {g_err:.3f}, rod error {rod_err:.2f}, "
-               f"forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s), {n_unstable} unstable rollouts")
+               f"forward {ms_fwd:.2f} ms ({out['fwd_tflops']:.1f} TFLOP/s), rollouts at the end {status_kinds}")
     return out
 
 
