@@ -32,10 +32,12 @@
 //    the directions pulled from the reservoir and books the outflow of its
 //    stored f*(t) towards the reservoir into a per-tile FP64 ledger slot
 //    (deterministic: each tile owns its slot);
-//  * rod nodes: their slots are written by the rod link kernel; on lattices
-//    with rods the step also stores every fluid node's densities (compute
-//    precision), which the rod passes read instead of summing 19 populations
-//    per surface node in the order of their lists.
+//  * rod nodes: the slots the next pull reads are written by the rod link
+//    kernel; the step stores zero deviations into all of them beforehand, so
+//    that waves cut by a rod store whole lines.  On lattices with rods the
+//    step also stores every node's densities (compute precision; zero on rod
+//    nodes), which the rod passes read instead of summing 19 populations per
+//    surface node in the order of their lists.
 //
 // Evaporation sink (a separate instantiation; FP32 storage, or FP64 with
 // tau = 1): after the
@@ -478,7 +480,15 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
 
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            if (!own_fin[r] || (cur_m[r] & MAT_ID_MASK) != MAT_FLUID) continue;
+            // rod nodes go through the same arithmetic (all their moments are
+            // zero, so every deviation they store is exactly zero) and store
+            // with the fluid lanes: a wave that a rod cuts through then still
+            // writes whole lines, where masked lanes would leave partial lines
+            // that HBM has to read, merge and write back.  Nothing reads these
+            // slots before the rod passes rewrite them (link) or refill them.
+            const uint8_t mid = cur_m[r] & MAT_ID_MASK;
+            if (!own_fin[r] || (mid != MAT_FLUID && mid != MAT_ROD)) continue;
+            const bool fluid = mid == MAT_FLUID;
             const int rc = own_ring[r];
             const C rho[2] = {cur_rho[r][0], cur_rho[r][1]};
             if (a.rho_out) {  // lattices with rods: the densities for the rod passes
@@ -540,12 +550,12 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                     const C ud = (cur_j[r][0][d] + cur_j[r][1][d] + C(0.5) * (F[0][d] + F[1][d])) * ir;
                     usq_chk += ud * ud;
                 }
-                if (!(rt > C(0))) st |= ST_RHO;
-                if (!(usq_chk <= C(0.09))) st |= (usq_chk != usq_chk) ? ST_NAN : ST_SPEED;
+                if (fluid && !(rt > C(0))) st |= ST_RHO;
+                if (fluid && !(usq_chk <= C(0.09))) st |= (usq_chk != usq_chk) ? ST_NAN : ST_SPEED;
             }
 
             const uint32_t voE = own[r].xy[1][1] * E;
-            const bool near_wall = (cur_m[r] & MAT_NEAR_WALL) != 0;
+            const bool near_wall = fluid && (cur_m[r] & MAT_NEAR_WALL) != 0;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 C ue[3];
@@ -582,7 +592,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                     if constexpr (TAU1) {
                         ds = deq[i];  // Eq. 1 with tau = 1: f* = f^eq
                     } else {
-                        ds = cur_f[r][k][i] - (cur_f[r][k][i] - deq[i]) * om[k];
+                        ds = fluid ? cur_f[r][k][i] - (cur_f[r][k][i] - deq[i]) * om[k] : C(0);
                     }
                     if constexpr (SINK) {
                         // Eq. 8: min(J, f*_0^A), at least 0, leaves A's rest population for B's
@@ -598,7 +608,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                     fstar[i] = ds;
                     buf_store<S>(Codec<S>::enc(ds), dst[k], voE, i * fsE + zE);
                 }
-                if (ledger_plane) {
+                if (ledger_plane && fluid) {
                     // this step's streaming moves the node's stored f*_i(t) with c_iz = +1
                     // into the reservoir and pulls w_i rho_top_k out of it
                     double outflow = 0.0, inflow = 0.0;
