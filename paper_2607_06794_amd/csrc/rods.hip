@@ -550,9 +550,24 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
 // ---------------------------------------------------------------------------
 // 3. re-mask: new occupancy of every rod (newid is -1 everywhere on entry) and
 //    the rod's surface list; one work-group per rod
+//
+// A rod's axis-aligned box is mostly empty for an oblique rod (a 24-node rod
+// on a diagonal fills a few percent of it), so the nodes visited are the
+// box's x-rows cut down to the x-interval within the shell radius of the
+// infinite axis line (a quadratic in x per row; the capsule's shell lies
+// inside that cylinder), widened by a node on each side.  Rows keep the box
+// order (z, then y, then x ascending), so the list is the one a walk over
+// the whole box gives.  Where the box wraps round a periodic x (lattices
+// about as small as the rod) or has more rows than the row table holds, the
+// walk covers whole rows.
 // ---------------------------------------------------------------------------
+constexpr int MASK_ROWS = 4096;  // row table of the re-mask work-group
+static_assert(MASK_ROWS % MB == 0, "rows are scanned MB at a time");
+
 __global__ void __launch_bounds__(MB) rod_mask_kernel(RodBatch bt) {
     __shared__ int wcount[MB / 64];
+    __shared__ int row_start[MASK_ROWS + 1];
+    __shared__ int row_x0[MASK_ROWS];
     int r;
     const RodArgs a = rod_of(bt, blockIdx.x, r);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -564,16 +579,96 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodBatch bt) {
     const int64_t nbox64 = (ex > 0 && ey > 0 && ez > 0) ? int64_t(ex) * ey * ez : 0;
     if (nbox64 > (int64_t(1) << 30) && threadIdx.x == 0) atomicOr(a.status, ST_ROD_WALL);
     const int nbox = nbox64 > (int64_t(1) << 30) ? 0 : int(nbox64);
-    const int exy = ex * ey;
+    const int nrows = nbox ? ey * ez : 0;
     const double r2in = a.radius * a.radius, r2sh = shell_r2(a);
+    const d3 X = ld3(rod + ROD_X), e = quat_axis(rod + ROD_Q);
+
+    // rows: candidate x-interval and its length, then starts by a block scan
+    const bool rows_fit = nrows <= MASK_ROWS;
+    int total = nbox;
+    if (rows_fit) {
+        const bool cull = !a.px || (X.x - b.lo[0] < 0.5 * a.nx - 1.0 && b.hi[0] - X.x < 0.5 * a.nx - 1.0);
+        // r2c: the shell radius with a margin far above the rounding of the
+        // discriminant; rods within ~2 degrees of x (A < 1e-3) walk whole rows
+        const double A = 1.0 - e.x * e.x, r2c = r2sh + 1e-6;
+        int carry = 0;
+        for (int q0 = 0; q0 < MASK_ROWS && q0 < nrows; q0 += MB) {
+            const int q = q0 + int(threadIdx.x);
+            int x0 = b.lo[0], cnt = 0;
+            if (q < nrows) {
+                int x1 = b.hi[0];
+                if (cull && A > 1e-3) {
+                    const int mz = q / ey, my = q - mz * ey;
+                    const double dy = min_img(double(b.lo[1] + my) - X.y, a.ny, a.py);
+                    const double dz = min_img(double(b.lo[2] + mz) - X.z, a.nz, a.pz);
+                    // |d|^2 - (d.e)^2 <= r^2 with d = (x - X.x, dy, dz)
+                    const double sp = dy * e.y + dz * e.z;
+                    const double B = -2.0 * e.x * sp, C = dy * dy + dz * dz - sp * sp - r2c;
+                    const double disc = B * B - 4.0 * A * C;
+                    if (disc < 0.0) {
+                        x1 = x0 - 1;
+                    } else {
+                        const double sq = sqrt(disc), i2a = 0.5 / A;
+                        const double lo = fmin(fmax(X.x + (-B - sq) * i2a, b.lo[0] - 2.0), b.hi[0] + 2.0);
+                        const double hi = fmin(fmax(X.x + (-B + sq) * i2a, b.lo[0] - 2.0), b.hi[0] + 2.0);
+                        x0 = max(x0, int(floor(lo)) - 1);
+                        x1 = min(x1, int(ceil(hi)) + 1);
+                    }
+                }
+                cnt = max(x1 - x0 + 1, 0);
+            }
+            // exclusive scan of cnt over the work-group
+            int v = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int u = __shfl_up(v, off, 64);
+                if (lane >= off) v += u;
+            }
+            if (lane == 63) wcount[wv] = v;
+            __syncthreads();
+            int wbase = 0, tot = 0;
+            for (int w = 0; w < MB / 64; ++w) {
+                wbase += w < wv ? wcount[w] : 0;
+                tot += wcount[w];
+            }
+            if (q < nrows) {
+                row_start[q] = carry + wbase + v - cnt;
+                row_x0[q] = x0;
+            }
+            carry += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) row_start[nrows] = carry;
+        __syncthreads();
+        total = carry;
+    }
+
     int base = 0;  // same in every thread
-    for (int m0 = 0; m0 < nbox; m0 += MB) {
+    for (int m0 = 0; m0 < total; m0 += MB) {
         const int m = m0 + int(threadIdx.x);
         bool listed = false;
         int64_t n = 0;
-        if (m < nbox) {
-            const int mz = m / exy, rem = m - mz * exy, my = rem / ex;
-            int x = b.lo[0] + (rem - my * ex), y = b.lo[1] + my, z = b.lo[2] + mz;
+        if (m < total) {
+            int x, y, z;
+            if (rows_fit) {
+                // the row holding candidate m: the last start <= m
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (row_start[mid] <= m) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int mz = lo / ey, my = lo - mz * ey;
+                x = row_x0[lo] + (m - row_start[lo]);
+                y = b.lo[1] + my;
+                z = b.lo[2] + mz;
+            } else {
+                const int exy = ex * ey;
+                const int mz = m / exy, rem = m - mz * exy, my = rem / ex;
+                x = b.lo[0] + (rem - my * ex);
+                y = b.lo[1] + my;
+                z = b.lo[2] + mz;
+            }
             const double d2 = axis_dist2(rod, mk(x, y, z), a);
             const bool in_box = wrap_coord(x, a.nx, a.px) && wrap_coord(y, a.ny, a.py) && wrap_coord(z, a.nz, a.pz);
             if (d2 <= r2in && !in_box) atomicOr(a.status, ST_ROD_WALL);  // a rod left the lattice
