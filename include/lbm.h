@@ -251,6 +251,50 @@ int lb_deposit(lb_ctx *ctx, const lb_deposit_spec *spec, double *g_x, double *s_
  * [ny][nx] (host, caller-owned).  Synchronises. */
 int lb_rod_map(lb_ctx *ctx, int32_t *map_host, hipStream_t stream);
 
+/*
+ * Resistor network of a deposit (Methods, electrical characterisation,
+ * Eqs. 15-18).  Nodes are beads; beads i != j with 0 < r_ij^2 < r_c^2
+ * (r_ij^2 = (dx^2 + dy^2) + dz^2 in FP64, plain Euclidean: no periodic
+ * images) are joined with conductance G_ij = 1 / r_ij.  Beads with
+ * x < x_src form the source electrode (potential dV), beads with x > x_snk
+ * the sink (potential 0); the other potentials satisfy Kirchhoff's current
+ * law, sum_j G_ij (V_i - V_j) = 0, solved by Jacobi-preconditioned conjugate
+ * gradients to ||r|| <= tol ||b|| (free beads with no path to an electrode
+ * keep V = 0 and carry no current).  Outputs:
+ *   V_dev[n]  potentials; I_dev[n]  Eq. 15, I_i = 1/2 sum_j G_ij |V_i - V_j|
+ *   (device, caller-owned, FP64);
+ *   out->I_tot   the current leaving the source electrode,
+ *   out->I_ref   dV / (x_snk - x_src): Eq. 16 with kappa_0 A = 1, the current
+ *                of an ideal straight chain of beads across the gap,
+ *   out->kappa   I_tot / I_ref (Eq. 18 for one deposit),
+ *   out->edges, n_source, n_sink, max_degree, iterations, rel_residual.
+ * pos_dev: [n][3] bead positions (device, FP64).  n <= LB_NET_MAX_BEADS; at
+ * most LB_NET_MAX_DEG neighbours per bead (LB_EINVAL otherwise, after the
+ * outputs are written).  LB_EUNSTABLE if the residual is still above tol
+ * after max_iter iterations (outputs written).  Allocates and frees its own
+ * workspace; synchronises.
+ */
+#define LB_NET_MAX_BEADS 65536
+#define LB_NET_MAX_DEG 64
+typedef struct {
+    double r_c, x_src, x_snk, dV, tol;
+    int32_t max_iter;
+} lb_kirchhoff_spec;
+typedef struct {
+    double I_tot, I_ref, kappa, rel_residual;
+    int32_t iterations, edges, n_source, n_sink, max_degree;
+} lb_kirchhoff_out;
+int lb_kirchhoff(const double *pos_dev, int32_t n, const lb_kirchhoff_spec *spec, double *V_dev, double *I_dev,
+                 lb_kirchhoff_out *out, hipStream_t stream);
+
+/* Beads of the rods for the network and the deposit profiles: nb = max(2,
+ * floor(2 h / bead_spacing + 1/2) + 1) <= 64 beads per rod evenly along its
+ * axis segment (half-length h = L/2 - R) about the stored centre, rod after
+ * rod, into pos_dev [n_rods * nb][3] (device, caller-owned, capacity `cap`
+ * beads).  *n_out = n_rods * nb (also when pos_dev is null or too small,
+ * which then returns LB_EINVAL).  Enqueued on `stream`. */
+int lb_rod_beads(lb_ctx *ctx, double bead_spacing, double *pos_dev, int32_t cap, int32_t *n_out, hipStream_t stream);
+
 /* Tile shape of the fused step: 64 x tile_y columns, rows_per_thread rows per
  * thread, zchunk planes marched per work-group. */
 typedef struct {
@@ -434,7 +478,7 @@ const char *lb_last_error(void);
 /* sizeof of lb_params, lb_buffers, lb_obs, lb_droplet, lb_deposit_spec,
  * lb_graph and lb_conv into out[0..6], so a binding can verify its mirrors of
  * the structs.  Never fails. */
-void lb_abi_sizes(size_t out[7]);
+void lb_abi_sizes(size_t out[9]);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,8 @@ EXPORTS = (
     "lb_droplet_shape",
     "lb_deposit",
     "lb_rod_map",
+    "lb_kirchhoff",
+    "lb_rod_beads",
     "lb_batch_workspace_bytes",
     "lb_batch_create",
     "lb_batch_step",
@@ -163,6 +165,31 @@ class LbGraph(ct.Structure):
     ]
 
 
+class LbKirchhoffSpec(ct.Structure):
+    _fields_ = [
+        ("r_c", ct.c_double),
+        ("x_src", ct.c_double),
+        ("x_snk", ct.c_double),
+        ("dV", ct.c_double),
+        ("tol", ct.c_double),
+        ("max_iter", ct.c_int32),
+    ]
+
+
+class LbKirchhoffOut(ct.Structure):
+    _fields_ = [
+        ("I_tot", ct.c_double),
+        ("I_ref", ct.c_double),
+        ("kappa", ct.c_double),
+        ("rel_residual", ct.c_double),
+        ("iterations", ct.c_int32),
+        ("edges", ct.c_int32),
+        ("n_source", ct.c_int32),
+        ("n_sink", ct.c_int32),
+        ("max_degree", ct.c_int32),
+    ]
+
+
 class LbConv(ct.Structure):
     _fields_ = [
         ("x1", ct.c_void_p),
@@ -184,7 +211,8 @@ class LbConv(ct.Structure):
     ]
 
 
-STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph", "LbConv")
+STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph", "LbConv", "LbKirchhoffSpec",
+           "LbKirchhoffOut")
 
 
 class LbError(RuntimeError):
@@ -248,6 +276,11 @@ def load(path: str = LIB_PATH):
     lib.lb_deposit.restype = ct.c_int
     lib.lb_rod_map.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.lb_rod_map.restype = ct.c_int
+    lib.lb_kirchhoff.argtypes = [ct.c_void_p, ct.c_int32, P(LbKirchhoffSpec), ct.c_void_p, ct.c_void_p,
+                                 P(LbKirchhoffOut), ct.c_void_p]
+    lib.lb_kirchhoff.restype = ct.c_int
+    lib.lb_rod_beads.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_int32, P(ct.c_int32), ct.c_void_p]
+    lib.lb_rod_beads.restype = ct.c_int
     lib.lb_batch_workspace_bytes.argtypes = [P(ct.c_void_p), ct.c_int32]
     lib.lb_batch_workspace_bytes.restype = ct.c_size_t
     lib.lb_batch_create.argtypes = [P(ct.c_void_p), ct.c_int32, ct.c_void_p, ct.c_void_p, P(ct.c_void_p)]

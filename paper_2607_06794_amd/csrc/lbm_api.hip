@@ -408,7 +408,7 @@ size_t lb_workspace_bytes(const lb_params *p) {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
-void lb_abi_sizes(size_t out[7]) {
+void lb_abi_sizes(size_t out[9]) {
     out[0] = sizeof(lb_params);
     out[1] = sizeof(lb_buffers);
     out[2] = sizeof(lb_obs);
@@ -416,6 +416,8 @@ void lb_abi_sizes(size_t out[7]) {
     out[4] = sizeof(lb_deposit_spec);
     out[5] = sizeof(lb_graph);
     out[6] = sizeof(lb_conv);
+    out[7] = sizeof(lb_kirchhoff_spec);
+    out[8] = sizeof(lb_kirchhoff_out);
 }
 
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
@@ -1380,6 +1382,104 @@ int lb_batch_destroy(lb_batch *b) {
         if (g) (void)hipGraphExecDestroy(g);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// resistor network of a deposit
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevBuf {  // workspace of one call, freed on every return path
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I, lb_kirchhoff_out *out,
+                 hipStream_t stream) {
+    if (!s || !out || n < 0) return fail(LB_EINVAL, "null argument or negative bead count");
+    if (n > 0 && (!pos || !V || !I)) return fail(LB_EINVAL, "null bead, potential or current buffer");
+    if (n > LB_NET_MAX_BEADS) return fail(LB_EINVAL, "at most %d beads", LB_NET_MAX_BEADS);
+    if (!(s->r_c > 0.0) || !std::isfinite(s->r_c) || !std::isfinite(s->x_src) || !std::isfinite(s->x_snk) ||
+        !(s->x_src < s->x_snk) || !std::isfinite(s->dV) || !(s->tol > 0.0) || s->max_iter < 0)
+        return fail(LB_EINVAL, "bad network spec (r_c > 0, x_src < x_snk, tol > 0, max_iter >= 0, finite values)");
+    memset(out, 0, sizeof *out);
+    out->I_ref = s->dV / (s->x_snk - s->x_src);
+    if (n == 0) return LB_OK;
+    const size_t nn = size_t(n);
+    const size_t b_nbr = nn * NET_DEG * sizeof(int), b_g = nn * NET_DEG * sizeof(double);
+    const size_t b_vec = nn * sizeof(double), b_deg = nn * sizeof(int);
+    const size_t bytes = b_g + 5 * b_vec + 8 * sizeof(double) + b_nbr + b_deg + 4 * sizeof(int);
+    DevBuf ws;
+    HIP_TRY(hipMalloc(&ws.p, bytes), "network workspace");
+    char *w = static_cast<char *>(ws.p);
+    NetArgs a{};
+    a.pos = pos;
+    a.n = n;
+    a.rc2 = s->r_c * s->r_c;
+    a.x_src = s->x_src;
+    a.x_snk = s->x_snk;
+    a.dV = s->dV;
+    a.tol = s->tol;
+    a.max_iter = s->max_iter;
+    a.V = V;
+    a.I = I;
+    // doubles first (8-byte aligned from the allocation), then the ints
+    a.g = reinterpret_cast<double *>(w);
+    w += b_g;
+    a.diag = reinterpret_cast<double *>(w);
+    a.r = a.diag + nn;
+    a.z = a.r + nn;
+    a.p = a.z + nn;
+    a.q = a.p + nn;
+    a.out = a.q + nn;
+    w += 5 * b_vec + 8 * sizeof(double);
+    a.nbr = reinterpret_cast<int *>(w);
+    a.deg = a.nbr + nn * NET_DEG;
+    a.cnt = a.deg + nn;
+    HIP_TRY(launch_net_edges(a, stream), "network edges");
+    HIP_TRY(launch_net_solve(a, stream), "network solve");
+    double ho[3];
+    int hc[4];
+    HIP_TRY(hipMemcpyAsync(ho, a.out, sizeof ho, hipMemcpyDeviceToHost, stream), "copy network result");
+    HIP_TRY(hipMemcpyAsync(hc, a.cnt, sizeof hc, hipMemcpyDeviceToHost, stream), "copy network counts");
+    HIP_TRY(hipStreamSynchronize(stream), "network sync");
+    out->I_tot = ho[0];
+    out->kappa = out->I_tot / out->I_ref;
+    out->rel_residual = ho[1];
+    out->iterations = int32_t(ho[2]);
+    out->max_degree = hc[0];
+    out->n_source = hc[1];
+    out->n_sink = hc[2];
+    out->edges = hc[3] / 2;
+    if (hc[0] > NET_DEG)
+        return fail(LB_EINVAL, "a bead has %d neighbours within r_c (at most %d)", hc[0], NET_DEG);
+    if (!(ho[1] <= s->tol))
+        return fail(LB_EUNSTABLE, "network solve: relative residual %.3e after %d iterations", ho[1], out->iterations);
+    return LB_OK;
+}
+
+int lb_rod_beads(lb_ctx *c, double spacing, double *pos, int32_t cap, int32_t *n_out, hipStream_t stream) {
+    if (!c || !n_out || cap < 0 || !(spacing > 0.0) || !std::isfinite(spacing))
+        return fail(LB_EINVAL, "null argument, negative capacity or bad bead spacing");
+    const lb_params &p = c->p;
+    const double half = 0.5 * p.rod_length - p.rod_radius;
+    const double nbd = floor(2.0 * half / spacing + 0.5) + 1.0;
+    const int nb = nbd < 2.0 ? 2 : (nbd > DEP_NB ? DEP_NB + 1 : int(nbd));
+    if (nb > DEP_NB) return fail(LB_EINVAL, "more than %d beads per rod", DEP_NB);
+    const int64_t n = int64_t(p.n_rods) * nb;
+    *n_out = int32_t(n);
+    if (n == 0) return LB_OK;
+    if (!pos || n > cap) return fail(LB_EINVAL, "bead buffer holds %d beads, %lld needed", int(cap), (long long)n);
+    HIP_TRY(launch_rod_beads(c->rods, p.n_rods, nb, half, pos, stream), "rod beads");
     return LB_OK;
 }
 

@@ -154,6 +154,25 @@ constexpr int PROBE_MAX = 256;  // pressure probes per call
 hipError_t launch_pressure(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
                            const double rref[2], double G, const int *xyz, int n, double *out, hipStream_t s);
 hipError_t launch_deposit(const DepArgs &d, hipStream_t s);
+
+// resistor network of a deposit (network.hip)
+constexpr int NET_DEG = 64;  // neighbours stored per bead
+struct NetArgs {
+    const double *pos;  // [n][3]
+    int n;
+    double rc2, x_src, x_snk, dV, tol;
+    int max_iter;
+    int *nbr;      // [n][NET_DEG]
+    double *g;     // [n][NET_DEG]
+    int *deg;      // [n]
+    double *V, *I; // [n] (caller's)
+    double *diag, *r, *z, *p, *q;  // [n] each
+    int *cnt;      // max degree, source beads, sink beads, stored directed edges
+    double *out;   // I_tot, relative residual, iterations
+};
+hipError_t launch_net_edges(const NetArgs &a, hipStream_t s);
+hipError_t launch_net_solve(const NetArgs &a, hipStream_t s);
+hipError_t launch_rod_beads(const double *rods, int n_rods, int nb, double half, double *pos, hipStream_t s);
 hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s);
 
 // surrogate (surrogate.hip): channels-last BF16 convolutions and helpers

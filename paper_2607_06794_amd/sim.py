@@ -224,6 +224,19 @@ class Lattice:
                 "labels": labels[: self.n_rods], "edges": g.edges, "largest": g.largest,
                 "spanning": bool(g.spanning)}
 
+    def rod_beads(self, spacing: float = 1.0):
+        """Beads of the rods (lb_rod_beads) as a CUDA FP64 tensor [n, 3]."""
+        import torch
+
+        n = ct.c_int32()
+        # first call with no buffer: only the count (and LB_EINVAL if any)
+        _lib.check(self.lib.lb_rod_beads(self._ctx, float(spacing), None, 0, ct.byref(n), _stream_ptr(self.stream)),
+                   allow=(_lib.LB_OK, _lib.LB_EINVAL))
+        pos = torch.empty((max(n.value, 1), 3), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.lb_rod_beads(self._ctx, float(spacing), ct.c_void_p(pos.data_ptr()), int(pos.shape[0]),
+                                         ct.byref(n), _stream_ptr(self.stream)))
+        return pos[: n.value]
+
     def snapshot(self):
         """Device copy of the lattice's state for restore(): the current
         populations and the workspace (material map, rods, ledgers, status)."""
@@ -319,6 +332,28 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+def kirchhoff(pos, r_c: float, x_src: float, x_snk: float, dV: float = 1.0, tol: float = 1e-12,
+              max_iter: int = 20000, stream=None) -> dict:
+    """Resistor network of a deposit (lb_kirchhoff, Eqs. 15-18) for bead
+    positions `pos`, a CUDA FP64 tensor [n, 3]: potentials V and node
+    currents I (CUDA tensors), I_tot, I_ref, kappa and the solve's counts."""
+    import torch
+
+    lib = _lib.load()
+    pos = pos.to(torch.float64).contiguous()
+    n = int(pos.shape[0])
+    V = torch.empty(max(n, 1), dtype=torch.float64, device=pos.device)
+    I = torch.empty_like(V)
+    spec = _lib.LbKirchhoffSpec(float(r_c), float(x_src), float(x_snk), float(dV), float(tol), int(max_iter))
+    out = _lib.LbKirchhoffOut()
+    st = torch.cuda.current_stream(pos.device) if stream is None else stream
+    _lib.check(lib.lb_kirchhoff(ct.c_void_p(pos.data_ptr()), n, ct.byref(spec), ct.c_void_p(V.data_ptr()),
+                                ct.c_void_p(I.data_ptr()), ct.byref(out), _stream_ptr(st)))
+    return {"V": V[:n], "I": I[:n], "I_tot": out.I_tot, "I_ref": out.I_ref, "kappa": out.kappa,
+            "rel_residual": out.rel_residual, "iterations": out.iterations, "edges": out.edges,
+            "n_source": out.n_source, "n_sink": out.n_sink, "max_degree": out.max_degree}
 
 
 class Batch:
