@@ -447,6 +447,37 @@ def traffic_record(prec, tile, n_fluid, ms_fused, rods=False):
             "vs_algorithmic": b / (algorithmic_bytes_per_lu(prec, rods) * n_fluid)}
 
 
+def network_form(case, rods, reps=5):
+    """The deposit's resistor network (Eqs. 15-18) for the benchmark droplet's
+    rods: beads at unit spacing along each rod (lb_rod_beads), joined below
+    r_c = 5.25 (the deposit graph's contact distance: 1.05 times the rods'
+    contact distance 5, as 2.1 is for the paper's beads of diameter 2),
+    electrodes 120 apart about the droplet centre.  Timed per lb_kirchhoff
+    call (workspace allocation, neighbour scan, solve, currents, copy-out)."""
+    import torch
+
+    from paper_2607_06794_amd.sim import Lattice, kirchhoff
+    from tests import cases
+
+    lp = rod_params(cases.lattice_params(case, "f32"))
+    lat = Lattice(lp, case["rho"], case["mat"], rods=rods)
+    pos = lat.rod_beads(1.0)
+    torch.cuda.synchronize()
+    lat.close()
+    spec = dict(r_c=5.25, x_src=68.0, x_snk=188.0)
+    o = kirchhoff(pos, **spec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        o = kirchhoff(pos, **spec)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    res = {"beads": int(pos.shape[0]), "bead_spacing": 1.0, **spec, "edges": o["edges"],
+           "iterations": o["iterations"], "rel_residual": o["rel_residual"], "I_tot": o["I_tot"],
+           "kappa": o["kappa"], "ms_per_solve": ms}
+    return res, pos.cpu().numpy()
+
+
 def cpu_baseline(case, sample_steps):
     from oracle import lbm
     from tests import cases
@@ -475,6 +506,7 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
+    ap.add_argument("--network", type=int, default=1, help="resistor network of the rods' beads (0: skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
     ap.add_argument("--unet-only", action="store_true", help="time the U-Net alone (one JSON line)")
@@ -558,6 +590,12 @@ def main():
         log(f"[bench] surrogate form: {args.surrogate} droplets")
         sur = surrogate_form(args.surrogate, epochs=args.surrogate_epochs, log_fn=log)
 
+    net, net_pos = None, None
+    if args.network > 0 and rods is not None:
+        net, net_pos = network_form(case, rods)
+        log(f"[bench] network: {net['beads']} beads, {net['edges']} edges, {net['iterations']} CG iterations, "
+            f"kappa* {net['kappa']:.4g}, {net['ms_per_solve']:.2f} ms per solve")
+
     cpu = None
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps of the same lattice")
@@ -565,6 +603,13 @@ def main():
         cpu = {"value": v, "unit": "MLUPS", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 NumPy oracle steps of the full 256x128x64 cap from t=0 "
                          f"({dt:.1f} s, 1 of {os.cpu_count()} host cores)"}
+        if net_pos is not None:
+            from oracle import network as onet
+
+            t0 = time.perf_counter()
+            o = onet.kirchhoff(net_pos, net["r_c"], net["x_src"], net["x_snk"])
+            cpu["network"] = {"ms_per_solve": (time.perf_counter() - t0) * 1e3, "kind": "oracle",
+                              "I_tot": o["I_tot"], "edges": o["edges"]}
 
     tr = traffic_record(args.prec, chosen, n_fluid, ms_fused, rods=n_rods > 0)
     out = {
@@ -598,6 +643,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "surrogate": sur,
+        "network": net,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
