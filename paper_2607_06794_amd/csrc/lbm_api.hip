@@ -1417,7 +1417,7 @@ int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, doubl
     const size_t nn = size_t(n);
     const size_t b_nbr = nn * NET_DEG * sizeof(int), b_g = nn * NET_DEG * sizeof(double);
     const size_t b_vec = nn * sizeof(double), b_deg = nn * sizeof(int);
-    const size_t bytes = b_g + 5 * b_vec + 8 * sizeof(double) + b_nbr + b_deg + 4 * sizeof(int);
+    const size_t bytes = b_g + 5 * b_vec + 8 * sizeof(double) + b_nbr + 2 * b_deg + 4 * sizeof(int);
     DevBuf ws;
     HIP_TRY(hipMalloc(&ws.p, bytes), "network workspace");
     char *w = static_cast<char *>(ws.p);
@@ -1444,7 +1444,8 @@ int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, doubl
     w += 5 * b_vec + 8 * sizeof(double);
     a.nbr = reinterpret_cast<int *>(w);
     a.deg = a.nbr + nn * NET_DEG;
-    a.cnt = a.deg + nn;
+    a.cls = a.deg + nn;
+    a.cnt = a.cls + nn;
     HIP_TRY(launch_net_edges(a, stream), "network edges");
     HIP_TRY(launch_net_solve(a, stream), "network solve");
     double ho[3];

@@ -165,6 +165,7 @@ struct NetArgs {
     int *nbr;      // [n][NET_DEG]
     double *g;     // [n][NET_DEG]
     int *deg;      // [n]
+    int *cls;      // [n]: 0 free, 1 source, 2 sink
     double *V, *I; // [n] (caller's)
     double *diag, *r, *z, *p, *q;  // [n] each
     int *cnt;      // max degree, source beads, sink beads, stored directed edges

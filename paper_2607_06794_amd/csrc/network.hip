@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
             dg += gk;
             if (net_class(a.pos[3 * j], a) == 1) b += gk * a.dV;
         }
+        a.cls[i] = ci;
         const bool fr = ci == 0;
         const double r = fr ? b : 0.0;
         const double z = (fr && dg > 0.0) ? r / dg : 0.0;
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
     atomicAdd(&a.cnt[1], nsrc);
     atomicAdd(&a.cnt[2], nsnk);
     atomicAdd(&a.cnt[3], dsum);
-    wg_sum(s0, sh);
+    wg_sum(s0, sh);  // its barriers also publish cls
     double rz = s0[0], rr = s0[1];
     const double bb = s0[1], stop2 = a.tol * a.tol * bb;
     int it = 0;
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
         double pq[1] = {0.0};
         for (int i = threadIdx.x; i < n; i += NET_CG) {
             double q = 0.0;
-            if (net_class(a.pos[3 * i], a) == 0) {
+            if (a.cls[i] == 0) {
                 const int dk = min(a.deg[i], NET_DEG);
                 double off = 0.0;
                 for (int k = 0; k < dk; ++k) off += a.g[size_t(i) * NET_DEG + k] * a.p[a.nbr[size_t(i) * NET_DEG + k]];
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
         const double alpha = rz / pq[0];
         double s1[2] = {0.0, 0.0};
         for (int i = threadIdx.x; i < n; i += NET_CG) {
-            if (net_class(a.pos[3 * i], a) != 0) continue;
+            if (a.cls[i] != 0) continue;
             const double r = a.r[i] - alpha * a.q[i];
             const double dg = a.diag[i];
             const double z = dg > 0.0 ? r / dg : 0.0;
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
         rz = s1[0];
         rr = s1[1];
         for (int i = threadIdx.x; i < n; i += NET_CG)
-            if (net_class(a.pos[3 * i], a) == 0) a.p[i] = a.z[i] + beta * a.p[i];
+            if (a.cls[i] == 0) a.p[i] = a.z[i] + beta * a.p[i];
         __syncthreads();  // the next product reads every bead's p
         ++it;
     }
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
     // Eq. 15 and the current leaving the source electrode
     double st[1] = {0.0};
     for (int i = threadIdx.x; i < n; i += NET_CG) {
-        const int ci = net_class(a.pos[3 * i], a);
+        const int ci = a.cls[i];
         const int dk = min(a.deg[i], NET_DEG);
         const double Vi = a.V[i];
         double s = 0.0;
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
             const int j = a.nbr[size_t(i) * NET_DEG + k];
             const double e = a.g[size_t(i) * NET_DEG + k] * (Vi - a.V[j]);
             s += fabs(e);
-            if (ci == 1 && net_class(a.pos[3 * j], a) != 1) st[0] += e;
+            if (ci == 1 && a.cls[j] != 1) st[0] += e;
         }
         a.I[i] = 0.5 * s;
     }
