@@ -500,7 +500,7 @@ def main():
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU baseline sample (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps in the CPU baseline sample (0: skip)")
     ap.add_argument("--rods", type=int, default=200, help="rods requested (stress placement)")
     ap.add_argument("--forms", type=int, default=1, help="also time the FP16/BF16 storage forms")
     ap.add_argument("--batched", type=int, default=64, help="lattices of the many-droplet sweep (0: skip)")
