@@ -351,6 +351,47 @@ class CoupledRun:
     def _cvec(self, i):
         return lbm.C[i].astype(np.float64)
 
+    @staticmethod
+    def link_term(i, rho_k, ub):
+        """Ladd's moving bounce-back addition 2 w_i rho_k (c_i . u_b) / c_s^2."""
+        return 2.0 * lbm.W[i] * rho_k * (lbm.C[i].astype(np.float64) @ ub) / lbm.CS2
+
+    def moving_bounce_back(self, fpost, f, rho_t):
+        """Rod links of the pull: a fluid node x whose source s = x - c_i is a
+        rod node takes f_i(x, t+1) = f*_ibar(x, t) + link_term (u_b the rigid
+        velocity at the link midpoint x_b = x - c_i / 2, minimum image).
+
+        Overwrites those entries of the pulled populations f in place and
+        returns the rod load (dP, dT: momentum -c_i (f*_ibar + f_i) per link,
+        torque about the centre taken at x_b) and the mass the added terms
+        carry out of the rods (dsolid[k], negative when the rods push mass
+        into the fluid)."""
+        rods = self.rods
+        nz, ny, nx = self.material.shape
+        fluid = self.material == lbm.FLUID
+        dP = np.zeros((rods.n, 3))
+        dT = np.zeros((rods.n, 3))
+        dsolid = np.zeros(2)
+        zz, yy, xx = np.nonzero(fluid)
+        for i in range(1, lbm.Q):
+            c = lbm.C[i]
+            sx, sy, sz = (xx - c[0]) % nx, (yy - c[1]) % ny, (zz - c[2]) % nz
+            rs = self.rid[sz, sy, sx]
+            sel = np.nonzero(rs >= 0)[0]
+            ci = self._cvec(i)
+            for m in sel:
+                x, y, z, r = xx[m], yy[m], zz[m], rs[m]
+                xb = np.array([x, y, z], dtype=np.float64) - 0.5 * ci
+                ub = rods.velocity_at(r, xb)
+                for k in range(2):
+                    add = self.link_term(i, rho_t[k, z, y, x], ub)
+                    f[k, i, z, y, x] = fpost[k, lbm.OPP[i], z, y, x] + add
+                    dsolid[k] -= add
+                    dp = -ci * (fpost[k, lbm.OPP[i], z, y, x] + f[k, i, z, y, x])
+                    dP[r] += dp
+                    dT[r] += np.cross(min_image(xb - rods.X[r], rods.box, rods.periodic), dp)
+        return dP, dT, dsolid
+
     def step(self, n=1):
         for _ in range(n):
             self._step()
@@ -364,29 +405,11 @@ class CoupledRun:
         fpost = self.f
         fluid = self.material == lbm.FLUID
         rho_t = np.array([fpost[k].sum(axis=0) for k in range(2)])  # collision invariant
-        dP = np.zeros((n, 3))
-        dT = np.zeros((n, 3))
 
         # ---- stream with boundaries; moving bounce-back at rod links
         f, dled = lbm.pull_stream(fpost, self.material, fp)
-        zz, yy, xx = np.nonzero(fluid)
-        for i in range(1, lbm.Q):
-            c = lbm.C[i]
-            sx, sy, sz = (xx - c[0]) % nx, (yy - c[1]) % ny, (zz - c[2]) % nz
-            rs = self.rid[sz, sy, sx]
-            sel = np.nonzero(rs >= 0)[0]
-            ci = self._cvec(i)
-            for m in sel:
-                x, y, z, r = xx[m], yy[m], zz[m], rs[m]
-                xb = np.array([x, y, z], dtype=np.float64) - 0.5 * ci
-                ub = rods.velocity_at(r, xb)
-                for k in range(2):
-                    add = 2.0 * lbm.W[i] * rho_t[k, z, y, x] * (ci @ ub) / lbm.CS2
-                    f[k, i, z, y, x] = fpost[k, lbm.OPP[i], z, y, x] + add
-                    self.solid[k] -= add
-                    dp = -ci * (fpost[k, lbm.OPP[i], z, y, x] + f[k, i, z, y, x])
-                    dP[r] += dp
-                    dT[r] += np.cross(min_image(xb - rods.X[r], rods.box, rods.periodic), dp)
+        dP, dT, dsolid = self.moving_bounce_back(fpost, f, rho_t)
+        self.solid += dsolid
 
         # ---- moments, force (rod nodes carry psi^s(rod)), collision
         rho = np.empty((2,) + shape)
@@ -402,6 +425,7 @@ class CoupledRun:
         fnew = np.where(fluid, lbm.collide(f, rho, ueq, fp), 0.0)
         # reaction to the adhesion force exerted by rod nodes y = x + c_i
         ps = np.asarray(fp.psi_solid, dtype=np.float64)[lbm.ROD]
+        zz, yy, xx = np.nonzero(fluid)
         for i in range(1, lbm.Q):
             c = lbm.C[i]
             ci = self._cvec(i)

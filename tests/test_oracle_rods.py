@@ -186,3 +186,256 @@ def test_resting_rod_is_static_bounce_back():
     # the rod has not moved a full node: masks agree
     assert run.last["covered"] == 0 and run.last["uncovered"] == 0
     assert np.array_equal(run.f, f_static)
+
+
+# --------------------------------------------------------------------------
+# moving bounce-back: Ladd's rule leaves a co-moving equilibrium unchanged
+# --------------------------------------------------------------------------
+
+
+def _comoving_links(V, omega, seed=11):
+    """Fluid at f*_k = f^eq(rho_k(x), u(x)) with u(x) = V + Omega x (x - X), the
+    rigid velocity field of the rod extended over the whole box (random rho_k).
+    For every rod link (fluid x, source x - c_i a rod node) the pull with
+    Ladd's moving bounce-back must return f^eq_i(rho_k(x), u(x)): the odd part
+    of Eq. 2 is w_i rho (c_i . u) / c_s^2, so f^eq_i - f^eq_ibar =
+    2 w_i rho (c_i . u) / c_s^2 exactly, and c_i . u_b is the same at x, at the
+    link midpoint and at the rod node for a rigid motion (c_i . (Omega x c_i) = 0).
+    Returns (pulled populations, expected, link mask, run, dP, dsolid)."""
+    shape = (14, 16, 22)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    rho = np.zeros((2,) + shape)
+    rho[0] = 1.0 + rng.uniform(-0.05, 0.05, size=shape)
+    rho[1] = 0.03 + rng.uniform(-0.01, 0.01, size=shape)
+    mat = np.zeros(shape, np.uint8)
+    fp = lbm.Params(shape=shape, G=0.0, psi_solid=np.zeros((9, 2)))
+    p = R.RodParams(length=12.0, radius=2.0, eps_att=0, wall_z=None)
+    q = np.array([np.cos(0.45), 0.5 * np.sin(0.45), 0.3 * np.sin(0.45), np.sqrt(0.66) * np.sin(0.45)])
+    Iperp = p.inertia[1]
+    Lang = np.asarray(omega, dtype=float) * Iperp  # omega perpendicular to the axis below
+    rods = R.Rods([[10.7, 8.3, 6.6]], [q], [V], [Lang], p, (nx, ny, nz), (1, 1, 1))
+    run = R.CoupledRun(rho, mat, fp, rods)
+    w = rods.omega(0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.stack([x, y, z]).astype(float) - rods.X[0][:, None, None, None]
+    for a, n in enumerate((nx, ny, nz)):
+        d[a] -= n * np.round(d[a] / n)
+    u = np.asarray(V, float)[:, None, None, None] + np.cross(w, d, axis=0)
+    fluid = run.material == lbm.FLUID
+    feq = np.stack([lbm.equilibrium(rho[k], u) for k in range(2)])
+    run.f = np.where(fluid, feq, 0.0)
+    rho_t = np.array([run.f[k].sum(axis=0) for k in range(2)])
+    f, _ = lbm.pull_stream(run.f, run.material, fp)
+    dP, dT, dsolid = run.moving_bounce_back(run.f, f, rho_t)
+    link = np.zeros((lbm.Q,) + shape, bool)
+    for i in range(1, lbm.Q):
+        link[i] = fluid & (lbm._shift(run.material, lbm.C[i]) == lbm.ROD)
+    return f, feq, link, run, dP, dsolid
+
+
+@pytest.mark.parametrize("V,omega", [((0.04, -0.03, 0.02), (0.0, 0.0, 0.0)),
+                                     ((0.0, 0.0, 0.0), (0.004, -0.006, 0.0)),
+                                     ((0.01, 0.02, -0.015), (-0.003, 0.002, 0.005))])
+def test_moving_bounce_back_returns_comoving_equilibrium(V, omega):
+    f, feq, link, run, _, _ = _comoving_links(V, omega)
+    assert link.sum() > 300
+    for k in range(2):
+        got = f[k][link]
+        want = feq[k][link]
+        assert np.abs(got - want).max() <= 1e-15 * np.abs(want).max() * 8
+    # the added terms are not trivially zero here
+    rho_t = np.array([run.f[k].sum(axis=0) for k in range(2)])
+    adds = [abs(R.CoupledRun.link_term(i, 1.0, run.rods.velocity_at(0, [5.0, 5.0, 5.0]))) for i in range(1, 19)]
+    assert max(adds) > 1e-4 and rho_t[0].max() > 0.9
+
+
+def test_moving_bounce_back_uniform_flow_exerts_no_force():
+    """Uniform densities, rod and fluid translating together: every lattice
+    line enters and leaves the closed rod surface equally often, and each
+    link carries -c_i times a term even in c_i, so the net load is zero
+    (Galilean invariance of the exchange)."""
+    shape = (14, 16, 22)
+    f, feq, link, run, dP, dsolid = _comoving_links((0.03, 0.01, -0.02), (0, 0, 0))
+    # rebuild with uniform densities
+    nz, ny, nx = shape
+    rho = np.zeros((2,) + shape)
+    rho[0], rho[1] = 1.0, 0.03
+    u = np.array([0.03, 0.01, -0.02])[:, None, None, None] * np.ones((3,) + shape)
+    fluid = run.material == lbm.FLUID
+    run.f = np.where(fluid, np.stack([lbm.equilibrium(rho[k], u) for k in range(2)]), 0.0)
+    rho_t = np.array([run.f[k].sum(axis=0) for k in range(2)])
+    f2, _ = lbm.pull_stream(run.f, run.material, run.fp)
+    dP, dT, dsolid = run.moving_bounce_back(run.f, f2, rho_t)
+    for i in range(1, lbm.Q):
+        assert link[i].sum() == link[lbm.OPP[i]].sum()
+    assert np.abs(dP).max() < 1e-13
+    # mass pushed by the moving surface: sum over links of 2 w_i rho c_i.u/cs2 = 0 too
+    assert np.abs(dsolid).max() < 1e-13
+
+
+@pytest.mark.parametrize("mistake", ["sign", "factor6", "no_rotation", "density_one"])
+def test_planted_bounce_back_mistakes_are_caught(monkeypatch, mistake):
+    """Plant a wrong moving bounce-back term in the oracle: the co-moving pin fails."""
+    right = R.CoupledRun.link_term
+
+    def wrong(i, rho_k, ub):
+        if mistake == "sign":
+            return -right(i, rho_k, ub)
+        if mistake == "factor6":
+            return 3.0 * right(i, rho_k, ub)
+        if mistake == "density_one":
+            return right(i, 1.0, ub)
+        return right(i, rho_k, ub)
+
+    monkeypatch.setattr(R.CoupledRun, "link_term", staticmethod(wrong))
+    if mistake == "no_rotation":
+        monkeypatch.setattr(R.Rods, "velocity_at", lambda self, r, x: self.V[r].copy())
+    worst = 0.0
+    for V, om in (((0.04, -0.03, 0.02), (0, 0, 0)), ((0.0, 0.0, 0.0), (0.004, -0.006, 0.0))):
+        f, feq, link, _, _, _ = _comoving_links(V, om)
+        worst = max(worst, max(np.abs(f[k][link] - feq[k][link]).max() for k in range(2)))
+    assert worst > 1e-6
+
+
+def test_link_velocity_is_the_same_anywhere_on_the_link():
+    """c_i . u_b and the torque arm (x_b - X) x (-c_i g) are identical for x_b at
+    the fluid node, at the link midpoint and at the rod node (rigid motion),
+    so the choice of the midpoint only fixes the rounding."""
+    rods = R.Rods([[10.0, 9.0, 8.0]], [[0.9, 0.1, 0.3, 0.2]], [[0.01, -0.02, 0.03]], [[3.0, -2.0, 5.0]],
+                  R.RodParams(length=12.0, wall_z=None), (30, 30, 30), (1, 1, 1))
+    rods.q[0] /= np.linalg.norm(rods.q[0])
+    x = np.array([13.0, 11.0, 9.0])
+    for i in range(1, lbm.Q):
+        ci = lbm.C[i].astype(float)
+        vals = [ci @ rods.velocity_at(0, x - s * ci) for s in (0.0, 0.5, 1.0)]
+        assert np.ptp(vals) < 1e-16
+        arms = [np.cross(x - s * ci - rods.X[0], -ci * 0.7) for s in (0.0, 0.5, 1.0)]
+        assert np.abs(np.array(arms) - arms[0]).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# rigid-body substeps: closed forms of the symplectic Euler scheme
+# --------------------------------------------------------------------------
+
+
+def _single_rod(n_sub=5, q=None, L=(0, 0, 0), V=(0, 0, 0)):
+    p = R.RodParams(length=24.0, radius=2.0, eps_att=0, wall_z=None, n_sub=n_sub)
+    q = np.array([1.0, 0, 0, 0]) if q is None else np.asarray(q, float) / np.linalg.norm(q)
+    return R.Rods([[40.0, 41.0, 42.0]], [q], [V], [L], p, (100, 100, 100), (0, 0, 0)), p
+
+
+def test_constant_force_matches_symplectic_euler_closed_form():
+    """F fixed over N steps of n substeps (dt = 1/n): V_m = V0 + m a dt and,
+    the position using the updated velocity, X_m = X0 + m V0 dt + a dt^2 m(m+1)/2."""
+    F = np.array([[0.7, -0.4, 0.25]])
+    V0 = np.array([0.01, 0.02, -0.03])
+    rods, p = _single_rod(V=V0)
+    X0 = rods.X[0].copy()
+    N = 6
+    for _ in range(N):
+        rods.integrate(F, np.zeros((1, 3)))
+    m, dt, a = N * p.n_sub, 1.0 / p.n_sub, F[0] / p.mass
+    assert np.allclose(rods.V[0], V0 + m * a * dt, rtol=1e-14, atol=1e-17)
+    Xw = X0 + m * V0 * dt + a * dt * dt * m * (m + 1) / 2
+    assert np.abs(rods.X[0] - Xw).max() < 1e-12
+    # the other order (position first) would give m(m-1)/2: distinguishable here
+    assert np.abs(a * dt * dt * m).max() > 1e-5
+
+
+def test_axial_torque_spins_with_the_parallel_inertia():
+    """A constant torque along the axis: L_m = m T dt, omega = L / I_par, the
+    axis stays put and the rotation angle is |T| dt^2 m(m+1) / (2 I_par)
+    (omega taken after the L update)."""
+    q0 = np.array([np.cos(0.3), 0.0, np.sin(0.3), 0.0])
+    rods, p = _single_rod(q=q0)
+    e = R.axis(rods.q[0])
+    Tq = 0.2 * e
+    N = 4
+    for _ in range(N):
+        rods.integrate(np.zeros((1, 3)), Tq[None])
+    m, dt = N * p.n_sub, 1.0 / p.n_sub
+    Ipar, _ = p.inertia
+    theta = np.linalg.norm(Tq) * dt * dt * m * (m + 1) / (2 * Ipar)
+    qw = R.quat_mul(np.concatenate([[np.cos(theta / 2)], np.sin(theta / 2) * e]), q0)
+    assert min(np.abs(rods.q[0] - qw).max(), np.abs(rods.q[0] + qw).max()) < 1e-13
+    assert np.allclose(R.axis(rods.q[0]), e, atol=1e-14)
+    assert np.allclose(rods.L[0], m * dt * Tq, rtol=1e-14)
+    assert theta > 1e-3
+
+
+def _free_top_exact(q0, Lang, p, t):
+    """Torque-free symmetric top: the orientation is a rotation about L at
+    |L| / I_perp after a spin about the initial axis e0 at (L . e0)(1/I_par -
+    1/I_perp):  q(t) = exp(t L / I_perp) exp(t b e0) q0 (space-frame rotations)."""
+    Ipar, Iperp = p.inertia
+    e0 = R.axis(q0)
+    b = (1.0 / Ipar - 1.0 / Iperp) * (Lang @ e0)
+
+    def qexp(w):
+        n = np.linalg.norm(w)
+        return np.concatenate([[np.cos(0.5 * n)], np.sin(0.5 * n) * w / n])
+
+    return R.quat_mul(R.quat_mul(qexp(t * Lang / Iperp), qexp(t * b * e0)), q0)
+
+
+def _free_top(n_sub, steps, omega_fn=None):
+    q0 = np.array([np.cos(0.35), np.sin(0.35) * 0.6, np.sin(0.35) * 0.8, 0.0])
+    p0 = R.RodParams(length=24.0, radius=2.0)
+    Lang = np.array([0.3, -0.2, 0.5]) * p0.inertia[1] * 0.02  # oblique to the axis
+    rods, p = _single_rod(n_sub=n_sub, q=q0, L=Lang)
+    if omega_fn is not None:
+        rods.omega = lambda r: omega_fn(rods, r)
+    for _ in range(steps):
+        rods.integrate(np.zeros((1, 3)), np.zeros((1, 3)))
+    qe = _free_top_exact(q0, Lang, p, steps)
+    err = min(np.abs(rods.q[0] - qe).max(), np.abs(rods.q[0] + qe).max())
+    return err, rods, Lang, qe
+
+
+def test_free_symmetric_top_precesses_about_L():
+    """L oblique to the axis, no torque: L is kept exactly, the axis precesses
+    about L at |L| / I_perp and the body spins about its axis at
+    (L . e)(1/I_par - 1/I_perp).  The exponential map with omega frozen over a
+    substep is first order: the error halves when the substeps double."""
+    e5, rods, Lang, qe = _free_top(5, 20)
+    e10, _, _, _ = _free_top(10, 20)
+    assert np.array_equal(rods.L[0], Lang)
+    assert e5 < 1e-3
+    assert 0.45 < e10 / e5 < 0.55
+    # the axis direction alone is within the same bound of the precessed axis
+    assert np.abs(R.axis(rods.q[0]) - R.axis(qe)).max() < 2e-3
+
+
+def test_planted_rigid_body_mistakes_are_caught():
+    """Drop the (1/I_par - 1/I_perp)(L.e)e term, or use I_par for every axis:
+    the free-top pin misses by 70x and 1000x."""
+    def no_par(rods, r):
+        return rods.L[r] / rods.p.inertia[1]
+
+    def all_par(rods, r):
+        return rods.L[r] / rods.p.inertia[0]
+
+    for fn in (no_par, all_par):
+        err, _, _, _ = _free_top(5, 20, fn)
+        assert err > 0.01  # the correct scheme is within 1e-3 (2.3e-4)
+
+
+def test_planted_position_first_order_is_caught():
+    """X updated with the old velocity (position before velocity) misses the
+    closed form of the constant-force pin."""
+    F = np.array([[0.7, -0.4, 0.25]])
+    rods, p = _single_rod()
+    X0 = rods.X[0].copy()
+
+    def integrate_x_first(F_hyd, T_hyd):
+        dt = 1.0 / p.n_sub
+        for _ in range(p.n_sub):
+            rods.X = rods.X + rods.V * dt
+            rods.V = rods.V + F_hyd / p.mass * dt
+
+    for _ in range(6):
+        integrate_x_first(F, np.zeros((1, 3)))
+    m, dt, a = 6 * p.n_sub, 1.0 / p.n_sub, F[0] / p.mass
+    Xw = X0 + a * dt * dt * m * (m + 1) / 2
+    assert np.abs(rods.X[0] - Xw).max() > 1e-5
