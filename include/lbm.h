@@ -271,8 +271,12 @@ int lb_rod_map(lb_ctx *ctx, int32_t *map_host, hipStream_t stream);
  * pos_dev: [n][3] bead positions (device, FP64).  n <= LB_NET_MAX_BEADS; at
  * most LB_NET_MAX_DEG neighbours per bead (LB_EINVAL otherwise, after the
  * outputs are written).  LB_EUNSTABLE if the residual is still above tol
- * after max_iter iterations (outputs written).  Allocates and frees its own
- * workspace; synchronises.
+ * after max_iter iterations (outputs written).
+ * workspace_dev: device scratch of at least lb_kirchhoff_workspace_bytes(n)
+ * bytes, 256-byte aligned, caller-owned (LB_EINVAL if null, misaligned or
+ * short while n > 0); nothing in it needs to be initialised and its contents
+ * mean nothing after the call.  Allocates nothing; enqueued on `stream`,
+ * then synchronises it to return the scalars.
  */
 #define LB_NET_MAX_BEADS 65536
 #define LB_NET_MAX_DEG 64
@@ -284,8 +288,10 @@ typedef struct {
     double I_tot, I_ref, kappa, rel_residual;
     int32_t iterations, edges, n_source, n_sink, max_degree;
 } lb_kirchhoff_out;
+size_t lb_kirchhoff_workspace_bytes(int32_t n);
 int lb_kirchhoff(const double *pos_dev, int32_t n, const lb_kirchhoff_spec *spec, double *V_dev, double *I_dev,
-                 lb_kirchhoff_out *out, hipStream_t stream);
+                 void *workspace_dev, size_t workspace_bytes, lb_kirchhoff_out *out, hipStream_t stream);
+
 
 /* Beads of the rods for the network and the deposit profiles: nb = max(2,
  * floor(2 h / bead_spacing + 1/2) + 1) <= 64 beads per rod evenly along its
@@ -342,7 +348,7 @@ int lb_batch_destroy(lb_batch *b);
  * channels-last: rho_A, rho_B, u_x, u_y, u_z, rod volume fraction, domain
  * mask (1 inside the lattice), fluid fraction (fluid nodes / 8).  Densities
  * are means over the fluid nodes of each 2 x 2 x 2 block; u is the block's
- * physical velocity sum (j + F/2) / sum rho over those nodes (Eq. 5 force F,
+ * physical velocity sum (j + F/2) / sum rho over those nodes (Shan-Chen force F,
  * the velocity the method reports), read off the stored post-collision state
  * as j* - F/2.  The lattice occupies cells [0, n/2) per axis (n even, n/2 <=
  * canvas size); cells outside hold gas (0.03, 1), zero velocity, mask 0 and

@@ -11,7 +11,7 @@ itself has no surrogate):
   nodes; u is the block's physical velocity, sum of (j* - F/2) over its fluid
   nodes divided by their summed density, where j* = sum_k sum_i f*_i c_i is
   the momentum of the stored post-collision state and F = F_A + F_B the
-  Shan-Chen plus body force of its densities (Eq. 5), so that with equal tau
+  Shan-Chen plus body force of its densities (the fluid step's force), so that with equal tau
   the momentum before collision is j* - F and the velocity u = (j + F/2) / rho
   the one the method reports), the rod volume
   fraction (rod nodes / 8), a domain mask (1 inside the lattice) and the
@@ -23,7 +23,7 @@ itself has no surrogate):
   renormalised; when none of the 8 corners holds fluid, the plain mean of the
   fluid-holding cells of the 4 x 4 x 4 block around them, and gas at rest
   when there is none either; then the post-collision state of those fields:
-  with F_k the force of the prolonged densities (Eq. 5), u' = u - F / (2 rho)
+  with F_k the Shan-Chen force of the prolonged densities, u' = u - F / (2 rho)
   and u_k^eq = u' + tau_k F_k / rho_k (the velocity shift of the collision),
   (u' alone where rho_k < 1e-12), f_i^k = f_i^eq(rho_k, u_k^eq) (Eq. 2) at
   fluid nodes, so that restricting
@@ -164,7 +164,7 @@ def admissible(rho, u):
 def lift(coarse, material, p):
     """Post-collision state f^k = f^eq(rho_k, u_k^eq) (Eq. 2) of the prolonged
     fields, made admissible, at fluid nodes, 0 elsewhere; u_k^eq = u - F /
-    (2 rho) + tau_k F_k / rho_k with F_k the force (Eq. 5) of the prolonged
+    (2 rho) + tau_k F_k / rho_k with F_k the Shan-Chen force of the prolonged
     densities (no half-force shift where rho vanishes)."""
     rho, u = admissible(*prolong(coarse, material))
     fluid = material == lbm.FLUID

@@ -37,6 +37,7 @@ EXPORTS = (
     "lb_deposit",
     "lb_rod_map",
     "lb_kirchhoff",
+    "lb_kirchhoff_workspace_bytes",
     "lb_rod_beads",
     "lb_batch_workspace_bytes",
     "lb_batch_create",
@@ -277,8 +278,10 @@ def load(path: str = LIB_PATH):
     lib.lb_rod_map.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.lb_rod_map.restype = ct.c_int
     lib.lb_kirchhoff.argtypes = [ct.c_void_p, ct.c_int32, P(LbKirchhoffSpec), ct.c_void_p, ct.c_void_p,
-                                 P(LbKirchhoffOut), ct.c_void_p]
+                                 ct.c_void_p, ct.c_size_t, P(LbKirchhoffOut), ct.c_void_p]
     lib.lb_kirchhoff.restype = ct.c_int
+    lib.lb_kirchhoff_workspace_bytes.argtypes = [ct.c_int32]
+    lib.lb_kirchhoff_workspace_bytes.restype = ct.c_size_t
     lib.lb_rod_beads.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_int32, P(ct.c_int32), ct.c_void_p]
     lib.lb_rod_beads.restype = ct.c_int
     lib.lb_batch_workspace_bytes.argtypes = [P(ct.c_void_p), ct.c_int32]

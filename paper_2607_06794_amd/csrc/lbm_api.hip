@@ -1392,35 +1392,23 @@ int lb_batch_destroy(lb_batch *b) {
 // ---------------------------------------------------------------------------
 namespace {
 
-struct DevBuf {  // workspace of one call, freed on every return path
-    void *p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
-
-}  // namespace
-
-extern "C" {
-
-int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I, lb_kirchhoff_out *out,
-                 hipStream_t stream) {
+int kirchhoff_check(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I,
+                    lb_kirchhoff_out *out) {
     if (!s || !out || n < 0) return fail(LB_EINVAL, "null argument or negative bead count");
     if (n > 0 && (!pos || !V || !I)) return fail(LB_EINVAL, "null bead, potential or current buffer");
     if (n > LB_NET_MAX_BEADS) return fail(LB_EINVAL, "at most %d beads", LB_NET_MAX_BEADS);
     if (!(s->r_c > 0.0) || !std::isfinite(s->r_c) || !std::isfinite(s->x_src) || !std::isfinite(s->x_snk) ||
         !(s->x_src < s->x_snk) || !std::isfinite(s->dV) || !(s->tol > 0.0) || s->max_iter < 0)
         return fail(LB_EINVAL, "bad network spec (r_c > 0, x_src < x_snk, tol > 0, max_iter >= 0, finite values)");
+    return LB_OK;
+}
+
+// the solve on a workspace of at least net_workspace_bytes(n) bytes
+int kirchhoff_run(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I, void *ws,
+                  lb_kirchhoff_out *out, hipStream_t stream) {
     memset(out, 0, sizeof *out);
     out->I_ref = s->dV / (s->x_snk - s->x_src);
     if (n == 0) return LB_OK;
-    const size_t nn = size_t(n);
-    const size_t b_nbr = nn * NET_DEG * sizeof(int), b_g = nn * NET_DEG * sizeof(double);
-    const size_t b_vec = nn * sizeof(double), b_deg = nn * sizeof(int);
-    const size_t bytes = b_g + 5 * b_vec + 8 * sizeof(double) + b_nbr + 2 * b_deg + 4 * sizeof(int);
-    DevBuf ws;
-    HIP_TRY(hipMalloc(&ws.p, bytes), "network workspace");
-    char *w = static_cast<char *>(ws.p);
     NetArgs a{};
     a.pos = pos;
     a.n = n;
@@ -1432,20 +1420,7 @@ int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, doubl
     a.max_iter = s->max_iter;
     a.V = V;
     a.I = I;
-    // doubles first (8-byte aligned from the allocation), then the ints
-    a.g = reinterpret_cast<double *>(w);
-    w += b_g;
-    a.diag = reinterpret_cast<double *>(w);
-    a.r = a.diag + nn;
-    a.z = a.r + nn;
-    a.p = a.z + nn;
-    a.q = a.p + nn;
-    a.out = a.q + nn;
-    w += 5 * b_vec + 8 * sizeof(double);
-    a.nbr = reinterpret_cast<int *>(w);
-    a.deg = a.nbr + nn * NET_DEG;
-    a.cls = a.deg + nn;
-    a.cnt = a.cls + nn;
+    net_carve(a, ws);
     HIP_TRY(launch_net_edges(a, stream), "network edges");
     HIP_TRY(launch_net_solve(a, stream), "network solve");
     double ho[3];
@@ -1466,6 +1441,26 @@ int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, doubl
     if (!(ho[1] <= s->tol))
         return fail(LB_EUNSTABLE, "network solve: relative residual %.3e after %d iterations", ho[1], out->iterations);
     return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_kirchhoff_workspace_bytes(int32_t n) { return n <= 0 ? 0 : net_workspace_bytes(size_t(n)); }
+
+int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I, void *ws,
+                 size_t ws_bytes, lb_kirchhoff_out *out, hipStream_t stream) {
+    const int rc = kirchhoff_check(pos, n, s, V, I, out);
+    if (rc != LB_OK) return rc;
+    if (n > 0) {
+        if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+            return fail(LB_EINVAL, "network workspace must be a non-null 256-byte aligned device pointer");
+        if (ws_bytes < net_workspace_bytes(size_t(n)))
+            return fail(LB_EINVAL, "network workspace of %zu bytes, %zu needed for %d beads", ws_bytes,
+                        net_workspace_bytes(size_t(n)), int(n));
+    }
+    return kirchhoff_run(pos, n, s, V, I, ws, out, stream);
 }
 
 int lb_rod_beads(lb_ctx *c, double spacing, double *pos, int32_t cap, int32_t *n_out, hipStream_t stream) {

@@ -171,6 +171,16 @@ struct NetArgs {
     int *cnt;      // max degree, source beads, sink beads, stored directed edges
     double *out;   // I_tot, relative residual, iterations
 };
+// workspace of one network solve of n beads: neighbour conductances [n][NET_DEG],
+// five CG vectors, 8 result doubles, neighbour indices [n][NET_DEG], degree
+// and class per bead, 4 counters; rounded up to 256 bytes
+constexpr size_t net_workspace_bytes(size_t n) {
+    return ((n * NET_DEG * sizeof(double) + 5 * n * sizeof(double) + 8 * sizeof(double) + n * NET_DEG * sizeof(int) +
+             2 * n * sizeof(int) + 4 * sizeof(int)) + 255) / 256 * 256;
+}
+// carve NetArgs' workspace pointers out of ws (256-byte aligned, at least
+// net_workspace_bytes(a.n) bytes)
+void net_carve(NetArgs &a, void *ws);
 hipError_t launch_net_edges(const NetArgs &a, hipStream_t s);
 hipError_t launch_net_solve(const NetArgs &a, hipStream_t s);
 hipError_t launch_rod_beads(const double *rods, int n_rods, int nb, double half, double *pos, hipStream_t s);

@@ -18,6 +18,25 @@
 
 namespace lbm {
 
+void net_carve(NetArgs &a, void *ws) {
+    const size_t nn = size_t(a.n);
+    char *w = static_cast<char *>(ws);
+    // doubles first (8-byte aligned from the 256-byte aligned base), then the ints
+    a.g = reinterpret_cast<double *>(w);
+    w += nn * NET_DEG * sizeof(double);
+    a.diag = reinterpret_cast<double *>(w);
+    a.r = a.diag + nn;
+    a.z = a.r + nn;
+    a.p = a.z + nn;
+    a.q = a.p + nn;
+    a.out = a.q + nn;
+    w += 5 * nn * sizeof(double) + 8 * sizeof(double);
+    a.nbr = reinterpret_cast<int *>(w);
+    a.deg = a.nbr + nn * NET_DEG;
+    a.cls = a.deg + nn;
+    a.cnt = a.cls + nn;
+}
+
 namespace {
 
 constexpr int NET_TB = 256;   // threads per work-group of the neighbour scan

@@ -848,7 +848,7 @@ __global__ void to_bf16_kernel(const float *x, int64_t n, uint16_t *y) {
 // restriction and lift
 //
 // Both work with the physical velocity u = (j + F/2) / rho of the method
-// (Eq. 5 force F, velocity shift of the collision).  The stored state is the
+// (Shan-Chen force F of the fused step, velocity shift of the collision).  The stored state is the
 // collision output f*, whose momentum is j* = j + F for equal relaxation
 // times, so a restriction reads u = (j* - F/2) / rho with F from the stored
 // densities, and a lift writes f*_k = f^eq(rho_k, u - F/(2 rho) + tau_k F_k /

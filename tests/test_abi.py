@@ -167,3 +167,24 @@ def test_sink_parameters_and_workspace_on_host(lib):
         assert init_rc(q.to_c()) == _lib.LB_ENOTSUP, q
     for bad in ((-1e-4, 0.01, 8.0), (1e-4, -0.01, 8.0), (1e-4, 0.01, 0.0), (float("nan"), 0.01, 8.0)):
         assert init_rc(LatticeParams(shape=shape, prec="f32", sink=bad).to_c()) == _lib.LB_EINVAL, bad
+
+
+def test_network_workspace_on_host(lib):
+    """lb_kirchhoff's workspace query and argument checks (no device call is
+    reached: every case fails validation first)."""
+    nb = [lib.lb_kirchhoff_workspace_bytes(n) for n in (0, 1, 100, 4200)]
+    assert nb[0] == 0 and all(b % 256 == 0 for b in nb)
+    # per bead: 64 conductances (8 B) and 64 indices (4 B), five vectors, degree and class
+    per = 64 * 12 + 5 * 8 + 2 * 4
+    assert 100 * per <= nb[2] < 100 * per + 256 + 96
+    assert 4200 * per <= nb[3] < 4200 * per + 256 + 96
+    spec = _lib.LbKirchhoffSpec(2.1, 5.0, 25.0, 1.0, 1e-12, 100)
+    out = _lib.LbKirchhoffOut()
+    fake = ct.c_void_p(4096)
+    # workspace missing, misaligned, too small
+    assert lib.lb_kirchhoff(fake, 100, ct.byref(spec), fake, fake, None, nb[2], ct.byref(out), None) == _lib.LB_EINVAL
+    assert lib.lb_kirchhoff(fake, 100, ct.byref(spec), fake, fake, ct.c_void_p(4096 + 8), nb[2], ct.byref(out),
+                            None) == _lib.LB_EINVAL
+    assert lib.lb_kirchhoff(fake, 100, ct.byref(spec), fake, fake, fake, nb[2] - 256, ct.byref(out),
+                            None) == _lib.LB_EINVAL
+    assert "workspace" in lib.lb_last_error().decode()

@@ -259,7 +259,7 @@ def _two_phase(shape, seed):
 
 def test_restrict_velocity_is_the_physical_velocity_of_the_collision():
     # the stored state after a step is the collision output of moments (rho,
-    # j) under the force F (Eq. 5); the canvas velocity must be the block
+    # j) under the Shan-Chen force F; the canvas velocity must be the block
     # mean of the physical velocity (j + F/2) / rho of that collision,
     # although restriction sees only f* (a dropped or flipped F/2 fails)
     shape = (10, 12, 14)
