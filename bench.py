@@ -317,13 +317,14 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     # 32), the speed bit alone (4: also set by the near-empty layer under the
     # reservoir), or nothing
     status_kinds = {
-        "clear": sum(1 for st in lat_status if st == 0),
-        "speed_only": sum(1 for st in lat_status if st == 4),
+        "clear": sum(1 for st in lat_status if st & ~64 == 0),
+        "speed_only": sum(1 for st in lat_status if st & ~64 == 4),
+        "far_refill_notice": sum(1 for st in lat_status if st & 64),
         "rod_limit": sum(1 for st in lat_status if st & 56 and not st & 3),
         "nonpositive_density": sum(1 for st in lat_status if st & 2 and not st & 1),
         "nan": sum(1 for st in lat_status if st & 1),
     }
-    n_unstable = int(sum(1 for st in lat_status if st & ~4))
+    n_unstable = int(sum(1 for st in lat_status if st & ~(4 | 64)))  # 64: far-refill notice
     out = {
         "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
         "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),

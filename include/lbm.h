@@ -37,7 +37,7 @@
  *    lb_last_error() returns a thread-local message for the last failure.
  *    Faults detected inside kernels (NaN, non-positive total density,
  *    |u| > 0.3, rod limits) set a device status word that lb_observables
- *    reports as LB_EUNSTABLE.
+ *    reports as LB_EUNSTABLE (notice bits alone do not).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -130,7 +130,10 @@ typedef struct {
     uint32_t status;       /* device status bits (1 NaN, 2 rho <= 0, 4 |u| > 0.3,
                               8 a rod point moved >= 0.9 in one step, 16 a rod
                               reached a wall, the reservoir or a closed end,
-                              32 a rod's surface or neighbour list overflowed) */
+                              32 a rod's surface or neighbour list overflowed;
+                              notice, not a fault: 64 a node a rod uncovered
+                              had no fluid neighbour and took the mean density
+                              of a farther ring x + s c_i, 2 <= s <= ceil(2R)+2) */
     double solid[2];       /* mass of component k moved from the fluid into rods */
     double rod_momentum[3];/* sum over rods of M V */
 } lb_obs;

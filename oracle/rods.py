@@ -30,7 +30,10 @@ bounce-back on every boundary link:
 * Re-mask after the move: a node the rod now covers gives its fluid mass to
   the solid-exchange ledger and its momentum to the rod; a node it uncovers
   gets f^eq(rho_bar, u_b) with rho_bar the mean density of its fluid
-  neighbours, paid for by the rod and the ledger.  All transfers of one
+  neighbours (fluid before and after the move), paid for by the rod and the
+  ledger.  A node with no such neighbour -- a pocket enclosed by touching
+  capsules -- takes the mean over the nearest ring x + s c_i (s = 2, 3, ...,
+  up to one more than a capsule's diameter plus one) that has fluid nodes.  All transfers of one
   re-mask use the rod state right after the substeps and are applied to the
   rod together.
 
@@ -326,6 +329,14 @@ class Rods:
 # --------------------------------------------------------------------------
 
 
+def refill_reach(radius):
+    """Farthest ring searched for the fluid neighbours of an uncovered node:
+    one more than a capsule's diameter plus one, so that a pocket between
+    touching capsules always reaches the fluid around them."""
+    return int(np.ceil(2.0 * radius)) + 2
+
+
+
 class CoupledRun:
     """Fluid (oracle.lbm) plus rods: the coupled step of the drying problem.
 
@@ -391,6 +402,37 @@ class CoupledRun:
                     dP[r] += dp
                     dT[r] += np.cross(min_image(xb - rods.X[r], rods.box, rods.periodic), dp)
         return dP, dT, dsolid
+
+    def refill_density(self, node, stay_fluid, rho_now, reach):
+        """rho_bar of an uncovered node (x, y, z): the mean density over the
+        nodes x + c_i (i = 1..18) that are fluid before and after the move; a
+        node with none of them (a pocket enclosed by touching capsules) takes
+        the mean over the first ring x + s c_i, s = 2 .. reach, that holds any
+        (positions beyond a closed end of a non-periodic direction are
+        skipped).  Returns (rho_bar[2], s) with s = 0 and rho_bar = 0 when
+        no ring up to `reach` holds a fluid node."""
+        nz, ny, nx = stay_fluid.shape
+        x, y, z = node
+        per = self.fp.periodic
+        for s in range(1, reach + 1):
+            acc = np.zeros(2)
+            cnt = 0
+            for i in range(1, lbm.Q):
+                q = []
+                for v, ci, n, pp in ((z, lbm.C[i][2], nz, per[2]), (y, lbm.C[i][1], ny, per[1]),
+                                     (x, lbm.C[i][0], nx, per[0])):
+                    w = v + s * int(ci)
+                    if pp:
+                        w %= n
+                    elif not 0 <= w < n:
+                        break
+                    q.append(w)
+                if len(q) == 3 and stay_fluid[q[0], q[1], q[2]]:
+                    acc += rho_now[:, q[0], q[1], q[2]]
+                    cnt += 1
+            if cnt:
+                return acc / cnt, s
+        return np.zeros(2), 0
 
     def step(self, n=1):
         for _ in range(n):
@@ -470,18 +512,13 @@ class CoupledRun:
             dL[r] += np.cross(min_image(pos - rods.X[r], rods.box, rods.periodic), mom)
             f[:, :, z, y, x] = 0.0
         rho_now = np.array([f[k].sum(axis=0) for k in range(2)])
+        far = 0
+        reach = refill_reach(rods.p.radius)
         for z, y, x in zip(*np.nonzero(uncovered)):
             r = old_rid[z, y, x]
             pos = np.array([x, y, z], dtype=np.float64)
-            acc = np.zeros(2)
-            cnt = 0
-            for i in range(1, lbm.Q):
-                c = lbm.C[i]
-                qz, qy, qx = (z + c[2]) % nz, (y + c[1]) % ny, (x + c[0]) % nx
-                if stay_fluid[qz, qy, qx]:
-                    acc += rho_now[:, qz, qy, qx]
-                    cnt += 1
-            rbar = acc / cnt if cnt else np.zeros(2)
+            rbar, s_used = self.refill_density((x, y, z), stay_fluid, rho_now, reach)
+            far += s_used > 1
             ub = rods.velocity_at(r, pos)
             mom = np.zeros(3)
             for k in range(2):
@@ -496,7 +533,8 @@ class CoupledRun:
         self.material = np.where(new_rid >= 0, lbm.ROD, self.static).astype(np.uint8)
         self.f = f
         self.t += 1
-        self.last = {"dP": dP, "dT": dT, "covered": int(covered.sum()), "uncovered": int(uncovered.sum())}
+        self.last = {"dP": dP, "dT": dT, "covered": int(covered.sum()), "uncovered": int(uncovered.sum()),
+                     "far_refills": int(far)}
 
     # ------------------------------------------------------------ totals --
     def fluid_mass(self):

@@ -656,7 +656,9 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     out->solid[0] = rs[0];
     out->solid[1] = rs[1];
     for (int q = 0; q < 3; ++q) out->rod_momentum[q] = rs[2 + q];
-    if (st) return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3, 8 rod motion, 16 rod at a wall, 32 rod list)", st);
+    if (st & ~ST_NOTICES)
+        return fail(LB_EUNSTABLE, "device status word 0x%x (1 NaN, 2 rho <= 0, 4 |u| > 0.3, 8 rod motion, 16 rod at a "
+                                  "wall, 32 rod list; 64 far refill is a notice)", st);
     return LB_OK;
 }
 

@@ -48,6 +48,10 @@ __host__ __device__ inline bool is_static_wall(uint8_t id) { return id >= 2 && i
 
 // status bits
 constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u, ST_ROD = 8u, ST_ROD_WALL = 16u, ST_ROD_LIST = 32u;
+// notice, not a fault: an uncovered node had no fluid neighbour and took its
+// densities from a farther ring (a pocket enclosed by touching capsules)
+constexpr unsigned ST_REFILL_FAR = 64u;
+constexpr unsigned ST_NOTICES = ST_REFILL_FAR;
 
 // ---------------------------------------------------------------------------
 // storage codecs: S = element type in HBM, C = compute type in registers.

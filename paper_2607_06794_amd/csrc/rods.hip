@@ -777,7 +777,11 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     if (unc) un_node[slot] = n;
     __syncthreads();
     // refill: f = f^eq(rho_bar, u_b), rho_bar = mean over the neighbours that
-    // are fluid before and after the move
+    // are fluid before and after the move.  A node with none of them (a
+    // pocket enclosed by touching capsules) takes the mean over the first
+    // ring x + s c_i, s = 2 .. reach, that holds any, and raises the notice
+    // bit ST_REFILL_FAR.
+    const int reach = int(ceil(2.0 * a.radius)) + 2;
     for (int e = wv; e < tot; e += RB / 64) {
         const int64_t un = un_node[e];
         const int ux = int(un % a.nx), uy = int((un / a.nx) % a.ny), uz = int(un / (int64_t(a.nx) * a.ny));
@@ -787,24 +791,33 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
         const double rref_k = k ? a.rho_ref[1] : a.rho_ref[0];
         double val = 0.0;
         bool ok = false, wall = false;
-        if (lane < 2 * (Q - 1)) {
-            int xx = ux + cx(i), yy = uy + cy(i), zz = uz + cz(i);
-            if (wrap_coord(xx, a.nx, a.px) && wrap_coord(yy, a.ny, a.py) && wrap_coord(zz, a.nz, a.pz)) {
-                const int64_t q = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-                const uint8_t mq = a.mat[q] & MAT_ID_MASK;
-                wall = is_static_wall(mq);
-                ok = mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0;
-                if (ok && bt.rho_fresh) {
-                    val = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
-                } else if (ok) {
-                    double s = 0.0;
+        int cnt = 0;
+        for (int sr = 1; sr <= reach; ++sr) {  // wave-uniform: ends at the first ring with fluid
+            val = 0.0;
+            ok = false;
+            if (lane < 2 * (Q - 1)) {
+                int xx = ux + sr * cx(i), yy = uy + sr * cy(i), zz = uz + sr * cz(i);
+                if (wrap_coord(xx, a.nx, a.px) && wrap_coord(yy, a.ny, a.py) && wrap_coord(zz, a.nz, a.pz)) {
+                    const int64_t q = (int64_t(zz) * a.ny + yy) * a.nx + xx;
+                    const uint8_t mq = a.mat[q] & MAT_ID_MASK;
+                    if (sr == 1) wall = is_static_wall(mq);
+                    ok = mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0;
+                    if (ok && bt.rho_fresh) {
+                        val = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
+                    } else if (ok) {
+                        double s = 0.0;
 #pragma unroll
-                    for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
-                    val = s;
+                        for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
+                        val = s;
+                    }
                 }
             }
+            cnt = __popcll(__ballot(ok && k == 0));
+            if (cnt) {
+                if (sr > 1 && lane == 0) atomicOr(a.status, ST_REFILL_FAR);
+                break;
+            }
         }
-        const int cnt = __popcll(__ballot(ok && k == 0));
         const bool near_wall = __ballot(wall) != 0;
         double rb[2] = {wave_sum_d(k == 0 ? val : 0.0), wave_sum_d(k == 1 ? val : 0.0)};
         if (cnt) {

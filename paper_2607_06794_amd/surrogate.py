@@ -399,7 +399,7 @@ def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True)
             restrict(lat, D, H, W, xf[i, s], xb[i, s])
             st = int(lat.observables(allow_unstable=True)["status"])
             u = xf[i, s].view(P, 8)[:, 2:5]
-            healthy[i, s] = (st & ~4) == 0 and bool(torch.isfinite(u).all()) and float(u.abs().max()) <= 0.15
+            healthy[i, s] = (st & ~(4 | 64)) == 0 and bool(torch.isfinite(u).all()) and float(u.abs().max()) <= 0.15
     torch.cuda.synchronize()
     return xf, xb, healthy
 

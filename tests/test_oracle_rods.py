@@ -439,3 +439,110 @@ def test_planted_position_first_order_is_caught():
     m, dt, a = 6 * p.n_sub, 1.0 / p.n_sub, F[0] / p.mass
     Xw = X0 + a * dt * dt * m * (m + 1) / 2
     assert np.abs(rods.X[0] - Xw).max() > 1e-5
+
+
+# --------------------------------------------------------------------------
+# refill of uncovered nodes: enclosed pockets between touching capsules
+# --------------------------------------------------------------------------
+
+
+def _stub_run(periodic):
+    run = R.CoupledRun.__new__(R.CoupledRun)
+    run.fp = lbm.Params(shape=(9, 9, 9), periodic=periodic)
+    return run
+
+
+def test_refill_density_rings_by_hand():
+    shape = (9, 9, 9)
+    stay = np.zeros(shape, bool)
+    rho = np.zeros((2,) + shape)
+    run = _stub_run((True, True, True))
+    x, y, z = 4, 4, 4
+    # first ring: two fluid neighbours -> their mean, s = 1
+    stay[z, y, x + 1] = stay[z + 1, y + 1, x] = True
+    rho[:, z, y, x + 1] = (0.9, 0.05)
+    rho[:, z + 1, y + 1, x] = (1.1, 0.01)
+    rb, s = run.refill_density((x, y, z), stay, rho, 6)
+    assert s == 1 and np.allclose(rb, (1.0, 0.03), rtol=1e-15)
+    # none in the first ring, three in the second (x + 2 c_i), one node off
+    # every ray (x + (1, 2, 0)) ignored
+    stay[:] = False
+    for (dx, dy, dz), v in (((2, 0, 0), 0.8), ((0, -2, 2), 1.0), ((-2, 2, 0), 1.2), ((1, 2, 0), 9.0)):
+        stay[z + dz, y + dy, x + dx] = True
+        rho[:, z + dz, y + dy, x + dx] = (v, 0.1 * v)
+    rb, s = run.refill_density((x, y, z), stay, rho, 6)
+    assert s == 2 and np.allclose(rb, (1.0, 0.1), rtol=1e-15)
+    # periodic wrap at s = 3 through the low x face (node at x = 1, fluid at x = 7)
+    stay[:] = False
+    stay[z, y, 7] = True
+    rho[:, z, y, 7] = (0.7, 0.2)
+    rb, s = run.refill_density((1, y, z), stay, rho, 6)
+    assert s == 3 and np.array_equal(rb, (0.7, 0.2))
+    rb, s = run.refill_density((1, y, z), stay, rho, 2)
+    assert s == 0 and np.array_equal(rb, (0.0, 0.0))
+    # a closed z end is not wrapped: the node at z = 1 sees nothing through z < 0
+    closed = _stub_run((True, True, False))
+    stay[:] = False
+    stay[8, 4, 4] = True  # would be x - 2 c_z through a wrap from z = 1
+    rho[:, 8, 4, 4] = (1.0, 1.0)
+    assert closed.refill_density((4, 4, 1), stay, rho, 6)[1] == 0
+    assert run.refill_density((4, 4, 1), stay, rho, 6)[1] == 2
+
+
+POCKET = dict(
+    X=[[13.641862, 8.477799, 9.227982], [9.837508, 11.063572, 10.704474], [10.892625, 11.246163, 8.814955],
+       [9.135597, 11.887222, 6.753526], [13.61286, 10.627683, 7.359403]],
+    Q=[[0.873668, 0.206958, -0.44031, 0.0], [0.867072, -0.337488, 0.366453, 0.0], [0.873134, -0.474117, -0.113356, 0.0],
+       [0.584921, -0.700266, 0.409261, 0.0], [0.829011, 0.506635, -0.236775, 0.0]],
+    V0=[0.495753, -0.189351, 0.279956])
+
+
+def pocket_run():
+    """Five overlapping capsules (heavy, no pair forces) in uniform liquid; the
+    first slides out of a node that the other four enclose, so the node has no
+    fluid neighbour when it is uncovered."""
+    shape = (18, 18, 22)
+    rho = np.zeros((2,) + shape)
+    rho[0], rho[1] = 1.0, 0.03
+    mat = np.zeros(shape, np.uint8)
+    psi = np.zeros((9, 2))
+    psi[lbm.ROD] = (0.6, 0.25)
+    fp = lbm.Params(shape=shape, G=3.6, psi_solid=psi)
+    q = np.array(POCKET["Q"])
+    q /= np.linalg.norm(q, axis=1)[:, None]
+    V = np.zeros((5, 3))
+    V[0] = POCKET["V0"]
+    p = R.RodParams(length=12.0, radius=2.0, wall_z=None, eps_rep=1e-12, eps_att=0.0, rho_rod=1e6)
+    rods = R.Rods(POCKET["X"], q, V, np.zeros((5, 3)), p, (22, 18, 18), (1, 1, 1))
+    return R.CoupledRun(rho, mat, fp, rods)
+
+
+def test_enclosed_pocket_refill_keeps_every_fluid_node_filled():
+    run = pocket_run()
+    M0 = run.fluid_mass()
+    P0 = run.total_momentum()
+    run.step()
+    assert run.last["uncovered"] > 0 and run.last["far_refills"] >= 1
+    fl = run.material == lbm.FLUID
+    rho = np.array([run.f[k].sum(axis=0) for k in range(2)])
+    assert np.all(rho[:, fl] > 0.0)
+    assert np.allclose(run.fluid_mass() + run.solid, M0, rtol=1e-13)
+    assert np.abs(run.total_momentum() - P0).max() <= 1e-14 * np.abs(P0).max()  # heavy rods: round-off of |P|
+
+
+def test_planted_first_ring_only_refill_leaves_an_empty_node(monkeypatch):
+    """The first-ring rule alone gives the enclosed node rho_bar = 0: an empty
+    fluid node, which the next fluid step cannot fill while all its
+    neighbours are rod nodes -- the non-positive density the sweep droplets
+    raised."""
+    right = R.CoupledRun.refill_density
+
+    def first_ring_only(self, node, stay, rho, reach):
+        return right(self, node, stay, rho, 1)
+
+    monkeypatch.setattr(R.CoupledRun, "refill_density", first_ring_only)
+    run = pocket_run()
+    run.step()
+    fl = run.material == lbm.FLUID
+    rho = np.array([run.f[k].sum(axis=0) for k in range(2)])
+    assert np.any(rho[0][fl] == 0.0) and np.any(rho[1][fl] == 0.0)
