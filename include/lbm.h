@@ -295,6 +295,22 @@ size_t lb_kirchhoff_workspace_bytes(int32_t n);
 int lb_kirchhoff(const double *pos_dev, int32_t n, const lb_kirchhoff_spec *spec, double *V_dev, double *I_dev,
                  void *workspace_dev, size_t workspace_bytes, lb_kirchhoff_out *out, hipStream_t stream);
 
+/*
+ * lb_kirchhoff without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, outputs, errors and
+ * synchronisation as lb_kirchhoff; the workspace is a fixed device array of
+ * lb_kirchhoff_workspace_bytes(LB_NET_NOALLOC_MAX_BEADS) bytes (about 6.7 MB)
+ * that each GPU holds from the first call until the process ends.  n above
+ * LB_NET_NOALLOC_MAX_BEADS returns LB_EINVAL.  The stream must belong to the
+ * current device.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other streams, other host threads) race and give
+ * undefined results.  The kernels write every scratch word before reading
+ * it, so the previous call's contents do not matter.
+ */
+#define LB_NET_NOALLOC_MAX_BEADS 8192
+int lb_kirchhoff_noalloc(const double *pos_dev, int32_t n, const lb_kirchhoff_spec *spec, double *V_dev,
+                         double *I_dev, lb_kirchhoff_out *out, hipStream_t stream);
 
 /* Beads of the rods for the network and the deposit profiles: nb = max(2,
  * floor(2 h / bead_spacing + 1/2) + 1) <= 64 beads per rod evenly along its

@@ -15,6 +15,7 @@ LB_OK, LB_EINVAL, LB_ENOTSUP, LB_EHIP, LB_EUNSTABLE, LB_EPLACE = 0, -1, -2, -3, 
 LB_F64, LB_F32, LB_F16DEV, LB_BF16DEV = 0, 1, 2, 3
 LB_NMAT = 9
 LB_MAX_RODS = 512
+LB_NET_NOALLOC_MAX_BEADS = 8192  # include/lbm.h
 
 # Every exported symbol declared in include/lbm.h
 EXPORTS = (
@@ -38,6 +39,7 @@ EXPORTS = (
     "lb_rod_map",
     "lb_kirchhoff",
     "lb_kirchhoff_workspace_bytes",
+    "lb_kirchhoff_noalloc",
     "lb_rod_beads",
     "lb_batch_workspace_bytes",
     "lb_batch_create",
@@ -282,6 +284,9 @@ def load(path: str = LIB_PATH):
     lib.lb_kirchhoff.restype = ct.c_int
     lib.lb_kirchhoff_workspace_bytes.argtypes = [ct.c_int32]
     lib.lb_kirchhoff_workspace_bytes.restype = ct.c_size_t
+    lib.lb_kirchhoff_noalloc.argtypes = [ct.c_void_p, ct.c_int32, P(LbKirchhoffSpec), ct.c_void_p, ct.c_void_p,
+                                         P(LbKirchhoffOut), ct.c_void_p]
+    lib.lb_kirchhoff_noalloc.restype = ct.c_int
     lib.lb_rod_beads.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_int32, P(ct.c_int32), ct.c_void_p]
     lib.lb_rod_beads.restype = ct.c_int
     lib.lb_batch_workspace_bytes.argtypes = [P(ct.c_void_p), ct.c_int32]

@@ -1465,6 +1465,21 @@ int lb_kirchhoff(const double *pos, int32_t n, const lb_kirchhoff_spec *s, doubl
     return kirchhoff_run(pos, n, s, V, I, ws, out, stream);
 }
 
+int lb_kirchhoff_noalloc(const double *pos, int32_t n, const lb_kirchhoff_spec *s, double *V, double *I,
+                         lb_kirchhoff_out *out, hipStream_t stream) {
+    const int rc = kirchhoff_check(pos, n, s, V, I, out);
+    if (rc != LB_OK) return rc;
+    if (n > LB_NET_NOALLOC_MAX_BEADS)
+        return fail(LB_EINVAL, "lb_kirchhoff_noalloc takes at most %d beads (%d given); use lb_kirchhoff with a "
+                               "caller workspace", LB_NET_NOALLOC_MAX_BEADS, int(n));
+    void *scratch = nullptr;
+    size_t bytes = 0;
+    HIP_TRY(net_static_scratch(&scratch, &bytes), "network scratch address");
+    if (n > 0 && bytes < net_workspace_bytes(size_t(n)))
+        return fail(LB_EINVAL, "network scratch of %zu bytes too small", bytes);
+    return kirchhoff_run(pos, n, s, V, I, scratch, out, stream);
+}
+
 int lb_rod_beads(lb_ctx *c, double spacing, double *pos, int32_t cap, int32_t *n_out, hipStream_t stream) {
     if (!c || !n_out || cap < 0 || !(spacing > 0.0) || !std::isfinite(spacing))
         return fail(LB_EINVAL, "null argument, negative capacity or bad bead spacing");

@@ -183,6 +183,9 @@ constexpr size_t net_workspace_bytes(size_t n) {
 void net_carve(NetArgs &a, void *ws);
 hipError_t launch_net_edges(const NetArgs &a, hipStream_t s);
 hipError_t launch_net_solve(const NetArgs &a, hipStream_t s);
+// device address of the fixed network scratch on the current device (looked
+// up once per device) and its size in bytes
+hipError_t net_static_scratch(void **ptr, size_t *bytes);
 hipError_t launch_rod_beads(const double *rods, int n_rods, int nb, double half, double *pos, hipStream_t s);
 hipError_t launch_rod_map(const uint8_t *mat, int nx, int ny, int nz, int32_t *map, hipStream_t s);
 

@@ -13,10 +13,40 @@
 //    is bounded by the caller's iteration limit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+#include "lbm.h"
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
+
+// Fixed scratch of lb_kirchhoff_noalloc: the workspace of a network of up to
+// LB_NET_NOALLOC_MAX_BEADS beads, one copy per GPU for the life of the
+// process.  Host code never uses this name as an address (on the host it is a
+// stand-in symbol); net_static_scratch() returns the device address.
+static __device__ __align__(256) char net_scratch[net_workspace_bytes(LB_NET_NOALLOC_MAX_BEADS)];
+
+hipError_t net_static_scratch(void **ptr, size_t *bytes) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(net_scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = sizeof(net_scratch);
+    return hipSuccess;
+}
 
 void net_carve(NetArgs &a, void *ws) {
     const size_t nn = size_t(a.n);

@@ -335,12 +335,13 @@ class Lattice:
 
 
 def kirchhoff(pos, r_c: float, x_src: float, x_snk: float, dV: float = 1.0, tol: float = 1e-12,
-              max_iter: int = 20000, stream=None) -> dict:
+              max_iter: int = 20000, stream=None, noalloc: bool = False) -> dict:
     """Resistor network of a deposit (lb_kirchhoff, Eqs. 15-18) for bead
     positions `pos`, a CUDA FP64 tensor [n, 3]: potentials V and node
     currents I (CUDA tensors), I_tot, I_ref, kappa and the solve's counts.
     The solve's workspace is a torch tensor sized by
-    lb_kirchhoff_workspace_bytes."""
+    lb_kirchhoff_workspace_bytes; noalloc=True calls lb_kirchhoff_noalloc,
+    which uses the library's fixed device scratch instead."""
     import torch
 
     lib = _lib.load()
@@ -351,12 +352,16 @@ def kirchhoff(pos, r_c: float, x_src: float, x_snk: float, dV: float = 1.0, tol:
     spec = _lib.LbKirchhoffSpec(float(r_c), float(x_src), float(x_snk), float(dV), float(tol), int(max_iter))
     out = _lib.LbKirchhoffOut()
     st = torch.cuda.current_stream(pos.device) if stream is None else stream
-    nb = int(lib.lb_kirchhoff_workspace_bytes(n))
-    ws = torch.empty(nb + 256, dtype=torch.uint8, device=pos.device)
-    wp = (ws.data_ptr() + 255) & ~255
-    _lib.check(lib.lb_kirchhoff(ct.c_void_p(pos.data_ptr()), n, ct.byref(spec), ct.c_void_p(V.data_ptr()),
-                                ct.c_void_p(I.data_ptr()), ct.c_void_p(wp if n else None), nb, ct.byref(out),
-                                _stream_ptr(st)))
+    if noalloc:
+        _lib.check(lib.lb_kirchhoff_noalloc(ct.c_void_p(pos.data_ptr()), n, ct.byref(spec), ct.c_void_p(V.data_ptr()),
+                                            ct.c_void_p(I.data_ptr()), ct.byref(out), _stream_ptr(st)))
+    else:
+        nb = int(lib.lb_kirchhoff_workspace_bytes(n))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=pos.device)
+        wp = (ws.data_ptr() + 255) & ~255
+        _lib.check(lib.lb_kirchhoff(ct.c_void_p(pos.data_ptr()), n, ct.byref(spec), ct.c_void_p(V.data_ptr()),
+                                    ct.c_void_p(I.data_ptr()), ct.c_void_p(wp if n else None), nb, ct.byref(out),
+                                    _stream_ptr(st)))
     return {"V": V[:n], "I": I[:n], "I_tot": out.I_tot, "I_ref": out.I_ref, "kappa": out.kappa,
             "rel_residual": out.rel_residual, "iterations": out.iterations, "edges": out.edges,
             "n_source": out.n_source, "n_sink": out.n_sink, "max_degree": out.max_degree}

@@ -169,7 +169,7 @@ def test_sink_parameters_and_workspace_on_host(lib):
         assert init_rc(LatticeParams(shape=shape, prec="f32", sink=bad).to_c()) == _lib.LB_EINVAL, bad
 
 
-def test_network_workspace_on_host(lib):
+def test_network_workspace_and_limits_on_host(lib):
     """lb_kirchhoff's workspace query and argument checks (no device call is
     reached: every case fails validation first)."""
     nb = [lib.lb_kirchhoff_workspace_bytes(n) for n in (0, 1, 100, 4200)]
@@ -188,3 +188,10 @@ def test_network_workspace_on_host(lib):
     assert lib.lb_kirchhoff(fake, 100, ct.byref(spec), fake, fake, fake, nb[2] - 256, ct.byref(out),
                             None) == _lib.LB_EINVAL
     assert "workspace" in lib.lb_last_error().decode()
+    # the allocation-free variant: bead limit, then the same spec checks
+    big = _lib.LB_NET_NOALLOC_MAX_BEADS + 1
+    assert lib.lb_kirchhoff_noalloc(fake, big, ct.byref(spec), fake, fake, ct.byref(out), None) == _lib.LB_EINVAL
+    assert "at most" in lib.lb_last_error().decode()
+    bad = _lib.LbKirchhoffSpec(2.1, 25.0, 5.0, 1.0, 1e-12, 100)
+    assert lib.lb_kirchhoff_noalloc(fake, 10, ct.byref(bad), fake, fake, ct.byref(out), None) == _lib.LB_EINVAL
+    assert lib.lb_kirchhoff_noalloc(None, 10, ct.byref(spec), fake, fake, ct.byref(out), None) == _lib.LB_EINVAL
