@@ -490,11 +490,11 @@ def test_refill_density_rings_by_hand():
 
 
 POCKET = dict(
-    X=[[13.641862, 8.477799, 9.227982], [9.837508, 11.063572, 10.704474], [10.892625, 11.246163, 8.814955],
-       [9.135597, 11.887222, 6.753526], [13.61286, 10.627683, 7.359403]],
-    Q=[[0.873668, 0.206958, -0.44031, 0.0], [0.867072, -0.337488, 0.366453, 0.0], [0.873134, -0.474117, -0.113356, 0.0],
-       [0.584921, -0.700266, 0.409261, 0.0], [0.829011, 0.506635, -0.236775, 0.0]],
-    V0=[0.495753, -0.189351, 0.279956])
+    X=[[9.020064, 10.320612, 7.641499], [13.387424, 8.764085, 11.020971], [8.59099, 6.644925, 9.48745],
+       [9.340319, 6.46289, 7.132206], [12.149523, 9.100366, 6.180325]],
+    Q=[[0.533138, -0.201023, -0.821799, 0.0], [0.197892, -0.752418, 0.628256, 0.0], [0.186819, -0.974079, -0.127552, 0.0],
+       [0.487011, -0.435238, -0.757224, 0.0], [0.954717, 0.106518, 0.277794, 0.0]],
+    V0=[-0.155726, 0.125496, -0.000284])
 
 
 def pocket_run():
