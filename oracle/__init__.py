@@ -11,4 +11,8 @@ lbm          two-component Shan-Chen D3Q19 BGK step (Methods, Eqs. 1-3)
 rods         rigid capsule rods: pair potentials (Eqs. 10, 12), rigid-body
              substeps, masks, moving bounce-back bookkeeping
 observables  deposit statistics g^b (Eq. 14), S_x^b (Eq. 13), contact graph
+network      resistor network of a deposit (Eqs. 15-18)
+surrogate    restriction, prolongation, lift, 3-D convolutions, U-Net, Adam
+cg           colour-gradient step: colour-blind BGK with Guo forcing, CSF
+             tension from grad C, recolouring, geometry-aware wetting
 """
