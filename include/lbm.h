@@ -110,7 +110,40 @@ typedef struct {
     double sink_J0;               /* flux scale J0 >= 0 */
     double sink_K;                /* kinetic resistance K >= 0 (0.01 in the paper) */
     double sink_h0;               /* initial droplet height h0 > 0 (nodes) */
+    /* fluid model: LB_MODEL_SC, the Shan-Chen pseudopotential step (fields
+     * above), or LB_MODEL_CG, the paper's colour-gradient step (Methods,
+     * fluid-filament paragraphs; Eqs. 1-3): per component BGK (tau[k])
+     * towards the equilibrium of the common velocity u = (sum_k j_k + F/2) /
+     * rho with Guo's forcing, the capillary force F = (cg_sigma / 2) kappa
+     * |grad C| n of the colour field C = (rho_1 - rho_2) / rho (n = grad C /
+     * |grad C| where |grad C| > cg_grad_eps, kappa = -div n, both with the
+     * isotropic D3Q19 stencil) plus rho * body_force, shared by the
+     * components in proportion to their densities, then recolouring
+     * f^{1,2}_i = (rho_{1,2} / rho) f*_i +- cg_beta (rho_1 rho_2 / rho) w_i
+     * c_i.n / |c_i|.  Wetting: a wall node next to the fluid carries the
+     * w-weighted mean colour of its fluid neighbours, and a fluid node next
+     * to walls turns its normal to -cos(theta) n_w + sin(theta) t (n_w the
+     * wall normal from its solid neighbours, t the unit tangential part of
+     * n, theta the w-weighted mean of cg_theta over those neighbours).
+     * FP64 or FP32 storage, no rods, reservoir or sink (LB_ENOTSUP). */
+    int32_t model;
+    double cg_sigma;              /* interfacial tension (lattice units) */
+    double cg_beta;               /* recolouring segregation parameter (0, 1] */
+    double cg_grad_eps;           /* |grad C| below which the normal is zero */
+    double cg_theta[LB_NMAT];     /* contact angle of wall material m (radians, through component 1) */
+    /* 16-bit storage forms: 0 round to nearest even, 1 stochastic rounding
+     * (the value goes to the upper of its two representable neighbours with
+     * probability equal to its distance from the lower one over their
+     * spacing; random bits from a counter-based hash of node, population
+     * array, step and sr_seed), which keeps the stored errors unbiased.  Only
+     * the fused Shan-Chen step rounds stochastically (lb_init, the rod passes
+     * and the surrogate's lift round to nearest); a batch does not take such
+     * lattices (LB_ENOTSUP). */
+    int32_t round_stochastic;
+    uint32_t sr_seed;
 } lb_params;
+
+enum { LB_MODEL_SC = 0, LB_MODEL_CG = 1 };
 
 /* Caller-owned device buffers. */
 typedef struct {

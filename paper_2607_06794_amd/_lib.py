@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "liblbm.so")
 LB_OK, LB_EINVAL, LB_ENOTSUP, LB_EHIP, LB_EUNSTABLE, LB_EPLACE = 0, -1, -2, -3, -4, 1
 LB_F64, LB_F32, LB_F16DEV, LB_BF16DEV = 0, 1, 2, 3
 LB_NMAT = 9
+LB_MODEL_SC, LB_MODEL_CG = 0, 1
 LB_MAX_RODS = 512
 LB_NET_NOALLOC_MAX_BEADS = 8192  # include/lbm.h
 
@@ -102,6 +103,13 @@ class LbParams(ct.Structure):
         ("sink_J0", ct.c_double),
         ("sink_K", ct.c_double),
         ("sink_h0", ct.c_double),
+        ("model", ct.c_int32),
+        ("cg_sigma", ct.c_double),
+        ("cg_beta", ct.c_double),
+        ("cg_grad_eps", ct.c_double),
+        ("cg_theta", ct.c_double * LB_NMAT),
+        ("round_stochastic", ct.c_int32),
+        ("sr_seed", ct.c_uint32),
     ]
 
 

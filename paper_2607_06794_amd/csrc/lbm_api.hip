@@ -131,7 +131,7 @@ static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
 
 struct WsLayout {
     size_t mat, ledger, heights, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
-        nbr, nbr_cnt, rodargs, rho, obs, total;
+        nbr, nbr_cnt, rodargs, rho, cg, obs, total;
     int max_tiles;
     int nslots;  // ledger slot pairs
 };
@@ -185,6 +185,9 @@ WsLayout ws_layout(const lb_params *p) {
     // the fluid step for the rod passes
     w.rho = o;
     o = align256(o + (rods ? 2 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
+    // colour-gradient step: colour [fs] and normal [4][fs] in compute precision
+    w.cg = o;
+    o = align256(o + (p->model == LB_MODEL_CG ? 5 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
     w.obs = o;
     o = align256(o + obs_bytes(p));
     w.total = o;
@@ -224,6 +227,19 @@ int validate(const lb_params *p) {
         if (!(p->sink_J0 >= 0.0) || !isfinite(p->sink_J0) || !(p->sink_K >= 0.0) || !isfinite(p->sink_K) ||
             !(p->sink_h0 > 0.0) || !isfinite(p->sink_h0))
             return fail(LB_EINVAL, "sink needs J0 >= 0, K >= 0 and h0 > 0 (finite)");
+    }
+    if (p->model != LB_MODEL_SC && p->model != LB_MODEL_CG) return fail(LB_EINVAL, "unknown fluid model %d", p->model);
+    if (p->model == LB_MODEL_CG) {
+        if (p->prec != LB_F64 && p->prec != LB_F32)
+            return fail(LB_ENOTSUP, "the colour-gradient step runs with FP64 or FP32 storage");
+        if (p->n_rods > 0 || p->evap_on || p->sink_on)
+            return fail(LB_ENOTSUP, "the colour-gradient step takes no rods, reservoir or sink");
+        if (!(p->cg_sigma >= 0.0) || !isfinite(p->cg_sigma) || !(p->cg_beta > 0.0 && p->cg_beta <= 1.0) ||
+            !(p->cg_grad_eps > 0.0) || !isfinite(p->cg_grad_eps))
+            return fail(LB_EINVAL, "colour gradient needs sigma >= 0, 0 < beta <= 1 and grad_eps > 0");
+        for (int m = 0; m < LB_NMAT; ++m)
+            if (!(p->cg_theta[m] >= 0.0 && p->cg_theta[m] <= M_PI))
+                return fail(LB_EINVAL, "contact angle of material %d outside [0, pi]", m);
     }
     // the integrator keeps 13 doubles per rod in one work-group's shared memory
     if (p->n_rods < 0 || p->n_rods > LB_MAX_RODS)
@@ -297,6 +313,7 @@ struct lb_ctx {
     char *obs;
     RodArgs *rodargs_dev;      // rod records with f = f[0] and f = f[1]
     void *rho;                 // [2][fs] fluid densities for the rod passes (lattices with rods)
+    void *cg;                  // colour-gradient step: colour [fs] and normal [4][fs], or null
     int rho_fresh;             // rho holds the densities of the current state
     RodArgs rodargs_host[2];
     double psi_host[32];
@@ -475,6 +492,7 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->obs = ws + w.obs;
     c->rodargs_dev = reinterpret_cast<RodArgs *>(ws + w.rodargs);
     c->rho = p->n_rods > 0 ? static_cast<void *>(ws + w.rho) : nullptr;
+    c->cg = p->model == LB_MODEL_CG ? static_cast<void *>(ws + w.cg) : nullptr;
     c->rho_fresh = 0;
     for (int m = 0; m < 16; ++m)
         for (int k = 0; k < 2; ++k)
@@ -511,6 +529,8 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
         return cleanup(hip_fail(e, "init populations"));
     if ((e = launch_slot_fill(p->prec, c->f[0], c->fs, c->mat, p->nx, p->ny, p->nz, per, stream)) != hipSuccess)
         return cleanup(hip_fail(e, "slot fill"));
+    if (c->cg && (e = hipMemsetAsync(c->cg, 0, 5 * size_t(c->fs) * (p->prec == LB_F64 ? 8 : 4), stream)) != hipSuccess)
+        return cleanup(hip_fail(e, "clear colour arrays"));
     if (p->n_rods > 0) {
         if ((e = hipMemcpyAsync(c->rods, rod_stage.data(), rod_stage.size() * sizeof(double), hipMemcpyHostToDevice,
                                 stream)) != hipSuccess)
@@ -591,10 +611,43 @@ static StepArgs step_args(const lb_ctx *c, int cur) {
         a.sink_ledger = c->ledger + 2 * size_t(c->max_tiles);
     }
     a.rho_out = c->rho;
+    if (p.round_stochastic && (p.prec == LB_F16DEV || p.prec == LB_BF16DEV))
+        a.sr_key = (uint32_t(c->steps + 1) * 0x9E3779B1u ^ p.sr_seed) | 1u;  // never 0 (0 = nearest)
     return a;
 }
 
 static bool is_tau1(const lb_params &p) { return p.tau[0] == 1.0 && p.tau[1] == 1.0; }
+
+// colour-gradient step record of a context whose current state is in buffer cur
+static CGArgs cg_args(const lb_ctx *c, int cur) {
+    const lb_params &p = c->p;
+    CGArgs a{};
+    a.fsrc = c->f[cur];
+    a.fdst = c->f[cur ^ 1];
+    a.mat = c->mat;
+    a.status = c->status;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.px = p.periodic[0];
+    a.py = p.periodic[1];
+    a.pz = p.periodic[2];
+    a.fs = c->fs;
+    a.nodes = nodes(&p);
+    for (int k = 0; k < 2; ++k) {
+        a.omega[k] = 1.0 / p.tau[k];
+        a.rho_ref[k] = c->rref[k];
+    }
+    a.sigma = p.cg_sigma;
+    a.beta = p.cg_beta;
+    a.grad_eps = p.cg_grad_eps;
+    for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
+    for (int m = 0; m < 16; ++m) a.cos_theta[m] = m < LB_NMAT ? cos(p.cg_theta[m]) : 0.0;
+    const size_t eb = p.prec == LB_F64 ? 8 : 4;
+    a.colour = c->cg;
+    a.normal = static_cast<char *>(c->cg) + size_t(c->fs) * eb;
+    return a;
+}
 
 // liquid-node counts per column of the current state into the buffer the
 // next step reads (chunk slot 0; the other slots cleared)
@@ -613,8 +666,9 @@ int lb_step(lb_ctx *c, int32_t nsteps, hipStream_t stream) {
     const lb_params &p = c->p;
     const bool tau1 = is_tau1(p);
     for (int s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_sc_step(p.prec, tau1, c->tile, step_args(c, c->cur), stream);
-        if (e != hipSuccess) return hip_fail(e, "sc_step launch");
+        hipError_t e = p.model == LB_MODEL_CG ? launch_cg_step(p.prec, cg_args(c, c->cur), stream)
+                                              : launch_sc_step(p.prec, tau1, c->tile, step_args(c, c->cur), stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
         c->cur ^= 1;
         c->steps++;
     }
@@ -1104,6 +1158,7 @@ int lb_set_tiles(lb_ctx *c, const lb_tile *t, hipStream_t stream) {
 
 int lb_autotune(lb_ctx *c, int32_t trial_steps, hipStream_t stream, lb_tile *best) {
     if (!c || !best || trial_steps < 1) return fail(LB_EINVAL, "bad autotune arguments");
+    if (c->p.model != LB_MODEL_SC) return fail(LB_ENOTSUP, "the colour-gradient step has no tile shape to tune");
     const bool tau1 = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
     const int shapes[4][2] = {{4, 1}, {8, 1}, {8, 2}, {16, 2}};
     const int nz = c->p.nz;
@@ -1234,6 +1289,10 @@ int batch_check(lb_ctx *const *ctxs, int n) {
         if (!ctxs[i]) return fail(LB_EINVAL, "null lattice %d", i);
         if (ctxs[i]->p.prec != ctxs[0]->p.prec) return fail(LB_EINVAL, "lattices of a batch share one precision");
         if (ctxs[i]->p.sink_on) return fail(LB_ENOTSUP, "lattice %d uses the evaporation sink, which a batch does not run", i);
+        if (ctxs[i]->p.round_stochastic)
+            return fail(LB_ENOTSUP, "lattice %d rounds stochastically, which a batch does not run", i);
+        if (ctxs[i]->p.model != LB_MODEL_SC)
+            return fail(LB_ENOTSUP, "lattice %d runs the colour-gradient step, which a batch does not run", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(LB_EINVAL, "lattice %d appears twice", i);
     }

@@ -33,7 +33,28 @@ struct StepArgs {
     int32_t *h_write;       // the same for this step
     double *sink_ledger;    // [ntx*nty*nzc][2] mass moved A -> B, one running pair per work-group
     void *rho_out;          // [2][fs] fluid densities in compute precision for the rod passes, or null
+    uint32_t sr_key;        // 16-bit storage: nonzero = stochastic rounding keyed by this step value
 };
+
+// Colour-gradient step (three passes over the lattice; cg_step.hip)
+struct CGArgs {
+    const void *fsrc;
+    void *fdst;
+    const uint8_t *mat;
+    unsigned *status;
+    int nx, ny, nz;
+    int px, py, pz;
+    int64_t fs;     // elements between population arrays
+    int64_t nodes;  // nx * ny * nz
+    double omega[2];
+    double sigma, beta, grad_eps;
+    double g[3];
+    double rho_ref[2];
+    double cos_theta[16];  // cos of the contact angle per material id
+    void *colour;          // [fs] C of every fluid node (compute precision)
+    void *normal;          // [4][fs] n_x, n_y, n_z, |grad C| (compute precision)
+};
+hipError_t launch_cg_step(int prec, const CGArgs &a, hipStream_t s);
 
 // Tile shape of the fused step: TX = 64 columns x tile_y rows, each thread
 // owning rows_per_thread rows; the work-group marches zchunk planes.

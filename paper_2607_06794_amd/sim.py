@@ -49,6 +49,15 @@ class LatticeParams:
     zchunk: int = 0
     # interfacial evaporation sink of Eq. 8: (J0, K, h0), None: off
     sink: tuple | None = None
+    # fluid model: "sc" (Shan-Chen) or "cg" (the paper's colour gradient)
+    model: str = "sc"
+    cg_sigma: float = 0.01
+    cg_beta: float = 0.7
+    cg_grad_eps: float = 1e-2
+    cg_theta: np.ndarray = field(default_factory=lambda: np.full(9, np.pi / 2))  # radians per wall material
+    # 16-bit storage: "nearest" (round to nearest even) or "stochastic"
+    rounding: str = "nearest"
+    sr_seed: int = 0
 
     def to_c(self) -> _lib.LbParams:
         p = _lib.LbParams()
@@ -82,6 +91,13 @@ class LatticeParams:
         p.tile_y = int(self.tile_y)
         p.rows_per_thread = int(self.rows_per_thread)
         p.zchunk = int(self.zchunk)
+        p.model = {"sc": _lib.LB_MODEL_SC, "cg": _lib.LB_MODEL_CG}[self.model]
+        p.cg_sigma, p.cg_beta, p.cg_grad_eps = float(self.cg_sigma), float(self.cg_beta), float(self.cg_grad_eps)
+        th = np.asarray(self.cg_theta, dtype=np.float64)
+        for m in range(_lib.LB_NMAT):
+            p.cg_theta[m] = float(th[m]) if m < th.shape[0] else np.pi / 2
+        p.round_stochastic = {"nearest": 0, "stochastic": 1}[self.rounding]
+        p.sr_seed = int(self.sr_seed) & 0xFFFFFFFF
         p.sink_on = int(self.sink is not None)
         if self.sink is not None:
             p.sink_J0, p.sink_K, p.sink_h0 = (float(v) for v in self.sink)
