@@ -295,8 +295,11 @@ def init_params(seed, cin=IN_CH, ch=CH, cout=OUT_CH):
     return P
 
 
-def unet_forward(x, P, ch=CH):
-    """x [D, H, W, 7] -> (prediction [D, H, W, 6], cache)."""
+def unet_forward(x, P, ch=CH, act_round=None):
+    """x [D, H, W, 7] -> (prediction [D, H, W, 6], cache).  act_round
+    (optional) models the storage precision of the activations: it is applied
+    to every hidden layer's output after the ReLU and to every pooled map."""
+    rnd = act_round if act_round is not None else (lambda a: a)
     cache = {"x": x}
     h = x
     skips = []
@@ -305,17 +308,17 @@ def unet_forward(x, P, ch=CH):
         for s in "ab":
             name = f"enc{lvl}{s}"
             cache[name + ":in"] = h
-            h = np.maximum(conv3d(h, *P[name]), 0.0)
+            h = rnd(np.maximum(conv3d(h, *P[name]), 0.0))
             cache[name + ":out"] = h
         if lvl < nlev - 1:
             skips.append(h)
-            h = pool2(h)
+            h = rnd(pool2(h))
     for lvl in range(nlev - 2, -1, -1):
         h = np.concatenate([up2(h), skips[lvl]], axis=-1)
         for s in "ab":
             name = f"dec{lvl}{s}"
             cache[name + ":in"] = h
-            h = np.maximum(conv3d(h, *P[name]), 0.0)
+            h = rnd(np.maximum(conv3d(h, *P[name]), 0.0))
             cache[name + ":out"] = h
     cache["out:in"] = h
     y = conv3d(h, *P["out"])

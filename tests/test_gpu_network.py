@@ -105,8 +105,9 @@ def test_rod_beads_match_oracle_layout():
     lp.rod_length, lp.rod_radius = rp["length"], rp["radius"]
     lat = Lattice(lp, c["rho"], c["mat"], rods=c["rods"])
     beads = lat.rod_beads(1.0).cpu().numpy()
-    rods = lat.rods()
     lat.close()
+    rods = np.array(c["rods"], dtype=np.float64)  # the inputs both sides were given
+    rods[:, 3:7] /= np.linalg.norm(rods[:, 3:7], axis=1)[:, None]
     half = 0.5 * ROD["length"] - ROD["radius"]
     axes = np.array([R.axis(q) for q in rods[:, 3:7]])
     ref, nb = N.rod_beads(rods[:, :3], axes, half, 1.0)
