@@ -283,6 +283,23 @@ typedef struct {
 int lb_deposit(lb_ctx *ctx, const lb_deposit_spec *spec, double *g_x, double *s_x, int32_t *n_x, double *g_y,
                double *s_y, int32_t *n_y, int32_t *labels, lb_graph *graph, hipStream_t stream);
 
+/*
+ * The same profiles averaged over independent runs and, when mirror != 0,
+ * over each run's mirror images at the droplet centre (x -> 2 xc - x, y ->
+ * 2 yc - y, both): the angle brackets of Eqs. 13 and 14 (Results, nematic
+ * order and density profile: profiles averaged over independent runs and
+ * their mirror images).  g^b is the mean over all images of each image's
+ * normalised bead profile; S_x^b the mean over the images with segments in
+ * bin b of their bin means (0 where none has); n_x, n_y the segments per
+ * bin summed over the images.  ctxs[0..n_runs) share the lattice extent,
+ * periodicity and rod shape (LB_EINVAL otherwise); the sums run on the
+ * device in ctxs[0]'s workspace, image after image in run order.  Outputs
+ * are host arrays as for lb_deposit.  Synchronises.
+ */
+int lb_deposit_ensemble(lb_ctx *const *ctxs, int32_t n_runs, const lb_deposit_spec *spec, int32_t mirror,
+                        double *g_x, double *s_x, int32_t *n_x, double *g_y, double *s_y, int32_t *n_y,
+                        hipStream_t stream);
+
 /* z-projected rod occupancy: rod nodes per (y, x) column into map_host
  * [ny][nx] (host, caller-owned).  Synchronises. */
 int lb_rod_map(lb_ctx *ctx, int32_t *map_host, hipStream_t stream);
@@ -497,6 +514,56 @@ int lb_pool2_backward(const float *gc, const float *skip, int32_t skip_stride, i
 int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_t H, int32_t W, float *gc,
                     hipStream_t stream);
 int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream);        /* graph-safe clear */
+
+/*
+ * The whole surrogate network in one call each way (the benchmark spec form (4): a
+ * 3-D convolutional encoder-decoder on the coarse canvas).  nlev levels
+ * (2..4) of ch[l] channels: per level two 3x3x3 ReLU convolutions, 2x2x2
+ * average pooling down; on the way up nearest-neighbour upsampling
+ * concatenated with the level's skip, two ReLU convolutions; a final linear
+ * 3x3x3 convolution to cout channels.  Layers are numbered in forward order:
+ * enc0a, enc0b, ..., enc{nlev-1}b, dec{nlev-2}a, dec{nlev-2}b, ..., dec0b,
+ * out (4 nlev - 1 layers).  All pointers are device buffers owned by the
+ * caller, channels-last [D][H][W][C] per level l of P_l = (D H W) / 8^l
+ * cells:
+ *   p, g     FP32 parameters and gradients (layer L: weights [27][cin][cout]
+ *            at off_w[L], biases [cout] at off_b[L], element offsets, 4-byte
+ *            aligned blocks of 16 bytes);
+ *   pb, pt   BF16 weights, and the same packed [cout][27][cin] for the
+ *            forward (lb_conv_pack_weights), at the same offsets;
+ *   act[L]   BF16 outputs of the hidden layers L < 4 nlev - 2, P_l x ch[l];
+ *   pooled   BF16 pooled maps, level l: P_{l+1} x ch[l];
+ *   out      FP32 network output [P_0][cout];
+ *   gA, gB   FP32 gradient scratch per level, P_l x max(ch[l] + ch[l+1],
+ *            cin, 2 ch[nlev-1]) and P_l x max(ch) elements;
+ *   gcat     FP32 per level l < nlev - 1, P_l x (ch[l] + ch[l+1]) elements;
+ *   gm       BF16 scratch of the largest layer output, P_l x cout;
+ *   acc      FP32 split-K scratch of the coarse levels (largest layer output
+ *            of levels >= 1).
+ * cin and the channel counts are multiples of 8; D, H, W divisible by
+ * 2^(nlev-1).  lb_sur_forward(x) writes act, pooled and out for the BF16
+ * input x [P_0][cin]; lb_sur_backward(x, gout) adds to g the parameter
+ * gradients for dloss/dout = gout [P_0][cout] (FP32) of the forward of the
+ * same x, whose activations it reads.  Asynchronous; LB_EINVAL on bad
+ * shapes or null pointers.
+ */
+#define LB_UNET_MAXLEV 4
+#define LB_UNET_MAXLAYER (4 * LB_UNET_MAXLEV - 1)
+typedef struct {
+    int32_t D, H, W, nlev, cin, cout;
+    int32_t ch[LB_UNET_MAXLEV];
+    float *p, *g;
+    void *pb, *pt;
+    int64_t off_w[LB_UNET_MAXLAYER], off_b[LB_UNET_MAXLAYER];
+    void *act[LB_UNET_MAXLAYER];
+    void *pooled[LB_UNET_MAXLEV];
+    float *out;
+    float *gA[LB_UNET_MAXLEV], *gB[LB_UNET_MAXLEV], *gcat[LB_UNET_MAXLEV];
+    void *gm;
+    float *acc;
+} lb_unet;
+int lb_sur_forward(const lb_unet *net, const void *x, hipStream_t stream);
+int lb_sur_backward(const lb_unet *net, const void *x, const float *gout, hipStream_t stream);
 int lb_to_bf16(const float *x, int64_t n, void *y, hipStream_t stream);       /* round to nearest even */
 /* Network input from an FP32 canvas of P cells: y[:, c] = BF16((x[:, c] -
  * shift[c]) * gain[c]) (shift, gain: host, 8 finite values each). */
@@ -534,9 +601,10 @@ int lb_destroy(lb_ctx *ctx);
 const char *lb_last_error(void);
 
 /* sizeof of lb_params, lb_buffers, lb_obs, lb_droplet, lb_deposit_spec,
- * lb_graph and lb_conv into out[0..6], so a binding can verify its mirrors of
- * the structs.  Never fails. */
-void lb_abi_sizes(size_t out[9]);
+ * lb_graph, lb_conv, lb_kirchhoff_spec, lb_kirchhoff_out and lb_unet into
+ * out[0..9], so a binding can verify its mirrors of the structs.  Never
+ * fails. */
+void lb_abi_sizes(size_t out[10]);
 
 #ifdef __cplusplus
 }

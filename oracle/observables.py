@@ -27,7 +27,12 @@ What it follows
     - S_x^b (Eq. 13): mean of 2 cos^2(zeta) - 1 over the segments whose
       midpoints fall in bin b, zeta the angle to the axial x direction;
     - axial profiles bin x inside |y - y_c| <= strip_y / 2; transverse
-      profiles bin y inside |x - x_c| <= strip_x / 2.
+      profiles bin y inside |x - x_c| <= strip_x / 2;
+    - the angle brackets of Eqs. 13 and 14 average over independent runs and
+      over the mirror images of each run at the droplet centre (Results,
+      nematic order and density profile): g^b is the mean of the images'
+      normalised profiles, S_x^b the mean over the images with segments in
+      the bin.
 * Rod contact graph (Methods, electrical network model: filaments connect
   when closer than a cutoff): rods are connected when the distance between
   their axis segments is below r_c; reported are the edge count, the size of
@@ -197,6 +202,63 @@ def deposit_profiles(X, Q, half, box, spec: DepositSpec, periodic=(True, True, F
     Sx = np.where(nsx > 0, sx_sum / np.maximum(nsx, 1), 0.0)
     Sy = np.where(nsy > 0, sy_sum / np.maximum(nsy, 1), 0.0)
     return norm(gx_cnt), Sx, nsx, norm(gy_cnt), Sy, nsy
+
+
+def mirror_rods(X, Q, xc, yc, mx, my):
+    """Mirror image of a rod configuration at the droplet centre: x -> 2 xc - x
+    when mx, y -> 2 yc - y when my (centres and axes; a rod is symmetric end
+    to end, so the reflected axis direction serves as its axis)."""
+    Xm = np.array(X, dtype=np.float64).copy()
+    Em = np.array([axis(np.asarray(q, float)) for q in Q])
+    if mx:
+        Xm[:, 0] = 2.0 * xc - Xm[:, 0]
+        Em[:, 0] = -Em[:, 0]
+    if my:
+        Xm[:, 1] = 2.0 * yc - Xm[:, 1]
+        Em[:, 1] = -Em[:, 1]
+    return Xm, Em
+
+
+def _quat_of_axis(e):
+    """Unit quaternion turning e_z into e (the rod's axis is all the profiles use)."""
+    e = np.asarray(e, float) / np.linalg.norm(e)
+    if e[2] < -1.0 + 1e-12:
+        return np.array([0.0, 1.0, 0.0, 0.0])
+    q = np.array([1.0 + e[2], -e[1], e[0], 0.0])
+    return q / np.linalg.norm(q)
+
+
+def ensemble_profiles(runs, half, box, spec: DepositSpec, mirror=True, periodic=(True, True, False)):
+    """Profiles averaged over independent runs and, with mirror, over each
+    run's mirror images at the droplet centre (x, y and both reflected): the
+    angle brackets of Eqs. 13 and 14.  runs: list of (X, Q) rod sets.
+    g^b is the mean over all images of each image's normalised bead profile;
+    S_x^b the mean over the images that have segments in bin b of their bin
+    means (0 where none has); N^b the segments of bin b summed over images.
+    Returns (g_x, S_x, N_x, g_y, S_y, N_y)."""
+    images = [(0, 0), (1, 0), (0, 1), (1, 1)] if mirror else [(0, 0)]
+    acc = None
+    for X, Q in runs:
+        for mx, my in images:
+            Xm, Em = mirror_rods(X, Q, spec.xc, spec.yc, mx, my)
+            Qm = [_quat_of_axis(e) for e in Em]
+            prof = deposit_profiles(Xm, Qm, half, box, spec, periodic)
+            if acc is None:
+                acc = {"g": [np.zeros_like(prof[0]), np.zeros_like(prof[3])],
+                       "s": [np.zeros_like(prof[1]), np.zeros_like(prof[4])],
+                       "ns": [np.zeros_like(prof[2]), np.zeros_like(prof[5])],
+                       "cnt": [np.zeros_like(prof[1]), np.zeros_like(prof[4])], "m": 0}
+            for d, (g, S, N) in enumerate(((prof[0], prof[1], prof[2]), (prof[3], prof[4], prof[5]))):
+                acc["g"][d] += g
+                acc["s"][d] += np.where(N > 0, S, 0.0)
+                acc["cnt"][d] += N > 0
+                acc["ns"][d] += N
+            acc["m"] += 1
+    out = []
+    for d in range(2):
+        c = acc["cnt"][d]
+        out += [acc["g"][d] / acc["m"], np.where(c > 0, acc["s"][d] / np.maximum(c, 1), 0.0), acc["ns"][d]]
+    return tuple(out)
 
 
 def rod_column_map(material):

@@ -39,6 +39,9 @@ EXPORTS = (
     "lb_deposit",
     "lb_rod_map",
     "lb_kirchhoff",
+    "lb_deposit_ensemble",
+    "lb_sur_forward",
+    "lb_sur_backward",
     "lb_kirchhoff_workspace_bytes",
     "lb_kirchhoff_noalloc",
     "lb_rod_beads",
@@ -222,8 +225,28 @@ class LbConv(ct.Structure):
     ]
 
 
+LB_UNET_MAXLEV = 4
+LB_UNET_MAXLAYER = 4 * LB_UNET_MAXLEV - 1
+
+
+class LbUnet(ct.Structure):
+    _fields_ = [
+        ("D", ct.c_int32), ("H", ct.c_int32), ("W", ct.c_int32), ("nlev", ct.c_int32), ("cin", ct.c_int32),
+        ("cout", ct.c_int32),
+        ("ch", ct.c_int32 * LB_UNET_MAXLEV),
+        ("p", ct.c_void_p), ("g", ct.c_void_p), ("pb", ct.c_void_p), ("pt", ct.c_void_p),
+        ("off_w", ct.c_int64 * LB_UNET_MAXLAYER), ("off_b", ct.c_int64 * LB_UNET_MAXLAYER),
+        ("act", ct.c_void_p * LB_UNET_MAXLAYER),
+        ("pooled", ct.c_void_p * LB_UNET_MAXLEV),
+        ("out", ct.c_void_p),
+        ("gA", ct.c_void_p * LB_UNET_MAXLEV), ("gB", ct.c_void_p * LB_UNET_MAXLEV), ("gcat", ct.c_void_p * LB_UNET_MAXLEV),
+        ("gm", ct.c_void_p),
+        ("acc", ct.c_void_p),
+    ]
+
+
 STRUCTS = ("LbParams", "LbBuffers", "LbObs", "LbDroplet", "LbDepositSpec", "LbGraph", "LbConv", "LbKirchhoffSpec",
-           "LbKirchhoffOut")
+           "LbKirchhoffOut", "LbUnet")
 
 
 class LbError(RuntimeError):
@@ -285,6 +308,12 @@ def load(path: str = LIB_PATH):
     lib.lb_droplet_shape.restype = ct.c_int
     lib.lb_deposit.argtypes = [ct.c_void_p, P(LbDepositSpec)] + [ct.c_void_p] * 7 + [P(LbGraph), ct.c_void_p]
     lib.lb_deposit.restype = ct.c_int
+    lib.lb_deposit_ensemble.argtypes = [ct.c_void_p, ct.c_int32, P(LbDepositSpec), ct.c_int32] + [ct.c_void_p] * 7
+    lib.lb_deposit_ensemble.restype = ct.c_int
+    lib.lb_sur_forward.argtypes = [P(LbUnet), ct.c_void_p, ct.c_void_p]
+    lib.lb_sur_forward.restype = ct.c_int
+    lib.lb_sur_backward.argtypes = [P(LbUnet), ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_sur_backward.restype = ct.c_int
     lib.lb_rod_map.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.lb_rod_map.restype = ct.c_int
     lib.lb_kirchhoff.argtypes = [ct.c_void_p, ct.c_int32, P(LbKirchhoffSpec), ct.c_void_p, ct.c_void_p,

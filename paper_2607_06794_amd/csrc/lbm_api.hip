@@ -92,7 +92,8 @@ static int rod_nblk(const lb_params &p) { return rod_shell_cap(p) / 256; }
 
 // Observable scratch: droplet column scan, then deposit binning and graph.
 struct ObsLayout {
-    size_t col_h, col_wet, line_x, line_y, out, bins, sval, dep_out, labels, graph, map, probe_xyz, probe_p, total;
+    size_t col_h, col_wet, line_x, line_y, out, bins, sval, dep_out, ens_acc, ens_out, labels, graph, map, probe_xyz,
+        probe_p, total;
 };
 static ObsLayout obs_layout(const lb_params *p) {
     ObsLayout l{};
@@ -113,6 +114,10 @@ static ObsLayout obs_layout(const lb_params *p) {
     l.sval = o;
     o = align256(o + nr * sizeof(double));
     l.dep_out = o;
+    o = align256(o + 6 * DEP_MAXBIN * sizeof(double));
+    l.ens_acc = o;
+    o = align256(o + 8 * DEP_MAXBIN * sizeof(double));
+    l.ens_out = o;
     o = align256(o + 6 * DEP_MAXBIN * sizeof(double));
     l.labels = o;
     o = align256(o + nr * sizeof(int32_t));
@@ -425,7 +430,7 @@ size_t lb_workspace_bytes(const lb_params *p) {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
-void lb_abi_sizes(size_t out[9]) {
+void lb_abi_sizes(size_t out[10]) {
     out[0] = sizeof(lb_params);
     out[1] = sizeof(lb_buffers);
     out[2] = sizeof(lb_obs);
@@ -435,6 +440,7 @@ void lb_abi_sizes(size_t out[9]) {
     out[6] = sizeof(lb_conv);
     out[7] = sizeof(lb_kirchhoff_spec);
     out[8] = sizeof(lb_kirchhoff_out);
+    out[9] = sizeof(lb_unet);
 }
 
 int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_host, const uint8_t *material_host,
@@ -778,9 +784,8 @@ int lb_pressure(lb_ctx *c, const int32_t *xyz, int32_t n, double *p_out, hipStre
     return LB_OK;
 }
 
-int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, int32_t *n_x, double *g_y, double *s_y,
-               int32_t *n_y, int32_t *labels, lb_graph *graph, hipStream_t stream) {
-    if (!c || !s || !g_x || !s_x || !n_x || !g_y || !s_y || !n_y || !graph) return fail(LB_EINVAL, "null argument");
+// deposit arguments of a context for a spec (validated); nb_out: beads per rod
+static int deposit_args(lb_ctx *c, const lb_deposit_spec *s, DepArgs &d) {
     const lb_params &p = c->p;
     if (s->n_bins_x < 1 || s->n_bins_x > DEP_MAXBIN || s->n_bins_y < 1 || s->n_bins_y > DEP_MAXBIN)
         return fail(LB_EINVAL, "bins per profile must be in [1, %d]", DEP_MAXBIN);
@@ -791,7 +796,7 @@ int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, in
     const int nb = nbd < 2.0 ? 2 : (nbd > DEP_NB ? DEP_NB + 1 : int(nbd));
     if (nb > DEP_NB) return fail(LB_EINVAL, "more than %d beads per rod", DEP_NB);
     const ObsLayout l = obs_layout(&p);
-    DepArgs d{};
+    d = DepArgs{};
     d.rods = c->rods;
     d.n_rods = p.n_rods;
     d.nb = nb;
@@ -816,6 +821,16 @@ int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, in
     d.out = reinterpret_cast<double *>(c->obs + l.dep_out);
     d.labels = reinterpret_cast<int32_t *>(c->obs + l.labels);
     d.graph = reinterpret_cast<int32_t *>(c->obs + l.graph);
+    return LB_OK;
+}
+
+int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, int32_t *n_x, double *g_y, double *s_y,
+               int32_t *n_y, int32_t *labels, lb_graph *graph, hipStream_t stream) {
+    if (!c || !s || !g_x || !s_x || !n_x || !g_y || !s_y || !n_y || !graph) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = c->p;
+    DepArgs d;
+    const int rc = deposit_args(c, s, d);
+    if (rc != LB_OK) return rc;
     HIP_TRY(launch_deposit(d, stream), "deposit");
     std::vector<double> res(6 * DEP_MAXBIN);
     int32_t gr[4];
@@ -845,6 +860,50 @@ int lb_deposit(lb_ctx *c, const lb_deposit_spec *s, double *g_x, double *s_x, in
     graph->spanning = gr[3];
     if (labels)
         for (size_t r = 0; r < lab.size(); ++r) labels[r] = lab[r];
+    return LB_OK;
+}
+
+int lb_deposit_ensemble(lb_ctx *const *ctxs, int32_t n_runs, const lb_deposit_spec *s, int32_t mirror, double *g_x,
+                        double *s_x, int32_t *n_x, double *g_y, double *s_y, int32_t *n_y, hipStream_t stream) {
+    if (!ctxs || n_runs < 1 || !s || !g_x || !s_x || !n_x || !g_y || !s_y || !n_y)
+        return fail(LB_EINVAL, "null argument or no runs");
+    for (int r = 0; r < n_runs; ++r) {
+        if (!ctxs[r]) return fail(LB_EINVAL, "null run %d", r);
+        const lb_params &a = ctxs[r]->p, &b = ctxs[0]->p;
+        if (a.nx != b.nx || a.ny != b.ny || a.periodic[0] != b.periodic[0] || a.periodic[1] != b.periodic[1] ||
+            a.rod_length != b.rod_length || a.rod_radius != b.rod_radius)
+            return fail(LB_EINVAL, "run %d differs from run 0 in lattice extent, periodicity or rod shape", r);
+    }
+    const ObsLayout l0 = obs_layout(&ctxs[0]->p);
+    double *acc = reinterpret_cast<double *>(ctxs[0]->obs + l0.ens_acc);
+    double *out = reinterpret_cast<double *>(ctxs[0]->obs + l0.ens_out);
+    HIP_TRY(hipMemsetAsync(acc, 0, 8 * DEP_MAXBIN * sizeof(double), stream), "clear ensemble sums");
+    const int nimg = mirror ? 4 : 1;
+    for (int r = 0; r < n_runs; ++r) {
+        DepArgs d;
+        const int rc = deposit_args(ctxs[r], s, d);
+        if (rc != LB_OK) return rc;
+        for (int m = 0; m < nimg; ++m) {
+            d.mirror_x = m & 1;
+            d.mirror_y = (m >> 1) & 1;
+            HIP_TRY(launch_deposit_accumulate(d, acc, stream), "deposit image");
+        }
+    }
+    HIP_TRY(launch_deposit_finish(acc, s->n_bins_x, s->n_bins_y, n_runs * nimg, out, stream), "deposit ensemble");
+    std::vector<double> res(6 * DEP_MAXBIN);
+    HIP_TRY(hipMemcpyAsync(res.data(), out, res.size() * sizeof(double), hipMemcpyDeviceToHost, stream),
+            "copy ensemble");
+    HIP_TRY(hipStreamSynchronize(stream), "ensemble sync");
+    for (int b = 0; b < s->n_bins_x; ++b) {
+        g_x[b] = res[b];
+        s_x[b] = res[DEP_MAXBIN + b];
+        n_x[b] = int32_t(res[2 * DEP_MAXBIN + b]);
+    }
+    for (int b = 0; b < s->n_bins_y; ++b) {
+        g_y[b] = res[3 * DEP_MAXBIN + b];
+        s_y[b] = res[4 * DEP_MAXBIN + b];
+        n_y[b] = int32_t(res[5 * DEP_MAXBIN + b]);
+    }
     return LB_OK;
 }
 
@@ -1034,6 +1093,157 @@ int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_
     if (!g || !gc || C < 1 || stride < C || D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2)
         return fail(LB_EINVAL, "bad upsampling gradient");
     HIP_TRY(launch_up2_back(g, stride, C, D, H, W, gc, stream), "upsample backward");
+    return LB_OK;
+}
+
+// ---- whole-network surrogate calls ----------------------------------------
+namespace {
+
+struct UnetLayer {
+    int c1, c2, cout, up1, lvl;
+};
+
+// layer L of the forward order (shapes as lb_sur_forward describes)
+UnetLayer unet_layer(const lb_unet *n, int L) {
+    const int nl = n->nlev;
+    if (L < 2 * nl) {
+        const int lvl = L / 2, part = L % 2;
+        const int cprev = lvl == 0 ? n->cin : n->ch[lvl - 1];
+        return {part == 0 ? cprev : n->ch[lvl], 0, n->ch[lvl], 0, lvl};
+    }
+    if (L == 4 * nl - 2) return {n->ch[0], 0, n->cout, 0, 0};
+    const int k = L - 2 * nl, lvl = nl - 2 - k / 2, part = k % 2;
+    const int ccoarse = lvl + 1 == nl - 1 ? n->ch[nl - 1] : n->ch[lvl + 1];
+    return part == 0 ? UnetLayer{ccoarse, n->ch[lvl], n->ch[lvl], 1, lvl} : UnetLayer{n->ch[lvl], 0, n->ch[lvl], 0, lvl};
+}
+
+int unet_enc(int lvl, int part) { return 2 * lvl + part; }
+int unet_dec(const lb_unet *n, int lvl, int part) { return 2 * n->nlev + 2 * (n->nlev - 2 - lvl) + part; }
+
+lb_conv unet_conv(const lb_unet *n, int L, const void *x1, const void *x2, void *y, float *yf, int relu) {
+    const UnetLayer l = unet_layer(n, L);
+    lb_conv c{};
+    c.x1 = x1;
+    c.c1 = l.c1;
+    c.up1 = l.up1;
+    c.x2 = x2;
+    c.c2 = l.c2;
+    c.w = static_cast<const uint16_t *>(n->pb) + n->off_w[L];
+    c.wt = static_cast<const uint16_t *>(n->pt) + n->off_w[L];
+    c.b = n->p + n->off_b[L];
+    c.y = y;
+    c.yf = yf;
+    c.acc = l.lvl >= 1 ? n->acc : nullptr;
+    c.D = n->D >> l.lvl;
+    c.H = n->H >> l.lvl;
+    c.W = n->W >> l.lvl;
+    c.cout = l.cout;
+    c.relu = relu;
+    return c;
+}
+
+int unet_check(const lb_unet *n, const void *x) {
+    if (!n || !x) return fail(LB_EINVAL, "null network or input");
+    if (n->nlev < 2 || n->nlev > LB_UNET_MAXLEV) return fail(LB_EINVAL, "nlev must be in [2, %d]", LB_UNET_MAXLEV);
+    const int m = 1 << (n->nlev - 1);
+    if (n->D < m || n->H < m || n->W < m || n->D % m || n->H % m || n->W % m)
+        return fail(LB_EINVAL, "canvas must be divisible by 2^(nlev - 1)");
+    if (!n->p || !n->g || !n->pb || !n->pt || !n->out || !n->gm || !n->acc) return fail(LB_EINVAL, "null network buffer");
+    for (int L = 0; L < 4 * n->nlev - 2; ++L)
+        if (!n->act[L]) return fail(LB_EINVAL, "null activation of layer %d", L);
+    for (int l = 0; l < n->nlev; ++l) {
+        if (!n->gA[l] || !n->gB[l]) return fail(LB_EINVAL, "null gradient scratch of level %d", l);
+        if (l < n->nlev - 1 && (!n->pooled[l] || !n->gcat[l])) return fail(LB_EINVAL, "null level %d buffer", l);
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+int lb_sur_forward(const lb_unet *n, const void *x, hipStream_t stream) {
+    int rc = unet_check(n, x);
+    if (rc) return rc;
+    const int nl = n->nlev;
+    const void *h = x;
+    for (int lvl = 0; lvl < nl; ++lvl) {
+        for (int part = 0; part < 2; ++part) {
+            const int L = unet_enc(lvl, part);
+            const lb_conv c = unet_conv(n, L, h, nullptr, n->act[L], nullptr, 1);
+            if ((rc = lb_conv3d_forward(&c, stream))) return rc;
+            h = n->act[L];
+        }
+        if (lvl < nl - 1) {
+            if ((rc = lb_pool2(h, n->D >> lvl, n->H >> lvl, n->W >> lvl, n->ch[lvl], n->pooled[lvl], stream))) return rc;
+            h = n->pooled[lvl];
+        }
+    }
+    for (int lvl = nl - 2; lvl >= 0; --lvl) {
+        const int La = unet_dec(n, lvl, 0), Lb = unet_dec(n, lvl, 1);
+        lb_conv c = unet_conv(n, La, h, n->act[unet_enc(lvl, 1)], n->act[La], nullptr, 1);
+        if ((rc = lb_conv3d_forward(&c, stream))) return rc;
+        c = unet_conv(n, Lb, n->act[La], nullptr, n->act[Lb], nullptr, 1);
+        if ((rc = lb_conv3d_forward(&c, stream))) return rc;
+        h = n->act[Lb];
+    }
+    const lb_conv c = unet_conv(n, 4 * nl - 2, h, nullptr, nullptr, n->out, 0);
+    return lb_conv3d_forward(&c, stream);
+}
+
+// gradient of one layer: pre-activation gradient of dy (through the ReLU
+// mask of its output y), weight and bias gradients, input gradient into dx
+static int unet_layer_grad(const lb_unet *n, int L, const void *x1, const void *x2, const void *y, const float *dy,
+                           float *dx, hipStream_t stream) {
+    const int relu = L == 4 * n->nlev - 2 ? 0 : 1;
+    const lb_conv c = unet_conv(n, L, x1, x2, const_cast<void *>(y), nullptr, relu);
+    const int64_t cnt = int64_t(c.D) * c.H * c.W * c.cout;
+    int rc;
+    if ((rc = lb_relu_grad(dy, y, cnt, relu, n->gm, stream))) return rc;
+    if ((rc = lb_conv3d_backward_weights(&c, n->gm, n->g + n->off_w[L], n->g + n->off_b[L], stream))) return rc;
+    if (dx) return lb_conv3d_backward_data(&c, n->gm, dx, stream);
+    return LB_OK;
+}
+
+int lb_sur_backward(const lb_unet *n, const void *x, const float *gout, hipStream_t stream) {
+    int rc = unet_check(n, x);
+    if (rc) return rc;
+    if (!gout) return fail(LB_EINVAL, "null output gradient");
+    const int nl = n->nlev;
+    float *g = n->gB[0];
+    if ((rc = unet_layer_grad(n, 4 * nl - 2, n->act[unet_dec(n, 0, 1)], nullptr, nullptr, gout, g, stream))) return rc;
+    // decoder, finest level first: dec{l}b, then dec{l}a whose input is (up(coarse), skip)
+    for (int lvl = 0; lvl < nl - 1; ++lvl) {
+        float *ga = n->gA[lvl];
+        const int La = unet_dec(n, lvl, 0), Lb = unet_dec(n, lvl, 1);
+        if ((rc = unet_layer_grad(n, Lb, n->act[La], nullptr, n->act[Lb], g, ga, stream))) return rc;
+        const void *coarse = lvl + 1 < nl - 1 ? n->act[unet_dec(n, lvl + 1, 1)] : n->act[unet_enc(nl - 1, 1)];
+        const int cup = lvl + 1 < nl - 1 ? n->ch[lvl + 1] : n->ch[nl - 1];
+        if ((rc = unet_layer_grad(n, La, coarse, n->act[unet_enc(lvl, 1)], n->act[La], ga, n->gcat[lvl], stream)))
+            return rc;
+        g = n->gB[lvl + 1];
+        if ((rc = lb_up2_backward(n->gcat[lvl], cup + n->ch[lvl], cup, n->D >> lvl, n->H >> lvl, n->W >> lvl, g,
+                                  stream)))
+            return rc;
+    }
+    // encoder, coarsest level first
+    for (int lvl = nl - 1; lvl >= 0; --lvl) {
+        if (lvl < nl - 1) {
+            // gradient of enc{lvl}b's output: through the pooling plus the skip
+            const int cup = lvl + 1 < nl - 1 ? n->ch[lvl + 1] : n->ch[nl - 1];
+            float *gn = n->gA[lvl];
+            if ((rc = lb_pool2_backward(g, n->gcat[lvl], cup + n->ch[lvl], cup, n->D >> lvl, n->H >> lvl, n->W >> lvl,
+                                        n->ch[lvl], gn, stream)))
+                return rc;
+            g = gn;
+        }
+        float *ga = g != n->gB[lvl] ? n->gB[lvl] : n->gA[lvl];
+        const int La = unet_enc(lvl, 0), Lb = unet_enc(lvl, 1);
+        if ((rc = unet_layer_grad(n, Lb, n->act[La], nullptr, n->act[Lb], g, ga, stream))) return rc;
+        const void *xin = lvl == 0 ? x : n->pooled[lvl - 1];
+        float *gb = nullptr;
+        if (lvl > 0) gb = ga != n->gB[lvl] ? n->gB[lvl] : n->gA[lvl];
+        if ((rc = unet_layer_grad(n, La, xin, nullptr, n->act[La], ga, gb, stream))) return rc;
+        if (lvl > 0) g = gb;
+    }
     return LB_OK;
 }
 

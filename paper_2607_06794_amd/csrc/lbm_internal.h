@@ -169,12 +169,19 @@ struct DepArgs {
     double *out;     // axial: count, S, segments [3][DEP_MAXBIN]; then transverse, same
     int32_t *labels; // [n_rods] cluster label (smallest rod index of the cluster)
     int32_t *graph;  // n_rods, edges, largest cluster, spanning
+    int mirror_x, mirror_y;  // bin the mirror image at (xc, yc): x -> 2 xc - x, y -> 2 yc - y
 };
 hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t s);
 constexpr int PROBE_MAX = 256;  // pressure probes per call
 hipError_t launch_pressure(int prec, const void *f, int64_t fs, const uint8_t *mat, int nx, int ny, int nz,
                            const double rref[2], double G, const int *xyz, int n, double *out, hipStream_t s);
 hipError_t launch_deposit(const DepArgs &d, hipStream_t s);
+// ensemble of deposit profiles: the profiles of d (its mirror flags set) into
+// the running sums acc [8][DEP_MAXBIN] (g axial, g transverse, S sums, S
+// counts, segment counts); finish turns acc into out [6][DEP_MAXBIN]
+// (g_x, S_x, N_x, g_y, S_y, N_y) after `images` accumulations
+hipError_t launch_deposit_accumulate(const DepArgs &d, double *acc, hipStream_t s);
+hipError_t launch_deposit_finish(const double *acc, int nbx, int nby, int images, double *out, hipStream_t s);
 
 // resistor network of a deposit (network.hip)
 constexpr int NET_DEG = 64;  // neighbours stored per bead

@@ -150,7 +150,16 @@ __global__ void __launch_bounds__(LB_MAX_RODS) deposit_kernel(DepArgs d) {
         const double *rod = d.rods + r * ROD_STRIDE;
         double e[3];
         rod_axis(rod + ROD_Q, e);
-        const double X[3] = {rod[ROD_X], rod[ROD_X + 1], rod[ROD_X + 2]};
+        double X[3] = {rod[ROD_X], rod[ROD_X + 1], rod[ROD_X + 2]};
+        // mirror image at the droplet centre (the rod is symmetric end to end)
+        if (d.mirror_x) {
+            X[0] = 2.0 * d.xc - X[0];
+            e[0] = -e[0];
+        }
+        if (d.mirror_y) {
+            X[1] = 2.0 * d.yc - X[1];
+            e[1] = -e[1];
+        }
         int16_t *bx = d.bins + size_t(r) * DEP_NB * 4;
         int16_t *by = bx + DEP_NB, *sx = by + DEP_NB, *sy = sx + DEP_NB;
         double prev[3] = {0, 0, 0};
@@ -381,6 +390,52 @@ hipError_t launch_droplet(int prec, const void *f, const ObsArgs &o, hipStream_t
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(shape_final_kernel, dim3(1), dim3(1024), 0, s, o);
+    return hipGetLastError();
+}
+
+// one image's profiles into the ensemble sums: Eq. 14 normalises the bead
+// counts by their mean over the bins (summed in bin order by one thread);
+// Eq. 13's bin means enter only where the image has segments
+__global__ void __launch_bounds__(2 * DEP_MAXBIN) deposit_accumulate_kernel(const double *out, int nbx, int nby,
+                                                                           double *acc) {
+    __shared__ double mean[2];
+    if (threadIdx.x < 2) {
+        const int d = threadIdx.x, nb = d ? nby : nbx;
+        const double *cnt = out + d * 3 * DEP_MAXBIN;
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += cnt[b];
+        mean[d] = t / nb;
+    }
+    __syncthreads();
+    const int d = threadIdx.x >= DEP_MAXBIN, b = threadIdx.x - d * DEP_MAXBIN;
+    if (b >= (d ? nby : nbx)) return;
+    const double *o = out + d * 3 * DEP_MAXBIN;
+    const double nseg = o[2 * DEP_MAXBIN + b];
+    acc[d * DEP_MAXBIN + b] += mean[d] > 0.0 ? o[b] / mean[d] : 0.0;
+    acc[(2 + d) * DEP_MAXBIN + b] += nseg > 0.0 ? o[DEP_MAXBIN + b] : 0.0;
+    acc[(4 + d) * DEP_MAXBIN + b] += nseg > 0.0 ? 1.0 : 0.0;
+    acc[(6 + d) * DEP_MAXBIN + b] += nseg;
+}
+
+__global__ void __launch_bounds__(2 * DEP_MAXBIN) deposit_finish_kernel(const double *acc, int nbx, int nby,
+                                                                       int images, double *out) {
+    const int d = threadIdx.x >= DEP_MAXBIN, b = threadIdx.x - d * DEP_MAXBIN;
+    if (b >= (d ? nby : nbx)) return;
+    const double c = acc[(4 + d) * DEP_MAXBIN + b];
+    double *o = out + d * 3 * DEP_MAXBIN;
+    o[b] = acc[d * DEP_MAXBIN + b] / images;
+    o[DEP_MAXBIN + b] = c > 0.0 ? acc[(2 + d) * DEP_MAXBIN + b] / c : 0.0;
+    o[2 * DEP_MAXBIN + b] = acc[(6 + d) * DEP_MAXBIN + b];
+}
+
+hipError_t launch_deposit_accumulate(const DepArgs &d, double *acc, hipStream_t s) {
+    hipLaunchKernelGGL(deposit_kernel, dim3(1), dim3(LB_MAX_RODS), 0, s, d);
+    hipLaunchKernelGGL(deposit_accumulate_kernel, dim3(1), dim3(2 * DEP_MAXBIN), 0, s, d.out, d.nbx, d.nby, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_finish(const double *acc, int nbx, int nby, int images, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(deposit_finish_kernel, dim3(1), dim3(2 * DEP_MAXBIN), 0, s, acc, nbx, nby, images, out);
     return hipGetLastError();
 }
 

@@ -350,6 +350,23 @@ class Lattice:
             pass
 
 
+def deposit_ensemble(lattices, n_bins_x: int, n_bins_y: int, xc: float, yc: float, strip_x: float, strip_y: float,
+                     bead_spacing: float = 2.0, mirror: bool = True, stream=None) -> dict:
+    """Deposit profiles g^b and S_x^b averaged over the rods of several
+    lattices (independent runs) and, with mirror, their mirror images at
+    (xc, yc) (lb_deposit_ensemble)."""
+    lib = _lib.load()
+    ctxs = (ct.c_void_p * len(lattices))(*[lat._ctx for lat in lattices])
+    spec = _lib.LbDepositSpec(int(n_bins_x), int(n_bins_y), xc, yc, strip_x, strip_y, bead_spacing, 0.0, 0.0, 0.0)
+    gx, sx, gy, sy = np.zeros(n_bins_x), np.zeros(n_bins_x), np.zeros(n_bins_y), np.zeros(n_bins_y)
+    nx_, ny_ = np.zeros(n_bins_x, np.int32), np.zeros(n_bins_y, np.int32)
+    ptr = lambda a: a.ctypes.data_as(ct.c_void_p)
+    st = stream if stream is not None else lattices[0].stream
+    _lib.check(lib.lb_deposit_ensemble(ctxs, len(lattices), ct.byref(spec), int(bool(mirror)), ptr(gx), ptr(sx),
+                                       ptr(nx_), ptr(gy), ptr(sy), ptr(ny_), _stream_ptr(st)))
+    return {"g_x": gx, "s_x": sx, "n_x": nx_, "g_y": gy, "s_y": sy, "n_y": ny_}
+
+
 def kirchhoff(pos, r_c: float, x_src: float, x_snk: float, dV: float = 1.0, tol: float = 1e-12,
               max_iter: int = 20000, stream=None, noalloc: bool = False) -> dict:
     """Resistor network of a deposit (lb_kirchhoff, Eqs. 15-18) for bead

@@ -2,8 +2,10 @@
 and run with the library's own kernels (BF16 matrix-core convolutions with
 FP32 accumulation, pooling and gradient plumbing, the loss and Adam).
 
-This module only allocates device buffers (PyTorch tensors) and sequences the
-C-ABI calls; every arithmetic step runs in liblbm.so.
+This module only allocates device buffers (PyTorch tensors), describes them
+to the library (lb_unet) and sequences the C-ABI calls; every arithmetic step
+runs in liblbm.so, the whole network's forward and backward passes in one call
+each (lb_sur_forward, lb_sur_backward).
 
 Network (four levels, 32-64-128-128 channels): per level two 3x3x3 ReLU
 convolutions; 2x2x2 average pooling down; on the way up nearest-neighbour
@@ -101,6 +103,26 @@ class UNet:
         self.in_shift = np.zeros(8, np.float32)
         self.in_gain = np.array([1, 1, 100, 100, 100, 1, 1, 1], np.float32)
         self.xin = torch.zeros(self.P[0] * CIN, **bf)
+        self.desc = self._descriptor()
+
+    def _descriptor(self):
+        """The library's description of this network's buffers (lb_unet)."""
+        d = _lib.LbUnet()
+        d.D, d.H, d.W, d.nlev, d.cin, d.cout = self.D, self.H, self.W, len(self.ch), CIN, COUT
+        for l, c in enumerate(self.ch):
+            d.ch[l] = c
+        d.p, d.g, d.pb, d.pt = self.p.data_ptr(), self.g.data_ptr(), self.pb.data_ptr(), self.pt.data_ptr()
+        for L, (name, *_rest) in enumerate(self.layers):
+            o, _, ob, _ = self.off[name]
+            d.off_w[L], d.off_b[L] = o, ob
+            if name != "out":
+                d.act[L] = self.act[name].data_ptr()
+        for l in range(len(self.ch)):
+            d.gA[l], d.gB[l] = self.gA[l].data_ptr(), self.gB[l].data_ptr()
+            if l < len(self.ch) - 1:
+                d.pooled[l], d.gcat[l] = self.pooled[l].data_ptr(), self.gcat[l].data_ptr()
+        d.out, d.gm, d.acc = self.out.data_ptr(), self.gm.data_ptr(), self.acc.data_ptr()
+        return d
 
     def set_scale(self, scale):
         self.scale = np.ascontiguousarray(scale, dtype=np.float32).reshape(6)
@@ -181,85 +203,20 @@ class UNet:
     # ---------------------------------------------------------------- forward
     def forward(self, x_bf16):
         """x_bf16: int16 tensor [P0 * 8] (BF16 canvas).  Returns self.out, the FP32
-        [P0][8] network output before the residual."""
-        s = self._s()
-        nlev = len(self.ch)
+        [P0][8] network output before the residual (lb_sur_forward: the whole
+        network in one library call)."""
         self._x = x_bf16
-        h = x_bf16
-        for lvl in range(nlev):
-            for part in "ab":
-                name = f"enc{lvl}{part}"
-                cv, _, _ = self._conv(name, h, None, y=self.act[name])
-                _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
-                h = self.act[name]
-            if lvl < nlev - 1:
-                _lib.check(self.lib.lb_pool2(_p(h), self.D >> lvl, self.H >> lvl, self.W >> lvl, self.ch[lvl],
-                                             _p(self.pooled[lvl]), s))
-                h = self.pooled[lvl]
-        for lvl in range(nlev - 2, -1, -1):
-            name = f"dec{lvl}a"
-            cv, _, _ = self._conv(name, h, self.act[f"enc{lvl}b"], y=self.act[name])
-            _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
-            name = f"dec{lvl}b"
-            cv, _, _ = self._conv(name, self.act[f"dec{lvl}a"], None, y=self.act[name])
-            _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
-            h = self.act[name]
-        cv, _, _ = self._conv("out", h, None, yf=self.out, relu=0)
-        _lib.check(self.lib.lb_conv3d_forward(ct.byref(cv), s))
+        _lib.check(self.lib.lb_sur_forward(ct.byref(self.desc), _p(x_bf16), self._s()))
         return self.out
 
     # --------------------------------------------------------------- backward
     def zero_grad(self):
         _lib.check(self.lib.lb_fill_f32(_p(self.g), self.nparam, 0.0, self._s()))
 
-    def _wgrad_dgrad(self, name, x1, x2, y, dy, dx):
-        cv, o, ob = self._conv(name, x1, x2, y=y, relu=0 if name == "out" else 1)
-        s = self._s()
-        n = cv.D * cv.H * cv.W * cv.cout
-        _lib.check(self.lib.lb_relu_grad(_p(dy), _p(y) if y is not None else None, n, cv.relu, _p(self.gm), s))
-        _lib.check(self.lib.lb_conv3d_backward_weights(ct.byref(cv), _p(self.gm), ct.c_void_p(self.g.data_ptr() + 4 * o),
-                                                       ct.c_void_p(self.g.data_ptr() + 4 * ob), s))
-        if dx is not None:
-            _lib.check(self.lib.lb_conv3d_backward_data(ct.byref(cv), _p(self.gm), _p(dx), s))
-
     def backward(self, gout):
         """Accumulate the parameter gradients for dloss/dout = gout [P0][8] FP32
-        (uses the activations of the last forward call)."""
-        s = self._s()
-        nlev = len(self.ch)
-        g = self.gB[0]
-        self._wgrad_dgrad("out", self.act["dec0b"], None, None, gout, g)
-        gl = {}
-        for lvl in range(0, nlev - 1):
-            # dec{lvl}b, then dec{lvl}a whose input is (up(h), skip)
-            ga = self.gA[lvl]
-            self._wgrad_dgrad(f"dec{lvl}b", self.act[f"dec{lvl}a"], None, self.act[f"dec{lvl}b"], g, ga)
-            coarse = self.act[f"dec{lvl + 1}b"] if lvl + 1 < nlev - 1 else self.act[f"enc{nlev - 1}b"]
-            cup = self.ch[lvl + 1] if lvl + 1 < nlev - 1 else self.ch[-1]
-            gcat = self.gcat[lvl]
-            self._wgrad_dgrad(f"dec{lvl}a", coarse, self.act[f"enc{lvl}b"], self.act[f"dec{lvl}a"], ga, gcat)
-            gl[lvl] = (gcat, cup + self.ch[lvl], cup)
-            # gradient of the coarse input: sum over the upsampled children
-            g = self.gB[lvl + 1]
-            _lib.check(self.lib.lb_up2_backward(_p(gcat), cup + self.ch[lvl], cup, self.D >> lvl, self.H >> lvl,
-                                                self.W >> lvl, _p(g), s))
-        for lvl in range(nlev - 1, -1, -1):
-            if lvl < nlev - 1:
-                # gradient of enc{lvl}b's output: through the pooling plus the skip
-                gcat, stride, off = gl[lvl]
-                gn = self.gA[lvl]
-                _lib.check(self.lib.lb_pool2_backward(_p(g), _p(gcat), stride, off, self.D >> lvl, self.H >> lvl,
-                                                      self.W >> lvl, self.ch[lvl], _p(gn), s))
-                g = gn
-            ga = self.gB[lvl] if g is not self.gB[lvl] else self.gA[lvl]
-            self._wgrad_dgrad(f"enc{lvl}b", self.act[f"enc{lvl}a"], None, self.act[f"enc{lvl}b"], g, ga)
-            xin = self._x if lvl == 0 else self.pooled[lvl - 1]
-            gb = None
-            if lvl > 0:
-                gb = self.gB[lvl] if ga is not self.gB[lvl] else self.gA[lvl]
-            self._wgrad_dgrad(f"enc{lvl}a", xin, None, self.act[f"enc{lvl}a"], ga, gb)
-            if lvl > 0:
-                g = gb
+        (uses the activations of the last forward call; lb_sur_backward)."""
+        _lib.check(self.lib.lb_sur_backward(ct.byref(self.desc), _p(self._x), _p(gout), self._s()))
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.step_count += 1

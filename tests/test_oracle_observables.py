@@ -162,3 +162,58 @@ def test_rod_column_map():
     mat[2, 0, 0] = lbm.ROD
     m = O.rod_column_map(mat)
     assert m[2, 3] == 3 and m[0, 0] == 1 and m.sum() == 4
+
+
+# --------------------------------------------------------------------------
+# ensemble profiles: runs and mirror images (the angle brackets of Eqs. 13-14)
+# --------------------------------------------------------------------------
+def _runs(seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        X = np.c_[rng.uniform(20, 76, n), rng.uniform(10, 38, n), rng.uniform(2, 4, n)]
+        Q = [O._quat_of_axis(e) for e in rng.normal(size=(n, 3))]
+        out.append((X, Q))
+    return out
+
+
+ESPEC = dict(n_bins_x=12, n_bins_y=6, xc=47.5, yc=23.5, strip_x=60, strip_y=30)
+
+
+def test_ensemble_without_mirror_is_the_mean_of_the_runs():
+    spec = O.DepositSpec(**ESPEC)
+    runs = _runs(11, (30, 25, 7))
+    e = O.ensemble_profiles(runs, 10.0, (96, 48, 20), spec, mirror=False)
+    single = [O.deposit_profiles(X, Q, 10.0, (96, 48, 20), spec) for X, Q in runs]
+    for d, (gi, si, ni) in enumerate(((0, 1, 2), (3, 4, 5))):
+        assert np.allclose(e[gi], np.mean([p[gi] for p in single], axis=0), rtol=1e-15, atol=1e-15)
+        assert np.array_equal(e[ni], np.sum([p[ni] for p in single], axis=0))
+        # S: mean over the runs that have segments in the bin, by hand
+        for b in range(len(e[si])):
+            vals = [p[si][b] for p in single if p[ni][b] > 0]
+            assert e[si][b] == pytest.approx(np.mean(vals) if vals else 0.0, abs=1e-15)
+    assert e[0].mean() == pytest.approx(1.0, rel=1e-14)
+
+
+def test_ensemble_with_mirror_images_is_symmetric():
+    """The four images of a run give the same ensemble as the four images of
+    its mirrored copy; a run placed symmetrically about the centre gives its
+    own profile; an axial rod pair mirrored in x fills the mirror bins."""
+    spec = O.DepositSpec(**ESPEC)
+    box = (96, 48, 20)
+    (X, Q), = _runs(12, (40,))
+    Xm, Em = O.mirror_rods(X, Q, spec.xc, spec.yc, 1, 1)
+    a = O.ensemble_profiles([(X, Q)], 10.0, box, spec)
+    b = O.ensemble_profiles([(Xm, [O._quat_of_axis(e) for e in Em])], 10.0, box, spec)
+    for u, v in zip(a, b):
+        assert np.abs(u - v).max() < 1e-12
+    # a rod along x at (xc - 20, yc) and its mirror at (xc + 20, yc): already symmetric
+    qx = O._quat_of_axis([1.0, 0.0, 0.0])
+    sym = (np.array([[spec.xc - 20.0, spec.yc, 3.0], [spec.xc + 20.0, spec.yc, 3.0]]), [qx, qx])
+    e = O.ensemble_profiles([sym], 10.0, box, spec)
+    p = O.deposit_profiles(*sym, 10.0, box, spec)
+    assert np.allclose(e[0], p[0]) and np.allclose(e[1], p[1])
+    # one rod only: its x-mirror image puts beads in the mirrored bins
+    one = (sym[0][:1], sym[1][:1])
+    e1 = O.ensemble_profiles([one], 10.0, box, spec)
+    assert np.allclose(e1[0], e[0])
