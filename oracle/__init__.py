@@ -15,4 +15,7 @@ network      resistor network of a deposit (Eqs. 15-18)
 surrogate    restriction, prolongation, lift, 3-D convolutions, U-Net, Adam
 cg           colour-gradient step: colour-blind BGK with Guo forcing, CSF
              tension from grad C, recolouring, geometry-aware wetting
+filaments    bead-spring filaments (Eqs. 9-12): FENE bonds, excluded volume,
+             bending, cohesion, substrate adhesion and friction, drag and
+             solvation coupling to the fluid, five substeps per step
 """
