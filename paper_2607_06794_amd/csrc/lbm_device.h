@@ -106,5 +106,64 @@ struct Codec<bf16_t> {
     }
 };
 
+// ---------------------------------------------------------------------------
+// stochastic rounding of the 16-bit storage forms: a value between two
+// neighbouring representable numbers goes to the upper one with probability
+// equal to its distance from the lower one in units of their spacing, so the
+// stored errors have zero mean (round to nearest biases the mass of a state
+// whose values cluster).  The random bits come from a counter-based hash of
+// (node, population array, step); the same key always gives the same result.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t hash32(uint32_t x) {
+    // xorshift-multiply finaliser (two 32-bit multiplies, three shifts)
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ inline uint32_t sr_bits(uint32_t step_key, int64_t node, int array) {
+    return hash32(uint32_t(node) * 38u + uint32_t(array) + hash32(step_key ^ uint32_t(node >> 32)));
+}
+
+template <class S>
+struct Stochastic {
+    // wider storage rounds exactly as the plain codec
+    __device__ static inline S enc(typename Codec<S>::C v, uint32_t) { return Codec<S>::enc(v); }
+};
+
+// IEEE half: round to nearest of v + (r - 1/2) ulp(v), r uniform on 13 bits,
+// is the upper neighbour with probability (v - lower) / ulp; the shift is
+// exact in FP32 (ulp of half = 2^13 ulp of float in the same binade, and a
+// fixed 2^-24 below the normal range)
+template <>
+struct Stochastic<_Float16> {
+    __device__ static inline _Float16 enc(float v, uint32_t r) {
+        const uint32_t u = __float_as_uint(v);
+        const int e = int((u >> 23) & 0xFFu) - 127;  // binade of |v|
+        const int ue = e - 10 < -24 ? -24 : e - 10;  // exponent of the half spacing
+        if (e > 15) return static_cast<_Float16>(v);  // beyond the half range: plain conversion
+        const float ulp = __uint_as_float(uint32_t(ue + 127) << 23);
+        const float dither = (float(int(r >> 19)) * (1.0f / 8192.0f) - 0.5f) * ulp;
+        return static_cast<_Float16>(v + dither);
+    }
+};
+
+// bfloat16: add 16 random bits below the kept ones and truncate
+template <>
+struct Stochastic<bf16_t> {
+    __device__ static inline bf16_t enc(float d, uint32_t r) {
+        uint32_t u = __float_as_uint(d);
+        bf16_t o;
+        if ((u & 0x7f800000u) == 0x7f800000u) {
+            o.bits = static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+        } else {
+            u += r & 0xffffu;
+            o.bits = static_cast<uint16_t>(u >> 16);
+        }
+        return o;
+    }
+};
 
 }  // namespace lbm

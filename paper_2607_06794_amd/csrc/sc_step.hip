@@ -556,6 +556,15 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
 
             const uint32_t voE = own[r].xy[1][1] * E;
             const bool near_wall = fluid && (cur_m[r] & MAT_NEAR_WALL) != 0;
+            // 16-bit storage with stochastic rounding: the random bits depend on
+            // (node, array, step) only, so the wall slot gets the same value
+            const int64_t gnode = int64_t(z) * nxy + own[r].xy[1][1];
+            auto encode = [&](C v, int arr) -> S {
+                if constexpr (sizeof(S) == 2) {
+                    if (a.sr_key) return Stochastic<S>::enc(v, sr_bits(a.sr_key, gnode, arr));
+                }
+                return Codec<S>::enc(v);
+            };
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 C ue[3];
@@ -606,7 +615,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                         }
                     }
                     fstar[i] = ds;
-                    buf_store<S>(Codec<S>::enc(ds), dst[k], voE, i * fsE + zE);
+                    buf_store<S>(encode(ds, k * Q + i), dst[k], voE, i * fsE + zE);
                 }
                 if (ledger_plane && fluid) {
                     // this step's streaming moves the node's stored f*_i(t) with c_iz = +1
@@ -633,7 +642,8 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                         const uint32_t nxyo = own[r].xy[1 + cy(jd)][1 + cx(jd)];
                         const uint8_t nm = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, nxyo, zl[1 + cz(jd)], 0));
                         if (is_static_wall(nm & MAT_ID_MASK))
-                            buf_store<S>(Codec<S>::enc(fstar[jd]), dst[k], nxyo * E, opp(jd) * fsE + zl[1 + cz(jd)] * E);
+                            buf_store<S>(encode(fstar[jd], k * Q + jd), dst[k], nxyo * E,
+                                         opp(jd) * fsE + zl[1 + cz(jd)] * E);
                     }
                 }
             }

@@ -31,13 +31,17 @@ def oracle_run(name, steps):
 
 
 def gpu_run(name, prec, steps, rho_ref=(0.0, 0.0), **tile):
+    """GPU run of a case; the observables carry mass0, the stored state's
+    masses at step 0 (after the initial store into the storage format)."""
     from paper_2607_06794_amd.sim import Lattice
 
     c = CASES[name]()
     say(f"[gpu] case={name} prec={prec} steps={steps} rho_ref={rho_ref} tile={tile} shape={c['shape']}")
     lat = Lattice(cases.lattice_params(c, prec, rho_ref=rho_ref, **tile), c["rho"], c["mat"])
+    m0 = lat.observables()["mass"]
     lat.step(steps)
     obs = lat.observables()
+    obs["mass0"] = m0
     rho, f = lat.export()
     lat.close()
     return f, rho, obs
@@ -140,58 +144,105 @@ def test_poiseuille_body_force_channel():
     assert cases.rel_err(fg, fo) <= 1e-12
 
 
-def test_full_size_cap_one_step_parity_f32():
-    """Full 256 x 128 x 64 cap in the benchmark's launch configuration.
-
-    The GPU runs 20 steps; the oracle takes one step from the GPU's exported
-    state (decoded FP32 values, exactly representable in FP64) and the GPU's
-    next step must agree to the FP32 bar; ledger closure holds throughout.
-    """
+def test_full_size_cap_two_steps_parity_f32():
+    """Full 256 x 128 x 64 cap in the benchmark's launch configuration: two
+    FP32 steps against two oracle steps from the same inputs (populations to
+    the FP32 bar, ledger), ledger closure on the GPU."""
     from paper_2607_06794_amd.sim import Lattice
 
     c = cases.cap_case()
-    say("[gpu] full-size cap: 20 + 1 steps f32")
+    say("[gpu] full-size cap: 2 steps f32")
     lat = Lattice(cases.lattice_params(c, "f32"), c["rho"], c["mat"])
-    lat.step(20)
-    o20 = lat.observables()
-    _, f20 = lat.export()
-    lat.step(1)
-    o21 = lat.observables()
-    rg21, fg21 = lat.export()
+    lat.step(2)
+    o2 = lat.observables()
+    _, fg2 = lat.export()
     lat.close()
-    fo21, dled, _ = lbm.fluid_step(f20, c["mat"], cases.oracle_params(c))
-    ef = cases.rel_err(fg21, fo21)
-    say(f"[gpu] full-size one-step rel err f {ef:.3e}")
+    run = lbm.Run(c["rho"], c["mat"], cases.oracle_params(c))
+    run.step(2)
+    ef = cases.rel_err(fg2, run.f)
+    say(f"[gpu] full-size two-step rel err f {ef:.3e}")
     assert ef <= 1e-6
-    assert np.allclose(o21["ledger"] - o20["ledger"], dled, rtol=1e-4, atol=1e-6)
+    assert np.allclose(o2["ledger"], run.ledger, rtol=1e-5, atol=1e-6)
     m0 = np.where(c["mat"] == 0, c["rho"], 0).sum(axis=(1, 2, 3))
-    assert np.all(np.abs(o21["mass"] + o21["ledger"] - m0) / m0 < 1e-5)
+    assert np.all(np.abs(o2["mass"] + o2["ledger"] - m0) / m0 < 1e-5)
 
 
-@pytest.mark.parametrize("prec,rho_ref,bound", [("f16dev", 0.0, 5e-2), ("bf16dev", 0.0, 1.5e-1),
-                                                 ("f16dev", 1.0, 3e-1), ("bf16dev", 1.0, 1.0)])
-def test_16bit_storage_error_report(prec, rho_ref, bound):
-    """32^3 droplet, 1000 steps, populations stored in 16 bits, FP32 compute.
+# Bounds of the 16-bit storage errors after 10^4 steps, fixed before the runs
+# were measured, from the rounding model of the storage: stochastic rounding
+# of every stored value at every step (the kernel's rounding with its
+# hash-based random bits; tests/golden/make_config3_oracle.py runs the FP64
+# oracle with it, three seeds per form).
+# * the mass of each component random-walks: drift within 5 sigma_M of the
+#   closed form in tests/golden/errors.py (rounding_walk);
+# * the droplet drifts (16-bit storage keeps neither the total momentum nor
+#   its position): within K_MODEL times the largest drift of the model runs;
+# * once that drift is translated back, the density errors (whole field and
+#   per phase, max and RMS) within K_MODEL times the model runs' largest.
+# The pointwise errors without the alignment are reported beside them: after
+# 10^4 steps they measure where the drifting droplet sits.
+K_MODEL = 4.0
+ALIGNED_KEYS = ("rho_A", "rho_B", "liquid_rho_A", "liquid_rho_B", "gas_rho_A", "gas_rho_B", "interface_rho_A",
+                "interface_rho_B")
 
-    Reports max / RMS density error split into liquid (C > 0.5), gas
-    (C < -0.5) and interface against the FP64 oracle, for plain storage
-    (rho_ref = 0) and for deviations from the lattice weights (rho_ref = 1).
-    The bounds are the measured error levels of each storage form (round to
-    nearest even per stored population, amplified by the interface dynamics),
-    not parity claims.
-    """
-    fo, ro, _, _ = oracle_run("cfg1", 1000)
-    fg, rg, obs = gpu_run("cfg1", prec, 1000, rho_ref=(rho_ref, rho_ref))
-    Cf = (ro[0] - ro[1]) / (ro[0] + ro[1])
-    for name, sel in (("liquid", Cf > 0.5), ("gas", Cf < -0.5), ("interface", np.abs(Cf) <= 0.5)):
-        for k in range(2):
-            d = rg[k][sel] - ro[k][sel]
-            say(f"[gpu] {prec} rho_ref={rho_ref} rho_{k} {name}: max {np.abs(d).max():.3e} "
-                f"rms {np.sqrt((d ** 2).mean()):.3e}")
-    ef, er = cases.rel_err(fg, fo), cases.rel_err(rg, ro)
-    say(f"[gpu] {prec} rho_ref={rho_ref}: rel err f {ef:.3e} rho {er:.3e}")
+
+@pytest.mark.parametrize("prec,rho_ref", [("f16dev", 0.0), ("bf16dev", 0.0), ("f16dev", 1.0), ("bf16dev", 1.0)])
+def test_16bit_storage_error_at_1e4_steps(prec, rho_ref):
+    """32^3 droplet, 10^4 steps, populations stored in 16 bits with stochastic
+    rounding (rho_ref = 0: f_i; rho_ref = 1: f_i - w_i, the deviation from the
+    lattice weights), FP32 compute, against the FP64 oracle's fields."""
+    import json
+
+    from tests.golden import errors as G
+
+    fmt = "f16" if prec == "f16dev" else "bf16"
+    gold = np.load(G.CONFIG3_ORACLE)
+    rho_o, u_o = gold["rho"].astype(np.float64), gold["u"].astype(np.float64)
+    runs = json.load(open(G.CONFIG3_MODEL))["forms"][f"{fmt}|rho_ref={rho_ref:g}"]
+    fg, rg, obs = gpu_run("cfg1", prec, 10000, rho_ref=(rho_ref, rho_ref), rounding="stochastic")
     assert obs["status"] == 0
-    assert er <= bound and ef <= bound
+    ug = G.velocity(rg, fg)
+    raw = G.field_errors(rg, ug, rho_o, u_o, obs["mass"], gold["mass"])
+    # mass drift from the stored initial state (round to nearest at lb_init)
+    raw["mass_rel"] = [float(abs(obs["mass"][k] - obs["mass0"][k]) / obs["mass0"][k]) for k in range(2)]
+    al = G.aligned_errors(rg, ug, rho_o, u_o)
+    sig_m = G.rounding_walk(rho_o, rho_ref, fmt, 10000)
+    mdisp = max(float(np.linalg.norm(r["aligned"]["displacement"])) for r in runs)
+    tag = f"[gpu] {prec} rho_ref={rho_ref:g}"
+    for key in ("rho_A", "rho_B", "u") + ALIGNED_KEYS[2:]:
+        mm = max(r["aligned"][key]["max"] for r in runs)
+        mr = max(r["aligned"][key]["rms"] for r in runs)
+        say(f"{tag} {key}: max {raw[key]['max']:.3e} rms {raw[key]['rms']:.3e} | aligned max {al[key]['max']:.3e} "
+            f"rms {al[key]['rms']:.3e} (model <= {mm:.3e} / {mr:.3e})")
+    d = float(np.linalg.norm(al["displacement"]))
+    say(f"{tag} mass drift {raw['mass_rel']} (5 sigma {[5 * v for v in sig_m]}), droplet drift {d:.3f} "
+        f"(model runs up to {mdisp:.3f})")
+    for k in range(2):
+        assert raw["mass_rel"][k] <= 5.0 * sig_m[k]
+    assert d <= K_MODEL * mdisp
+    for key in ALIGNED_KEYS:
+        for m in ("max", "rms"):
+            assert al[key][m] <= K_MODEL * max(r["aligned"][key][m] for r in runs), (key, m)
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_16bit_nearest_rounding_drifts_the_mass(prec):
+    """Round to nearest even, 2000 steps: the stored values cluster (the bulk
+    phases hold nearly equal populations), so the rounding errors share a
+    sign and the mass drifts far beyond the stochastic-rounding walk -- the
+    reason the storage forms round stochastically."""
+    from tests.golden import errors as G
+
+    fmt = "f16" if prec == "f16dev" else "bf16"
+    rho0 = CASES["cfg1"]()["rho"]
+    _, rn, on = gpu_run("cfg1", prec, 2000)
+    _, rs, os_ = gpu_run("cfg1", prec, 2000, rounding="stochastic")
+    sig_m = G.rounding_walk(rho0, 0.0, fmt, 2000)
+    # drift from the stored initial state (the oracle keeps the mass exactly)
+    dn = np.abs(on["mass"] - on["mass0"]) / on["mass0"]
+    ds = np.abs(os_["mass"] - os_["mass0"]) / os_["mass0"]
+    say(f"[gpu] {prec} 2000 steps: mass drift nearest {dn}, stochastic {ds}, sigma {sig_m}")
+    assert np.all(ds <= 5.0 * np.asarray(sig_m))
+    assert np.max(dn / np.asarray(sig_m)) > 10.0
 
 
 def test_deviation_storage_fp64_parity():
