@@ -64,6 +64,7 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3 } lb_prec;
 
 #define LB_NMAT 9
 #define LB_MAX_RODS 512 /* rods per lattice */
+#define LB_FIL_MAX_BEADS 4096 /* filament beads per lattice */
 
 /* All parameters of one lattice (plain data; mirrored by a Python dataclass). */
 typedef struct {
@@ -141,6 +142,46 @@ typedef struct {
      * lattices (LB_ENOTSUP). */
     int32_t round_stochastic;
     uint32_t sr_seed;
+    /* bead-spring filaments (Methods, filament paragraphs; Eqs. 9-12):
+     * n_fil chains of fil_beads beads each (at most LB_FIL_MAX_BEADS beads in
+     * all), bead mass pi fil_d0^3 / 6.  Forces on bead a from bead b at
+     * distance d along r = x_a - x_b (minimum image), each -dU/dd r / d:
+     *   every pair with d <= fil_d0: excluded volume (Eq. 10)
+     *     U = fil_eps [(d0/d)^12 - 2 (d0/d)^6] + fil_eps;
+     *   neighbours in a chain: FENE (Eq. 9)
+     *     U = -1/2 fil_k_s fil_R_m^2 ln(1 - d^2 / fil_R_m^2);
+     *   second neighbours in a chain: bending (Eq. 11) U = 1/2 fil_k_b (d - 2 d0)^2;
+     *   beads of different chains with d0 < d < fil_r_cut: cohesion
+     *     (Eq. 12) U = fil_eps_coh [(d0/d)^12 - 2 (d0/d)^6] (force only);
+     *   the wall plane z = wall_z (when wall_on), h = z - wall_z, 0 < h <
+     *     fil_r_cut_s: adhesion U = fil_eps_s [(s/h)^12 - 2 (s/h)^6],
+     *     s = fil_sigma_s, and friction -v_t min(fil_mu N / |v_t|, m / dt)
+     *     on the tangential velocity v_t with the normal load N = max(0,
+     *     -(every other z-force + the attractive part of the adhesion));
+     *   drag -fil_gamma (V - u) and solvation fil_kappa_s grad C, u and
+     *     grad C interpolated (trilinear, weights renormalised over fluid
+     *     nodes) from the physical velocity (sum_k j*_k - F/2) / rho and the
+     *     lattice gradient 3 sum_i w_i C(x + c_i) c_i of the colour
+     *     C = (rho_A - rho_B) / rho of the state after the fluid step, held
+     *     over the substeps.
+     * n_sub substeps (forces, then V, then X).  The fluid receives the drag's
+     * and the solvation's reactions, spread with the same weights, by the
+     * exact-difference rule.  Non-bonded partners come from a list built at
+     * the start of each update over the range max(d0, r_cut) + fil_skin;
+     * a bead moving more than fil_skin / 2 in one update raises status bit 8,
+     * a list longer than 48 bit 32.  FP64 or FP32 storage, Shan-Chen model,
+     * no rods in the same lattice (LB_ENOTSUP); a batch does not take such
+     * lattices. */
+    int32_t n_fil;                /* filaments (0: none) */
+    int32_t fil_beads;            /* beads per filament */
+    double fil_k_s, fil_R_m;      /* FENE spring constant and maximum extension (0.3, 2.4) */
+    double fil_eps, fil_d0;       /* excluded volume strength and bead diameter (0.03, 2) */
+    double fil_k_b;               /* bending stiffness (8) */
+    double fil_eps_coh, fil_r_cut;/* cohesion well depth and cut-off */
+    double fil_eps_s, fil_sigma_s, fil_r_cut_s; /* substrate adhesion (0.006), its minimum and cut-off */
+    double fil_mu;                /* friction coefficient */
+    double fil_gamma, fil_kappa_s;/* drag coefficient, solvation strength */
+    double fil_skin;              /* partner-list skin */
 } lb_params;
 
 enum { LB_MODEL_SC = 0, LB_MODEL_CG = 1 };
@@ -204,6 +245,22 @@ int lb_rods_step(lb_ctx *ctx, hipStream_t stream);
 /* Copy the rod states to out_host [n_rods][13] (layout as in lb_init).
  * Synchronises. */
 int lb_rods_get(lb_ctx *ctx, double *out_host, hipStream_t stream);
+
+/* Filaments (see lb_params): beads_host [n_fil * fil_beads][6] holds each
+ * bead's position (x, y, z) and velocity, bead b of filament f at row
+ * f * fil_beads + b.  Uploads them and clears the momentum grid; call once
+ * after lb_init (LB_EINVAL without filaments).  Synchronises. */
+int lb_fil_set(lb_ctx *ctx, const double *beads_host, hipStream_t stream);
+
+/* One filament update after lb_step(1): interpolate the fluid velocity and
+ * colour gradient at the beads, n_sub substeps, hand the reactions back to
+ * the stored populations.  A no-op without filaments.  Asynchronous. */
+int lb_fil_step(lb_ctx *ctx, hipStream_t stream);
+
+/* Copy per bead [n_beads][12]: position, velocity, the interpolated fluid
+ * velocity of the last update and the impulse the fluid received from the
+ * bead in it.  Synchronises. */
+int lb_fil_get(lb_ctx *ctx, double *out_host, hipStream_t stream);
 
 /* Advance the fluid nsteps >= 0 time steps (pull stream, boundaries, moments,
  * pseudopotential force, velocity shift, BGK collision, store; reservoir

@@ -16,6 +16,7 @@ LB_F64, LB_F32, LB_F16DEV, LB_BF16DEV = 0, 1, 2, 3
 LB_NMAT = 9
 LB_MODEL_SC, LB_MODEL_CG = 0, 1
 LB_MAX_RODS = 512
+LB_FIL_MAX_BEADS = 4096
 LB_NET_NOALLOC_MAX_BEADS = 8192  # include/lbm.h
 
 # Every exported symbol declared in include/lbm.h
@@ -35,6 +36,9 @@ EXPORTS = (
     "lb_autotune",
     "lb_rods_step",
     "lb_rods_get",
+    "lb_fil_set",
+    "lb_fil_step",
+    "lb_fil_get",
     "lb_droplet_shape",
     "lb_deposit",
     "lb_rod_map",
@@ -113,6 +117,22 @@ class LbParams(ct.Structure):
         ("cg_theta", ct.c_double * LB_NMAT),
         ("round_stochastic", ct.c_int32),
         ("sr_seed", ct.c_uint32),
+        ("n_fil", ct.c_int32),
+        ("fil_beads", ct.c_int32),
+        ("fil_k_s", ct.c_double),
+        ("fil_R_m", ct.c_double),
+        ("fil_eps", ct.c_double),
+        ("fil_d0", ct.c_double),
+        ("fil_k_b", ct.c_double),
+        ("fil_eps_coh", ct.c_double),
+        ("fil_r_cut", ct.c_double),
+        ("fil_eps_s", ct.c_double),
+        ("fil_sigma_s", ct.c_double),
+        ("fil_r_cut_s", ct.c_double),
+        ("fil_mu", ct.c_double),
+        ("fil_gamma", ct.c_double),
+        ("fil_kappa_s", ct.c_double),
+        ("fil_skin", ct.c_double),
     ]
 
 
@@ -300,6 +320,12 @@ def load(path: str = LIB_PATH):
     lib.lb_rods_step.restype = ct.c_int
     lib.lb_rods_get.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
     lib.lb_rods_get.restype = ct.c_int
+    lib.lb_fil_set.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_fil_set.restype = ct.c_int
+    lib.lb_fil_step.argtypes = [ct.c_void_p, ct.c_void_p]
+    lib.lb_fil_step.restype = ct.c_int
+    lib.lb_fil_get.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.lb_fil_get.restype = ct.c_int
     lib.lb_set_tiles.argtypes = [ct.c_void_p, P(LbTile), ct.c_void_p]
     lib.lb_set_tiles.restype = ct.c_int
     lib.lb_autotune.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p, P(LbTile)]

@@ -11,7 +11,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["sc_step.hip", "cg_step.hip", "aux.hip", "rods.hip", "observe.hip", "surrogate.hip", "network.hip", "lbm_api.hip"]
+SOURCES = ["sc_step.hip", "cg_step.hip", "aux.hip", "rods.hip", "filaments.hip", "observe.hip", "surrogate.hip", "network.hip", "lbm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

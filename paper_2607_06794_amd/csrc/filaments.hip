@@ -1,0 +1,530 @@
+// Bead-spring filaments coupled to the Shan-Chen fluid (gfx950).
+//
+// The paper's nanowires (Methods, filament paragraphs): chains of beads with
+// FENE bonds (Eq. 9), excluded volume between all beads (Eq. 10), harmonic
+// springs between second neighbours for stiffness (Eq. 11), Lennard-Jones
+// cohesion between filaments (Eq. 12), substrate adhesion and load-dependent
+// friction, a drag towards the local fluid velocity whose momentum goes back
+// to the fluid, a solvation force along the colour gradient, and five bead
+// substeps per lattice step.
+//
+// One filament update, after the fluid step, in five launches:
+//   gather   one thread per bead: the eight lattice nodes around the bead,
+//            their trilinear weights renormalised over fluid nodes, the
+//            physical velocity (sum_k j*_k - F/2) / rho and the colour
+//            gradient 3 sum_i w_i C(x + c_i) c_i of each node, interpolated;
+//   list     one thread per bead: non-bonded partners within the interaction
+//            range plus a skin, ascending index order (bead positions staged
+//            through shared memory in tiles);
+//   substeps one work-group holds every bead position in shared memory and
+//            runs the five substeps (forces at the substep start, then V and
+//            X), summing per bead the impulse the fluid receives;
+//   spread   one thread per bead adds its impulse times each weight into a
+//            fixed-point (2^-50) momentum grid with 64-bit integer atomics:
+//            integer addition is exact, so the sums do not depend on order;
+//   apply    one thread per (bead, stencil node): the first thread to claim a
+//            node adds its summed momentum dp to the stored state by the
+//            exact-difference rule f*_k += f^eq(rho_k, u_k + dp / rho) -
+//            f^eq(rho_k, u_k), which keeps every density and adds dp exactly.
+// All bead arithmetic is FP64.
+#include <type_traits>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr double FIX_SCALE = FIL_FIX;
+constexpr double FIX_INV = 1.0 / FIX_SCALE;
+
+struct v3 {
+    double x, y, z;
+};
+__device__ inline v3 operator+(v3 a, v3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline v3 operator-(v3 a, v3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline v3 operator*(double s, v3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline v3 ld(const double *p) { return {p[0], p[1], p[2]}; }
+__device__ inline void st(double *p, v3 v) {
+    p[0] = v.x;
+    p[1] = v.y;
+    p[2] = v.z;
+}
+
+__device__ inline double wrap_pos(double x, double box, int per) {
+    if (!per) return x;
+    // remainder with the sign of the box: fmod, then one shift of negatives
+    double r = fmod(x, box);
+    if (r != 0.0 && r < 0.0) r += box;
+    return r;
+}
+__device__ inline double min_img(double d, double box, int per) { return per ? d - box * rint(d / box) : d; }
+__device__ inline v3 min_image(v3 d, const FilArgs &a) {
+    return {min_img(d.x, a.nx, a.px), min_img(d.y, a.ny, a.py), min_img(d.z, a.nz, a.pz)};
+}
+
+__device__ inline int wrap_idx(int i, int n) { return ((i % n) + n) % n; }
+
+template <class S>
+__device__ inline double popf(const FilArgs &a, const S *f, int k, int i, int64_t n) {
+    return static_cast<double>(Codec<S>::dec(f[(int64_t(k) * Q + i) * a.fs + n])) + wgt<double>(i) * a.rho_ref[k];
+}
+
+// densities of fluid node n: the density array while it holds the current
+// state, else the sum of the populations
+template <class S>
+__device__ inline void node_rho(const FilArgs &a, const S *f, int64_t n, double rho[2]) {
+    if (a.rho_fresh) {
+        const typename Codec<S>::C *ro = static_cast<const typename Codec<S>::C *>(a.rho);
+        rho[0] = double(ro[n]);
+        rho[1] = double(ro[a.fs + n]);
+        return;
+    }
+    for (int k = 0; k < 2; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += popf(a, f, k, i, n);
+        rho[k] = s;
+    }
+}
+
+__device__ inline int64_t node_at(const FilArgs &a, int x, int y, int z) {
+    return (int64_t(z) * a.ny + y) * a.nx + x;
+}
+
+// neighbour x + c_i of an interior fluid node (closed directions end in
+// non-fluid planes, so the neighbour of a fluid node exists)
+__device__ inline int64_t nb_of(const FilArgs &a, int x, int y, int z, int i) {
+    const int xn = a.px ? wrap_idx(x + cx(i), a.nx) : x + cx(i);
+    const int yn = a.py ? wrap_idx(y + cy(i), a.ny) : y + cy(i);
+    const int zn = a.pz ? wrap_idx(z + cz(i), a.nz) : z + cz(i);
+    return node_at(a, xn, yn, zn);
+}
+
+// physical velocity and colour gradient of fluid node (x, y, z)
+template <class S>
+__device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v3 &u, v3 &gc) {
+    const int64_t n = node_at(a, x, y, z);
+    double rho[2];
+    node_rho(a, f, n, rho);
+    // post-collision momentum of both components
+    v3 jk[2];
+    for (int k = 0; k < 2; ++k) {
+        jk[k] = {0.0, 0.0, 0.0};
+        for (int i = 1; i < Q; ++i) {
+            const double fi = popf(a, f, k, i, n);
+            jk[k] = jk[k] + v3{cx(i) * fi, cy(i) * fi, cz(i) * fi};
+        }
+    }
+    const v3 js = jk[0] + jk[1];
+    const double tot = rho[0] + rho[1];
+    const double ts = tot > 0.0 ? tot : 1.0;
+    const double C0 = (rho[0] - rho[1]) / ts;
+    // Shan-Chen force of the stored densities and the lattice colour gradient
+    v3 s[2] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    v3 g = {0.0, 0.0, 0.0};
+    for (int i = 1; i < Q; ++i) {
+        const int64_t m = nb_of(a, x, y, z, i);
+        const uint8_t id = a.mat[m] & MAT_ID_MASK;
+        double psi[2], Cn;
+        if (id == MAT_FLUID) {
+            node_rho(a, f, m, psi);
+            const double tn = psi[0] + psi[1];
+            Cn = (psi[0] - psi[1]) / (tn > 0.0 ? tn : 1.0);
+        } else {
+            if (id == MAT_GHOST) {
+                psi[0] = a.rho_top[0];
+                psi[1] = a.rho_top[1];
+            } else {
+                psi[0] = a.psi_tab[2 * id];
+                psi[1] = a.psi_tab[2 * id + 1];
+            }
+            Cn = C0;
+        }
+        const double w = wgt<double>(i);
+        const v3 c = {double(cx(i)), double(cy(i)), double(cz(i))};
+        s[0] = s[0] + (w * psi[1]) * c;  // partner of component A is B
+        s[1] = s[1] + (w * psi[0]) * c;
+        g = g + (3.0 * w * Cn) * c;
+    }
+    v3 F = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 2; ++k) {
+        const double gp = -a.G * rho[k];
+        F = F + v3{gp * s[k].x + rho[k] * a.g[0], gp * s[k].y + rho[k] * a.g[1], gp * s[k].z + rho[k] * a.g[2]};
+    }
+    u = {(js.x - 0.5 * F.x) / ts, (js.y - 0.5 * F.y) / ts, (js.z - 0.5 * F.z) / ts};
+    gc = g;
+}
+
+// ---------------------------------------------------------------------------
+// 1. gather: stencil, renormalised weights, interpolated velocity and grad C
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void fil_gather_kernel(FilArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.n) return;
+    const S *f = static_cast<const S *>(a.f);
+    double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    const v3 X = ld(rec + FIL_X);
+    const double bx = floor(X.x), by = floor(X.y), bz = floor(X.z);
+    const double fr[3] = {X.x - bx, X.y - by, X.z - bz};
+    const int base[3] = {int(bx), int(by), int(bz)};
+    const int dims[3] = {a.nx, a.ny, a.nz}, per[3] = {a.px, a.py, a.pz};
+    int node[8];
+    double w[8];
+    double wsum = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int d[3] = {e & 1, (e >> 1) & 1, e >> 2};
+        int idx[3];
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            idx[q] = base[q] + d[q];
+            if (per[q])
+                idx[q] = wrap_idx(idx[q], dims[q]);
+            else if (idx[q] < 0 || idx[q] >= dims[q])
+                ok = false;
+        }
+        node[e] = -1;
+        w[e] = 0.0;
+        if (!ok) continue;
+        const int64_t n = node_at(a, idx[0], idx[1], idx[2]);
+        if ((a.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
+        node[e] = int(n);
+        w[e] = (d[0] ? fr[0] : 1.0 - fr[0]) * (d[1] ? fr[1] : 1.0 - fr[1]) * (d[2] ? fr[2] : 1.0 - fr[2]);
+        wsum += w[e];
+    }
+    v3 ub = {0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0};
+    const int coupled = wsum > 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if (!coupled || node[e] < 0) {
+            node[e] = -1;
+            w[e] = 0.0;
+            continue;
+        }
+        w[e] = w[e] / wsum;
+        const int64_t n = node[e];
+        const int x = int(n % a.nx), y = int((n / a.nx) % a.ny), z = int(n / (int64_t(a.nx) * a.ny));
+        v3 u, g;
+        node_fields(a, f, x, y, z, u, g);
+        ub = ub + w[e] * u;
+        gb = gb + w[e] * g;
+    }
+    st(rec + FIL_U, ub);
+    st(rec + FIL_GC, gb);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        rec[FIL_W + e] = w[e];
+        a.sten[size_t(b) * 8 + e] = node[e];
+    }
+    rec[FIL_COUPLED] = coupled;
+}
+
+// ---------------------------------------------------------------------------
+// 2. non-bonded partner lists: every other bead within the range plus the
+//    skin, except the chain's own beads at most two apart (their forces are
+//    the bonded ones)
+// ---------------------------------------------------------------------------
+constexpr int LT = 256;
+
+__global__ __launch_bounds__(LT) void fil_list_kernel(FilArgs a, double range2) {
+    __shared__ double sx[LT][3];
+    const int b = blockIdx.x * LT + threadIdx.x;
+    const bool act = b < a.n;
+    v3 X = {0.0, 0.0, 0.0};
+    if (act) {
+        X = ld(a.bead + size_t(b) * FIL_STRIDE + FIL_X);
+        st(a.bead + size_t(b) * FIL_STRIDE + FIL_X0, X);
+    }
+    const int cb = act ? b / a.per_chain : -1, ib = act ? b % a.per_chain : 0;
+    int cnt = 0;
+    for (int t0 = 0; t0 < a.n; t0 += LT) {
+        const int j = t0 + threadIdx.x;
+        if (j < a.n) {
+            const double *r = a.bead + size_t(j) * FIL_STRIDE + FIL_X;
+            sx[threadIdx.x][0] = r[0];
+            sx[threadIdx.x][1] = r[1];
+            sx[threadIdx.x][2] = r[2];
+        }
+        __syncthreads();
+        const int lim = min(LT, a.n - t0);
+        if (act)
+            for (int q = 0; q < lim; ++q) {
+                const int o = t0 + q;
+                if (o == b) continue;
+                if (o / a.per_chain == cb && abs(o % a.per_chain - ib) <= 2) continue;
+                const v3 r = min_image(X - v3{sx[q][0], sx[q][1], sx[q][2]}, a);
+                const double d2 = r.x * r.x + r.y * r.y + r.z * r.z;
+                if (d2 < range2) {
+                    if (cnt < FIL_NBR) a.nbr[size_t(b) * FIL_NBR + cnt] = o;
+                    ++cnt;
+                }
+            }
+        __syncthreads();
+    }
+    if (act) {
+        if (cnt > FIL_NBR) {
+            atomicOr(a.status, ST_ROD_LIST);
+            cnt = FIL_NBR;
+        }
+        a.nbr_cnt[b] = cnt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. substeps: one work-group, positions in shared memory
+// ---------------------------------------------------------------------------
+__device__ inline double phi_d(double d, double d0) {
+    // d/dd of (d0/d)^12 - 2 (d0/d)^6
+    const double q = d0 / d;
+    const double q2 = q * q;
+    const double x6 = q2 * q2 * q2;
+    return 12.0 * (x6 - x6 * x6) / d;
+}
+
+__device__ inline double wca_f(double d, const FilArgs &a) { return d <= a.d0 ? -a.eps * phi_d(d, a.d0) : 0.0; }
+__device__ inline double fene_f(double d, const FilArgs &a) {
+    const double q = d / a.R_m;
+    return -a.k_s * d / (1.0 - q * q);
+}
+__device__ inline double bend_f(double d, const FilArgs &a) { return -a.k_b * (d - 2.0 * a.d0); }
+__device__ inline double coh_f(double d, const FilArgs &a) {
+    return (a.eps_coh > 0.0 && d > a.d0 && d < a.r_cut) ? -a.eps_coh * phi_d(d, a.d0) : 0.0;
+}
+__device__ inline double sub_f(double h, const FilArgs &a) {
+    return (h > 0.0 && h < a.r_cut_s) ? -a.eps_s * phi_d(h, a.sigma_s) : 0.0;
+}
+
+__global__ __launch_bounds__(FIL_TPB) void fil_substep_kernel(FilArgs a) {
+    __shared__ double sX[3 * FIL_MAX];  // bead positions
+    const int tid = threadIdx.x;
+    for (int b = tid; b < a.n; b += FIL_TPB) {
+        const double *r = a.bead + size_t(b) * FIL_STRIDE + FIL_X;
+        sX[3 * b] = r[0];
+        sX[3 * b + 1] = r[1];
+        sX[3 * b + 2] = r[2];
+        st(a.bead + size_t(b) * FIL_STRIDE + FIL_IMP, v3{0.0, 0.0, 0.0});
+    }
+    __syncthreads();
+    const double dt = 1.0 / a.n_sub;
+    const double m = a.mass;
+    unsigned flags = 0;
+    constexpr int PER = (FIL_MAX + FIL_TPB - 1) / FIL_TPB;
+    for (int sub = 0; sub < a.n_sub; ++sub) {
+        v3 Xn[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int b = tid + k * FIL_TPB;
+            if (b >= a.n) break;
+            double *rec = a.bead + size_t(b) * FIL_STRIDE;
+            const v3 X = {sX[3 * b], sX[3 * b + 1], sX[3 * b + 2]};
+            const int ch = b / a.per_chain, ib = b % a.per_chain;
+            v3 Fi = {0.0, 0.0, 0.0};
+            auto pair = [&](int o, int kind) {
+                const v3 r = min_image(X - v3{sX[3 * o], sX[3 * o + 1], sX[3 * o + 2]}, a);
+                const double d = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
+                double fm = 0.0;
+                if (d <= a.d0) fm += wca_f(d, a);
+                if (kind == 1) {
+                    fm += fene_f(d, a);
+                    if (!(d < a.R_m)) flags |= ST_ROD;
+                }
+                if (kind == 2) fm += bend_f(d, a);
+                if (kind == 3) fm += coh_f(d, a);
+                if (fm != 0.0) Fi = Fi + v3{fm * r.x / d, fm * r.y / d, fm * r.z / d};
+            };
+            // every partner in ascending bead index: the chain's bonded ones
+            // (at most two apart) merged into the ascending partner list
+            const int nc = a.nbr_cnt[b];
+            int dj = -2;
+            auto bonded_below = [&](int lim) {
+                for (; dj <= 2; ++dj) {
+                    const int j = ib + dj;
+                    if (dj == 0 || j < 0 || j >= a.per_chain) continue;
+                    const int o = ch * a.per_chain + j;
+                    if (o >= lim) break;
+                    pair(o, dj == -1 || dj == 1 ? 1 : 2);
+                }
+            };
+            for (int q = 0; q < nc; ++q) {
+                const int o = a.nbr[size_t(b) * FIL_NBR + q];
+                bonded_below(o);
+                pair(o, o / a.per_chain == ch ? 0 : 3);
+            }
+            bonded_below(a.n);
+            v3 Fs = {0.0, 0.0, 0.0};
+            const double h = X.z - a.wall_z;
+            if (a.wall_on) Fs.z = sub_f(h, a);
+            const int coupled = rec[FIL_COUPLED] != 0.0;
+            const v3 V = ld(rec + FIL_V);
+            const v3 U = ld(rec + FIL_U);
+            const v3 Fd = coupled ? (-a.gamma) * (V - U) : v3{0.0, 0.0, 0.0};
+            const v3 Fsv = coupled ? a.kappa_s * ld(rec + FIL_GC) : v3{0.0, 0.0, 0.0};
+            const v3 Fo = (Fi + Fd) + Fsv;
+            v3 Ff = {0.0, 0.0, 0.0};
+            if (a.wall_on && h > 0.0 && h < a.r_cut_s) {
+                const double fz = Fo.z + fmin(Fs.z, 0.0);
+                const double N = fmax(0.0, -fz);
+                const double s = sqrt(V.x * V.x + V.y * V.y);
+                if (N > 0.0 && s > 0.0) {
+                    const double c = fmin(a.mu * N / s, m / dt);
+                    Ff = {-V.x * c, -V.y * c, 0.0};
+                }
+            }
+            const v3 imp = ld(rec + FIL_IMP);
+            st(rec + FIL_IMP, imp + dt * ((-1.0) * (Fd + Fsv)));
+            // symplectic Euler: V first, X with the new V
+            const v3 acc = (Fo + Fs) + Ff;
+            const v3 Vx = {V.x + acc.x / m * dt, V.y + acc.y / m * dt, V.z + acc.z / m * dt};
+            st(rec + FIL_V, Vx);
+            v3 Xp = {X.x + Vx.x * dt, X.y + Vx.y * dt, X.z + Vx.z * dt};
+            Xp = {wrap_pos(Xp.x, a.nx, a.px), wrap_pos(Xp.y, a.ny, a.py), wrap_pos(Xp.z, a.nz, a.pz)};
+            Xn[k] = Xp;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int b = tid + k * FIL_TPB;
+            if (b >= a.n) break;
+            sX[3 * b] = Xn[k].x;
+            sX[3 * b + 1] = Xn[k].y;
+            sX[3 * b + 2] = Xn[k].z;
+        }
+        __syncthreads();
+    }
+    for (int b = tid; b < a.n; b += FIL_TPB) {
+        double *rec = a.bead + size_t(b) * FIL_STRIDE;
+        const v3 X = {sX[3 * b], sX[3 * b + 1], sX[3 * b + 2]};
+        st(rec + FIL_X, X);
+        // the partner lists hold for moves below half the skin per step
+        const v3 d = min_image(X - ld(rec + FIL_X0), a);
+        if (d.x * d.x + d.y * d.y + d.z * d.z > 0.25 * a.skin * a.skin) flags |= ST_ROD;
+        if (!(X.x == X.x && X.y == X.y && X.z == X.z)) flags |= ST_NAN;
+    }
+    if (flags) atomicOr(a.status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// 4. spread the impulses onto the fixed-point momentum grid
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fil_spread_kernel(FilArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.n) return;
+    const double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    if (rec[FIL_COUPLED] == 0.0) return;
+    const double imp[3] = {rec[FIL_IMP], rec[FIL_IMP + 1], rec[FIL_IMP + 2]};
+    for (int e = 0; e < 8; ++e) {
+        const int n = a.sten[size_t(b) * 8 + e];
+        if (n < 0) continue;
+        const double w = rec[FIL_W + e];
+        for (int d = 0; d < 3; ++d) {
+            const long long q = llrint(w * imp[d] * FIX_SCALE);
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.grid + int64_t(d) * a.fs + n),
+                      static_cast<unsigned long long>(q));
+        }
+        a.claim[n] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. apply the summed momentum by the exact-difference rule
+// ---------------------------------------------------------------------------
+__device__ inline double feq_i(int i, double rho, v3 u) {
+    const double cu = cx(i) * u.x + cy(i) * u.y + cz(i) * u.z;
+    const double usq = u.x * u.x + u.y * u.y + u.z * u.z;
+    return wgt<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void fil_apply_kernel(FilArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n * 8) return;
+    const int n = a.sten[t];
+    if (n < 0) return;
+    if (atomicExch(a.claim + n, 0) != 1) return;
+    v3 dp;
+    unsigned long long *g = reinterpret_cast<unsigned long long *>(a.grid);
+    dp.x = double(static_cast<long long>(atomicExch(g + n, 0ull))) * FIX_INV;
+    dp.y = double(static_cast<long long>(atomicExch(g + a.fs + n, 0ull))) * FIX_INV;
+    dp.z = double(static_cast<long long>(atomicExch(g + 2 * a.fs + n, 0ull))) * FIX_INV;
+    S *f = static_cast<S *>(a.f);
+    double rho[2];
+    v3 uk[2];
+    for (int k = 0; k < 2; ++k) {
+        double r = 0.0;
+        v3 j = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; ++i) {
+            const double fi = popf(a, f, k, i, n);
+            r += fi;
+            j = j + v3{cx(i) * fi, cy(i) * fi, cz(i) * fi};
+        }
+        rho[k] = r;
+        uk[k] = r > 0.0 ? v3{j.x / r, j.y / r, j.z / r} : v3{0.0, 0.0, 0.0};
+    }
+    const double tot = rho[0] + rho[1];
+    if (!(tot > 0.0)) return;
+    const v3 du = {dp.x / tot, dp.y / tot, dp.z / tot};
+    // a node next to a static wall has already handed f*_j to the wall node
+    // x + c_j as direction opp(j) (halfway bounce-back of the next pull): the
+    // updated value goes there too
+    const bool near_wall = (a.mat[n] & MAT_NEAR_WALL) != 0;
+    const int x = int(n % a.nx), y = int((n / a.nx) % a.ny), z = int(n / (int64_t(a.nx) * a.ny));
+    // the plane below the reservoir booked the outflow of its stored f* when
+    // the fluid step wrote it; the change of that outflow goes to the ledger
+    const bool top = a.evap && z == a.nz - 2;
+    for (int k = 0; k < 2; ++k) {
+        if (!(rho[k] > 0.0)) continue;
+        const v3 un = uk[k] + du;
+        double dout = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            const int64_t idx = (int64_t(k) * Q + i) * a.fs + n;
+            const double fi = popf(a, f, k, i, n);
+            const double v = fi + (feq_i(i, rho[k], un) - feq_i(i, rho[k], uk[k]));
+            const S sv = Codec<S>::enc(static_cast<typename Codec<S>::C>(v - wgt<double>(i) * a.rho_ref[k]));
+            f[idx] = sv;
+            if (top && cz(i) == 1) dout += popf(a, f, k, i, n) - fi;
+            if (near_wall && i > 0) {
+                const int64_t q = nb_of(a, x, y, z, i);
+                if (is_static_wall(a.mat[q] & MAT_ID_MASK)) f[(int64_t(k) * Q + opp(i)) * a.fs + q] = sv;
+            }
+        }
+        if (top && dout != 0.0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.led + k),
+                      static_cast<unsigned long long>(llrint(dout * FIX_SCALE)));
+    }
+}
+
+template <class F>
+static hipError_t fil_by_prec(int prec, F &&fn) {
+    switch (prec) {
+        case LB_F64:
+            return fn(static_cast<double *>(nullptr));
+        case LB_F32:
+            return fn(static_cast<float *>(nullptr));
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const int g = (a.n + 255) / 256;
+    double range = a.d0;
+    if (a.eps_coh > 0.0 && a.r_cut > range) range = a.r_cut;
+    range += a.skin;
+    return fil_by_prec(prec, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(fil_gather_kernel<S>, dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(fil_list_kernel, dim3((a.n + LT - 1) / LT), dim3(LT), 0, s, a, range * range);
+        hipLaunchKernelGGL(fil_substep_kernel, dim3(1), dim3(FIL_TPB), 0, s, a);
+        hipLaunchKernelGGL(fil_spread_kernel, dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(fil_apply_kernel<S>, dim3((a.n * 8 + 255) / 256), dim3(256), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace lbm

@@ -136,10 +136,12 @@ static size_t obs_bytes(const lb_params *p) { return obs_layout(p).total; }
 
 struct WsLayout {
     size_t mat, ledger, heights, status, partials, result, psi, carry, rods, rodid, newid, rodsum, rodpart, shell, shell_cnt,
-        nbr, nbr_cnt, rodargs, rho, cg, obs, total;
+        nbr, nbr_cnt, rodargs, rho, cg, fil, fil_sten, fil_nbr, fil_cnt, fil_grid, fil_claim, fil_led, obs, total;
     int max_tiles;
     int nslots;  // ledger slot pairs
 };
+
+int fil_beads(const lb_params *p) { return p->n_fil > 0 && p->fil_beads > 0 ? p->n_fil * p->fil_beads : 0; }
 
 WsLayout ws_layout(const lb_params *p) {
     WsLayout w{};
@@ -189,7 +191,26 @@ WsLayout ws_layout(const lb_params *p) {
     // fluid densities of the current state in compute precision, written by
     // the fluid step for the rod passes
     w.rho = o;
-    o = align256(o + (rods ? 2 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
+    const bool dens = rods || fil_beads(p) > 0;
+    o = align256(o + (dens ? 2 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
+    // filaments: bead records, stencils, partner lists, the fixed-point
+    // momentum grid [3][fs] and its claim flags [fs]
+    const size_t nb = size_t(fil_beads(p));
+    const bool fil = nb > 0;
+    w.fil = o;
+    o = align256(o + nb * FIL_STRIDE * sizeof(double));
+    w.fil_sten = o;
+    o = align256(o + nb * 8 * sizeof(int));
+    w.fil_nbr = o;
+    o = align256(o + nb * FIL_NBR * sizeof(int));
+    w.fil_cnt = o;
+    o = align256(o + nb * sizeof(int));
+    w.fil_grid = o;
+    o = align256(o + (fil ? 3 * size_t(lb_pop_stride(p)) * sizeof(long long) : 0));
+    w.fil_claim = o;
+    o = align256(o + (fil ? size_t(lb_pop_stride(p)) * sizeof(int) : 0));
+    w.fil_led = o;
+    o = align256(o + (fil ? 2 * sizeof(long long) : 0));
     // colour-gradient step: colour [fs] and normal [4][fs] in compute precision
     w.cg = o;
     o = align256(o + (p->model == LB_MODEL_CG ? 5 * size_t(lb_pop_stride(p)) * (p->prec == LB_F64 ? 8 : 4) : 0));
@@ -245,6 +266,24 @@ int validate(const lb_params *p) {
         for (int m = 0; m < LB_NMAT; ++m)
             if (!(p->cg_theta[m] >= 0.0 && p->cg_theta[m] <= M_PI))
                 return fail(LB_EINVAL, "contact angle of material %d outside [0, pi]", m);
+    }
+    if (p->n_fil < 0 || p->fil_beads < 0) return fail(LB_EINVAL, "negative filament count");
+    if (p->n_fil > 0) {
+        if (p->fil_beads < 1) return fail(LB_EINVAL, "filaments need at least one bead each");
+        if (int64_t(p->n_fil) * p->fil_beads > LB_FIL_MAX_BEADS)
+            return fail(LB_EINVAL, "%lld beads exceed LB_FIL_MAX_BEADS = %d", (long long)p->n_fil * p->fil_beads,
+                        LB_FIL_MAX_BEADS);
+        if (p->prec != LB_F64 && p->prec != LB_F32) return fail(LB_ENOTSUP, "filaments run with FP64 or FP32 storage");
+        if (p->model != LB_MODEL_SC || p->n_rods > 0)
+            return fail(LB_ENOTSUP, "filaments run with the Shan-Chen step and without rods");
+        if (p->n_sub < 1) return fail(LB_EINVAL, "n_sub must be >= 1");
+        if (!(p->fil_d0 > 0.0) || !(p->fil_R_m > 0.0) || !(p->fil_k_s >= 0.0) || !(p->fil_k_b >= 0.0) ||
+            !(p->fil_eps >= 0.0) || !(p->fil_eps_coh >= 0.0) || !(p->fil_gamma >= 0.0) || !isfinite(p->fil_kappa_s) ||
+            !(p->fil_mu >= 0.0) || !(p->fil_skin > 0.0) || !(p->fil_eps_s >= 0.0))
+            return fail(LB_EINVAL, "bad filament parameters");
+        if (p->fil_eps_coh > 0.0 && !(p->fil_r_cut > p->fil_d0)) return fail(LB_EINVAL, "cohesion cut-off must exceed d0");
+        if (p->wall_on && (!(p->fil_sigma_s > 0.0) || !(p->fil_r_cut_s > 0.0)))
+            return fail(LB_EINVAL, "bad substrate interaction");
     }
     // the integrator keeps 13 doubles per rod in one work-group's shared memory
     if (p->n_rods < 0 || p->n_rods > LB_MAX_RODS)
@@ -320,6 +359,11 @@ struct lb_ctx {
     void *rho;                 // [2][fs] fluid densities for the rod passes (lattices with rods)
     void *cg;                  // colour-gradient step: colour [fs] and normal [4][fs], or null
     int rho_fresh;             // rho holds the densities of the current state
+    double *fil;               // filament bead records, or null
+    int *fil_sten, *fil_nbr, *fil_cnt, *fil_claim;
+    long long *fil_grid;
+    long long *fil_led;        // [2] reservoir ledger change from the filament impulses (2^-50 units)
+    int fil_ready;             // lb_fil_set has uploaded the beads
     RodArgs rodargs_host[2];
     double psi_host[32];
     TileCfg tile;
@@ -497,7 +541,15 @@ int lb_init(const lb_params *p, const lb_buffers *buf, const double *rho_init_ho
     c->nbr_cnt = reinterpret_cast<int *>(ws + w.nbr_cnt);
     c->obs = ws + w.obs;
     c->rodargs_dev = reinterpret_cast<RodArgs *>(ws + w.rodargs);
-    c->rho = p->n_rods > 0 ? static_cast<void *>(ws + w.rho) : nullptr;
+    c->rho = (p->n_rods > 0 || fil_beads(p) > 0) ? static_cast<void *>(ws + w.rho) : nullptr;
+    c->fil = fil_beads(p) > 0 ? reinterpret_cast<double *>(ws + w.fil) : nullptr;
+    c->fil_sten = reinterpret_cast<int *>(ws + w.fil_sten);
+    c->fil_nbr = reinterpret_cast<int *>(ws + w.fil_nbr);
+    c->fil_cnt = reinterpret_cast<int *>(ws + w.fil_cnt);
+    c->fil_grid = reinterpret_cast<long long *>(ws + w.fil_grid);
+    c->fil_claim = reinterpret_cast<int *>(ws + w.fil_claim);
+    c->fil_led = reinterpret_cast<long long *>(ws + w.fil_led);
+    c->fil_ready = 0;
     c->cg = p->model == LB_MODEL_CG ? static_cast<void *>(ws + w.cg) : nullptr;
     c->rho_fresh = 0;
     for (int m = 0; m < 16; ++m)
@@ -697,6 +749,9 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
         HIP_TRY(launch_rods_sums(rod_args(c), c->rodsum, stream), "rod sums");
         HIP_TRY(hipMemcpyAsync(rs, c->rodsum, sizeof rs, hipMemcpyDeviceToHost, stream), "copy rod sums");
     }
+    long long fl[2] = {0, 0};
+    if (c->fil && c->fil_ready)
+        HIP_TRY(hipMemcpyAsync(fl, c->fil_led, sizeof fl, hipMemcpyDeviceToHost, stream), "copy filament ledger");
     HIP_TRY(hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, stream), "copy observables");
     HIP_TRY(hipMemcpyAsync(&st, c->status, sizeof st, hipMemcpyDeviceToHost, stream), "copy status");
     HIP_TRY(hipStreamSynchronize(stream), "observables sync");
@@ -704,8 +759,8 @@ int lb_observables(lb_ctx *c, lb_obs *out, hipStream_t stream) {
     out->step = c->steps;
     out->mass[0] = r[0];
     out->mass[1] = r[1];
-    out->ledger[0] = r[2];
-    out->ledger[1] = r[3];
+    out->ledger[0] = r[2] + double(fl[0]) / FIL_FIX;
+    out->ledger[1] = r[3] + double(fl[1]) / FIL_FIX;
     out->momentum[0] = r[4];
     out->momentum[1] = r[5];
     out->momentum[2] = r[6];
@@ -1352,6 +1407,105 @@ int lb_rods_get(lb_ctx *c, double *out_host, hipStream_t stream) {
     return LB_OK;
 }
 
+static FilArgs fil_args(lb_ctx *c) {
+    const lb_params &p = c->p;
+    FilArgs a{};
+    a.f = c->f[c->cur];
+    a.rho = c->rho;
+    a.rho_fresh = c->rho_fresh;
+    a.mat = c->mat;
+    a.psi_tab = c->psi;
+    a.bead = c->fil;
+    a.sten = c->fil_sten;
+    a.nbr = c->fil_nbr;
+    a.nbr_cnt = c->fil_cnt;
+    a.grid = c->fil_grid;
+    a.claim = c->fil_claim;
+    a.led = c->fil_led;
+    a.evap = p.evap_on;
+    a.status = c->status;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.px = p.periodic[0];
+    a.py = p.periodic[1];
+    a.pz = p.periodic[2];
+    a.fs = c->fs;
+    a.n = fil_beads(&p);
+    a.per_chain = p.fil_beads;
+    a.n_sub = p.n_sub;
+    a.k_s = p.fil_k_s;
+    a.R_m = p.fil_R_m;
+    a.eps = p.fil_eps;
+    a.d0 = p.fil_d0;
+    a.k_b = p.fil_k_b;
+    a.eps_coh = p.fil_eps_coh;
+    a.r_cut = p.fil_r_cut;
+    a.eps_s = p.fil_eps_s;
+    a.sigma_s = p.fil_sigma_s;
+    a.r_cut_s = p.fil_r_cut_s;
+    a.mu = p.fil_mu;
+    a.gamma = p.fil_gamma;
+    a.kappa_s = p.fil_kappa_s;
+    a.mass = M_PI * p.fil_d0 * p.fil_d0 * p.fil_d0 / 6.0;
+    a.skin = p.fil_skin;
+    a.wall_on = p.wall_on;
+    a.wall_z = p.wall_z;
+    a.G = p.G;
+    for (int d = 0; d < 3; ++d) a.g[d] = p.body_force[d];
+    for (int k = 0; k < 2; ++k) {
+        a.rho_top[k] = p.rho_top[k];
+        a.rho_ref[k] = c->rref[k];
+    }
+    return a;
+}
+
+int lb_fil_set(lb_ctx *c, const double *beads_host, hipStream_t stream) {
+    if (!c || !beads_host) return fail(LB_EINVAL, "null argument");
+    const int n = fil_beads(&c->p);
+    if (n == 0) return fail(LB_EINVAL, "the lattice has no filaments");
+    std::vector<double> rec(size_t(n) * FIL_STRIDE, 0.0);
+    for (int b = 0; b < n; ++b)
+        for (int q = 0; q < 6; ++q) {
+            const double v = beads_host[6 * b + q];
+            if (!isfinite(v)) return fail(LB_EINVAL, "bead %d: non-finite state", b);
+            rec[size_t(b) * FIL_STRIDE + FIL_X + q] = v;  // X then V
+        }
+    HIP_TRY(hipMemcpyAsync(c->fil, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload beads");
+    HIP_TRY(hipMemsetAsync(c->fil_grid, 0, 3 * size_t(c->fs) * sizeof(long long), stream), "clear momentum grid");
+    HIP_TRY(hipMemsetAsync(c->fil_claim, 0, size_t(c->fs) * sizeof(int), stream), "clear claims");
+    HIP_TRY(hipMemsetAsync(c->fil_led, 0, 2 * sizeof(long long), stream), "clear filament ledger");
+    HIP_TRY(hipMemsetAsync(c->fil_sten, 0xFF, size_t(n) * 8 * sizeof(int), stream), "clear stencils");
+    HIP_TRY(hipStreamSynchronize(stream), "beads sync");
+    c->fil_ready = 1;
+    return LB_OK;
+}
+
+int lb_fil_step(lb_ctx *c, hipStream_t stream) {
+    if (!c) return fail(LB_EINVAL, "null ctx");
+    if (fil_beads(&c->p) == 0) return LB_OK;
+    if (!c->fil_ready) return fail(LB_EINVAL, "lb_fil_set has not been called");
+    HIP_TRY(launch_fil_step(c->p.prec, fil_args(c), stream), "filament step");
+    return LB_OK;
+}
+
+int lb_fil_get(lb_ctx *c, double *out_host, hipStream_t stream) {
+    const int n = c ? fil_beads(&c->p) : 0;
+    if (!c || (!out_host && n > 0)) return fail(LB_EINVAL, "null argument");
+    if (n == 0) return LB_OK;
+    std::vector<double> tmp(size_t(n) * FIL_STRIDE);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), c->fil, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, stream), "copy beads");
+    HIP_TRY(hipStreamSynchronize(stream), "beads sync");
+    for (int b = 0; b < n; ++b) {
+        const double *r = tmp.data() + size_t(b) * FIL_STRIDE;
+        double *o = out_host + 12 * size_t(b);
+        for (int q = 0; q < 6; ++q) o[q] = r[FIL_X + q];
+        for (int q = 0; q < 3; ++q) o[6 + q] = r[FIL_U + q];
+        for (int q = 0; q < 3; ++q) o[9 + q] = r[FIL_IMP + q];
+    }
+    return LB_OK;
+}
+
 int lb_set_tiles(lb_ctx *c, const lb_tile *t, hipStream_t stream) {
     if (!c || !t) return fail(LB_EINVAL, "null argument");
     const bool tau1 = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
@@ -1503,6 +1657,8 @@ int batch_check(lb_ctx *const *ctxs, int n) {
             return fail(LB_ENOTSUP, "lattice %d rounds stochastically, which a batch does not run", i);
         if (ctxs[i]->p.model != LB_MODEL_SC)
             return fail(LB_ENOTSUP, "lattice %d runs the colour-gradient step, which a batch does not run", i);
+        if (fil_beads(&ctxs[i]->p) > 0)
+            return fail(LB_ENOTSUP, "lattice %d carries filaments, which a batch does not run", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(LB_EINVAL, "lattice %d appears twice", i);
     }

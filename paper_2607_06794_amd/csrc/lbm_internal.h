@@ -119,6 +119,42 @@ hipError_t launch_rods_jump(const RodArgs &a, const RodBatch &bt, const float *c
                             double steps, hipStream_t s);
 hipError_t launch_rods_link(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s);
 
+// Bead-spring filaments (filaments.hip): bead records FIL_STRIDE doubles
+constexpr int FIL_STRIDE = 32;
+constexpr int FIL_X = 0, FIL_V = 3;       // position, velocity
+constexpr int FIL_U = 6, FIL_GC = 9;      // interpolated fluid velocity and colour gradient of this step
+constexpr int FIL_IMP = 12, FIL_X0 = 15;  // impulse given to the fluid this step; position at list time
+constexpr int FIL_W = 18;                 // [8] renormalised stencil weights
+constexpr int FIL_COUPLED = 26;           // 1 when a stencil node is fluid
+constexpr int FIL_NBR = 48;               // non-bonded partners per bead
+constexpr int FIL_MAX = LB_FIL_MAX_BEADS; // beads per lattice (positions of all in one work-group's LDS)
+constexpr int FIL_TPB = 1024;
+constexpr double FIL_FIX = 1125899906842624.0;  // 2^50: fixed-point unit of the momentum grid and ledger
+
+struct FilArgs {
+    void *f;          // current populations (post-collision state)
+    const void *rho;  // [2][fs] densities of the current state (compute precision)
+    int rho_fresh;    // 1: rho holds them; 0: sum the populations
+    const uint8_t *mat;
+    const double *psi_tab;  // [16][2] ghost pseudo-densities per material id
+    double *bead;           // [n][FIL_STRIDE]
+    int *sten;              // [n][8] stencil node indices (-1: none)
+    int *nbr, *nbr_cnt;     // [n][FIL_NBR], [n]
+    long long *grid;        // [3][fs] momentum per node in units of 2^-50
+    int *claim;             // [fs] 1: grid entry waiting to be applied
+    long long *led;         // [2] reservoir ledger change from the impulses, units of 2^-50
+    int evap;               // the plane z = nz - 1 is the reservoir
+    unsigned *status;
+    int nx, ny, nz, px, py, pz;
+    int64_t fs;
+    int n, per_chain, n_sub;
+    double k_s, R_m, eps, d0, k_b, eps_coh, r_cut, eps_s, sigma_s, r_cut_s, mu, gamma, kappa_s, mass, skin;
+    int wall_on;
+    double wall_z;
+    double G, g[3], rho_top[2], rho_ref[2];
+};
+hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s);
+
 hipError_t launch_sc_step(int prec, bool tau1, const TileCfg &t, const StepArgs &a, hipStream_t s);
 // all: device array of per-lattice step records; work: device list of
 // (lattice, logical tile) entries, (-1, -1) for padding

@@ -197,6 +197,62 @@ def place_rods(n_req, length, radius, box, inside=None, seed=3000, gap=1.0, marg
     return np.array(placed).reshape(-1, 13)
 
 
+def place_filaments(n_req, n_per, spacing, box, inside=None, seed=3500, clearance=2.5, margin=1.0, zmin=2.0,
+                    max_trials=100000):
+    """Random sequential placement of straight bead chains.
+
+    box: (nx, ny, nz).  Each trial draws a centre uniform in the box (3
+    uniforms) and an axis from a normalised Gaussian triplet (3 normals), in
+    that order, from PCG64(seed); the chain's n_per beads sit at
+    centre + (b - (n_per - 1) / 2) spacing axis.  A trial is accepted when
+    every bead is at least ``zmin`` above z = 0 and below nz - 1 - zmin,
+    ``inside`` (if given) holds at each bead and at the six points ``margin``
+    away from it along the axes, and every bead is at least ``clearance``
+    from every bead already placed (minimum image in x and y).  Stops after
+    n_req chains or max_trials trials.  Returns [n * n_per][6]: positions
+    (x, y, z) and zero velocities.
+    """
+    rng = _rng(seed)
+    nx, ny, nz = box
+    offs = (np.arange(n_per) - 0.5 * (n_per - 1)) * spacing
+    placed = []
+    for _ in range(max_trials):
+        if len(placed) >= n_req:
+            break
+        c = rng.uniform(0.0, 1.0, 3) * np.array([nx, ny, nz], dtype=np.float64)
+        e = rng.normal(size=3)
+        e /= np.linalg.norm(e)
+        beads = c[None, :] + offs[:, None] * e[None, :]
+        if beads[:, 2].min() < zmin or beads[:, 2].max() > nz - 1 - zmin:
+            continue
+        if inside is not None:
+            ok = True
+            for q in beads:
+                for d in ([0, 0, 0], [margin, 0, 0], [-margin, 0, 0], [0, margin, 0], [0, -margin, 0],
+                          [0, 0, margin], [0, 0, -margin]):
+                    if not inside(*(q + np.array(d, dtype=np.float64))):
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                continue
+        if placed:
+            other = np.concatenate(placed)
+            d = beads[:, None, :] - other[None, :, :]
+            d[..., 0] -= nx * np.round(d[..., 0] / nx)
+            d[..., 1] -= ny * np.round(d[..., 1] / ny)
+            if np.sqrt((d * d).sum(-1)).min() < clearance:
+                continue
+        beads[:, 0] %= nx
+        beads[:, 1] %= ny
+        placed.append(beads)
+    if not placed:
+        return np.zeros((0, 6))
+    X = np.concatenate(placed)
+    return np.concatenate([X, np.zeros_like(X)], axis=1)
+
+
 def cap_inside(spec: CapSpec):
     """Membership test of the sessile cap of ``sessile_cap`` (continuous coordinates)."""
     nz, ny, nx = spec.shape

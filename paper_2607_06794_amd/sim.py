@@ -58,6 +58,23 @@ class LatticeParams:
     # 16-bit storage: "nearest" (round to nearest even) or "stochastic"
     rounding: str = "nearest"
     sr_seed: int = 0
+    # bead-spring filaments: n_fil chains of fil_beads beads (see lb_params)
+    n_fil: int = 0
+    fil_beads: int = 6
+    fil_k_s: float = 0.3
+    fil_R_m: float = 2.4
+    fil_eps: float = 0.03
+    fil_d0: float = 2.0
+    fil_k_b: float = 8.0
+    fil_eps_coh: float = 0.0
+    fil_r_cut: float = 3.0
+    fil_eps_s: float = 0.006
+    fil_sigma_s: float = 1.0
+    fil_r_cut_s: float = 2.5
+    fil_mu: float = 0.5
+    fil_gamma: float = 1.0
+    fil_kappa_s: float = 0.05
+    fil_skin: float = 1.0
 
     def to_c(self) -> _lib.LbParams:
         p = _lib.LbParams()
@@ -98,6 +115,10 @@ class LatticeParams:
             p.cg_theta[m] = float(th[m]) if m < th.shape[0] else np.pi / 2
         p.round_stochastic = {"nearest": 0, "stochastic": 1}[self.rounding]
         p.sr_seed = int(self.sr_seed) & 0xFFFFFFFF
+        p.n_fil, p.fil_beads = int(self.n_fil), int(self.fil_beads)
+        for name in ("k_s", "R_m", "eps", "d0", "k_b", "eps_coh", "r_cut", "eps_s", "sigma_s", "r_cut_s", "mu", "gamma",
+                     "kappa_s", "skin"):
+            setattr(p, "fil_" + name, float(getattr(self, "fil_" + name)))
         p.sink_on = int(self.sink is not None)
         if self.sink is not None:
             p.sink_J0, p.sink_K, p.sink_h0 = (float(v) for v in self.sink)
@@ -115,8 +136,10 @@ class Lattice:
     """One lattice on one GPU: caller-owned buffers plus a liblbm context."""
 
     def __init__(self, params: LatticeParams, rho0: np.ndarray, material: np.ndarray, device="cuda:0", stream=None,
-                 rods: np.ndarray | None = None):
-        """rods: optional FP64 [n][13] array (X, q (w,x,y,z), V, L) per rod."""
+                 rods: np.ndarray | None = None, beads: np.ndarray | None = None):
+        """rods: optional FP64 [n][13] array (X, q (w,x,y,z), V, L) per rod;
+        beads: FP64 [n_fil * fil_beads][6] positions and velocities of the
+        filaments' beads (params.n_fil > 0)."""
         import torch
 
         self.lib = _lib.load()
@@ -156,6 +179,11 @@ class Lattice:
                 ct.byref(self._ctx),
             )
         _lib.check(rc)
+        self.n_beads = int(params.n_fil) * int(params.fil_beads) if params.n_fil > 0 else 0
+        if self.n_beads:
+            b = np.ascontiguousarray(beads, dtype=np.float64).reshape(self.n_beads, 6)
+            with torch.cuda.device(self.device):
+                _lib.check(self.lib.lb_fil_set(self._ctx, b.ctypes.data_as(ct.c_void_p), _stream_ptr(self.stream)))
 
     # ------------------------------------------------------------------
     def step(self, n: int = 1):
@@ -170,12 +198,26 @@ class Lattice:
         _lib.check(self.lib.lb_rods_step(self._ctx, _stream_ptr(self.stream)))
         return self
 
+    def filament_step(self):
+        _lib.check(self.lib.lb_fil_step(self._ctx, _stream_ptr(self.stream)))
+        return self
+
     def coupled_step(self, n: int = 1):
-        """n coupled steps: one fluid step then one rod update each."""
+        """n coupled steps: one fluid step then one rod or filament update each."""
         for _ in range(int(n)):
             self.step(1)
-            self.rods_step()
+            if self.n_beads:
+                self.filament_step()
+            else:
+                self.rods_step()
         return self
+
+    def beads(self) -> np.ndarray:
+        """[n_beads][12]: position, velocity, interpolated fluid velocity and
+        the impulse handed to the fluid in the last filament update."""
+        out = np.zeros((self.n_beads, 12))
+        _lib.check(self.lib.lb_fil_get(self._ctx, out.ctypes.data_as(ct.c_void_p), _stream_ptr(self.stream)))
+        return out
 
     def rods(self) -> np.ndarray:
         out = np.zeros((self.n_rods, 13))
