@@ -135,8 +135,10 @@ typedef struct {
     /* 16-bit storage forms: 0 round to nearest even, 1 stochastic rounding
      * (the value goes to the upper of its two representable neighbours with
      * probability equal to its distance from the lower one over their
-     * spacing; random bits from a counter-based hash of node, population
-     * array, step and sr_seed), which keeps the stored errors unbiased.  Only
+     * spacing; random bits from a xorshift32 stream per node and step,
+     * seeded by a hash of node, step and sr_seed and advanced per population
+     * array, so they depend on node, array and step only), which keeps the
+     * stored errors unbiased.  Only
      * the fused Shan-Chen step rounds stochastically (lb_init, the rod passes
      * and the surrogate's lift round to nearest); a batch does not take such
      * lattices (LB_ENOTSUP). */

@@ -111,8 +111,10 @@ struct Codec<bf16_t> {
 // neighbouring representable numbers goes to the upper one with probability
 // equal to its distance from the lower one in units of their spacing, so the
 // stored errors have zero mean (round to nearest biases the mass of a state
-// whose values cluster).  The random bits come from a counter-based hash of
-// (node, population array, step); the same key always gives the same result.
+// whose values cluster).  Random bits: a xorshift32 stream per node and step,
+// seeded by a hash of (node, step key); each 32-bit draw serves two
+// population arrays (16 bits each) in array order, so the bits of an element
+// depend on (node, array, step) only.
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t hash32(uint32_t x) {
     // xorshift-multiply finaliser (two 32-bit multiplies, three shifts)
@@ -123,9 +125,30 @@ __device__ inline uint32_t hash32(uint32_t x) {
     x ^= x >> 16;
     return x;
 }
-__device__ inline uint32_t sr_bits(uint32_t step_key, int64_t node, int array) {
-    return hash32(uint32_t(node) * 38u + uint32_t(array) + hash32(step_key ^ uint32_t(node >> 32)));
+// nonzero seed of a node's stream in the step keyed by step_key
+__device__ inline uint32_t sr_seed(uint32_t step_key, int64_t node) {
+    return hash32(uint32_t(node) ^ hash32(step_key ^ uint32_t(node >> 32))) | 1u;
 }
+// Marsaglia's xorshift32 (shifts 13, 17, 5): full period on nonzero states
+__device__ inline uint32_t xorshift32(uint32_t x) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
+// 16 random bits for population array arr (0, 1, 2, ... in order): even
+// arrays advance the stream and take its low half, odd ones its high half
+struct SrStream {
+    uint32_t state, word;
+    __device__ inline uint32_t bits(int arr) {
+        if ((arr & 1) == 0) {
+            state = xorshift32(state);
+            word = state;
+            return word & 0xffffu;
+        }
+        return word >> 16;
+    }
+};
 
 template <class S>
 struct Stochastic {
@@ -133,20 +156,23 @@ struct Stochastic {
     __device__ static inline S enc(typename Codec<S>::C v, uint32_t) { return Codec<S>::enc(v); }
 };
 
-// IEEE half: round to nearest of v + (r - 1/2) ulp(v), r uniform on 13 bits,
-// is the upper neighbour with probability (v - lower) / ulp; the shift is
-// exact in FP32 (ulp of half = 2^13 ulp of float in the same binade, and a
-// fixed 2^-24 below the normal range)
+// IEEE half from float, r: 16 random bits.  From 2^-14 up the float keeps
+// 13 more fraction bits than the half: adding 13 random bits to the
+// magnitude's bit pattern and clearing them rounds up with probability
+// (v - lower) / spacing, and the conversion of the result is exact (a carry
+// moves on into the exponent, the next representable number; beyond the
+// half's range the conversion overflows as a plain one would).  Below 2^-14
+// the half's spacing is the fixed 2^-24: there round to nearest of
+// v + (r - 1/2) 2^-24, exact in float (a rarely taken branch).
 template <>
 struct Stochastic<_Float16> {
     __device__ static inline _Float16 enc(float v, uint32_t r) {
         const uint32_t u = __float_as_uint(v);
-        const int e = int((u >> 23) & 0xFFu) - 127;  // binade of |v|
-        const int ue = e - 10 < -24 ? -24 : e - 10;  // exponent of the half spacing
-        if (e > 15) return static_cast<_Float16>(v);  // beyond the half range: plain conversion
-        const float ulp = __uint_as_float(uint32_t(ue + 127) << 23);
-        const float dither = (float(int(r >> 19)) * (1.0f / 8192.0f) - 0.5f) * ulp;
-        return static_cast<_Float16>(v + dither);
+        if (__builtin_expect(((u >> 23) & 0xFFu) < 113u, 0)) {
+            const float dither = (float(int(r & 0x1FFFu)) * (1.0f / 8192.0f) - 0.5f) * 5.9604644775390625e-08f;
+            return static_cast<_Float16>(v + dither);
+        }
+        return static_cast<_Float16>(__uint_as_float((u + (r & 0x1FFFu)) & ~0x1FFFu));
     }
 };
 

@@ -557,11 +557,15 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
             const uint32_t voE = own[r].xy[1][1] * E;
             const bool near_wall = fluid && (cur_m[r] & MAT_NEAR_WALL) != 0;
             // 16-bit storage with stochastic rounding: the random bits depend on
-            // (node, array, step) only, so the wall slot gets the same value
+            // (node, array, step) only; the wall slots reuse the encoded values
             const int64_t gnode = int64_t(z) * nxy + own[r].xy[1][1];
+            SrStream sr{0u, 0u};
+            if constexpr (sizeof(S) == 2) {
+                if (a.sr_key) sr.state = sr_seed(a.sr_key, gnode);
+            }
             auto encode = [&](C v, int arr) -> S {
                 if constexpr (sizeof(S) == 2) {
-                    if (a.sr_key) return Stochastic<S>::enc(v, sr_bits(a.sr_key, gnode, arr));
+                    if (a.sr_key) return Stochastic<S>::enc(v, sr.bits(arr));
                 }
                 return Codec<S>::enc(v);
             };
@@ -574,7 +578,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                 for (int d = 0; d < 3; ++d) ue[d] = up[d] + F[k][d] * rk;
                 const C usq = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
                 const C dr = cur_drho[r][k];
-                C fstar[Q];
+                S sstar[Q];
                 C deq_sum = C(0);
                 // Eq. 2 as a deviation, built per opposite pair (i, opp(i)):
                 //   f^eq - w rref = w (rho - rref) + w rho [9/2 (c.u)^2 - 3/2 u^2]  +-  w rho 3 c.u
@@ -614,8 +618,8 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                             }
                         }
                     }
-                    fstar[i] = ds;
-                    buf_store<S>(encode(ds, k * Q + i), dst[k], voE, i * fsE + zE);
+                    sstar[i] = encode(ds, k * Q + i);
+                    buf_store<S>(sstar[i], dst[k], voE, i * fsE + zE);
                 }
                 if (ledger_plane && fluid) {
                     // this step's streaming moves the node's stored f*_i(t) with c_iz = +1
@@ -642,7 +646,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                         const uint32_t nxyo = own[r].xy[1 + cy(jd)][1 + cx(jd)];
                         const uint8_t nm = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(matr, nxyo, zl[1 + cz(jd)], 0));
                         if (is_static_wall(nm & MAT_ID_MASK))
-                            buf_store<S>(encode(fstar[jd], k * Q + jd), dst[k], nxyo * E,
+                            buf_store<S>(sstar[jd], dst[k], nxyo * E,
                                          opp(jd) * fsE + zl[1 + cz(jd)] * E);
                     }
                 }
