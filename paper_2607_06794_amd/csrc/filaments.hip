@@ -9,16 +9,16 @@
 // substeps per lattice step.
 //
 // One filament update, after the fluid step, in five launches:
-//   gather   one thread per bead: the eight lattice nodes around the bead,
+//   gather   eight lanes per bead: the eight lattice nodes around the bead,
 //            their trilinear weights renormalised over fluid nodes, the
 //            physical velocity (sum_k j*_k - F/2) / rho and the colour
 //            gradient 3 sum_i w_i C(x + c_i) c_i of each node, interpolated;
-//   list     one thread per bead: non-bonded partners within the interaction
-//            range plus a skin, ascending index order (bead positions staged
-//            through shared memory in tiles);
-//   substeps one work-group holds every bead position in shared memory and
-//            runs the five substeps (forces at the substep start, then V and
-//            X), summing per bead the impulse the fluid receives;
+//   list     one wavefront per bead: non-bonded partners within the
+//            interaction range plus a skin, in ascending index order;
+//   substeps one launch per substep, one thread per bead: forces from the
+//            previous substep's positions, then V and X into the other
+//            position slot of the bead record; the impulse the fluid
+//            receives summed per bead;
 //   spread   one thread per bead adds its impulse times each weight into a
 //            fixed-point (2^-50) momentum grid with 64-bit integer atomics:
 //            integer addition is exact, so the sums do not depend on order;
@@ -81,8 +81,10 @@ __device__ inline void node_rho(const FilArgs &a, const S *f, int64_t n, double 
         rho[1] = double(ro[a.fs + n]);
         return;
     }
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         double s = 0.0;
+#pragma unroll
         for (int i = 0; i < Q; ++i) s += popf(a, f, k, i, n);
         rho[k] = s;
     }
@@ -109,8 +111,10 @@ __device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v
     node_rho(a, f, n, rho);
     // post-collision momentum of both components
     v3 jk[2];
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         jk[k] = {0.0, 0.0, 0.0};
+#pragma unroll
         for (int i = 1; i < Q; ++i) {
             const double fi = popf(a, f, k, i, n);
             jk[k] = jk[k] + v3{cx(i) * fi, cy(i) * fi, cz(i) * fi};
@@ -123,6 +127,7 @@ __device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v
     // Shan-Chen force of the stored densities and the lattice colour gradient
     v3 s[2] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     v3 g = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int i = 1; i < Q; ++i) {
         const int64_t m = nb_of(a, x, y, z, i);
         const uint8_t id = a.mat[m] & MAT_ID_MASK;
@@ -148,6 +153,7 @@ __device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v
         g = g + (3.0 * w * Cn) * c;
     }
     v3 F = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         const double gp = -a.G * rho[k];
         F = F + v3{gp * s[k].x + rho[k] * a.g[0], gp * s[k].y + rho[k] * a.g[1], gp * s[k].z + rho[k] * a.g[2]};
@@ -157,114 +163,104 @@ __device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v
 }
 
 // ---------------------------------------------------------------------------
-// 1. gather: stencil, renormalised weights, interpolated velocity and grad C
+// 1. gather: eight lanes per bead, one per stencil node; the weights and the
+//    interpolated fields are summed in stencil order through lane shuffles
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(256) void fil_gather_kernel(FilArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.n) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = t >> 3, e = t & 7;
+    const int lane0 = (threadIdx.x & 63) & ~7;  // first lane of this bead's group
+    const bool act = b < a.n;
     const S *f = static_cast<const S *>(a.f);
-    double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    double *rec = a.bead + size_t(act ? b : 0) * FIL_STRIDE;
     const v3 X = ld(rec + FIL_X);
     const double bx = floor(X.x), by = floor(X.y), bz = floor(X.z);
     const double fr[3] = {X.x - bx, X.y - by, X.z - bz};
     const int base[3] = {int(bx), int(by), int(bz)};
     const int dims[3] = {a.nx, a.ny, a.nz}, per[3] = {a.px, a.py, a.pz};
-    int node[8];
-    double w[8];
+    const int d[3] = {e & 1, (e >> 1) & 1, e >> 2};
+    int idx[3];
+    bool ok = act;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        idx[q] = base[q] + d[q];
+        if (per[q])
+            idx[q] = wrap_idx(idx[q], dims[q]);
+        else if (idx[q] < 0 || idx[q] >= dims[q])
+            ok = false;
+    }
+    int node = -1;
+    double w = 0.0;
+    if (ok) {
+        const int64_t n = node_at(a, idx[0], idx[1], idx[2]);
+        if ((a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
+            node = int(n);
+            w = (d[0] ? fr[0] : 1.0 - fr[0]) * (d[1] ? fr[1] : 1.0 - fr[1]) * (d[2] ? fr[2] : 1.0 - fr[2]);
+        }
+    }
     double wsum = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int d[3] = {e & 1, (e >> 1) & 1, e >> 2};
-        int idx[3];
-        bool ok = true;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            idx[q] = base[q] + d[q];
-            if (per[q])
-                idx[q] = wrap_idx(idx[q], dims[q]);
-            else if (idx[q] < 0 || idx[q] >= dims[q])
-                ok = false;
-        }
-        node[e] = -1;
-        w[e] = 0.0;
-        if (!ok) continue;
-        const int64_t n = node_at(a, idx[0], idx[1], idx[2]);
-        if ((a.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
-        node[e] = int(n);
-        w[e] = (d[0] ? fr[0] : 1.0 - fr[0]) * (d[1] ? fr[1] : 1.0 - fr[1]) * (d[2] ? fr[2] : 1.0 - fr[2]);
-        wsum += w[e];
+    for (int q = 0; q < 8; ++q) wsum += __shfl(w, lane0 + q, 64);
+    const int coupled = wsum > 0.0;
+    v3 u = {0.0, 0.0, 0.0}, g = {0.0, 0.0, 0.0};
+    if (coupled && node >= 0) {
+        w = w / wsum;
+        const int64_t n = node;
+        node_fields(a, f, int(n % a.nx), int((n / a.nx) % a.ny), int(n / (int64_t(a.nx) * a.ny)), u, g);
+    } else {
+        node = -1;
+        w = 0.0;
     }
     v3 ub = {0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0};
-    const int coupled = wsum > 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        if (!coupled || node[e] < 0) {
-            node[e] = -1;
-            w[e] = 0.0;
-            continue;
-        }
-        w[e] = w[e] / wsum;
-        const int64_t n = node[e];
-        const int x = int(n % a.nx), y = int((n / a.nx) % a.ny), z = int(n / (int64_t(a.nx) * a.ny));
-        v3 u, g;
-        node_fields(a, f, x, y, z, u, g);
-        ub = ub + w[e] * u;
-        gb = gb + w[e] * g;
+    for (int q = 0; q < 8; ++q) {
+        const double wq = __shfl(w, lane0 + q, 64);
+        const v3 uq = {__shfl(u.x, lane0 + q, 64), __shfl(u.y, lane0 + q, 64), __shfl(u.z, lane0 + q, 64)};
+        const v3 gq = {__shfl(g.x, lane0 + q, 64), __shfl(g.y, lane0 + q, 64), __shfl(g.z, lane0 + q, 64)};
+        ub = ub + wq * uq;
+        gb = gb + wq * gq;
     }
-    st(rec + FIL_U, ub);
-    st(rec + FIL_GC, gb);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        rec[FIL_W + e] = w[e];
-        a.sten[size_t(b) * 8 + e] = node[e];
+    if (!act) return;
+    rec[FIL_W + e] = w;
+    a.sten[size_t(b) * 8 + e] = node;
+    if (e == 0) {
+        st(rec + FIL_U, ub);
+        st(rec + FIL_GC, gb);
+        rec[FIL_COUPLED] = coupled;
     }
-    rec[FIL_COUPLED] = coupled;
 }
 
 // ---------------------------------------------------------------------------
 // 2. non-bonded partner lists: every other bead within the range plus the
 //    skin, except the chain's own beads at most two apart (their forces are
-//    the bonded ones)
+//    the bonded ones).  One wavefront per bead scans the candidates 64 at a
+//    time and appends the hits in ascending order (ballot and prefix count).
 // ---------------------------------------------------------------------------
 constexpr int LT = 256;
 
 __global__ __launch_bounds__(LT) void fil_list_kernel(FilArgs a, double range2) {
-    __shared__ double sx[LT][3];
-    const int b = blockIdx.x * LT + threadIdx.x;
-    const bool act = b < a.n;
-    v3 X = {0.0, 0.0, 0.0};
-    if (act) {
-        X = ld(a.bead + size_t(b) * FIL_STRIDE + FIL_X);
-        st(a.bead + size_t(b) * FIL_STRIDE + FIL_X0, X);
-    }
-    const int cb = act ? b / a.per_chain : -1, ib = act ? b % a.per_chain : 0;
+    const int b = blockIdx.x * (LT / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= a.n) return;  // uniform per wavefront
+    double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    const v3 X = ld(rec + FIL_X);
+    if (lane == 0) st(rec + FIL_X0, X);
+    const int cb = b / a.per_chain, ib = b % a.per_chain;
     int cnt = 0;
-    for (int t0 = 0; t0 < a.n; t0 += LT) {
-        const int j = t0 + threadIdx.x;
-        if (j < a.n) {
-            const double *r = a.bead + size_t(j) * FIL_STRIDE + FIL_X;
-            sx[threadIdx.x][0] = r[0];
-            sx[threadIdx.x][1] = r[1];
-            sx[threadIdx.x][2] = r[2];
+    for (int o0 = 0; o0 < a.n; o0 += 64) {
+        const int o = o0 + lane;
+        bool hit = false;
+        if (o < a.n && o != b && !(o / a.per_chain == cb && abs(o % a.per_chain - ib) <= 2)) {
+            const v3 r = min_image(X - ld(a.bead + size_t(o) * FIL_STRIDE + FIL_X), a);
+            hit = r.x * r.x + r.y * r.y + r.z * r.z < range2;
         }
-        __syncthreads();
-        const int lim = min(LT, a.n - t0);
-        if (act)
-            for (int q = 0; q < lim; ++q) {
-                const int o = t0 + q;
-                if (o == b) continue;
-                if (o / a.per_chain == cb && abs(o % a.per_chain - ib) <= 2) continue;
-                const v3 r = min_image(X - v3{sx[q][0], sx[q][1], sx[q][2]}, a);
-                const double d2 = r.x * r.x + r.y * r.y + r.z * r.z;
-                if (d2 < range2) {
-                    if (cnt < FIL_NBR) a.nbr[size_t(b) * FIL_NBR + cnt] = o;
-                    ++cnt;
-                }
-            }
-        __syncthreads();
+        const unsigned long long m = __ballot(hit);
+        const int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+        if (hit && pos < FIL_NBR) a.nbr[size_t(b) * FIL_NBR + pos] = o;
+        cnt += __popcll(m);
     }
-    if (act) {
+    if (lane == 0) {
         if (cnt > FIL_NBR) {
             atomicOr(a.status, ST_ROD_LIST);
             cnt = FIL_NBR;
@@ -274,7 +270,9 @@ __global__ __launch_bounds__(LT) void fil_list_kernel(FilArgs a, double range2) 
 }
 
 // ---------------------------------------------------------------------------
-// 3. substeps: one work-group, positions in shared memory
+// 3. one substep per launch, one thread per bead: forces from the positions
+//    of the previous substep (src), then V and X (dst), the two position
+//    slots of each bead record alternating
 // ---------------------------------------------------------------------------
 __device__ inline double phi_d(double d, double d0) {
     // d/dd of (d0/d)^12 - 2 (d0/d)^6
@@ -297,122 +295,98 @@ __device__ inline double sub_f(double h, const FilArgs &a) {
     return (h > 0.0 && h < a.r_cut_s) ? -a.eps_s * phi_d(h, a.sigma_s) : 0.0;
 }
 
-__global__ __launch_bounds__(FIL_TPB) void fil_substep_kernel(FilArgs a) {
-    __shared__ double sX[3 * FIL_MAX];  // bead positions
-    const int tid = threadIdx.x;
-    for (int b = tid; b < a.n; b += FIL_TPB) {
-        const double *r = a.bead + size_t(b) * FIL_STRIDE + FIL_X;
-        sX[3 * b] = r[0];
-        sX[3 * b + 1] = r[1];
-        sX[3 * b + 2] = r[2];
-        st(a.bead + size_t(b) * FIL_STRIDE + FIL_IMP, v3{0.0, 0.0, 0.0});
-    }
-    __syncthreads();
+constexpr int ST_TPB = 64;
+
+__global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src, int first) {
+    const int b = blockIdx.x * ST_TPB + threadIdx.x;
+    if (b >= a.n) return;
+    const int dst = src == FIL_X ? FIL_XN : FIL_X;
+    double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    if (first) st(rec + FIL_IMP, v3{0.0, 0.0, 0.0});
     const double dt = 1.0 / a.n_sub;
     const double m = a.mass;
     unsigned flags = 0;
-    constexpr int PER = (FIL_MAX + FIL_TPB - 1) / FIL_TPB;
-    for (int sub = 0; sub < a.n_sub; ++sub) {
-        v3 Xn[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int b = tid + k * FIL_TPB;
-            if (b >= a.n) break;
-            double *rec = a.bead + size_t(b) * FIL_STRIDE;
-            const v3 X = {sX[3 * b], sX[3 * b + 1], sX[3 * b + 2]};
-            const int ch = b / a.per_chain, ib = b % a.per_chain;
-            v3 Fi = {0.0, 0.0, 0.0};
-            auto pair = [&](int o, int kind) {
-                const v3 r = min_image(X - v3{sX[3 * o], sX[3 * o + 1], sX[3 * o + 2]}, a);
-                const double d = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
-                double fm = 0.0;
-                if (d <= a.d0) fm += wca_f(d, a);
-                if (kind == 1) {
-                    fm += fene_f(d, a);
-                    if (!(d < a.R_m)) flags |= ST_ROD;
-                }
-                if (kind == 2) fm += bend_f(d, a);
-                if (kind == 3) fm += coh_f(d, a);
-                if (fm != 0.0) Fi = Fi + v3{fm * r.x / d, fm * r.y / d, fm * r.z / d};
-            };
-            // every partner in ascending bead index: the chain's bonded ones
-            // (at most two apart) merged into the ascending partner list
-            const int nc = a.nbr_cnt[b];
-            int dj = -2;
-            auto bonded_below = [&](int lim) {
-                for (; dj <= 2; ++dj) {
-                    const int j = ib + dj;
-                    if (dj == 0 || j < 0 || j >= a.per_chain) continue;
-                    const int o = ch * a.per_chain + j;
-                    if (o >= lim) break;
-                    pair(o, dj == -1 || dj == 1 ? 1 : 2);
-                }
-            };
-            for (int q = 0; q < nc; ++q) {
-                const int o = a.nbr[size_t(b) * FIL_NBR + q];
-                bonded_below(o);
-                pair(o, o / a.per_chain == ch ? 0 : 3);
-            }
-            bonded_below(a.n);
-            v3 Fs = {0.0, 0.0, 0.0};
-            const double h = X.z - a.wall_z;
-            if (a.wall_on) Fs.z = sub_f(h, a);
-            const int coupled = rec[FIL_COUPLED] != 0.0;
-            const v3 V = ld(rec + FIL_V);
-            const v3 U = ld(rec + FIL_U);
-            const v3 Fd = coupled ? (-a.gamma) * (V - U) : v3{0.0, 0.0, 0.0};
-            const v3 Fsv = coupled ? a.kappa_s * ld(rec + FIL_GC) : v3{0.0, 0.0, 0.0};
-            const v3 Fo = (Fi + Fd) + Fsv;
-            v3 Ff = {0.0, 0.0, 0.0};
-            if (a.wall_on && h > 0.0 && h < a.r_cut_s) {
-                const double fz = Fo.z + fmin(Fs.z, 0.0);
-                const double N = fmax(0.0, -fz);
-                const double s = sqrt(V.x * V.x + V.y * V.y);
-                if (N > 0.0 && s > 0.0) {
-                    const double c = fmin(a.mu * N / s, m / dt);
-                    Ff = {-V.x * c, -V.y * c, 0.0};
-                }
-            }
-            const v3 imp = ld(rec + FIL_IMP);
-            st(rec + FIL_IMP, imp + dt * ((-1.0) * (Fd + Fsv)));
-            // symplectic Euler: V first, X with the new V
-            const v3 acc = (Fo + Fs) + Ff;
-            const v3 Vx = {V.x + acc.x / m * dt, V.y + acc.y / m * dt, V.z + acc.z / m * dt};
-            st(rec + FIL_V, Vx);
-            v3 Xp = {X.x + Vx.x * dt, X.y + Vx.y * dt, X.z + Vx.z * dt};
-            Xp = {wrap_pos(Xp.x, a.nx, a.px), wrap_pos(Xp.y, a.ny, a.py), wrap_pos(Xp.z, a.nz, a.pz)};
-            Xn[k] = Xp;
+    const v3 X = ld(rec + src);
+    const int ch = b / a.per_chain, ib = b % a.per_chain;
+    v3 Fi = {0.0, 0.0, 0.0};
+    auto pair = [&](int o, int kind) {
+        const v3 r = min_image(X - ld(a.bead + size_t(o) * FIL_STRIDE + src), a);
+        const double d = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
+        double fm = 0.0;
+        if (d <= a.d0) fm += wca_f(d, a);
+        if (kind == 1) {
+            fm += fene_f(d, a);
+            if (!(d < a.R_m)) flags |= ST_ROD;
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int b = tid + k * FIL_TPB;
-            if (b >= a.n) break;
-            sX[3 * b] = Xn[k].x;
-            sX[3 * b + 1] = Xn[k].y;
-            sX[3 * b + 2] = Xn[k].z;
+        if (kind == 2) fm += bend_f(d, a);
+        if (kind == 3) fm += coh_f(d, a);
+        if (fm != 0.0) Fi = Fi + v3{fm * r.x / d, fm * r.y / d, fm * r.z / d};
+    };
+    // every partner in ascending bead index: the chain's bonded ones (at most
+    // two apart) merged into the ascending partner list
+    const int nc = a.nbr_cnt[b];
+    int dj = -2;
+    auto bonded_below = [&](int lim) {
+        for (; dj <= 2; ++dj) {
+            const int j = ib + dj;
+            if (dj == 0 || j < 0 || j >= a.per_chain) continue;
+            const int o = ch * a.per_chain + j;
+            if (o >= lim) break;
+            pair(o, dj == -1 || dj == 1 ? 1 : 2);
         }
-        __syncthreads();
+    };
+    for (int q = 0; q < nc; ++q) {
+        const int o = a.nbr[size_t(b) * FIL_NBR + q];
+        bonded_below(o);
+        pair(o, o / a.per_chain == ch ? 0 : 3);
     }
-    for (int b = tid; b < a.n; b += FIL_TPB) {
-        double *rec = a.bead + size_t(b) * FIL_STRIDE;
-        const v3 X = {sX[3 * b], sX[3 * b + 1], sX[3 * b + 2]};
-        st(rec + FIL_X, X);
-        // the partner lists hold for moves below half the skin per step
-        const v3 d = min_image(X - ld(rec + FIL_X0), a);
-        if (d.x * d.x + d.y * d.y + d.z * d.z > 0.25 * a.skin * a.skin) flags |= ST_ROD;
-        if (!(X.x == X.x && X.y == X.y && X.z == X.z)) flags |= ST_NAN;
+    bonded_below(a.n);
+    v3 Fs = {0.0, 0.0, 0.0};
+    const double h = X.z - a.wall_z;
+    if (a.wall_on) Fs.z = sub_f(h, a);
+    const int coupled = rec[FIL_COUPLED] != 0.0;
+    const v3 V = ld(rec + FIL_V);
+    const v3 U = ld(rec + FIL_U);
+    const v3 Fd = coupled ? (-a.gamma) * (V - U) : v3{0.0, 0.0, 0.0};
+    const v3 Fsv = coupled ? a.kappa_s * ld(rec + FIL_GC) : v3{0.0, 0.0, 0.0};
+    const v3 Fo = (Fi + Fd) + Fsv;
+    v3 Ff = {0.0, 0.0, 0.0};
+    if (a.wall_on && h > 0.0 && h < a.r_cut_s) {
+        const double fz = Fo.z + fmin(Fs.z, 0.0);
+        const double N = fmax(0.0, -fz);
+        const double sv = sqrt(V.x * V.x + V.y * V.y);
+        if (N > 0.0 && sv > 0.0) {
+            const double c = fmin(a.mu * N / sv, m / dt);
+            Ff = {-V.x * c, -V.y * c, 0.0};
+        }
     }
+    const v3 imp = ld(rec + FIL_IMP);
+    st(rec + FIL_IMP, imp + dt * ((-1.0) * (Fd + Fsv)));
+    // symplectic Euler: V first, X with the new V
+    const v3 acc = (Fo + Fs) + Ff;
+    const v3 Vn = {V.x + acc.x / m * dt, V.y + acc.y / m * dt, V.z + acc.z / m * dt};
+    st(rec + FIL_V, Vn);
+    const v3 Xp = {X.x + Vn.x * dt, X.y + Vn.y * dt, X.z + Vn.z * dt};
+    st(rec + dst, v3{wrap_pos(Xp.x, a.nx, a.px), wrap_pos(Xp.y, a.ny, a.py), wrap_pos(Xp.z, a.nz, a.pz)});
     if (flags) atomicOr(a.status, flags);
 }
 
 // ---------------------------------------------------------------------------
 // 4. spread the impulses onto the fixed-point momentum grid
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fil_spread_kernel(FilArgs a) {
+__global__ __launch_bounds__(256) void fil_spread_kernel(FilArgs a, int last) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.n) return;
-    const double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    double *rec = a.bead + size_t(b) * FIL_STRIDE;
+    // the last substep's positions become the bead's position; the partner
+    // lists hold for moves below half the skin per update
+    const v3 X = ld(rec + last);
+    if (last != FIL_X) st(rec + FIL_X, X);
+    const v3 dd = min_image(X - ld(rec + FIL_X0), a);
+    unsigned flags = 0;
+    if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > 0.25 * a.skin * a.skin) flags |= ST_ROD;
+    if (!(X.x == X.x && X.y == X.y && X.z == X.z)) flags |= ST_NAN;
+    if (flags) atomicOr(a.status, flags);
     if (rec[FIL_COUPLED] == 0.0) return;
     const double imp[3] = {rec[FIL_IMP], rec[FIL_IMP + 1], rec[FIL_IMP + 2]};
     for (int e = 0; e < 8; ++e) {
@@ -518,10 +492,15 @@ hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s) {
     range += a.skin;
     return fil_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(fil_gather_kernel<S>, dim3(g), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(fil_list_kernel, dim3((a.n + LT - 1) / LT), dim3(LT), 0, s, a, range * range);
-        hipLaunchKernelGGL(fil_substep_kernel, dim3(1), dim3(FIL_TPB), 0, s, a);
-        hipLaunchKernelGGL(fil_spread_kernel, dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(fil_gather_kernel<S>, dim3((a.n * 8 + 255) / 256), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(fil_list_kernel, dim3((a.n + LT / 64 - 1) / (LT / 64)), dim3(LT), 0, s, a, range * range);
+        int src = FIL_X;
+        for (int sub = 0; sub < a.n_sub; ++sub) {
+            hipLaunchKernelGGL(fil_substep_kernel, dim3((a.n + ST_TPB - 1) / ST_TPB), dim3(ST_TPB), 0, s, a, src,
+                               sub == 0 ? 1 : 0);
+            src = src == FIL_X ? FIL_XN : FIL_X;
+        }
+        hipLaunchKernelGGL(fil_spread_kernel, dim3(g), dim3(256), 0, s, a, src);
         hipLaunchKernelGGL(fil_apply_kernel<S>, dim3((a.n * 8 + 255) / 256), dim3(256), 0, s, a);
         return hipGetLastError();
     });

@@ -126,9 +126,9 @@ constexpr int FIL_U = 6, FIL_GC = 9;      // interpolated fluid velocity and col
 constexpr int FIL_IMP = 12, FIL_X0 = 15;  // impulse given to the fluid this step; position at list time
 constexpr int FIL_W = 18;                 // [8] renormalised stencil weights
 constexpr int FIL_COUPLED = 26;           // 1 when a stencil node is fluid
+constexpr int FIL_XN = 27;                // position slot the substeps alternate with FIL_X
 constexpr int FIL_NBR = 48;               // non-bonded partners per bead
-constexpr int FIL_MAX = LB_FIL_MAX_BEADS; // beads per lattice (positions of all in one work-group's LDS)
-constexpr int FIL_TPB = 1024;
+constexpr int FIL_MAX = LB_FIL_MAX_BEADS; // beads per lattice
 constexpr double FIL_FIX = 1125899906842624.0;  // 2^50: fixed-point unit of the momentum grid and ledger
 
 struct FilArgs {
