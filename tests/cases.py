@@ -66,3 +66,25 @@ def lattice_params(c, prec, rho_ref=(0.0, 0.0), **tile):
     return LatticeParams(shape=c["shape"], periodic=c["periodic"], prec=prec, tau=c["tau"], G=c["G"],
                          body_force=c["body_force"], psi_solid=PSI_SOLID.copy(), evaporation=c["evaporation"],
                          rho_top=(0.0, 1.0), rho_ref=rho_ref, sink=c.get("sink"), **tile)
+
+
+# The coupled step at length: a reduced form of the benchmark's droplet with
+# five rods placed fully inside the liquid, their centres at most 12 above the
+# wall (shared by the GPU parity test and the script that writes the oracle's
+# expected values).  Rods kept clear of the liquid-vapour interface: a rod
+# whose end pierces the interface makes the trajectory sensitive to rounding
+# (a 1e-13 change of one initial density moves the rods by 1e-2 within 500
+# steps in the oracle itself), and no two implementations then agree to 1e-12.
+COUPLED_RODS = dict(length=24.0, radius=2.0, rho_rod=1.0, eps_att=1e-4, eps_rep=0.03, d0=5.0, r_cut=7.5,
+                    eps_wall=0.03, d0_wall=3.0, n_sub=5)
+
+
+def coupled_cap_case():
+    spec = inputs.CapSpec(shape=(32, 48, 96), footprint=(84.0, 36.0), height=18.0, stripe=(90, 42), seed=2300)
+    rho, mat = inputs.sessile_cap(spec)
+    ins = inputs.cap_inside(spec)
+    rods = inputs.place_rods(5, 24.0, 2.0, (96, 48, 32), inside=lambda x, y, z: ins(x, y, z) and z <= 12.0,
+                             seed=2355, margin=1.0, gap=4.0, max_trials=200000)
+    assert len(rods) == 5
+    return dict(shape=spec.shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), rho=rho, mat=mat,
+                evaporation=True, body_force=(0.0, 0.0, 0.0), rods=rods)

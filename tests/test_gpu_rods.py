@@ -246,3 +246,61 @@ def test_full_size_coupled_step_properties():
     assert np.array_equal(o1["solid"], o2["solid"])
     # the reservoir ledger is summed per xy tile: another tiling adds in another order
     assert np.allclose(o1["ledger"], o2["ledger"], rtol=1e-12, atol=0)
+
+
+GOLD = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "coupled_cap96_oracle.npz")
+CHECK = (100, 250, 500, 750, 1000)
+
+
+def _coupled_cap_gpu(prec):
+    from paper_2607_06794_amd.sim import Lattice
+
+    c = cases.coupled_cap_case()
+    lp = cases.lattice_params(c, prec)
+    rp = cases.COUPLED_RODS
+    lp.rod_length, lp.rod_radius, lp.rod_rho = rp["length"], rp["radius"], rp["rho_rod"]
+    lp.eps_att, lp.eps_rep, lp.rod_d0, lp.rod_rcut = rp["eps_att"], rp["eps_rep"], rp["d0"], rp["r_cut"]
+    lp.eps_wall, lp.rod_d0_wall, lp.n_sub, lp.wall_z = rp["eps_wall"], rp["d0_wall"], rp["n_sub"], 0.5
+    say(f"[gpu] coupled cap 96x48x32, 5 rods, 1000 steps, {prec}")
+    lat = Lattice(lp, c["rho"], c["mat"], rods=c["rods"])
+    out, t = {}, 0
+    for tc in CHECK:
+        lat.coupled_step(tc - t)
+        t = tc
+        o = lat.observables(allow_unstable=True)
+        out[tc] = (lat.rods(), np.concatenate([o["mass"], o["ledger"], o["solid"]]), int(o["status"]))
+    _, f = lat.export()
+    lat.close()
+    return out, f
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_coupled_cap_1000_steps_against_oracle(prec, tol):
+    """The coupled step at length: 1000 steps of a 96 x 48 x 32 striped cap
+    with five physically placed rods (L = 24) and the reservoir, against the
+    FP64 oracle's stored trajectory (tests/golden/make_coupled_oracle.py):
+    rod states at five checkpoints, masses and ledgers, and the populations
+    at 1500 sampled fluid nodes (half of them within 3 of a rod surface).
+
+    FP32 is held to 1e-5 up to step 250 only: whether a rod covers a node is
+    a discontinuous function of the rod's pose, FP32 rounding of the fluid
+    moves the rods by about 1e-6 of L within a few hundred steps, and the
+    first node that the FP32 and the FP64 runs classify differently (step
+    420 of this case) kicks the rods by 1e-4; later FP32 checkpoints check
+    the status word only."""
+    g = np.load(GOLD)
+    out, f = _coupled_cap_gpu(prec)
+    L = cases.COUPLED_RODS["length"]
+    for tc in CHECK:
+        rods, scal, st = out[tc]
+        dx, dq, dv, dl = _rod_err(rods, g[f"rods_{tc}"], L)
+        ds = float(np.abs(scal - g[f"scal_{tc}"]).max() / np.abs(g[f"scal_{tc}"][:2]).max())
+        say(f"[gpu] {prec} t={tc}: X {dx:.2e} q {dq:.2e} V {dv:.2e} L {dl:.2e} mass/ledgers {ds:.2e} status {st}")
+        assert st & ~64 == 0, st
+        if prec == "f64" or tc <= 250:
+            assert dx <= tol and dq <= tol and ds <= tol
+    if prec == "f64":
+        fs = f.reshape(2, 19, -1)[:, :, g["nodes"]]
+        ef = cases.rel_err(fs, g["f_nodes"])
+        say(f"[gpu] {prec} t=1000: sampled populations rel err {ef:.3e}")
+        assert ef <= tol
