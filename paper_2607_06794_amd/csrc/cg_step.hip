@@ -10,8 +10,9 @@
 // The curvature needs the colour two nodes out, so the step runs as three
 // passes over SoA arrays (thread per node, x fastest, coalesced):
 //   1. colour:  pull the 38 populations of each fluid node, C into an array;
-//   2. normal:  grad C from the neighbours' C (a solid neighbour contributes
-//               the w-weighted mean colour of its own fluid neighbours),
+//               then each static wall node's ghost colour, the w-weighted
+//               mean C of its fluid neighbours, into the same array;
+//   2. normal:  grad C from the neighbours' C (ghost colours on walls),
 //               unit normal with the contact-angle correction next to walls,
 //               n and |grad C| into four arrays;
 //   3. collide: pull again, moments, curvature from the neighbours' normals,
@@ -91,19 +92,21 @@ __global__ void __launch_bounds__(256) cg_colour_kernel(CGArgs a) {
     static_cast<C *>(a.colour)[n] = rt > C(0) ? (r0 - r1) / rt : C(0);
 }
 
-// colour seen at node q: C on fluid nodes; on a static wall node the
-// w-weighted mean C of its fluid neighbours (the ghost layer); 0 elsewhere
+// ---- pass 1b: ghost colour of the static wall nodes: the w-weighted mean C
+// of each wall node's fluid neighbours (0 without any), stored in the colour
+// array so that the normal pass reads one value per neighbour
 template <class C>
-__device__ inline C colour_at(const CGArgs &a, int qx, int qy, int qz) {
-    const int64_t q = (int64_t(qz) * a.ny + qy) * a.nx + qx;
-    const uint8_t m = a.mat[q] & MAT_ID_MASK;
-    const C *col = static_cast<const C *>(a.colour);
-    if (m == MAT_FLUID) return col[q];
-    if (!is_static_wall(m)) return C(0);
+__global__ void __launch_bounds__(256) cg_ghost_kernel(CGArgs a) {
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= a.nodes) return;
+    if (!is_static_wall(a.mat[n] & MAT_ID_MASK)) return;
+    int x, y, z;
+    decode(n, a, x, y, z);
+    C *col = static_cast<C *>(a.colour);
     C num = C(0), den = C(0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
-        int vx = qx, vy = qy, vz = qz;
+        int vx = x, vy = y, vz = z;
         if (!step_axis(vx, cx(j), a.nx, a.px) || !step_axis(vy, cy(j), a.ny, a.py) || !step_axis(vz, cz(j), a.nz, a.pz))
             continue;
         const int64_t v = (int64_t(vz) * a.ny + vy) * a.nx + vx;
@@ -112,7 +115,16 @@ __device__ inline C colour_at(const CGArgs &a, int qx, int qy, int qz) {
             den += wgt<C>(j);
         }
     }
-    return den > C(0) ? num / den : C(0);
+    col[n] = den > C(0) ? num / den : C(0);
+}
+
+// colour seen at node q: C on fluid nodes, the ghost colour on static wall
+// nodes, 0 elsewhere
+template <class C>
+__device__ inline C colour_at(const CGArgs &a, int qx, int qy, int qz) {
+    const int64_t q = (int64_t(qz) * a.ny + qy) * a.nx + qx;
+    const uint8_t m = a.mat[q] & MAT_ID_MASK;
+    return (m == MAT_FLUID || is_static_wall(m)) ? static_cast<const C *>(a.colour)[q] : C(0);
 }
 
 // ---- pass 2: interface normal ---------------------------------------------
@@ -309,11 +321,13 @@ hipError_t launch_cg_step(int prec, const CGArgs &a, hipStream_t s) {
     switch (prec) {
         case LB_F64:
             hipLaunchKernelGGL(cg_colour_kernel<double>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(cg_ghost_kernel<double>, grid, block, 0, s, a);
             hipLaunchKernelGGL(cg_normal_kernel<double>, grid, block, 0, s, a);
             hipLaunchKernelGGL(cg_collide_kernel<double>, grid, block, 0, s, a);
             return hipGetLastError();
         case LB_F32:
             hipLaunchKernelGGL(cg_colour_kernel<float>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(cg_ghost_kernel<float>, grid, block, 0, s, a);
             hipLaunchKernelGGL(cg_normal_kernel<float>, grid, block, 0, s, a);
             hipLaunchKernelGGL(cg_collide_kernel<float>, grid, block, 0, s, a);
             return hipGetLastError();
