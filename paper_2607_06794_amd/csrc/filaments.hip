@@ -309,8 +309,8 @@ __global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src,
     const v3 X = ld(rec + src);
     const int ch = b / a.per_chain, ib = b % a.per_chain;
     v3 Fi = {0.0, 0.0, 0.0};
-    auto pair = [&](int o, int kind) {
-        const v3 r = min_image(X - ld(a.bead + size_t(o) * FIL_STRIDE + src), a);
+    auto pair = [&](v3 Xo, int kind) {
+        const v3 r = min_image(X - Xo, a);
         const double d = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
         double fm = 0.0;
         if (d <= a.d0) fm += wca_f(d, a);
@@ -322,23 +322,46 @@ __global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src,
         if (kind == 3) fm += coh_f(d, a);
         if (fm != 0.0) Fi = Fi + v3{fm * r.x / d, fm * r.y / d, fm * r.z / d};
     };
-    // every partner in ascending bead index: the chain's bonded ones (at most
-    // two apart) merged into the ascending partner list
-    const int nc = a.nbr_cnt[b];
-    int dj = -2;
+    // positions of the chain's bonded partners (at most two apart) and of the
+    // listed partners are loaded ahead, eight at a time, so that their loads
+    // overlap; the forces are then added in ascending partner index, the
+    // bonded ones merged into the ascending list
+    v3 Xb[4];
+    int ob[4], kb[4], nb = 0;
+#pragma unroll
+    for (int dj = -2; dj <= 2; ++dj) {
+        const int j = ib + dj;
+        if (dj == 0 || j < 0 || j >= a.per_chain) continue;
+        ob[nb] = ch * a.per_chain + j;
+        kb[nb] = (dj == -1 || dj == 1) ? 1 : 2;
+        ++nb;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u < nb) Xb[u] = ld(a.bead + size_t(ob[u]) * FIL_STRIDE + src);
+    int ub = 0;
     auto bonded_below = [&](int lim) {
-        for (; dj <= 2; ++dj) {
-            const int j = ib + dj;
-            if (dj == 0 || j < 0 || j >= a.per_chain) continue;
-            const int o = ch * a.per_chain + j;
-            if (o >= lim) break;
-            pair(o, dj == -1 || dj == 1 ? 1 : 2);
-        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u >= ub && u < nb && ob[u] < lim) {
+                pair(Xb[u], kb[u]);
+                ub = u + 1;
+            }
     };
-    for (int q = 0; q < nc; ++q) {
-        const int o = a.nbr[size_t(b) * FIL_NBR + q];
-        bonded_below(o);
-        pair(o, o / a.per_chain == ch ? 0 : 3);
+    const int nc = a.nbr_cnt[b];
+    for (int q0 = 0; q0 < nc; q0 += 8) {
+        int oi[8];
+        v3 Xo[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) oi[u] = q0 + u < nc ? a.nbr[size_t(b) * FIL_NBR + q0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Xo[u] = oi[u] >= 0 ? ld(a.bead + size_t(oi[u]) * FIL_STRIDE + src) : X;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (oi[u] < 0) break;
+            bonded_below(oi[u]);
+            pair(Xo[u], oi[u] / a.per_chain == ch ? 0 : 3);
+        }
     }
     bonded_below(a.n);
     v3 Fs = {0.0, 0.0, 0.0};
