@@ -263,15 +263,63 @@ __device__ inline void node_densities(const RodArgs &a, int fresh, const S *f, i
     }
 }
 
+// densities rho_k of fluid node n as stored in the density array (which
+// exists on every lattice with rods): loaded ahead of the neighbour ids and
+// used only while the array holds the current state
+template <class S>
+__device__ inline void stored_densities(const RodArgs &a, int64_t n, double rho[2]) {
+    const typename Codec<S>::C *ro = static_cast<const typename Codec<S>::C *>(a.rho);
+    rho[0] = double(ro[n]);
+    rho[1] = double(ro[a.fs + n]);
+}
+
 // listed node of this thread: false if the entry is past the end of the list
 __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, int &y, int &z) {
     const int idx = blockIdx.x * RB + threadIdx.x;
     if (idx >= a.shell_cnt[r]) return false;
-    n = a.shell[size_t(r) * a.shell_cap + idx];
-    x = int(n % a.nx);
-    y = int((n / a.nx) % a.ny);
-    z = int(n / (int64_t(a.nx) * a.ny));
+    // list entries are 32-bit node indices: 32-bit division
+    const uint32_t u = static_cast<uint32_t>(a.shell[size_t(r) * a.shell_cap + idx]);
+    const uint32_t nx = a.nx, ny = a.ny, row = u / nx;
+    n = u;
+    x = int(u - row * nx);
+    y = int(row % ny);
+    z = int(row / ny);
     return true;
+}
+
+// Directions i (bit i) in which the node (x, y, z) + sgn c_i (sgn = +1 or -1,
+// the node inside the lattice) belongs to rod r.  The neighbour across a
+// closed boundary is read at its wrapped index and ignored, so that all 18
+// loads are issued together instead of one after another behind the bounds
+// tests.
+__device__ inline unsigned rod_neighbours(const RodArgs &a, int x, int y, int z, int sgn, int r) {
+    int16_t id[Q];
+    unsigned in = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        int xx = x + sgn * cx(i), yy = y + sgn * cy(i), zz = z + sgn * cz(i);
+        const bool out = ((xx < 0 || xx >= a.nx) && !a.px) || ((yy < 0 || yy >= a.ny) && !a.py) ||
+                         ((zz < 0 || zz >= a.nz) && !a.pz);
+        xx = xx < 0 ? xx + a.nx : (xx >= a.nx ? xx - a.nx : xx);
+        yy = yy < 0 ? yy + a.ny : (yy >= a.ny ? yy - a.ny : yy);
+        zz = zz < 0 ? zz + a.nz : (zz >= a.nz ? zz - a.nz : zz);
+        in |= out ? 0u : 1u << i;
+        id[i] = a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx];
+    }
+    unsigned m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) m |= ((in >> i) & 1u) && id[i] == r ? 1u << i : 0u;
+    return m;
+}
+
+// index of the node (x, y, z) + sgn c_i, for a direction rod_neighbours
+// reported (so inside the lattice after one wrap)
+__device__ inline int64_t step_node(const RodArgs &a, int x, int y, int z, int sgn, int i) {
+    int xx = x + sgn * cx(i), yy = y + sgn * cy(i), zz = z + sgn * cz(i);
+    xx = xx < 0 ? xx + a.nx : (xx >= a.nx ? xx - a.nx : xx);
+    yy = yy < 0 ? yy + a.ny : (yy >= a.ny ? yy - a.ny : yy);
+    zz = zz < 0 ? zz + a.nz : (zz >= a.nz ? zz - a.nz : zz);
+    return (int64_t(zz) * a.ny + yy) * a.nx + xx;
 }
 
 // ---------------------------------------------------------------------------
@@ -292,32 +340,35 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     double acc[6] = {0, 0, 0, 0, 0, 0};
     int64_t n;
     int x, y, z;
-    if (shell_node(a, r, n, x, y, z) && (a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
-        unsigned links = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            int xx = x + cx(i), yy = y + cy(i), zz = z + cz(i);
-            if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-            if (a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx] == r) links |= 1u << i;
-        }
+    if (shell_node(a, r, n, x, y, z)) {
+        // material, densities and the 18 neighbour ids are loaded together
+        const uint8_t mt = a.mat[n];
+        double rho[2];
+        stored_densities<S>(a, n, rho);
+        unsigned links = rod_neighbours(a, x, y, z, 1, r);
+        if ((mt & MAT_ID_MASK) != MAT_FLUID) links = 0;
         if (links) {
-            double rho[2];
-            node_densities<S>(a, bt.rho_fresh, f, n, rho);
-            const d3 dx0 = min_image(mk(x, y, z) - X, a);
+            if (!bt.rho_fresh) node_densities<S>(a, 0, f, n, rho);
+            // every link's force is G (rho_A psi_B + rho_B psi_A) w_i c_i, and
+            // its torque about X at the rod node x + c_i equals that of the
+            // same force at x (c_i x c_i = 0): the node adds sum_i w_i c_i once
+            double wx = 0.0, wy = 0.0, wz = 0.0;
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                if (!(links & (1u << i))) continue;
-                const double g = a.G * wgt<double>(i) * (rho[0] * a.psi_rod[1] + rho[1] * a.psi_rod[0]);
-                const d3 fr = mk(g * cx(i), g * cy(i), g * cz(i));
-                const d3 arm = dx0 + mk(cx(i), cy(i), cz(i));  // the rod node x + c_i
-                const d3 tq = cross(arm, fr);
-                acc[0] += fr.x;
-                acc[1] += fr.y;
-                acc[2] += fr.z;
-                acc[3] += tq.x;
-                acc[4] += tq.y;
-                acc[5] += tq.z;
+                const double w = (links >> i) & 1u ? wgt<double>(i) : 0.0;
+                if (cx(i)) wx += cx(i) * w;
+                if (cy(i)) wy += cy(i) * w;
+                if (cz(i)) wz += cz(i) * w;
             }
+            const double g = a.G * (rho[0] * a.psi_rod[1] + rho[1] * a.psi_rod[0]);
+            const d3 fr = mk(g * wx, g * wy, g * wz);
+            const d3 tq = cross(min_image(mk(x, y, z) - X, a), fr);
+            acc[0] = fr.x;
+            acc[1] = fr.y;
+            acc[2] = fr.z;
+            acc[3] = tq.x;
+            acc[4] = tq.y;
+            acc[5] = tq.z;
         }
     }
     block_sums(acc, sh, part_slot(a.part_adh, a, r, blockIdx.x));
@@ -784,7 +835,8 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     const int reach = int(ceil(2.0 * a.radius)) + 2;
     for (int e = wv; e < tot; e += RB / 64) {
         const int64_t un = un_node[e];
-        const int ux = int(un % a.nx), uy = int((un / a.nx) % a.ny), uz = int(un / (int64_t(a.nx) * a.ny));
+        const uint32_t uu = static_cast<uint32_t>(un), urow = uu / uint32_t(a.nx);
+        const int ux = int(uu - urow * uint32_t(a.nx)), uy = int(urow % uint32_t(a.ny)), uz = int(urow / uint32_t(a.ny));
         const int i = 1 + (lane >> 1), k = lane & 1;
         // select, not index: a run-time index into the argument record would
         // put the whole record in private memory
@@ -797,20 +849,23 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
             ok = false;
             if (lane < 2 * (Q - 1)) {
                 int xx = ux + sr * cx(i), yy = uy + sr * cy(i), zz = uz + sr * cz(i);
-                if (wrap_coord(xx, a.nx, a.px) && wrap_coord(yy, a.ny, a.py) && wrap_coord(zz, a.nz, a.pz)) {
-                    const int64_t q = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-                    const uint8_t mq = a.mat[q] & MAT_ID_MASK;
-                    if (sr == 1) wall = is_static_wall(mq);
-                    ok = mq == MAT_FLUID && a.rodid[q] < 0 && a.newid[q] < 0;
-                    if (ok && bt.rho_fresh) {
-                        val = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
-                    } else if (ok) {
-                        double s = 0.0;
+                const bool inb = wrap_coord(xx, a.nx, a.px) & wrap_coord(yy, a.ny, a.py) & wrap_coord(zz, a.nz, a.pz);
+                // material, ids and stored density of the neighbour loaded
+                // together (a neighbour outside the lattice reads the node itself)
+                const int64_t q = inb ? (int64_t(zz) * a.ny + yy) * a.nx + xx : un;
+                const uint8_t mq = a.mat[q] & MAT_ID_MASK;
+                const int rq = a.rodid[q], nq = a.newid[q];
+                const double dq = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
+                if (sr == 1) wall = inb && is_static_wall(mq);
+                ok = inb && mq == MAT_FLUID && rq < 0 && nq < 0;
+                double v = dq;  // used on every path, so its load is not deferred into a branch
+                if (ok && !bt.rho_fresh) {
+                    double s = 0.0;
 #pragma unroll
-                        for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
-                        val = s;
-                    }
+                    for (int j = 0; j < Q; ++j) s += decf(f, (k * Q + j) * a.fs + q) + wgt<double>(j) * rref_k;
+                    v = s;
                 }
+                val = ok ? v : 0.0;
             }
             cnt = __popcll(__ballot(ok && k == 0));
             if (cnt) {
@@ -888,7 +943,10 @@ __global__ void __launch_bounds__(RB) rod_commit_kernel(RodBatch bt) {
     }
     int64_t n;
     int x, y, z;
-    if (shell_node(a, r, n, x, y, z) && (a.rodid[n] == r || a.newid[n] == r)) a.rodid[n] = int16_t(a.newid[n]);
+    if (shell_node(a, r, n, x, y, z)) {
+        const int oid = a.rodid[n], nid = a.newid[n];
+        if (oid == r || nid == r) a.rodid[n] = int16_t(nid);
+    }
 }
 
 // totals over rods in a fixed order: solid ledger [2], rod momentum M V [3]
@@ -910,6 +968,7 @@ __global__ void rod_sums_kernel(RodArgs a, double *out) {
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
+    using C = typename Codec<S>::C;
     __shared__ double sh[RB / 64 * 8];
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
@@ -924,68 +983,60 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
     int64_t n;
     int x, y, z;
     if (shell_node(a, r, n, x, y, z)) {
-        if (a.newid[n] == r) a.newid[n] = -1;
-        unsigned links = 0;
-        if ((a.mat[n] & MAT_ID_MASK) == MAT_FLUID) {
+        // material, densities and the 18 neighbour ids are loaded together
+        const uint8_t mt = a.mat[n];
+        const int nid = a.newid[n];
+        double rho[2];
+        stored_densities<S>(a, n, rho);
+        unsigned links = rod_neighbours(a, x, y, z, -1, r);
+        if ((mt & MAT_ID_MASK) != MAT_FLUID) links = 0;
+        if (links) {
+            if (!bt.rho_fresh) node_densities<S>(a, 0, f, n, rho);
+            // f*_opp(i)(x) of every linked direction, all loads in flight
+            // together: a lane without the link reads its node's rest
+            // population instead (a line the wave reads anyway), so that no
+            // load sits behind a branch that would wait for it
+            S fo[Q][2];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
-                if (!wrap_coord(xx, a.nx, a.px) || !wrap_coord(yy, a.ny, a.py) || !wrap_coord(zz, a.nz, a.pz)) continue;
-                if (a.rodid[(zz * a.ny + yy) * a.nx + xx] == r) links |= 1u << i;
+                const bool l = (links >> i) & 1u;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) fo[i][k] = f[(l ? (k * Q + opp(i)) * a.fs : 0) + n];
             }
-        }
-        if (links) {
-            double rho[2];
-            node_densities<S>(a, bt.rho_fresh, f, n, rho);
             const d3 dx0 = min_image(mk(x, y, z) - X, a);
-            // one linked direction at a time (rolled: an unrolled body per
-            // direction costs occupancy). The two f*_opp(i)(x) of the next
-            // link are loaded before this link's stores, so one load latency
-            // overlaps the previous link's arithmetic instead of two
-            // serialised ones per link; the stores go to rod nodes and never
-            // alias these reads of the fluid node x
-            int i = __builtin_ctz(links);
-            double fo[2], fn[2];
+            // wall velocity at the link midpoint x - c_i / 2: V + Omega x (dx0 -
+            // c_i / 2), whose component along c_i is that of u0 = V + Omega x dx0
+            // (Omega x c_i is normal to c_i)
+            const d3 u0 = Vr + cross(Om, dx0);
+            d3 P = mk(0, 0, 0);
 #pragma unroll
-            for (int k = 0; k < 2; ++k) fo[k] = decf(f, (k * Q + opp(i)) * a.fs + n);
-            for (unsigned m = links; m;) {
-                m &= m - 1;
-                const int inext = m ? __builtin_ctz(m) : i;
-#pragma unroll
-                for (int k = 0; k < 2; ++k) fn[k] = decf(f, (k * Q + opp(inext)) * a.fs + n);
-                int xx = x - cx(i), yy = y - cy(i), zz = z - cz(i);
-                wrap_coord(xx, a.nx, a.px);
-                wrap_coord(yy, a.ny, a.py);
-                wrap_coord(zz, a.nz, a.pz);
-                const int64_t s = (int64_t(zz) * a.ny + yy) * a.nx + xx;
-                const d3 ci = mk(cx(i), cy(i), cz(i));
-                // link midpoint relative to the centre: the node's minimum
-                // image shifted by -c_i / 2 (a surface node is far from the
-                // half-box, so the shift never needs a second wrap)
-                const d3 arm = dx0 - 0.5 * ci;
-                const d3 ub = Vr + cross(Om, arm);
-                const double cu = dot(ci, ub);
-                d3 dp = mk(0, 0, 0);
+            for (int i = 1; i < Q; ++i) {
+                if (!((links >> i) & 1u)) continue;
+                const int64_t s = step_node(a, x, y, z, -1, i);
+                const double cu = cx(i) * u0.x + cy(i) * u0.y + cz(i) * u0.z;
+                double q = 0.0;
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const double f_o = fo[k] + wgt<double>(opp(i)) * a.rho_ref[k];
+                    const double f_o = double(Codec<S>::dec(fo[i][k])) + wgt<double>(opp(i)) * a.rho_ref[k];
                     const double add = 2.0 * wgt<double>(i) * rho[k] * cu * 3.0;
                     const double fin = f_o + add;
-                    f[(k * Q + i) * a.fs + s] = Codec<S>::enc(typename Codec<S>::C(fin - wgt<double>(i) * a.rho_ref[k]));
-                    dp = dp - (f_o + fin) * ci;
+                    f[(k * Q + i) * a.fs + s] = Codec<S>::enc(C(fin - wgt<double>(i) * a.rho_ref[k]));
+                    q += f_o + fin;
                     acc[6 + k] -= add;
-                    fo[k] = fn[k];
                 }
-                i = inext;
-                const d3 tq = cross(arm, dp);
-                acc[0] += dp.x;
-                acc[1] += dp.y;
-                acc[2] += dp.z;
-                acc[3] += tq.x;
-                acc[4] += tq.y;
-                acc[5] += tq.z;
+                // the link's momentum -(f_o + fin) c_i; its torque about X at the
+                // midpoint equals that at x (c_i x c_i = 0)
+                P = P - q * mk(cx(i), cy(i), cz(i));
             }
+            const d3 tq = cross(dx0, P);
+            acc[0] = P.x;
+            acc[1] = P.y;
+            acc[2] = P.z;
+            acc[3] = tq.x;
+            acc[4] = tq.y;
+            acc[5] = tq.z;
         }
+        if (nid == r) a.newid[n] = -1;
     }
     // read by the next rod update, after the fluid step has streamed these slots
     block_sums(acc, sh, part_slot(a.part_link, a, r, blockIdx.x));
