@@ -46,6 +46,26 @@ constexpr uint8_t MAT_FLUID = 0, MAT_GHOST = 1, MAT_ROD = 8;
 constexpr uint8_t MAT_ID_MASK = 0x0F, MAT_NEAR_WALL = 0x80;
 __host__ __device__ inline bool is_static_wall(uint8_t id) { return id >= 2 && id <= 7; }
 
+// A pointer into device memory seen in the global address space.  Pointers
+// read from an argument record are generic (flat) to the compiler, and a flat
+// load also counts as an LDS/scalar access: any later wait for a scalar load
+// then waits for it too, which serialises loads that could overlap.  Loads and
+// stores through this view are global accesses, tracked on their own.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *gptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+// one element read through that view (class types, such as bf16_t, as their bits)
+template <class T>
+__device__ inline T gload(const T *p) {
+    if constexpr (__is_class(T)) {
+        static_assert(sizeof(T) == 2, "2-byte storage types only");
+        return __builtin_bit_cast(T, *gptr(reinterpret_cast<const uint16_t *>(p)));
+    } else {
+        return *gptr(p);
+    }
+}
+
 // status bits
 constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u, ST_ROD = 8u, ST_ROD_WALL = 16u, ST_ROD_LIST = 32u;
 // notice, not a fault: an uncovered node had no fluid neighbour and took its

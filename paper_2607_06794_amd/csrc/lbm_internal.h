@@ -70,8 +70,8 @@ constexpr int ROD_X = 0, ROD_Q = 3, ROD_V = 7, ROD_L = 10;  // centre, quaternio
 constexpr int ROD_FS = 13, ROD_TS = 16;                      // momentum exchanged by the streamed links
 constexpr int ROD_FA = 19, ROD_TA = 22;                      // adhesion reaction
 constexpr int ROD_FC = 25, ROD_TC = 28;                      // contact force of the current substep
-constexpr int ROD_XOLD = 31, ROD_QOLD = 34;                  // pose before the last move
 constexpr int ROD_SOLID = 38;                                // mass exchanged with the fluid [2]
+constexpr int ROD_VPRE = 40, ROD_LPRE = 43;                  // momenta the integrator left (before the re-mask transfers)
 constexpr int ROD_PART = 8;                                  // doubles per (rod, block) partial-sum slot
 constexpr int ROD_NBR = 64;                                  // neighbour-list entries per rod
 

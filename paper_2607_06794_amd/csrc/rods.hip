@@ -37,6 +37,11 @@ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * 
 __device__ inline d3 cross(d3 a, d3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 
 __device__ inline d3 ld3(const double *p) { return {p[0], p[1], p[2]}; }
+// the same from device memory (rod records), as global loads
+__device__ inline d3 gld3(const double *p) {
+    const auto *g = gptr(p);
+    return {g[0], g[1], g[2]};
+}
 __device__ inline void st3(double *p, d3 v) {
     p[0] = v.x;
     p[1] = v.y;
@@ -123,7 +128,7 @@ __device__ inline double seg_seg(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2) {
 
 template <class S>
 __device__ inline double decf(const S *f, int64_t idx) {
-    return static_cast<double>(Codec<S>::dec(f[idx]));
+    return static_cast<double>(Codec<S>::dec(gload(f + idx)));
 }
 
 // integer bounding box of the capsule (plus margin) in lattice coordinates
@@ -239,7 +244,7 @@ __device__ inline double shell_r2(const RodArgs &a) { return (a.radius + 1.5) * 
 // far fewer nodes than its capacity) does no work: it writes the n zeros its
 // block sums would have produced into its partial-sum slot (if any) and ends.
 __device__ inline bool idle_block(const RodArgs &a, int r, double *slot, int n) {
-    if (int(blockIdx.x) * RB < a.shell_cnt[r]) return false;
+    if (int(blockIdx.x) * RB < gptr(a.shell_cnt)[r]) return false;
     if (slot && int(threadIdx.x) < n) slot[threadIdx.x] = 0.0;
     return true;
 }
@@ -268,7 +273,7 @@ __device__ inline void node_densities(const RodArgs &a, int fresh, const S *f, i
 // used only while the array holds the current state
 template <class S>
 __device__ inline void stored_densities(const RodArgs &a, int64_t n, double rho[2]) {
-    const typename Codec<S>::C *ro = static_cast<const typename Codec<S>::C *>(a.rho);
+    const auto *ro = gptr(static_cast<const typename Codec<S>::C *>(a.rho));
     rho[0] = double(ro[n]);
     rho[1] = double(ro[a.fs + n]);
 }
@@ -276,9 +281,9 @@ __device__ inline void stored_densities(const RodArgs &a, int64_t n, double rho[
 // listed node of this thread: false if the entry is past the end of the list
 __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, int &y, int &z) {
     const int idx = blockIdx.x * RB + threadIdx.x;
-    if (idx >= a.shell_cnt[r]) return false;
+    if (idx >= gptr(a.shell_cnt)[r]) return false;
     // list entries are 32-bit node indices: 32-bit division
-    const uint32_t u = static_cast<uint32_t>(a.shell[size_t(r) * a.shell_cap + idx]);
+    const uint32_t u = static_cast<uint32_t>(gptr(a.shell)[size_t(r) * a.shell_cap + idx]);
     const uint32_t nx = a.nx, ny = a.ny, row = u / nx;
     n = u;
     x = int(u - row * nx);
@@ -288,12 +293,13 @@ __device__ inline bool shell_node(const RodArgs &a, int r, int64_t &n, int &x, i
 }
 
 // Directions i (bit i) in which the node (x, y, z) + sgn c_i (sgn = +1 or -1,
-// the node inside the lattice) belongs to rod r.  The neighbour across a
+// the node inside the lattice) belongs to rod r by the id array ids.  The neighbour across a
 // closed boundary is read at its wrapped index and ignored, so that all 18
 // loads are issued together instead of one after another behind the bounds
 // tests.
-__device__ inline unsigned rod_neighbours(const RodArgs &a, int x, int y, int z, int sgn, int r) {
-    int16_t id[Q];
+template <class T>
+__device__ inline unsigned rod_neighbours(const T *ids, const RodArgs &a, int x, int y, int z, int sgn, int r) {
+    int id[Q];
     unsigned in = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -304,7 +310,7 @@ __device__ inline unsigned rod_neighbours(const RodArgs &a, int x, int y, int z,
         yy = yy < 0 ? yy + a.ny : (yy >= a.ny ? yy - a.ny : yy);
         zz = zz < 0 ? zz + a.nz : (zz >= a.nz ? zz - a.nz : zz);
         in |= out ? 0u : 1u << i;
-        id[i] = a.rodid[(int64_t(zz) * a.ny + yy) * a.nx + xx];
+        id[i] = gptr(ids)[(int64_t(zz) * a.ny + yy) * a.nx + xx];
     }
     unsigned m = 0;
 #pragma unroll
@@ -327,9 +333,19 @@ __device__ inline int64_t step_node(const RodArgs &a, int x, int y, int z, int s
 //    F_rod += G psi_k(x) w_i psi^s_kbar c_i (psi_k(x) = rho_k(x), the collision
 //    invariant of the current post-collision state), torque about X at y
 // ---------------------------------------------------------------------------
+__device__ void rod_list(const RodBatch &bt, int g);
+
+// The launch has one work-group column more than the widest surface list:
+// work-group (last, r) builds rod r's neighbour list instead.  The pass also
+// returns rod r's entries of newid to -1 for the next re-mask (the previous
+// step's commit left them equal to the occupancy).
 template <class S>
 __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     __shared__ double sh[RB / 64 * 8];
+    if (blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x < 64) rod_list(bt, blockIdx.y);
+        return;
+    }
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
@@ -342,11 +358,13 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     int x, y, z;
     if (shell_node(a, r, n, x, y, z)) {
         // material, densities and the 18 neighbour ids are loaded together
-        const uint8_t mt = a.mat[n];
+        const uint8_t mt = gptr(a.mat)[n];
+        const int nid = gptr(a.newid)[n];
         double rho[2];
         stored_densities<S>(a, n, rho);
-        unsigned links = rod_neighbours(a, x, y, z, 1, r);
+        unsigned links = rod_neighbours(a.rodid, a, x, y, z, 1, r);
         if ((mt & MAT_ID_MASK) != MAT_FLUID) links = 0;
+        if (nid == r) a.newid[n] = -1;
         if (links) {
             if (!bt.rho_fresh) node_densities<S>(a, 0, f, n, rho);
             // every link's force is G (rho_A psi_B + rho_B psi_A) w_i c_i, and
@@ -375,41 +393,30 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
 }
 
 // ---------------------------------------------------------------------------
-// 2a. per rod (one wavefront each): the fluid load of the step that just ran
-//     (momentum of the streamed links, adhesion reaction; the mass carried by
-//     the streamed moving bounce-back is booked now), and the list of rods
-//     that can come within interaction range during this step (each point of
-//     a rod moves less than 0.9 per step, so a pair farther apart than
-//     r_int + 2 at the start stays out of range)
+// 2a. per rod (one wavefront, run as an extra work-group of the adhesion
+//     launch): the fluid load of the streamed links, and the list of rods
+//     that can come within interaction range during this step (each point of a rod moves less than 0.9 per step, so a pair
+//     farther apart than r_int + 2 at the start stays out of range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) rod_pairs_kernel(RodBatch bt) {
+__device__ void rod_list(const RodBatch &bt, int g) {
     int r;
-    const RodArgs a = rod_of(bt, blockIdx.x, r);
+    const RodArgs a = rod_of(bt, g, r);
     const int lane = threadIdx.x;
     double *rod = a.rods + r * ROD_STRIDE;
     {
-        double ls[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ad[6] = {0, 0, 0, 0, 0, 0};
+        // the momentum of the links the fluid step just streamed (their mass
+        // is booked now), summed over the link pass's work-groups
+        double ls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int b = lane; b < a.nblk; b += 64) {
             const double *pl = part_slot(a.part_link, a, r, b);
-            const double *pa = part_slot(a.part_adh, a, r, b);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) ls[q] += pl[q];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) ad[q] += pa[q];
+            for (int q = 0; q < 8; ++q) ls[q] += gptr(pl)[q];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) ls[q] = wave_sum_d(ls[q]);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) ad[q] = wave_sum_d(ad[q]);
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) rod[ROD_XOLD + q] = rod[ROD_X + q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) rod[ROD_QOLD + q] = rod[ROD_Q + q];
-#pragma unroll
             for (int q = 0; q < 6; ++q) rod[ROD_FS + q] = ls[q];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) rod[ROD_FA + q] = ad[q];
             rod[ROD_SOLID] += ls[6];
             rod[ROD_SOLID + 1] += ls[7];
         }
@@ -447,102 +454,184 @@ __global__ void __launch_bounds__(64) rod_pairs_kernel(RodBatch bt) {
 // ---------------------------------------------------------------------------
 // 2b. rigid-body substeps: one work-group of LB_MAX_RODS threads.  Centres
 //     and axes of all rods live in shared memory for the whole step.  Pair
-//     forces: TPR adjacent lanes per rod (the largest power of two that fits
-//     the work-group: 2 for 200 rods, 16 for 20) split its neighbour list
-//     (lane j takes entries j, j + TPR, ...) and add their sums with a fixed
-//     xor butterfly into shared memory.  Rod update: thread r
-//     keeps rod r's velocity, angular momentum and fluid load in registers
-//     and advances it (threads 0 .. n - 1, so the FP64 update runs on as few
-//     wavefronts as possible).
+//     forces: the neighbour lists are laid end to end into one list of
+//     (rod, neighbour) terms, dealt to all threads of the work-group (one
+//     term per thread while there are fewer terms than threads), so that the
+//     FP64 work spreads over every wavefront instead of following the longest
+//     list; each term's force and torque go to shared memory, and thread r
+//     adds rod r's terms in list order.  Rod update: thread r keeps rod r's
+//     velocity, angular momentum and fluid load in registers and advances it.
 // ---------------------------------------------------------------------------
-constexpr int RS_X = 0, RS_Q = 3, RS_F = 7, RS_N = 13;  // shared-memory record per rod: X, q, F, T
+constexpr int RS_X = 0, RS_Q = 3, RS_N = 7;  // shared-memory record per rod: X, q
+constexpr int TCAP = 1024;  // pair terms whose results shared memory holds at a time
+constexpr int TPK = 4096;   // pair terms whose (rod, neighbour) is kept for the step
 
 __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt) {
     extern __shared__ double rs[];  // [n_rods][RS_N]
+    __shared__ int toff[LB_MAX_RODS + 1];  // rod r's terms: [toff[r], toff[r + 1])
+    __shared__ int tpair[TPK];             // term g < TPK: rod | neighbour << 16
+    __shared__ double tres[TCAP][6];       // force, torque of the terms of one chunk
+    __shared__ int wsum[LB_MAX_RODS / 64];
     const RodArgs a = bt.all[blockIdx.x];  // one work-group per lattice
     const int nr = a.n_rods;
-    // as many lanes per rod as the work-group holds (a power of two, so the
-    // lanes of one rod stay adjacent within a wavefront)
-    int TPR = 1;
-    while (TPR < 64 && 2 * TPR * nr <= LB_MAX_RODS) TPR *= 2;
-    // pair role
-    const int pr = threadIdx.x / TPR, sub_lane = threadIdx.x % TPR;
-    const bool pmine = pr < nr;
-    // update role
-    const int me = threadIdx.x;
+    if (nr == 0) return;  // uniform per work-group
+    const int me = threadIdx.x, lane = me & 63, wv = me >> 6;
     const bool mine = me < nr;
     const double dt = 1.0 / a.n_sub;
     d3 V = mk(0, 0, 0), Lm = mk(0, 0, 0), Fx = mk(0, 0, 0), Tx = mk(0, 0, 0), F = mk(0, 0, 0), T = mk(0, 0, 0);
     double *rm = rs + (mine ? me : 0) * RS_N;
     const double *rod = a.rods + (mine ? me : 0) * ROD_STRIDE;
+    d3 X0 = mk(0, 0, 0), e0 = mk(0, 0, 1);
+    const int nn = mine ? gptr(a.nbr_cnt)[me] : 0;
     if (mine) {
+        // every load of the prologue is issued before the first store to
+        // shared memory (which the compiler must assume may alias them)
+        double xq[7];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) rm[RS_X + q] = rod[ROD_X + q];  // X then q
-        V = ld3(rod + ROD_V);
-        Lm = ld3(rod + ROD_L);
-        Fx = ld3(rod + ROD_FS) + ld3(rod + ROD_FA);
-        Tx = ld3(rod + ROD_TS) + ld3(rod + ROD_TA);
+        for (int q = 0; q < 7; ++q) xq[q] = gptr(rod)[ROD_X + q];  // X then q
+        V = gld3(rod + ROD_V);
+        Lm = gld3(rod + ROD_L);
+        const d3 fs = gld3(rod + ROD_FS), ts = gld3(rod + ROD_TS);
+        // the adhesion reaction of the step that just ran, summed over the
+        // surface-list work-groups in order (eight slots' loads in flight at a
+        // time: a slot past the end reads the last one again and adds zero)
+        double ad[6] = {0, 0, 0, 0, 0, 0};
+        for (int b0 = 0; b0 < a.nblk; b0 += 8) {
+            double va[8][6];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double *pa = part_slot(a.part_adh, a, me, min(b0 + u, a.nblk - 1));
+#pragma unroll
+                for (int q = 0; q < 6; ++q) va[u][q] = gptr(pa)[q];
+            }
+            // (a select, not a branch, so that no load is deferred past it)
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) ad[q] += b0 + u < a.nblk ? va[u][q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 7; ++q) rm[RS_X + q] = xq[q];
+        X0 = mk(xq[0], xq[1], xq[2]);
+        e0 = quat_axis(xq + 3);
+        double *rw = a.rods + me * ROD_STRIDE;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rw[ROD_FA + q] = ad[q];
+        Fx = fs + mk(ad[0], ad[1], ad[2]);
+        Tx = ts + mk(ad[3], ad[4], ad[5]);
     }
-    const int nn = pmine ? a.nbr_cnt[pr] : 0;
-    const d3 X0 = mine ? ld3(rod + ROD_XOLD) : mk(0, 0, 0);
-    const d3 e0 = mine ? quat_axis(rod + ROD_QOLD) : mk(0, 0, 1);
-    bool moved_far = false;
+    // term offsets: exclusive scan of the list lengths over the work-group
+    int v = nn;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[wv] = v;
     __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < LB_MAX_RODS / 64; ++w) {
+        base += w < wv ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    const int my_off = base + v - nn;
+    if (mine) toff[me] = my_off;
+    if (me == 0) toff[nr] = total;
+    const int nterm = total;
+    // rod me's list into the kept term table (entries in list order)
+    if (mine) {
+        for (int l0 = 0; l0 < nn; l0 += 8) {
+            int16_t sb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sb[u] = gptr(a.nbr)[me * ROD_NBR + min(l0 + u, nn - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (l0 + u < nn && my_off + l0 + u < TPK) tpair[my_off + l0 + u] = me | (int(sb[u]) << 16);
+        }
+    }
+    const double dt_m = dt / a.mass, iIperp = 1.0 / a.Iperp, dI = 1.0 / a.Ipar - 1.0 / a.Iperp;
+    const double reach = a.half + a.radius;
+    bool moved_far = false;
+    // distance check of the previous substep's pose, made while the next
+    // substep's pair forces are computed (off the update's critical path)
+    d3 Xc = X0, ec = e0;
+    __syncthreads();
+
+    // force and torque on rod ra from rod rb at this substep's poses; exactly
+    // zero for touching axes (d = 0) and beyond the potential's range
+    auto term = [&](int g, double (&out)[6]) {
+        int ra, rb;
+        if (g < TPK) {
+            const int pq = tpair[g];
+            ra = pq & 0xffff;
+            rb = pq >> 16;
+        } else {  // past the kept table: the owning rod by bisection of the offsets
+            int lo = 0, hi = nr - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (toff[mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            ra = lo;
+            rb = gptr(a.nbr)[ra * ROD_NBR + (g - toff[ra])];
+        }
+        const double *pa_ = rs + ra * RS_N, *pb_ = rs + rb * RS_N;
+        const d3 Xa = ld3(pa_ + RS_X), ea = quat_axis(pa_ + RS_Q);
+        const d3 Xb = ld3(pb_ + RS_X), eb = quat_axis(pb_ + RS_Q);
+        const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
+        const d3 dx = min_image(Xb - Xa, a);
+        const d3 shift = dx - (Xb - Xa);
+        const d3 pb = Xb - a.half * eb + shift, qb = Xb + a.half * eb + shift;
+        d3 ca, cb;
+        const double d = seg_seg(pa, qa, pb, qb, ca, cb);
+        const double fmd = d > 0.0 ? pair_force_over_d(d, a) : 0.0;
+        const d3 fv = fmd * (ca - cb);
+        const d3 tv = cross(ca - Xa, fv);
+        out[0] = fv.x;
+        out[1] = fv.y;
+        out[2] = fv.z;
+        out[3] = tv.x;
+        out[4] = tv.y;
+        out[5] = tv.z;
+    };
+
     for (int sub = 0; sub < a.n_sub; ++sub) {
-        // contact forces between rods at the positions of this substep
+        // contact forces between rods at the positions of this substep, in
+        // chunks of TCAP terms (a single chunk unless the lists are long)
         d3 Fp = mk(0, 0, 0), Tp = mk(0, 0, 0);
-        if (pmine) {
-            const double *ra = rs + pr * RS_N;
-            const d3 Xa = ld3(ra + RS_X), ea = quat_axis(ra + RS_Q);
-            const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
-            // force and torque on rod pr from one neighbour; exactly zero
-            // for touching axes (d = 0) and beyond the potential's range
-            auto term = [&](int l, d3 &fv, d3 &tv) {
-                const double *rb = rs + a.nbr[pr * ROD_NBR + l] * RS_N;
-                const d3 Xb = ld3(rb + RS_X);
-                const d3 dx = min_image(Xb - Xa, a);
-                const d3 shift = dx - (Xb - Xa);
-                const d3 eb = quat_axis(rb + RS_Q);
-                const d3 pb = Xb - a.half * eb + shift, qb = Xb + a.half * eb + shift;
-                d3 ca, cb;
-                const double d = seg_seg(pa, qa, pb, qb, ca, cb);
-                const double fmd = d > 0.0 ? pair_force_over_d(d, a) : 0.0;
-                fv = fmd * (ca - cb);
-                tv = cross(ca - Xa, fv);
-            };
-            // two neighbours per iteration without branches, so that their
-            // dependent FP64 chains interleave; added in list order
-            int l = sub_lane;
-            for (; l + TPR < nn; l += 2 * TPR) {
-                d3 f0, t0, f1, t1;
-                term(l, f0, t0);
-                term(l + TPR, f1, t1);
-                Fp = Fp + f0;
-                Tp = Tp + t0;
-                Fp = Fp + f1;
-                Tp = Tp + t1;
+        for (int c0 = 0; c0 < nterm; c0 += TCAP) {
+            const int c1 = min(nterm, c0 + TCAP);
+            // two terms per thread and iteration, so that their dependent
+            // FP64 chains interleave
+            for (int g = c0 + me; g < c1; g += 2 * LB_MAX_RODS) {
+                double o0[6], o1[6];
+                const int g1 = g + LB_MAX_RODS;
+                term(g, o0);
+                if (g1 < c1) term(g1, o1);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) tres[g - c0][q] = o0[q];
+                if (g1 < c1)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) tres[g1 - c0][q] = o1[q];
             }
-            if (l < nn) {
-                d3 f0, t0;
-                term(l, f0, t0);
-                Fp = Fp + f0;
-                Tp = Tp + t0;
+            __syncthreads();
+            if (mine) {  // rod me's terms of this chunk, in list order
+                const int l0 = max(my_off, c0), l1 = min(my_off + nn, c1);
+                for (int l = l0; l < l1; ++l) {
+                    Fp = Fp + mk(tres[l - c0][0], tres[l - c0][1], tres[l - c0][2]);
+                    Tp = Tp + mk(tres[l - c0][3], tres[l - c0][4], tres[l - c0][5]);
+                }
             }
+            if (c1 < nterm) __syncthreads();  // the next chunk overwrites the results
         }
-        // the rod's lanes are adjacent within one wavefront: fixed butterfly
-        for (int o = 1; o < TPR; o <<= 1) {
-            Fp = mk(Fp.x + __shfl_xor(Fp.x, o, 64), Fp.y + __shfl_xor(Fp.y, o, 64), Fp.z + __shfl_xor(Fp.z, o, 64));
-            Tp = mk(Tp.x + __shfl_xor(Tp.x, o, 64), Tp.y + __shfl_xor(Tp.y, o, 64), Tp.z + __shfl_xor(Tp.z, o, 64));
-        }
-        if (pmine && sub_lane == 0) {
-            double *rf = rs + pr * RS_N + RS_F;
-            st3(rf, Fp);
-            st3(rf + 3, Tp);
-        }
-        __syncthreads();
         if (mine) {
-            F = ld3(rm + RS_F);
-            T = ld3(rm + RS_F + 3);
+            {
+                const d3 dX = min_image(Xc - X0, a);
+                const d3 de = ec - e0;
+                moved_far |= !(sqrt(dot(dX, dX)) + reach * sqrt(dot(de, de)) < 0.9);
+            }
+            F = Fp;
+            T = Tp;
             if (a.wall_on) {
                 const d3 Xa = ld3(rm + RS_X), ea = quat_axis(rm + RS_Q);
                 const d3 pa = Xa - a.half * ea, qa = Xa + a.half * ea;
@@ -554,17 +643,19 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
                     T = T + cross(low - Xa, fw);
                 }
             }
-            V = V + (dt / a.mass) * (Fx + F);
+            V = V + dt_m * (Fx + F);
             d3 X = ld3(rm + RS_X) + dt * V;
             Lm = Lm + dt * (Tx + T);
             // omega = I^-1 L with the current axis, then q <- exp(omega dt / 2) q
             const d3 e = quat_axis(rm + RS_Q);
-            const d3 w = (1.0 / a.Iperp) * Lm + ((1.0 / a.Ipar - 1.0 / a.Iperp) * dot(Lm, e)) * e;
+            const d3 w = iIperp * Lm + (dI * dot(Lm, e)) * e;
             const double wn = sqrt(dot(w, w));
             if (wn > 0.0) {
                 const double h = 0.5 * wn * dt;
-                const double sh = sin(h) / wn;
-                const double dq[4] = {cos(h), sh * w.x, sh * w.y, sh * w.z};
+                double sn, cs;
+                sincos(h, &sn, &cs);
+                const double sh = sn / wn;
+                const double dq[4] = {cs, sh * w.x, sh * w.y, sh * w.z};
                 const double q[4] = {rm[RS_Q], rm[RS_Q + 1], rm[RS_Q + 2], rm[RS_Q + 3]};
                 double qn[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
                                 dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
@@ -579,19 +670,24 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
             if (a.pz) X.z = X.z - a.nz * floor(X.z / a.nz);
             st3(rm + RS_X, X);
             // every point of the rod stays within 0.9 of where it started the
-            // step (the re-mask and the neighbour list rely on it)
-            const d3 dX = min_image(X - X0, a);
-            const d3 de = quat_axis(rm + RS_Q) - e0;
-            moved_far |= !(sqrt(dot(dX, dX)) + (a.half + a.radius) * sqrt(dot(de, de)) < 0.9);
+            // step (the re-mask and the neighbour list rely on it): checked at
+            // the start of the next substep and after the last
+            Xc = X;
+            ec = quat_axis(rm + RS_Q);
         }
         __syncthreads();
     }
     if (mine) {
+        const d3 dX = min_image(Xc - X0, a);
+        const d3 de = ec - e0;
+        moved_far |= !(sqrt(dot(dX, dX)) + reach * sqrt(dot(de, de)) < 0.9);
         double *rw = a.rods + me * ROD_STRIDE;
 #pragma unroll
         for (int q = 0; q < 7; ++q) rw[ROD_X + q] = rm[RS_X + q];
         st3(rw + ROD_V, V);
         st3(rw + ROD_L, Lm);
+        st3(rw + ROD_VPRE, V);
+        st3(rw + ROD_LPRE, Lm);
         st3(rw + ROD_FC, F);
         st3(rw + ROD_TC, T);
         if (moved_far) atomicOr(a.status, ST_ROD);
@@ -785,7 +881,7 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     bool unc = false;
     if (shell_node(a, r, n, x, y, z)) {
         // a node passing from one rod to another stays solid and is neither
-        const int oldid = a.rodid[n], newid = a.newid[n];
+        const int oldid = gptr(a.rodid)[n], newid = gptr(a.newid)[n];
         unc = oldid == r && newid < 0;
         if (newid == r && oldid < 0) {  // covered
             if (!init) {
@@ -849,13 +945,14 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
             ok = false;
             if (lane < 2 * (Q - 1)) {
                 int xx = ux + sr * cx(i), yy = uy + sr * cy(i), zz = uz + sr * cz(i);
-                const bool inb = wrap_coord(xx, a.nx, a.px) & wrap_coord(yy, a.ny, a.py) & wrap_coord(zz, a.nz, a.pz);
+                const bool okx = wrap_coord(xx, a.nx, a.px), oky = wrap_coord(yy, a.ny, a.py);
+                const bool inb = okx && oky && wrap_coord(zz, a.nz, a.pz);
                 // material, ids and stored density of the neighbour loaded
                 // together (a neighbour outside the lattice reads the node itself)
                 const int64_t q = inb ? (int64_t(zz) * a.ny + yy) * a.nx + xx : un;
-                const uint8_t mq = a.mat[q] & MAT_ID_MASK;
-                const int rq = a.rodid[q], nq = a.newid[q];
-                const double dq = double(static_cast<const typename Codec<S>::C *>(a.rho)[k * a.fs + q]);
+                const uint8_t mq = gptr(a.mat)[q] & MAT_ID_MASK;
+                const int rq = gptr(a.rodid)[q], nq = gptr(a.newid)[q];
+                const double dq = double(gptr(static_cast<const typename Codec<S>::C *>(a.rho))[k * a.fs + q]);
                 if (sr == 1) wall = inb && is_static_wall(mq);
                 ok = inb && mq == MAT_FLUID && rq < 0 && nq < 0;
                 double v = dq;  // used on every path, so its load is not deferred into a branch
@@ -915,40 +1012,6 @@ __global__ void __launch_bounds__(RB) rod_update_kernel(RodBatch bt, int init) {
     block_sums(acc, sh, part_slot(a.part_upd, a, r, blockIdx.x), init != 0);
 }
 
-// commit the new occupancy of rod r (after every work-group has read the old
-// one); work-group (0, r) also applies rod r's cover/uncover transfers
-__global__ void __launch_bounds__(RB) rod_commit_kernel(RodBatch bt) {
-    int r;
-    const RodArgs a = rod_of(bt, blockIdx.y, r);
-    if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
-    if (blockIdx.x > 0 && idle_block(a, r, nullptr, 0)) return;  // block 0 also sums the rod's partials
-    double *rod = a.rods + r * ROD_STRIDE;
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-        double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int b = threadIdx.x; b < a.nblk; b += 64) {
-            const double *p = part_slot(a.part_upd, a, r, b);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) t[q] += p[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) t[q] = wave_sum_d(t[q]);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) rod[ROD_V + q] += t[q] / a.mass;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) rod[ROD_L + q] += t[3 + q];
-            rod[ROD_SOLID] += t[6];
-            rod[ROD_SOLID + 1] += t[7];
-        }
-    }
-    int64_t n;
-    int x, y, z;
-    if (shell_node(a, r, n, x, y, z)) {
-        const int oid = a.rodid[n], nid = a.newid[n];
-        if (oid == r || nid == r) a.rodid[n] = int16_t(nid);
-    }
-}
-
 // totals over rods in a fixed order: solid ledger [2], rod momentum M V [3]
 __global__ void rod_sums_kernel(RodArgs a, double *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -963,33 +1026,71 @@ __global__ void rod_sums_kernel(RodArgs a, double *out) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. moving bounce-back slots for the next pull, and the momentum they carry;
-//    also returns rod r's entries of newid to -1 for the next re-mask
+// 5. commit and moving bounce-back slots.  COMMIT (after a re-mask): commit
+//    the new occupancy of rod r -- every work-group of the update pass has
+//    read the old one -- and apply the rod's cover/uncover transfers; then,
+//    with the new occupancy (newid, equal to what the commit writes) and the
+//    momenta after the transfers, write the slots the next pull reads and the
+//    momentum they carry.  Without COMMIT (the occupancy is current, as after
+//    a lift): the slots only.
 // ---------------------------------------------------------------------------
-template <class S>
-__global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
+template <class S, bool COMMIT>
+__global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt, int init) {
     using C = typename Codec<S>::C;
     __shared__ double sh[RB / 64 * 8];
+    __shared__ double tr[8];
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
-    if (idle_block(a, r, part_slot(a.part_link, a, r, blockIdx.x), 8)) return;
+    // work-group 0 books the transfers even when the list is empty
+    if (!(COMMIT && blockIdx.x == 0) && idle_block(a, r, part_slot(a.part_link, a, r, blockIdx.x), 8)) return;
     S *f = static_cast<S *>(a.f);
-    const double *rod = a.rods + r * ROD_STRIDE;
+    double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
-    // the rod's velocity and angular velocity, once per work-group
-    const d3 Vr = ld3(rod + ROD_V), Om = omega_of(rod, a);
+    d3 Vr = ld3(rod + ROD_V), Lr = ld3(rod + ROD_L);
+    if (COMMIT && !init) {
+        // every work-group sums the update pass's transfers in the same order
+        // and adds them to the momenta the integrator left, so that none reads
+        // the record work-group 0 rewrites
+        if (threadIdx.x < 64) {
+            double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int b = threadIdx.x; b < a.nblk; b += 64) {
+                const double *p = part_slot(a.part_upd, a, r, b);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t[q] += gptr(p)[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] = wave_sum_d(t[q]);
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) tr[q] = t[q];
+        }
+        __syncthreads();
+        const d3 V0 = ld3(rod + ROD_VPRE), L0 = ld3(rod + ROD_LPRE);
+        Vr = mk(V0.x + tr[0] / a.mass, V0.y + tr[1] / a.mass, V0.z + tr[2] / a.mass);
+        Lr = mk(L0.x + tr[3], L0.y + tr[4], L0.z + tr[5]);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st3(rod + ROD_V, Vr);
+            st3(rod + ROD_L, Lr);
+            rod[ROD_SOLID] += tr[6];
+            rod[ROD_SOLID + 1] += tr[7];
+        }
+    }
+    // the rod's angular velocity I^-1 L, once per work-group
+    const d3 e = quat_axis(rod + ROD_Q);
+    const d3 Om = (1.0 / a.Iperp) * Lr + ((1.0 / a.Ipar - 1.0 / a.Iperp) * dot(Lr, e)) * e;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // dP[3], dT[3], mass[2]
     int64_t n;
     int x, y, z;
     if (shell_node(a, r, n, x, y, z)) {
         // material, densities and the 18 neighbour ids are loaded together
-        const uint8_t mt = a.mat[n];
-        const int nid = a.newid[n];
+        const uint8_t mt = gptr(a.mat)[n];
+        const int oid = gptr(a.rodid)[n], nid = gptr(a.newid)[n];
         double rho[2];
         stored_densities<S>(a, n, rho);
-        unsigned links = rod_neighbours(a, x, y, z, -1, r);
+        unsigned links = COMMIT ? rod_neighbours(a.newid, a, x, y, z, -1, r) : rod_neighbours(a.rodid, a, x, y, z, -1, r);
         if ((mt & MAT_ID_MASK) != MAT_FLUID) links = 0;
+        if (COMMIT && (oid == r || nid == r)) a.rodid[n] = int16_t(nid);
         if (links) {
             if (!bt.rho_fresh) node_densities<S>(a, 0, f, n, rho);
             // f*_opp(i)(x) of every linked direction, all loads in flight
@@ -1001,7 +1102,7 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
             for (int i = 1; i < Q; ++i) {
                 const bool l = (links >> i) & 1u;
 #pragma unroll
-                for (int k = 0; k < 2; ++k) fo[i][k] = f[(l ? (k * Q + opp(i)) * a.fs : 0) + n];
+                for (int k = 0; k < 2; ++k) fo[i][k] = gload(f + (l ? (k * Q + opp(i)) * a.fs : 0) + n);
             }
             const d3 dx0 = min_image(mk(x, y, z) - X, a);
             // wall velocity at the link midpoint x - c_i / 2: V + Omega x (dx0 -
@@ -1036,7 +1137,6 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt) {
             acc[4] = tq.y;
             acc[5] = tq.z;
         }
-        if (nid == r) a.newid[n] = -1;
     }
     // read by the next rod update, after the fluid step has streamed these slots
     block_sums(acc, sh, part_slot(a.part_link, a, r, blockIdx.x));
@@ -1208,8 +1308,7 @@ hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hip
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 1);
-        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, bt);
-        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL((rod_link_kernel<S, true>), grid, dim3(RB), 0, s, bt, 1);
         return hipGetLastError();
     });
 }
@@ -1229,7 +1328,7 @@ hipError_t launch_rods_link(int prec, const RodArgs &a, const RodBatch &bt, hipS
     const dim3 grid(a.nblk, a.n_rods);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL((rod_link_kernel<S, false>), grid, dim3(RB), 0, s, bt, 0);
         return hipGetLastError();
     });
 }
@@ -1245,14 +1344,13 @@ hipError_t launch_rods_step(int prec, const RodBatch &bt, int n_lat, int total_r
     const dim3 grid(nblk_max, total_rods);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(rod_adhesion_kernel<S>, grid, dim3(RB), 0, s, bt);
-        hipLaunchKernelGGL(rod_pairs_kernel, dim3(total_rods), dim3(64), 0, s, bt);
+        // adhesion, with one more column of work-groups for the neighbour lists
+        hipLaunchKernelGGL(rod_adhesion_kernel<S>, dim3(nblk_max + 1, total_rods), dim3(RB), 0, s, bt);
         hipLaunchKernelGGL(rod_integrate_kernel, dim3(n_lat), dim3(LB_MAX_RODS), size_t(max_rods) * RS_N * sizeof(double),
                            s, bt);
         hipLaunchKernelGGL(rod_mask_kernel, dim3(total_rods), dim3(MB), 0, s, bt);
         hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 0);
-        hipLaunchKernelGGL(rod_commit_kernel, grid, dim3(RB), 0, s, bt);
-        hipLaunchKernelGGL(rod_link_kernel<S>, grid, dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL((rod_link_kernel<S, true>), grid, dim3(RB), 0, s, bt, 0);
         return hipGetLastError();
     });
 }
