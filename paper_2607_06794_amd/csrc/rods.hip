@@ -226,6 +226,29 @@ __device__ inline double *part_slot(double *base, const RodArgs &a, int r, int b
     return base + (size_t(r) * a.nblk + b) * ROD_PART;
 }
 
+// The sum over rod r's nblk work-groups of their partial-sum slots of `part`
+// (N values each), in work-group order, eight slots' loads in flight at a
+// time (a slot past the end reads the last one again and adds zero; a select,
+// not a branch, so that no load is deferred past it)
+template <int N>
+__device__ inline void slot_sums(const RodArgs &a, double *part, int r, double (&out)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = 0.0;
+    for (int b0 = 0; b0 < a.nblk; b0 += 8) {
+        double v[8][N];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double *ps = part_slot(part, a, r, min(b0 + u, a.nblk - 1));
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[u][q] = gptr(ps)[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < N; ++q) out[q] += b0 + u < a.nblk ? v[u][q] : 0.0;
+    }
+}
+
 // record and local index of global rod g (one lattice when bt.map is null)
 __device__ inline RodArgs rod_of(const RodBatch &bt, int g, int &r) {
     int lat = 0;
@@ -333,25 +356,17 @@ __device__ inline int64_t step_node(const RodArgs &a, int x, int y, int z, int s
 //    F_rod += G psi_k(x) w_i psi^s_kbar c_i (psi_k(x) = rho_k(x), the collision
 //    invariant of the current post-collision state), torque about X at y
 // ---------------------------------------------------------------------------
-__device__ void rod_list(const RodBatch &bt, int g);
-
-// The launch has one work-group column more than the widest surface list:
-// work-group (last, r) builds rod r's neighbour list instead.  The pass also
-// returns rod r's entries of newid to -1 for the next re-mask (the previous
-// step's commit left them equal to the occupancy).
+// The pass also returns rod r's entries of newid to -1 for the next re-mask
+// (the previous step's commit left them equal to the occupancy).
 template <class S>
 __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
     __shared__ double sh[RB / 64 * 8];
-    if (blockIdx.x == gridDim.x - 1) {
-        if (threadIdx.x < 64) rod_list(bt, blockIdx.y);
-        return;
-    }
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    double *rod = a.rods + r * ROD_STRIDE;
     if (idle_block(a, r, part_slot(a.part_adh, a, r, blockIdx.x), 6)) return;
     const S *f = static_cast<const S *>(a.f);
-    const double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     int64_t n;
@@ -393,34 +408,17 @@ __global__ void __launch_bounds__(RB) rod_adhesion_kernel(RodBatch bt) {
 }
 
 // ---------------------------------------------------------------------------
-// 2a. per rod (one wavefront, run as an extra work-group of the adhesion
-//     launch): the fluid load of the streamed links, and the list of rods
-//     that can come within interaction range during this step (each point of a rod moves less than 0.9 per step, so a pair
-//     farther apart than r_int + 2 at the start stays out of range)
+// 2a. per rod (one wavefront, run as an extra work-group of the re-mask
+//     launch, after the rods have moved): the list of rods that can come
+//     within interaction range during the next step (each point of a rod
+//     moves less than 0.9 per step, so a pair farther apart than r_int + 2 at
+//     the start stays out of range)
 // ---------------------------------------------------------------------------
 __device__ void rod_list(const RodBatch &bt, int g) {
     int r;
     const RodArgs a = rod_of(bt, g, r);
     const int lane = threadIdx.x;
-    double *rod = a.rods + r * ROD_STRIDE;
-    {
-        // the momentum of the links the fluid step just streamed (their mass
-        // is booked now), summed over the link pass's work-groups
-        double ls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int b = lane; b < a.nblk; b += 64) {
-            const double *pl = part_slot(a.part_link, a, r, b);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ls[q] += gptr(pl)[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ls[q] = wave_sum_d(ls[q]);
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) rod[ROD_FS + q] = ls[q];
-            rod[ROD_SOLID] += ls[6];
-            rod[ROD_SOLID + 1] += ls[7];
-        }
-    }
+    const double *rod = a.rods + r * ROD_STRIDE;
     const double r_int = fmax(a.d0, a.eps_att > 0.0 ? a.r_cut : a.d0);
     const double keep = r_int + 2.0, reach = 2.0 * a.half + keep;
     const d3 Xa = ld3(rod + ROD_X), ea = quat_axis(rod + ROD_Q);
@@ -472,6 +470,7 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
     __shared__ int tpair[TPK];             // term g < TPK: rod | neighbour << 16
     __shared__ double tres[TCAP][6];       // force, torque of the terms of one chunk
     __shared__ int wsum[LB_MAX_RODS / 64];
+    __shared__ double lsum[LB_MAX_RODS / 2][8];
     const RodArgs a = bt.all[blockIdx.x];  // one work-group per lattice
     const int nr = a.n_rods;
     if (nr == 0) return;  // uniform per work-group
@@ -483,6 +482,8 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
     const double *rod = a.rods + (mine ? me : 0) * ROD_STRIDE;
     d3 X0 = mk(0, 0, 0), e0 = mk(0, 0, 1);
     const int nn = mine ? gptr(a.nbr_cnt)[me] : 0;
+    const bool split = nr <= LB_MAX_RODS / 2;
+    double ad[6], ls[8];
     if (mine) {
         // every load of the prologue is issued before the first store to
         // shared memory (which the compiler must assume may alias them)
@@ -491,34 +492,22 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
         for (int q = 0; q < 7; ++q) xq[q] = gptr(rod)[ROD_X + q];  // X then q
         V = gld3(rod + ROD_V);
         Lm = gld3(rod + ROD_L);
-        const d3 fs = gld3(rod + ROD_FS), ts = gld3(rod + ROD_TS);
-        // the adhesion reaction of the step that just ran, summed over the
-        // surface-list work-groups in order (eight slots' loads in flight at a
-        // time: a slot past the end reads the last one again and adds zero)
-        double ad[6] = {0, 0, 0, 0, 0, 0};
-        for (int b0 = 0; b0 < a.nblk; b0 += 8) {
-            double va[8][6];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const double *pa = part_slot(a.part_adh, a, me, min(b0 + u, a.nblk - 1));
-#pragma unroll
-                for (int q = 0; q < 6; ++q) va[u][q] = gptr(pa)[q];
-            }
-            // (a select, not a branch, so that no load is deferred past it)
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) ad[q] += b0 + u < a.nblk ? va[u][q] : 0.0;
-        }
+        // the adhesion reaction of the step that just ran
+        slot_sums(a, a.part_adh, me, ad);
+        if (!split) slot_sums(a, a.part_link, me, ls);
 #pragma unroll
         for (int q = 0; q < 7; ++q) rm[RS_X + q] = xq[q];
         X0 = mk(xq[0], xq[1], xq[2]);
         e0 = quat_axis(xq + 3);
-        double *rw = a.rods + me * ROD_STRIDE;
+    }
+    // the momentum of the links the fluid step just streamed (their mass is
+    // booked now): summed by the upper half of the work-group when the rods
+    // fit in the lower half
+    if (split && me >= LB_MAX_RODS / 2 && me - LB_MAX_RODS / 2 < nr) {
+        double t[8];
+        slot_sums(a, a.part_link, me - LB_MAX_RODS / 2, t);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) rw[ROD_FA + q] = ad[q];
-        Fx = fs + mk(ad[0], ad[1], ad[2]);
-        Tx = ts + mk(ad[3], ad[4], ad[5]);
+        for (int q = 0; q < 8; ++q) lsum[me - LB_MAX_RODS / 2][q] = t[q];
     }
     // term offsets: exclusive scan of the list lengths over the work-group
     int v = nn;
@@ -535,7 +524,21 @@ __global__ void __launch_bounds__(LB_MAX_RODS) rod_integrate_kernel(RodBatch bt)
         total += wsum[w];
     }
     const int my_off = base + v - nn;
-    if (mine) toff[me] = my_off;
+    if (mine) {
+        if (split)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ls[q] = lsum[me][q];
+        double *rw = a.rods + me * ROD_STRIDE;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rw[ROD_FS + q] = ls[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rw[ROD_FA + q] = ad[q];
+        rw[ROD_SOLID] += ls[6];
+        rw[ROD_SOLID + 1] += ls[7];
+        Fx = mk(ls[0], ls[1], ls[2]) + mk(ad[0], ad[1], ad[2]);
+        Tx = mk(ls[3], ls[4], ls[5]) + mk(ad[3], ad[4], ad[5]);
+        toff[me] = my_off;
+    }
     if (me == 0) toff[nr] = total;
     const int nterm = total;
     // rod me's list into the kept term table (entries in list order)
@@ -715,6 +718,13 @@ __global__ void __launch_bounds__(MB) rod_mask_kernel(RodBatch bt) {
     __shared__ int wcount[MB / 64];
     __shared__ int row_start[MASK_ROWS + 1];
     __shared__ int row_x0[MASK_ROWS];
+    // the launch has twice as many work-groups as rods: the second half
+    // builds the neighbour lists for the next step
+    const int nrod = gridDim.x / 2;
+    if (int(blockIdx.x) >= nrod) {
+        if (threadIdx.x < 64) rod_list(bt, blockIdx.x - nrod);
+        return;
+    }
     int r;
     const RodArgs a = rod_of(bt, blockIdx.x, r);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1042,10 +1052,10 @@ __global__ void __launch_bounds__(RB) rod_link_kernel(RodBatch bt, int init) {
     int r;
     const RodArgs a = rod_of(bt, blockIdx.y, r);
     if (int(blockIdx.x) >= a.nblk) return;  // uniform per block
+    double *rod = a.rods + r * ROD_STRIDE;
     // work-group 0 books the transfers even when the list is empty
     if (!(COMMIT && blockIdx.x == 0) && idle_block(a, r, part_slot(a.part_link, a, r, blockIdx.x), 8)) return;
     S *f = static_cast<S *>(a.f);
-    double *rod = a.rods + r * ROD_STRIDE;
     const d3 X = ld3(rod + ROD_X);
     d3 Vr = ld3(rod + ROD_V), Lr = ld3(rod + ROD_L);
     if (COMMIT && !init) {
@@ -1304,7 +1314,7 @@ hipError_t launch_rods_place(int prec, const RodArgs &a, const RodBatch &bt, hip
     const int64_t n = int64_t(a.nx) * a.ny * a.nz;
     const dim3 grid(a.nblk, a.n_rods);
     hipLaunchKernelGGL(fill_i32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.newid, n, -1);
-    hipLaunchKernelGGL(rod_mask_kernel, dim3(a.n_rods), dim3(MB), 0, s, bt);
+    hipLaunchKernelGGL(rod_mask_kernel, dim3(2 * a.n_rods), dim3(MB), 0, s, bt);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 1);
@@ -1344,11 +1354,11 @@ hipError_t launch_rods_step(int prec, const RodBatch &bt, int n_lat, int total_r
     const dim3 grid(nblk_max, total_rods);
     return rods_by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        // adhesion, with one more column of work-groups for the neighbour lists
-        hipLaunchKernelGGL(rod_adhesion_kernel<S>, dim3(nblk_max + 1, total_rods), dim3(RB), 0, s, bt);
+        hipLaunchKernelGGL(rod_adhesion_kernel<S>, grid, dim3(RB), 0, s, bt);
         hipLaunchKernelGGL(rod_integrate_kernel, dim3(n_lat), dim3(LB_MAX_RODS), size_t(max_rods) * RS_N * sizeof(double),
                            s, bt);
-        hipLaunchKernelGGL(rod_mask_kernel, dim3(total_rods), dim3(MB), 0, s, bt);
+        // the re-mask, with one work-group per rod more for the neighbour lists
+        hipLaunchKernelGGL(rod_mask_kernel, dim3(2 * total_rods), dim3(MB), 0, s, bt);
         hipLaunchKernelGGL(rod_update_kernel<S>, grid, dim3(RB), 0, s, bt, 0);
         hipLaunchKernelGGL((rod_link_kernel<S, true>), grid, dim3(RB), 0, s, bt, 0);
         return hipGetLastError();
