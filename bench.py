@@ -537,21 +537,26 @@ def traffic_record(prec, tile, n_fluid, ms_fused, rods=False, bpl=None):
     return {"bytes_per_launch": b, "gbs": b / (ms_fused * 1e-3) / 1e9, "vs_algorithmic": b / (bpl * n_fluid)}
 
 
-def network_form(case, rods, reps=5):
-    """The deposit's resistor network (Eqs. 15-18) for the benchmark droplet's
-    rods: beads at unit spacing along each rod (lb_rod_beads), joined below
-    r_c = 5.25 (the deposit graph's contact distance: 1.05 times the rods'
-    contact distance 5, as 2.1 is for the paper's beads of diameter 2),
-    electrodes 120 apart about the droplet centre.  Timed per lb_kirchhoff
-    call (workspace allocation, neighbour scan, solve, currents, copy-out)."""
+def network_form(case, reps=5, n_rods=300, seed=5000):
+    """The deposit's resistor network (Eqs. 15-18) on a dried deposit: n_rods
+    rods of the benchmark's shape lying crossed on the substrate of the
+    256 x 128 x 64 cap (inputs.deposit_rods: centres uniform in x 40-216,
+    y 4-124 at z 3.5, directions at a uniform angle), as beads every 2 nodes
+    along each axis (lb_rod_beads), joined below r_c = 5.25 (1.05 times the
+    rods' contact distance 5, as 2.1 is for the paper's beads of diameter 2),
+    electrodes at x 68 and 188.  This deposit percolates between the
+    electrodes.  Timed per lb_kirchhoff call (neighbour scan, solve,
+    currents, copy-out; the workspace is the caller's)."""
     import torch
 
+    from paper_2607_06794_amd import inputs
     from paper_2607_06794_amd.sim import Lattice, kirchhoff
     from tests import cases
 
+    rods = inputs.deposit_rods(n_rods, (40.0, 216.0), (4.0, 124.0), 3.5, seed=seed)
     lp = rod_params(cases.lattice_params(case, "f32"))
     lat = Lattice(lp, case["rho"], case["mat"], rods=rods)
-    pos = lat.rod_beads(1.0)
+    pos = lat.rod_beads(2.0)
     torch.cuda.synchronize()
     lat.close()
     spec = dict(r_c=5.25, x_src=68.0, x_snk=188.0)
@@ -562,7 +567,8 @@ def network_form(case, rods, reps=5):
         o = kirchhoff(pos, **spec)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / reps * 1e3
-    res = {"beads": int(pos.shape[0]), "bead_spacing": 1.0, **spec, "edges": o["edges"],
+    res = {"deposit": f"{n_rods} crossed rods on the substrate (seed {seed})", "beads": int(pos.shape[0]),
+           "bead_spacing": 2.0, **spec, "edges": o["edges"], "max_degree": o["max_degree"],
            "iterations": o["iterations"], "rel_residual": o["rel_residual"], "I_tot": o["I_tot"],
            "kappa": o["kappa"], "ms_per_solve": ms}
     return res, pos.cpu().numpy()
@@ -786,8 +792,8 @@ def main():
         sur = surrogate_form(args.surrogate, epochs=args.surrogate_epochs, log_fn=log)
 
     net, net_pos = None, None
-    if args.network > 0 and rods is not None:
-        net, net_pos = network_form(case, rods)
+    if args.network > 0:
+        net, net_pos = network_form(case)
         log(f"[bench] network: {net['beads']} beads, {net['edges']} edges, {net['iterations']} CG iterations, "
             f"kappa* {net['kappa']:.4g}, {net['ms_per_solve']:.2f} ms per solve")
 

@@ -8,9 +8,10 @@
 //  * neighbours: one thread per bead scans every bead through LDS tiles in
 //    index order (a deterministic, ascending neighbour list per bead);
 //  * Kirchhoff: a Jacobi-preconditioned conjugate-gradient solve in one
-//    work-group -- the vectors stay in L2, each iteration costs one sparse
-//    product and two work-group reductions in a fixed order, and the loop
-//    is bounded by the caller's iteration limit.
+//    work-group -- the search direction in LDS (up to NET_LDS_P beads), the
+//    other vectors in L2; each iteration costs one sparse product and two
+//    work-group reductions in a fixed order, and the loop is bounded by the
+//    caller's iteration limit.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -133,10 +134,18 @@ __global__ void __launch_bounds__(NET_TB) net_edges_kernel(NetArgs a) {
     if (own) a.deg[i] = k;
 }
 
+// Networks of up to NET_LDS_P beads keep the search direction p in LDS for
+// the whole solve: the sparse product reads p at every neighbour, and from
+// LDS that read no longer waits on the load of the neighbour's index from L2.
+constexpr int NET_LDS_P = 16384;
+
 // potentials (Jacobi-preconditioned CG on the free beads; the electrode beads
 // are fixed), then Eq. 15's node currents and the current leaving the source
+template <bool LP>
 __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
     __shared__ double sh[4 * (NET_CG / 64)];
+    extern __shared__ double lds_p[];
+    double *P = LP ? lds_p : a.p;
     const int n = a.n;
     if (threadIdx.x == 0) {
         for (int q = 0; q < 4; ++q) a.cnt[q] = 0;
@@ -163,7 +172,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
         a.V[i] = ci == 1 ? a.dV : 0.0;
         a.r[i] = r;
         a.z[i] = z;
-        a.p[i] = z;
+        P[i] = z;
         s0[0] += r * z;
         s0[1] += r * r;
         maxdeg = max(maxdeg, d);
@@ -186,12 +195,25 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
             double q = 0.0;
             if (a.cls[i] == 0) {
                 const int dk = min(a.deg[i], NET_DEG);
+                const int *nb = a.nbr + size_t(i) * NET_DEG;
+                const double *gi = a.g + size_t(i) * NET_DEG;
                 double off = 0.0;
-                for (int k = 0; k < dk; ++k) off += a.g[size_t(i) * NET_DEG + k] * a.p[a.nbr[size_t(i) * NET_DEG + k]];
-                q = a.diag[i] * a.p[i] - off;
+                int k = 0;
+                // four edges' index and conductance loads in flight at a time,
+                // added in edge order
+                for (; k + 4 <= dk; k += 4) {
+                    const int j0 = nb[k], j1 = nb[k + 1], j2 = nb[k + 2], j3 = nb[k + 3];
+                    const double g0 = gi[k], g1 = gi[k + 1], g2 = gi[k + 2], g3 = gi[k + 3];
+                    off += g0 * P[j0];
+                    off += g1 * P[j1];
+                    off += g2 * P[j2];
+                    off += g3 * P[j3];
+                }
+                for (; k < dk; ++k) off += gi[k] * P[nb[k]];
+                q = a.diag[i] * P[i] - off;
             }
             a.q[i] = q;
-            pq[0] += a.p[i] * q;
+            pq[0] += P[i] * q;
         }
         wg_sum(pq, sh);
         if (!(pq[0] > 0.0)) break;  // same value in every thread
@@ -202,7 +224,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
             const double r = a.r[i] - alpha * a.q[i];
             const double dg = a.diag[i];
             const double z = dg > 0.0 ? r / dg : 0.0;
-            a.V[i] += alpha * a.p[i];
+            a.V[i] += alpha * P[i];
             a.r[i] = r;
             a.z[i] = z;
             s1[0] += r * z;
@@ -213,7 +235,7 @@ __global__ void __launch_bounds__(NET_CG) net_solve_kernel(NetArgs a) {
         rz = s1[0];
         rr = s1[1];
         for (int i = threadIdx.x; i < n; i += NET_CG)
-            if (a.cls[i] == 0) a.p[i] = a.z[i] + beta * a.p[i];
+            if (a.cls[i] == 0) P[i] = a.z[i] + beta * P[i];
         __syncthreads();  // the next product reads every bead's p
         ++it;
     }
@@ -264,7 +286,10 @@ hipError_t launch_net_edges(const NetArgs &a, hipStream_t s) {
 
 hipError_t launch_net_solve(const NetArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(net_solve_kernel, dim3(1), dim3(NET_CG), 0, s, a);
+    if (a.n <= NET_LDS_P)
+        hipLaunchKernelGGL(net_solve_kernel<true>, dim3(1), dim3(NET_CG), size_t(a.n) * sizeof(double), s, a);
+    else
+        hipLaunchKernelGGL(net_solve_kernel<false>, dim3(1), dim3(NET_CG), 0, s, a);
     return hipGetLastError();
 }
 

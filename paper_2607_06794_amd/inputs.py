@@ -197,6 +197,24 @@ def place_rods(n_req, length, radius, box, inside=None, seed=3000, gap=1.0, marg
     return np.array(placed).reshape(-1, 13)
 
 
+def deposit_rods(n, x_range, y_range, z, seed=5000):
+    """A dried deposit's rods: n rods lying on the substrate, axes in the xy
+    plane at height z, centres uniform in x_range x y_range and directions at
+    a uniform angle.  Draws per rod from PCG64(seed): centre x, centre y
+    (2 uniforms), angle (1 uniform), in that order.  Rods may cross (a
+    deposit's rods lie on each other).  Returns an [n][13] array: centre,
+    quaternion (w, x, y, z), zero velocity, zero angular momentum."""
+    rng = _rng(seed)
+    out = np.zeros((n, 13))
+    for r in range(n):
+        cx = x_range[0] + (x_range[1] - x_range[0]) * rng.random()
+        cy = y_range[0] + (y_range[1] - y_range[0]) * rng.random()
+        phi = 2.0 * np.pi * rng.random()
+        out[r, :3] = (cx, cy, z)
+        out[r, 3:7] = _quat_from_axis((np.cos(phi), np.sin(phi), 0.0))
+    return out
+
+
 def place_filaments(n_req, n_per, spacing, box, inside=None, seed=3500, clearance=2.5, margin=1.0, zmin=2.0,
                     max_trials=100000):
     """Random sequential placement of straight bead chains.
