@@ -284,7 +284,7 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     lats = [make(d) for d in specs]
     batch = Batch(lats)
     t0 = time.perf_counter()
-    xf, xb, healthy = SU.rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=warm)
+    xf, xb, healthy = SU.rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=warm, log=log_fn)
     t_gen = time.perf_counter() - t0
     batch.close()
     lat_status = []
@@ -692,6 +692,8 @@ def main():
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
     ap.add_argument("--network", type=int, default=1, help="resistor network of the rods' beads (0: skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
+    ap.add_argument("--surrogate-snapshots", type=int, default=8,
+                    help="canvases per droplet (pairs: 7/8 of the droplets x (snapshots - 1))")
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
     ap.add_argument("--unet-only", action="store_true", help="time the U-Net alone (one JSON line)")
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB of a plain copy for counter calibration, then exit")
@@ -789,7 +791,7 @@ def main():
     sur = None
     if args.surrogate > 0:
         log(f"[bench] surrogate form: {args.surrogate} droplets")
-        sur = surrogate_form(args.surrogate, epochs=args.surrogate_epochs, log_fn=log)
+        sur = surrogate_form(args.surrogate, n_snap=args.surrogate_snapshots, epochs=args.surrogate_epochs, log_fn=log)
 
     net, net_pos = None, None
     if args.network > 0:

@@ -333,13 +333,13 @@ def channel_scales(net, pairs, floor=1e-6):
     return np.maximum(np.sqrt(acc[:6] / max(acc[6], 1.0)), floor).astype(np.float32)
 
 
-def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True):
+def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True, log=None):
     """Canvases of every lattice every `interval` steps (after `warm` steps):
     tensors [n_lat, n_snap, P * 8] in FP32 and BF16, and a host array
     healthy[n_lat, n_snap]: so far no NaN, no non-positive density, no rod
     limit (status bits 1, 2, 8, 16, 32; the velocity bit 4 alone also trips
     on the start-up transient of a fresh cap) and no canvas speed above
-    0.15."""
+    0.15.  log(str), if given, hears of every snapshot taken."""
     import torch
 
     P = D * H * W
@@ -357,6 +357,8 @@ def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True)
             st = int(lat.observables(allow_unstable=True)["status"])
             u = xf[i, s].view(P, 8)[:, 2:5]
             healthy[i, s] = (st & ~(4 | 64)) == 0 and bool(torch.isfinite(u).all()) and float(u.abs().max()) <= 0.15
+        if log:
+            log(f"[surrogate] snapshot {s + 1}/{n_snap}: {int(healthy[:, s].sum())} of {len(lats)} lattices healthy")
     torch.cuda.synchronize()
     return xf, xb, healthy
 
