@@ -296,13 +296,14 @@ __device__ inline double sub_f(double h, const FilArgs &a) {
 }
 
 constexpr int ST_TPB = 64;
+constexpr int ST_LPB = 8;  // lanes per bead: each takes every eighth partner
 
 __global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src, int first) {
-    const int b = blockIdx.x * ST_TPB + threadIdx.x;
-    if (b >= a.n) return;
+    const int b = (blockIdx.x * ST_TPB + threadIdx.x) / ST_LPB;
+    const int ln = threadIdx.x % ST_LPB;
+    if (b >= a.n) return;  // uniform per group of ST_LPB lanes (n beads fill whole groups or none)
     const int dst = src == FIL_X ? FIL_XN : FIL_X;
     double *rec = a.bead + size_t(b) * FIL_STRIDE;
-    if (first) st(rec + FIL_IMP, v3{0.0, 0.0, 0.0});
     const double dt = 1.0 / a.n_sub;
     const double m = a.mass;
     unsigned flags = 0;
@@ -322,48 +323,39 @@ __global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src,
         if (kind == 3) fm += coh_f(d, a);
         if (fm != 0.0) Fi = Fi + v3{fm * r.x / d, fm * r.y / d, fm * r.z / d};
     };
-    // positions of the chain's bonded partners (at most two apart) and of the
-    // listed partners are loaded ahead, eight at a time, so that their loads
-    // overlap; the forces are then added in ascending partner index, the
-    // bonded ones merged into the ascending list
-    v3 Xb[4];
-    int ob[4], kb[4], nb = 0;
+    // the partners are split over the bead's lanes: lane j takes the bonded
+    // partner j (at most four: the chain's beads up to two apart) and the
+    // listed partners j, j + 8, ...; the lanes' sums are added with a fixed
+    // xor butterfly
+    {
+        int cnt = 0;
 #pragma unroll
-    for (int dj = -2; dj <= 2; ++dj) {
-        const int j = ib + dj;
-        if (dj == 0 || j < 0 || j >= a.per_chain) continue;
-        ob[nb] = ch * a.per_chain + j;
-        kb[nb] = (dj == -1 || dj == 1) ? 1 : 2;
-        ++nb;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (u < nb) Xb[u] = ld(a.bead + size_t(ob[u]) * FIL_STRIDE + src);
-    int ub = 0;
-    auto bonded_below = [&](int lim) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u >= ub && u < nb && ob[u] < lim) {
-                pair(Xb[u], kb[u]);
-                ub = u + 1;
-            }
-    };
-    const int nc = a.nbr_cnt[b];
-    for (int q0 = 0; q0 < nc; q0 += 8) {
-        int oi[8];
-        v3 Xo[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) oi[u] = q0 + u < nc ? a.nbr[size_t(b) * FIL_NBR + q0 + u] : -1;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) Xo[u] = oi[u] >= 0 ? ld(a.bead + size_t(oi[u]) * FIL_STRIDE + src) : X;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (oi[u] < 0) break;
-            bonded_below(oi[u]);
-            pair(Xo[u], oi[u] / a.per_chain == ch ? 0 : 3);
+        for (int dj = -2; dj <= 2; ++dj) {
+            const int j = ib + dj;
+            if (dj == 0 || j < 0 || j >= a.per_chain) continue;
+            if (cnt == ln) pair(ld(a.bead + size_t(ch * a.per_chain + j) * FIL_STRIDE + src), (dj == -1 || dj == 1) ? 1 : 2);
+            ++cnt;
         }
     }
-    bonded_below(a.n);
+    const int nc = a.nbr_cnt[b];
+    for (int q0 = ln; q0 < nc; q0 += 2 * ST_LPB) {
+        // two partners per lane and iteration, their loads in flight together
+        const int o0 = a.nbr[size_t(b) * FIL_NBR + q0];
+        const int q1 = q0 + ST_LPB;
+        const int o1 = q1 < nc ? a.nbr[size_t(b) * FIL_NBR + q1] : o0;
+        const v3 X0 = ld(a.bead + size_t(o0) * FIL_STRIDE + src), X1 = ld(a.bead + size_t(o1) * FIL_STRIDE + src);
+        pair(X0, o0 / a.per_chain == ch ? 0 : 3);
+        if (q1 < nc) pair(X1, o1 / a.per_chain == ch ? 0 : 3);
+    }
+#pragma unroll
+    for (int o = 1; o < ST_LPB; o <<= 1) {
+        Fi.x += __shfl_xor(Fi.x, o, 64);
+        Fi.y += __shfl_xor(Fi.y, o, 64);
+        Fi.z += __shfl_xor(Fi.z, o, 64);
+    }
+    flags |= __shfl_xor(flags, 1, 64) | __shfl_xor(flags, 2, 64) | __shfl_xor(flags, 4, 64);
+    if (ln != 0) return;
+    if (first) st(rec + FIL_IMP, v3{0.0, 0.0, 0.0});
     v3 Fs = {0.0, 0.0, 0.0};
     const double h = X.z - a.wall_z;
     if (a.wall_on) Fs.z = sub_f(h, a);
@@ -519,8 +511,8 @@ hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(fil_list_kernel, dim3((a.n + LT / 64 - 1) / (LT / 64)), dim3(LT), 0, s, a, range * range);
         int src = FIL_X;
         for (int sub = 0; sub < a.n_sub; ++sub) {
-            hipLaunchKernelGGL(fil_substep_kernel, dim3((a.n + ST_TPB - 1) / ST_TPB), dim3(ST_TPB), 0, s, a, src,
-                               sub == 0 ? 1 : 0);
+            hipLaunchKernelGGL(fil_substep_kernel, dim3((a.n * ST_LPB + ST_TPB - 1) / ST_TPB), dim3(ST_TPB), 0, s, a,
+                               src, sub == 0 ? 1 : 0);
             src = src == FIL_X ? FIL_XN : FIL_X;
         }
         hipLaunchKernelGGL(fil_spread_kernel, dim3(g), dim3(256), 0, s, a, src);
