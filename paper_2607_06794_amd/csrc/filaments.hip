@@ -22,8 +22,8 @@
 //   spread   one thread per bead adds its impulse times each weight into a
 //            fixed-point (2^-50) momentum grid with 64-bit integer atomics:
 //            integer addition is exact, so the sums do not depend on order;
-//   apply    one thread per (bead, stencil node): the first thread to claim a
-//            node adds its summed momentum dp to the stored state by the
+//   apply    one thread per (bead, stencil node): the node's owner (the
+//            lowest such index, recorded by the spread pass) adds its summed momentum dp to the stored state by the
 //            exact-difference rule f*_k += f^eq(rho_k, u_k + dp / rho) -
 //            f^eq(rho_k, u_k), which keeps every density and adds dp exactly.
 // All bead arithmetic is FP64.
@@ -390,31 +390,32 @@ __global__ __launch_bounds__(ST_TPB) void fil_substep_kernel(FilArgs a, int src,
 // 4. spread the impulses onto the fixed-point momentum grid
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fil_spread_kernel(FilArgs a, int last) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    // eight lanes per bead, lane e on stencil node e; each node's owner for
+    // the apply pass is the lowest (bead, e) index that touches it
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = t / 8, e = t % 8;
     if (b >= a.n) return;
     double *rec = a.bead + size_t(b) * FIL_STRIDE;
-    // the last substep's positions become the bead's position; the partner
-    // lists hold for moves below half the skin per update
-    const v3 X = ld(rec + last);
-    if (last != FIL_X) st(rec + FIL_X, X);
-    const v3 dd = min_image(X - ld(rec + FIL_X0), a);
-    unsigned flags = 0;
-    if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > 0.25 * a.skin * a.skin) flags |= ST_ROD;
-    if (!(X.x == X.x && X.y == X.y && X.z == X.z)) flags |= ST_NAN;
-    if (flags) atomicOr(a.status, flags);
-    if (rec[FIL_COUPLED] == 0.0) return;
-    const double imp[3] = {rec[FIL_IMP], rec[FIL_IMP + 1], rec[FIL_IMP + 2]};
-    for (int e = 0; e < 8; ++e) {
-        const int n = a.sten[size_t(b) * 8 + e];
-        if (n < 0) continue;
-        const double w = rec[FIL_W + e];
-        for (int d = 0; d < 3; ++d) {
-            const long long q = llrint(w * imp[d] * FIX_SCALE);
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.grid + int64_t(d) * a.fs + n),
-                      static_cast<unsigned long long>(q));
-        }
-        a.claim[n] = 1;
+    if (e == 0) {
+        // the last substep's positions become the bead's position; the
+        // partner lists hold for moves below half the skin per update
+        const v3 X = ld(rec + last);
+        if (last != FIL_X) st(rec + FIL_X, X);
+        const v3 dd = min_image(X - ld(rec + FIL_X0), a);
+        unsigned flags = 0;
+        if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > 0.25 * a.skin * a.skin) flags |= ST_ROD;
+        if (!(X.x == X.x && X.y == X.y && X.z == X.z)) flags |= ST_NAN;
+        if (flags) atomicOr(a.status, flags);
     }
+    if (rec[FIL_COUPLED] == 0.0) return;
+    const int n = a.sten[t];
+    if (n < 0) return;
+    const double w = rec[FIL_W + e];
+    for (int d = 0; d < 3; ++d) {
+        const long long q = llrint(w * rec[FIL_IMP + d] * FIX_SCALE);
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.grid + int64_t(d) * a.fs + n), static_cast<unsigned long long>(q));
+    }
+    atomicMin(a.claim + n, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,22 +433,33 @@ __global__ __launch_bounds__(256) void fil_apply_kernel(FilArgs a) {
     if (t >= a.n * 8) return;
     const int n = a.sten[t];
     if (n < 0) return;
-    if (atomicExch(a.claim + n, 0) != 1) return;
-    v3 dp;
-    unsigned long long *g = reinterpret_cast<unsigned long long *>(a.grid);
-    dp.x = double(static_cast<long long>(atomicExch(g + n, 0ull))) * FIX_INV;
-    dp.y = double(static_cast<long long>(atomicExch(g + a.fs + n, 0ull))) * FIX_INV;
-    dp.z = double(static_cast<long long>(atomicExch(g + 2 * a.fs + n, 0ull))) * FIX_INV;
+    // only the node's owner (set by the spread pass) applies it, then returns
+    // the owner slot and the node's sums to their empty values
+    if (a.claim[n] != t) return;
+    a.claim[n] = FIL_NO_OWNER;
+    long long *g = a.grid;
+    const v3 dp = {double(g[n]) * FIX_INV, double(g[a.fs + n]) * FIX_INV, double(g[2 * a.fs + n]) * FIX_INV};
+    g[n] = 0;
+    g[a.fs + n] = 0;
+    g[2 * a.fs + n] = 0;
     S *f = static_cast<S *>(a.f);
+    // the node's 38 populations, all loaded before any store (a store through
+    // f would otherwise order every later load behind it)
+    double fv[2][Q];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fv[k][i] = popf(a, f, k, i, n);
     double rho[2];
     v3 uk[2];
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         double r = 0.0;
         v3 j = {0.0, 0.0, 0.0};
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double fi = popf(a, f, k, i, n);
-            r += fi;
-            j = j + v3{cx(i) * fi, cy(i) * fi, cz(i) * fi};
+            r += fv[k][i];
+            j = j + v3{cx(i) * fv[k][i], cy(i) * fv[k][i], cz(i) * fv[k][i]};
         }
         rho[k] = r;
         uk[k] = r > 0.0 ? v3{j.x / r, j.y / r, j.z / r} : v3{0.0, 0.0, 0.0};
@@ -457,27 +469,35 @@ __global__ __launch_bounds__(256) void fil_apply_kernel(FilArgs a) {
     const v3 du = {dp.x / tot, dp.y / tot, dp.z / tot};
     // a node next to a static wall has already handed f*_j to the wall node
     // x + c_j as direction opp(j) (halfway bounce-back of the next pull): the
-    // updated value goes there too
+    // updated value goes there too (the 18 neighbours' materials loaded together)
     const bool near_wall = (a.mat[n] & MAT_NEAR_WALL) != 0;
-    const int x = int(n % a.nx), y = int((n / a.nx) % a.ny), z = int(n / (int64_t(a.nx) * a.ny));
+    const uint32_t un32 = static_cast<uint32_t>(n), row = un32 / uint32_t(a.nx);
+    const int x = int(un32 - row * uint32_t(a.nx)), y = int(row % uint32_t(a.ny)), z = int(row / uint32_t(a.ny));
+    uint32_t walls = 0;
+    if (near_wall) {
+        uint8_t mq[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) mq[i] = a.mat[nb_of(a, x, y, z, i)];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) walls |= is_static_wall(mq[i] & MAT_ID_MASK) ? 1u << i : 0u;
+    }
     // the plane below the reservoir booked the outflow of its stored f* when
     // the fluid step wrote it; the change of that outflow goes to the ledger
     const bool top = a.evap && z == a.nz - 2;
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         if (!(rho[k] > 0.0)) continue;
         const v3 un = uk[k] + du;
         double dout = 0.0;
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t idx = (int64_t(k) * Q + i) * a.fs + n;
-            const double fi = popf(a, f, k, i, n);
-            const double v = fi + (feq_i(i, rho[k], un) - feq_i(i, rho[k], uk[k]));
+            const double v = fv[k][i] + (feq_i(i, rho[k], un) - feq_i(i, rho[k], uk[k]));
             const S sv = Codec<S>::enc(static_cast<typename Codec<S>::C>(v - wgt<double>(i) * a.rho_ref[k]));
             f[idx] = sv;
-            if (top && cz(i) == 1) dout += popf(a, f, k, i, n) - fi;
-            if (near_wall && i > 0) {
-                const int64_t q = nb_of(a, x, y, z, i);
-                if (is_static_wall(a.mat[q] & MAT_ID_MASK)) f[(int64_t(k) * Q + opp(i)) * a.fs + q] = sv;
-            }
+            // the stored value as the next read of it decodes it
+            if (top && cz(i) == 1) dout += (static_cast<double>(Codec<S>::dec(sv)) + wgt<double>(i) * a.rho_ref[k]) - fv[k][i];
+            if ((walls >> i) & 1u) f[(int64_t(k) * Q + opp(i)) * a.fs + nb_of(a, x, y, z, i)] = sv;
         }
         if (top && dout != 0.0)
             atomicAdd(reinterpret_cast<unsigned long long *>(a.led + k),
@@ -501,7 +521,6 @@ static hipError_t fil_by_prec(int prec, F &&fn) {
 
 hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const int g = (a.n + 255) / 256;
     double range = a.d0;
     if (a.eps_coh > 0.0 && a.r_cut > range) range = a.r_cut;
     range += a.skin;
@@ -515,7 +534,7 @@ hipError_t launch_fil_step(int prec, const FilArgs &a, hipStream_t s) {
                                src, sub == 0 ? 1 : 0);
             src = src == FIL_X ? FIL_XN : FIL_X;
         }
-        hipLaunchKernelGGL(fil_spread_kernel, dim3(g), dim3(256), 0, s, a, src);
+        hipLaunchKernelGGL(fil_spread_kernel, dim3((a.n * 8 + 255) / 256), dim3(256), 0, s, a, src);
         hipLaunchKernelGGL(fil_apply_kernel<S>, dim3((a.n * 8 + 255) / 256), dim3(256), 0, s, a);
         return hipGetLastError();
     });

@@ -1473,7 +1473,7 @@ int lb_fil_set(lb_ctx *c, const double *beads_host, hipStream_t stream) {
         }
     HIP_TRY(hipMemcpyAsync(c->fil, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload beads");
     HIP_TRY(hipMemsetAsync(c->fil_grid, 0, 3 * size_t(c->fs) * sizeof(long long), stream), "clear momentum grid");
-    HIP_TRY(hipMemsetAsync(c->fil_claim, 0, size_t(c->fs) * sizeof(int), stream), "clear claims");
+    HIP_TRY(hipMemsetAsync(c->fil_claim, 0x7F, size_t(c->fs) * sizeof(int), stream), "clear owners");  // FIL_NO_OWNER
     HIP_TRY(hipMemsetAsync(c->fil_led, 0, 2 * sizeof(long long), stream), "clear filament ledger");
     HIP_TRY(hipMemsetAsync(c->fil_sten, 0xFF, size_t(n) * 8 * sizeof(int), stream), "clear stencils");
     HIP_TRY(hipStreamSynchronize(stream), "beads sync");

@@ -130,6 +130,7 @@ constexpr int FIL_XN = 27;                // position slot the substeps alternat
 constexpr int FIL_NBR = 48;               // non-bonded partners per bead
 constexpr int FIL_MAX = LB_FIL_MAX_BEADS; // beads per lattice
 constexpr double FIL_FIX = 1125899906842624.0;  // 2^50: fixed-point unit of the momentum grid and ledger
+constexpr int FIL_NO_OWNER = 0x7F7F7F7F;        // empty owner slot (the byte 0x7F repeated)
 
 struct FilArgs {
     void *f;          // current populations (post-collision state)
@@ -141,7 +142,7 @@ struct FilArgs {
     int *sten;              // [n][8] stencil node indices (-1: none)
     int *nbr, *nbr_cnt;     // [n][FIL_NBR], [n]
     long long *grid;        // [3][fs] momentum per node in units of 2^-50
-    int *claim;             // [fs] 1: grid entry waiting to be applied
+    int *claim;             // [fs] owner (lowest (bead, stencil) index) of a grid entry waiting to be applied, else FIL_NO_OWNER
     long long *led;         // [2] reservoir ledger change from the impulses, units of 2^-50
     int evap;               // the plane z = nz - 1 is the reservoir
     unsigned *status;
