@@ -124,16 +124,35 @@ __device__ void node_fields(const FilArgs &a, const S *f, int x, int y, int z, v
     const double tot = rho[0] + rho[1];
     const double ts = tot > 0.0 ? tot : 1.0;
     const double C0 = (rho[0] - rho[1]) / ts;
-    // Shan-Chen force of the stored densities and the lattice colour gradient
+    // Shan-Chen force of the stored densities and the lattice colour gradient;
+    // the neighbours' materials and stored densities are loaded together (the
+    // density array exists on every lattice with filaments; it is used only
+    // while it holds the current state)
+    uint8_t idn[Q];
+    double pn[Q][2];
+    {
+        const auto *ro = static_cast<const typename Codec<S>::C *>(a.rho);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int64_t m = nb_of(a, x, y, z, i);
+            idn[i] = a.mat[m] & MAT_ID_MASK;
+            pn[i][0] = double(ro[m]);
+            pn[i][1] = double(ro[a.fs + m]);
+        }
+    }
     v3 s[2] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     v3 g = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int64_t m = nb_of(a, x, y, z, i);
-        const uint8_t id = a.mat[m] & MAT_ID_MASK;
+        const uint8_t id = idn[i];
         double psi[2], Cn;
         if (id == MAT_FLUID) {
-            node_rho(a, f, m, psi);
+            if (a.rho_fresh) {
+                psi[0] = pn[i][0];
+                psi[1] = pn[i][1];
+            } else {
+                node_rho(a, f, nb_of(a, x, y, z, i), psi);
+            }
             const double tn = psi[0] + psi[1];
             Cn = (psi[0] - psi[1]) / (tn > 0.0 ? tn : 1.0);
         } else {
@@ -207,7 +226,8 @@ __global__ __launch_bounds__(256) void fil_gather_kernel(FilArgs a) {
     if (coupled && node >= 0) {
         w = w / wsum;
         const int64_t n = node;
-        node_fields(a, f, int(n % a.nx), int((n / a.nx) % a.ny), int(n / (int64_t(a.nx) * a.ny)), u, g);
+        const uint32_t un = static_cast<uint32_t>(n), row = un / uint32_t(a.nx);
+        node_fields(a, f, int(un - row * uint32_t(a.nx)), int(row % uint32_t(a.ny)), int(row / uint32_t(a.ny)), u, g);
     } else {
         node = -1;
         w = 0.0;
