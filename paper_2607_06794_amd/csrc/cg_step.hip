@@ -204,6 +204,7 @@ __global__ void __launch_bounds__(256) cg_collide_kernel(CGArgs a) {
     if (n >= a.nodes) return;
     const uint8_t mb = a.mat[n];
     if ((mb & MAT_ID_MASK) != MAT_FLUID) return;
+    const unsigned known = *a.status;  // status bits already raised before this launch
     int x, y, z;
     decode(n, a, x, y, z);
     C fv[2][Q];
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(256) cg_collide_kernel(CGArgs a) {
         unsigned st = 0;
         if (!(rt > C(0))) st |= ST_RHO;
         if (!(usq <= C(0.09))) st |= (usq != usq) ? ST_NAN : ST_SPEED;
-        if (st) atomicOr(a.status, st);
+        post_status(a.status, known, st);
     }
     const C uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
     // colour-blind post-collision populations: per component BGK towards

@@ -73,6 +73,24 @@ constexpr unsigned ST_NAN = 1u, ST_RHO = 2u, ST_SPEED = 4u, ST_ROD = 8u, ST_ROD_
 constexpr unsigned ST_REFILL_FAR = 64u;
 constexpr unsigned ST_NOTICES = ST_REFILL_FAR;
 
+// Adds per-node status bits to a lattice's status word.  `known` is the word
+// as the kernel found it at its start: bits already set are not sent again,
+// and the rest go out in one atomic per wavefront (the bits ORed over the
+// active lanes by ballots), so a lattice that has gone bad everywhere costs
+// no atomics at all after its first bad step (one per node and step to a
+// single word made such a lattice several times slower than a healthy one).
+// Every active lane of the wavefront calls it with its own bits.
+__device__ inline void post_status(unsigned *status, unsigned known, unsigned st) {
+    const unsigned fresh = st & ~known;
+    if (__ballot(fresh != 0) == 0) return;
+    unsigned w = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if (__ballot((fresh >> b) & 1u)) w |= 1u << b;
+    const unsigned long long act = __ballot(1);
+    if (__lane_id() == __ffsll(static_cast<long long>(act)) - 1) atomicOr(status, w);
+}
+
 // ---------------------------------------------------------------------------
 // storage codecs: S = element type in HBM, C = compute type in registers.
 // The kernels store and compute the deviation d_i = f_i - w_i*rho_ref[k]

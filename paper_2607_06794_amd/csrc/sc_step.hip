@@ -222,6 +222,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
     const __amdgpu_buffer_rsrc_t matr = make_rsrc(a.mat, nxy * a.nz);
 
     if (tid < 32) psi_tab[tid >> 1][tid & 1] = C(a.psi_tab[tid]);
+    const unsigned known = *a.status;  // status bits already raised before this launch
 
     // constants in compute precision; rref is the storage reference density
     // (populations travel as d_i = f_i - w_i rref)
@@ -657,7 +658,7 @@ __device__ __forceinline__ void sc_step_tile(const StepArgs &a, int b, int nblk,
                 sink_mv += double(sink_d);
             }
         }
-        if (st) atomicOr(a.status, st);
+        post_status(a.status, known, st);
 
         if (ledger_plane) {  // uniform across the block
             const int w = tid >> 6;

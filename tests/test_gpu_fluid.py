@@ -381,3 +381,44 @@ def test_degenerate_lattices(kind):
     assert np.abs(np.where(fl, f - run.f, 0)).max() <= 1e-13 * max(1.0, np.abs(run.f).max())
     assert np.allclose(obs["mass"], m0, rtol=1e-13, atol=1e-300) and obs["status"] == 0
     assert obs["fluid_nodes"] == int((mat == 0).sum())
+
+
+def test_failed_lattice_raises_status_without_slowing_down():
+    # a lattice whose state is NaN everywhere raises ST_NAN and then steps as
+    # fast as a healthy one: the status word takes each bit once per
+    # wavefront and only while it is not yet set (an atomic per node and step
+    # into the one word made such a lattice several times slower, and a
+    # batch with one failed lattice slowed down with it); a single NaN node
+    # raises the bit too
+    import torch
+
+    from paper_2607_06794_amd.sim import Lattice, LatticeParams
+
+    shape = (64, 128, 128)
+    mat = np.zeros(shape, np.uint8)
+    rng = np.random.default_rng(11)
+    # the A-rich bulk phase of the droplet cases (stable at G = 3.6)
+    ok = np.stack([1.0 + 1e-3 * rng.uniform(-1, 1, size=shape), 0.03 + 1e-4 * rng.uniform(-1, 1, size=shape)])
+    one = ok.copy()
+    one[0, 30, 60, 70] = np.nan
+    bad = np.full_like(ok, np.nan)
+    lp = LatticeParams(shape=shape, periodic=(True, True, True), prec="f32", G=3.6)
+    times, status = {}, {}
+    for name, rho in (("healthy", ok), ("one_nan", one), ("all_nan", bad)):
+        say(f"[gpu] failed-lattice status: {name} {shape}")
+        lat = Lattice(lp, rho, mat)
+        lat.step(5)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        lat.step(40)
+        e1.record(s)
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / 40
+        status[name] = int(lat.observables(allow_unstable=True)["status"])
+        lat.close()
+    say(f"[gpu] ms per step {times}, status {status}")
+    assert status["healthy"] == 0
+    assert status["one_nan"] & 1 and status["all_nan"] & 1
+    assert times["all_nan"] <= 1.5 * times["healthy"] + 0.02
