@@ -296,11 +296,15 @@ def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005):
 
     The network's prediction is lifted onto the lattice (rods advected and
     re-placed first); if its rho_A mass differs from M_t - rate * interval
-    (rate: the measured rho_A loss to the reservoir per step) by more than
-    `threshold` of M_t, the lattice returns to its state before the jump and
-    runs the `interval` steps of the method instead; otherwise K coupled
-    re-equilibration steps follow.  A jump books nothing in the reservoir
-    ledger.  Returns {"surrogate": bool, "mass_error": float}.
+    by more than `threshold` of M_t, the lattice returns to its state before
+    the jump and runs the `interval` steps of the method instead; otherwise
+    K coupled re-equilibration steps follow.  `rate` is the caller's estimate
+    of the rho_A mass the lattice loses per step over the interval, from
+    every cause (the reservoir, mass taken into moving rods); the drying
+    lattice's own loss rate is only steady enough for such an estimate once
+    the start-up transient of a fresh cap has passed.  A jump books nothing
+    in the reservoir ledger.  Returns {"surrogate": bool, "mass_error":
+    float, "mass": the lifted rho_A mass, "mass_t": M_t}.
     """
     import torch
 
@@ -317,9 +321,9 @@ def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005):
     if err > threshold:
         lat.restore(snap)
         lat.coupled_step(interval)
-        return {"surrogate": False, "mass_error": err}
+        return {"surrogate": False, "mass_error": err, "mass": m_pred, "mass_t": m_t}
     lat.coupled_step(K)
-    return {"surrogate": True, "mass_error": err}
+    return {"surrogate": True, "mass_error": err, "mass": m_pred, "mass_t": m_t}
 
 
 def channel_scales(net, pairs, floor=1e-6):
