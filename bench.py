@@ -253,7 +253,8 @@ def batched_form(steps, warmup, n_lattices=64):
     return out
 
 
-def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=50, jump_after=3, log_fn=None):
+def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=50, jump_after=3, lam=100.0,
+                   log_fn=None):
     """Learned surrogate: LBM trajectories of the droplet sweep (physically
     placed rods) restricted to the 128 x 64 x 32 canvas every `interval` steps;
     the U-Net is trained with the library's kernels on the first 7/8 of the
@@ -304,10 +305,10 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
             if finite[i, s] and finite[i, s + 1] and finite[i, s - 1]]
     net = SU.UNet(D, H, W).init(0)
     t0 = time.perf_counter()
-    hist = SU.fit(net, train, epochs=epochs, batch=4, lr=3e-4, lam=100.0, log=log_fn)
+    hist = SU.fit(net, train, epochs=epochs, batch=4, lr=3e-4, lam=lam, log=log_fn)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    ev = SU.evaluate(net, test, lam=100.0, prev=prev)
+    ev = SU.evaluate(net, test, lam=lam, prev=prev)
     # forward throughput of the network (matrix-core work)
     flops = sum(2.0 * 27 * (c1 + c2) * co * net.P[lvl] for _, c1, c2, co, _, lvl in net.layers)
     stream = torch.cuda.current_stream()
@@ -390,27 +391,53 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     ms_lbm = float(np.mean([t["ms_lbm"] for t in passed])) if passed else None
     ms_sur = float(np.mean([t["ms_advance"] for t in passed])) if passed else None
     eff = sum(t["ms_lbm"] for t in tried) / sum(t["ms_advance"] for t in tried)
-    ma = lat_a.observables(allow_unstable=True)
-    mb = lat_b.observables(allow_unstable=True)
-    mass_err = float(abs(mb["mass"][0] - ma["mass"][0]) / ma["mass"][0])
-    # deposit: L1 distance of the z-projected rod-fraction maps of the two
-    # end states on the canvas, over the LBM map's total
-    ca, _ = SU.restrict(lat_a, D, H, W)
-    cb, _ = SU.restrict(lat_b, D, H, W)
-    rmap_a = ca.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
-    rmap_b = cb.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
-    dep_err = float(np.abs(rmap_a - rmap_b).sum() / max(rmap_a.sum(), 1e-30)) if rmap_a.sum() > 0 else 0.0
-    # deposit density profile g^b along x (Eq. 14) and the contact graph
     nzl, nyl, nxl = specs[idx]["shape"]
     dspec = (16, 4, (nxl - 1) / 2, (nyl - 1) / 2, float(nxl), nyl / 2.0)
-    da, db = lat_a.deposit(*dspec), lat_b.deposit(*dspec)
-    g_err = float(np.abs(da["g_x"] - db["g_x"]).mean())
-    ra, rb = lat_a.rods(), lat_b.rods()
-    dx_r = rb[:, :3] - ra[:, :3]
-    for ax, n in ((0, nxl), (1, nyl)):
-        dx_r[:, ax] -= n * np.round(dx_r[:, ax] / n)
-    rod_err = float(np.sqrt((dx_r ** 2).sum(axis=1)).mean()) if len(ra) else 0.0
-    status_b = int(mb["status"])
+
+    def compare(ref, other):
+        """rho_A mass, deposit map, g^b (x) (Eq. 14), rod positions and
+        contact graph of `other` against `ref`."""
+        ma = ref.observables(allow_unstable=True)
+        mb = other.observables(allow_unstable=True)
+        # deposit: L1 distance of the z-projected rod-fraction maps of the
+        # two states on the canvas, over the reference map's total
+        ca, _ = SU.restrict(ref, D, H, W)
+        cb, _ = SU.restrict(other, D, H, W)
+        rmap_a = ca.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
+        rmap_b = cb.view(D, H, W, 8)[..., 5].sum(dim=0).cpu().numpy()
+        da, db = ref.deposit(*dspec), other.deposit(*dspec)
+        ra, rb = ref.rods(), other.rods()
+        dx_r = rb[:, :3] - ra[:, :3]
+        for ax, n in ((0, nxl), (1, nyl)):
+            dx_r[:, ax] -= n * np.round(dx_r[:, ax] / n)
+        return {"mass": float(abs(mb["mass"][0] - ma["mass"][0]) / ma["mass"][0]),
+                "deposit": float(np.abs(rmap_a - rmap_b).sum() / max(rmap_a.sum(), 1e-30)) if rmap_a.sum() > 0 else 0.0,
+                "g_x": float(np.abs(da["g_x"] - db["g_x"]).mean()),
+                "rods": float(np.sqrt((dx_r ** 2).sum(axis=1)).mean()) if len(ra) else 0.0,
+                "edges": [int(da["edges"]), int(da["largest"]), int(db["edges"]), int(db["largest"])],
+                "status": int(mb["status"])}
+
+    acc = compare(lat_a, lat_b)
+    # the method against itself: the kept droplet's state at t0 with every
+    # stored population scaled by 1 + 1e-6 u (u uniform in [-1, 1], seeded),
+    # run over the same interval; the same figures then give the resolution
+    # that one trajectory allows for each of them (the coupled dynamics
+    # amplifies such differences)
+    # (a twin run to t0: the steps are deterministic, and a snapshot goes
+    # back only into the lattice it came from)
+    lat_c = make(specs[idx])
+    lat_c.coupled_step(t0)
+    snap_c = lat_c.snapshot()
+    f32 = snap_c[0].view(torch.float32)
+    gen = torch.Generator(device=f32.device).manual_seed(7)
+    f32.mul_(1.0 + 1e-6 * (2.0 * torch.rand(f32.shape, generator=gen, device=f32.device) - 1.0))
+    lat_c.restore(snap_c)
+    lat_c.coupled_step(interval)
+    own = compare(lat_a, lat_c)
+    lat_c.close()
+    mass_err, dep_err, g_err, rod_err = acc["mass"], acc["deposit"], acc["g_x"], acc["rods"]
+    ra = lat_a.rods()
+    status_b = acc["status"]
     lat_a.close()
     lat_b.close()
     # end-of-rollout status words by what they flag: NaN (bit 1), a
@@ -429,7 +456,7 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     out = {
         "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
         "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),
-        "data_generation_s": t_gen, "train_s": t_train, "epochs": epochs, "train_loss": hist,
+        "data_generation_s": t_gen, "train_s": t_train, "epochs": epochs, "mass_loss_weight": lam, "train_loss": hist,
         "test_loss": ev, "gain_over_persistence": ev["persistence"] / max(ev["net"], 1e-30),
         "fwd_ms": ms_fwd, "fwd_tflops": flops / (ms_fwd * 1e-3) / 1e12, "fwd_gflop_per_sample": flops / 1e9,
         "jump_at_step": t0, "jumps_tried": len(tried), "jumps_passed": len(passed), "jumps": trials,
@@ -440,7 +467,8 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         "accuracy_droplet": idx, "accuracy_jump_passed": bool(adv["surrogate"]),
         "mass_error_vs_lbm": mass_err, "deposit_error_vs_lbm": dep_err, "g_x_error_vs_lbm": g_err,
         "rod_position_error": rod_err, "rods": int(len(ra)),
-        "contacts": {"lbm": [int(da["edges"]), int(da["largest"])], "surrogate": [int(db["edges"]), int(db["largest"])]},
+        "contacts": {"lbm": acc["edges"][:2], "surrogate": acc["edges"][2:]},
+        "lbm_self_sensitivity": {"perturbation": "populations x (1 + 1e-6 u) at the jump's start", **own},
         "fallback_threshold": 0.005, "jump_mass_error": float(adv["mass_error"]),
         "reservoir_rate_per_step": float(rate),
         "status_after_jump": status_b,
@@ -719,6 +747,8 @@ def main():
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
     ap.add_argument("--network", type=int, default=1, help="resistor network of the rods' beads (0: skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
+    ap.add_argument("--surrogate-lambda", type=float, default=100.0,
+                    help="weight of the squared relative rho_A mass error in the training loss")
     ap.add_argument("--surrogate-snapshots", type=int, default=16,
                     help="canvases per droplet (pairs: 7/8 of the droplets x (snapshots - 1))")
     ap.add_argument("--tile-cache", default=None, help="JSON file for the autotuner's tile choices")
@@ -818,7 +848,8 @@ def main():
     sur = None
     if args.surrogate > 0:
         log(f"[bench] surrogate form: {args.surrogate} droplets")
-        sur = surrogate_form(args.surrogate, n_snap=args.surrogate_snapshots, epochs=args.surrogate_epochs, log_fn=log)
+        sur = surrogate_form(args.surrogate, n_snap=args.surrogate_snapshots, epochs=args.surrogate_epochs,
+                             lam=args.surrogate_lambda, log_fn=log)
 
     net, net_pos = None, None
     if args.network > 0:

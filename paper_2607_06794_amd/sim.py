@@ -297,12 +297,14 @@ class Lattice:
 
     def snapshot(self):
         """Device copy of the lattice's state for restore(): the current
-        populations and the workspace (material map, rods, ledgers, status)."""
+        populations and the workspace (material map, rods, ledgers, status).
+        The workspace holds device addresses of this lattice's own buffers,
+        so a snapshot goes back only into the lattice that took it."""
         import torch
 
         torch.cuda.synchronize(self.device)
         cur = self.lib.lb_current_buffer(self._ctx)
-        snap = (self.f[cur].clone(), self.ws.clone())
+        snap = (self.f[cur].clone(), self.ws.clone(), self.ws.data_ptr())
         torch.cuda.synchronize(self.device)
         return snap
 
@@ -313,7 +315,9 @@ class Lattice:
         current now."""
         import torch
 
-        f, ws = snap
+        f, ws, owner = snap
+        if owner != self.ws.data_ptr():
+            raise ValueError("snapshot of another lattice (its workspace points at that lattice's buffers)")
         torch.cuda.synchronize(self.device)
         cur = self.lib.lb_current_buffer(self._ctx)
         self.f[cur].copy_(f)

@@ -367,17 +367,22 @@ def rollout_snapshots(batch, lats, n_snap, interval, D, H, W, warm=0, rods=True,
     return xf, xb, healthy
 
 
-def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None, warmup=100):
+def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None, warmup=100, lr_end=0.1):
     """Adam on (x_f32, x_bf16, y_f32) pairs, `batch` samples per update
     (gradients summed), in channel-normalised units (scales from the pairs);
-    the learning rate ramps up linearly over the first `warmup` updates.
-    Returns the mean training loss of every epoch."""
+    the learning rate ramps up linearly over the first `warmup` updates and
+    then follows a half cosine down to lr_end x lr at the last update (at a
+    constant rate, runs of several hundred updates per epoch blew up into a
+    network that predicts no change).  Returns the mean training loss of
+    every epoch."""
     rng = np.random.Generator(np.random.PCG64(seed))
     import torch
 
     net.set_scale(channel_scales(net, pairs))
     gout = torch.zeros(net.P[0] * COUT, dtype=torch.float32, device=net.device)
     hist = []
+    total = epochs * ((len(pairs) + batch - 1) // batch)
+    done = 0
     for ep in range(epochs):
         order = rng.permutation(len(pairs))
         tot = 0.0
@@ -389,8 +394,9 @@ def fit(net, pairs, epochs=1, batch=4, lr=1e-3, lam=1.0, seed=0, log=None, warmu
                 loss, _ = net.loss(xf, yf, lam, grad=gout)
                 net.backward(gout)
                 tot += loss
-            upd = net.step_count + 1
-            net.adam(lr * min(1.0, upd / max(1, warmup)))
+            done += 1
+            decay = lr_end + (1.0 - lr_end) * 0.5 * (1.0 + np.cos(np.pi * min(1.0, done / max(1, total))))
+            net.adam(lr * min(1.0, done / max(1, warmup)) * decay)
         hist.append(tot / max(1, len(pairs)))
         if log:
             log(f"[surrogate] epoch {ep}: loss {hist[-1]:.4e}")

@@ -489,5 +489,9 @@ def test_surrogate_advance_and_fallback():
     assert np.array_equal(fa, fb) and np.array_equal(lat.rods(), twin.rods())
     oa, ob = lat.observables(), twin.observables()
     assert np.array_equal(oa["ledger"], ob["ledger"]) and np.array_equal(oa["solid"], ob["solid"])
+    # a snapshot goes back only into its own lattice: the workspace it holds
+    # carries the device addresses of that lattice's buffers
+    with pytest.raises(ValueError):
+        twin.restore(lat.snapshot())
     lat.close()
     twin.close()
