@@ -254,7 +254,7 @@ def batched_form(steps, warmup, n_lattices=64):
 
 
 def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=50, jump_after=3, lam=100.0,
-                   log_fn=None):
+                   n_ens=12, log_fn=None):
     """Learned surrogate: LBM trajectories of the droplet sweep (physically
     placed rods) restricted to the 128 x 64 x 32 canvas every `interval` steps;
     the U-Net is trained with the library's kernels on the first 7/8 of the
@@ -435,6 +435,74 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     lat_c.coupled_step(interval)
     own = compare(lat_a, lat_c)
     lat_c.close()
+
+    # The deposit density as the paper measures it (the g^b profile of
+    # Eq. 14 averaged over independent runs and their mirror images): n_ens
+    # runs of the accuracy droplet's configuration (the cap's noise and the
+    # rod placement drawn anew), each carried from t0 over one interval by
+    # the method, by a jump (taken whatever the mass rule says, so that this
+    # measures the network; the rule's verdicts are counted), and by the
+    # method from populations scaled by 1 + 1e-6 u at t0 (the resolution).
+    ens = None
+    if n_ens > 0:
+        from paper_2607_06794_amd.sim import deposit_ensemble
+
+        lbm_runs, sur_runs, own_runs, per_sur, per_own, runs_info = [], [], [], [], [], []
+        passes = 0
+        for run in range(n_ens):
+            d = next(inputs.sweep_droplets(idx + 1, placement="physical", first=idx, run=run))
+            la, lb, lc = make(d), make(d), make(d)
+            for lat in (la, lb, lc):
+                lat.coupled_step(t0 - interval)
+            m_prev = float(lb.observables(allow_unstable=True)["mass"][0])
+            for lat in (la, lb, lc):
+                lat.coupled_step(interval)
+            ob = lb.observables(allow_unstable=True)
+            if int(ob["status"]) & 3:
+                runs_info.append({"run": run, "skipped": f"status {int(ob['status'])} at step {t0}"})
+                for lat in (la, lb, lc):
+                    lat.close()
+                continue
+            rate_r = (m_prev - float(ob["mass"][0])) / interval
+            snap = lc.snapshot()
+            f32 = snap[0].view(torch.float32)
+            gen = torch.Generator(device=f32.device).manual_seed(100 + run)
+            f32.mul_(1.0 + 1e-6 * (2.0 * torch.rand(f32.shape, generator=gen, device=f32.device) - 1.0))
+            lc.restore(snap)
+            del snap, f32
+            la.coupled_step(interval)
+            lc.coupled_step(interval)
+            st_ac = [int(lat.observables(allow_unstable=True)["status"]) for lat in (la, lc)]
+            if (st_ac[0] | st_ac[1]) & 3:  # the method itself failed over the interval: no member
+                runs_info.append({"run": run, "skipped": f"method status {st_ac} after the interval"})
+                for lat in (la, lb, lc):
+                    lat.close()
+                continue
+            r = SU.advance(lb, net, D, H, W, interval=interval, K=K, rate=rate_r, threshold=1.0)
+            passes += int(r["mass_error"] <= 0.005)
+            ga, gb, gc = (lat.deposit(*dspec)["g_x"] for lat in (la, lb, lc))
+            per_sur.append(float(np.abs(ga - gb).mean()))
+            per_own.append(float(np.abs(ga - gc).mean()))
+            runs_info.append({"run": run, "rods": int(la.n_rods), "g_x_error": per_sur[-1], "g_x_error_own": per_own[-1],
+                              "status": [int(lat.observables(allow_unstable=True)["status"]) for lat in (la, lb, lc)]})
+            lbm_runs.append(la)
+            sur_runs.append(lb)
+            own_runs.append(lc)
+        if lbm_runs:
+            ea, eb, ec = (deposit_ensemble(runs, *dspec[:6], mirror=True)["g_x"]
+                          for runs in (lbm_runs, sur_runs, own_runs))
+            ens = {"droplet": idx, "runs": len(lbm_runs), "runs_tried": n_ens, "mirror_images": True, "from_step": t0,
+                   "g_x_error": float(np.abs(ea - eb).mean()), "g_x_error_own": float(np.abs(ea - ec).mean()),
+                   "per_run_g_x_error": float(np.mean(per_sur)), "per_run_g_x_error_own": float(np.mean(per_own)),
+                   "jumps_within_rule": passes, "g_x_lbm": ea.tolist(), "g_x_surrogate": eb.tolist(),
+                   "g_x_own": ec.tolist(), "per_run": runs_info}
+        for lat in lbm_runs + sur_runs + own_runs:
+            lat.close()
+        if log_fn and ens:
+            log_fn(f"[surrogate] ensemble of {ens['runs']} runs with mirror images: g_x error "
+                   f"{ens['g_x_error']:.4f} (the method against itself {ens['g_x_error_own']:.4f}; one run "
+                   f"{ens['per_run_g_x_error']:.4f} / {ens['per_run_g_x_error_own']:.4f}), "
+                   f"{passes} of {ens['runs']} jumps within the rule")
     mass_err, dep_err, g_err, rod_err = acc["mass"], acc["deposit"], acc["g_x"], acc["rods"]
     ra = lat_a.rods()
     status_b = acc["status"]
@@ -469,6 +537,7 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         "rod_position_error": rod_err, "rods": int(len(ra)),
         "contacts": {"lbm": acc["edges"][:2], "surrogate": acc["edges"][2:]},
         "lbm_self_sensitivity": {"perturbation": "populations x (1 + 1e-6 u) at the jump's start", **own},
+        "deposit_ensemble": ens,
         "fallback_threshold": 0.005, "jump_mass_error": float(adv["mass_error"]),
         "reservoir_rate_per_step": float(rate),
         "status_after_jump": status_b,
@@ -747,6 +816,8 @@ def main():
     ap.add_argument("--surrogate", type=int, default=64, help="droplets for the surrogate data (0: skip)")
     ap.add_argument("--network", type=int, default=1, help="resistor network of the rods' beads (0: skip)")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
+    ap.add_argument("--surrogate-ensemble", type=int, default=12,
+                    help="independent runs of the accuracy droplet for the ensemble deposit comparison (0: skip)")
     ap.add_argument("--surrogate-lambda", type=float, default=100.0,
                     help="weight of the squared relative rho_A mass error in the training loss")
     ap.add_argument("--surrogate-snapshots", type=int, default=16,
@@ -849,7 +920,7 @@ def main():
     if args.surrogate > 0:
         log(f"[bench] surrogate form: {args.surrogate} droplets")
         sur = surrogate_form(args.surrogate, n_snap=args.surrogate_snapshots, epochs=args.surrogate_epochs,
-                             lam=args.surrogate_lambda, log_fn=log)
+                             lam=args.surrogate_lambda, n_ens=args.surrogate_ensemble, log_fn=log)
 
     net, net_pos = None, None
     if args.network > 0:

@@ -283,7 +283,7 @@ def cap_inside(spec: CapSpec):
     return inside
 
 
-def sweep_droplets(n=64, seed0=4000, rods=True, placement="stress"):
+def sweep_droplets(n=64, seed0=4000, rods=True, placement="stress", first=0, run=0):
     """Parameter sweep of sessile caps of uneven size (many-droplet batches).
 
     Droplet i (seed seed0 + i): NX from (128, 160, 192, 224, 256) in turn,
@@ -297,9 +297,13 @@ def sweep_droplets(n=64, seed0=4000, rods=True, placement="stress"):
     seed seed0 + 500 + i, 3 trials per requested rod), or with
     placement="physical" as many of them as fit fully inside the cap with a
     one-node margin (seed seed0 + 500 + i, 20 trials per requested rod).
-    Yields dicts with shape, rho, mat, rods, rod_length, eps_att, aspect.
+    Yields dicts with shape, rho, mat, rods, rod_length, eps_att, aspect for
+    droplets first .. n - 1.  run > 0 gives an independent run of the same
+    droplets: the same shape and parameters, the cap's noise drawn with seed
+    seed0 + i + 1000 run and the rods placed with seed seed0 + 500 + i +
+    1000 run.
     """
-    for i in range(n):
+    for i in range(first, n):
         nx = (128, 160, 192, 224, 256)[i % 5]
         ny, nz = nx // 2, 48 + 16 * (nx - 128) // 128
         rng = _rng(seed0 + i)
@@ -310,13 +314,13 @@ def sweep_droplets(n=64, seed0=4000, rods=True, placement="stress"):
         fx = 0.6 * nx
         fy = fx / ar
         spec = CapSpec(shape=(nz, ny, nx), footprint=(fx, fy), height=min(0.4 * nz, 0.66 * fy),
-                       stripe=(min(fx + 20.0, nx), min(fy + 20.0, ny)), seed=seed0 + i)
+                       stripe=(min(fx + 20.0, nx), min(fy + 20.0, ny)), seed=seed0 + i + 1000 * run)
         rho, mat = sessile_cap(spec)
         r = None
         if rods and placement == "physical":
-            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=cap_inside(spec), seed=seed0 + 500 + i,
-                           margin=1.0, max_trials=20 * n_rods)
+            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=cap_inside(spec),
+                           seed=seed0 + 500 + i + 1000 * run, margin=1.0, max_trials=20 * n_rods)
         elif rods:
-            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=None, seed=seed0 + 500 + i,
+            r = place_rods(n_rods, length, 2.0, (nx, ny, nz), inside=None, seed=seed0 + 500 + i + 1000 * run,
                            max_trials=3 * n_rods)
         yield dict(shape=(nz, ny, nx), rho=rho, mat=mat, rods=r, rod_length=length, eps_att=eps, aspect=ar)
