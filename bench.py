@@ -254,7 +254,7 @@ def batched_form(steps, warmup, n_lattices=64):
 
 
 def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=50, jump_after=3, lam=100.0,
-                   n_ens=12, log_fn=None):
+                   n_ens=12, drift=0.5, log_fn=None):
     """Learned surrogate: LBM trajectories of the droplet sweep (physically
     placed rods) restricted to the 128 x 64 x 32 canvas every `interval` steps;
     the U-Net is trained with the library's kernels on the first 7/8 of the
@@ -282,6 +282,13 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         lp = rod_params(cases.lattice_params(c, "f32"), length=d["rod_length"])
         lp.eps_att = d["eps_att"]
         return Lattice(lp, d["rho"], d["mat"], rods=d["rods"] if d["rods"] is not None and len(d["rods"]) else None)
+
+    def rods_centres(lat):
+        """Rod centres (CUDA FP64 [n, 3]) for a jump that continues each
+        rod's displacement since now; None when the jump holds the rods."""
+        if drift < 0 or not lat.n_rods:
+            return None
+        return torch.from_numpy(np.ascontiguousarray(lat.rods()[:, :3])).to(lat.device)
 
     lats = [make(d) for d in specs]
     batch = Batch(lats)
@@ -338,11 +345,13 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     t0 = warm + jump_after * interval
     trials = []
     keep = None
+    ens_pick = None
     for idx in range(ntrain, len(specs)):
         lat_a, lat_b = make(specs[idx]), make(specs[idx])
         for lat in (lat_a, lat_b):
             lat.coupled_step(t0 - interval)
         m_prev = float(lat_b.observables(allow_unstable=True)["mass"][0])
+        x_prev = rods_centres(lat_b)
         for lat in (lat_a, lat_b):
             lat.coupled_step(interval)
         ob = lat_b.observables(allow_unstable=True)
@@ -361,7 +370,8 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
         torch.cuda.synchronize()
         ms_lbm = e0.elapsed_time(e1)
         e0.record(stream)
-        adv = SU.advance(lat_b, net, D, H, W, interval=interval, K=K, rate=rate, threshold=0.005)
+        adv = SU.advance(lat_b, net, D, H, W, interval=interval, K=K, rate=rate, threshold=0.005, rods_prev=x_prev,
+                         drift=drift)
         e1.record(stream)
         torch.cuda.synchronize()
         ms_sur = e0.elapsed_time(e1)
@@ -372,20 +382,25 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
                        "rule_error_of_lbm": abs(m_lbm - (m_now - rate * interval)) / m_now,
                        "jump_mass_error_vs_lbm": abs(float(adv["mass"]) - m_lbm) / m_lbm,
                        "lbm_status": int(oa["status"])})
-        # accuracy figures on the largest test droplet whose jump passed (else the largest)
-        if keep is None or (adv["surrogate"] and (not keep[4] or nodes > keep[5])) or \
-                (not keep[4] and not adv["surrogate"] and nodes > keep[5]):
+        # accuracy figures on the largest test droplet with rods whose jump
+        # passed (else the largest with rods, else the largest); the ensemble
+        # below takes the largest tried droplet with rods whatever its jump did
+        has_rods = lat_b.n_rods > 0
+        if has_rods and (ens_pick is None or nodes > ens_pick[1]):
+            ens_pick = (idx, nodes)
+        key = (bool(adv["surrogate"]) and has_rods, has_rods, nodes)
+        if keep is None or key > keep[7]:
             if keep is not None:
                 keep[0].close()
                 keep[1].close()
-            keep = [lat_a, lat_b, idx, rate, bool(adv["surrogate"]), nodes, adv]
+            keep = [lat_a, lat_b, idx, rate, bool(adv["surrogate"]), nodes, adv, key]
         else:
             lat_a.close()
             lat_b.close()
     if keep is None:  # every test droplet failed before the jump
         return {"canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
                 "test_loss": ev, "jump_at_step": t0, "jumps_tried": 0, "jumps_passed": 0, "jumps": trials}
-    lat_a, lat_b, idx, rate, _, _, adv = keep
+    lat_a, lat_b, idx, rate, _, _, adv, _ = keep
     tried = [t for t in trials if "skipped" not in t]
     passed = [t for t in tried if t["passed"]]
     ms_lbm = float(np.mean([t["ms_lbm"] for t in passed])) if passed else None
@@ -444,17 +459,24 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     # measures the network; the rule's verdicts are counted), and by the
     # method from populations scaled by 1 + 1e-6 u at t0 (the resolution).
     ens = None
-    if n_ens > 0:
+    if n_ens > 0 and ens_pick is not None:
+        eidx = ens_pick[0]
+        enz, eny, enx = specs[eidx]["shape"]
+        edspec = (16, 4, (enx - 1) / 2, (eny - 1) / 2, float(enx), eny / 2.0)
         from paper_2607_06794_amd.sim import deposit_ensemble
 
         lbm_runs, sur_runs, own_runs, per_sur, per_own, runs_info = [], [], [], [], [], []
         passes = 0
         for run in range(n_ens):
-            d = next(inputs.sweep_droplets(idx + 1, placement="physical", first=idx, run=run))
+            d = next(inputs.sweep_droplets(eidx + 1, placement="physical", first=eidx, run=run))
+            if d["rods"] is None or len(d["rods"]) == 0:
+                runs_info.append({"run": run, "skipped": "no rod fits"})
+                continue
             la, lb, lc = make(d), make(d), make(d)
             for lat in (la, lb, lc):
                 lat.coupled_step(t0 - interval)
             m_prev = float(lb.observables(allow_unstable=True)["mass"][0])
+            x_prev_r = rods_centres(lb)
             for lat in (la, lb, lc):
                 lat.coupled_step(interval)
             ob = lb.observables(allow_unstable=True)
@@ -478,9 +500,10 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
                 for lat in (la, lb, lc):
                     lat.close()
                 continue
-            r = SU.advance(lb, net, D, H, W, interval=interval, K=K, rate=rate_r, threshold=1.0)
+            r = SU.advance(lb, net, D, H, W, interval=interval, K=K, rate=rate_r, threshold=1.0, rods_prev=x_prev_r,
+                           drift=drift)
             passes += int(r["mass_error"] <= 0.005)
-            ga, gb, gc = (lat.deposit(*dspec)["g_x"] for lat in (la, lb, lc))
+            ga, gb, gc = (lat.deposit(*edspec)["g_x"] for lat in (la, lb, lc))
             per_sur.append(float(np.abs(ga - gb).mean()))
             per_own.append(float(np.abs(ga - gc).mean()))
             runs_info.append({"run": run, "rods": int(la.n_rods), "g_x_error": per_sur[-1], "g_x_error_own": per_own[-1],
@@ -489,9 +512,9 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
             sur_runs.append(lb)
             own_runs.append(lc)
         if lbm_runs:
-            ea, eb, ec = (deposit_ensemble(runs, *dspec[:6], mirror=True)["g_x"]
+            ea, eb, ec = (deposit_ensemble(runs, *edspec, mirror=True)["g_x"]
                           for runs in (lbm_runs, sur_runs, own_runs))
-            ens = {"droplet": idx, "runs": len(lbm_runs), "runs_tried": n_ens, "mirror_images": True, "from_step": t0,
+            ens = {"droplet": eidx, "runs": len(lbm_runs), "runs_tried": n_ens, "mirror_images": True, "from_step": t0,
                    "g_x_error": float(np.abs(ea - eb).mean()), "g_x_error_own": float(np.abs(ea - ec).mean()),
                    "per_run_g_x_error": float(np.mean(per_sur)), "per_run_g_x_error_own": float(np.mean(per_own)),
                    "jumps_within_rule": passes, "g_x_lbm": ea.tolist(), "g_x_surrogate": eb.tolist(),
@@ -524,7 +547,8 @@ def surrogate_form(n_droplets=64, n_snap=8, interval=500, epochs=2, warm=200, K=
     out = {
         "canvas": [W, H, D], "droplets": len(specs), "train_pairs": len(train), "test_pairs": len(test),
         "interval_steps": interval, "reequilibration_steps": K, "params": int(net.nparam),
-        "data_generation_s": t_gen, "train_s": t_train, "epochs": epochs, "mass_loss_weight": lam, "train_loss": hist,
+        "data_generation_s": t_gen, "train_s": t_train, "epochs": epochs, "mass_loss_weight": lam, "rod_drift": drift,
+        "train_loss": hist,
         "test_loss": ev, "gain_over_persistence": ev["persistence"] / max(ev["net"], 1e-30),
         "fwd_ms": ms_fwd, "fwd_tflops": flops / (ms_fwd * 1e-3) / 1e12, "fwd_gflop_per_sample": flops / 1e9,
         "jump_at_step": t0, "jumps_tried": len(tried), "jumps_passed": len(passed), "jumps": trials,
@@ -818,6 +842,9 @@ def main():
     ap.add_argument("--surrogate-epochs", type=int, default=40)
     ap.add_argument("--surrogate-ensemble", type=int, default=12,
                     help="independent runs of the accuracy droplet for the ensemble deposit comparison (0: skip)")
+    ap.add_argument("--surrogate-drift", type=float, default=0.5,
+                    help="a jump moves each rod by this times its displacement over the interval before "
+                         "(negative: rods held in place)")
     ap.add_argument("--surrogate-lambda", type=float, default=100.0,
                     help="weight of the squared relative rho_A mass error in the training loss")
     ap.add_argument("--surrogate-snapshots", type=int, default=16,
@@ -920,7 +947,8 @@ def main():
     if args.surrogate > 0:
         log(f"[bench] surrogate form: {args.surrogate} droplets")
         sur = surrogate_form(args.surrogate, n_snap=args.surrogate_snapshots, epochs=args.surrogate_epochs,
-                             lam=args.surrogate_lambda, n_ens=args.surrogate_ensemble, log_fn=log)
+                             lam=args.surrogate_lambda, n_ens=args.surrogate_ensemble, drift=args.surrogate_drift,
+                             log_fn=log)
 
     net, net_pos = None, None
     if args.network > 0:

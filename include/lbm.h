@@ -517,6 +517,16 @@ int lb_sur_lift(lb_ctx *ctx, const float *coarse_f32, int32_t D, int32_t H, int3
  * fills the vacated nodes.  Asynchronous. */
 int lb_sur_jump_rods(lb_ctx *ctx, const float *coarse_now, const float *coarse_next, int32_t D, int32_t H, int32_t W,
                      double steps, hipStream_t stream);
+/* Rods over a surrogate jump from their own recent motion (the alternative to
+ * lb_sur_jump_rods): each centre continues `factor` times its minimum-image
+ * displacement since x_prev, the device array [n_rods][3] (FP64, x y z) of the
+ * centres one interval earlier (owned by the caller, read before the call
+ * returns its work to the stream); kept one node off closed end planes.
+ * Velocity, orientation and angular momentum are kept; the same rods-only
+ * relaxation and re-placement as lb_sur_jump_rods follow.  Call before
+ * lb_sur_lift.  LB_EINVAL for a null pointer or a non-finite factor; a lattice
+ * without rods returns at once.  Asynchronous. */
+int lb_sur_drift_rods(lb_ctx *ctx, const double *x_prev, double factor, hipStream_t stream);
 
 /*
  * 3-D convolution, 3 x 3 x 3 taps, zero padding, channels-last BF16 tensors

@@ -56,6 +56,7 @@ EXPORTS = (
     "lb_sur_restrict",
     "lb_sur_lift",
     "lb_sur_jump_rods",
+    "lb_sur_drift_rods",
     "lb_conv3d_forward",
     "lb_conv3d_backward_data",
     "lb_conv3d_backward_weights",
@@ -365,6 +366,7 @@ def load(path: str = LIB_PATH):
         "lb_sur_restrict": [V, I32, I32, I32, V, V, V],
         "lb_sur_lift": [V, V, I32, I32, I32, V],
         "lb_sur_jump_rods": [V, V, V, I32, I32, I32, D_, V],
+        "lb_sur_drift_rods": [V, V, D_, V],
         "lb_conv3d_forward": [P(LbConv), V],
         "lb_conv3d_backward_data": [P(LbConv), V, V, V],
         "lb_conv3d_backward_weights": [P(LbConv), V, V, V, V],

@@ -1054,6 +1054,21 @@ int lb_sur_jump_rods(lb_ctx *c, const float *coarse_now, const float *coarse_nex
     return LB_OK;
 }
 
+int lb_sur_drift_rods(lb_ctx *c, const double *x_prev, double factor, hipStream_t stream) {
+    if (!c || !x_prev) return fail(LB_EINVAL, "null argument");
+    if (!std::isfinite(factor)) return fail(LB_EINVAL, "non-finite drift factor");
+    const lb_params &p = c->p;
+    if (p.n_rods == 0) return LB_OK;
+    c->rho_fresh = 0;
+    const RodArgs &a = c->rodargs_host[c->cur];
+    const RodBatch bt{c->rodargs_dev + c->cur, nullptr, 0};
+    HIP_TRY(launch_rods_drift(a, bt, x_prev, factor, stream), "rod drift");
+    HIP_TRY(launch_rods_place(p.prec, a, bt, stream), "re-place rods");
+    const int per[3] = {p.periodic[0], p.periodic[1], p.periodic[2]};
+    HIP_TRY(launch_flags(c->mat, p.nx, p.ny, p.nz, per, stream), "flags after the drift");
+    return LB_OK;
+}
+
 static int conv_check(const lb_conv *a, bool fwd) {
     if (!a || !a->x1 || !a->w) return fail(LB_EINVAL, "null convolution argument");
     if (fwd && !a->wt) return fail(LB_EINVAL, "the forward needs the packed weights wt");

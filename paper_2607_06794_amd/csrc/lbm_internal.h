@@ -117,6 +117,9 @@ hipError_t launch_rods_sums(const RodArgs &a, double *out, hipStream_t s);
 // rod nodes are returned to fluid (re-place with launch_rods_place)
 hipError_t launch_rods_jump(const RodArgs &a, const RodBatch &bt, const float *c0, const float *c1, int D, int H, int W,
                             double steps, hipStream_t s);
+// rods continue factor x their displacement since x_prev ([n_rods][3] centres,
+// device), relaxed like a jump; re-place with launch_rods_place
+hipError_t launch_rods_drift(const RodArgs &a, const RodBatch &bt, const double *x_prev, double factor, hipStream_t s);
 hipError_t launch_rods_link(int prec, const RodArgs &a, const RodBatch &bt, hipStream_t s);
 
 // Bead-spring filaments (filaments.hip): bead records FIL_STRIDE doubles

@@ -1202,6 +1202,26 @@ __global__ void rod_jump_kernel(RodBatch bt, const float *c0, const float *c1, i
     st3(rod + ROD_V, V);
 }
 
+// Rods over a jump from their own recent motion: each centre continues
+// `factor` times the (minimum-image) displacement it made since x_prev, the
+// centres one interval earlier ([n_rods][3]); kept one node off closed end
+// planes like the advected jump.  Velocity, orientation and angular momentum
+// are kept.
+__global__ void rod_drift_kernel(RodBatch bt, const double *x_prev, double factor) {
+    const RodArgs a = bt.all[0];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_rods) return;
+    double *rod = a.rods + r * ROD_STRIDE;
+    d3 X = ld3(rod + ROD_X);
+    const d3 dX = min_image(X - ld3(x_prev + 3 * r), a);
+    X = X + factor * dX;
+    if (a.px) X.x = X.x - a.nx * floor(X.x / a.nx);
+    if (a.py) X.y = X.y - a.ny * floor(X.y / a.ny);
+    if (a.pz) X.z = X.z - a.nz * floor(X.z / a.nz);
+    if (!a.pz) X.z = clamp_ends(a, quat_axis(rod + ROD_Q), X.z);
+    st3(rod + ROD_X, X);
+}
+
 // Rods-only relaxation after the advection of a jump: overlaps the jump made
 // (axis segments closer than the contact distance d0 of the excluded-volume
 // potential, or an axis end closer than d0_wall to the wall) are removed by
@@ -1328,6 +1348,15 @@ hipError_t launch_rods_jump(const RodArgs &a, const RodBatch &bt, const float *c
     if (a.n_rods == 0) return hipSuccess;
     const int64_t n = int64_t(a.nx) * a.ny * a.nz;
     hipLaunchKernelGGL(rod_jump_kernel, dim3((a.n_rods + 63) / 64), dim3(64), 0, s, bt, c0, c1, D, H, W, steps);
+    hipLaunchKernelGGL(rod_relax_kernel, dim3(1), dim3(LB_MAX_RODS), size_t(a.n_rods) * 6 * sizeof(double), s, bt);
+    hipLaunchKernelGGL(unrod_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.mat, a.rodid, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rods_drift(const RodArgs &a, const RodBatch &bt, const double *x_prev, double factor, hipStream_t s) {
+    if (a.n_rods == 0) return hipSuccess;
+    const int64_t n = int64_t(a.nx) * a.ny * a.nz;
+    hipLaunchKernelGGL(rod_drift_kernel, dim3((a.n_rods + 63) / 64), dim3(64), 0, s, bt, x_prev, factor);
     hipLaunchKernelGGL(rod_relax_kernel, dim3(1), dim3(LB_MAX_RODS), size_t(a.n_rods) * 6 * sizeof(double), s, bt);
     hipLaunchKernelGGL(unrod_kernel, dim3(fill_grid(n)), dim3(256), 0, s, a.mat, a.rodid, n);
     return hipGetLastError();

@@ -275,6 +275,14 @@ def jump_rods(lat, now_f32, next_f32, D, H, W, steps):
     _lib.check(lib.lb_sur_jump_rods(lat._ctx, _p(now_f32), _p(next_f32), D, H, W, float(steps), _stream(lat)))
 
 
+def drift_rods(lat, x_prev, factor):
+    """Each rod continues factor x its displacement since x_prev (a CUDA FP64
+    tensor [n_rods, 3] of the centres one interval earlier); re-placed."""
+    lib = _lib.load()
+    x_prev = x_prev.contiguous()
+    _lib.check(lib.lb_sur_drift_rods(lat._ctx, _p(x_prev), float(factor), _stream(lat)))
+
+
 def _stream(lat):
     import torch
 
@@ -291,7 +299,8 @@ def predict(net, x_f32, x_bf16=None, pred_f32=None, pred_bf16=None):
     return pred_f32, pred_bf16
 
 
-def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005, rod_mobility=0.0):
+def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005, rod_mobility=0.0, rods_prev=None,
+            drift=0.5):
     """One interval of a lattice by the surrogate, with the fallback rule.
 
     The network's prediction is lifted onto the lattice (rods advected and
@@ -308,8 +317,11 @@ def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005, ro
     after): over 500 steps of the drying caps the rods moved 1.5 nodes on
     average, and that advection put them 2.4 nodes from where the method
     took them against 1.5 for centres held in place, so the default holds
-    them.  Returns {"surrogate": bool, "mass_error": float, "mass": the
-    lifted rho_A mass, "mass_t": M_t}.
+    them.  Given rods_prev (a CUDA FP64 tensor [n_rods, 3] of the centres
+    one interval earlier), each rod instead continues `drift` times its
+    displacement since then (1.2 nodes off the method's for drift = 0.5).
+    Returns {"surrogate": bool, "mass_error": float, "mass": the lifted
+    rho_A mass, "mass_t": M_t}.
     """
     import torch
 
@@ -318,7 +330,9 @@ def advance(lat, net, D, H, W, interval=500, K=50, rate=0.0, threshold=0.005, ro
     xf, _ = restrict(lat, D, H, W)
     pf = torch.empty_like(xf)
     predict(net, xf, pred_f32=pf)
-    if lat.n_rods:
+    if lat.n_rods and rods_prev is not None:
+        drift_rods(lat, rods_prev, drift)
+    elif lat.n_rods:
         jump_rods(lat, xf, pf, D, H, W, interval * float(rod_mobility))
     lift(lat, pf, D, H, W)
     m_pred = float(lat.observables(allow_unstable=True)["mass"][0])

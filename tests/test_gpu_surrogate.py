@@ -445,6 +445,59 @@ def test_rod_jump_moves_and_replaces_rods():
     lat.close()
 
 
+def test_rod_drift_continues_the_previous_displacement():
+    """lb_sur_drift_rods: with the centres of one interval earlier given as
+    the present ones shifted by (1.2, -0.6, 0), each rod has moved by
+    (-1.2, 0.6, 0) since then and moves by half of that again, (-0.6, 0.3,
+    0) with the periodic wrap, orientation and velocity kept; the rod map is the oracle's mask of the new poses, and the
+    lattice steps on healthily after the lift."""
+    import torch
+
+    from oracle import rods as R
+    from paper_2607_06794_amd import inputs
+    from paper_2607_06794_amd import surrogate as SU
+    from paper_2607_06794_amd.sim import Lattice
+
+    spec = inputs.CapSpec(shape=(32, 48, 96), footprint=(70.0, 28.0), height=14.0, stripe=(80, 34), seed=5201)
+    rho, mat = inputs.sessile_cap(spec)
+    rods = inputs.place_rods(4, 12.0, 2.0, (96, 48, 32), inside=inputs.cap_inside(spec), seed=5202, margin=1.0,
+                             max_trials=20000)
+    assert len(rods) >= 2
+    c = dict(shape=spec.shape, periodic=(True, True, False), G=3.6, tau=(1.0, 1.0), evaporation=True,
+             body_force=(0.0, 0.0, 0.0))
+    lp = cases.lattice_params(c, "f32")
+    lp.rod_length, lp.rod_radius, lp.wall_z = 12.0, 2.0, 0.5
+    lat = Lattice(lp, rho, mat, rods=rods)
+    lat.coupled_step(10)
+    say(f"[gpu] rod drift: {len(rods)} rods on {spec.shape}")
+    before = lat.rods()
+    prev = before[:, :3] - np.array([-1.2, 0.6, 0.0])
+    prev[:, 0] %= 96  # the earlier centres as the lattice stores them (wrapped)
+    prev[:, 1] %= 48
+    SU.drift_rods(lat, torch.from_numpy(np.ascontiguousarray(prev)).to("cuda:0"), 0.5)
+    D, H, W = 16, 24, 48
+    now_f, _ = SU.restrict(lat, D, H, W)
+    SU.lift(lat, now_f, D, H, W)
+    after = lat.rods()
+    want_x = before[:, :3] + np.array([-0.6, 0.3, 0.0])
+    want_x[:, 0] %= 96
+    want_x[:, 1] %= 48
+    # z stays, kept between the closed end planes as every jump keeps it
+    for r in range(len(before)):
+        ez = abs(R.axis(before[r, 3:7])[2]) * 6.0 + 2.0
+        want_x[r, 2] = min(max(want_x[r, 2], 1.5 + ez), 32 - 2.5 - ez)
+    assert np.abs(after[:, :3] - want_x).max() < 1e-12
+    assert np.array_equal(after[:, 3:13], before[:, 3:13])  # orientation, velocity, angular momentum kept
+    rp = R.RodParams(length=12.0, radius=2.0)
+    orods = R.Rods(after[:, :3], after[:, 3:7], after[:, 7:10], after[:, 10:13], rp, (96, 48, 32), (True, True, False))
+    assert np.array_equal(lat.rod_map(), (orods.mask(spec.shape) >= 0).sum(axis=0))
+    with pytest.raises(Exception):
+        SU.drift_rods(lat, torch.from_numpy(np.ascontiguousarray(prev)).to("cuda:0"), float("nan"))
+    lat.coupled_step(20)
+    assert lat.observables(allow_unstable=True)["status"] == 0
+    lat.close()
+
+
 def test_surrogate_advance_and_fallback():
     """A network that keeps the state (zero output) passes a loose mass check:
     the surrogate path runs (jump, lift, K steps).  A network whose output adds
