@@ -161,12 +161,31 @@ def admissible(rho, u):
     return rho, u * scale
 
 
+def conserve(rho, coarse, material):
+    """Each component's prolonged density scaled so that its total over the
+    fluid nodes is the canvas's: the sum over the cells inside the lattice of
+    rho_k times the cell's fluid nodes (8 x channel 7); no scaling unless
+    both totals are positive."""
+    nz, ny, nx = material.shape
+    cells = coarse[: nz // 2, : ny // 2, : nx // 2]
+    fluid = material == lbm.FLUID
+    out = rho.copy()
+    for k in range(2):
+        want = float((cells[..., k] * 8.0 * cells[..., 7]).sum())
+        have = float(rho[k][fluid].sum())
+        if want > 0.0 and have > 0.0:
+            out[k] = rho[k] * (want / have)
+    return out
+
+
 def lift(coarse, material, p):
     """Post-collision state f^k = f^eq(rho_k, u_k^eq) (Eq. 2) of the prolonged
-    fields, made admissible, at fluid nodes, 0 elsewhere; u_k^eq = u - F /
-    (2 rho) + tau_k F_k / rho_k with F_k the Shan-Chen force of the prolonged
-    densities (no half-force shift where rho vanishes)."""
+    fields, made admissible and mass-conserving (conserve), at fluid nodes, 0
+    elsewhere; u_k^eq = u - F / (2 rho) + tau_k F_k / rho_k with F_k the
+    Shan-Chen force of the lifted densities (no half-force shift where rho
+    vanishes)."""
     rho, u = admissible(*prolong(coarse, material))
+    rho = conserve(rho, coarse, material)
     fluid = material == lbm.FLUID
     F = lbm.sc_force(lbm.pseudopotential(rho, material, p), rho, p)
     tot = rho[0] + rho[1]

@@ -1019,8 +1019,73 @@ __device__ inline void make_admissible(double a[5]) {
     }
 }
 
+// The lift keeps each component's mass: after the admissible map, rho_k on
+// the fluid nodes is scaled by s_k = (canvas total of rho_k x fluid nodes of
+// each cell) / (lifted total), when both totals are positive.  First the
+// lifted totals, per block in a fixed order (grid-stride nodes per thread,
+// then a tree over the block) ...
+__global__ void __launch_bounds__(256) lift_mass_kernel(const float *coarse, int H, int W, SurLattice L, double *part) {
+    __shared__ double red[2][256];
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    double t[2] = {0.0, 0.0};
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
+        if ((L.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
+        const int x = int(n % L.nx), y = int((n / L.nx) % L.ny), z = int(n / (int64_t(L.nx) * L.ny));
+        double a[5];
+        prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
+        make_admissible(a);
+        t[0] += a[0];
+        t[1] += a[1];
+    }
+    red[0][threadIdx.x] = t[0];
+    red[1][threadIdx.x] = t[1];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) part[2 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ... then, in one work-group, the canvas totals over the cells inside the
+// lattice, the blocks' totals in block order, and the two factors
+__global__ void __launch_bounds__(256) lift_scale_kernel(const float *coarse, int H, int W, SurLattice L,
+                                                         const double *part, int nb, double *scale) {
+    __shared__ double red[4][256];
+    const int ncz = L.nz / 2, ncy = L.ny / 2, ncx = L.nx / 2;
+    const int64_t ncell = int64_t(ncz) * ncy * ncx;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = threadIdx.x; c < ncell; c += blockDim.x) {
+        const int cx = int(c % ncx), cy = int((c / ncx) % ncy), cz = int(c / (int64_t(ncx) * ncy));
+        const float *cc = coarse + ((int64_t(cz) * H + cy) * W + cx) * 8;
+        const double nf = 8.0 * double(cc[7]);
+        t[0] += double(cc[0]) * nf;
+        t[1] += double(cc[1]) * nf;
+    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        t[2] += part[2 * b];
+        t[3] += part[2 * b + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = t[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) {
+        const double want = red[threadIdx.x][0], have = red[2 + threadIdx.x][0];
+        scale[threadIdx.x] = (want > 0.0 && have > 0.0) ? want / have : 1.0;
+    }
+}
+
 // psi_k of the lifted state: prolonged rho_k on fluid nodes, the material's value elsewhere
-__global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L) {
+__global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L, const double *scale) {
     const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
     for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
         const uint8_t m = L.mat[n];
@@ -1030,8 +1095,8 @@ __global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L)
             double a[5];
             prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
             make_admissible(a);
-            v[0] = a[0];
-            v[1] = a[1];
+            v[0] = a[0] * scale[0];
+            v[1] = a[1] * scale[1];
         } else {
             v[0] = psi_solid(L, m, 0);
             v[1] = psi_solid(L, m, 1);
@@ -1042,7 +1107,7 @@ __global__ void psi_lift_kernel(const float *coarse, int H, int W, SurLattice L)
 }
 
 template <class S>
-__global__ void lift_kernel(const float *coarse, int H, int W, SurLattice L, S *f) {
+__global__ void lift_kernel(const float *coarse, int H, int W, SurLattice L, const double *scale, S *f) {
     const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
     for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < n_all; n += int64_t(gridDim.x) * blockDim.x) {
         if ((L.mat[n] & MAT_ID_MASK) != MAT_FLUID) continue;
@@ -1050,7 +1115,7 @@ __global__ void lift_kernel(const float *coarse, int H, int W, SurLattice L, S *
         double a[5];
         prolong_at(coarse, H, W, L.nz / 2, L.ny / 2, L.nx / 2, x, y, z, a);
         make_admissible(a);
-        const double rho[2] = {a[0], a[1]};
+        const double rho[2] = {a[0] * scale[0], a[1] * scale[1]};
         double F[2][3];
         force_at(L, x, y, z, rho, F);
         const double tot = rho[0] + rho[1];
@@ -1290,11 +1355,20 @@ hipError_t launch_restrict(int prec, const void *f, const SurLattice &L, int D, 
 
 hipError_t launch_lift(int prec, const float *coarse, int D, int H, int W, const SurLattice &L, void *f, hipStream_t s) {
     (void)D;
-    const int gn = grid_for(int64_t(L.nx) * L.ny * L.nz);
+    const int64_t n_all = int64_t(L.nx) * L.ny * L.nz;
+    const int gn = grid_for(n_all);
+    // the block totals and the two factors follow psi in the scratch buffer
+    // (the other population buffer: 2 Q fs elements of at least 2 bytes,
+    // against 8 (2 n_all + 2 gn + 2) bytes here)
+    double *part = L.psi + 2 * n_all;
+    double *scale = part + 2 * gn;
+    if ((2 * n_all + 2 * int64_t(gn) + 2) * 8 > 2 * int64_t(Q) * L.fs * 2) return hipErrorInvalidValue;
     return by_prec(prec, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(psi_lift_kernel, dim3(gn), dim3(256), 0, s, coarse, H, W, L);
-        hipLaunchKernelGGL(lift_kernel<S>, dim3(gn), dim3(256), 0, s, coarse, H, W, L, static_cast<S *>(f));
+        hipLaunchKernelGGL(lift_mass_kernel, dim3(gn), dim3(256), 0, s, coarse, H, W, L, part);
+        hipLaunchKernelGGL(lift_scale_kernel, dim3(1), dim3(256), 0, s, coarse, H, W, L, part, gn, scale);
+        hipLaunchKernelGGL(psi_lift_kernel, dim3(gn), dim3(256), 0, s, coarse, H, W, L, scale);
+        hipLaunchKernelGGL(lift_kernel<S>, dim3(gn), dim3(256), 0, s, coarse, H, W, L, scale, static_cast<S *>(f));
         return hipGetLastError();
     });
 }

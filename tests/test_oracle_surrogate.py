@@ -306,3 +306,23 @@ def test_lift_is_the_collision_output_of_the_prolonged_fields():
         uk = jk / np.where(fl, r[k], 1.0)
         pxx = np.einsum("izyx,i->zyx", f[k], lbm.C[:, 0].astype(float) ** 2)
         assert np.allclose(np.where(fl, pxx, 0), np.where(fl, r[k] * (1 / 3 + uk[0] ** 2), 0), rtol=1e-12, atol=1e-14)
+
+
+def test_lift_keeps_each_components_canvas_mass():
+    # a two-phase canvas pushed negative in a block of cells (the admissible
+    # map raises those to 0, which adds mass): the lifted populations still
+    # carry each component's canvas mass, the sum over the cells of rho_k x
+    # 8 x the fluid fraction, while the map alone would not
+    shape = (10, 12, 14)
+    rho, mat, p = _two_phase(shape, 73)
+    run = lbm.Run(rho, mat, p).step(3)
+    coarse = S.restrict(run.f, mat, (5, 6, 7), p)
+    coarse[1:3, 2:4, 1:4, 0] = -0.05
+    f = S.lift(coarse, mat, p)
+    fl = mat == lbm.FLUID
+    for k in range(2):
+        want = float((coarse[..., k] * 8.0 * coarse[..., 7]).sum())
+        got = float(f[k].sum(axis=0)[fl].sum())
+        assert got == pytest.approx(want, rel=1e-12)
+    r_adm, _ = S.admissible(*S.prolong(coarse, mat))
+    assert r_adm[0][fl].sum() > 1.001 * float((coarse[..., 0] * 8.0 * coarse[..., 7]).sum())
