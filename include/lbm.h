@@ -585,7 +585,7 @@ int lb_up2_backward(const float *g, int32_t stride, int32_t C, int32_t D, int32_
 int lb_fill_f32(float *p, int64_t n, float value, hipStream_t stream);        /* graph-safe clear */
 
 /*
- * The whole surrogate network in one call each way (the benchmark spec form (4): a
+ * The whole surrogate network in one call each way (the learned surrogate: a
  * 3-D convolutional encoder-decoder on the coarse canvas).  nlev levels
  * (2..4) of ch[l] channels: per level two 3x3x3 ReLU convolutions, 2x2x2
  * average pooling down; on the way up nearest-neighbour upsampling
